@@ -42,7 +42,9 @@
  *   R10 alpha = -expm1(-kappa ds), the same quantity as Eq. (2) without cancellation;
  *   R11 the residual uses I_b of the last cell marched, as in Algorithm 1's formula;
  *   R12 each ray also draws a direction octant ("cone") o uniformly, p(n,g,o) = p(n,g)/8,
- *       and its direction is drawn inside that octant; together isotropic.
+ *       and its direction is drawn inside that octant; together isotropic;
+ *   R13 if nothing emits at T_max (sum of e_{n,g} is zero) the pdf is uniform over (n,g):
+ *       every ray value is then zero and any positive pdf gives that exactly.
  */
 #include <math.h>
 #include <stdint.h>
@@ -209,7 +211,14 @@ int orc_plain_pdf(const orc_problem *P, double *p, double *cdf_b, double *cdf_g,
         }
         E += eb[n];
     }
-    if (!err && !(E > 0.0)) err = ORC_INVALID;
+    if (!err && !(E > 0.0)) {      /* R13: nothing emits at T_max, every ray value is 0 */
+        E = 0.0;
+        for (int n = 0; n < P->nb; ++n) {
+            eb[n] = 0.0;
+            for (int g = 0; g < P->ng; ++g) { e[n * P->ng + g] = 1.0; eb[n] += 1.0; }
+            E += eb[n];
+        }
+    }
     if (!err) {
         double run = 0.0;
         for (int n = 0; n < P->nb; ++n) {
