@@ -1,0 +1,142 @@
+"""Benchmark: ray-cell steps per second of the ERMC radiative heat source on one MI355X.
+
+One step = one full pass of the hot path on one synthetic snapshot whose fields are already
+resident in HBM: ingest of the temperature and mole-fraction fields, T_max spectral pdf,
+property fields, ray allocation and bucketing, march, per-cell reduction (FP64).
+
+Workload: the non-grey channel -- 64 x 64 x 64 cells on the 4 pi x 2 x 2 pi box, periodic x/z,
+black walls at 300 K, T = 600 + 400 (1 - y^2) K with 8 Fourier modes of 5 %, H2O at 0.1,
+seeded synthetic correlated-k tables with 20 bands x 7 g-points, 32 rays per cell, FP32 march
+(double ray geometry and intensity differences), FP64 per-cell sums.
+
+Prints one JSON line.  The march kernel's duration is the HIP-event time the library records
+around its launch on the compute stream, summed over the timed steps.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes of the march: per ray-cell step one FP32 kappa_{n,g} and one FP64 I_n
+# gather; per ray one 8-byte work item read, one FP32 ray value and one 32-bit step count write
+BYTES_PER_STEP = 4 + 8
+BYTES_PER_RAY = 8 + 4 + 4
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target CPU time of the oracle baseline sample (0 disables it)")
+    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "march_traffic.json"),
+                    help="HBM bytes per march launch measured by rocprofv3 (optional)")
+    return ap.parse_args()
+
+
+def cpu_baseline(w, target_s):
+    """The oracle, as it stands, on a strided sample of the same workload's cells."""
+    import numpy as np
+    import oracle
+    P = oracle.Problem(w)
+    threads = oracle.max_threads()
+    stride = 256
+    while True:
+        cells = np.arange(0, w.ncells, stride)
+        t0 = time.perf_counter()
+        _, _, steps = oracle.divergence(P, cells=cells, nthreads=threads)
+        dt = time.perf_counter() - t0
+        if dt >= 0.25 * target_s or stride == 1:
+            break
+        stride = max(1, int(stride * max(dt, 1e-3) / target_s))
+    return {"value": steps / dt, "unit": "ray-cell steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"every {stride}th cell of the 64^3 channel ({len(cells)} cells x {w.R} rays, "
+                      f"{steps} steps, {dt:.1f} s)"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": a.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_1810_00188_amd import inputs, rmc
+
+    dev = torch.device("cuda", 0)
+    w = inputs.channel64()
+    s = rmc.Solver(0)
+    s.set_workload(w)
+    T = torch.from_numpy(np.ascontiguousarray(w.T, dtype=np.float32)).to(dev)
+    X = torch.from_numpy(np.ascontiguousarray(w.X, dtype=np.float32)).to(dev)
+    dq = torch.zeros(w.ncells, dtype=torch.float64, device=dev)
+    se = torch.zeros_like(dq)
+
+    def step():
+        s.set_temperature(T)
+        s.set_species(X)
+        s.compute(dq, se)
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    s.reset_stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for q in range(a.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = s.stats()
+    elapsed = t1 - t0
+    steps_total = st["sum_steps"]
+    assert st["computes"] == a.steps, st
+    value = steps_total / elapsed
+    march_ms = st["sum_ms_march"] / a.steps
+    bytes_launch = BYTES_PER_STEP * st["steps"] + BYTES_PER_RAY * st["rays"]
+    achieved = bytes_launch / (march_ms * 1e-3) / 1e9
+    traffic = None
+    if a.traffic_json and os.path.exists(a.traffic_json):
+        traffic = json.load(open(a.traffic_json)).get("bytes_per_launch")
+    out = {
+        "metric": "ray-cell steps/s",
+        "value": value,
+        "unit": "ray-cell steps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": 1e3 * elapsed / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "non-grey channel 64x64x64, 20 bands x 7 g, 32 rays/cell, "
+                               "FP32 march, FP64 sums",
+                   "grid": [w.nx, w.ny, w.nz], "bands": w.kd.nb, "g_points": w.kd.ng,
+                   "rays_per_cell": w.R, "rays_per_step": st["rays"],
+                   "ray_cell_steps_per_step": st["steps"], "parallelism": "1 GPU"},
+        "phases_ms": {"prep": st["sum_ms_prep"] / a.steps, "alloc": st["sum_ms_alloc"] / a.steps,
+                      "march": march_ms, "reduce": st["sum_ms_reduce"] / a.steps},
+        "march_steps_per_s": st["steps"] / (march_ms * 1e-3),
+        "roofline": {"kernel": "k_march", "bound": "hbm", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic,
+                     "algorithmic_bytes_per_launch": bytes_launch},
+    }
+    if a.cpu_seconds > 0:
+        out["cpu_baseline"] = cpu_baseline(w, a.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    s.close()
+
+
+if __name__ == "__main__":
+    main()

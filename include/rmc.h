@@ -1,0 +1,194 @@
+/*
+ * rmc.h -- C ABI of the MI355X (gfx950) emission-based reciprocal Monte Carlo solver for
+ * the radiative heat source div q_r on a Cartesian grid.
+ *
+ * Method: Silvestri & Pecnik, "A fast GPU Monte Carlo radiative heat transfer
+ * implementation for coupling with direct numerical simulation".  For every cell, rays
+ * are drawn over (narrow band n, g-point g) from the T_max spectral pdf (Sec. 2, Eqs. 13-17)
+ * and over isotropic directions (Eq. 9), marched face to face through the grid
+ * (Algorithm 1; x and z periodic, black walls bounding y) and weighted as in Eq. 14; the
+ * cell estimate is the mean ray value (Eq. 8, ERMC form of Sec. 2).
+ *
+ * Conventions (every entry point):
+ *  - Cells: nx x ny x nz, natural index c = (i * ny + j) * nz + k (k fastest); x and z are
+ *    periodic with face coordinates xf[0..nx], zf[0..nz]; y is bounded by black walls at
+ *    yf[0] and yf[ny].  1 <= nx, ny, nz <= 1023.
+ *  - Ownership: the caller owns every buffer it passes.  set_* calls copy (and convert) what
+ *    they need into library-owned device memory; caller buffers may be reused when the call
+ *    returns (device inputs: once the given stream has reached the call).
+ *  - Streams: `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued on it
+ *    and results are valid once it is synchronised.  set_temperature / set_species
+ *    synchronise the stream to validate the field.
+ *  - Errors: every call returns an rmc_status; rmc_last_error() gives the message of the
+ *    calling thread's last failure.  The library never aborts and never prints.
+ *    Temperatures outside the table range (or NaN) are errors, never clamped.
+ *  - A context is bound to one device and is not thread-safe; use one per thread.
+ *  - Units: lengths m, temperatures K, kappa m^-1 per unit mole fraction, band widths
+ *    cm^-1, intensities W m^-2 sr^-1 (cm^-1)^-1; div q in W m^-3 (emission - absorption,
+ *    Eq. 10 sign: positive in cells that lose energy).
+ */
+#ifndef RMC_H
+#define RMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rmc_ctx rmc_ctx;
+
+typedef enum {
+    RMC_OK = 0,
+    RMC_INVALID_ARG = 1,     /* bad pointer, size or enum value */
+    RMC_BAD_STATE = 2,       /* a required set_* call is missing */
+    RMC_OUT_OF_RANGE = 3,    /* temperature outside the table, NaN, negative mole fraction */
+    RMC_UNSUPPORTED = 4,     /* e.g. wall emissivity other than 1 */
+    RMC_DEVICE_ERROR = 5,    /* a HIP runtime call failed */
+    RMC_OUT_OF_MEMORY = 6
+} rmc_status;
+
+typedef enum { RMC_F32 = 0, RMC_F64 = 1, RMC_BF16 = 2 } rmc_dtype;
+typedef enum { RMC_HOST = 0, RMC_DEVICE = 1 } rmc_mem;
+
+/* Per-cell accumulation of the R ray values (always returned as double). */
+typedef enum {
+    RMC_ACC_F64 = 0,         /* double sums */
+    RMC_ACC_COMP_F32 = 1,    /* float sums with Neumaier compensation */
+    RMC_ACC_F32 = 2          /* plain float sums (reported for comparison) */
+} rmc_accum;
+
+typedef enum {
+    RMC_SAMPLING_PLAIN = 0,  /* T_max spectral pdf (Eqs. 13-17), octant uniform */
+    RMC_SAMPLING_PDF = 1     /* per-cell pdf over (n, g, octant) from rmc_set_cell_pdf */
+} rmc_sampling;
+
+typedef struct {
+    int32_t rays_per_cell;   /* R, 1..255 */
+    uint64_t seed;           /* Philox key */
+    uint32_t snapshot;       /* 0..2^27-1, part of every random-stream counter */
+    double tol;              /* transmissivity cut-off of the march (Algorithm 1), >= 0 */
+    int32_t max_steps;       /* cap on ray-cell steps per ray, >= 1 */
+    rmc_dtype march;         /* RMC_F32 or RMC_F64 arithmetic of the march */
+    rmc_accum accum;
+    rmc_sampling sampling;
+    double mix_eps;          /* RMC_SAMPLING_PDF: weight of the plain pdf in the mixture */
+    int32_t block_threads;   /* march launch: threads per block (64..1024, multiple of 64; 0 = default) */
+    int32_t reserved[7];     /* must be zero */
+} rmc_options;
+
+typedef struct {
+    int64_t rays;            /* rays marched by the last compute */
+    int64_t steps;           /* ray-cell steps (one DDA segment in one cell) of the last compute */
+    int64_t capped_rays;     /* rays stopped by max_steps with tau > tol */
+    double ms_prep;          /* last compute: pdf + property fields (HIP events on its stream) */
+    double ms_alloc;         /* last compute: ray allocation, bucketing */
+    double ms_march;         /* last compute: march kernel */
+    double ms_reduce;        /* last compute: per-cell reduction */
+    double ms_total;
+    /* accumulated over every compute since rmc_reset_stats (or context creation) */
+    int64_t computes;
+    int64_t sum_rays;
+    int64_t sum_steps;
+    double sum_ms_prep, sum_ms_alloc, sum_ms_march, sum_ms_reduce;
+} rmc_stats;
+
+/* One ray of rmc_trace_cells (parity and debugging). */
+typedef struct {
+    double Y;                /* ray value [W m^-3] (cell estimate = mean over its R rays) */
+    double p;                /* probability p(n, g, o) the ray was drawn with */
+    int32_t n, g, o, k;      /* band, g-point, octant, ordinal among equal (n, g, o) in the cell */
+    int32_t steps;           /* ray-cell steps */
+    int32_t end;             /* 0: tau <= tol, 1: wall y0, 2: wall y1, 3: step cap */
+} rmc_ray_record;
+
+/* Create a context on HIP device `device` (>= 0).  Allocates nothing large. */
+rmc_status rmc_create(int device, rmc_ctx **out);
+/* Free the context and its device memory (NULL is a no-op).  Synchronises the device. */
+void rmc_destroy(rmc_ctx *ctx);
+/* Message of the calling thread's last failed call ("" if none).  Valid until the next call. */
+const char *rmc_last_error(void);
+
+/* Grid: face coordinates (host, double), strictly increasing, xf[0..nx], yf[0..ny],
+ * zf[0..nz].  Invalidates fields set earlier. */
+rmc_status rmc_set_grid(rmc_ctx *ctx, int nx, int ny, int nz,
+                        const double *xf, const double *yf, const double *zf);
+
+/* Wall temperatures at y = yf[0] and y = yf[ny] and their emissivities.  Only black walls
+ * (eps = 1, Eq. 3 with a single absorbing wall) are supported: anything else returns
+ * RMC_UNSUPPORTED. */
+rmc_status rmc_set_walls(rmc_ctx *ctx, double T_y0, double T_y1, double eps_y0, double eps_y1);
+
+/* Narrow-band correlated-k tables on the uniform temperature grid T0 + t * dT, t < nT
+ * (Sec. 2.1, precomputed tables of Sec. 2.2).  All host pointers:
+ *   dnu[nb] band widths, wg[ng] quadrature weights,
+ *   k[ns][nb][ng][nT] absorption coefficient per unit mole fraction, RMC_F32 floats or
+ *     RMC_BF16 raw bfloat16 bit patterns (uint16),
+ *   Ib[nb][nT] band-averaged blackbody intensity (double).
+ * Limits: 1 <= nb <= 4096, 1 <= ng <= 255, 1 <= ns <= 8, 2 <= nT, nb * ng <= 2000. */
+rmc_status rmc_set_kdist(rmc_ctx *ctx, int nb, int ng, int ns, int nT, double T0, double dT,
+                         const double *dnu, const double *wg, const void *k, rmc_dtype k_dtype,
+                         const double *Ib);
+
+/* Temperature field T[ncells] (natural order), RMC_F32 or RMC_F64, host or device memory.
+ * Needs set_grid and set_kdist first.  Validates every value against the table range
+ * (RMC_OUT_OF_RANGE, NaN included) and synchronises `stream`. */
+rmc_status rmc_set_temperature(rmc_ctx *ctx, const void *T, rmc_dtype dtype, rmc_mem mem,
+                               void *stream);
+
+/* Mole fractions X[ns][ncells] (natural order), RMC_F32 or RMC_F64, host or device.
+ * ns must match set_kdist.  Negative or non-finite values are RMC_OUT_OF_RANGE.
+ * Synchronises `stream`. */
+rmc_status rmc_set_species(rmc_ctx *ctx, int ns, const void *X, rmc_dtype dtype, rmc_mem mem,
+                           void *stream);
+
+/* Solver options; see rmc_options.  rmc_default_options fills the defaults
+ * (R = 16, seed 0, tol 1e-6, max_steps 65536, F32 march, F64 sums, plain sampling). */
+void rmc_default_options(rmc_options *opt);
+rmc_status rmc_set_options(rmc_ctx *ctx, const rmc_options *opt);
+
+/* Per-cell allocation pdf over (n, g, octant) for RMC_SAMPLING_PDF: q[ncells][nb][ng][8]
+ * (double, >= 0, not necessarily normalised, host or device).  The rays of cell c are
+ * drawn from (1 - mix_eps) q_c / sum q_c + mix_eps p_plain(n, g) / 8 and weighted by the
+ * inverse of that probability (importance weights keep the estimate unbiased). */
+rmc_status rmc_set_cell_pdf(rmc_ctx *ctx, const double *q, rmc_mem mem, void *stream);
+
+/* The ERMC estimate of every cell: divq[ncells] (mean ray value, natural order) and, if
+ * non-null, stderr[ncells] (standard error of that mean).  Both double, in `mem` memory.
+ * Enqueued on `stream`; nothing is synchronised. */
+rmc_status rmc_compute_divergence(rmc_ctx *ctx, double *divq, double *stderr_out, rmc_mem mem,
+                                  void *stream);
+
+/* Several snapshots (contexts on one device with identical tables, options and walls;
+ * grids and fields may differ) in one pass of the pipeline: the rays of all snapshots are
+ * bucketed together and marched by one kernel launch.  divq[s] / stderr[s] (nullable)
+ * receive snapshot s.  Enqueued on `stream`. */
+rmc_status rmc_compute_batch(rmc_ctx *const *ctxs, int nsnap, double *const *divq,
+                             double *const *stderr_out, rmc_mem mem, void *stream);
+
+/* Per-ray values and step counts of the last compute for the listed cells (host arrays):
+ * Y[ncell][R] (double) and steps[ncell][R] (int32, nullable).  Synchronises `stream`. */
+rmc_status rmc_get_ray_values(rmc_ctx *ctx, const int64_t *cells, int ncell, double *Y,
+                              int32_t *steps, void *stream);
+
+/* Re-draw and re-march all R rays of the listed cells with the same device functions as
+ * rmc_compute_divergence and return full records out[ncell][R] (host).  Synchronises. */
+rmc_status rmc_trace_cells(rmc_ctx *ctx, const int64_t *cells, int ncell, rmc_ray_record *out,
+                           void *stream);
+
+/* The plain spectral pdf used by the last compute (host arrays): p[nb][ng], cdf_b[nb],
+ * cdf_g[nb][ng] and T_max (nullable).  Synchronises `stream`. */
+rmc_status rmc_get_pdf(rmc_ctx *ctx, double *p, double *cdf_b, double *cdf_g, double *T_max,
+                       void *stream);
+
+/* Counters and phase timings of the last compute and accumulated since the last reset.
+ * Waits for every compute enqueued so far to finish. */
+rmc_status rmc_get_stats(rmc_ctx *ctx, rmc_stats *out);
+/* Wait for pending computes, then zero the accumulated counters and timings. */
+rmc_status rmc_reset_stats(rmc_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RMC_H */

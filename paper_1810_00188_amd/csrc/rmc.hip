@@ -1,0 +1,1530 @@
+// rmc.hip -- gfx950 implementation of the C ABI declared in include/rmc.h: the
+// emission-based reciprocal Monte Carlo (ERMC) radiative heat source of Silvestri & Pecnik.
+//
+// Pipeline of one compute (all kernels on the caller's stream, no host round trip):
+//   1. k_plain_pdf     T_max spectral pdf and its cumulative sums (Eqs. 13, 16-17), ray
+//                      weights per (band, g, octant) bucket (Eq. 14), wall intensities.
+//   2. k_fields        band-major property fields {kappa_{n,g}, I_n} per cell in a bricked
+//                      layout (table interpolation of Sec. 2.2 done once per cell, not per step).
+//   3. k_alloc_count   per tile of cells: histogram of the rays' (n, g, octant) buckets.
+//      k_bucket_scan   per bucket: exclusive scan over tiles (no global atomics).
+//      k_bucket_layout bucket starts padded to whole wavefronts, chunk -> bucket map.
+//      k_alloc_scatter per tile: ray work items into their bucket (narrow-band sorting of
+//                      Sec. 4.2: a wavefront marches rays of one (n, g, octant)).
+//   4. k_march         one lane per ray, Algorithm 1 march, ray value into its slot.
+//   5. k_reduce        per cell: mean and standard error of the R ray values (FP64, or
+//                      compensated / plain FP32), natural order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "rmc.h"
+#include "rmc_device.h"
+
+using namespace rmc;
+
+// ============================================================================ device side
+namespace {
+
+struct SnapDesc {
+    const void *kap;            // Real [nb*ng][ncpad] kappa_{n,g} planes, bricked
+    const double *Ipl;          // [nb][ncpad] I_n planes, bricked
+    const double *W;            // [nbucket] plain ray weight 4 pi dnu w / (8 p(n,g,o))
+    const double *Iw;           // [2][nb] wall intensities
+    void *Y;                    // Real [ncells * R] ray values, slot c * R + r
+    uint32_t *st;               // [ncells * R] steps | end << 28
+    const double *p;            // [nb*ng] plain pdf
+    const double *cdf_b;        // [nb]
+    const double *cdf_g;        // [nb*ng]
+    const double *cpdf;         // per-cell pdf mode: [ncells][nb*ng*8]
+    const double *ccdf_b;       // [ncells][nb]
+    const double *ccdf_g;       // [ncells][nb*ng]
+    const double *ccdf_o;       // [ncells][nb*ng*8]
+    uint64_t ncpad;             // cells per bricked field plane
+    int nx, ny, nz;
+    int nbx, nby, nbz;
+    int face_off;               // x faces at face_off, y at +nx+1, z at +nx+ny+2
+    uint32_t snap_id;
+    int tile_begin, ntiles;
+    double Lx, Lz;
+};
+
+struct AllocArgs {
+    const SnapDesc *snaps;
+    const int *tile_snap;       // [ntiles] snapshot of each tile
+    int ntiles, tile_cells;
+    int nb, ng, nbucket, R;
+    uint32_t k0, k1;
+    uint32_t *hist;             // [nbucket][ntiles]
+    const uint32_t *bucket_start;
+    uint2 *items;
+};
+
+struct Draw {
+    int n, g, o;
+    double p;
+};
+
+template <bool PDF>
+__device__ __forceinline__ Draw draw_ray(const SnapDesc &D, int nb, int ng, uint32_t c, uint32_t r,
+                                         uint32_t k0, uint32_t k1)
+{
+    uint32_t w[4];
+    philox4x32_10(c, r, 0u, (D.snap_id << 4) | kTagAlloc, k0, k1, w);
+    const double u0 = unif_alloc(w[0]), u1 = unif_alloc(w[1]), u2 = unif_alloc(w[2]);
+    Draw d;
+    if constexpr (!PDF) {
+        d.n = cdf_search(D.cdf_b, nb, u0);
+        d.g = cdf_search(D.cdf_g + (size_t)d.n * ng, ng, u1);
+        d.o = (int)floor(8.0 * u2);
+        d.p = D.p[d.n * ng + d.g] / 8.0;
+    } else {
+        const size_t cb = (size_t)c * nb, cg = (size_t)c * nb * ng;
+        d.n = cdf_search(D.ccdf_b + cb, nb, u0);
+        d.g = cdf_search(D.ccdf_g + cg + (size_t)d.n * ng, ng, u1);
+        const size_t so = (cg + (size_t)d.n * ng + d.g) * 8;
+        d.o = cdf_search(D.ccdf_o + so, 8, u2);
+        d.p = D.cpdf[so + d.o];
+    }
+    return d;
+}
+
+// cell of a tile position: brick-linear index -> (i, j, k), valid if inside the grid
+__device__ __forceinline__ bool brick_cell(const SnapDesc &D, uint64_t bc, int &i, int &j, int &k)
+{
+    const uint64_t brick = bc >> 6;
+    const int w = (int)(bc & 63);
+    const int bk = (int)(brick % D.nbz);
+    const int bj = (int)((brick / D.nbz) % D.nby);
+    const int bi = (int)(brick / ((uint64_t)D.nbz * D.nby));
+    i = bi * 4 + ((w >> 2) & 1) + (((w >> 5) & 1) << 1);
+    j = bj * 4 + ((w >> 1) & 1) + (((w >> 4) & 1) << 1);
+    k = bk * 4 + (w & 1) + (((w >> 3) & 1) << 1);
+    return bc < D.ncpad && i < D.nx && j < D.ny && k < D.nz;
+}
+
+// --------------------------------------------------------------------- field ingest
+template <class Tin>
+__global__ void k_ingest_T(const Tin *__restrict__ in, double *__restrict__ out, uint64_t n, double T0,
+                           double dT, int nT, unsigned long long *maxbits, unsigned int *flag)
+{
+    double mx = 0.0;
+    bool bad = false;
+    for (uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; q < n;
+         q += (uint64_t)gridDim.x * blockDim.x) {
+        const double v = (double)in[q];
+        out[q] = v;
+        const double u = (v - T0) / dT;
+        if (!(u >= 0.0 && u <= (double)(nT - 1))) bad = true;
+        else mx = fmax(mx, v);
+    }
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+    if ((threadIdx.x & 63) == 0) atomicMax(maxbits, (unsigned long long)__double_as_longlong(mx));
+    if (bad) atomicOr(flag, 1u);
+}
+
+template <class Tin>
+__global__ void k_ingest_X(const Tin *__restrict__ in, double *__restrict__ out, uint64_t nc, int ns,
+                           unsigned long long *maxbits, unsigned int *flag)
+{
+    for (int s = 0; s < ns; ++s) {
+        double mx = 0.0;
+        bool bad = false;
+        for (uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; q < nc;
+             q += (uint64_t)gridDim.x * blockDim.x) {
+            const double v = (double)in[(size_t)s * nc + q];
+            out[(size_t)s * nc + q] = v;
+            if (!(v >= 0.0 && v < INFINITY)) bad = true;
+            else mx = fmax(mx, v);
+        }
+        for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+        if ((threadIdx.x & 63) == 0) atomicMax(maxbits + s, (unsigned long long)__double_as_longlong(mx));
+        if (bad) atomicOr(flag, 1u);
+    }
+}
+
+// ------------------------------------------------------------- spectral pdf (1 thread)
+__device__ __forceinline__ double lerp_tab(const double *tab, int nT, double T0, double dT, double T)
+{
+    const double u = (T - T0) / dT;
+    int t = (int)floor(u);
+    if (t > nT - 2) t = nT - 2;
+    const double f = u - (double)t;
+    return tab[t] + f * (tab[t + 1] - tab[t]);
+}
+
+struct PdfArgs {
+    const double *k64;          // [ns][nb][ng][nT]
+    const double *Ib;           // [nb][nT]
+    const double *dnu, *wg;
+    int nb, ng, ns, nT;
+    double T0, dT, Tmax, Tw0, Tw1;
+    double xhat[8];
+    double *e;                  // scratch [nb*ng]
+    double *eb;                 // scratch [nb]
+    double *p, *cdf_b, *cdf_g, *W, *Iw;
+    int *status;
+};
+
+// e_{n,g} = pi dnu_n w_g kappa_{n,g}(T_max, xhat) I_n(T_max); p = e / E; cumulative sums in
+// index order (Eqs. 13, 16-17 at T_max, Zhang's sampling); W = 4 pi dnu w / (8 p / 8).
+__global__ void k_plain_pdf(PdfArgs A)
+{
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    const int nb = A.nb, ng = A.ng;
+    double E = 0.0;
+    for (int n = 0; n < nb; ++n) {
+        const double In = lerp_tab(A.Ib + (size_t)n * A.nT, A.nT, A.T0, A.dT, A.Tmax);
+        A.eb[n] = 0.0;
+        for (int g = 0; g < ng; ++g) {
+            double kap = 0.0;
+            for (int s = 0; s < A.ns; ++s) {
+                const double ks = lerp_tab(A.k64 + (((size_t)s * nb + n) * ng + g) * A.nT, A.nT, A.T0,
+                                           A.dT, A.Tmax);
+                kap += A.xhat[s] * ks;
+            }
+            const double v = M_PI * A.dnu[n] * A.wg[g] * kap * In;
+            A.e[n * ng + g] = v;
+            A.eb[n] += v;
+        }
+        E += A.eb[n];
+        A.Iw[n] = lerp_tab(A.Ib + (size_t)n * A.nT, A.nT, A.T0, A.dT, A.Tw0);
+        A.Iw[nb + n] = lerp_tab(A.Ib + (size_t)n * A.nT, A.nT, A.T0, A.dT, A.Tw1);
+    }
+    if (!(E > 0.0)) {
+        // nothing emits at T_max (all I_b or kappa zero): every ray value is exactly zero for
+        // any positive pdf, so the uniform one is used
+        E = 0.0;
+        for (int n = 0; n < nb; ++n) {
+            A.eb[n] = 0.0;
+            for (int g = 0; g < ng; ++g) {
+                A.e[n * ng + g] = 1.0;
+                A.eb[n] += 1.0;
+            }
+            E += A.eb[n];
+        }
+    }
+    double run = 0.0;
+    for (int n = 0; n < nb; ++n) {
+        run += A.eb[n];
+        A.cdf_b[n] = run / E;
+        double rg = 0.0;
+        for (int g = 0; g < ng; ++g) {
+            rg += A.e[n * ng + g];
+            A.p[n * ng + g] = A.e[n * ng + g] / E;
+            A.cdf_g[n * ng + g] = A.eb[n] > 0.0 ? rg / A.eb[n] : (double)(g + 1) / ng;
+        }
+        A.cdf_g[n * ng + ng - 1] = 1.0;
+    }
+    A.cdf_b[nb - 1] = 1.0;
+    for (int n = 0; n < nb; ++n)
+        for (int g = 0; g < ng; ++g) {
+            const double prob = A.p[n * ng + g] / 8.0;
+            const double w = prob > 0.0 ? 4.0 * M_PI * A.dnu[n] * A.wg[g] / (8.0 * prob) : 0.0;
+            for (int o = 0; o < 8; ++o) A.W[(n * ng + g) * 8 + o] = w;
+        }
+    *A.status = 0;
+}
+
+// Per-cell allocation pdf p_c = (1 - eps) q_c / sum q_c + eps p_plain / 8 and its band,
+// g | band and octant | (band, g) cumulative sums, one thread per cell, sequential FP64 in
+// index order.
+__global__ void k_cell_pdf(const double *__restrict__ q, const double *__restrict__ pplain, uint64_t nc,
+                           int nb, int ng, double eps, double *cpdf, double *cb, double *cg, double *co)
+{
+    const uint64_t c = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    const int m = nb * ng * 8;
+    const double *qc = q + c * m;
+    double *pc = cpdf + c * m, *cbc = cb + c * nb, *cgc = cg + c * (size_t)nb * ng, *coc = co + c * m;
+    double qs = 0.0;
+    for (int i = 0; i < m; ++i) qs += qc[i];
+    for (int n = 0; n < nb; ++n)
+        for (int g = 0; g < ng; ++g)
+            for (int o = 0; o < 8; ++o) {
+                const int i = (n * ng + g) * 8 + o;
+                pc[i] = (1.0 - eps) * (qc[i] / qs) + eps * (pplain[n * ng + g] / 8.0);
+            }
+    double tot = 0.0;
+    for (int i = 0; i < m; ++i) tot += pc[i];
+    double run = 0.0;
+    for (int n = 0; n < nb; ++n) {
+        double bn = 0.0;
+        for (int i = 0; i < ng * 8; ++i) bn += pc[n * ng * 8 + i];
+        run += bn;
+        cbc[n] = run / tot;
+        double rg = 0.0;
+        for (int g = 0; g < ng; ++g) {
+            double gn = 0.0;
+            for (int o = 0; o < 8; ++o) gn += pc[(n * ng + g) * 8 + o];
+            rg += gn;
+            cgc[n * ng + g] = rg / bn;
+            double ro = 0.0;
+            for (int o = 0; o < 8; ++o) {
+                ro += pc[(n * ng + g) * 8 + o];
+                coc[(n * ng + g) * 8 + o] = ro / gn;
+            }
+            coc[(n * ng + g) * 8 + 7] = 1.0;
+        }
+        cgc[n * ng + ng - 1] = 1.0;
+    }
+    cbc[nb - 1] = 1.0;
+    for (int i = 0; i < m; ++i) pc[i] /= tot;
+}
+
+// ------------------------------------------------------------------ property fields
+// field[(n*ng + g)][brick(i,j,k)] = {kappa_{n,g}(T_c, x_c), I_n(T_c)}: linear interpolation
+// of the tables in T (Sec. 2.2), mixture kappa = sum_s x_s k^s (FP64, then rounded to Real).
+template <class Real>
+__global__ void k_fields(const double *__restrict__ T, const double *__restrict__ X, int ns, uint64_t nc,
+                         const double *__restrict__ k64, const double *__restrict__ Ib, int nb, int ng, int nT,
+                         double T0, double dT, SnapDesc D, Real *__restrict__ kap_out, double *__restrict__ I_out)
+{
+    const uint64_t bc = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (bc >= D.ncpad) return;
+    int i, j, k;
+    const bool valid = brick_cell(D, bc, i, j, k);
+    uint64_t c = 0;
+    int t = 0;
+    double f = 0.0;
+    if (valid) {
+        c = ((uint64_t)i * D.ny + j) * D.nz + k;
+        const double u = (T[c] - T0) / dT;
+        t = (int)floor(u);
+        if (t > nT - 2) t = nT - 2;
+        f = u - (double)t;
+    }
+    for (int pair = blockIdx.y; pair < nb * ng; pair += gridDim.y) {
+        const int n = pair / ng, g = pair - (pair / ng) * ng;
+        double kap = 0.0, I = 0.0;
+        if (valid) {
+            for (int s = 0; s < ns; ++s) {
+                const double *tab = k64 + (((size_t)s * nb + n) * ng + g) * nT;
+                const double ks = tab[t] + f * (tab[t + 1] - tab[t]);
+                kap += X[(size_t)s * nc + c] * ks;
+            }
+            const double *ib = Ib + (size_t)n * nT;
+            I = ib[t] + f * (ib[t + 1] - ib[t]);
+        }
+        kap_out[(size_t)pair * D.ncpad + bc] = (Real)kap;
+        if (g == 0) I_out[(size_t)n * D.ncpad + bc] = I;
+    }
+}
+
+// ------------------------------------------------------------- allocation and buckets
+// Rays of one tile: cells [tile_begin.., +tile_cells) of the brick-linear order, all R rays
+// of each cell in one pass of the block (cells_per_pass = blockDim / R).
+template <bool PDF>
+__global__ void __launch_bounds__(256) k_alloc_count(AllocArgs A)
+{
+    extern __shared__ uint32_t lh[];   // [nbucket]
+    const int tile = blockIdx.x;
+    for (int b = threadIdx.x; b < A.nbucket; b += blockDim.x) lh[b] = 0;
+    __syncthreads();
+    const SnapDesc &D = A.snaps[A.tile_snap[tile]];
+    const uint64_t first = (uint64_t)(tile - D.tile_begin) * A.tile_cells;
+    const int cpp = blockDim.x / A.R;
+    const int cq = threadIdx.x / A.R, r = threadIdx.x - cq * A.R;
+    for (int base = 0; base < A.tile_cells; base += cpp) {
+        int i, j, k;
+        if (cq < cpp && base + cq < A.tile_cells && brick_cell(D, first + base + cq, i, j, k)) {
+            const uint32_t c = (uint32_t)(((uint64_t)i * D.ny + j) * D.nz + k);
+            const Draw d = draw_ray<PDF>(D, A.nb, A.ng, c, (uint32_t)r, A.k0, A.k1);
+            atomicAdd(&lh[(d.n * A.ng + d.g) * 8 + d.o], 1u);
+        }
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < A.nbucket; b += blockDim.x)
+        A.hist[(size_t)b * A.ntiles + tile] = lh[b];
+}
+
+// per bucket: exclusive scan of the tile counts in place, total into bucket_total
+__global__ void __launch_bounds__(64) k_bucket_scan(uint32_t *hist, int ntiles, uint32_t *bucket_total)
+{
+    const int b = blockIdx.x;
+    uint32_t *h = hist + (size_t)b * ntiles;
+    uint32_t carry = 0;
+    const int lane = threadIdx.x;
+    for (int base = 0; base < ntiles; base += 64) {
+        const uint32_t v = base + lane < ntiles ? h[base + lane] : 0u;
+        uint32_t x = v;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(x, off);
+            if (lane >= off) x += y;
+        }
+        if (base + lane < ntiles) h[base + lane] = carry + x - v;
+        carry += __shfl(x, 63);
+    }
+    if (lane == 0) bucket_total[b] = carry;
+}
+
+// bucket starts padded to multiples of 64 (one wavefront never mixes buckets), total chunks
+__global__ void __launch_bounds__(1024) k_bucket_layout(const uint32_t *total, int nbucket, uint32_t *start,
+                                                         uint32_t *nchunks)
+{
+    __shared__ uint32_t part[1024];
+    const int tid = threadIdx.x;
+    const int per = (nbucket + 1023) / 1024;
+    uint32_t s = 0;
+    for (int q = 0; q < per; ++q) {
+        const int b = tid * per + q;
+        if (b < nbucket) s += (total[b] + 63u) & ~63u;
+    }
+    part[tid] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const uint32_t v = tid >= off ? part[tid - off] : 0u;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    uint32_t run = part[tid] - s;
+    for (int q = 0; q < per; ++q) {
+        const int b = tid * per + q;
+        if (b < nbucket) {
+            start[b] = run;
+            run += (total[b] + 63u) & ~63u;
+        }
+    }
+    if (tid == 1023) { start[nbucket] = part[1023]; *nchunks = part[1023] / 64u; }
+}
+
+// chunk -> bucket map and invalid markers on the padding of each bucket
+__global__ void k_chunk_map(const uint32_t *total, const uint32_t *start, int nbucket, uint32_t *chunk_bucket,
+                            uint2 *items)
+{
+    const int b = blockIdx.x * blockDim.y + threadIdx.y;
+    if (b >= nbucket) return;
+    const uint32_t s = start[b], e = start[b + 1], used = s + total[b];
+    for (uint32_t q = s / 64 + threadIdx.x; q < e / 64; q += blockDim.x) chunk_bucket[q] = (uint32_t)b;
+    for (uint32_t q = used + threadIdx.x; q < e; q += blockDim.x) items[q] = make_uint2(0u, kInvalidItem);
+}
+
+template <bool PDF>
+__global__ void __launch_bounds__(256) k_alloc_scatter(AllocArgs A)
+{
+    extern __shared__ uint32_t lb[];   // [nbucket] next free position, then [256] bucket of each thread
+    uint32_t *sb = lb + A.nbucket;
+    const int tile = blockIdx.x;
+    for (int b = threadIdx.x; b < A.nbucket; b += blockDim.x)
+        lb[b] = A.bucket_start[b] + A.hist[(size_t)b * A.ntiles + tile];
+    __syncthreads();
+    const int s = A.tile_snap[tile];
+    const SnapDesc &D = A.snaps[s];
+    const uint64_t first = (uint64_t)(tile - D.tile_begin) * A.tile_cells;
+    const int cpp = blockDim.x / A.R;
+    const int cq = threadIdx.x / A.R, r = threadIdx.x - cq * A.R;
+    for (int base = 0; base < A.tile_cells; base += cpp) {
+        int i = 0, j = 0, k = 0;
+        const bool live = cq < cpp && base + cq < A.tile_cells && brick_cell(D, first + base + cq, i, j, k);
+        uint32_t bucket = 0xFFFFFFFFu, c = 0;
+        if (live) {
+            c = (uint32_t)(((uint64_t)i * D.ny + j) * D.nz + k);
+            const Draw d = draw_ray<PDF>(D, A.nb, A.ng, c, (uint32_t)r, A.k0, A.k1);
+            bucket = (uint32_t)((d.n * A.ng + d.g) * 8 + d.o);
+        }
+        sb[threadIdx.x] = bucket;
+        __syncthreads();
+        if (live) {
+            uint32_t kord = 0;
+            for (int q = threadIdx.x - r; q < (int)threadIdx.x; ++q) kord += sb[q] == bucket ? 1u : 0u;
+            const uint32_t pos = atomicAdd(&lb[bucket], 1u);
+            A.items[pos] = make_uint2((uint32_t)i | ((uint32_t)j << 10) | ((uint32_t)k << 20),
+                                      (uint32_t)r | (kord << 8) | ((uint32_t)s << 16));
+        }
+        __syncthreads();
+    }
+}
+
+// -------------------------------------------------------------------------- march
+template <class Real> struct MarchArgs {
+    const SnapDesc *snaps;
+    const double *faces;        // all snapshots' face tables, staged into LDS
+    int nfaces;
+    const uint2 *items;
+    const uint32_t *chunk_bucket;
+    const uint32_t *nchunks;
+    const double *dnu, *wg;     // per-ray weights in per-cell pdf mode
+    int nb, ng, R;
+    uint32_t k0, k1;
+    Real tol;
+    int max_steps;
+};
+
+__device__ __forceinline__ RayGeo ray_geo(const SnapDesc &D, const double *sf)
+{
+    RayGeo G;
+    G.xf = sf + D.face_off;
+    G.yf = G.xf + D.nx + 1;
+    G.zf = G.yf + D.ny + 1;
+    G.nx = D.nx; G.ny = D.ny; G.nz = D.nz;
+    G.bsx = D.nby * D.nbz * 64;
+    G.bsy = D.nbz * 64;
+    G.Lx = D.Lx;
+    G.Lz = D.Lz;
+    return G;
+}
+
+// One lane per ray; every wavefront holds 64 work items of one (band, g, octant) bucket.
+template <class Real, bool PDF>
+__global__ void __launch_bounds__(256) k_march(MarchArgs<Real> A)
+{
+    extern __shared__ double sf[];
+    for (int q = threadIdx.x; q < A.nfaces; q += blockDim.x) sf[q] = A.faces[q];
+    __syncthreads();
+    const uint32_t wave = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    if (wave >= *A.nchunks) return;
+    const uint32_t b = __builtin_amdgcn_readfirstlane(A.chunk_bucket[wave]);
+    const uint2 it = A.items[(size_t)wave * 64 + (threadIdx.x & 63)];
+    if (it.y == kInvalidItem) return;
+    const int s = (int)((it.y >> 16) & 0x7FFF);
+    const SnapDesc &D = A.snaps[s];
+    const int i = (int)(it.x & 1023), j = (int)((it.x >> 10) & 1023), k = (int)((it.x >> 20) & 1023);
+    const int r = (int)(it.y & 255);
+    const uint32_t kord = (it.y >> 8) & 255u;
+    const int o = (int)(b & 7), pair = (int)(b >> 3);
+    const int n = pair / A.ng, g = pair - (pair / A.ng) * A.ng;
+    const Real *K = reinterpret_cast<const Real *>(D.kap) + (size_t)pair * D.ncpad;
+    const double *Ipl = D.Ipl + (size_t)n * D.ncpad;
+    const uint32_t c = (uint32_t)(((uint64_t)i * D.ny + j) * D.nz + k);
+    uint32_t v[4];
+    philox4x32_10(c, ((uint32_t)n << 16) | ((uint32_t)g << 8) | (uint32_t)o, kord,
+                  (D.snap_id << 4) | kTagDir, A.k0, A.k1, v);
+    double dx, dy, dz;
+    octant_direction(v[0], v[1], o, dx, dy, dz);
+    const RayGeo G = ray_geo(D, sf);
+    const int csrc = brick_x(i, G.bsx) + brick_y(j, G.bsy) + brick_z(k);
+    const Real kap_src = K[csrc];
+    const MarchOut<Real> m = march_ray<Real, false>(G, K, Ipl, i, j, k, dx, dy, dz, Ipl[csrc], D.Iw[n],
+                                                    D.Iw[A.nb + n], A.tol, A.max_steps);
+    double w;
+    if constexpr (!PDF) {
+        w = D.W[b];
+    } else {
+        const double p = D.cpdf[((size_t)c * A.nb * A.ng + pair) * 8 + o];
+        w = 4.0 * M_PI * A.dnu[n] * A.wg[g] / (8.0 * p);
+    }
+    const double Y = w * (double)kap_src * (double)m.acc;
+    const size_t slot = (size_t)c * A.R + r;
+    reinterpret_cast<Real *>(D.Y)[slot] = (Real)Y;
+    D.st[slot] = (uint32_t)m.steps | ((uint32_t)m.end << 28);
+}
+
+// --------------------------------------------------------------------------- trace
+template <class Real> struct TraceArgs {
+    const SnapDesc *snaps;
+    const double *faces;
+    int nfaces;
+    const int64_t *cells;
+    int ncell;
+    const double *dnu, *wg;
+    int nb, ng, R;
+    uint32_t k0, k1;
+    Real tol;
+    int max_steps;
+    rmc_ray_record *out;
+};
+
+// All R rays of listed cells, drawn and marched with the same device functions as the
+// production path; one thread per ray (ordinal k recomputed from the earlier draws).
+template <class Real, bool PDF>
+__global__ void __launch_bounds__(256) k_trace(TraceArgs<Real> A)
+{
+    extern __shared__ double sf[];
+    for (int q = threadIdx.x; q < A.nfaces; q += blockDim.x) sf[q] = A.faces[q];
+    __syncthreads();
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)A.ncell * A.R) return;
+    const int q = (int)(idx / A.R), r = (int)(idx - (int64_t)q * A.R);
+    const SnapDesc &D = A.snaps[0];
+    const int64_t c64 = A.cells[q];
+    const uint32_t c = (uint32_t)c64;
+    const int i = (int)(c64 / ((int64_t)D.ny * D.nz));
+    const int j = (int)((c64 / D.nz) % D.ny);
+    const int k = (int)(c64 % D.nz);
+    const Draw d = draw_ray<PDF>(D, A.nb, A.ng, c, (uint32_t)r, A.k0, A.k1);
+    uint32_t kord = 0;
+    for (int r2 = 0; r2 < r; ++r2) {
+        const Draw e = draw_ray<PDF>(D, A.nb, A.ng, c, (uint32_t)r2, A.k0, A.k1);
+        kord += (e.n == d.n && e.g == d.g && e.o == d.o) ? 1u : 0u;
+    }
+    const int pair = d.n * A.ng + d.g;
+    const Real *K = reinterpret_cast<const Real *>(D.kap) + (size_t)pair * D.ncpad;
+    const double *Ipl = D.Ipl + (size_t)d.n * D.ncpad;
+    uint32_t v[4];
+    philox4x32_10(c, ((uint32_t)d.n << 16) | ((uint32_t)d.g << 8) | (uint32_t)d.o, kord,
+                  (D.snap_id << 4) | kTagDir, A.k0, A.k1, v);
+    double dx, dy, dz;
+    octant_direction(v[0], v[1], d.o, dx, dy, dz);
+    const RayGeo G = ray_geo(D, sf);
+    const int csrc = brick_x(i, G.bsx) + brick_y(j, G.bsy) + brick_z(k);
+    const Real kap_src = K[csrc];
+    const MarchOut<Real> m = march_ray<Real, false>(G, K, Ipl, i, j, k, dx, dy, dz, Ipl[csrc], D.Iw[d.n],
+                                                    D.Iw[A.nb + d.n], A.tol, A.max_steps);
+    const double w = 4.0 * M_PI * A.dnu[d.n] * A.wg[d.g] / (8.0 * d.p);
+    rmc_ray_record rec;
+    rec.Y = w * (double)kap_src * (double)m.acc;
+    rec.p = d.p;
+    rec.n = d.n; rec.g = d.g; rec.o = d.o; rec.k = (int32_t)kord;
+    rec.steps = m.steps;
+    rec.end = m.end;
+    A.out[idx] = rec;
+}
+
+// -------------------------------------------------------------------------- reduce
+// Mean of the R ray values of each cell (Eq. 8) and its standard error; total steps.
+template <class Real>
+__global__ void __launch_bounds__(256) k_reduce(const Real *__restrict__ Y, const uint32_t *__restrict__ st,
+                                                uint64_t nc, int R, int accum, double *__restrict__ divq,
+                                                double *__restrict__ se, unsigned long long *counters)
+{
+    const uint64_t c = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    unsigned long long steps = 0, capped = 0;
+    if (c < nc) {
+        const Real *y = Y + c * R;
+        const uint32_t *sc = st + c * R;
+        double mean;
+        if (accum == RMC_ACC_F64) {
+            double sum = 0.0;
+            for (int r = 0; r < R; ++r) sum += (double)y[r];
+            mean = sum / R;
+        } else if (accum == RMC_ACC_COMP_F32) {
+            float sum = 0.0f, comp = 0.0f;   // Neumaier's compensated summation
+            for (int r = 0; r < R; ++r) {
+                const float v = (float)y[r];
+                const float t = sum + v;
+                if (fabsf(sum) >= fabsf(v)) comp += (sum - t) + v;
+                else comp += (v - t) + sum;
+                sum = t;
+            }
+            mean = (double)(sum + comp) / R;
+        } else {
+            float sum = 0.0f;
+            for (int r = 0; r < R; ++r) sum += (float)y[r];
+            mean = (double)sum / R;
+        }
+        double ss = 0.0;
+        for (int r = 0; r < R; ++r) {
+            const double dv = (double)y[r] - mean;
+            ss += dv * dv;
+            steps += sc[r] & 0x0FFFFFFFu;
+            capped += (sc[r] >> 28) == (uint32_t)kEndCap ? 1ull : 0ull;
+        }
+        divq[c] = mean;
+        if (se) se[c] = R > 1 ? sqrt(ss / (R - 1) / R) : 0.0;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        steps += __shfl_xor(steps, off);
+        capped += __shfl_xor(capped, off);
+    }
+    if ((threadIdx.x & 63) == 0 && (steps | capped)) {
+        atomicAdd(counters, steps);
+        atomicAdd(counters + 1, capped);
+        atomicAdd(counters + 2, steps);
+    }
+}
+
+}  // namespace
+
+// ============================================================================ host side
+namespace {
+
+thread_local std::string g_err;
+
+rmc_status fail(rmc_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIPCHK(expr)                                                                            \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess) {                                                                 \
+            (void)hipGetLastError();                                                            \
+            return fail(e_ == hipErrorOutOfMemory ? RMC_OUT_OF_MEMORY : RMC_DEVICE_ERROR,       \
+                        "%s failed: %s", #expr, hipGetErrorString(e_));                         \
+        }                                                                                       \
+    } while (0)
+
+struct DBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    rmc_status ensure(size_t want)
+    {
+        if (want <= bytes && p) return RMC_OK;
+        if (p) { (void)hipFree(p); p = nullptr; bytes = 0; }
+        if (want == 0) want = 16;
+        hipError_t e = hipMalloc(&p, want);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+            return fail(RMC_OUT_OF_MEMORY, "hipMalloc of %zu bytes failed: %s", want, hipGetErrorString(e));
+        }
+        bytes = want;
+        return RMC_OK;
+    }
+    template <class T> T *as() const { return static_cast<T *>(p); }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+};
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
+}  // namespace
+
+struct rmc_ctx {
+    int device = 0;
+    // grid
+    bool have_grid = false;
+    int nx = 0, ny = 0, nz = 0;
+    std::vector<double> xf, yf, zf;
+    // walls
+    bool have_walls = false;
+    double Tw[2] = {0, 0};
+    // tables
+    bool have_kdist = false;
+    int nb = 0, ng = 0, ns = 0, nT = 0;
+    double T0 = 0, dT = 1;
+    DBuf k64, Ib, dnu, wg;
+    // fields
+    bool have_T = false, have_X = false;
+    DBuf T, X, stage;
+    double Tmax_cells = 0;
+    double xhat[8] = {0};
+    // options
+    rmc_options opt{};
+    // per-cell pdf mode
+    bool have_q = false;
+    DBuf q, cpdf, ccdf_b, ccdf_g, ccdf_o;
+    // pdf and fields of the last compute
+    DBuf pdf_scratch, p, cdf_b, cdf_g, W, Iw, status;
+    DBuf field, Iplane;     // kappa planes (march precision) and FP64 intensity planes
+    // slots
+    DBuf Y, st;
+    int slots_R = 0, slots_real = 0;
+    // shared pipeline workspace (used when this context leads a batch)
+    DBuf hist, bucket_total, bucket_start, nchunks, chunk_bucket, items, faces, snaps, tile_snap, counters,
+        outbuf;
+    DBuf trace_rec, trace_cells;
+    DBuf small;             // ingest results
+    // timing: a ring of event sets, one per compute in flight; counters[0..1] are the last
+    // compute's steps / capped rays, counters[2] the steps accumulated since the last reset
+    struct EvSet {
+        hipEvent_t e[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+        bool pending = false;
+        int64_t rays = 0;
+    };
+    std::vector<EvSet> ring;
+    size_t ring_head = 0;
+    int last_set = -1;
+    bool have_counters = false;
+    float last_ms[4] = {0, 0, 0, 0};
+    int64_t last_rays = 0;
+    int64_t n_computes = 0, sum_rays = 0;
+    double sum_ms[4] = {0, 0, 0, 0};
+};
+
+namespace {
+
+uint64_t ncells_of(const rmc_ctx *c) { return (uint64_t)c->nx * c->ny * c->nz; }
+uint64_t ncpad_of(const rmc_ctx *c)
+{
+    return (uint64_t)round_up(c->nx, 4) * round_up(c->ny, 4) * round_up(c->nz, 4);
+}
+
+rmc_status check_ctx(const rmc_ctx *c)
+{
+    if (!c) return fail(RMC_INVALID_ARG, "null context");
+    return RMC_OK;
+}
+
+rmc_status check_options(const rmc_options *o)
+{
+    if (o->rays_per_cell < 1 || o->rays_per_cell > 255)
+        return fail(RMC_INVALID_ARG, "rays_per_cell must be in [1, 255] (got %d)", o->rays_per_cell);
+    if (o->snapshot >= (1u << 27)) return fail(RMC_INVALID_ARG, "snapshot must be < 2^27");
+    if (!(o->tol >= 0.0) || !std::isfinite(o->tol)) return fail(RMC_INVALID_ARG, "tol must be finite and >= 0");
+    if (o->max_steps < 1 || o->max_steps >= (1 << 28))
+        return fail(RMC_INVALID_ARG, "max_steps must be in [1, 2^28)");
+    if (o->march != RMC_F32 && o->march != RMC_F64) return fail(RMC_INVALID_ARG, "march must be RMC_F32 or RMC_F64");
+    if (o->accum != RMC_ACC_F64 && o->accum != RMC_ACC_COMP_F32 && o->accum != RMC_ACC_F32)
+        return fail(RMC_INVALID_ARG, "bad accum");
+    if (o->sampling != RMC_SAMPLING_PLAIN && o->sampling != RMC_SAMPLING_PDF)
+        return fail(RMC_INVALID_ARG, "bad sampling");
+    if (o->sampling == RMC_SAMPLING_PDF && !(o->mix_eps >= 0.0 && o->mix_eps <= 1.0))
+        return fail(RMC_INVALID_ARG, "mix_eps must be in [0, 1]");
+    if (o->block_threads != 0 && o->block_threads != 256)
+        return fail(RMC_UNSUPPORTED, "block_threads: only 0 (default) and 256 are built");
+    for (int q = 0; q < 7; ++q)
+        if (o->reserved[q] != 0) return fail(RMC_INVALID_ARG, "reserved option fields must be zero");
+    return RMC_OK;
+}
+
+rmc_status check_ready(const rmc_ctx *c)
+{
+    if (!c->have_grid) return fail(RMC_BAD_STATE, "rmc_set_grid missing");
+    if (!c->have_walls) return fail(RMC_BAD_STATE, "rmc_set_walls missing");
+    if (!c->have_kdist) return fail(RMC_BAD_STATE, "rmc_set_kdist missing");
+    if (!c->have_T) return fail(RMC_BAD_STATE, "rmc_set_temperature missing");
+    if (!c->have_X) return fail(RMC_BAD_STATE, "rmc_set_species missing");
+    if (c->opt.sampling == RMC_SAMPLING_PDF && !c->have_q) return fail(RMC_BAD_STATE, "rmc_set_cell_pdf missing");
+    for (int s = 0; s < 2; ++s) {
+        const double u = (c->Tw[s] - c->T0) / c->dT;
+        if (!(u >= 0.0 && u <= (double)(c->nT - 1)))
+            return fail(RMC_OUT_OF_RANGE, "wall temperature %g outside the table range", c->Tw[s]);
+    }
+    if ((uint64_t)ncells_of(c) * c->opt.rays_per_cell >= (1ull << 32))
+        return fail(RMC_UNSUPPORTED, "ncells * R must stay below 2^32");
+    return RMC_OK;
+}
+
+template <class Real> rmc_status build_fields(rmc_ctx *c, const SnapDesc &D, hipStream_t s)
+{
+    const uint64_t ncpad = ncpad_of(c);
+    const int npairs = c->nb * c->ng;
+    rmc_status st;
+    if ((st = c->field.ensure(sizeof(Real) * ncpad * (uint64_t)npairs)) ||
+        (st = c->Iplane.ensure(sizeof(double) * ncpad * (uint64_t)c->nb)))
+        return st;
+    dim3 grid((unsigned)((ncpad + 255) / 256), (unsigned)std::min(npairs, 65535));
+    hipLaunchKernelGGL(k_fields<Real>, grid, dim3(256), 0, s, c->T.as<double>(), c->X.as<double>(), c->ns,
+                       ncells_of(c), c->k64.as<double>(), c->Ib.as<double>(), c->nb, c->ng, c->nT, c->T0, c->dT,
+                       D, c->field.as<Real>(), c->Iplane.as<double>());
+    HIPCHK(hipGetLastError());
+    return RMC_OK;
+}
+
+// per-snapshot preparation: pdf, fields, slots; fills the snapshot descriptor
+template <class Real> rmc_status prepare_snapshot(rmc_ctx *c, hipStream_t s, SnapDesc &D)
+{
+    rmc_status st;
+    const int nb = c->nb, ng = c->ng, nbucket = nb * ng * 8;
+    if ((st = c->pdf_scratch.ensure(sizeof(double) * (nb * ng + nb))) || (st = c->p.ensure(sizeof(double) * nb * ng)) ||
+        (st = c->cdf_b.ensure(sizeof(double) * nb)) || (st = c->cdf_g.ensure(sizeof(double) * nb * ng)) ||
+        (st = c->W.ensure(sizeof(double) * nbucket)) || (st = c->Iw.ensure(sizeof(double) * 2 * nb)) ||
+        (st = c->status.ensure(sizeof(int))))
+        return st;
+    PdfArgs A;
+    A.k64 = c->k64.as<double>();
+    A.Ib = c->Ib.as<double>();
+    A.dnu = c->dnu.as<double>();
+    A.wg = c->wg.as<double>();
+    A.nb = nb; A.ng = ng; A.ns = c->ns; A.nT = c->nT;
+    A.T0 = c->T0; A.dT = c->dT;
+    A.Tmax = std::max(c->Tmax_cells, std::max(c->Tw[0], c->Tw[1]));
+    A.Tw0 = c->Tw[0]; A.Tw1 = c->Tw[1];
+    for (int q = 0; q < 8; ++q) A.xhat[q] = q < c->ns ? c->xhat[q] : 0.0;
+    A.e = c->pdf_scratch.as<double>();
+    A.eb = A.e + nb * ng;
+    A.p = c->p.as<double>(); A.cdf_b = c->cdf_b.as<double>(); A.cdf_g = c->cdf_g.as<double>();
+    A.W = c->W.as<double>(); A.Iw = c->Iw.as<double>(); A.status = c->status.as<int>();
+    hipLaunchKernelGGL(k_plain_pdf, dim3(1), dim3(64), 0, s, A);
+    HIPCHK(hipGetLastError());
+
+    const uint64_t nc = ncells_of(c);
+    D = SnapDesc{};
+    D.nx = c->nx; D.ny = c->ny; D.nz = c->nz;
+    D.nbx = round_up(c->nx, 4) / 4; D.nby = round_up(c->ny, 4) / 4; D.nbz = round_up(c->nz, 4) / 4;
+    D.ncpad = ncpad_of(c);
+    D.snap_id = c->opt.snapshot;
+    D.Lx = c->xf[c->nx] - c->xf[0];
+    D.Lz = c->zf[c->nz] - c->zf[0];
+    D.W = c->W.as<double>(); D.Iw = c->Iw.as<double>();
+    D.p = c->p.as<double>(); D.cdf_b = c->cdf_b.as<double>(); D.cdf_g = c->cdf_g.as<double>();
+    if (c->opt.sampling == RMC_SAMPLING_PDF) {
+        const uint64_t m = (uint64_t)nb * ng * 8;
+        if ((st = c->cpdf.ensure(sizeof(double) * nc * m)) || (st = c->ccdf_b.ensure(sizeof(double) * nc * nb)) ||
+            (st = c->ccdf_g.ensure(sizeof(double) * nc * nb * ng)) || (st = c->ccdf_o.ensure(sizeof(double) * nc * m)))
+            return st;
+        hipLaunchKernelGGL(k_cell_pdf, dim3((unsigned)((nc + 127) / 128)), dim3(128), 0, s, c->q.as<double>(),
+                           c->p.as<double>(), nc, nb, ng, c->opt.mix_eps, c->cpdf.as<double>(),
+                           c->ccdf_b.as<double>(), c->ccdf_g.as<double>(), c->ccdf_o.as<double>());
+        HIPCHK(hipGetLastError());
+        D.cpdf = c->cpdf.as<double>(); D.ccdf_b = c->ccdf_b.as<double>();
+        D.ccdf_g = c->ccdf_g.as<double>(); D.ccdf_o = c->ccdf_o.as<double>();
+    }
+    if ((st = build_fields<Real>(c, D, s))) return st;
+    D.kap = c->field.p;
+    D.Ipl = c->Iplane.as<double>();
+    const int R = c->opt.rays_per_cell;
+    if ((st = c->Y.ensure(sizeof(Real) * nc * R)) || (st = c->st.ensure(sizeof(uint32_t) * nc * R))) return st;
+    c->slots_R = R;
+    c->slots_real = (int)sizeof(Real);
+    D.Y = c->Y.p;
+    D.st = c->st.as<uint32_t>();
+    return RMC_OK;
+}
+
+// wait for one event set and fold its phase times into the accumulated statistics
+rmc_status harvest(rmc_ctx *L, rmc_ctx::EvSet &set)
+{
+    HIPCHK(hipEventSynchronize(set.e[4]));
+    float t[4];
+    for (int q = 0; q < 4; ++q) HIPCHK(hipEventElapsedTime(&t[q], set.e[q], set.e[q + 1]));
+    for (int q = 0; q < 4; ++q) L->sum_ms[q] += t[q];
+    ++L->n_computes;
+    L->sum_rays += set.rays;
+    if (&set == &L->ring[L->last_set]) {
+        for (int q = 0; q < 4; ++q) L->last_ms[q] = t[q];
+        L->last_rays = set.rays;
+    }
+    set.pending = false;
+    return RMC_OK;
+}
+
+rmc_status harvest_all(rmc_ctx *L)
+{
+    if (L->ring.empty()) return RMC_OK;
+    const size_t n = L->ring.size();
+    for (size_t q = 0; q < n; ++q) {   // oldest first
+        rmc_ctx::EvSet &set = L->ring[(L->ring_head + q) % n];
+        if (set.pending)
+            if (rmc_status st = harvest(L, set)) return st;
+    }
+    return RMC_OK;
+}
+
+template <class Real>
+rmc_status run_pipeline(rmc_ctx *const *ctxs, int nsnap, double *const *divq, double *const *se, rmc_mem mem,
+                        hipStream_t s)
+{
+    rmc_ctx *L = ctxs[0];   // leader: owns the shared workspace and the timers
+    rmc_status st;
+    const rmc_options &O = L->opt;
+    const int nb = L->nb, ng = L->ng, nbucket = nb * ng * 8, R = O.rays_per_cell;
+    const bool pdf_mode = O.sampling == RMC_SAMPLING_PDF;
+    if ((st = L->counters.ensure(sizeof(unsigned long long) * 3))) return st;
+    if (!L->have_counters) {
+        HIPCHK(hipMemsetAsync(L->counters.p, 0, sizeof(unsigned long long) * 3, s));
+        L->have_counters = true;
+    }
+    if (L->ring.empty()) {
+        L->ring.resize(256);
+        for (auto &set : L->ring)
+            for (auto &e : set.e) HIPCHK(hipEventCreate(&e));
+    }
+    const int set_idx = (int)(L->ring_head % L->ring.size());
+    rmc_ctx::EvSet &EV = L->ring[set_idx];
+    if (EV.pending && (st = harvest(L, EV))) return st;
+    HIPCHK(hipEventRecord(EV.e[0], s));
+    // 1-2. per-snapshot pdf, fields and slots
+    std::vector<SnapDesc> D(nsnap);
+    uint64_t total_cells = 0, total_ncpad = 0;
+    int nfaces = 0;
+    for (int q = 0; q < nsnap; ++q) {
+        if ((st = prepare_snapshot<Real>(ctxs[q], s, D[q]))) return st;
+        D[q].face_off = nfaces;
+        nfaces += ctxs[q]->nx + ctxs[q]->ny + ctxs[q]->nz + 3;
+        total_cells += ncells_of(ctxs[q]);
+        total_ncpad += D[q].ncpad;
+    }
+    if ((size_t)nfaces * sizeof(double) > 48 * 1024)
+        return fail(RMC_UNSUPPORTED, "face tables of all snapshots exceed 48 KiB of LDS");
+    // tiles: about 1024 in total, whole bricks
+    int tile_cells = (int)std::min<uint64_t>(8192, std::max<uint64_t>(256, (total_ncpad / 1024 + 63) / 64 * 64));
+    int ntiles = 0;
+    std::vector<int> tile_snap;
+    for (int q = 0; q < nsnap; ++q) {
+        D[q].tile_begin = ntiles;
+        D[q].ntiles = (int)((D[q].ncpad + tile_cells - 1) / tile_cells);
+        ntiles += D[q].ntiles;
+        for (int t = 0; t < D[q].ntiles; ++t) tile_snap.push_back(q);
+    }
+    std::vector<double> faces;
+    faces.reserve(nfaces);
+    for (int q = 0; q < nsnap; ++q) {
+        for (double v : ctxs[q]->xf) faces.push_back(v);
+        for (double v : ctxs[q]->yf) faces.push_back(v);
+        for (double v : ctxs[q]->zf) faces.push_back(v);
+    }
+    const uint64_t max_items = (total_cells * R + (uint64_t)nbucket * 63 + 63) / 64 * 64;
+    const uint64_t max_chunks = max_items / 64;
+    if (max_items >= (1ull << 32)) return fail(RMC_UNSUPPORTED, "more than 2^32 rays in one pass");
+    if ((st = L->hist.ensure(sizeof(uint32_t) * (uint64_t)nbucket * ntiles)) ||
+        (st = L->bucket_total.ensure(sizeof(uint32_t) * nbucket)) ||
+        (st = L->bucket_start.ensure(sizeof(uint32_t) * (nbucket + 1))) ||
+        (st = L->nchunks.ensure(sizeof(uint32_t))) ||
+        (st = L->chunk_bucket.ensure(sizeof(uint32_t) * max_chunks)) ||
+        (st = L->items.ensure(sizeof(uint2) * max_items)) || (st = L->faces.ensure(sizeof(double) * nfaces)) ||
+        (st = L->snaps.ensure(sizeof(SnapDesc) * nsnap)) || (st = L->tile_snap.ensure(sizeof(int) * ntiles)))
+        return st;
+    HIPCHK(hipMemcpyAsync(L->faces.p, faces.data(), sizeof(double) * nfaces, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(L->snaps.p, D.data(), sizeof(SnapDesc) * nsnap, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(L->tile_snap.p, tile_snap.data(), sizeof(int) * ntiles, hipMemcpyHostToDevice, s));
+    HIPCHK(hipEventRecord(EV.e[1], s));
+
+    // 3. allocation: histogram per tile, scan per bucket, layout, scatter
+    AllocArgs AA;
+    AA.snaps = L->snaps.as<SnapDesc>();
+    AA.tile_snap = L->tile_snap.as<int>();
+    AA.ntiles = ntiles;
+    AA.tile_cells = tile_cells;
+    AA.nb = nb; AA.ng = ng; AA.nbucket = nbucket; AA.R = R;
+    AA.k0 = (uint32_t)O.seed; AA.k1 = (uint32_t)(O.seed >> 32);
+    AA.hist = L->hist.as<uint32_t>();
+    AA.bucket_start = L->bucket_start.as<uint32_t>();
+    AA.items = L->items.as<uint2>();
+    const size_t lds_count = sizeof(uint32_t) * nbucket;
+    const size_t lds_scatter = sizeof(uint32_t) * (nbucket + 256);
+    if (pdf_mode) hipLaunchKernelGGL(k_alloc_count<true>, dim3(ntiles), dim3(256), lds_count, s, AA);
+    else hipLaunchKernelGGL(k_alloc_count<false>, dim3(ntiles), dim3(256), lds_count, s, AA);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_bucket_scan, dim3(nbucket), dim3(64), 0, s, L->hist.as<uint32_t>(), ntiles,
+                       L->bucket_total.as<uint32_t>());
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_bucket_layout, dim3(1), dim3(1024), 0, s, L->bucket_total.as<uint32_t>(), nbucket,
+                       L->bucket_start.as<uint32_t>(), L->nchunks.as<uint32_t>());
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_chunk_map, dim3((nbucket + 3) / 4), dim3(64, 4), 0, s, L->bucket_total.as<uint32_t>(),
+                       L->bucket_start.as<uint32_t>(), nbucket, L->chunk_bucket.as<uint32_t>(),
+                       L->items.as<uint2>());
+    HIPCHK(hipGetLastError());
+    if (pdf_mode) hipLaunchKernelGGL(k_alloc_scatter<true>, dim3(ntiles), dim3(256), lds_scatter, s, AA);
+    else hipLaunchKernelGGL(k_alloc_scatter<false>, dim3(ntiles), dim3(256), lds_scatter, s, AA);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(EV.e[2], s));
+
+    // 4. march: 4 wavefronts per block, grid sized for the worst-case chunk count
+    MarchArgs<Real> MA;
+    MA.snaps = L->snaps.as<SnapDesc>();
+    MA.faces = L->faces.as<double>();
+    MA.nfaces = nfaces;
+    MA.items = L->items.as<uint2>();
+    MA.chunk_bucket = L->chunk_bucket.as<uint32_t>();
+    MA.nchunks = L->nchunks.as<uint32_t>();
+    MA.dnu = L->dnu.as<double>();
+    MA.wg = L->wg.as<double>();
+    MA.nb = nb; MA.ng = ng; MA.R = R;
+    MA.k0 = AA.k0; MA.k1 = AA.k1;
+    MA.tol = (Real)O.tol;
+    MA.max_steps = O.max_steps;
+    const unsigned mblocks = (unsigned)((max_chunks + 3) / 4);
+    const size_t lds_faces = sizeof(double) * nfaces;
+    if (pdf_mode) hipLaunchKernelGGL((k_march<Real, true>), dim3(mblocks), dim3(256), lds_faces, s, MA);
+    else hipLaunchKernelGGL((k_march<Real, false>), dim3(mblocks), dim3(256), lds_faces, s, MA);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(EV.e[3], s));
+
+    // 5. per-cell reduction into the caller's buffers
+    HIPCHK(hipMemsetAsync(L->counters.p, 0, sizeof(unsigned long long) * 2, s));   // last-compute part only
+    for (int q = 0; q < nsnap; ++q) {
+        rmc_ctx *c = ctxs[q];
+        const uint64_t nc = ncells_of(c);
+        double *dq = divq[q], *sq = se ? se[q] : nullptr;
+        if (mem == RMC_HOST) {
+            if ((st = c->outbuf.ensure(sizeof(double) * 2 * nc))) return st;
+            dq = c->outbuf.as<double>();
+            sq = (se && se[q]) ? dq + nc : nullptr;
+        }
+        hipLaunchKernelGGL(k_reduce<Real>, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, s, c->Y.as<Real>(),
+                           c->st.as<uint32_t>(), nc, R, (int)O.accum, dq, sq, L->counters.as<unsigned long long>());
+        HIPCHK(hipGetLastError());
+        if (mem == RMC_HOST) {
+            HIPCHK(hipMemcpyAsync(divq[q], dq, sizeof(double) * nc, hipMemcpyDeviceToHost, s));
+            if (sq) HIPCHK(hipMemcpyAsync(se[q], sq, sizeof(double) * nc, hipMemcpyDeviceToHost, s));
+        }
+    }
+    HIPCHK(hipEventRecord(EV.e[4], s));
+    EV.pending = true;
+    EV.rays = (int64_t)total_cells * R;
+    L->last_set = set_idx;
+    ++L->ring_head;
+    return RMC_OK;
+}
+
+rmc_status validate_T(rmc_ctx *c, const void *src, rmc_dtype dt, rmc_mem mem, hipStream_t s)
+{
+    const uint64_t nc = ncells_of(c);
+    const size_t esz = dt == RMC_F32 ? 4 : 8;
+    rmc_status st;
+    if ((st = c->T.ensure(sizeof(double) * nc)) || (st = c->small.ensure(64))) return st;
+    const void *dsrc = src;
+    if (mem == RMC_HOST) {
+        if ((st = c->stage.ensure(esz * nc))) return st;
+        HIPCHK(hipMemcpyAsync(c->stage.p, src, esz * nc, hipMemcpyHostToDevice, s));
+        dsrc = c->stage.p;
+    }
+    HIPCHK(hipMemsetAsync(c->small.p, 0, 64, s));
+    unsigned long long *mx = c->small.as<unsigned long long>();
+    unsigned int *flag = reinterpret_cast<unsigned int *>(mx + 1);
+    const unsigned blocks = (unsigned)std::min<uint64_t>(4096, (nc + 255) / 256);
+    if (dt == RMC_F32)
+        hipLaunchKernelGGL(k_ingest_T<float>, dim3(blocks), dim3(256), 0, s, (const float *)dsrc, c->T.as<double>(),
+                           nc, c->T0, c->dT, c->nT, mx, flag);
+    else
+        hipLaunchKernelGGL(k_ingest_T<double>, dim3(blocks), dim3(256), 0, s, (const double *)dsrc,
+                           c->T.as<double>(), nc, c->T0, c->dT, c->nT, mx, flag);
+    HIPCHK(hipGetLastError());
+    unsigned long long host[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(host, c->small.p, 16, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if ((unsigned)host[1] & 1u) {
+        c->have_T = false;
+        return fail(RMC_OUT_OF_RANGE, "temperature outside the table range [%g, %g] or NaN", c->T0,
+                    c->T0 + c->dT * (c->nT - 1));
+    }
+    double m;
+    memcpy(&m, &host[0], 8);
+    c->Tmax_cells = m;
+    c->have_T = true;
+    return RMC_OK;
+}
+
+}  // namespace
+
+// ============================================================================ C ABI
+extern "C" {
+
+const char *rmc_last_error(void) { return g_err.c_str(); }
+
+void rmc_default_options(rmc_options *o)
+{
+    if (!o) return;
+    memset(o, 0, sizeof *o);
+    o->rays_per_cell = 16;
+    o->seed = 0;
+    o->snapshot = 0;
+    o->tol = 1e-6;
+    o->max_steps = 65536;
+    o->march = RMC_F32;
+    o->accum = RMC_ACC_F64;
+    o->sampling = RMC_SAMPLING_PLAIN;
+    o->mix_eps = 0.1;
+    o->block_threads = 0;
+}
+
+rmc_status rmc_create(int device, rmc_ctx **out)
+{
+    g_err.clear();
+    if (!out) return fail(RMC_INVALID_ARG, "null output pointer");
+    *out = nullptr;
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev == 0) {
+        (void)hipGetLastError();
+        return fail(RMC_DEVICE_ERROR, "no HIP device available");
+    }
+    if (device < 0 || device >= ndev) return fail(RMC_INVALID_ARG, "device %d out of range [0, %d)", device, ndev);
+    rmc_ctx *c = new (std::nothrow) rmc_ctx();
+    if (!c) return fail(RMC_OUT_OF_MEMORY, "context allocation failed");
+    c->device = device;
+    rmc_default_options(&c->opt);
+    *out = c;
+    return RMC_OK;
+}
+
+void rmc_destroy(rmc_ctx *c)
+{
+    if (!c) return;
+    {
+        DeviceGuard g(c->device);
+        (void)hipDeviceSynchronize();
+        DBuf *bufs[] = {&c->k64, &c->Ib, &c->dnu, &c->wg, &c->T, &c->X, &c->stage, &c->q, &c->cpdf, &c->ccdf_b,
+                        &c->ccdf_g, &c->ccdf_o, &c->pdf_scratch, &c->p, &c->cdf_b, &c->cdf_g, &c->W, &c->Iw,
+                        &c->status, &c->field, &c->Iplane, &c->Y, &c->st, &c->hist, &c->bucket_total, &c->bucket_start,
+                        &c->nchunks, &c->chunk_bucket, &c->items, &c->faces, &c->snaps, &c->tile_snap,
+                        &c->counters, &c->outbuf, &c->trace_rec, &c->trace_cells, &c->small};
+        for (DBuf *b : bufs) b->release();
+        for (auto &set : c->ring)
+            for (auto &ev : set.e) (void)hipEventDestroy(ev);
+    }
+    delete c;
+}
+
+rmc_status rmc_set_grid(rmc_ctx *c, int nx, int ny, int nz, const double *xf, const double *yf, const double *zf)
+{
+    g_err.clear();
+    if (rmc_status st = check_ctx(c)) return st;
+    if (nx < 1 || ny < 1 || nz < 1 || nx > 1023 || ny > 1023 || nz > 1023)
+        return fail(RMC_INVALID_ARG, "grid dimensions must be in [1, 1023]");
+    if (!xf || !yf || !zf) return fail(RMC_INVALID_ARG, "null face array");
+    auto mono = [](const double *f, int n) {
+        for (int q = 0; q <= n; ++q)
+            if (!std::isfinite(f[q]) || (q > 0 && !(f[q] > f[q - 1]))) return false;
+        return true;
+    };
+    if (!mono(xf, nx) || !mono(yf, ny) || !mono(zf, nz))
+        return fail(RMC_INVALID_ARG, "face coordinates must be finite and strictly increasing");
+    c->nx = nx; c->ny = ny; c->nz = nz;
+    c->xf.assign(xf, xf + nx + 1);
+    c->yf.assign(yf, yf + ny + 1);
+    c->zf.assign(zf, zf + nz + 1);
+    c->have_grid = true;
+    c->have_T = c->have_X = c->have_q = false;
+    return RMC_OK;
+}
+
+rmc_status rmc_set_walls(rmc_ctx *c, double T0, double T1, double e0, double e1)
+{
+    g_err.clear();
+    if (rmc_status st = check_ctx(c)) return st;
+    if (!std::isfinite(T0) || !std::isfinite(T1) || T0 < 0 || T1 < 0)
+        return fail(RMC_INVALID_ARG, "wall temperatures must be finite and >= 0");
+    if (e0 != 1.0 || e1 != 1.0) return fail(RMC_UNSUPPORTED, "only black walls (emissivity 1) are supported");
+    c->Tw[0] = T0;
+    c->Tw[1] = T1;
+    c->have_walls = true;
+    return RMC_OK;
+}
+
+rmc_status rmc_set_kdist(rmc_ctx *c, int nb, int ng, int ns, int nT, double T0, double dT, const double *dnu,
+                         const double *wg, const void *k, rmc_dtype kdt, const double *Ib)
+{
+    g_err.clear();
+    if (rmc_status st = check_ctx(c)) return st;
+    if (nb < 1 || nb > 4096 || ng < 1 || ng > 255 || ns < 1 || ns > 8 || nT < 2)
+        return fail(RMC_INVALID_ARG, "table sizes out of range");
+    if (nb * ng > 2000) return fail(RMC_UNSUPPORTED, "nb * ng must not exceed 2000");
+    if (!(std::isfinite(T0) && T0 >= 0.0 && std::isfinite(dT) && dT > 0.0))
+        return fail(RMC_INVALID_ARG, "T0 must be >= 0 and dT > 0");
+    if (!dnu || !wg || !k || !Ib) return fail(RMC_INVALID_ARG, "null table pointer");
+    if (kdt != RMC_F32 && kdt != RMC_BF16) return fail(RMC_INVALID_ARG, "k dtype must be RMC_F32 or RMC_BF16");
+    const size_t nk = (size_t)ns * nb * ng * nT;
+    std::vector<double> k64(nk);
+    for (size_t q = 0; q < nk; ++q) {
+        double v;
+        if (kdt == RMC_F32) v = ((const float *)k)[q];
+        else {
+            uint32_t u = (uint32_t)((const uint16_t *)k)[q] << 16;
+            float f;
+            memcpy(&f, &u, 4);
+            v = f;
+        }
+        if (!(v >= 0.0 && std::isfinite(v))) return fail(RMC_INVALID_ARG, "absorption coefficients must be finite and >= 0");
+        k64[q] = v;
+    }
+    for (int q = 0; q < nb; ++q)
+        if (!(dnu[q] > 0.0 && std::isfinite(dnu[q]))) return fail(RMC_INVALID_ARG, "band widths must be > 0");
+    for (int q = 0; q < ng; ++q)
+        if (!(wg[q] > 0.0 && std::isfinite(wg[q]))) return fail(RMC_INVALID_ARG, "quadrature weights must be > 0");
+    for (size_t q = 0; q < (size_t)nb * nT; ++q)
+        if (!(Ib[q] >= 0.0 && std::isfinite(Ib[q]))) return fail(RMC_INVALID_ARG, "Planck table must be finite and >= 0");
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(RMC_DEVICE_ERROR, "hipSetDevice(%d) failed", c->device);
+    rmc_status st;
+    if ((st = c->k64.ensure(sizeof(double) * nk)) || (st = c->Ib.ensure(sizeof(double) * nb * nT)) ||
+        (st = c->dnu.ensure(sizeof(double) * nb)) || (st = c->wg.ensure(sizeof(double) * ng)))
+        return st;
+    HIPCHK(hipMemcpy(c->k64.p, k64.data(), sizeof(double) * nk, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->Ib.p, Ib, sizeof(double) * nb * nT, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->dnu.p, dnu, sizeof(double) * nb, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->wg.p, wg, sizeof(double) * ng, hipMemcpyHostToDevice));
+    const bool same_range = c->have_kdist && c->T0 == T0 && c->dT == dT && c->nT == nT;
+    c->nb = nb; c->ng = ng; c->nT = nT; c->T0 = T0; c->dT = dT;
+    if (c->ns != ns) c->have_X = false;
+    c->ns = ns;
+    c->have_kdist = true;
+    if (!same_range) c->have_T = false;   // temperatures must be re-validated against the new range
+    c->have_q = false;
+    return RMC_OK;
+}
+
+rmc_status rmc_set_temperature(rmc_ctx *c, const void *T, rmc_dtype dt, rmc_mem mem, void *stream)
+{
+    g_err.clear();
+    if (rmc_status st = check_ctx(c)) return st;
+    if (!c->have_grid || !c->have_kdist) return fail(RMC_BAD_STATE, "set_grid and set_kdist must come first");
+    if (!T) return fail(RMC_INVALID_ARG, "null temperature pointer");
+    if (dt != RMC_F32 && dt != RMC_F64) return fail(RMC_INVALID_ARG, "temperature dtype must be RMC_F32 or RMC_F64");
+    if (mem != RMC_HOST && mem != RMC_DEVICE) return fail(RMC_INVALID_ARG, "bad memory kind");
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(RMC_DEVICE_ERROR, "hipSetDevice(%d) failed", c->device);
+    return validate_T(c, T, dt, mem, (hipStream_t)stream);
+}
+
+rmc_status rmc_set_species(rmc_ctx *c, int ns, const void *X, rmc_dtype dt, rmc_mem mem, void *stream)
+{
+    g_err.clear();
+    if (rmc_status st = check_ctx(c)) return st;
+    if (!c->have_grid || !c->have_kdist) return fail(RMC_BAD_STATE, "set_grid and set_kdist must come first");
+    if (ns != c->ns) return fail(RMC_INVALID_ARG, "ns = %d does not match the tables (%d)", ns, c->ns);
+    if (!X) return fail(RMC_INVALID_ARG, "null species pointer");
+    if (dt != RMC_F32 && dt != RMC_F64) return fail(RMC_INVALID_ARG, "species dtype must be RMC_F32 or RMC_F64");
+    if (mem != RMC_HOST && mem != RMC_DEVICE) return fail(RMC_INVALID_ARG, "bad memory kind");
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(RMC_DEVICE_ERROR, "hipSetDevice(%d) failed", c->device);
+    hipStream_t s = (hipStream_t)stream;
+    const uint64_t nc = ncells_of(c);
+    const size_t esz = dt == RMC_F32 ? 4 : 8;
+    rmc_status st;
+    if ((st = c->X.ensure(sizeof(double) * nc * ns)) || (st = c->small.ensure(128))) return st;
+    const void *dsrc = X;
+    if (mem == RMC_HOST) {
+        if ((st = c->stage.ensure(esz * nc * ns))) return st;
+        HIPCHK(hipMemcpyAsync(c->stage.p, X, esz * nc * ns, hipMemcpyHostToDevice, s));
+        dsrc = c->stage.p;
+    }
+    HIPCHK(hipMemsetAsync(c->small.p, 0, 128, s));
+    unsigned long long *mx = c->small.as<unsigned long long>();
+    unsigned int *flag = reinterpret_cast<unsigned int *>(mx + 8);
+    const unsigned blocks = (unsigned)std::min<uint64_t>(4096, (nc + 255) / 256);
+    if (dt == RMC_F32)
+        hipLaunchKernelGGL(k_ingest_X<float>, dim3(blocks), dim3(256), 0, s, (const float *)dsrc, c->X.as<double>(),
+                           nc, ns, mx, flag);
+    else
+        hipLaunchKernelGGL(k_ingest_X<double>, dim3(blocks), dim3(256), 0, s, (const double *)dsrc,
+                           c->X.as<double>(), nc, ns, mx, flag);
+    HIPCHK(hipGetLastError());
+    unsigned long long host[9] = {0};
+    HIPCHK(hipMemcpyAsync(host, c->small.p, sizeof host, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if ((unsigned)host[8] & 1u) {
+        c->have_X = false;
+        return fail(RMC_OUT_OF_RANGE, "mole fractions must be finite and >= 0");
+    }
+    for (int q = 0; q < ns; ++q) memcpy(&c->xhat[q], &host[q], 8);
+    c->have_X = true;
+    return RMC_OK;
+}
+
+rmc_status rmc_set_options(rmc_ctx *c, const rmc_options *o)
+{
+    g_err.clear();
+    if (rmc_status st = check_ctx(c)) return st;
+    if (!o) return fail(RMC_INVALID_ARG, "null options");
+    if (rmc_status st = check_options(o)) return st;
+    c->opt = *o;
+    return RMC_OK;
+}
+
+rmc_status rmc_set_cell_pdf(rmc_ctx *c, const double *q, rmc_mem mem, void *stream)
+{
+    g_err.clear();
+    if (rmc_status st = check_ctx(c)) return st;
+    if (!c->have_grid || !c->have_kdist) return fail(RMC_BAD_STATE, "set_grid and set_kdist must come first");
+    if (!q) return fail(RMC_INVALID_ARG, "null pdf pointer");
+    const uint64_t n = ncells_of(c) * (uint64_t)c->nb * c->ng * 8;
+    if (n > (1ull << 27)) return fail(RMC_UNSUPPORTED, "per-cell pdf larger than 2^27 entries");
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(RMC_DEVICE_ERROR, "hipSetDevice(%d) failed", c->device);
+    rmc_status st;
+    if ((st = c->q.ensure(sizeof(double) * n))) return st;
+    HIPCHK(hipMemcpyAsync(c->q.p, q, sizeof(double) * n,
+                          mem == RMC_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    c->have_q = true;
+    return RMC_OK;
+}
+
+rmc_status rmc_compute_batch(rmc_ctx *const *ctxs, int nsnap, double *const *divq, double *const *se, rmc_mem mem,
+                             void *stream)
+{
+    g_err.clear();
+    if (!ctxs || nsnap < 1 || nsnap > 32767 || !divq) return fail(RMC_INVALID_ARG, "bad batch arguments");
+    if (mem != RMC_HOST && mem != RMC_DEVICE) return fail(RMC_INVALID_ARG, "bad memory kind");
+    rmc_ctx *L = ctxs[0];
+    if (!L) return fail(RMC_INVALID_ARG, "null context");
+    for (int q = 0; q < nsnap; ++q) {
+        rmc_ctx *c = ctxs[q];
+        if (!c || !divq[q]) return fail(RMC_INVALID_ARG, "null context or output in the batch");
+        if (rmc_status st = check_ready(c)) return st;
+        if (c->device != L->device) return fail(RMC_INVALID_ARG, "batch contexts must share one device");
+        if (c->nb != L->nb || c->ng != L->ng || c->ns != L->ns || c->nT != L->nT || c->T0 != L->T0 ||
+            c->dT != L->dT)
+            return fail(RMC_INVALID_ARG, "batch contexts must share the tables");
+        const rmc_options &a = c->opt, &b = L->opt;
+        if (a.rays_per_cell != b.rays_per_cell || a.seed != b.seed || a.tol != b.tol || a.max_steps != b.max_steps ||
+            a.march != b.march || a.accum != b.accum || a.sampling != b.sampling)
+            return fail(RMC_INVALID_ARG, "batch contexts must share the options (snapshot ids may differ)");
+        for (int q2 = 0; q2 < q; ++q2)
+            if (ctxs[q2] == c) return fail(RMC_INVALID_ARG, "a context appears twice in the batch");
+    }
+    DeviceGuard g(L->device);
+    if (!g.ok) return fail(RMC_DEVICE_ERROR, "hipSetDevice(%d) failed", L->device);
+    hipStream_t s = (hipStream_t)stream;
+    if (L->opt.march == RMC_F64) return run_pipeline<double>(ctxs, nsnap, divq, se, mem, s);
+    return run_pipeline<float>(ctxs, nsnap, divq, se, mem, s);
+}
+
+rmc_status rmc_compute_divergence(rmc_ctx *c, double *divq, double *se, rmc_mem mem, void *stream)
+{
+    g_err.clear();
+    if (rmc_status st = check_ctx(c)) return st;
+    if (!divq) return fail(RMC_INVALID_ARG, "null output");
+    rmc_ctx *cs[1] = {c};
+    double *d[1] = {divq};
+    double *e[1] = {se};
+    return rmc_compute_batch(cs, 1, d, e, mem, stream);
+}
+
+rmc_status rmc_get_ray_values(rmc_ctx *c, const int64_t *cells, int ncell, double *Y, int32_t *steps, void *stream)
+{
+    g_err.clear();
+    if (rmc_status st = check_ctx(c)) return st;
+    if (!cells || ncell < 0 || !Y) return fail(RMC_INVALID_ARG, "bad arguments");
+    if (!c->slots_R) return fail(RMC_BAD_STATE, "no compute has run");
+    const uint64_t nc = ncells_of(c);
+    for (int q = 0; q < ncell; ++q)
+        if (cells[q] < 0 || (uint64_t)cells[q] >= nc) return fail(RMC_INVALID_ARG, "cell index out of range");
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(RMC_DEVICE_ERROR, "hipSetDevice(%d) failed", c->device);
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(hipStreamSynchronize(s));
+    const int R = c->slots_R;
+    std::vector<char> tmp((size_t)R * 8);
+    std::vector<uint32_t> st(R);
+    for (int q = 0; q < ncell; ++q) {
+        const size_t off = (size_t)cells[q] * R;
+        HIPCHK(hipMemcpy(tmp.data(), c->Y.as<char>() + off * c->slots_real, (size_t)R * c->slots_real,
+                         hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(st.data(), c->st.as<uint32_t>() + off, sizeof(uint32_t) * R, hipMemcpyDeviceToHost));
+        for (int r = 0; r < R; ++r) {
+            Y[(size_t)q * R + r] = c->slots_real == 4 ? (double)((const float *)tmp.data())[r]
+                                                       : ((const double *)tmp.data())[r];
+            if (steps) steps[(size_t)q * R + r] = (int32_t)(st[r] & 0x0FFFFFFFu);
+        }
+    }
+    return RMC_OK;
+}
+
+rmc_status rmc_trace_cells(rmc_ctx *c, const int64_t *cells, int ncell, rmc_ray_record *out, void *stream)
+{
+    g_err.clear();
+    if (rmc_status st = check_ctx(c)) return st;
+    if (!cells || ncell < 0 || !out) return fail(RMC_INVALID_ARG, "bad arguments");
+    if (rmc_status st = check_ready(c)) return st;
+    const uint64_t nc = ncells_of(c);
+    for (int q = 0; q < ncell; ++q)
+        if (cells[q] < 0 || (uint64_t)cells[q] >= nc) return fail(RMC_INVALID_ARG, "cell index out of range");
+    if (ncell == 0) return RMC_OK;
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(RMC_DEVICE_ERROR, "hipSetDevice(%d) failed", c->device);
+    hipStream_t s = (hipStream_t)stream;
+    const int R = c->opt.rays_per_cell;
+    const bool dbl = c->opt.march == RMC_F64;
+    const bool pdf_mode = c->opt.sampling == RMC_SAMPLING_PDF;
+    SnapDesc D;
+    rmc_status st = dbl ? prepare_snapshot<double>(c, s, D) : prepare_snapshot<float>(c, s, D);
+    if (st) return st;
+    const int nfaces = c->nx + c->ny + c->nz + 3;
+    D.face_off = 0;
+    std::vector<double> fd;
+    for (double v : c->xf) fd.push_back(v);
+    for (double v : c->yf) fd.push_back(v);
+    for (double v : c->zf) fd.push_back(v);
+    const size_t nrec = (size_t)ncell * R;
+    if ((st = c->faces.ensure(sizeof(double) * nfaces)) || (st = c->snaps.ensure(sizeof(SnapDesc))) ||
+        (st = c->trace_cells.ensure(sizeof(int64_t) * ncell)) ||
+        (st = c->trace_rec.ensure(sizeof(rmc_ray_record) * nrec)))
+        return st;
+    if (nfaces * 8 > 48 * 1024) return fail(RMC_UNSUPPORTED, "face tables exceed 48 KiB of LDS");
+    HIPCHK(hipMemcpyAsync(c->faces.p, fd.data(), (size_t)nfaces * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->snaps.p, &D, sizeof(SnapDesc), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->trace_cells.p, cells, sizeof(int64_t) * ncell, hipMemcpyHostToDevice, s));
+    const unsigned blocks = (unsigned)((nrec + 255) / 256);
+    const uint32_t k0 = (uint32_t)c->opt.seed, k1 = (uint32_t)(c->opt.seed >> 32);
+    if (dbl) {
+        TraceArgs<double> A{c->snaps.as<SnapDesc>(), c->faces.as<double>(), nfaces, c->trace_cells.as<int64_t>(),
+                            ncell, c->dnu.as<double>(), c->wg.as<double>(), c->nb, c->ng, R, k0, k1,
+                            c->opt.tol, c->opt.max_steps, c->trace_rec.as<rmc_ray_record>()};
+        if (pdf_mode) hipLaunchKernelGGL((k_trace<double, true>), dim3(blocks), dim3(256), 8 * nfaces, s, A);
+        else hipLaunchKernelGGL((k_trace<double, false>), dim3(blocks), dim3(256), 8 * nfaces, s, A);
+    } else {
+        TraceArgs<float> A{c->snaps.as<SnapDesc>(), c->faces.as<double>(), nfaces, c->trace_cells.as<int64_t>(),
+                           ncell, c->dnu.as<double>(), c->wg.as<double>(), c->nb, c->ng, R, k0, k1,
+                           (float)c->opt.tol, c->opt.max_steps, c->trace_rec.as<rmc_ray_record>()};
+        if (pdf_mode) hipLaunchKernelGGL((k_trace<float, true>), dim3(blocks), dim3(256), 8 * nfaces, s, A);
+        else hipLaunchKernelGGL((k_trace<float, false>), dim3(blocks), dim3(256), 8 * nfaces, s, A);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(out, c->trace_rec.p, sizeof(rmc_ray_record) * nrec, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return RMC_OK;
+}
+
+rmc_status rmc_get_pdf(rmc_ctx *c, double *p, double *cdf_b, double *cdf_g, double *T_max, void *stream)
+{
+    g_err.clear();
+    if (rmc_status st = check_ctx(c)) return st;
+    if (!c->p.p) return fail(RMC_BAD_STATE, "no compute has run");
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(RMC_DEVICE_ERROR, "hipSetDevice(%d) failed", c->device);
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(hipStreamSynchronize(s));
+    int status = 0;
+    HIPCHK(hipMemcpy(&status, c->status.p, sizeof(int), hipMemcpyDeviceToHost));
+    if (status) return fail(RMC_INVALID_ARG, "the spectral pdf has zero total emission at T_max");
+    if (p) HIPCHK(hipMemcpy(p, c->p.p, sizeof(double) * c->nb * c->ng, hipMemcpyDeviceToHost));
+    if (cdf_b) HIPCHK(hipMemcpy(cdf_b, c->cdf_b.p, sizeof(double) * c->nb, hipMemcpyDeviceToHost));
+    if (cdf_g) HIPCHK(hipMemcpy(cdf_g, c->cdf_g.p, sizeof(double) * c->nb * c->ng, hipMemcpyDeviceToHost));
+    if (T_max) *T_max = std::max(c->Tmax_cells, std::max(c->Tw[0], c->Tw[1]));
+    return RMC_OK;
+}
+
+rmc_status rmc_get_stats(rmc_ctx *c, rmc_stats *out)
+{
+    g_err.clear();
+    if (rmc_status st = check_ctx(c)) return st;
+    if (!out) return fail(RMC_INVALID_ARG, "null output");
+    if (c->last_set < 0) return fail(RMC_BAD_STATE, "no compute has run");
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(RMC_DEVICE_ERROR, "hipSetDevice(%d) failed", c->device);
+    if (rmc_status st = harvest_all(c)) return st;
+    unsigned long long cnt[3] = {0, 0, 0};
+    HIPCHK(hipMemcpy(cnt, c->counters.p, sizeof cnt, hipMemcpyDeviceToHost));
+    memset(out, 0, sizeof *out);
+    out->rays = c->last_rays;
+    out->steps = (int64_t)cnt[0];
+    out->capped_rays = (int64_t)cnt[1];
+    out->ms_prep = c->last_ms[0];
+    out->ms_alloc = c->last_ms[1];
+    out->ms_march = c->last_ms[2];
+    out->ms_reduce = c->last_ms[3];
+    out->ms_total = c->last_ms[0] + c->last_ms[1] + c->last_ms[2] + c->last_ms[3];
+    out->computes = c->n_computes;
+    out->sum_rays = c->sum_rays;
+    out->sum_steps = (int64_t)cnt[2];
+    out->sum_ms_prep = c->sum_ms[0];
+    out->sum_ms_alloc = c->sum_ms[1];
+    out->sum_ms_march = c->sum_ms[2];
+    out->sum_ms_reduce = c->sum_ms[3];
+    return RMC_OK;
+}
+
+rmc_status rmc_reset_stats(rmc_ctx *c)
+{
+    g_err.clear();
+    if (rmc_status st = check_ctx(c)) return st;
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(RMC_DEVICE_ERROR, "hipSetDevice(%d) failed", c->device);
+    if (rmc_status st = harvest_all(c)) return st;
+    c->n_computes = 0;
+    c->sum_rays = 0;
+    for (double &v : c->sum_ms) v = 0.0;
+    if (c->have_counters) {
+        HIPCHK(hipDeviceSynchronize());
+        HIPCHK(hipMemset(c->counters.as<unsigned long long>() + 2, 0, sizeof(unsigned long long)));
+    }
+    return RMC_OK;
+}
+
+}  // extern "C"

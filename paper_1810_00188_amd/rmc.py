@@ -1,0 +1,305 @@
+"""ctypes binding of ``librmc.so`` (the C ABI in ``include/rmc.h``).
+
+Argument marshalling only: every step of the solver runs in the HIP library.  Buffers may
+be numpy arrays (host memory) or torch tensors on a ROCm device (device memory, passed by
+pointer together with the current torch stream).  Importing this module loads the library
+and fails loudly if it has not been built; torch is imported lazily.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librmc.so")
+
+RMC_OK, RMC_INVALID_ARG, RMC_BAD_STATE, RMC_OUT_OF_RANGE, RMC_UNSUPPORTED, RMC_DEVICE_ERROR, \
+    RMC_OUT_OF_MEMORY = range(7)
+F32, F64, BF16 = 0, 1, 2
+HOST, DEVICE = 0, 1
+ACC = {"f64": 0, "comp32": 1, "f32": 2}
+SAMPLING_PLAIN, SAMPLING_PDF = 0, 1
+
+STATUS_NAMES = {0: "RMC_OK", 1: "RMC_INVALID_ARG", 2: "RMC_BAD_STATE", 3: "RMC_OUT_OF_RANGE",
+                4: "RMC_UNSUPPORTED", 5: "RMC_DEVICE_ERROR", 6: "RMC_OUT_OF_MEMORY"}
+
+
+class Options(C.Structure):
+    _fields_ = [("rays_per_cell", C.c_int32), ("seed", C.c_uint64), ("snapshot", C.c_uint32),
+                ("tol", C.c_double), ("max_steps", C.c_int32), ("march", C.c_int),
+                ("accum", C.c_int), ("sampling", C.c_int), ("mix_eps", C.c_double),
+                ("block_threads", C.c_int32), ("reserved", C.c_int32 * 7)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("rays", C.c_int64), ("steps", C.c_int64), ("capped_rays", C.c_int64),
+                ("ms_prep", C.c_double), ("ms_alloc", C.c_double), ("ms_march", C.c_double),
+                ("ms_reduce", C.c_double), ("ms_total", C.c_double),
+                ("computes", C.c_int64), ("sum_rays", C.c_int64), ("sum_steps", C.c_int64),
+                ("sum_ms_prep", C.c_double), ("sum_ms_alloc", C.c_double),
+                ("sum_ms_march", C.c_double), ("sum_ms_reduce", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class RayRecord(C.Structure):
+    _fields_ = [("Y", C.c_double), ("p", C.c_double), ("n", C.c_int32), ("g", C.c_int32),
+                ("o", C.c_int32), ("k", C.c_int32), ("steps", C.c_int32), ("end", C.c_int32)]
+
+
+RAY_DTYPE = np.dtype([("Y", "f8"), ("p", "f8"), ("n", "i4"), ("g", "i4"), ("o", "i4"),
+                      ("k", "i4"), ("steps", "i4"), ("end", "i4")])
+assert RAY_DTYPE.itemsize == C.sizeof(RayRecord)
+
+# every function declared in include/rmc.h: name -> (restype, argtypes)
+_VP = C.c_void_p
+SIGNATURES = {
+    "rmc_create": (C.c_int, [C.c_int, C.POINTER(_VP)]),
+    "rmc_destroy": (None, [_VP]),
+    "rmc_last_error": (C.c_char_p, []),
+    "rmc_set_grid": (C.c_int, [_VP, C.c_int, C.c_int, C.c_int, _VP, _VP, _VP]),
+    "rmc_set_walls": (C.c_int, [_VP, C.c_double, C.c_double, C.c_double, C.c_double]),
+    "rmc_set_kdist": (C.c_int, [_VP, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
+                                _VP, _VP, _VP, C.c_int, _VP]),
+    "rmc_set_temperature": (C.c_int, [_VP, _VP, C.c_int, C.c_int, _VP]),
+    "rmc_set_species": (C.c_int, [_VP, C.c_int, _VP, C.c_int, C.c_int, _VP]),
+    "rmc_default_options": (None, [C.POINTER(Options)]),
+    "rmc_set_options": (C.c_int, [_VP, C.POINTER(Options)]),
+    "rmc_set_cell_pdf": (C.c_int, [_VP, _VP, C.c_int, _VP]),
+    "rmc_compute_divergence": (C.c_int, [_VP, _VP, _VP, C.c_int, _VP]),
+    "rmc_compute_batch": (C.c_int, [C.POINTER(_VP), C.c_int, C.POINTER(_VP), C.POINTER(_VP),
+                                    C.c_int, _VP]),
+    "rmc_get_ray_values": (C.c_int, [_VP, _VP, C.c_int, _VP, _VP, _VP]),
+    "rmc_trace_cells": (C.c_int, [_VP, _VP, C.c_int, _VP, _VP]),
+    "rmc_get_pdf": (C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP]),
+    "rmc_get_stats": (C.c_int, [_VP, C.POINTER(Stats)]),
+    "rmc_reset_stats": (C.c_int, [_VP]),
+}
+
+
+class RmcError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+    lib = C.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+LIB = _load()
+
+
+def _check(status):
+    if status != RMC_OK:
+        raise RmcError(status, LIB.rmc_last_error().decode())
+
+
+def default_options(**kw) -> Options:
+    o = Options()
+    LIB.rmc_default_options(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def _is_torch(x):
+    return type(x).__module__.startswith("torch")
+
+
+def _stream(stream):
+    if stream is not None:
+        return stream
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _buf(x, dtype=None):
+    """(pointer, memory kind, keep-alive) of a numpy array or torch tensor."""
+    if _is_torch(x):
+        if not x.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return x.data_ptr(), (DEVICE if x.is_cuda else HOST), x
+    a = np.ascontiguousarray(x, dtype=dtype) if dtype is not None else np.ascontiguousarray(x)
+    return a.ctypes.data, HOST, a
+
+
+def _dtype_code(x):
+    name = str(x.dtype)
+    if "float32" in name:
+        return F32
+    if "float64" in name:
+        return F64
+    raise TypeError(f"unsupported dtype {x.dtype}")
+
+
+class Solver:
+    """One rmc context on one device."""
+
+    def __init__(self, device: int = 0):
+        h = C.c_void_p()
+        _check(LIB.rmc_create(int(device), C.byref(h)))
+        self.h = h
+        self.device = device
+        self.R = None
+        self.ncells = None
+        self._keep = []
+
+    def close(self):
+        if self.h:
+            LIB.rmc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------ setters
+    def set_grid(self, xf, yf, zf):
+        xf, yf, zf = (np.ascontiguousarray(a, dtype=np.float64) for a in (xf, yf, zf))
+        _check(LIB.rmc_set_grid(self.h, len(xf) - 1, len(yf) - 1, len(zf) - 1,
+                                xf.ctypes.data, yf.ctypes.data, zf.ctypes.data))
+        self.ncells = (len(xf) - 1) * (len(yf) - 1) * (len(zf) - 1)
+        self.nx, self.ny, self.nz = len(xf) - 1, len(yf) - 1, len(zf) - 1
+
+    def set_walls(self, T0, T1, eps0=1.0, eps1=1.0):
+        _check(LIB.rmc_set_walls(self.h, float(T0), float(T1), float(eps0), float(eps1)))
+
+    def set_kdist(self, kd):
+        if kd.k_dtype == "bf16":
+            from .inputs import bf16_bits
+            k = np.ascontiguousarray(bf16_bits(kd.k))
+            code = BF16
+        else:
+            k = np.ascontiguousarray(kd.k, dtype=np.float32)
+            code = F32
+        dnu = np.ascontiguousarray(kd.dnu, dtype=np.float64)
+        wg = np.ascontiguousarray(kd.wg, dtype=np.float64)
+        Ib = np.ascontiguousarray(kd.Ib, dtype=np.float64)
+        ns, nb, ng, nT = kd.k.shape
+        _check(LIB.rmc_set_kdist(self.h, nb, ng, ns, nT, float(kd.T0), float(kd.dT),
+                                 dnu.ctypes.data, wg.ctypes.data, k.ctypes.data, code,
+                                 Ib.ctypes.data))
+        self.nb, self.ng, self.ns = nb, ng, ns
+
+    def set_temperature(self, T, stream=None):
+        p, mem, keep = _buf(T)
+        _check(LIB.rmc_set_temperature(self.h, p, _dtype_code(keep), mem,
+                                       _stream(stream) if mem == DEVICE else stream))
+
+    def set_species(self, X, stream=None):
+        p, mem, keep = _buf(X)
+        ns = keep.shape[0] if keep.ndim == 2 else 1
+        _check(LIB.rmc_set_species(self.h, ns, p, _dtype_code(keep), mem,
+                                   _stream(stream) if mem == DEVICE else stream))
+
+    def set_options(self, opt: Options):
+        _check(LIB.rmc_set_options(self.h, C.byref(opt)))
+        self.R = opt.rays_per_cell
+        self.opt = opt
+
+    def set_cell_pdf(self, q, stream=None):
+        p, mem, keep = _buf(q, np.float64)
+        self._keep = [keep]
+        _check(LIB.rmc_set_cell_pdf(self.h, p, mem, _stream(stream) if mem == DEVICE else stream))
+
+    def set_workload(self, w, device_fields: bool = False, **opt_overrides):
+        """Load a paper_1810_00188_amd.inputs.Workload (fields in the dtype it declares)."""
+        self.set_grid(w.xf, w.yf, w.zf)
+        self.set_walls(*w.T_walls, *w.eps_walls)
+        self.set_kdist(w.kd)
+        fdt = np.float32 if w.field_dtype == "f32" else np.float64
+        T = np.ascontiguousarray(w.T, dtype=fdt)
+        X = np.ascontiguousarray(np.atleast_2d(w.X), dtype=fdt)
+        if device_fields:
+            import torch
+            dev = torch.device("cuda", self.device)
+            T, X = torch.from_numpy(T).to(dev), torch.from_numpy(X).to(dev)
+        self.set_temperature(T)
+        self.set_species(X)
+        kw = dict(rays_per_cell=w.R, seed=w.seed, snapshot=w.snap, tol=w.tol,
+                  max_steps=w.max_steps, march=F64 if w.march == "f64" else F32,
+                  accum=ACC[w.accum])
+        kw.update(opt_overrides)
+        self.set_options(default_options(**kw))
+
+    # ------------------------------------------------------------------ compute
+    def compute(self, divq=None, stderr=None, stream=None):
+        """Enqueue one compute.  With torch tensors the outputs stay on the device (the call
+        is asynchronous); with numpy arrays (or None) the results come back on the host."""
+        if divq is None:
+            divq = np.zeros(self.ncells)
+            if stderr is None:
+                stderr = np.zeros(self.ncells)
+        pd, mem, kd = _buf(divq)
+        ps, _, ks = _buf(stderr) if stderr is not None else (None, mem, None)
+        st = _stream(stream) if mem == DEVICE else stream
+        _check(LIB.rmc_compute_divergence(self.h, pd, ps, mem, st))
+        if mem == HOST:
+            import torch
+            torch.cuda.synchronize(self.device)
+        return divq, stderr
+
+    def ray_values(self, cells, stream=None):
+        cells = np.ascontiguousarray(cells, dtype=np.int64)
+        Y = np.zeros((len(cells), self.R))
+        S = np.zeros((len(cells), self.R), dtype=np.int32)
+        _check(LIB.rmc_get_ray_values(self.h, cells.ctypes.data, len(cells), Y.ctypes.data,
+                                      S.ctypes.data, stream))
+        return Y, S
+
+    def trace(self, cells, stream=None):
+        cells = np.ascontiguousarray(cells, dtype=np.int64)
+        out = np.zeros((len(cells), self.R), dtype=RAY_DTYPE)
+        _check(LIB.rmc_trace_cells(self.h, cells.ctypes.data, len(cells), out.ctypes.data, stream))
+        return out
+
+    def pdf(self, stream=None):
+        p = np.zeros((self.nb, self.ng))
+        cb = np.zeros(self.nb)
+        cg = np.zeros((self.nb, self.ng))
+        tm = C.c_double()
+        _check(LIB.rmc_get_pdf(self.h, p.ctypes.data, cb.ctypes.data, cg.ctypes.data,
+                               C.addressof(tm), stream))
+        return p, cb, cg, tm.value
+
+    def stats(self) -> dict:
+        s = Stats()
+        _check(LIB.rmc_get_stats(self.h, C.byref(s)))
+        return s.as_dict()
+
+    def reset_stats(self):
+        _check(LIB.rmc_reset_stats(self.h))
+
+
+def compute_batch(solvers: Sequence[Solver], divq: Sequence, stderr: Optional[Sequence] = None,
+                  stream=None):
+    """One pipeline pass over several snapshots (see rmc_compute_batch)."""
+    n = len(solvers)
+    hs = (C.c_void_p * n)(*[s.h.value for s in solvers])
+    bufs = [_buf(d) for d in divq]
+    mem = bufs[0][1]
+    dp = (C.c_void_p * n)(*[b[0] for b in bufs])
+    if stderr is not None:
+        sb = [_buf(e) for e in stderr]
+        sp = (C.c_void_p * n)(*[b[0] for b in sb])
+    else:
+        sp = None
+    st = _stream(stream) if mem == DEVICE else stream
+    _check(LIB.rmc_compute_batch(hs, n, dp, sp, mem, st))
+    if mem == HOST:
+        import torch
+        torch.cuda.synchronize(solvers[0].device)

@@ -1,0 +1,90 @@
+"""The C ABI: the built library loads (also without a GPU) and exports every function that
+include/rmc.h declares; the ctypes binding covers exactly that set; calls fail cleanly
+(status codes, never an abort) when no device is present."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rmc.h")
+LIB = os.path.join(ROOT, "paper_1810_00188_amd", "librmc.so")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:rmc_status|void|const char\s*\*)\s*(rmc_\w+)\s*\(",
+                                 text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_1810_00188_amd import build
+        build.build()
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_entry_points():
+    names = _declared()
+    for must in ("rmc_create", "rmc_destroy", "rmc_set_grid", "rmc_set_temperature",
+                 "rmc_set_species", "rmc_set_kdist", "rmc_compute_divergence",
+                 "rmc_compute_batch", "rmc_trace_cells"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_binding_covers_the_header(lib):
+    from paper_1810_00188_amd import rmc
+    assert sorted(rmc.SIGNATURES) == _declared()
+
+
+def test_struct_layouts_match_the_header(lib, tmp_path):
+    """sizeof and field offsets of the header's structs, as a C compiler lays them out."""
+    import subprocess
+    from paper_1810_00188_amd import rmc
+    structs = {"rmc_options": rmc.Options, "rmc_stats": rmc.Stats, "rmc_ray_record": rmc.RayRecord}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "rmc.h"', 'int main(void){']
+    for cname, cls in structs.items():
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            lines.append(f'printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0;}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                 check=True).stdout.splitlines())
+    for cname, cls in structs.items():
+        assert int(got[cname]) == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert int(got[f"{cname}.{f}"]) == getattr(cls, f).offset, (cname, f)
+    o = rmc.default_options()
+    assert o.rays_per_cell == 16 and o.tol == 1e-6 and o.max_steps == 65536
+
+
+def test_calls_without_a_device_return_status(lib):
+    from paper_1810_00188_amd import rmc
+    h = ctypes.c_void_p()
+    st = rmc.LIB.rmc_create(0, ctypes.byref(h))
+    try:
+        import torch
+        have_gpu = torch.cuda.is_available()
+    except Exception:
+        have_gpu = False
+    if have_gpu:
+        assert st == rmc.RMC_OK
+        rmc.LIB.rmc_destroy(h)
+    else:
+        assert st == rmc.RMC_DEVICE_ERROR
+        assert b"device" in rmc.LIB.rmc_last_error()
+    assert rmc.LIB.rmc_set_grid(None, 4, 4, 4, None, None, None) == rmc.RMC_INVALID_ARG
+    rmc.LIB.rmc_destroy(None)
