@@ -1,0 +1,112 @@
+"""Pins of the FP64 allocation-network reference: analytic backward against central finite
+differences, the loss gradient against finite differences, and the loss minimiser against
+its closed form p_s proportional to sqrt(E[h^2 | s])."""
+import numpy as np
+import pytest
+
+from oracle import mlp
+from paper_1810_00188_amd import inputs
+
+
+def test_parameter_count():
+    assert mlp.N_PARAMS == 9224
+
+
+def test_backward_matches_finite_differences():
+    rng = np.random.default_rng(0)
+    p = mlp.init_params(1)
+    for k in p:
+        p[k] = p[k] + 0.05 * rng.normal(size=p[k].shape)   # nonzero biases
+    x = rng.normal(size=(7, 3, mlp.N_IN))
+    dz = rng.normal(size=(7, 3, mlp.N_OUT))
+    z, cache = mlp.forward(p, x)
+    g = mlp.flatten(mlp.backward(p, cache, dz))
+    v = mlp.flatten(p)
+    h = 1e-6
+    idx = rng.choice(len(v), 300, replace=False)
+    for q in idx:
+        vp, vm = v.copy(), v.copy()
+        vp[q] += h
+        vm[q] -= h
+        fp = np.sum(dz * mlp.forward(mlp.unflatten(vp), x)[0])
+        fm = np.sum(dz * mlp.forward(mlp.unflatten(vm), x)[0])
+        fd = (fp - fm) / (2 * h)
+        assert abs(fd - g[q]) <= 1e-6 * max(1.0, abs(fd)), (q, fd, g[q])
+
+
+def _toy(nc=3, nb=2, ng=3, nray=40, seed=0):
+    rng = np.random.default_rng(seed)
+    p_plain = rng.dirichlet(np.ones(nb * ng)).reshape(nb, ng)
+    zg = rng.normal(size=(nc, nb, ng, 8))
+    cell_of = np.repeat(np.arange(nc), nray)
+    strata = rng.integers(0, nb * ng * 8, nc * nray)
+    p0 = np.repeat(p_plain.reshape(-1), 8)[strata] / 8
+    h = rng.normal(size=nc * nray) * rng.uniform(0.1, 3, nc * nray)
+    return zg, p_plain, cell_of, strata, h, p0
+
+
+def test_loss_gradient_matches_finite_differences():
+    zg, p_plain, cell_of, strata, h, p0 = _toy()
+    L, dz = mlp.allocation_loss(zg, p_plain, 0.1, cell_of, strata, h, p0)
+    hstep = 1e-6
+    rng = np.random.default_rng(3)
+    for q in rng.choice(zg.size, 60, replace=False):
+        a, b = zg.copy().ravel(), zg.copy().ravel()
+        a[q] += hstep
+        b[q] -= hstep
+        fd = (mlp.allocation_loss(a.reshape(zg.shape), p_plain, 0.1, cell_of, strata, h, p0)[0]
+              - mlp.allocation_loss(b.reshape(zg.shape), p_plain, 0.1, cell_of, strata, h, p0)[0]) / (2 * hstep)
+        assert abs(fd - dz.ravel()[q]) <= 1e-6 * max(1e-3, abs(fd))
+
+
+def test_loss_minimiser_is_sqrt_second_moment():
+    """With every stratum observed once per cell with weight h_s^2 (exact expectation), the
+    minimiser over free logits (eps = 0) is p_s = sqrt(H_s) / sum sqrt(H)."""
+    nb, ng = 2, 2
+    S = nb * ng * 8
+    rng = np.random.default_rng(5)
+    H = rng.uniform(0.01, 4.0, S)
+    p_plain = np.full((nb, ng), 1.0 / (nb * ng))
+    strata = np.arange(S)
+    p0 = np.full(S, 1.0 / S)
+    h = np.sqrt(H) * p0              # the estimator's value h/p0 has square H
+    cell_of = np.zeros(S, dtype=int)
+    z = np.zeros((1, nb, ng, 8))
+    m = np.zeros_like(z)
+    s2 = np.zeros_like(z)
+    for t in range(1, 6001):
+        L, dz = mlp.allocation_loss(z, p_plain, 0.0, cell_of, strata, h, p0)
+        v, m, s2 = mlp.adam_step(z.ravel(), dz.ravel(), m.ravel(), s2.ravel(), t, lr=0.02)
+        z, m, s2 = v.reshape(z.shape), m.reshape(z.shape), s2.reshape(z.shape)
+    p = mlp.cell_pdf(z, p_plain, 0.0).ravel()
+    target = np.sqrt(H) / np.sqrt(H).sum()
+    np.testing.assert_allclose(p, target, rtol=2e-3)
+
+
+def test_octant_frame_and_pdf_normalisation():
+    rng = np.random.default_rng(2)
+    z = rng.normal(size=(4, 2, 3, 8))
+    m = np.array([0, 1, 5, 7])
+    zg = mlp.octant_logits(z, m)
+    for c in range(4):
+        for o in range(8):
+            assert np.array_equal(zg[c, :, :, o], z[c, :, :, o ^ m[c]])
+    p = mlp.cell_pdf(zg, np.full((2, 3), 1 / 6), 0.2)
+    np.testing.assert_allclose(p.reshape(4, -1).sum(axis=1), 1.0, rtol=1e-14)
+    assert np.all(p >= 0.2 / 6 / 8 - 1e-18)
+
+
+def test_features_and_gradient():
+    w = inputs.channel(nx=6, ny=5, nz=4, nb=3, ng=2, amp=0.1).replace(T_walls=(300.0, 500.0))
+    g = mlp.gradient_T(w)
+    # a linear field in x (periodic central difference of a linear profile away from the seam)
+    T = np.broadcast_to((500.0 + 10.0 * np.arange(6))[:, None, None], (6, 5, 4)).reshape(-1)
+    gl = mlp.gradient_T(w.replace(T=T))
+    dx = w.xf[1] - w.xf[0]
+    np.testing.assert_allclose(gl[0][1:-1], 10.0 / dx, rtol=1e-12)
+    fc, m = mlp.cell_features(w)
+    assert fc.shape == (w.ncells, 3) and m.shape == (w.ncells,)
+    kpt = mlp.planck_mean_tables(w.kd)
+    assert kpt.shape == (1, w.kd.nT)
+    assert kpt[0, 100] == pytest.approx(10.0 / 0.1, rel=1e-6)   # table scaled to 10 m^-1 at x = 0.1
+    assert g.shape == (3, 6, 5, 4)
