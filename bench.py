@@ -36,29 +36,36 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle baseline sample (0 disables it)")
+    ap.add_argument("--long-ray-steps", type=int, default=0,
+                    help="steps a ray takes in the lane kernel before the segmented long-ray "
+                         "kernel continues it (0: library default)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy three times (the "
+                         "reference point that scales rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "march_traffic.json"),
                     help="HBM bytes per march launch measured by rocprofv3 (optional)")
     return ap.parse_args()
 
 
 def cpu_baseline(w, target_s):
-    """The oracle, as it stands, on a strided sample of the same workload's cells."""
-    import numpy as np
+    """The oracle, as it stands, on whole passes over the same workload, repeated with fresh
+    snapshot numbers (fresh random streams) until about target_s seconds have elapsed."""
     import oracle
-    P = oracle.Problem(w)
     threads = oracle.max_threads()
-    stride = 256
+    steps = 0
+    passes = 0
+    t0 = time.perf_counter()
     while True:
-        cells = np.arange(0, w.ncells, stride)
-        t0 = time.perf_counter()
-        _, _, steps = oracle.divergence(P, cells=cells, nthreads=threads)
+        P = oracle.Problem(w.replace(snap=w.snap + 1 + passes))
+        _, _, st = oracle.divergence(P, nthreads=threads)
+        steps += st
+        passes += 1
         dt = time.perf_counter() - t0
-        if dt >= 0.25 * target_s or stride == 1:
+        if dt >= target_s:
             break
-        stride = max(1, int(stride * max(dt, 1e-3) / target_s))
     return {"value": steps / dt, "unit": "ray-cell steps/s", "cores": threads, "kind": "oracle",
-            "sample": f"every {stride}th cell of the 64^3 channel ({len(cells)} cells x {w.R} rays, "
-                      f"{steps} steps, {dt:.1f} s)"}
+            "sample": f"{passes} whole passes of the 64^3 channel ({w.ncells} cells x {w.R} rays), "
+                      f"{steps} steps in {dt:.1f} s"}
 
 
 def main():
@@ -72,9 +79,18 @@ def main():
     from paper_1810_00188_amd import inputs, rmc
 
     dev = torch.device("cuda", 0)
+    if a.copy_probe:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_each_way": src.numel() * 4, "copies": 3}), flush=True)
+        return
     w = inputs.channel64()
     s = rmc.Solver(0)
-    s.set_workload(w)
+    overrides = {"long_ray_steps": a.long_ray_steps} if a.long_ray_steps else {}
+    s.set_workload(w, **overrides)
     T = torch.from_numpy(np.ascontiguousarray(w.T, dtype=np.float32)).to(dev)
     X = torch.from_numpy(np.ascontiguousarray(w.X, dtype=np.float32)).to(dev)
     dq = torch.zeros(w.ncells, dtype=torch.float64, device=dev)

@@ -74,8 +74,11 @@ typedef struct {
     rmc_accum accum;
     rmc_sampling sampling;
     double mix_eps;          /* RMC_SAMPLING_PDF: weight of the plain pdf in the mixture */
-    int32_t block_threads;   /* march launch: threads per block (64..1024, multiple of 64; 0 = default) */
-    int32_t reserved[7];     /* must be zero */
+    int32_t block_threads;   /* march launch: threads per block (0 = default 256; only 256 is built) */
+    int32_t long_ray_steps;  /* FP32 march on uniform x/z: rays still marching after this many steps
+                                are finished by 64 lanes in parallel segments (0 = default 256,
+                                >= max_steps disables it) */
+    int32_t reserved[6];     /* must be zero */
 } rmc_options;
 
 typedef struct {
@@ -166,6 +169,22 @@ rmc_status rmc_compute_divergence(rmc_ctx *ctx, double *divq, double *stderr_out
  * receive snapshot s.  Enqueued on `stream`. */
 rmc_status rmc_compute_batch(rmc_ctx *const *ctxs, int nsnap, double *const *divq,
                              double *const *stderr_out, rmc_mem mem, void *stream);
+
+/* A compute of one or more snapshots captured into a HIP graph, for callers that replay the
+ * same computation on new fields (a DNS loop): rmc_graph_capture plans the batch (allocates
+ * and uploads descriptors, runs nothing else), then captures the kernel sequence of one
+ * rmc_compute_batch with device outputs divq[s] / stderr[s] (nullable) on `stream`, which must
+ * not be the null stream.  rmc_graph_launch replays it: the replay reads the contexts' current
+ * temperature and species fields (rmc_set_temperature / rmc_set_species may be called between
+ * replays) and writes the same output buffers.  Any other set_* call on a captured context,
+ * or a compute that grows its buffers, invalidates the graph: launching it then returns
+ * RMC_BAD_STATE.  Replays do not update rmc_get_stats.  Destroy a graph before the contexts it
+ * captured. */
+typedef struct rmc_graph rmc_graph;
+rmc_status rmc_graph_capture(rmc_ctx *const *ctxs, int nsnap, double *const *divq,
+                             double *const *stderr_out, void *stream, rmc_graph **out);
+rmc_status rmc_graph_launch(rmc_graph *graph, void *stream);
+void rmc_graph_destroy(rmc_graph *graph);
 
 /* Per-ray values and step counts of the last compute for the listed cells (host arrays):
  * Y[ncell][R] (double) and steps[ncell][R] (int32, nullable).  Synchronises `stream`. */

@@ -53,6 +53,7 @@ struct SnapDesc {
     uint32_t snap_id;
     int tile_begin, ntiles;
     double Lx, Lz;
+    double hx, hz;              // cell widths along x and z when those axes are uniform
 };
 
 struct AllocArgs {
@@ -63,7 +64,7 @@ struct AllocArgs {
     uint32_t k0, k1;
     uint32_t *hist;             // [nbucket][ntiles]
     const uint32_t *bucket_start;
-    uint2 *items;
+    uint4 *items;               // (i | j<<10 | k<<20, r | k_ord<<8 | snapshot<<16, dir word 0, dir word 1)
 };
 
 struct Draw {
@@ -110,11 +111,45 @@ __device__ __forceinline__ bool brick_cell(const SnapDesc &D, uint64_t bc, int &
 }
 
 // --------------------------------------------------------------------- field ingest
-template <class Tin>
-__global__ void k_ingest_T(const Tin *__restrict__ in, double *__restrict__ out, uint64_t n, double T0,
-                           double dT, int nT, unsigned long long *maxbits, unsigned int *flag)
+// block-wide max of non-negative doubles, one atomic per block (on the bit pattern, which
+// orders non-negative doubles like the values)
+__device__ __forceinline__ void block_max_atomic(double mx, unsigned long long *dst)
 {
-    double mx = 0.0;
+    __shared__ double wm[16];
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) wm[wv] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = wm[0];
+        for (int q = 1; q < (int)(blockDim.x >> 6); ++q) m = fmax(m, wm[q]);
+        atomicMax(dst, (unsigned long long)__double_as_longlong(m));
+    }
+    __syncthreads();
+}
+
+// block-wide min of non-negative doubles, one atomic per block
+__device__ __forceinline__ void block_min_atomic(double mn, unsigned long long *dst)
+{
+    __shared__ double wm[16];
+    for (int off = 32; off > 0; off >>= 1) mn = fmin(mn, __shfl_xor(mn, off));
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) wm[wv] = mn;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = wm[0];
+        for (int q = 1; q < (int)(blockDim.x >> 6); ++q) m = fmin(m, wm[q]);
+        atomicMin(dst, (unsigned long long)__double_as_longlong(m));
+    }
+    __syncthreads();
+}
+
+template <class Tin>
+__global__ void __launch_bounds__(256) k_ingest_T(const Tin *__restrict__ in, double *__restrict__ out, uint64_t n,
+                                                  double T0, double dT, int nT, unsigned long long *maxbits,
+                                                  unsigned int *flag)
+{
+    double mx = 0.0, mn = INFINITY;
     bool bad = false;
     for (uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; q < n;
          q += (uint64_t)gridDim.x * blockDim.x) {
@@ -122,31 +157,41 @@ __global__ void k_ingest_T(const Tin *__restrict__ in, double *__restrict__ out,
         out[q] = v;
         const double u = (v - T0) / dT;
         if (!(u >= 0.0 && u <= (double)(nT - 1))) bad = true;
-        else mx = fmax(mx, v);
+        else { mx = fmax(mx, v); mn = fmin(mn, v); }
     }
-    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
-    if ((threadIdx.x & 63) == 0) atomicMax(maxbits, (unsigned long long)__double_as_longlong(mx));
     if (bad) atomicOr(flag, 1u);
+    block_max_atomic(mx, maxbits);
+    block_min_atomic(mn, maxbits + 2);
 }
 
 template <class Tin>
-__global__ void k_ingest_X(const Tin *__restrict__ in, double *__restrict__ out, uint64_t nc, int ns,
-                           unsigned long long *maxbits, unsigned int *flag)
+__global__ void __launch_bounds__(256) k_ingest_X(const Tin *__restrict__ in, double *__restrict__ out, uint64_t nc,
+                                                  int ns, unsigned long long *maxbits, unsigned int *flag)
 {
-    for (int s = 0; s < ns; ++s) {
-        double mx = 0.0;
+    for (int sp = 0; sp < ns; ++sp) {
+        double mx = 0.0, mn = INFINITY;
         bool bad = false;
         for (uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; q < nc;
              q += (uint64_t)gridDim.x * blockDim.x) {
-            const double v = (double)in[(size_t)s * nc + q];
-            out[(size_t)s * nc + q] = v;
+            const double v = (double)in[(size_t)sp * nc + q];
+            out[(size_t)sp * nc + q] = v;
             if (!(v >= 0.0 && v < INFINITY)) bad = true;
-            else mx = fmax(mx, v);
+            else { mx = fmax(mx, v); mn = fmin(mn, v); }
         }
-        for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
-        if ((threadIdx.x & 63) == 0) atomicMax(maxbits + s, (unsigned long long)__double_as_longlong(mx));
         if (bad) atomicOr(flag, 1u);
+        block_max_atomic(mx, maxbits + sp);
+        block_min_atomic(mn, maxbits + 8 + sp);
     }
+}
+
+__global__ void k_zero_u64(unsigned long long *p, int n)
+{
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0ull;
+}
+
+__global__ void k_zero_u32(uint32_t *p, int n)
+{
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
 }
 
 // ------------------------------------------------------------- spectral pdf (1 thread)
@@ -164,8 +209,8 @@ struct PdfArgs {
     const double *Ib;           // [nb][nT]
     const double *dnu, *wg;
     int nb, ng, ns, nT;
-    double T0, dT, Tmax, Tw0, Tw1;
-    double xhat[8];
+    double T0, dT, Tw0, Tw1;
+    const double *scal;         // [0]: max cell temperature, [1..ns]: largest mole fractions
     double *e;                  // scratch [nb*ng]
     double *eb;                 // scratch [nb]
     double *p, *cdf_b, *cdf_g, *W, *Iw;
@@ -174,46 +219,61 @@ struct PdfArgs {
 
 // e_{n,g} = pi dnu_n w_g kappa_{n,g}(T_max, xhat) I_n(T_max); p = e / E; cumulative sums in
 // index order (Eqs. 13, 16-17 at T_max, Zhang's sampling); W = 4 pi dnu w / (8 p / 8).
-__global__ void k_plain_pdf(PdfArgs A)
+// One block: the independent terms in parallel, every running sum by one thread in index
+// order (the same operations, in the same order, as the sequential definition).
+__global__ void __launch_bounds__(256) k_plain_pdf(PdfArgs A)
 {
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
-    const int nb = A.nb, ng = A.ng;
-    double E = 0.0;
-    for (int n = 0; n < nb; ++n) {
-        const double In = lerp_tab(A.Ib + (size_t)n * A.nT, A.nT, A.T0, A.dT, A.Tmax);
-        A.eb[n] = 0.0;
-        for (int g = 0; g < ng; ++g) {
-            double kap = 0.0;
-            for (int s = 0; s < A.ns; ++s) {
-                const double ks = lerp_tab(A.k64 + (((size_t)s * nb + n) * ng + g) * A.nT, A.nT, A.T0,
-                                           A.dT, A.Tmax);
-                kap += A.xhat[s] * ks;
-            }
-            const double v = M_PI * A.dnu[n] * A.wg[g] * kap * In;
-            A.e[n * ng + g] = v;
-            A.eb[n] += v;
+    const int nb = A.nb, ng = A.ng, npair = nb * ng;
+    __shared__ double E_sh;
+    double Tmax = A.Tw0 > A.Tw1 ? A.Tw0 : A.Tw1;
+    if (A.scal[0] > Tmax) Tmax = A.scal[0];
+    for (int pr = threadIdx.x; pr < npair; pr += blockDim.x) {
+        const int n = pr / ng, g = pr - (pr / ng) * ng;
+        const double In = lerp_tab(A.Ib + (size_t)n * A.nT, A.nT, A.T0, A.dT, Tmax);
+        double kap = 0.0;
+        for (int sp = 0; sp < A.ns; ++sp) {
+            const double ks = lerp_tab(A.k64 + (((size_t)sp * nb + n) * ng + g) * A.nT, A.nT, A.T0, A.dT, Tmax);
+            kap += A.scal[1 + sp] * ks;
         }
-        E += A.eb[n];
+        A.e[pr] = M_PI * A.dnu[n] * A.wg[g] * kap * In;
+    }
+    __syncthreads();
+    for (int n = threadIdx.x; n < nb; n += blockDim.x) {
+        double eb = 0.0;
+        for (int g = 0; g < ng; ++g) eb += A.e[n * ng + g];
+        A.eb[n] = eb;
         A.Iw[n] = lerp_tab(A.Ib + (size_t)n * A.nT, A.nT, A.T0, A.dT, A.Tw0);
         A.Iw[nb + n] = lerp_tab(A.Ib + (size_t)n * A.nT, A.nT, A.T0, A.dT, A.Tw1);
     }
-    if (!(E > 0.0)) {
-        // nothing emits at T_max (all I_b or kappa zero): every ray value is exactly zero for
-        // any positive pdf, so the uniform one is used
-        E = 0.0;
-        for (int n = 0; n < nb; ++n) {
-            A.eb[n] = 0.0;
-            for (int g = 0; g < ng; ++g) {
-                A.e[n * ng + g] = 1.0;
-                A.eb[n] += 1.0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double E = 0.0;
+        for (int n = 0; n < nb; ++n) E += A.eb[n];
+        if (!(E > 0.0)) {
+            // nothing emits at T_max (all I_b or kappa zero): every ray value is exactly zero
+            // for any positive pdf, so the uniform one is used
+            E = 0.0;
+            for (int n = 0; n < nb; ++n) {
+                A.eb[n] = 0.0;
+                for (int g = 0; g < ng; ++g) {
+                    A.e[n * ng + g] = 1.0;
+                    A.eb[n] += 1.0;
+                }
+                E += A.eb[n];
             }
-            E += A.eb[n];
         }
+        double run = 0.0;
+        for (int n = 0; n < nb; ++n) {
+            run += A.eb[n];
+            A.cdf_b[n] = run / E;
+        }
+        A.cdf_b[nb - 1] = 1.0;
+        E_sh = E;
+        *A.status = 0;
     }
-    double run = 0.0;
-    for (int n = 0; n < nb; ++n) {
-        run += A.eb[n];
-        A.cdf_b[n] = run / E;
+    __syncthreads();
+    const double E = E_sh;
+    for (int n = threadIdx.x; n < nb; n += blockDim.x) {
         double rg = 0.0;
         for (int g = 0; g < ng; ++g) {
             rg += A.e[n * ng + g];
@@ -222,14 +282,13 @@ __global__ void k_plain_pdf(PdfArgs A)
         }
         A.cdf_g[n * ng + ng - 1] = 1.0;
     }
-    A.cdf_b[nb - 1] = 1.0;
-    for (int n = 0; n < nb; ++n)
-        for (int g = 0; g < ng; ++g) {
-            const double prob = A.p[n * ng + g] / 8.0;
-            const double w = prob > 0.0 ? 4.0 * M_PI * A.dnu[n] * A.wg[g] / (8.0 * prob) : 0.0;
-            for (int o = 0; o < 8; ++o) A.W[(n * ng + g) * 8 + o] = w;
-        }
-    *A.status = 0;
+    __syncthreads();
+    for (int pr = threadIdx.x; pr < npair; pr += blockDim.x) {
+        const int n = pr / ng, g = pr - (pr / ng) * ng;
+        const double prob = A.p[pr] / 8.0;
+        const double w = prob > 0.0 ? 4.0 * M_PI * A.dnu[n] * A.wg[g] / (8.0 * prob) : 0.0;
+        for (int o = 0; o < 8; ++o) A.W[pr * 8 + o] = w;
+    }
 }
 
 // Per-cell allocation pdf p_c = (1 - eps) q_c / sum q_c + eps p_plain / 8 and its band,
@@ -282,38 +341,44 @@ __global__ void k_cell_pdf(const double *__restrict__ q, const double *__restric
 // field[(n*ng + g)][brick(i,j,k)] = {kappa_{n,g}(T_c, x_c), I_n(T_c)}: linear interpolation
 // of the tables in T (Sec. 2.2), mixture kappa = sum_s x_s k^s (FP64, then rounded to Real).
 template <class Real>
-__global__ void k_fields(const double *__restrict__ T, const double *__restrict__ X, int ns, uint64_t nc,
-                         const double *__restrict__ k64, const double *__restrict__ Ib, int nb, int ng, int nT,
-                         double T0, double dT, SnapDesc D, Real *__restrict__ kap_out, double *__restrict__ I_out)
+__global__ void __launch_bounds__(256) k_fields(const double *__restrict__ T, const double *__restrict__ X, int ns,
+                                                uint64_t nc, const double *__restrict__ k64,
+                                                const double *__restrict__ Ib, int nb, int ng, int nT, double T0,
+                                                double dT, SnapDesc D, Real *__restrict__ kap_out,
+                                                double *__restrict__ I_out)
 {
     const uint64_t bc = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
     if (bc >= D.ncpad) return;
     int i, j, k;
     const bool valid = brick_cell(D, bc, i, j, k);
-    uint64_t c = 0;
     int t = 0;
     double f = 0.0;
+    double x[8];
     if (valid) {
-        c = ((uint64_t)i * D.ny + j) * D.nz + k;
+        const uint64_t c = ((uint64_t)i * D.ny + j) * D.nz + k;
         const double u = (T[c] - T0) / dT;
         t = (int)floor(u);
         if (t > nT - 2) t = nT - 2;
         f = u - (double)t;
+        for (int sp = 0; sp < ns; ++sp) x[sp] = X[(size_t)sp * nc + c];
     }
-    for (int pair = blockIdx.y; pair < nb * ng; pair += gridDim.y) {
-        const int n = pair / ng, g = pair - (pair / ng) * ng;
-        double kap = 0.0, I = 0.0;
+    for (int n = blockIdx.y; n < nb; n += gridDim.y) {
+        double I = 0.0;
         if (valid) {
-            for (int s = 0; s < ns; ++s) {
-                const double *tab = k64 + (((size_t)s * nb + n) * ng + g) * nT;
-                const double ks = tab[t] + f * (tab[t + 1] - tab[t]);
-                kap += X[(size_t)s * nc + c] * ks;
-            }
             const double *ib = Ib + (size_t)n * nT;
             I = ib[t] + f * (ib[t + 1] - ib[t]);
         }
-        kap_out[(size_t)pair * D.ncpad + bc] = (Real)kap;
-        if (g == 0) I_out[(size_t)n * D.ncpad + bc] = I;
+        I_out[(size_t)n * D.ncpad + bc] = I;
+        for (int g = 0; g < ng; ++g) {
+            double kap = 0.0;
+            if (valid)
+                for (int sp = 0; sp < ns; ++sp) {
+                    const double *tab = k64 + (((size_t)sp * nb + n) * ng + g) * nT;
+                    const double ks = tab[t] + f * (tab[t + 1] - tab[t]);
+                    kap += x[sp] * ks;
+                }
+            kap_out[((size_t)n * ng + g) * D.ncpad + bc] = (Real)kap;
+        }
     }
 }
 
@@ -365,16 +430,17 @@ __global__ void __launch_bounds__(64) k_bucket_scan(uint32_t *hist, int ntiles, 
 }
 
 // bucket starts padded to multiples of 64 (one wavefront never mixes buckets), total chunks
-__global__ void __launch_bounds__(1024) k_bucket_layout(const uint32_t *total, int nbucket, uint32_t *start,
-                                                         uint32_t *nchunks)
+// (buckets laid out in the given order: longest expected rays first)
+__global__ void __launch_bounds__(1024) k_bucket_layout(const uint32_t *total, const uint32_t *order, int nbucket,
+                                                         uint32_t *start, uint32_t *nchunks)
 {
     __shared__ uint32_t part[1024];
     const int tid = threadIdx.x;
     const int per = (nbucket + 1023) / 1024;
     uint32_t s = 0;
     for (int q = 0; q < per; ++q) {
-        const int b = tid * per + q;
-        if (b < nbucket) s += (total[b] + 63u) & ~63u;
+        const int pos = tid * per + q;
+        if (pos < nbucket) s += (total[order[pos]] + 63u) & ~63u;
     }
     part[tid] = s;
     __syncthreads();
@@ -386,8 +452,9 @@ __global__ void __launch_bounds__(1024) k_bucket_layout(const uint32_t *total, i
     }
     uint32_t run = part[tid] - s;
     for (int q = 0; q < per; ++q) {
-        const int b = tid * per + q;
-        if (b < nbucket) {
+        const int pos = tid * per + q;
+        if (pos < nbucket) {
+            const uint32_t b = order[pos];
             start[b] = run;
             run += (total[b] + 63u) & ~63u;
         }
@@ -397,13 +464,13 @@ __global__ void __launch_bounds__(1024) k_bucket_layout(const uint32_t *total, i
 
 // chunk -> bucket map and invalid markers on the padding of each bucket
 __global__ void k_chunk_map(const uint32_t *total, const uint32_t *start, int nbucket, uint32_t *chunk_bucket,
-                            uint2 *items)
+                            uint4 *items)
 {
     const int b = blockIdx.x * blockDim.y + threadIdx.y;
     if (b >= nbucket) return;
-    const uint32_t s = start[b], e = start[b + 1], used = s + total[b];
+    const uint32_t s = start[b], e = s + ((total[b] + 63u) & ~63u), used = s + total[b];
     for (uint32_t q = s / 64 + threadIdx.x; q < e / 64; q += blockDim.x) chunk_bucket[q] = (uint32_t)b;
-    for (uint32_t q = used + threadIdx.x; q < e; q += blockDim.x) items[q] = make_uint2(0u, kInvalidItem);
+    for (uint32_t q = used + threadIdx.x; q < e; q += blockDim.x) items[q] = make_uint4(0u, kInvalidItem, 0u, 0u);
 }
 
 template <bool PDF>
@@ -434,9 +501,13 @@ __global__ void __launch_bounds__(256) k_alloc_scatter(AllocArgs A)
         if (live) {
             uint32_t kord = 0;
             for (int q = threadIdx.x - r; q < (int)threadIdx.x; ++q) kord += sb[q] == bucket ? 1u : 0u;
+            // direction stream of the ray, keyed by (cell, band, g, octant, ordinal)
+            const uint32_t n = (bucket >> 3) / (uint32_t)A.ng, g = (bucket >> 3) - n * (uint32_t)A.ng;
+            uint32_t v[4];
+            philox4x32_10(c, (n << 16) | (g << 8) | (bucket & 7u), kord, (D.snap_id << 4) | kTagDir, A.k0, A.k1, v);
             const uint32_t pos = atomicAdd(&lb[bucket], 1u);
-            A.items[pos] = make_uint2((uint32_t)i | ((uint32_t)j << 10) | ((uint32_t)k << 20),
-                                      (uint32_t)r | (kord << 8) | ((uint32_t)s << 16));
+            A.items[pos] = make_uint4((uint32_t)i | ((uint32_t)j << 10) | ((uint32_t)k << 20),
+                                      (uint32_t)r | (kord << 8) | ((uint32_t)s << 16), v[0], v[1]);
         }
         __syncthreads();
     }
@@ -447,7 +518,7 @@ template <class Real> struct MarchArgs {
     const SnapDesc *snaps;
     const double *faces;        // all snapshots' face tables, staged into LDS
     int nfaces;
-    const uint2 *items;
+    const uint4 *items;
     const uint32_t *chunk_bucket;
     const uint32_t *nchunks;
     const double *dnu, *wg;     // per-ray weights in per-cell pdf mode
@@ -455,6 +526,19 @@ template <class Real> struct MarchArgs {
     uint32_t k0, k1;
     Real tol;
     int max_steps;
+    int cap;                    // steps a ray takes in the lane kernel before it is handed to k_march_long
+    const float *kmin;          // per (n, g): lower bound of kappa over the field (segmenting range)
+    struct ContRec *cont;       // continuation records of capped rays
+    uint32_t *cont_count;
+    uint32_t cont_cap;
+};
+
+// State of a ray handed from the lane kernel to k_march_long after `steps` steps.
+struct ContRec {
+    uint32_t q;                 // work item index
+    int i, j, k, steps;         // cell of the next step
+    double tau, acc;
+    double t, tx, ty, tz;       // current parameter, next-face parameters
 };
 
 __device__ __forceinline__ RayGeo ray_geo(const SnapDesc &D, const double *sf)
@@ -471,49 +555,270 @@ __device__ __forceinline__ RayGeo ray_geo(const SnapDesc &D, const double *sf)
     return G;
 }
 
-// One lane per ray; every wavefront holds 64 work items of one (band, g, octant) bucket.
-template <class Real, bool PDF>
-__global__ void __launch_bounds__(256) k_march(MarchArgs<Real> A)
+// One ray per lane, no refill: every wavefront marches its 64 work items of one bucket and
+// retires when its longest ray ends; the hardware scheduler balances the many short-lived
+// wavefronts.
+template <class Real, bool PDF, bool INC_XZ, bool MULTI>
+__global__ void __launch_bounds__(256) k_march_lane(MarchArgs<Real> A)
 {
     extern __shared__ double sf[];
     for (int q = threadIdx.x; q < A.nfaces; q += blockDim.x) sf[q] = A.faces[q];
     __syncthreads();
     const uint32_t wave = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-    if (wave >= *A.nchunks) return;
-    const uint32_t b = __builtin_amdgcn_readfirstlane(A.chunk_bucket[wave]);
-    const uint2 it = A.items[(size_t)wave * 64 + (threadIdx.x & 63)];
+    if (wave >= __builtin_amdgcn_readfirstlane(*A.nchunks)) return;
+    const uint32_t b = __builtin_amdgcn_readfirstlane(gld(A.chunk_bucket + wave));
+    const uint4 it = gld(A.items + (size_t)wave * 64 + (threadIdx.x & 63));
     if (it.y == kInvalidItem) return;
-    const int s = (int)((it.y >> 16) & 0x7FFF);
+    const int s = MULTI ? (int)((it.y >> 16) & 0x7FFF) : 0;
     const SnapDesc &D = A.snaps[s];
+    const RayGeo G = ray_geo(D, sf);
+    XzUniform U;
+    U.hx = D.hx;
+    U.hz = D.hz;
     const int i = (int)(it.x & 1023), j = (int)((it.x >> 10) & 1023), k = (int)((it.x >> 20) & 1023);
     const int r = (int)(it.y & 255);
-    const uint32_t kord = (it.y >> 8) & 255u;
     const int o = (int)(b & 7), pair = (int)(b >> 3);
-    const int n = pair / A.ng, g = pair - (pair / A.ng) * A.ng;
+    const int n = pair / A.ng;
     const Real *K = reinterpret_cast<const Real *>(D.kap) + (size_t)pair * D.ncpad;
     const double *Ipl = D.Ipl + (size_t)n * D.ncpad;
     const uint32_t c = (uint32_t)(((uint64_t)i * D.ny + j) * D.nz + k);
-    uint32_t v[4];
-    philox4x32_10(c, ((uint32_t)n << 16) | ((uint32_t)g << 8) | (uint32_t)o, kord,
-                  (D.snap_id << 4) | kTagDir, A.k0, A.k1, v);
     double dx, dy, dz;
-    octant_direction(v[0], v[1], o, dx, dy, dz);
-    const RayGeo G = ray_geo(D, sf);
-    const int csrc = brick_x(i, G.bsx) + brick_y(j, G.bsy) + brick_z(k);
-    const Real kap_src = K[csrc];
-    const MarchOut<Real> m = march_ray<Real, false>(G, K, Ipl, i, j, k, dx, dy, dz, Ipl[csrc], D.Iw[n],
-                                                    D.Iw[A.nb + n], A.tol, A.max_steps);
+    octant_direction(it.z, it.w, o, dx, dy, dz);
+    Ray<Real, INC_XZ> R;
+    Real kap_src;
+    double Isrc;
+    ray_init(R, G, U, K, Ipl, i, j, k, dx, dy, dz, kap_src, Isrc);
+    if (!ray_march(R, G, K, Ipl, D.Iw + n, D.Iw + A.nb + n, A.tol, A.max_steps, kap_src, Isrc, A.cap)) {
+        // long ray: hand its state to k_march_long (or, if the list is full, finish it here)
+        const uint32_t idx = atomicAdd(A.cont_count, 1u);
+        if (idx < A.cont_cap) {
+            ContRec rc;
+            rc.q = (uint32_t)((size_t)wave * 64 + (threadIdx.x & 63));
+            rc.i = R.i; rc.j = R.j; rc.k = R.k; rc.steps = R.steps;
+            rc.tau = R.tau; rc.acc = R.acc;
+            rc.t = R.t; rc.tx = R.tx; rc.ty = R.ty; rc.tz = R.tz;
+            A.cont[idx] = rc;
+            return;
+        }
+        const int cell = R.px + R.py + R.pz;
+        ray_march(R, G, K, Ipl, D.Iw + n, D.Iw + A.nb + n, A.tol, A.max_steps, gld(K + cell), gld(Ipl + cell),
+                  A.max_steps);
+    }
     double w;
     if constexpr (!PDF) {
-        w = D.W[b];
+        w = gld(D.W + b);
     } else {
-        const double p = D.cpdf[((size_t)c * A.nb * A.ng + pair) * 8 + o];
-        w = 4.0 * M_PI * A.dnu[n] * A.wg[g] / (8.0 * p);
+        const double p = gld(D.cpdf + ((size_t)c * A.nb * A.ng + pair) * 8 + o);
+        w = 4.0 * M_PI * A.dnu[n] * A.wg[pair - n * A.ng] / (8.0 * p);
     }
-    const double Y = w * (double)kap_src * (double)m.acc;
     const size_t slot = (size_t)c * A.R + r;
-    reinterpret_cast<Real *>(D.Y)[slot] = (Real)Y;
-    D.st[slot] = (uint32_t)m.steps | ((uint32_t)m.end << 28);
+    reinterpret_cast<Real *>(D.Y)[slot] = (Real)(w * (double)kap_src * (double)R.acc);
+    D.st[slot] = (uint32_t)R.steps | ((uint32_t)R.end << 28);
+}
+
+// Long rays (FP32 march, uniform periodic x and z): one wavefront per ray handed over by the
+// lane kernel.  The path is continued in rounds.  A round covers the parameter range up to
+// tend (the wall, the distance at which even the smallest kappa of the field would bring tau
+// to tol, 1.25 times the distance the optical depth seen so far predicts, and the step cap,
+// whichever is first) and splits it at the crossings of the axis (x or z) the ray advances
+// fastest along into 64 segments, one per lane.  Each lane marches its segment with tau = 1
+// (same geometry and absorption as the sequential march); a prefix product of the segment
+// transmissivities gives every segment's incoming tau.  The first segment in which the ray
+// stops (tau <= tol, the wall, or the step cap) is re-marched sequentially with its true
+// incoming tau and step count, and the ray value is
+//   acc = acc_before + sum_{l < l*} tau_in(l) acc_l + acc(l*).
+// When no segment stops, the contributions are added and the next round starts where the
+// last segment ended.
+template <bool PDF, bool MULTI>
+__global__ void __launch_bounds__(256) k_march_long(MarchArgs<float> A)
+{
+    extern __shared__ double sf[];
+    for (int q = threadIdx.x; q < A.nfaces; q += blockDim.x) sf[q] = A.faces[q];
+    __syncthreads();
+    const int lane = (int)(threadIdx.x & 63);
+    const uint32_t nrec = min(__builtin_amdgcn_readfirstlane(*A.cont_count), A.cont_cap);
+    const uint32_t nwaves = gridDim.x * (blockDim.x >> 6);
+    for (uint32_t wv = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) >> 6); wv < nrec;
+         wv += nwaves) {
+        const ContRec rc = A.cont[wv];
+        const uint4 it = gld(A.items + rc.q);
+        const uint32_t b = gld(A.chunk_bucket + (rc.q >> 6));
+        const int s = MULTI ? (int)((it.y >> 16) & 0x7FFF) : 0;
+        const SnapDesc &D = A.snaps[s];
+        const RayGeo G = ray_geo(D, sf);
+        XzUniform U;
+        U.hx = D.hx;
+        U.hz = D.hz;
+        const int ci = (int)(it.x & 1023), cj = (int)((it.x >> 10) & 1023), ck = (int)((it.x >> 20) & 1023);
+        const int r = (int)(it.y & 255);
+        const int o = (int)(b & 7), pair = (int)(b >> 3);
+        const int n = pair / A.ng;
+        const float *K = reinterpret_cast<const float *>(D.kap) + (size_t)pair * D.ncpad;
+        const double *Ipl = D.Ipl + (size_t)n * D.ncpad;
+        const uint32_t c = (uint32_t)(((uint64_t)ci * D.ny + cj) * D.nz + ck);
+        double dx, dy, dz;
+        octant_direction(it.z, it.w, o, dx, dy, dz);
+        Ray<float, true> R;
+        float kap_src;
+        double Isrc;
+        ray_init(R, G, U, K, Ipl, ci, cj, ck, dx, dy, dz, kap_src, Isrc);
+        const bool ax = fabs(dx) >= fabs(dz);            // the crossing axis
+        const double dta = ax ? R.dtx : R.dtz;
+        const double tw = (((dy > 0.0) ? G.yf[G.ny] : G.yf[0]) - R.oy) * R.ry;   // the wall
+        const float km = gld(A.kmin + pair);
+        // wave-uniform state of the ray at the start of a round
+        int si = rc.i, sj = rc.j, sk = rc.k, ssteps = rc.steps;
+        double st = rc.t, stx = rc.tx, sty = rc.ty, stz = rc.tz, stau = rc.tau, sacc = rc.acc;
+        while (true) {
+            double tend = tw;
+            const double od = log(stau / (double)A.tol);  // optical depth left (> 0: the ray goes on)
+            if (km > 0.0f) tend = fmin(tend, st + od / (double)km);
+            const double kobs = st > 0.0 ? -log(stau) / st : 0.0;
+            if (kobs > 0.0) tend = fmin(tend, st + 1.25 * od / kobs);
+            const double ta0 = ax ? stx : stz;
+            tend = fmin(tend, ta0 + (double)(A.max_steps - ssteps) * dta);   // every crossing is a step
+            const long M = ta0 < tend ? (long)floor((tend - ta0) / dta) + 1 : 0;
+            const long B0 = (M * lane) / 64, B1 = (M * (lane + 1)) / 64;
+            const bool empty = lane < 63 && B1 == B0;
+            R.tau = 1.0;
+            R.acc = 0.0;
+            R.steps = 0;
+            R.end = kEndTol;
+            if (B0 == 0) {
+                R.i = si; R.j = sj; R.k = sk;
+                R.t = st; R.tx = stx; R.ty = sty; R.tz = stz;
+            } else {
+                const long m0 = B0 - 1;                   // the crossing the segment starts on
+                const double ts = ta0 + (double)m0 * dta;
+                R.t = ts;
+                if (ax) {
+                    int ii = (int)(((long)si + ((R.sgn & 1) ? -(m0 + 1) : (m0 + 1))) % G.nx);
+                    R.i = ii < 0 ? ii + G.nx : ii;
+                    R.tx = ta0 + (double)(m0 + 1) * dta;
+                    const double z = R.oz + ts * dz - G.zf[0];
+                    const double u = z / U.hz;
+                    long kb = (R.sgn & 4) ? (long)ceil(u) - 1 : (long)floor(u);
+                    R.tz = (G.zf[0] + (double)(kb + ((R.sgn & 4) ? 0 : 1)) * U.hz - R.oz) * R.rz;
+                    int kk = (int)(kb % G.nz);
+                    R.k = kk < 0 ? kk + G.nz : kk;
+                } else {
+                    int kk = (int)(((long)sk + ((R.sgn & 4) ? -(m0 + 1) : (m0 + 1))) % G.nz);
+                    R.k = kk < 0 ? kk + G.nz : kk;
+                    R.tz = ta0 + (double)(m0 + 1) * dta;
+                    const double x = R.ox + ts * dx - G.xf[0];
+                    const double u = x / U.hx;
+                    long ib = (R.sgn & 1) ? (long)ceil(u) - 1 : (long)floor(u);
+                    R.tx = (G.xf[0] + (double)(ib + ((R.sgn & 1) ? 0 : 1)) * U.hx - R.ox) * R.rx;
+                    int ii = (int)(ib % G.nx);
+                    R.i = ii < 0 ? ii + G.nx : ii;
+                }
+                const double y = R.oy + ts * dy;
+                int lo = 0, hi = G.ny - 1;                // cell containing y, entered in direction dy
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    const bool below = (dy > 0.0) ? (G.yf[mid] <= y) : (G.yf[mid] < y);
+                    if (below) lo = mid; else hi = mid - 1;
+                }
+                R.j = lo;
+                R.ty = (G.yf[lo + ((R.sgn & 2) ? 0 : 1)] - R.oy) * R.ry;
+            }
+            R.px = brick_x(R.i, G.bsx); R.py = brick_y(R.j, G.bsy); R.pz = brick_z(R.k);
+            const int start_i = R.i, start_j = R.j, start_k = R.k;
+            const double start_t = R.t, start_tx = R.tx, start_ty = R.ty, start_tz = R.tz;
+            // local march of the segment with tau = 1: lanes below 63 end on their last
+            // crossing, lane 63 at tend
+            bool wall_end = false;
+            if (!empty) {
+                long next = B0;
+                const int cur0 = R.px + R.py + R.pz;
+                float kc = gld(K + cur0);
+                double Ic = gld(Ipl + cur0);
+                while (true) {
+                    const double te = R.tx < R.ty ? (R.tz < R.tx ? R.tz : R.tx) : (R.tz < R.ty ? R.tz : R.ty);
+                    const bool cross = (ax ? R.tx : R.tz) == te;
+                    double ds;
+                    bool wall;
+                    const int cell = ray_advance(R, G, ds, wall);
+                    const float x = kc * (float)ds;
+                    float a, e;
+                    absorb_f32(x, a, e);
+                    R.acc += (double)((float)R.tau * a * (float)(Isrc - Ic));
+                    R.tau *= x < 0.25f ? 1.0 - (double)a : (double)e;
+                    ++R.steps;
+                    if (wall) {
+                        R.acc += R.tau * (Isrc - gld(R.end == kEndWallLo ? D.Iw + n : D.Iw + A.nb + n));
+                        R.tau = 0.0;
+                        wall_end = true;
+                        break;
+                    }
+                    if (!(R.tau > (double)A.tol)) break;
+                    if (lane < 63 ? (cross && ++next == B1) : (R.t >= tend)) break;
+                    if (R.steps >= A.max_steps) break;
+                    kc = gld(K + cell);
+                    Ic = gld(Ipl + cell);
+                }
+            }
+            // incoming tau and steps of every segment
+            double pin = R.tau;                // inclusive prefix product over lanes
+            int sin_ = R.steps;                // inclusive prefix sum of steps
+            for (int off = 1; off < 64; off <<= 1) {
+                const double pv = __shfl_up(pin, off);
+                const int sv = __shfl_up(sin_, off);
+                if (lane >= off) { pin *= pv; sin_ += sv; }
+            }
+            double tau_in = __shfl_up(pin, 1);
+            int steps_in = __shfl_up(sin_, 1);
+            if (lane == 0) { tau_in = 1.0; steps_in = 0; }
+            tau_in *= stau;
+            steps_in += ssteps;
+            const bool stops = !empty && (wall_end || !(tau_in * R.tau > (double)A.tol) ||
+                                          steps_in + R.steps >= A.max_steps);
+            const uint64_t sm = __ballot(stops);
+            if (sm == 0) {
+                // nothing stopped: add the contributions, continue from the end of lane 63
+                double contrib = tau_in * R.acc;
+                for (int off = 32; off > 0; off >>= 1) contrib += __shfl_xor(contrib, off);
+                sacc += contrib;
+                stau = __shfl(tau_in * R.tau, 63);
+                ssteps = __shfl(steps_in + R.steps, 63);
+                si = __shfl(R.i, 63); sj = __shfl(R.j, 63); sk = __shfl(R.k, 63);
+                st = __shfl(R.t, 63); stx = __shfl(R.tx, 63); sty = __shfl(R.ty, 63); stz = __shfl(R.tz, 63);
+                continue;
+            }
+            const int lstar = __ffsll((long long)sm) - 1;
+            double contrib = (lane < lstar) ? tau_in * R.acc : 0.0;
+            if (lane == lstar) {
+                // re-march the stopping segment with its true incoming tau and step count
+                R.i = start_i; R.j = start_j; R.k = start_k;
+                R.t = start_t; R.tx = start_tx; R.ty = start_ty; R.tz = start_tz;
+                R.px = brick_x(R.i, G.bsx); R.py = brick_y(R.j, G.bsy); R.pz = brick_z(R.k);
+                R.tau = tau_in;
+                R.acc = 0.0;
+                R.steps = steps_in;
+                R.end = kEndTol;
+                const int cur = R.px + R.py + R.pz;
+                ray_march(R, G, K, Ipl, D.Iw + n, D.Iw + A.nb + n, A.tol, A.max_steps, gld(K + cur),
+                          gld(Ipl + cur), A.max_steps);
+                contrib = R.acc;
+            }
+            // fixed-order wave sum of the contributions
+            for (int off = 32; off > 0; off >>= 1) contrib += __shfl_xor(contrib, off);
+            if (lane == lstar) {
+                double w;
+                if constexpr (!PDF) {
+                    w = gld(D.W + b);
+                } else {
+                    const double p = gld(D.cpdf + ((size_t)c * A.nb * A.ng + pair) * 8 + o);
+                    w = 4.0 * M_PI * A.dnu[n] * A.wg[pair - n * A.ng] / (8.0 * p);
+                }
+                const double acc = sacc + contrib;
+                const size_t slot = (size_t)c * A.R + r;
+                reinterpret_cast<float *>(D.Y)[slot] = (float)(w * (double)kap_src * acc);
+                D.st[slot] = (uint32_t)R.steps | ((uint32_t)R.end << 28);
+            }
+            break;
+        }
+    }
 }
 
 // --------------------------------------------------------------------------- trace
@@ -533,7 +838,7 @@ template <class Real> struct TraceArgs {
 
 // All R rays of listed cells, drawn and marched with the same device functions as the
 // production path; one thread per ray (ordinal k recomputed from the earlier draws).
-template <class Real, bool PDF>
+template <class Real, bool PDF, bool INC_XZ>
 __global__ void __launch_bounds__(256) k_trace(TraceArgs<Real> A)
 {
     extern __shared__ double sf[];
@@ -563,61 +868,84 @@ __global__ void __launch_bounds__(256) k_trace(TraceArgs<Real> A)
     double dx, dy, dz;
     octant_direction(v[0], v[1], d.o, dx, dy, dz);
     const RayGeo G = ray_geo(D, sf);
-    const int csrc = brick_x(i, G.bsx) + brick_y(j, G.bsy) + brick_z(k);
-    const Real kap_src = K[csrc];
-    const MarchOut<Real> m = march_ray<Real, false>(G, K, Ipl, i, j, k, dx, dy, dz, Ipl[csrc], D.Iw[d.n],
-                                                    D.Iw[A.nb + d.n], A.tol, A.max_steps);
+    XzUniform U;
+    U.hx = D.hx;
+    U.hz = D.hz;
+    Ray<Real, INC_XZ> R;
+    Real kap_src;
+    double Isrc;
+    ray_init(R, G, U, K, Ipl, i, j, k, dx, dy, dz, kap_src, Isrc);
+    ray_march(R, G, K, Ipl, D.Iw + d.n, D.Iw + A.nb + d.n, A.tol, A.max_steps, kap_src, Isrc, A.max_steps);
     const double w = 4.0 * M_PI * A.dnu[d.n] * A.wg[d.g] / (8.0 * d.p);
     rmc_ray_record rec;
-    rec.Y = w * (double)kap_src * (double)m.acc;
+    rec.Y = w * (double)kap_src * (double)R.acc;
     rec.p = d.p;
     rec.n = d.n; rec.g = d.g; rec.o = d.o; rec.k = (int32_t)kord;
-    rec.steps = m.steps;
-    rec.end = m.end;
+    rec.steps = R.steps;
+    rec.end = R.end;
     A.out[idx] = rec;
 }
 
 // -------------------------------------------------------------------------- reduce
-// Mean of the R ray values of each cell (Eq. 8) and its standard error; total steps.
+// Mean of the R ray values of each cell (Eq. 8) and its standard error; total steps.  The
+// slots of a group of cells are loaded coalesced into LDS (padded against bank conflicts),
+// then one thread sums one cell's R values in slot order.
+constexpr int kRedVals = 4096;
+__device__ __forceinline__ int red_pad(int q) { return q + (q >> 5); }
+
 template <class Real>
 __global__ void __launch_bounds__(256) k_reduce(const Real *__restrict__ Y, const uint32_t *__restrict__ st,
                                                 uint64_t nc, int R, int accum, double *__restrict__ divq,
                                                 double *__restrict__ se, unsigned long long *counters)
 {
-    const uint64_t c = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    __shared__ Real ys[kRedVals + kRedVals / 32];
+    __shared__ uint32_t ss[kRedVals + kRedVals / 32];
+    const int cpg = kRedVals / R;                 // cells per group
     unsigned long long steps = 0, capped = 0;
-    if (c < nc) {
-        const Real *y = Y + c * R;
-        const uint32_t *sc = st + c * R;
-        double mean;
-        if (accum == RMC_ACC_F64) {
-            double sum = 0.0;
-            for (int r = 0; r < R; ++r) sum += (double)y[r];
-            mean = sum / R;
-        } else if (accum == RMC_ACC_COMP_F32) {
-            float sum = 0.0f, comp = 0.0f;   // Neumaier's compensated summation
-            for (int r = 0; r < R; ++r) {
-                const float v = (float)y[r];
-                const float t = sum + v;
-                if (fabsf(sum) >= fabsf(v)) comp += (sum - t) + v;
-                else comp += (v - t) + sum;
-                sum = t;
+    for (uint64_t base = (uint64_t)blockIdx.x * cpg; base < nc; base += (uint64_t)gridDim.x * cpg) {
+        const int ncell = (int)min((uint64_t)cpg, nc - base);
+        const int nval = ncell * R;
+        const Real *yb = Y + base * R;
+        const uint32_t *sb = st + base * R;
+        for (int q = threadIdx.x; q < nval; q += blockDim.x) {
+            ys[red_pad(q)] = yb[q];
+            ss[red_pad(q)] = sb[q];
+        }
+        __syncthreads();
+        for (int cq = threadIdx.x; cq < ncell; cq += blockDim.x) {
+            const int o = cq * R;
+            double mean;
+            if (accum == RMC_ACC_F64) {
+                double sum = 0.0;
+                for (int r = 0; r < R; ++r) sum += (double)ys[red_pad(o + r)];
+                mean = sum / R;
+            } else if (accum == RMC_ACC_COMP_F32) {
+                float sum = 0.0f, comp = 0.0f;   // Neumaier's compensated summation
+                for (int r = 0; r < R; ++r) {
+                    const float v = (float)ys[red_pad(o + r)];
+                    const float t = sum + v;
+                    if (fabsf(sum) >= fabsf(v)) comp += (sum - t) + v;
+                    else comp += (v - t) + sum;
+                    sum = t;
+                }
+                mean = (double)(sum + comp) / R;
+            } else {
+                float sum = 0.0f;
+                for (int r = 0; r < R; ++r) sum += (float)ys[red_pad(o + r)];
+                mean = (double)sum / R;
             }
-            mean = (double)(sum + comp) / R;
-        } else {
-            float sum = 0.0f;
-            for (int r = 0; r < R; ++r) sum += (float)y[r];
-            mean = (double)sum / R;
+            double sq = 0.0;
+            for (int r = 0; r < R; ++r) {
+                const double dv = (double)ys[red_pad(o + r)] - mean;
+                sq += dv * dv;
+                const uint32_t w = ss[red_pad(o + r)];
+                steps += w & 0x0FFFFFFFu;
+                capped += (w >> 28) == (uint32_t)kEndCap ? 1ull : 0ull;
+            }
+            divq[base + cq] = mean;
+            if (se) se[base + cq] = R > 1 ? sqrt(sq / (R - 1) / R) : 0.0;
         }
-        double ss = 0.0;
-        for (int r = 0; r < R; ++r) {
-            const double dv = (double)y[r] - mean;
-            ss += dv * dv;
-            steps += sc[r] & 0x0FFFFFFFu;
-            capped += (sc[r] >> 28) == (uint32_t)kEndCap ? 1ull : 0ull;
-        }
-        divq[c] = mean;
-        if (se) se[c] = R > 1 ? sqrt(ss / (R - 1) / R) : 0.0;
+        __syncthreads();
     }
     for (int off = 32; off > 0; off >>= 1) {
         steps += __shfl_xor(steps, off);
@@ -716,11 +1044,13 @@ struct rmc_ctx {
     int nb = 0, ng = 0, ns = 0, nT = 0;
     double T0 = 0, dT = 1;
     DBuf k64, Ib, dnu, wg;
+    std::vector<double> k64_host;   // for the march order heuristic (kappa at T_max per (n, g))
     // fields
     bool have_T = false, have_X = false;
     DBuf T, X, stage;
     double Tmax_cells = 0;
     double xhat[8] = {0};
+    int graphs = 0;         // live graphs capturing this context
     // options
     rmc_options opt{};
     // per-cell pdf mode
@@ -735,8 +1065,18 @@ struct rmc_ctx {
     // shared pipeline workspace (used when this context leads a batch)
     DBuf hist, bucket_total, bucket_start, nchunks, chunk_bucket, items, faces, snaps, tile_snap, counters,
         outbuf;
-    DBuf trace_rec, trace_cells;
+    DBuf trace_rec, trace_cells, border, kmin, cont, cont_count;
+    std::vector<float> h_kmin;
+    double Tmin_cells = 0;
+    double xmin[8] = {0};
+    // host staging of the per-compute descriptors (kept alive until the next compute)
+    std::vector<double> h_faces;
+    std::vector<unsigned char> h_snaps;
+    std::vector<int> h_tile_snap;
+    std::vector<uint32_t> h_order;
     DBuf small;             // ingest results
+    DBuf scal;              // [0]: max cell temperature, [1..8]: largest mole fraction per species
+    uint64_t config_version = 0;   // bumped by every set_* that changes sizes or kernel arguments
     // timing: a ring of event sets, one per compute in flight; counters[0..1] are the last
     // compute's steps / capped rays, counters[2] the steps accumulated since the last reset
     struct EvSet {
@@ -785,7 +1125,8 @@ rmc_status check_options(const rmc_options *o)
         return fail(RMC_INVALID_ARG, "mix_eps must be in [0, 1]");
     if (o->block_threads != 0 && o->block_threads != 256)
         return fail(RMC_UNSUPPORTED, "block_threads: only 0 (default) and 256 are built");
-    for (int q = 0; q < 7; ++q)
+    if (o->long_ray_steps < 0) return fail(RMC_INVALID_ARG, "long_ray_steps must be >= 0");
+    for (int q = 0; q < 6; ++q)
         if (o->reserved[q] != 0) return fail(RMC_INVALID_ARG, "reserved option fields must be zero");
     return RMC_OK;
 }
@@ -808,50 +1149,82 @@ rmc_status check_ready(const rmc_ctx *c)
     return RMC_OK;
 }
 
-template <class Real> rmc_status build_fields(rmc_ctx *c, const SnapDesc &D, hipStream_t s)
+// width of a uniformly spaced axis (faces equal to f0 + q h within 1e-12 of the length), else 0
+double uniform_width(const std::vector<double> &f)
 {
-    const uint64_t ncpad = ncpad_of(c);
-    const int npairs = c->nb * c->ng;
-    rmc_status st;
-    if ((st = c->field.ensure(sizeof(Real) * ncpad * (uint64_t)npairs)) ||
-        (st = c->Iplane.ensure(sizeof(double) * ncpad * (uint64_t)c->nb)))
-        return st;
-    dim3 grid((unsigned)((ncpad + 255) / 256), (unsigned)std::min(npairs, 65535));
-    hipLaunchKernelGGL(k_fields<Real>, grid, dim3(256), 0, s, c->T.as<double>(), c->X.as<double>(), c->ns,
-                       ncells_of(c), c->k64.as<double>(), c->Ib.as<double>(), c->nb, c->ng, c->nT, c->T0, c->dT,
-                       D, c->field.as<Real>(), c->Iplane.as<double>());
-    HIPCHK(hipGetLastError());
-    return RMC_OK;
+    const int n = (int)f.size() - 1;
+    const double L = f[n] - f[0], h = L / n;
+    for (int q = 0; q <= n; ++q)
+        if (std::fabs(f[q] - (f[0] + q * h)) > 1e-12 * L) return 0.0;
+    return h;
 }
 
-// per-snapshot preparation: pdf, fields, slots; fills the snapshot descriptor
-template <class Real> rmc_status prepare_snapshot(rmc_ctx *c, hipStream_t s, SnapDesc &D)
+// Bucket order of the march: (band, g) pairs by increasing kappa at T_max (longest rays
+// first, so the longest-running wavefronts start early), octants consecutive.
+void march_order(const rmc_ctx *c, std::vector<uint32_t> &order)
+{
+    const int nb = c->nb, ng = c->ng;
+    const double Tmax = std::max(c->Tmax_cells, std::max(c->Tw[0], c->Tw[1]));
+    const double u = (Tmax - c->T0) / c->dT;
+    int t = (int)std::floor(u);
+    if (t > c->nT - 2) t = c->nT - 2;
+    if (t < 0) t = 0;
+    const double f = u - t;
+    std::vector<std::pair<double, int>> key(nb * ng);
+    for (int pr = 0; pr < nb * ng; ++pr) {
+        double kap = 0.0;
+        for (int sp = 0; sp < c->ns; ++sp) {
+            const double *tab = c->k64_host.data() + ((size_t)sp * nb * ng + pr) * c->nT;
+            kap += c->xhat[sp] * (tab[t] + f * (tab[t + 1] - tab[t]));
+        }
+        key[pr] = {kap, pr};
+    }
+    std::stable_sort(key.begin(), key.end(), [](const std::pair<double, int> &a, const std::pair<double, int> &b) {
+        return a.first < b.first;
+    });
+    order.resize((size_t)nb * ng * 8);
+    for (int q = 0; q < nb * ng; ++q)
+        for (int o = 0; o < 8; ++o) order[(size_t)q * 8 + o] = (uint32_t)(key[q].second * 8 + o);
+}
+
+// per-snapshot plan: buffers and the snapshot descriptor (no work enqueued)
+// Lower bound of kappa_{n,g} over the field: smallest mole fractions times the smallest table
+// value over the nodes bracketing the field's temperature range (linear interpolation never
+// goes below the smaller of its two nodes).  Bounds how far a ray can march with tau > tol.
+void kappa_lower_bounds(const rmc_ctx *c, std::vector<float> &out)
+{
+    const int nb = c->nb, ng = c->ng;
+    int tlo = (int)std::floor((c->Tmin_cells - c->T0) / c->dT);
+    int thi = (int)std::floor((std::max(c->Tmax_cells, c->Tmin_cells) - c->T0) / c->dT) + 1;
+    tlo = std::max(0, std::min(tlo, c->nT - 1));
+    thi = std::max(tlo, std::min(thi, c->nT - 1));
+    out.assign((size_t)nb * ng, 0.0f);
+    for (int pr = 0; pr < nb * ng; ++pr) {
+        double kap = 0.0;
+        for (int sp = 0; sp < c->ns; ++sp) {
+            const double *tab = c->k64_host.data() + ((size_t)sp * nb * ng + pr) * c->nT;
+            double m = tab[tlo];
+            for (int t = tlo; t <= thi; ++t) m = std::min(m, tab[t]);
+            kap += c->xmin[sp] * m;
+        }
+        out[pr] = (float)(kap * (1.0 - 1e-6));
+    }
+}
+
+template <class Real> rmc_status plan_snapshot(rmc_ctx *c, SnapDesc &D)
 {
     rmc_status st;
     const int nb = c->nb, ng = c->ng, nbucket = nb * ng * 8;
+    const uint64_t nc = ncells_of(c);
+    const int R = c->opt.rays_per_cell;
     if ((st = c->pdf_scratch.ensure(sizeof(double) * (nb * ng + nb))) || (st = c->p.ensure(sizeof(double) * nb * ng)) ||
         (st = c->cdf_b.ensure(sizeof(double) * nb)) || (st = c->cdf_g.ensure(sizeof(double) * nb * ng)) ||
         (st = c->W.ensure(sizeof(double) * nbucket)) || (st = c->Iw.ensure(sizeof(double) * 2 * nb)) ||
-        (st = c->status.ensure(sizeof(int))))
+        (st = c->status.ensure(sizeof(int))) ||
+        (st = c->field.ensure(sizeof(Real) * ncpad_of(c) * (uint64_t)(nb * ng))) ||
+        (st = c->Iplane.ensure(sizeof(double) * ncpad_of(c) * (uint64_t)nb)) ||
+        (st = c->Y.ensure(sizeof(Real) * nc * R)) || (st = c->st.ensure(sizeof(uint32_t) * nc * R)))
         return st;
-    PdfArgs A;
-    A.k64 = c->k64.as<double>();
-    A.Ib = c->Ib.as<double>();
-    A.dnu = c->dnu.as<double>();
-    A.wg = c->wg.as<double>();
-    A.nb = nb; A.ng = ng; A.ns = c->ns; A.nT = c->nT;
-    A.T0 = c->T0; A.dT = c->dT;
-    A.Tmax = std::max(c->Tmax_cells, std::max(c->Tw[0], c->Tw[1]));
-    A.Tw0 = c->Tw[0]; A.Tw1 = c->Tw[1];
-    for (int q = 0; q < 8; ++q) A.xhat[q] = q < c->ns ? c->xhat[q] : 0.0;
-    A.e = c->pdf_scratch.as<double>();
-    A.eb = A.e + nb * ng;
-    A.p = c->p.as<double>(); A.cdf_b = c->cdf_b.as<double>(); A.cdf_g = c->cdf_g.as<double>();
-    A.W = c->W.as<double>(); A.Iw = c->Iw.as<double>(); A.status = c->status.as<int>();
-    hipLaunchKernelGGL(k_plain_pdf, dim3(1), dim3(64), 0, s, A);
-    HIPCHK(hipGetLastError());
-
-    const uint64_t nc = ncells_of(c);
     D = SnapDesc{};
     D.nx = c->nx; D.ny = c->ny; D.nz = c->nz;
     D.nbx = round_up(c->nx, 4) / 4; D.nby = round_up(c->ny, 4) / 4; D.nbz = round_up(c->nz, 4) / 4;
@@ -859,6 +1232,8 @@ template <class Real> rmc_status prepare_snapshot(rmc_ctx *c, hipStream_t s, Sna
     D.snap_id = c->opt.snapshot;
     D.Lx = c->xf[c->nx] - c->xf[0];
     D.Lz = c->zf[c->nz] - c->zf[0];
+    D.hx = uniform_width(c->xf);
+    D.hz = uniform_width(c->zf);
     D.W = c->W.as<double>(); D.Iw = c->Iw.as<double>();
     D.p = c->p.as<double>(); D.cdf_b = c->cdf_b.as<double>(); D.cdf_g = c->cdf_g.as<double>();
     if (c->opt.sampling == RMC_SAMPLING_PDF) {
@@ -866,22 +1241,50 @@ template <class Real> rmc_status prepare_snapshot(rmc_ctx *c, hipStream_t s, Sna
         if ((st = c->cpdf.ensure(sizeof(double) * nc * m)) || (st = c->ccdf_b.ensure(sizeof(double) * nc * nb)) ||
             (st = c->ccdf_g.ensure(sizeof(double) * nc * nb * ng)) || (st = c->ccdf_o.ensure(sizeof(double) * nc * m)))
             return st;
+        D.cpdf = c->cpdf.as<double>(); D.ccdf_b = c->ccdf_b.as<double>();
+        D.ccdf_g = c->ccdf_g.as<double>(); D.ccdf_o = c->ccdf_o.as<double>();
+    }
+    D.kap = c->field.p;
+    D.Ipl = c->Iplane.as<double>();
+    D.Y = c->Y.p;
+    D.st = c->st.as<uint32_t>();
+    c->slots_R = R;
+    c->slots_real = (int)sizeof(Real);
+    return RMC_OK;
+}
+
+// per-snapshot work: spectral pdf, per-cell pdfs, property fields (kernels only)
+template <class Real> rmc_status enqueue_snapshot(rmc_ctx *c, const SnapDesc &D, hipStream_t s)
+{
+    const int nb = c->nb, ng = c->ng;
+    const uint64_t nc = ncells_of(c);
+    PdfArgs A;
+    A.k64 = c->k64.as<double>();
+    A.Ib = c->Ib.as<double>();
+    A.dnu = c->dnu.as<double>();
+    A.wg = c->wg.as<double>();
+    A.nb = nb; A.ng = ng; A.ns = c->ns; A.nT = c->nT;
+    A.T0 = c->T0; A.dT = c->dT;
+    A.Tw0 = c->Tw[0]; A.Tw1 = c->Tw[1];
+    A.scal = c->scal.as<double>();
+    A.e = c->pdf_scratch.as<double>();
+    A.eb = A.e + nb * ng;
+    A.p = c->p.as<double>(); A.cdf_b = c->cdf_b.as<double>(); A.cdf_g = c->cdf_g.as<double>();
+    A.W = c->W.as<double>(); A.Iw = c->Iw.as<double>(); A.status = c->status.as<int>();
+    hipLaunchKernelGGL(k_plain_pdf, dim3(1), dim3(256), 0, s, A);
+    HIPCHK(hipGetLastError());
+    if (c->opt.sampling == RMC_SAMPLING_PDF) {
         hipLaunchKernelGGL(k_cell_pdf, dim3((unsigned)((nc + 127) / 128)), dim3(128), 0, s, c->q.as<double>(),
                            c->p.as<double>(), nc, nb, ng, c->opt.mix_eps, c->cpdf.as<double>(),
                            c->ccdf_b.as<double>(), c->ccdf_g.as<double>(), c->ccdf_o.as<double>());
         HIPCHK(hipGetLastError());
-        D.cpdf = c->cpdf.as<double>(); D.ccdf_b = c->ccdf_b.as<double>();
-        D.ccdf_g = c->ccdf_g.as<double>(); D.ccdf_o = c->ccdf_o.as<double>();
     }
-    if ((st = build_fields<Real>(c, D, s))) return st;
-    D.kap = c->field.p;
-    D.Ipl = c->Iplane.as<double>();
-    const int R = c->opt.rays_per_cell;
-    if ((st = c->Y.ensure(sizeof(Real) * nc * R)) || (st = c->st.ensure(sizeof(uint32_t) * nc * R))) return st;
-    c->slots_R = R;
-    c->slots_real = (int)sizeof(Real);
-    D.Y = c->Y.p;
-    D.st = c->st.as<uint32_t>();
+    const uint64_t ncpad = ncpad_of(c);
+    dim3 grid((unsigned)((ncpad + 255) / 256), (unsigned)std::min(c->nb, 65535));
+    hipLaunchKernelGGL(k_fields<Real>, grid, dim3(256), 0, s, c->T.as<double>(), c->X.as<double>(), c->ns, nc,
+                       c->k64.as<double>(), c->Ib.as<double>(), c->nb, c->ng, c->nT, c->T0, c->dT, D,
+                       c->field.as<Real>(), c->Iplane.as<double>());
+    HIPCHK(hipGetLastError());
     return RMC_OK;
 }
 
@@ -914,112 +1317,149 @@ rmc_status harvest_all(rmc_ctx *L)
     return RMC_OK;
 }
 
-template <class Real>
-rmc_status run_pipeline(rmc_ctx *const *ctxs, int nsnap, double *const *divq, double *const *se, rmc_mem mem,
-                        hipStream_t s)
+// Everything the enqueue phase needs; built on the host by plan_pipeline.
+struct Plan {
+    std::vector<rmc_ctx *> ctxs;
+    std::vector<SnapDesc> D;
+    int nfaces = 0, ntiles = 0, tile_cells = 0;
+    uint64_t total_cells = 0, max_chunks = 0;
+    bool inc_xz = true, pdf_mode = false;
+    uint32_t cont_cap = 0;
+};
+
+// Host part of a compute: buffers (allocated or grown), descriptors and their upload on s.
+template <class Real> rmc_status plan_pipeline(rmc_ctx *const *ctxs, int nsnap, Plan &P, hipStream_t s)
 {
     rmc_ctx *L = ctxs[0];   // leader: owns the shared workspace and the timers
     rmc_status st;
     const rmc_options &O = L->opt;
     const int nb = L->nb, ng = L->ng, nbucket = nb * ng * 8, R = O.rays_per_cell;
-    const bool pdf_mode = O.sampling == RMC_SAMPLING_PDF;
-    if ((st = L->counters.ensure(sizeof(unsigned long long) * 3))) return st;
-    if (!L->have_counters) {
-        HIPCHK(hipMemsetAsync(L->counters.p, 0, sizeof(unsigned long long) * 3, s));
-        L->have_counters = true;
-    }
-    if (L->ring.empty()) {
-        L->ring.resize(256);
-        for (auto &set : L->ring)
-            for (auto &e : set.e) HIPCHK(hipEventCreate(&e));
-    }
-    const int set_idx = (int)(L->ring_head % L->ring.size());
-    rmc_ctx::EvSet &EV = L->ring[set_idx];
-    if (EV.pending && (st = harvest(L, EV))) return st;
-    HIPCHK(hipEventRecord(EV.e[0], s));
-    // 1-2. per-snapshot pdf, fields and slots
-    std::vector<SnapDesc> D(nsnap);
-    uint64_t total_cells = 0, total_ncpad = 0;
-    int nfaces = 0;
+    P = Plan{};
+    P.ctxs.assign(ctxs, ctxs + nsnap);
+    P.pdf_mode = O.sampling == RMC_SAMPLING_PDF;
+    P.D.resize(nsnap);
+    uint64_t total_ncpad = 0;
     for (int q = 0; q < nsnap; ++q) {
-        if ((st = prepare_snapshot<Real>(ctxs[q], s, D[q]))) return st;
-        D[q].face_off = nfaces;
-        nfaces += ctxs[q]->nx + ctxs[q]->ny + ctxs[q]->nz + 3;
-        total_cells += ncells_of(ctxs[q]);
-        total_ncpad += D[q].ncpad;
+        if ((st = plan_snapshot<Real>(ctxs[q], P.D[q]))) return st;
+        P.D[q].face_off = P.nfaces;
+        P.nfaces += ctxs[q]->nx + ctxs[q]->ny + ctxs[q]->nz + 3;
+        P.total_cells += ncells_of(ctxs[q]);
+        total_ncpad += P.D[q].ncpad;
     }
-    if ((size_t)nfaces * sizeof(double) > 48 * 1024)
+    if ((size_t)P.nfaces * sizeof(double) > 48 * 1024)
         return fail(RMC_UNSUPPORTED, "face tables of all snapshots exceed 48 KiB of LDS");
     // tiles: about 1024 in total, whole bricks
-    int tile_cells = (int)std::min<uint64_t>(8192, std::max<uint64_t>(256, (total_ncpad / 1024 + 63) / 64 * 64));
-    int ntiles = 0;
-    std::vector<int> tile_snap;
+    P.tile_cells = (int)std::min<uint64_t>(8192, std::max<uint64_t>(256, (total_ncpad / 1024 + 63) / 64 * 64));
+    std::vector<int> &tile_snap = L->h_tile_snap;
+    tile_snap.clear();
     for (int q = 0; q < nsnap; ++q) {
-        D[q].tile_begin = ntiles;
-        D[q].ntiles = (int)((D[q].ncpad + tile_cells - 1) / tile_cells);
-        ntiles += D[q].ntiles;
-        for (int t = 0; t < D[q].ntiles; ++t) tile_snap.push_back(q);
+        P.D[q].tile_begin = P.ntiles;
+        P.D[q].ntiles = (int)((P.D[q].ncpad + P.tile_cells - 1) / P.tile_cells);
+        P.ntiles += P.D[q].ntiles;
+        for (int t = 0; t < P.D[q].ntiles; ++t) tile_snap.push_back(q);
+        P.inc_xz = P.inc_xz && P.D[q].hx > 0.0 && P.D[q].hz > 0.0;
     }
-    std::vector<double> faces;
-    faces.reserve(nfaces);
+    std::vector<double> &faces = L->h_faces;
+    faces.clear();
     for (int q = 0; q < nsnap; ++q) {
         for (double v : ctxs[q]->xf) faces.push_back(v);
         for (double v : ctxs[q]->yf) faces.push_back(v);
         for (double v : ctxs[q]->zf) faces.push_back(v);
     }
-    const uint64_t max_items = (total_cells * R + (uint64_t)nbucket * 63 + 63) / 64 * 64;
-    const uint64_t max_chunks = max_items / 64;
+    const uint64_t max_items = (P.total_cells * R + (uint64_t)nbucket * 63 + 63) / 64 * 64;
+    P.max_chunks = max_items / 64;
     if (max_items >= (1ull << 32)) return fail(RMC_UNSUPPORTED, "more than 2^32 rays in one pass");
-    if ((st = L->hist.ensure(sizeof(uint32_t) * (uint64_t)nbucket * ntiles)) ||
+    if ((st = L->hist.ensure(sizeof(uint32_t) * (uint64_t)nbucket * P.ntiles)) ||
         (st = L->bucket_total.ensure(sizeof(uint32_t) * nbucket)) ||
         (st = L->bucket_start.ensure(sizeof(uint32_t) * (nbucket + 1))) ||
         (st = L->nchunks.ensure(sizeof(uint32_t))) ||
-        (st = L->chunk_bucket.ensure(sizeof(uint32_t) * max_chunks)) ||
-        (st = L->items.ensure(sizeof(uint2) * max_items)) || (st = L->faces.ensure(sizeof(double) * nfaces)) ||
-        (st = L->snaps.ensure(sizeof(SnapDesc) * nsnap)) || (st = L->tile_snap.ensure(sizeof(int) * ntiles)))
+        (st = L->chunk_bucket.ensure(sizeof(uint32_t) * P.max_chunks)) ||
+        (st = L->items.ensure(sizeof(uint4) * max_items)) || (st = L->faces.ensure(sizeof(double) * P.nfaces)) ||
+        (st = L->snaps.ensure(sizeof(SnapDesc) * nsnap)) || (st = L->tile_snap.ensure(sizeof(int) * P.ntiles)) ||
+        (st = L->border.ensure(sizeof(uint32_t) * nbucket)) ||
+        (st = L->counters.ensure(sizeof(unsigned long long) * 3)) ||
+        (st = L->kmin.ensure(sizeof(float) * nb * ng)) || (st = L->cont_count.ensure(sizeof(uint32_t))))
         return st;
-    HIPCHK(hipMemcpyAsync(L->faces.p, faces.data(), sizeof(double) * nfaces, hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(L->snaps.p, D.data(), sizeof(SnapDesc) * nsnap, hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(L->tile_snap.p, tile_snap.data(), sizeof(int) * ntiles, hipMemcpyHostToDevice, s));
-    HIPCHK(hipEventRecord(EV.e[1], s));
+    P.cont_cap = (uint32_t)std::min<uint64_t>(P.total_cells * R, 1u << 20);
+    if ((st = L->cont.ensure(sizeof(ContRec) * P.cont_cap))) return st;
+    {   // kappa lower bound over all snapshots of the batch
+        std::vector<float> tmp;
+        kappa_lower_bounds(ctxs[0], L->h_kmin);
+        for (int q = 1; q < nsnap; ++q) {
+            kappa_lower_bounds(ctxs[q], tmp);
+            for (size_t u = 0; u < tmp.size(); ++u) L->h_kmin[u] = std::min(L->h_kmin[u], tmp[u]);
+        }
+    }
+    if (!L->have_counters) {
+        HIPCHK(hipMemsetAsync(L->counters.p, 0, sizeof(unsigned long long) * 3, s));
+        L->have_counters = true;
+    }
+    L->h_snaps.resize(sizeof(SnapDesc) * nsnap);
+    memcpy(L->h_snaps.data(), P.D.data(), sizeof(SnapDesc) * nsnap);
+    march_order(L, L->h_order);
+    HIPCHK(hipMemcpyAsync(L->faces.p, faces.data(), sizeof(double) * P.nfaces, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(L->snaps.p, L->h_snaps.data(), sizeof(SnapDesc) * nsnap, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(L->tile_snap.p, tile_snap.data(), sizeof(int) * P.ntiles, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(L->border.p, L->h_order.data(), sizeof(uint32_t) * nbucket, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(L->kmin.p, L->h_kmin.data(), sizeof(float) * nb * ng, hipMemcpyHostToDevice, s));
+    return RMC_OK;
+}
+
+// Device part of a compute: kernel launches only (no allocation, host copy or memset), so
+// that the sequence can be captured into a HIP graph.  divq / se are device pointers.
+// With EV, phase events are recorded (eager path only).
+template <class Real>
+rmc_status enqueue_pipeline(const Plan &P, double *const *divq, double *const *se, hipStream_t s,
+                            rmc_ctx::EvSet *EV)
+{
+    rmc_ctx *L = P.ctxs[0];
+    rmc_status st;
+    const rmc_options &O = L->opt;
+    const int nsnap = (int)P.ctxs.size();
+    const int nb = L->nb, ng = L->ng, nbucket = nb * ng * 8, R = O.rays_per_cell;
+    if (EV) HIPCHK(hipEventRecord(EV->e[0], s));
+    // 1-2. per-snapshot pdf and property fields
+    for (int q = 0; q < nsnap; ++q)
+        if ((st = enqueue_snapshot<Real>(P.ctxs[q], P.D[q], s))) return st;
+    if (EV) HIPCHK(hipEventRecord(EV->e[1], s));
 
     // 3. allocation: histogram per tile, scan per bucket, layout, scatter
     AllocArgs AA;
     AA.snaps = L->snaps.as<SnapDesc>();
     AA.tile_snap = L->tile_snap.as<int>();
-    AA.ntiles = ntiles;
-    AA.tile_cells = tile_cells;
+    AA.ntiles = P.ntiles;
+    AA.tile_cells = P.tile_cells;
     AA.nb = nb; AA.ng = ng; AA.nbucket = nbucket; AA.R = R;
     AA.k0 = (uint32_t)O.seed; AA.k1 = (uint32_t)(O.seed >> 32);
     AA.hist = L->hist.as<uint32_t>();
     AA.bucket_start = L->bucket_start.as<uint32_t>();
-    AA.items = L->items.as<uint2>();
+    AA.items = L->items.as<uint4>();
     const size_t lds_count = sizeof(uint32_t) * nbucket;
     const size_t lds_scatter = sizeof(uint32_t) * (nbucket + 256);
-    if (pdf_mode) hipLaunchKernelGGL(k_alloc_count<true>, dim3(ntiles), dim3(256), lds_count, s, AA);
-    else hipLaunchKernelGGL(k_alloc_count<false>, dim3(ntiles), dim3(256), lds_count, s, AA);
+    if (P.pdf_mode) hipLaunchKernelGGL(k_alloc_count<true>, dim3(P.ntiles), dim3(256), lds_count, s, AA);
+    else hipLaunchKernelGGL(k_alloc_count<false>, dim3(P.ntiles), dim3(256), lds_count, s, AA);
     HIPCHK(hipGetLastError());
-    hipLaunchKernelGGL(k_bucket_scan, dim3(nbucket), dim3(64), 0, s, L->hist.as<uint32_t>(), ntiles,
+    hipLaunchKernelGGL(k_bucket_scan, dim3(nbucket), dim3(64), 0, s, L->hist.as<uint32_t>(), P.ntiles,
                        L->bucket_total.as<uint32_t>());
     HIPCHK(hipGetLastError());
-    hipLaunchKernelGGL(k_bucket_layout, dim3(1), dim3(1024), 0, s, L->bucket_total.as<uint32_t>(), nbucket,
-                       L->bucket_start.as<uint32_t>(), L->nchunks.as<uint32_t>());
+    hipLaunchKernelGGL(k_bucket_layout, dim3(1), dim3(1024), 0, s, L->bucket_total.as<uint32_t>(),
+                       L->border.as<uint32_t>(), nbucket, L->bucket_start.as<uint32_t>(), L->nchunks.as<uint32_t>());
     HIPCHK(hipGetLastError());
     hipLaunchKernelGGL(k_chunk_map, dim3((nbucket + 3) / 4), dim3(64, 4), 0, s, L->bucket_total.as<uint32_t>(),
                        L->bucket_start.as<uint32_t>(), nbucket, L->chunk_bucket.as<uint32_t>(),
-                       L->items.as<uint2>());
+                       L->items.as<uint4>());
     HIPCHK(hipGetLastError());
-    if (pdf_mode) hipLaunchKernelGGL(k_alloc_scatter<true>, dim3(ntiles), dim3(256), lds_scatter, s, AA);
-    else hipLaunchKernelGGL(k_alloc_scatter<false>, dim3(ntiles), dim3(256), lds_scatter, s, AA);
+    if (P.pdf_mode) hipLaunchKernelGGL(k_alloc_scatter<true>, dim3(P.ntiles), dim3(256), lds_scatter, s, AA);
+    else hipLaunchKernelGGL(k_alloc_scatter<false>, dim3(P.ntiles), dim3(256), lds_scatter, s, AA);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipEventRecord(EV.e[2], s));
+    if (EV) HIPCHK(hipEventRecord(EV->e[2], s));
 
-    // 4. march: 4 wavefronts per block, grid sized for the worst-case chunk count
+    // 4. march: one wavefront per 64-ray chunk
     MarchArgs<Real> MA;
     MA.snaps = L->snaps.as<SnapDesc>();
     MA.faces = L->faces.as<double>();
-    MA.nfaces = nfaces;
-    MA.items = L->items.as<uint2>();
+    MA.nfaces = P.nfaces;
+    MA.items = L->items.as<uint4>();
     MA.chunk_bucket = L->chunk_bucket.as<uint32_t>();
     MA.nchunks = L->nchunks.as<uint32_t>();
     MA.dnu = L->dnu.as<double>();
@@ -1028,35 +1468,97 @@ rmc_status run_pipeline(rmc_ctx *const *ctxs, int nsnap, double *const *divq, do
     MA.k0 = AA.k0; MA.k1 = AA.k1;
     MA.tol = (Real)O.tol;
     MA.max_steps = O.max_steps;
-    const unsigned mblocks = (unsigned)((max_chunks + 3) / 4);
-    const size_t lds_faces = sizeof(double) * nfaces;
-    if (pdf_mode) hipLaunchKernelGGL((k_march<Real, true>), dim3(mblocks), dim3(256), lds_faces, s, MA);
-    else hipLaunchKernelGGL((k_march<Real, false>), dim3(mblocks), dim3(256), lds_faces, s, MA);
+    // long rays are segmented only in the FP32 march over uniform periodic x and z
+    const bool segment = sizeof(Real) == 4 && P.inc_xz;
+    const int lrs = O.long_ray_steps > 0 ? O.long_ray_steps : 256;
+    MA.cap = segment ? std::min(lrs, O.max_steps) : O.max_steps;
+    MA.kmin = L->kmin.as<float>();
+    MA.cont = L->cont.as<ContRec>();
+    MA.cont_count = L->cont_count.as<uint32_t>();
+    MA.cont_cap = P.cont_cap;
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, L->cont_count.as<uint32_t>(), 1);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipEventRecord(EV.e[3], s));
-
-    // 5. per-cell reduction into the caller's buffers
-    HIPCHK(hipMemsetAsync(L->counters.p, 0, sizeof(unsigned long long) * 2, s));   // last-compute part only
-    for (int q = 0; q < nsnap; ++q) {
-        rmc_ctx *c = ctxs[q];
-        const uint64_t nc = ncells_of(c);
-        double *dq = divq[q], *sq = se ? se[q] : nullptr;
-        if (mem == RMC_HOST) {
-            if ((st = c->outbuf.ensure(sizeof(double) * 2 * nc))) return st;
-            dq = c->outbuf.as<double>();
-            sq = (se && se[q]) ? dq + nc : nullptr;
-        }
-        hipLaunchKernelGGL(k_reduce<Real>, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, s, c->Y.as<Real>(),
-                           c->st.as<uint32_t>(), nc, R, (int)O.accum, dq, sq, L->counters.as<unsigned long long>());
-        HIPCHK(hipGetLastError());
-        if (mem == RMC_HOST) {
-            HIPCHK(hipMemcpyAsync(divq[q], dq, sizeof(double) * nc, hipMemcpyDeviceToHost, s));
-            if (sq) HIPCHK(hipMemcpyAsync(se[q], sq, sizeof(double) * nc, hipMemcpyDeviceToHost, s));
+    const unsigned mblocks = (unsigned)((P.max_chunks + 3) / 4);
+    const size_t lds_faces = sizeof(double) * P.nfaces;
+    const bool multi = nsnap > 1;
+#define RMC_MARCH(PDF_, INC_, MULTI_) \
+    hipLaunchKernelGGL((k_march_lane<Real, PDF_, INC_, MULTI_>), dim3(mblocks), dim3(256), lds_faces, s, MA)
+    if (P.pdf_mode) {
+        if (P.inc_xz) { if (multi) RMC_MARCH(true, true, true); else RMC_MARCH(true, true, false); }
+        else { if (multi) RMC_MARCH(true, false, true); else RMC_MARCH(true, false, false); }
+    } else {
+        if (P.inc_xz) { if (multi) RMC_MARCH(false, true, true); else RMC_MARCH(false, true, false); }
+        else { if (multi) RMC_MARCH(false, false, true); else RMC_MARCH(false, false, false); }
+    }
+#undef RMC_MARCH
+    HIPCHK(hipGetLastError());
+    if constexpr (sizeof(Real) == 4) {
+        if (segment && MA.cap < O.max_steps) {
+            if (P.pdf_mode) {
+                if (multi) hipLaunchKernelGGL((k_march_long<true, true>), dim3(1024), dim3(256), lds_faces, s, MA);
+                else hipLaunchKernelGGL((k_march_long<true, false>), dim3(1024), dim3(256), lds_faces, s, MA);
+            } else {
+                if (multi) hipLaunchKernelGGL((k_march_long<false, true>), dim3(1024), dim3(256), lds_faces, s, MA);
+                else hipLaunchKernelGGL((k_march_long<false, false>), dim3(1024), dim3(256), lds_faces, s, MA);
+            }
+            HIPCHK(hipGetLastError());
         }
     }
-    HIPCHK(hipEventRecord(EV.e[4], s));
+    if (EV) HIPCHK(hipEventRecord(EV->e[3], s));
+
+    // 5. per-cell reduction into the (device) output buffers
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, L->counters.as<unsigned long long>(), 2);
+    HIPCHK(hipGetLastError());
+    for (int q = 0; q < nsnap; ++q) {
+        rmc_ctx *c = P.ctxs[q];
+        const uint64_t nc = ncells_of(c);
+        const uint64_t groups = (nc + (kRedVals / R) - 1) / (kRedVals / R);
+        hipLaunchKernelGGL(k_reduce<Real>, dim3((unsigned)std::min<uint64_t>(groups, 2048)), dim3(256), 0, s,
+                           c->Y.as<Real>(), c->st.as<uint32_t>(), nc, R, (int)O.accum, divq[q],
+                           se ? se[q] : nullptr, L->counters.as<unsigned long long>());
+        HIPCHK(hipGetLastError());
+    }
+    if (EV) HIPCHK(hipEventRecord(EV->e[4], s));
+    return RMC_OK;
+}
+
+// Eager compute: plan, enqueue with phase events, copy host outputs back.
+template <class Real>
+rmc_status run_pipeline(rmc_ctx *const *ctxs, int nsnap, double *const *divq, double *const *se, rmc_mem mem,
+                        hipStream_t s)
+{
+    rmc_ctx *L = ctxs[0];
+    rmc_status st;
+    if (L->ring.empty()) {
+        L->ring.resize(256);
+        for (auto &set : L->ring)
+            for (auto &e : set.e) HIPCHK(hipEventCreate(&e));
+    }
+    const int set_idx = (int)(L->ring_head % L->ring.size());
+    rmc_ctx::EvSet &EV = L->ring[set_idx];
+    if (EV.pending && (st = harvest(L, EV))) return st;
+    Plan P;
+    if ((st = plan_pipeline<Real>(ctxs, nsnap, P, s))) return st;
+    std::vector<double *> dq(nsnap), sq(nsnap, nullptr);
+    for (int q = 0; q < nsnap; ++q) {
+        const uint64_t nc = ncells_of(ctxs[q]);
+        dq[q] = divq[q];
+        sq[q] = se ? se[q] : nullptr;
+        if (mem == RMC_HOST) {
+            if ((st = ctxs[q]->outbuf.ensure(sizeof(double) * 2 * nc))) return st;
+            dq[q] = ctxs[q]->outbuf.as<double>();
+            sq[q] = (se && se[q]) ? dq[q] + nc : nullptr;
+        }
+    }
+    if ((st = enqueue_pipeline<Real>(P, dq.data(), sq.data(), s, &EV))) return st;
+    if (mem == RMC_HOST)
+        for (int q = 0; q < nsnap; ++q) {
+            const uint64_t nc = ncells_of(ctxs[q]);
+            HIPCHK(hipMemcpyAsync(divq[q], dq[q], sizeof(double) * nc, hipMemcpyDeviceToHost, s));
+            if (sq[q]) HIPCHK(hipMemcpyAsync(se[q], sq[q], sizeof(double) * nc, hipMemcpyDeviceToHost, s));
+        }
     EV.pending = true;
-    EV.rays = (int64_t)total_cells * R;
+    EV.rays = (int64_t)P.total_cells * L->opt.rays_per_cell;
     L->last_set = set_idx;
     ++L->ring_head;
     return RMC_OK;
@@ -1067,7 +1569,8 @@ rmc_status validate_T(rmc_ctx *c, const void *src, rmc_dtype dt, rmc_mem mem, hi
     const uint64_t nc = ncells_of(c);
     const size_t esz = dt == RMC_F32 ? 4 : 8;
     rmc_status st;
-    if ((st = c->T.ensure(sizeof(double) * nc)) || (st = c->small.ensure(64))) return st;
+    if ((st = c->T.ensure(sizeof(double) * nc)) || (st = c->small.ensure(64)) || (st = c->scal.ensure(sizeof(double) * 9)))
+        return st;
     const void *dsrc = src;
     if (mem == RMC_HOST) {
         if ((st = c->stage.ensure(esz * nc))) return st;
@@ -1075,9 +1578,10 @@ rmc_status validate_T(rmc_ctx *c, const void *src, rmc_dtype dt, rmc_mem mem, hi
         dsrc = c->stage.p;
     }
     HIPCHK(hipMemsetAsync(c->small.p, 0, 64, s));
+    HIPCHK(hipMemsetAsync(c->small.as<unsigned long long>() + 2, 0x7F, 8, s));   // min slot: a huge double
     unsigned long long *mx = c->small.as<unsigned long long>();
     unsigned int *flag = reinterpret_cast<unsigned int *>(mx + 1);
-    const unsigned blocks = (unsigned)std::min<uint64_t>(4096, (nc + 255) / 256);
+    const unsigned blocks = (unsigned)std::min<uint64_t>(512, (nc + 255) / 256);
     if (dt == RMC_F32)
         hipLaunchKernelGGL(k_ingest_T<float>, dim3(blocks), dim3(256), 0, s, (const float *)dsrc, c->T.as<double>(),
                            nc, c->T0, c->dT, c->nT, mx, flag);
@@ -1085,8 +1589,8 @@ rmc_status validate_T(rmc_ctx *c, const void *src, rmc_dtype dt, rmc_mem mem, hi
         hipLaunchKernelGGL(k_ingest_T<double>, dim3(blocks), dim3(256), 0, s, (const double *)dsrc,
                            c->T.as<double>(), nc, c->T0, c->dT, c->nT, mx, flag);
     HIPCHK(hipGetLastError());
-    unsigned long long host[2] = {0, 0};
-    HIPCHK(hipMemcpyAsync(host, c->small.p, 16, hipMemcpyDeviceToHost, s));
+    unsigned long long host[3] = {0, 0, 0};
+    HIPCHK(hipMemcpyAsync(host, c->small.p, 24, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if ((unsigned)host[1] & 1u) {
         c->have_T = false;
@@ -1096,7 +1600,60 @@ rmc_status validate_T(rmc_ctx *c, const void *src, rmc_dtype dt, rmc_mem mem, hi
     double m;
     memcpy(&m, &host[0], 8);
     c->Tmax_cells = m;
+    memcpy(&c->Tmin_cells, &host[2], 8);
+    HIPCHK(hipMemcpyAsync(c->scal.p, &c->Tmax_cells, sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
     c->have_T = true;
+    return RMC_OK;
+}
+
+}  // namespace
+
+struct rmc_graph {
+    int device = 0;
+    std::vector<rmc_ctx *> ctxs;
+    std::vector<uint64_t> versions;
+    std::vector<std::vector<void *>> ptrs;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+// device buffers a captured compute reads or writes (a change means they were reallocated)
+std::vector<void *> buffer_ptrs(const rmc_ctx *c)
+{
+    const DBuf *b[] = {&c->k64, &c->Ib, &c->dnu, &c->wg, &c->T, &c->X, &c->scal, &c->q, &c->cpdf, &c->ccdf_b,
+                       &c->ccdf_g, &c->ccdf_o, &c->pdf_scratch, &c->p, &c->cdf_b, &c->cdf_g, &c->W, &c->Iw,
+                       &c->status, &c->field, &c->Iplane, &c->Y, &c->st, &c->hist, &c->bucket_total,
+                       &c->bucket_start, &c->nchunks, &c->chunk_bucket, &c->items, &c->faces, &c->snaps,
+                       &c->tile_snap, &c->border, &c->counters, &c->kmin, &c->cont, &c->cont_count};
+    std::vector<void *> v;
+    for (const DBuf *d : b) v.push_back(d->p);
+    return v;
+}
+
+// shared validation of a batch (compute or capture)
+rmc_status check_batch(rmc_ctx *const *ctxs, int nsnap)
+{
+    if (!ctxs || nsnap < 1 || nsnap > 32767) return fail(RMC_INVALID_ARG, "bad batch arguments");
+    rmc_ctx *L = ctxs[0];
+    if (!L) return fail(RMC_INVALID_ARG, "null context");
+    for (int q = 0; q < nsnap; ++q) {
+        rmc_ctx *c = ctxs[q];
+        if (!c) return fail(RMC_INVALID_ARG, "null context in the batch");
+        if (rmc_status st = check_ready(c)) return st;
+        if (c->device != L->device) return fail(RMC_INVALID_ARG, "batch contexts must share one device");
+        if (c->nb != L->nb || c->ng != L->ng || c->ns != L->ns || c->nT != L->nT || c->T0 != L->T0 ||
+            c->dT != L->dT)
+            return fail(RMC_INVALID_ARG, "batch contexts must share the tables");
+        const rmc_options &a = c->opt, &b = L->opt;
+        if (a.rays_per_cell != b.rays_per_cell || a.seed != b.seed || a.tol != b.tol || a.max_steps != b.max_steps ||
+            a.march != b.march || a.accum != b.accum || a.sampling != b.sampling)
+            return fail(RMC_INVALID_ARG, "batch contexts must share the options (snapshot ids may differ)");
+        for (int q2 = 0; q2 < q; ++q2)
+            if (ctxs[q2] == c) return fail(RMC_INVALID_ARG, "a context appears twice in the batch");
+    }
     return RMC_OK;
 }
 
@@ -1153,7 +1710,8 @@ void rmc_destroy(rmc_ctx *c)
                         &c->ccdf_g, &c->ccdf_o, &c->pdf_scratch, &c->p, &c->cdf_b, &c->cdf_g, &c->W, &c->Iw,
                         &c->status, &c->field, &c->Iplane, &c->Y, &c->st, &c->hist, &c->bucket_total, &c->bucket_start,
                         &c->nchunks, &c->chunk_bucket, &c->items, &c->faces, &c->snaps, &c->tile_snap,
-                        &c->counters, &c->outbuf, &c->trace_rec, &c->trace_cells, &c->small};
+                        &c->counters, &c->outbuf, &c->trace_rec, &c->trace_cells, &c->border, &c->small, &c->scal,
+                        &c->kmin, &c->cont, &c->cont_count};
         for (DBuf *b : bufs) b->release();
         for (auto &set : c->ring)
             for (auto &ev : set.e) (void)hipEventDestroy(ev);
@@ -1181,6 +1739,7 @@ rmc_status rmc_set_grid(rmc_ctx *c, int nx, int ny, int nz, const double *xf, co
     c->zf.assign(zf, zf + nz + 1);
     c->have_grid = true;
     c->have_T = c->have_X = c->have_q = false;
+    ++c->config_version;
     return RMC_OK;
 }
 
@@ -1194,6 +1753,7 @@ rmc_status rmc_set_walls(rmc_ctx *c, double T0, double T1, double e0, double e1)
     c->Tw[0] = T0;
     c->Tw[1] = T1;
     c->have_walls = true;
+    ++c->config_version;
     return RMC_OK;
 }
 
@@ -1236,6 +1796,7 @@ rmc_status rmc_set_kdist(rmc_ctx *c, int nb, int ng, int ns, int nT, double T0, 
         (st = c->dnu.ensure(sizeof(double) * nb)) || (st = c->wg.ensure(sizeof(double) * ng)))
         return st;
     HIPCHK(hipMemcpy(c->k64.p, k64.data(), sizeof(double) * nk, hipMemcpyHostToDevice));
+    c->k64_host = k64;
     HIPCHK(hipMemcpy(c->Ib.p, Ib, sizeof(double) * nb * nT, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c->dnu.p, dnu, sizeof(double) * nb, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c->wg.p, wg, sizeof(double) * ng, hipMemcpyHostToDevice));
@@ -1246,6 +1807,7 @@ rmc_status rmc_set_kdist(rmc_ctx *c, int nb, int ng, int ns, int nT, double T0, 
     c->have_kdist = true;
     if (!same_range) c->have_T = false;   // temperatures must be re-validated against the new range
     c->have_q = false;
+    ++c->config_version;
     return RMC_OK;
 }
 
@@ -1277,17 +1839,20 @@ rmc_status rmc_set_species(rmc_ctx *c, int ns, const void *X, rmc_dtype dt, rmc_
     const uint64_t nc = ncells_of(c);
     const size_t esz = dt == RMC_F32 ? 4 : 8;
     rmc_status st;
-    if ((st = c->X.ensure(sizeof(double) * nc * ns)) || (st = c->small.ensure(128))) return st;
+    if ((st = c->X.ensure(sizeof(double) * nc * ns)) || (st = c->small.ensure(256)) ||
+        (st = c->scal.ensure(sizeof(double) * 9)))
+        return st;
     const void *dsrc = X;
     if (mem == RMC_HOST) {
         if ((st = c->stage.ensure(esz * nc * ns))) return st;
         HIPCHK(hipMemcpyAsync(c->stage.p, X, esz * nc * ns, hipMemcpyHostToDevice, s));
         dsrc = c->stage.p;
     }
-    HIPCHK(hipMemsetAsync(c->small.p, 0, 128, s));
+    HIPCHK(hipMemsetAsync(c->small.p, 0, 256, s));
+    HIPCHK(hipMemsetAsync(c->small.as<unsigned long long>() + 8, 0x7F, 64, s));   // min slots: huge doubles
     unsigned long long *mx = c->small.as<unsigned long long>();
-    unsigned int *flag = reinterpret_cast<unsigned int *>(mx + 8);
-    const unsigned blocks = (unsigned)std::min<uint64_t>(4096, (nc + 255) / 256);
+    unsigned int *flag = reinterpret_cast<unsigned int *>(mx + 16);
+    const unsigned blocks = (unsigned)std::min<uint64_t>(512, (nc + 255) / 256);
     if (dt == RMC_F32)
         hipLaunchKernelGGL(k_ingest_X<float>, dim3(blocks), dim3(256), 0, s, (const float *)dsrc, c->X.as<double>(),
                            nc, ns, mx, flag);
@@ -1295,14 +1860,19 @@ rmc_status rmc_set_species(rmc_ctx *c, int ns, const void *X, rmc_dtype dt, rmc_
         hipLaunchKernelGGL(k_ingest_X<double>, dim3(blocks), dim3(256), 0, s, (const double *)dsrc,
                            c->X.as<double>(), nc, ns, mx, flag);
     HIPCHK(hipGetLastError());
-    unsigned long long host[9] = {0};
+    unsigned long long host[17] = {0};
     HIPCHK(hipMemcpyAsync(host, c->small.p, sizeof host, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    if ((unsigned)host[8] & 1u) {
+    if ((unsigned)host[16] & 1u) {
         c->have_X = false;
         return fail(RMC_OUT_OF_RANGE, "mole fractions must be finite and >= 0");
     }
-    for (int q = 0; q < ns; ++q) memcpy(&c->xhat[q], &host[q], 8);
+    for (int q = 0; q < ns; ++q) {
+        memcpy(&c->xhat[q], &host[q], 8);
+        memcpy(&c->xmin[q], &host[8 + q], 8);
+    }
+    HIPCHK(hipMemcpyAsync(c->scal.as<double>() + 1, c->xhat, sizeof(double) * ns, hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
     c->have_X = true;
     return RMC_OK;
 }
@@ -1314,6 +1884,7 @@ rmc_status rmc_set_options(rmc_ctx *c, const rmc_options *o)
     if (!o) return fail(RMC_INVALID_ARG, "null options");
     if (rmc_status st = check_options(o)) return st;
     c->opt = *o;
+    ++c->config_version;
     return RMC_OK;
 }
 
@@ -1339,25 +1910,12 @@ rmc_status rmc_compute_batch(rmc_ctx *const *ctxs, int nsnap, double *const *div
                              void *stream)
 {
     g_err.clear();
-    if (!ctxs || nsnap < 1 || nsnap > 32767 || !divq) return fail(RMC_INVALID_ARG, "bad batch arguments");
+    if (!divq) return fail(RMC_INVALID_ARG, "null outputs");
     if (mem != RMC_HOST && mem != RMC_DEVICE) return fail(RMC_INVALID_ARG, "bad memory kind");
+    if (rmc_status st = check_batch(ctxs, nsnap)) return st;
+    for (int q = 0; q < nsnap; ++q)
+        if (!divq[q]) return fail(RMC_INVALID_ARG, "null output in the batch");
     rmc_ctx *L = ctxs[0];
-    if (!L) return fail(RMC_INVALID_ARG, "null context");
-    for (int q = 0; q < nsnap; ++q) {
-        rmc_ctx *c = ctxs[q];
-        if (!c || !divq[q]) return fail(RMC_INVALID_ARG, "null context or output in the batch");
-        if (rmc_status st = check_ready(c)) return st;
-        if (c->device != L->device) return fail(RMC_INVALID_ARG, "batch contexts must share one device");
-        if (c->nb != L->nb || c->ng != L->ng || c->ns != L->ns || c->nT != L->nT || c->T0 != L->T0 ||
-            c->dT != L->dT)
-            return fail(RMC_INVALID_ARG, "batch contexts must share the tables");
-        const rmc_options &a = c->opt, &b = L->opt;
-        if (a.rays_per_cell != b.rays_per_cell || a.seed != b.seed || a.tol != b.tol || a.max_steps != b.max_steps ||
-            a.march != b.march || a.accum != b.accum || a.sampling != b.sampling)
-            return fail(RMC_INVALID_ARG, "batch contexts must share the options (snapshot ids may differ)");
-        for (int q2 = 0; q2 < q; ++q2)
-            if (ctxs[q2] == c) return fail(RMC_INVALID_ARG, "a context appears twice in the batch");
-    }
     DeviceGuard g(L->device);
     if (!g.ok) return fail(RMC_DEVICE_ERROR, "hipSetDevice(%d) failed", L->device);
     hipStream_t s = (hipStream_t)stream;
@@ -1374,6 +1932,89 @@ rmc_status rmc_compute_divergence(rmc_ctx *c, double *divq, double *se, rmc_mem 
     double *d[1] = {divq};
     double *e[1] = {se};
     return rmc_compute_batch(cs, 1, d, e, mem, stream);
+}
+
+rmc_status rmc_graph_capture(rmc_ctx *const *ctxs, int nsnap, double *const *divq, double *const *se, void *stream,
+                             rmc_graph **out)
+{
+    g_err.clear();
+    if (!out) return fail(RMC_INVALID_ARG, "null output pointer");
+    *out = nullptr;
+    if (!divq) return fail(RMC_INVALID_ARG, "null outputs");
+    if (!stream) return fail(RMC_INVALID_ARG, "graph capture needs a stream other than the null stream");
+    if (rmc_status st = check_batch(ctxs, nsnap)) return st;
+    for (int q = 0; q < nsnap; ++q)
+        if (!divq[q]) return fail(RMC_INVALID_ARG, "null output in the batch");
+    rmc_ctx *L = ctxs[0];
+    DeviceGuard g(L->device);
+    if (!g.ok) return fail(RMC_DEVICE_ERROR, "hipSetDevice(%d) failed", L->device);
+    hipStream_t s = (hipStream_t)stream;
+    const bool dbl = L->opt.march == RMC_F64;
+    Plan P;
+    rmc_status st = dbl ? plan_pipeline<double>(ctxs, nsnap, P, s) : plan_pipeline<float>(ctxs, nsnap, P, s);
+    if (st) return st;
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    st = dbl ? enqueue_pipeline<double>(P, divq, se, s, nullptr) : enqueue_pipeline<float>(P, divq, se, s, nullptr);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(s, &graph);
+    if (st || ec != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipGetLastError();
+        if (st) return st;
+        return fail(RMC_DEVICE_ERROR, "hipStreamEndCapture failed: %s", hipGetErrorString(ec));
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        (void)hipGetLastError();
+        return fail(RMC_DEVICE_ERROR, "hipGraphInstantiate failed: %s", hipGetErrorString(ei));
+    }
+    rmc_graph *G = new (std::nothrow) rmc_graph();
+    if (!G) {
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(graph);
+        return fail(RMC_OUT_OF_MEMORY, "graph allocation failed");
+    }
+    G->device = L->device;
+    G->ctxs.assign(ctxs, ctxs + nsnap);
+    for (rmc_ctx *c : G->ctxs) {
+        G->versions.push_back(c->config_version);
+        G->ptrs.push_back(buffer_ptrs(c));
+        ++c->graphs;
+    }
+    G->graph = graph;
+    G->exec = exec;
+    *out = G;
+    return RMC_OK;
+}
+
+rmc_status rmc_graph_launch(rmc_graph *G, void *stream)
+{
+    g_err.clear();
+    if (!G || !G->exec) return fail(RMC_INVALID_ARG, "null graph");
+    for (size_t q = 0; q < G->ctxs.size(); ++q) {
+        const rmc_ctx *c = G->ctxs[q];
+        if (c->config_version != G->versions[q] || buffer_ptrs(c) != G->ptrs[q] || !c->have_T || !c->have_X)
+            return fail(RMC_BAD_STATE, "a captured context changed since the capture; capture again");
+    }
+    DeviceGuard g(G->device);
+    if (!g.ok) return fail(RMC_DEVICE_ERROR, "hipSetDevice(%d) failed", G->device);
+    HIPCHK(hipGraphLaunch(G->exec, (hipStream_t)stream));
+    return RMC_OK;
+}
+
+void rmc_graph_destroy(rmc_graph *G)
+{
+    if (!G) return;
+    for (rmc_ctx *c : G->ctxs) --c->graphs;
+    {
+        DeviceGuard g(G->device);
+        if (G->exec) (void)hipGraphExecDestroy(G->exec);
+        if (G->graph) (void)hipGraphDestroy(G->graph);
+    }
+    delete G;
 }
 
 rmc_status rmc_get_ray_values(rmc_ctx *c, const int64_t *cells, int ncell, double *Y, int32_t *steps, void *stream)
@@ -1423,8 +2064,10 @@ rmc_status rmc_trace_cells(rmc_ctx *c, const int64_t *cells, int ncell, rmc_ray_
     const bool dbl = c->opt.march == RMC_F64;
     const bool pdf_mode = c->opt.sampling == RMC_SAMPLING_PDF;
     SnapDesc D;
-    rmc_status st = dbl ? prepare_snapshot<double>(c, s, D) : prepare_snapshot<float>(c, s, D);
+    rmc_status st = dbl ? plan_snapshot<double>(c, D) : plan_snapshot<float>(c, D);
     if (st) return st;
+    if ((st = dbl ? enqueue_snapshot<double>(c, D, s) : enqueue_snapshot<float>(c, D, s))) return st;
+    const bool inc_xz = D.hx > 0.0 && D.hz > 0.0;
     const int nfaces = c->nx + c->ny + c->nz + 3;
     D.face_off = 0;
     std::vector<double> fd;
@@ -1446,14 +2089,19 @@ rmc_status rmc_trace_cells(rmc_ctx *c, const int64_t *cells, int ncell, rmc_ray_
         TraceArgs<double> A{c->snaps.as<SnapDesc>(), c->faces.as<double>(), nfaces, c->trace_cells.as<int64_t>(),
                             ncell, c->dnu.as<double>(), c->wg.as<double>(), c->nb, c->ng, R, k0, k1,
                             c->opt.tol, c->opt.max_steps, c->trace_rec.as<rmc_ray_record>()};
-        if (pdf_mode) hipLaunchKernelGGL((k_trace<double, true>), dim3(blocks), dim3(256), 8 * nfaces, s, A);
-        else hipLaunchKernelGGL((k_trace<double, false>), dim3(blocks), dim3(256), 8 * nfaces, s, A);
+        if (pdf_mode) hipLaunchKernelGGL((k_trace<double, true, false>), dim3(blocks), dim3(256), 8 * nfaces, s, A);
+        else hipLaunchKernelGGL((k_trace<double, false, false>), dim3(blocks), dim3(256), 8 * nfaces, s, A);
     } else {
         TraceArgs<float> A{c->snaps.as<SnapDesc>(), c->faces.as<double>(), nfaces, c->trace_cells.as<int64_t>(),
                            ncell, c->dnu.as<double>(), c->wg.as<double>(), c->nb, c->ng, R, k0, k1,
                            (float)c->opt.tol, c->opt.max_steps, c->trace_rec.as<rmc_ray_record>()};
-        if (pdf_mode) hipLaunchKernelGGL((k_trace<float, true>), dim3(blocks), dim3(256), 8 * nfaces, s, A);
-        else hipLaunchKernelGGL((k_trace<float, false>), dim3(blocks), dim3(256), 8 * nfaces, s, A);
+        if (inc_xz) {
+            if (pdf_mode) hipLaunchKernelGGL((k_trace<float, true, true>), dim3(blocks), dim3(256), 8 * nfaces, s, A);
+            else hipLaunchKernelGGL((k_trace<float, false, true>), dim3(blocks), dim3(256), 8 * nfaces, s, A);
+        } else {
+            if (pdf_mode) hipLaunchKernelGGL((k_trace<float, true, false>), dim3(blocks), dim3(256), 8 * nfaces, s, A);
+            else hipLaunchKernelGGL((k_trace<float, false, false>), dim3(blocks), dim3(256), 8 * nfaces, s, A);
+        }
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(out, c->trace_rec.p, sizeof(rmc_ray_record) * nrec, hipMemcpyDeviceToHost, s));

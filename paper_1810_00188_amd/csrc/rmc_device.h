@@ -37,6 +37,23 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t
     out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
+// Load through a global-memory pointer.  Pointers read from descriptors are generic to the
+// compiler; without the address space the loads become flat loads, which wait on the LDS
+// counter as well and serialise the march.
+template <class T> __device__ __forceinline__ T gld(const T *p)
+{
+    typedef const __attribute__((address_space(1))) T gT;
+    return *(gT *)(p);
+}
+
+__device__ __forceinline__ uint4 gld(const uint4 *p)
+{
+    typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+    typedef const __attribute__((address_space(1))) v4u gv4u;
+    const v4u v = *(gv4u *)(p);
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+
 // Spectral / octant variate: all 32 bits, (w + 1/2) 2^-32, exact in double, in (0, 1).
 __device__ __forceinline__ double unif_alloc(uint32_t w) { return ((double)w + 0.5) * 0x1p-32; }
 
@@ -79,8 +96,8 @@ __device__ __forceinline__ void octant_direction(uint32_t w0, uint32_t w1, int o
 
 // Bricked layout of the property fields: 4x4x4 bricks in raster order (bk fastest), Morton
 // order inside a brick (bits i1 j1 k1 i0 j0 k0).  The offset is a sum of per-axis terms.
-__device__ __forceinline__ int brick_x(int i, int sx_) { return (i >> 2) * sx_ + ((i & 1) << 2) + ((i & 2) << 4); }
-__device__ __forceinline__ int brick_y(int j, int sy_) { return (j >> 2) * sy_ + ((j & 1) << 1) + ((j & 2) << 3); }
+__device__ __forceinline__ int brick_x(int i, int sx_) { return __mul24(i >> 2, sx_) + ((i & 1) << 2) + ((i & 2) << 4); }
+__device__ __forceinline__ int brick_y(int j, int sy_) { return __mul24(j >> 2, sy_) + ((j & 1) << 1) + ((j & 2) << 3); }
 __device__ __forceinline__ int brick_z(int k) { return ((k >> 2) << 6) + (k & 1) + ((k & 2) << 2); }
 
 // Geometry of one snapshot as seen by a ray.
@@ -89,13 +106,6 @@ struct RayGeo {
     int nx, ny, nz;
     int bsx, bsy;               // brick strides of the x and y brick index (in cells)
     double Lx, Lz;              // periodic lengths
-};
-
-template <class Real> struct MarchOut {
-    Real acc;                   // sum tau alpha (I_src - I_j) + wall + residual terms
-    Real absacc;                // same with |I_src - I_j| (only when asked for)
-    int steps;
-    int end;
 };
 
 // FP32 cell absorption: alpha = 1 - exp(-x) and the transmission factor exp(-x) of a
@@ -115,108 +125,204 @@ __device__ __forceinline__ void absorb_f32(float x, float &a, float &e)
     a = x < 0.25f ? x * p : 1.0f - e;
 }
 
-// March one ray from the centre of cell (ci, cj, ck) along (dx, dy, dz) (Algorithm 1, March):
-// ds = distance to the nearest face, alpha = 1 - exp(-kappa ds) (Eq. 2), acc += tau alpha
-// (I_src - I_cell), tau *= 1 - alpha (Eq. 3); every axis whose face is reached steps; x and z
-// wrap, leaving y hits a black wall (alpha = 1, I = I_b(T_wall)).  Stops at tau <= tol or after
-// max_steps and adds the residual tau (I_src - I_last).
+// One ray of the march (Algorithm 1, March).
 //
-// K is the kappa_{n,g} plane of the ray's (band, g-point), Ipl the I_n plane of its band, both
-// in the bricked layout.  The path geometry (face parameters t, segment lengths) and the
-// intensity differences are double in both precisions; Real sets the arithmetic of kappa,
-// alpha, tau and the accumulated sum: FP64 follows the reference operation by operation, FP32
-// takes the transmission as exp(-x) itself (absorb_f32).
-template <class Real, bool ABS>
-__device__ __forceinline__ MarchOut<Real>
-march_ray(const RayGeo &G, const Real *__restrict__ K, const double *__restrict__ Ipl, int ci, int cj, int ck,
-          double dx, double dy, double dz, double Isrc, double Iw0, double Iw1, Real tol, int max_steps)
+// Per step: ds = distance to the nearest face, alpha = 1 - exp(-kappa ds) (Eq. 2),
+// acc += tau alpha (I_src - I_cell), tau *= 1 - alpha (Eq. 3); every axis whose face is
+// reached steps; x and z wrap, leaving y hits a black wall (alpha = 1, I = I_b(T_wall)).
+// The ray stops at tau <= tol or after max_steps and adds the residual tau (I_src - I_last).
+//
+// The path geometry (face parameters t, segment lengths) and intensity differences are
+// double in both precisions, and so are tau and the accumulated sum (MI355X runs FP64
+// add/mul/fma at the rate of unpacked FP32; rays of thousands of steps would otherwise lose
+// 1e-5 to rounding).  Real sets the arithmetic of kappa and alpha: FP64 follows the reference
+// operation by operation (divisions, expm1, tau *= 1 - alpha); FP32 evaluates alpha and the
+// transmission in float (absorb_f32), uses one reciprocal per axis, and with INC_XZ advances
+// the uniform periodic axes by a constant parameter increment instead of re-reading face
+// coordinates.
+//
+// A step is split into its geometry (which cell comes next) and its absorption (physics of
+// the current cell), so that the next cell's kappa and I are requested before the current
+// cell's physics runs; the march loop is unrolled twice with two register sets, so a load
+// is always in flight while the other set is consumed.
+template <class Real, bool INC_XZ> struct Ray {
+    double tx, ty, tz, t;       // next-face parameters per axis, current parameter
+    double ox, oy, oz;          // origin (cell centre)
+    double rx, ry, rz;          // 1 / direction (FP32 path) or the direction (FP64 path)
+    double dtx, dtz;            // INC_XZ: parameter increment per x / z cell
+    double Isrc;                // source intensity
+    double tau, acc;
+    int i, j, k, wi, wk;        // current cell (x, z local index and wrap count)
+    int px, py, pz;             // brick offsets of the current cell
+    int sgn;                    // bit 0/1/2: x/y/z direction negative
+    int steps, end;
+};
+
+struct XzUniform {
+    double hx, hz;              // uniform cell widths along x and z (INC_XZ)
+};
+
+// Starts the ray at the centre of cell (ci, cj, ck); returns the source cell's kappa and I.
+template <class Real, bool INC_XZ>
+__device__ __forceinline__ void ray_init(Ray<Real, INC_XZ> &R, const RayGeo &G, const XzUniform &U,
+                                         const Real *__restrict__ K, const double *__restrict__ Ipl, int ci,
+                                         int cj, int ck, double dx, double dy, double dz, Real &kc, double &Ic)
 {
-    const double ox = 0.5 * (G.xf[ci] + G.xf[ci + 1]);
-    const double oy = 0.5 * (G.yf[cj] + G.yf[cj + 1]);
-    const double oz = 0.5 * (G.zf[ck] + G.zf[ck + 1]);
-    const int sx = dx > 0.0 ? 1 : -1, sy = dy > 0.0 ? 1 : -1, sz = dz > 0.0 ? 1 : -1;
-    const int ux = sx > 0, uy = sy > 0, uz = sz > 0;
-    // FP64 march: the reference's divisions; FP32 march: one reciprocal per axis and ray
-    const double rx = 1.0 / dx, ry = 1.0 / dy, rz = 1.0 / dz;
-    auto face_t = [&](double num, double d, double r) -> double {
-        if constexpr (sizeof(Real) == 8) return num / d;
-        else return num * r;
-    };
-    int i = ci, j = cj, k = ck, wi = 0, wk = 0;
-    double tx = face_t(G.xf[i + ux] - ox, dx, rx);
-    double ty = face_t(G.yf[j + uy] - oy, dy, ry);
-    double tz = face_t(G.zf[k + uz] - oz, dz, rz);
-    int px = brick_x(i, G.bsx), py = brick_y(j, G.bsy), pz = brick_z(k);
-    double t = 0.0, Ilast = Isrc;
-    Real tau = 1, acc = 0, absacc = 0;
-    int steps = 0, end = kEndTol;
-    while (tau > tol && steps < max_steps) {
-        const double te = fmin(tx, fmin(ty, tz));
-        const int cell = px + py + pz;
-        const Real kap = K[cell];
-        const double Ij = Ipl[cell];
-        if constexpr (sizeof(Real) == 8) {
-            const double ds = te - t;
-            const double dI = Isrc - Ij;
-            const double a = -expm1(-kap * ds);
-            acc += tau * a * dI;
-            if (ABS) absacc += tau * a * fabs(dI);
-            tau *= 1.0 - a;
-        } else {
-            const float ds = (float)(te - t);
-            const float dI = (float)(Isrc - Ij);
-            float a, e;
-            absorb_f32(kap * ds, a, e);
-            const float ta = tau * a;
-            acc = fmaf(ta, dI, acc);
-            if (ABS) absacc = fmaf(ta, fabsf(dI), absacc);
-            tau *= e;
-        }
-        ++steps;
-        t = te;
-        Ilast = Ij;
-        bool wall = false;
-        if (tx == te) {
-            i += sx;
-            if (i == G.nx) { i = 0; ++wi; }
-            if (i < 0) { i = G.nx - 1; --wi; }
-            px = brick_x(i, G.bsx);
-            tx = face_t(G.xf[i + ux] + (double)wi * G.Lx - ox, dx, rx);
-        }
-        if (ty == te) {
-            j += sy;
-            if (j < 0) { wall = true; end = kEndWallLo; }
-            else if (j >= G.ny) { wall = true; end = kEndWallHi; }
-            else {
-                py = brick_y(j, G.bsy);
-                ty = face_t(G.yf[j + uy] - oy, dy, ry);
-            }
-        }
-        if (tz == te) {
-            k += sz;
-            if (k == G.nz) { k = 0; ++wk; }
-            if (k < 0) { k = G.nz - 1; --wk; }
-            pz = brick_z(k);
-            tz = face_t(G.zf[k + uz] + (double)wk * G.Lz - oz, dz, rz);
-        }
-        if (wall) {
-            const Real dw = (Real)(Isrc - (end == kEndWallLo ? Iw0 : Iw1));
-            acc += tau * dw;
-            if (ABS) absacc += tau * fabs(dw);
-            tau = (Real)0;
-            break;
+    R.ox = 0.5 * (G.xf[ci] + G.xf[ci + 1]);
+    R.oy = 0.5 * (G.yf[cj] + G.yf[cj + 1]);
+    R.oz = 0.5 * (G.zf[ck] + G.zf[ck + 1]);
+    R.sgn = (dx > 0.0 ? 0 : 1) | (dy > 0.0 ? 0 : 2) | (dz > 0.0 ? 0 : 4);
+    if constexpr (sizeof(Real) == 8) {
+        R.rx = dx; R.ry = dy; R.rz = dz;
+        R.tx = (G.xf[ci + (dx > 0.0)] - R.ox) / dx;
+        R.ty = (G.yf[cj + (dy > 0.0)] - R.oy) / dy;
+        R.tz = (G.zf[ck + (dz > 0.0)] - R.oz) / dz;
+    } else {
+        R.rx = 1.0 / dx; R.ry = 1.0 / dy; R.rz = 1.0 / dz;
+        R.tx = (G.xf[ci + (dx > 0.0)] - R.ox) * R.rx;
+        R.ty = (G.yf[cj + (dy > 0.0)] - R.oy) * R.ry;
+        R.tz = (G.zf[ck + (dz > 0.0)] - R.oz) * R.rz;
+        if constexpr (INC_XZ) {
+            R.dtx = U.hx * fabs(R.rx);
+            R.dtz = U.hz * fabs(R.rz);
         }
     }
-    if (end == kEndTol && steps >= max_steps && tau > tol) end = kEndCap;
-    const Real dl = (Real)(Isrc - Ilast);
-    acc += tau * dl;
-    if (ABS) absacc += tau * fabs(dl);
-    MarchOut<Real> m;
-    m.acc = acc;
-    m.absacc = absacc;
-    m.steps = steps;
-    m.end = end;
-    return m;
+    R.i = ci; R.j = cj; R.k = ck; R.wi = 0; R.wk = 0;
+    R.px = brick_x(ci, G.bsx); R.py = brick_y(cj, G.bsy); R.pz = brick_z(ck);
+    const int cell = R.px + R.py + R.pz;
+    kc = gld(K + cell);
+    R.Isrc = gld(Ipl + cell);
+    Ic = R.Isrc;
+    R.t = 0.0;
+    R.tau = 1.0;
+    R.acc = 0.0;
+    R.steps = 0;
+    R.end = kEndTol;
+}
+
+// Whether the march loop runs at all (tau = 1 must exceed tol, max_steps >= 1).
+template <class Real> __device__ __forceinline__ bool march_starts(Real tol, int max_steps)
+{
+    return (Real)1 > tol && max_steps > 0;
+}
+
+// Geometry of a step: the segment length ds in the current cell, the axis steps, the wall
+// flag; returns the brick offset of the next cell (the current one at a wall, so that the
+// caller's load stays in bounds).
+template <class Real, bool INC_XZ>
+__device__ __forceinline__ int ray_advance(Ray<Real, INC_XZ> &R, const RayGeo &G, double &ds, bool &wall)
+{
+    const double te = R.tx < R.ty ? (R.tz < R.tx ? R.tz : R.tx) : (R.tz < R.ty ? R.tz : R.ty);
+    ds = te - R.t;
+    R.t = te;
+    wall = false;
+    const int cur = R.px + R.py + R.pz;
+    if constexpr (sizeof(Real) == 4 && INC_XZ) {
+        // uniform periodic x and z: branch-free updates
+        const bool mx = R.tx == te, mz = R.tz == te;
+        int i = R.i + (mx ? ((R.sgn & 1) ? -1 : 1) : 0);
+        i = i == G.nx ? 0 : (i < 0 ? G.nx - 1 : i);
+        R.i = i;
+        R.px = brick_x(i, G.bsx);
+        R.tx += mx ? R.dtx : 0.0;
+        int k = R.k + (mz ? ((R.sgn & 4) ? -1 : 1) : 0);
+        k = k == G.nz ? 0 : (k < 0 ? G.nz - 1 : k);
+        R.k = k;
+        R.pz = brick_z(k);
+        R.tz += mz ? R.dtz : 0.0;
+    } else {
+        if (R.tx == te) {
+            R.i += (R.sgn & 1) ? -1 : 1;
+            if (R.i == G.nx) { R.i = 0; ++R.wi; }
+            if (R.i < 0) { R.i = G.nx - 1; --R.wi; }
+            R.px = brick_x(R.i, G.bsx);
+            const double f = G.xf[R.i + 1 - (R.sgn & 1)] + (double)R.wi * G.Lx - R.ox;
+            if constexpr (sizeof(Real) == 4) R.tx = f * R.rx;
+            else R.tx = f / R.rx;
+        }
+        if (R.tz == te) {
+            R.k += (R.sgn & 4) ? -1 : 1;
+            if (R.k == G.nz) { R.k = 0; ++R.wk; }
+            if (R.k < 0) { R.k = G.nz - 1; --R.wk; }
+            R.pz = brick_z(R.k);
+            const double f = G.zf[R.k + 1 - ((R.sgn >> 2) & 1)] + (double)R.wk * G.Lz - R.oz;
+            if constexpr (sizeof(Real) == 4) R.tz = f * R.rz;
+            else R.tz = f / R.rz;
+        }
+    }
+    if (R.ty == te) {
+        R.j += (R.sgn & 2) ? -1 : 1;
+        if (R.j < 0) { wall = true; R.end = kEndWallLo; }
+        else if (R.j >= G.ny) { wall = true; R.end = kEndWallHi; }
+        else {
+            R.py = brick_y(R.j, G.bsy);
+            const double f = G.yf[R.j + 1 - ((R.sgn >> 1) & 1)] - R.oy;
+            if constexpr (sizeof(Real) == 4) R.ty = f * R.ry;
+            else R.ty = f / R.ry;
+        }
+    }
+    return wall ? cur : R.px + R.py + R.pz;
+}
+
+// Absorption of a step in the current cell (kappa kc, intensity Ic, length ds); adds the
+// wall term when the step ended on a wall and the residual when the ray stops.  Returns
+// true when the ray is finished.  Iw0 / Iw1 point at the band's wall intensities.
+template <class Real, bool INC_XZ>
+__device__ __forceinline__ bool ray_absorb(Ray<Real, INC_XZ> &R, Real kc, double Ic, double ds, bool wall,
+                                           const double *Iw0, const double *Iw1, Real tol, int max_steps)
+{
+    if constexpr (sizeof(Real) == 8) {
+        const double dI = R.Isrc - Ic;
+        const double a = -expm1(-kc * ds);
+        R.acc += R.tau * a * dI;
+        R.tau *= 1.0 - a;
+    } else {
+        const float x = kc * (float)ds;
+        float a, e;
+        absorb_f32(x, a, e);
+        R.acc += (double)((float)R.tau * a * (float)(R.Isrc - Ic));
+        R.tau *= x < 0.25f ? 1.0 - (double)a : (double)e;
+    }
+    ++R.steps;
+    if (wall) {
+        const double dw = R.Isrc - gld(R.end == kEndWallLo ? Iw0 : Iw1);
+        R.acc += R.tau * dw;
+        R.tau = 0.0;
+        R.acc += R.tau * (R.Isrc - Ic);   // residual of a finished ray: zero
+        return true;
+    }
+    if (!(R.tau > (double)tol && R.steps < max_steps)) {
+        if (R.steps >= max_steps && R.tau > (double)tol) R.end = kEndCap;
+        R.acc += R.tau * (R.Isrc - Ic);   // residual dump into the last cell marched
+        return true;
+    }
+    return false;
+}
+
+// The march of one ray, started by ray_init with (k0, I0) of the source cell, until it
+// finishes or has taken `cap` steps.  Returns true when finished; when capped, R holds the
+// state at the start of the next step (its cell, parameter and next-face parameters).
+template <class Real, bool INC_XZ>
+__device__ __forceinline__ bool ray_march(Ray<Real, INC_XZ> &R, const RayGeo &G, const Real *__restrict__ K,
+                                          const double *__restrict__ Ipl, const double *Iw0, const double *Iw1,
+                                          Real tol, int max_steps, Real k0, double I0, int cap)
+{
+    if (!march_starts(tol, max_steps)) return true;
+    Real k1;
+    double I1, ds;
+    bool wall;
+    while (true) {
+        int cell = ray_advance(R, G, ds, wall);
+        k1 = gld(K + cell);
+        I1 = gld(Ipl + cell);
+        if (ray_absorb(R, k0, I0, ds, wall, Iw0, Iw1, tol, max_steps)) return true;
+        if (R.steps >= cap) return false;
+        cell = ray_advance(R, G, ds, wall);
+        k0 = gld(K + cell);
+        I0 = gld(Ipl + cell);
+        if (ray_absorb(R, k1, I1, ds, wall, Iw0, Iw1, tol, max_steps)) return true;
+        if (R.steps >= cap) return false;
+    }
 }
 
 }  // namespace rmc

@@ -31,7 +31,8 @@ class Options(C.Structure):
     _fields_ = [("rays_per_cell", C.c_int32), ("seed", C.c_uint64), ("snapshot", C.c_uint32),
                 ("tol", C.c_double), ("max_steps", C.c_int32), ("march", C.c_int),
                 ("accum", C.c_int), ("sampling", C.c_int), ("mix_eps", C.c_double),
-                ("block_threads", C.c_int32), ("reserved", C.c_int32 * 7)]
+                ("block_threads", C.c_int32), ("long_ray_steps", C.c_int32),
+                ("reserved", C.c_int32 * 6)]
 
 
 class Stats(C.Structure):
@@ -78,6 +79,10 @@ SIGNATURES = {
     "rmc_get_pdf": (C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP]),
     "rmc_get_stats": (C.c_int, [_VP, C.POINTER(Stats)]),
     "rmc_reset_stats": (C.c_int, [_VP]),
+    "rmc_graph_capture": (C.c_int, [C.POINTER(_VP), C.c_int, C.POINTER(_VP), C.POINTER(_VP), _VP,
+                                    C.POINTER(_VP)]),
+    "rmc_graph_launch": (C.c_int, [_VP, _VP]),
+    "rmc_graph_destroy": (None, [_VP]),
 }
 
 
@@ -90,6 +95,14 @@ class RmcError(RuntimeError):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+    # PyTorch ships its own HIP runtime under the same soname (libamdhip64.so.7) as the
+    # system one this library links; the copy loaded first serves the whole process.  Load
+    # torch's first so that torch and this library share one runtime (the other order leaves
+    # torch unable to see the GPU).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(LIB_PATH)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)
@@ -283,6 +296,35 @@ class Solver:
 
     def reset_stats(self):
         _check(LIB.rmc_reset_stats(self.h))
+
+
+class Graph:
+    """A captured compute (rmc_graph_capture) of one or more solvers into device tensors."""
+
+    def __init__(self, solvers: Sequence[Solver], divq: Sequence, stderr: Optional[Sequence] = None,
+                 stream=None):
+        n = len(solvers)
+        hs = (C.c_void_p * n)(*[s.h.value for s in solvers])
+        dp = (C.c_void_p * n)(*[_buf(d)[0] for d in divq])
+        sp = (C.c_void_p * n)(*[_buf(e)[0] for e in stderr]) if stderr is not None else None
+        self._keep = (list(solvers), list(divq), list(stderr) if stderr is not None else None)
+        g = C.c_void_p()
+        _check(LIB.rmc_graph_capture(hs, n, dp, sp, _stream(stream), C.byref(g)))
+        self.g = g
+
+    def launch(self, stream=None):
+        _check(LIB.rmc_graph_launch(self.g, _stream(stream)))
+
+    def close(self):
+        if self.g:
+            LIB.rmc_graph_destroy(self.g)
+            self.g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def compute_batch(solvers: Sequence[Solver], divq: Sequence, stderr: Optional[Sequence] = None,

@@ -166,15 +166,55 @@ def test_channel64_sampled_production_launch():
     s.compute(dq, se)
     torch.cuda.synchronize()
     rng = np.random.default_rng(5)
-    cells = np.unique(np.concatenate([rng.choice(w.ncells, 300, replace=False),
+    P = oracle.Problem(w)
+    steps_all = oracle.trace_cells(P, np.arange(w.ncells))["steps"]
+    longest = np.argsort(-steps_all.max(axis=1))[:64]          # cells holding the longest rays
+    cells = np.unique(np.concatenate([rng.choice(w.ncells, 300, replace=False), longest,
                                       [0, w.ncells - 1]]))
     Y, S = s.ray_values(cells)
-    P = oracle.Problem(w)
     ref = oracle.trace_cells(P, cells)
+    say(f"channel64 longest ray {steps_all.max()} steps")
     _check_fp32_rays(w, cells, Y, S, ref)
     st = s.stats()
     say(f"channel64 stats {st}")
     assert st["rays"] == w.ncells * w.R
+
+
+@pytest.mark.parametrize("after", [1, 4, 37])
+def test_segmented_long_rays_match_oracle(after):
+    """Rays still marching after `after` steps are finished by 64 lanes in parallel segments:
+    with a tiny threshold nearly every ray takes that path; all must match the oracle."""
+    w = _small_channel(march="f32", nx=12, ny=10, nz=8, R=16, amp=0.05)
+    import dataclasses
+    w = w.replace(kd=dataclasses.replace(w.kd, k=w.kd.k * np.float32(0.05)))   # long paths
+    say(f"segmented march after {after} steps")
+    s = _solver(w, long_ray_steps=after)
+    s.compute()
+    cells = np.arange(w.ncells)
+    Y, S = s.ray_values(cells)
+    ref = oracle.trace_cells(oracle.Problem(w), cells)
+    say(f"oracle steps max {ref['steps'].max()} mean {ref['steps'].mean():.1f}")
+    _check_fp32_rays(w, cells, Y, S, ref)
+
+
+def test_segmented_rounds_with_transparent_slab():
+    """A slab with no absorbing gas makes the smallest kappa of the field zero, so only the
+    wall, the optical depth seen so far and the step cap bound a round; rays that start in
+    or cross the slab need several rounds.  All must match the oracle."""
+    w = _small_channel(march="f32", nx=12, ny=10, nz=8, R=16, amp=0.05)
+    import dataclasses
+    w = w.replace(kd=dataclasses.replace(w.kd, k=w.kd.k * np.float32(0.05)))
+    X = np.array(w.X, dtype=np.float64, copy=True).reshape(w.kd.ns, w.nx, w.ny, w.nz)
+    X[:, :, 3:6, :] = 0.0
+    w = w.replace(X=X.reshape(w.kd.ns, -1))
+    say("segmented march, transparent slab, after 2 steps")
+    s = _solver(w, long_ray_steps=2)
+    s.compute()
+    cells = np.arange(w.ncells)
+    Y, S = s.ray_values(cells)
+    ref = oracle.trace_cells(oracle.Problem(w), cells)
+    say(f"oracle steps max {ref['steps'].max()} mean {ref['steps'].mean():.1f}")
+    _check_fp32_rays(w, cells, Y, S, ref)
 
 
 # ----------------------------------------------------------------- properties, edges
@@ -299,3 +339,42 @@ def test_batch_equals_single_snapshots():
     rmc.compute_batch(solvers, outs)
     for a, b in zip(singles, outs):
         assert np.array_equal(a, b)
+
+
+# ------------------------------------------------------------------------- HIP graphs
+def test_graph_replays_match_eager():
+    """Capture one compute of a 2-snapshot batch, replay it several times with eager work and
+    synchronisations between the replays, and with new temperature fields set between
+    replays; every replay equals an eager compute of the same fields."""
+    ws = [_small_channel(march="f32", nx=8, ny=6, nz=5, R=8, field_seed=q).replace(snap=q) for q in range(2)]
+    kd = ws[0].kd
+    ws = [x.replace(kd=kd) for x in ws]
+    say("graph capture and replays")
+    dev = torch.device("cuda", 0)
+    solvers = [_solver(x, device_fields=True) for x in ws]
+    outs = [torch.zeros(x.ncells, dtype=torch.float64, device=dev) for x in ws]
+    errs = [torch.zeros_like(o) for o in outs]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        g = rmc.Graph(solvers, outs, errs)
+    eager_solvers = [_solver(x) for x in ws]
+    for rep in range(3):
+        if rep > 0:   # new fields for the next replay
+            for q, (sv, es) in enumerate(zip(solvers, eager_solvers)):
+                T = ws[q].T * (1.0 + 0.01 * rep)
+                sv.set_temperature(torch.from_numpy(T.astype(np.float32)).to(dev))
+                es.set_temperature(T.astype(np.float32))
+        with torch.cuda.stream(stream):
+            g.launch()
+        stream.synchronize()
+        _ = (torch.ones(1000, device=dev) * 2).sum().item()      # eager work between replays
+        for q, es in enumerate(eager_solvers):
+            ref, ref_se = es.compute()
+            assert np.array_equal(outs[q].cpu().numpy(), ref), (rep, q)
+            assert np.array_equal(errs[q].cpu().numpy(), ref_se), (rep, q)
+    # a changed option invalidates the graph
+    solvers[0].set_options(rmc.default_options(rays_per_cell=8, march=rmc.F32, seed=3))
+    with pytest.raises(rmc.RmcError) as e:
+        g.launch(stream=stream.cuda_stream)
+    assert e.value.status == rmc.RMC_BAD_STATE
+    g.close()
