@@ -9,8 +9,10 @@ black walls at 300 K, T = 600 + 400 (1 - y^2) K with 8 Fourier modes of 5 %, H2O
 seeded synthetic correlated-k tables with 20 bands x 7 g-points, 32 rays per cell, FP32 march
 (double ray geometry and intensity differences), FP64 per-cell sums.
 
-Prints one JSON line.  The march kernel's duration is the HIP-event time the library records
-around its launch on the compute stream, summed over the timed steps.
+Prints one JSON line.  The roofline is that of the dominant kernel, the lane march
+(k_march_lane): its duration is the HIP-event time the library records around its launch on
+the compute stream, summed over the timed steps; its algorithmic bytes count the steps it
+takes (all steps minus those of the long-ray kernel, which the library counts).
 """
 import argparse
 import json
@@ -24,9 +26,9 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 # algorithmic bytes of the march: per ray-cell step one FP32 kappa_{n,g} and one FP64 I_n
-# gather; per ray one 8-byte work item read, one FP32 ray value and one 32-bit step count write
+# gather; per ray one 16-byte work item read, one FP32 ray value and one 32-bit step count write
 BYTES_PER_STEP = 4 + 8
-BYTES_PER_RAY = 8 + 4 + 4
+BYTES_PER_RAY = 16 + 4 + 4
 
 
 def parse():
@@ -39,6 +41,10 @@ def parse():
     ap.add_argument("--long-ray-steps", type=int, default=0,
                     help="steps a ray takes in the lane kernel before the segmented long-ray "
                          "kernel continues it (0: library default)")
+    ap.add_argument("--xcd-span", type=int, default=0,
+                    help="consecutive 64-ray chunks each XCD takes in turn (0: library default)")
+    ap.add_argument("--length-sort", action="store_true",
+                    help="reorder each march workgroup's rays by expected length")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (the "
                          "reference point that scales rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -89,7 +95,8 @@ def main():
         return
     w = inputs.channel64()
     s = rmc.Solver(0)
-    overrides = {"long_ray_steps": a.long_ray_steps} if a.long_ray_steps else {}
+    overrides = {k: v for k, v in (("long_ray_steps", a.long_ray_steps), ("xcd_span", a.xcd_span),
+                                   ("length_sort", int(a.length_sort))) if v}
     s.set_workload(w, **overrides)
     T = torch.from_numpy(np.ascontiguousarray(w.T, dtype=np.float32)).to(dev)
     X = torch.from_numpy(np.ascontiguousarray(w.X, dtype=np.float32)).to(dev)
@@ -117,11 +124,13 @@ def main():
     assert st["computes"] == a.steps, st
     value = steps_total / elapsed
     march_ms = st["sum_ms_march"] / a.steps
-    bytes_launch = BYTES_PER_STEP * st["steps"] + BYTES_PER_RAY * st["rays"]
-    achieved = bytes_launch / (march_ms * 1e-3) / 1e9
+    lane_ms = st["sum_ms_march_lane"] / a.steps
+    lane_steps = st["steps"] - st["long_steps"]
+    bytes_launch = BYTES_PER_STEP * lane_steps + BYTES_PER_RAY * st["rays"]
+    achieved = bytes_launch / (lane_ms * 1e-3) / 1e9
     traffic = None
     if a.traffic_json and os.path.exists(a.traffic_json):
-        traffic = json.load(open(a.traffic_json)).get("bytes_per_launch")
+        traffic = json.load(open(a.traffic_json)).get("k_march_lane", {}).get("bytes_per_launch")
     out = {
         "metric": "ray-cell steps/s",
         "value": value,
@@ -143,10 +152,11 @@ def main():
         "phases_ms": {"prep": st["sum_ms_prep"] / a.steps, "alloc": st["sum_ms_alloc"] / a.steps,
                       "march": march_ms, "reduce": st["sum_ms_reduce"] / a.steps},
         "march_steps_per_s": st["steps"] / (march_ms * 1e-3),
-        "roofline": {"kernel": "k_march", "bound": "hbm", "achieved": achieved,
+        "roofline": {"kernel": "k_march_lane", "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic,
-                     "algorithmic_bytes_per_launch": bytes_launch},
+                     "traffic": traffic, "ms_per_launch": lane_ms,
+                     "algorithmic_bytes_per_launch": bytes_launch,
+                     "steps_per_launch": lane_steps, "rays_per_launch": st["rays"]},
     }
     if a.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(w, a.cpu_seconds)

@@ -61,7 +61,8 @@ typedef enum {
 
 typedef enum {
     RMC_SAMPLING_PLAIN = 0,  /* T_max spectral pdf (Eqs. 13-17), octant uniform */
-    RMC_SAMPLING_PDF = 1     /* per-cell pdf over (n, g, octant) from rmc_set_cell_pdf */
+    RMC_SAMPLING_PDF = 1,    /* per-cell pdf over (n, g, octant) from rmc_set_cell_pdf */
+    RMC_SAMPLING_LEARNED = 2 /* per-cell pdf proposed by the allocation network (rmc_set_allocator) */
 } rmc_sampling;
 
 typedef struct {
@@ -73,12 +74,21 @@ typedef struct {
     rmc_dtype march;         /* RMC_F32 or RMC_F64 arithmetic of the march */
     rmc_accum accum;
     rmc_sampling sampling;
-    double mix_eps;          /* RMC_SAMPLING_PDF: weight of the plain pdf in the mixture */
+    double mix_eps;          /* PDF and LEARNED sampling: weight of the plain pdf in the mixture */
     int32_t block_threads;   /* march launch: threads per block (0 = default 256; only 256 is built) */
     int32_t long_ray_steps;  /* FP32 march on uniform x/z: rays still marching after this many steps
                                 are finished by 64 lanes in parallel segments (0 = default 256,
                                 >= max_steps disables it) */
-    int32_t reserved[6];     /* must be zero */
+    int32_t xcd_span;        /* march launch order: workgroups are dealt to the 8 XCDs in turn, and
+                                each XCD takes runs of this many consecutive 64-ray chunks of the
+                                bucketed work list, so that the rays in flight on one XCD share
+                                their property planes in its L2 (power of two in [4, 2^20];
+                                0 = default 256; 4 = plain workgroup order) */
+    int32_t length_sort;     /* 1: each march workgroup reorders the rays of its four chunks by a
+                                class of their expected length first, so that a wavefront's rays
+                                end at similar times (fewer idle lanes, less gather coherence);
+                                0 (default): cell order.  Results are the same either way */
+    int32_t reserved[4];     /* must be zero */
 } rmc_options;
 
 typedef struct {
@@ -95,6 +105,10 @@ typedef struct {
     int64_t sum_rays;
     int64_t sum_steps;
     double sum_ms_prep, sum_ms_alloc, sum_ms_march, sum_ms_reduce;
+    /* the march split into its two kernels (FP32 march on uniform x/z): */
+    int64_t long_steps;      /* last compute: steps taken by the long-ray kernel */
+    double ms_march_lane;    /* last compute: the lane kernel alone (HIP events) */
+    double sum_ms_march_lane;
 } rmc_stats;
 
 /* One ray of rmc_trace_cells (parity and debugging). */
@@ -151,6 +165,17 @@ rmc_status rmc_set_species(rmc_ctx *ctx, int ns, const void *X, rmc_dtype dtype,
 void rmc_default_options(rmc_options *opt);
 rmc_status rmc_set_options(rmc_ctx *ctx, const rmc_options *opt);
 
+/* Autotuner of the launch schedule, an addition to the paper's method (its kernels run with
+ * fixed launch shapes, Sec. 3): times `reps` computes of the context's current workload on
+ * `stream` (HIP events, after one warm-up each) for every combination of xcd_span in
+ * {16, 64, 256, 1024} and length_sort in {0, 1}, and keeps the fastest in the context's
+ * options (out, nullable, receives them).  Only knobs that reorder work are tuned: results
+ * are bitwise the same for every candidate.  Needs grid, walls, tables, fields and options
+ * set.  cache_path (nullable): a text file of "signature : xcd_span length_sort" lines; a
+ * line for this workload and device skips the timing, otherwise the result is appended.
+ * Resets the statistics (rmc_reset_stats) after timing.  Synchronises the stream. */
+rmc_status rmc_autotune(rmc_ctx *ctx, int reps, const char *cache_path, rmc_options *out, void *stream);
+
 /* Per-cell allocation pdf over (n, g, octant) for RMC_SAMPLING_PDF: q[ncells][nb][ng][8]
  * (double, >= 0, not necessarily normalised, host or device).  The rays of cell c are
  * drawn from (1 - mix_eps) q_c / sum q_c + mix_eps p_plain(n, g) / 8 and weighted by the
@@ -200,6 +225,80 @@ rmc_status rmc_trace_cells(rmc_ctx *ctx, const int64_t *cells, int ncell, rmc_ra
  * cdf_g[nb][ng] and T_max (nullable).  Synchronises `stream`. */
 rmc_status rmc_get_pdf(rmc_ctx *ctx, double *p, double *cdf_b, double *cdf_g, double *T_max,
                        void *stream);
+
+/* ------------------------------------------------------------ learned ray allocation
+ * An addition to the paper's method.  A network proposes, for every cell, a pdf over
+ * (band n, g-point g, octant o) from which that cell's rays are drawn; each ray keeps the
+ * importance weight of Eq. 14 with the probability it was drawn with, so the estimate stays
+ * unbiased for any positive pdf (the argument that lets the T_max pdf stand in for a cell's
+ * own emission pdf, Eqs. 13-14).  With RMC_SAMPLING_LEARNED the rays of cell c are drawn from
+ *   p_c(n,g,o) = (1 - mix_eps) softmax over all (n,g,o) of zg_c + mix_eps p_plain(n,g) / 8,
+ * zg_c(n,g,o) = z(x_{c,n,g})[o xor m_c], where z is the network below and m_c the sign bits
+ * (x: 1, y: 2, z: 4) of the cell's temperature gradient, so that the network sees octants in
+ * the frame of the local gradient.  The draws use the cell's allocation stream exactly as the
+ * other modes (band, then g within the band, then octant, by inversion of cumulative sums
+ * taken in that order).  The per-cell pdf is never stored: one kernel computes a group of
+ * cells' logits (hidden layers on BF16 matrix cores, FP32 accumulation), the softmax and
+ * the draws (FP32 exponentials, FP64 sums) and writes each ray's stratum and probability.
+ *
+ * Network: x = (f - mu) / sd, f = [T_c / 1000 K, log10(1 + |grad T|_c), log10(kappa_P,c),
+ * nu_n / 1e4 cm^-1, g abscissa]; h1 = relu(W1 x + b1), h2 = relu(W2 h1 + b2),
+ * h3 = relu(W3 h2 + b3), z = W4 h3 + b4 (64 hidden units, 8 outputs).  kappa_P,c =
+ * sum_s x_s kP_s(T_c), kP_s(T) = pi sum_{n,g} dnu_n w_g k^s_{n,g}(T) I_n(T) / (sigma T^4)
+ * interpolated from the table nodes; grad T by central differences at the cell centres,
+ * periodic in x and z, walls as ghost values on the wall faces. */
+#define RMC_MLP_PARAMS 9224
+
+/* params[RMC_MLP_PARAMS] (float, row-major, output index first): W1[64][5], b1[64],
+ * W2[64][64], b2[64], W3[64][64], b3[64], W4[8][64], b4[8]; mu[5], sd[5] (sd > 0);
+ * nu_c[nb] band centres (cm^-1); gx[ng] g abscissae.  Host pointers, copied.  Resets the
+ * training state.  rmc_set_kdist invalidates it (call again afterwards). */
+rmc_status rmc_set_allocator(rmc_ctx *ctx, const float *params, const float *mu, const float *sd,
+                             const double *nu_c, const double *gx);
+/* The current parameters (host float[RMC_MLP_PARAMS]). */
+rmc_status rmc_get_allocator(rmc_ctx *ctx, float *params);
+
+/* Raw features of the current fields: feat[ncells][3] (float: T / 1000, log10(1 + |grad T|),
+ * log10(max(kappa_P, 1e-30))) and mask[ncells] (uint8: sign bits of grad T), natural cell
+ * order, in `mem` memory.  Host outputs synchronise the stream. */
+rmc_status rmc_get_features(rmc_ctx *ctx, float *feat, uint8_t *mask, rmc_mem mem, void *stream);
+
+/* The global-octant logits zg[ncell][nb][ng][8] (host float) of the listed cells, computed
+ * by the inference kernel of the learned mode.  Synchronises. */
+rmc_status rmc_allocator_logits(rmc_ctx *ctx, const int64_t *cells, int ncell, float *zg, void *stream);
+
+/* Draws of the last compute with RMC_SAMPLING_LEARNED for the listed cells (host arrays):
+ * stratum[ncell][R] = (n * ng + g) * 8 + o and p[ncell][R], the probability each ray was drawn
+ * with.  Synchronises. */
+rmc_status rmc_get_ray_draws(rmc_ctx *ctx, const int64_t *cells, int ncell, int32_t *stratum, double *p,
+                             void *stream);
+
+/* Training data of one step (all device pointers): ncell cells with raw features
+ * feat[ncell][3] and masks mask[ncell]; pplain[nb * ng] the plain pdf of the run the rays
+ * came from; nsamp rays drawn with that plain pdf, sorted by cell: ray i belongs to cell
+ * cell_of[i] (0 <= cell_of < ncell, non-decreasing), lies in stratum[i] = (n*ng + g)*8 + o,
+ * and has h[i] = Y_i p0_i (its value times the probability p0[i] it was drawn with).  At most
+ * 1024 rays per cell. */
+typedef struct {
+    int32_t ncell, nsamp;
+    const float *feat;
+    const uint8_t *mask;
+    const double *pplain;
+    const int32_t *cell_of, *stratum;
+    const double *h, *p0;
+} rmc_train_batch;
+
+/* Loss of the batch under the current parameters and its gradient (host float
+ * grad[RMC_MLP_PARAMS], nullable), from the FP32 training kernels.  The loss is the relative
+ * second moment averaged over the cells with samples: for cell c,
+ *   L_c = [mean_i h_i^2 / (p0_i p_c(s_i))] / [mean_i (h_i / p0_i)^2],
+ * an unbiased estimate of the second moment of the cell's estimator were its rays drawn from
+ * p_c, relative to the plain one; its minimiser over pdfs is p_s proportional to
+ * sqrt(E[h^2 | s]).  Synchronises.  RMC_INVALID_ARG if the samples are not sorted by cell. */
+rmc_status rmc_train_grad(rmc_ctx *ctx, const rmc_train_batch *batch, double *loss, float *grad, void *stream);
+/* One Adam step (Kingma & Ba; beta 0.9 / 0.999, eps 1e-8) of learning rate lr on the batch;
+ * loss (nullable) is the loss before the step.  Synchronises. */
+rmc_status rmc_train_step(rmc_ctx *ctx, const rmc_train_batch *batch, float lr, double *loss, void *stream);
 
 /* Counters and phase timings of the last compute and accumulated since the last reset.
  * Waits for every compute enqueued so far to finish. */

@@ -46,6 +46,8 @@ struct SnapDesc {
     const double *ccdf_b;       // [ncells][nb]
     const double *ccdf_g;       // [ncells][nb*ng]
     const double *ccdf_o;       // [ncells][nb*ng*8]
+    const uint32_t *dstrat;     // learned sampling: [ncells * R] drawn stratum (n*ng + g)*8 + o
+    double *dprob;              // per-cell pdf or learned sampling: [ncells * R] probability of each ray
     uint64_t ncpad;             // cells per bricked field plane
     int nx, ny, nz;
     int nbx, nby, nbz;
@@ -72,15 +74,27 @@ struct Draw {
     double p;
 };
 
-template <bool PDF>
+// Sampling modes: 0 the T_max pdf, 1 a per-cell pdf (rmc_set_cell_pdf), 2 the learned
+// allocation (draws made per cell by k_alloc_draw, read back here).
+template <int SM>
 __device__ __forceinline__ Draw draw_ray(const SnapDesc &D, int nb, int ng, uint32_t c, uint32_t r,
-                                         uint32_t k0, uint32_t k1)
+                                         uint32_t k0, uint32_t k1, int R)
 {
+    if constexpr (SM == 2) {
+        const size_t slot = (size_t)c * R + r;
+        const uint32_t st = gld(D.dstrat + slot);
+        Draw d;
+        d.o = (int)(st & 7u);
+        d.n = (int)(st >> 3) / ng;
+        d.g = (int)(st >> 3) - d.n * ng;
+        d.p = gld(D.dprob + slot);
+        return d;
+    }
     uint32_t w[4];
     philox4x32_10(c, r, 0u, (D.snap_id << 4) | kTagAlloc, k0, k1, w);
     const double u0 = unif_alloc(w[0]), u1 = unif_alloc(w[1]), u2 = unif_alloc(w[2]);
     Draw d;
-    if constexpr (!PDF) {
+    if constexpr (SM == 0) {
         d.n = cdf_search(D.cdf_b, nb, u0);
         d.g = cdf_search(D.cdf_g + (size_t)d.n * ng, ng, u1);
         d.o = (int)floor(8.0 * u2);
@@ -385,7 +399,7 @@ __global__ void __launch_bounds__(256) k_fields(const double *__restrict__ T, co
 // ------------------------------------------------------------- allocation and buckets
 // Rays of one tile: cells [tile_begin.., +tile_cells) of the brick-linear order, all R rays
 // of each cell in one pass of the block (cells_per_pass = blockDim / R).
-template <bool PDF>
+template <int SM>
 __global__ void __launch_bounds__(256) k_alloc_count(AllocArgs A)
 {
     extern __shared__ uint32_t lh[];   // [nbucket]
@@ -400,7 +414,7 @@ __global__ void __launch_bounds__(256) k_alloc_count(AllocArgs A)
         int i, j, k;
         if (cq < cpp && base + cq < A.tile_cells && brick_cell(D, first + base + cq, i, j, k)) {
             const uint32_t c = (uint32_t)(((uint64_t)i * D.ny + j) * D.nz + k);
-            const Draw d = draw_ray<PDF>(D, A.nb, A.ng, c, (uint32_t)r, A.k0, A.k1);
+            const Draw d = draw_ray<SM>(D, A.nb, A.ng, c, (uint32_t)r, A.k0, A.k1, A.R);
             atomicAdd(&lh[(d.n * A.ng + d.g) * 8 + d.o], 1u);
         }
     }
@@ -473,7 +487,7 @@ __global__ void k_chunk_map(const uint32_t *total, const uint32_t *start, int nb
     for (uint32_t q = used + threadIdx.x; q < e; q += blockDim.x) items[q] = make_uint4(0u, kInvalidItem, 0u, 0u);
 }
 
-template <bool PDF>
+template <int SM>
 __global__ void __launch_bounds__(256) k_alloc_scatter(AllocArgs A)
 {
     extern __shared__ uint32_t lb[];   // [nbucket] next free position, then [256] bucket of each thread
@@ -493,8 +507,9 @@ __global__ void __launch_bounds__(256) k_alloc_scatter(AllocArgs A)
         uint32_t bucket = 0xFFFFFFFFu, c = 0;
         if (live) {
             c = (uint32_t)(((uint64_t)i * D.ny + j) * D.nz + k);
-            const Draw d = draw_ray<PDF>(D, A.nb, A.ng, c, (uint32_t)r, A.k0, A.k1);
+            const Draw d = draw_ray<SM>(D, A.nb, A.ng, c, (uint32_t)r, A.k0, A.k1, A.R);
             bucket = (uint32_t)((d.n * A.ng + d.g) * 8 + d.o);
+            if constexpr (SM == 1) D.dprob[(size_t)c * A.R + r] = d.p;   // the march's weight
         }
         sb[threadIdx.x] = bucket;
         __syncthreads();
@@ -531,7 +546,32 @@ template <class Real> struct MarchArgs {
     struct ContRec *cont;       // continuation records of capped rays
     uint32_t *cont_count;
     uint32_t cont_cap;
+    unsigned long long *long_steps;   // steps taken by k_march_long in this compute
+    int span_log2;              // log2 of the run of consecutive chunks an XCD takes in turn
+    float log_inv_tol;          // ln(1 / tol), for the expected-length estimate
 };
+
+// Workgroups of a launch are dealt to the XCDs in turn (workgroup b runs on XCD b mod 8) and
+// each XCD starts its workgroups in order.  Wavefront `wib` of workgroup b = 8 k + x takes
+// position p = 4 k + wib in XCD x's sequence, which walks the runs x, x + 8, x + 16, ... of
+// 2^span_log2 consecutive chunks: the waves in flight on one XCD then work on neighbouring
+// chunks (one (n, g) pair, nearby cells), whose property planes its L2 keeps.  A run of 4
+// chunks gives the plain order chunk = 4 b + wib.
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ uint32_t xcd_chunk(uint32_t block, uint32_t wib, int span_log2)
+{
+    const uint32_t pos = (block / kXcds) * 4 + wib;
+    return ((block % kXcds + kXcds * (pos >> span_log2)) << span_log2) | (pos & ((1u << span_log2) - 1));
+}
+
+// Workgroups (of 4 wavefronts) a launch needs so that every chunk below max_chunks has a slot.
+inline uint64_t xcd_blocks(uint64_t max_chunks, int span_log2)
+{
+    const uint64_t span = 1ull << span_log2;
+    const uint64_t runs = (max_chunks + span - 1) / span;
+    return (uint64_t)kXcds * ((runs + kXcds - 1) / kXcds) * (span / 4);
+}
 
 // State of a ray handed from the lane kernel to k_march_long after `steps` steps.
 struct ContRec {
@@ -555,20 +595,102 @@ __device__ __forceinline__ RayGeo ray_geo(const SnapDesc &D, const double *sf)
     return G;
 }
 
-// One ray per lane, no refill: every wavefront marches its 64 work items of one bucket and
+// Expected-length class of a ray (quarter octaves of its estimated step count; larger is
+// longer).  The estimate counts the face crossings of the straight path until it reaches the
+// wall it heads for or the optical depth ln(1/tol) at the source cell's kappa:
+//   E = 1 + min(L_wall, ln(1/tol) / kappa_src) (|d_x| n_x / L_x + |d_y| n_y / L_y + |d_z| n_z / L_z).
+// It only orders work; no result depends on it.
+template <class Real>
+__device__ __forceinline__ uint32_t ray_len_class(const SnapDesc &D, const RayGeo &G, int pair, int i, int j, int k,
+                                                  double dx, double dy, double dz, float log_inv_tol)
+{
+    const Real *K = reinterpret_cast<const Real *>(D.kap) + (size_t)pair * D.ncpad;
+    const float kap = (float)gld(K + brick_x(i, G.bsx) + brick_y(j, G.bsy) + brick_z(k));
+    const double yc = 0.5 * (G.yf[j] + G.yf[j + 1]);
+    const float lw = (float)(((dy > 0.0) ? G.yf[G.ny] - yc : yc - G.yf[0]) / fabs(dy));
+    const float L = kap > 0.0f ? fminf(lw, log_inv_tol / kap) : lw;
+    const float dens = (float)(fabs(dx) * (double)G.nx / D.Lx + fabs(dy) * (double)G.ny / (G.yf[G.ny] - G.yf[0]) +
+                               fabs(dz) * (double)G.nz / D.Lz);
+    const float E = fminf(1.0f + L * dens, 1e9f);
+    const int c = (int)floorf(4.0f * __log2f(E));
+    return (uint32_t)(c < 0 ? 0 : (c > 63 ? 63 : c));
+}
+
+// One ray per lane, no refill: every wavefront marches 64 work items of one bucket and
 // retires when its longest ray ends; the hardware scheduler balances the many short-lived
-// wavefronts.
-template <class Real, bool PDF, bool INC_XZ, bool MULTI>
+// wavefronts.  With SORT, the workgroup first reorders the 256 items of its four chunks by
+// expected length (bitonic sort in LDS on (bucket segment, class, index) keys), so that a
+// wavefront's rays end at similar times while its sources stay within four neighbouring
+// chunks; items never leave the chunks of their bucket.
+// PDF: the ray's probability is per ray (dprob), not per bucket (W).
+template <class Real, bool PDF, bool INC_XZ, bool MULTI, bool SORT>
 __global__ void __launch_bounds__(256) k_march_lane(MarchArgs<Real> A)
 {
     extern __shared__ double sf[];
     for (int q = threadIdx.x; q < A.nfaces; q += blockDim.x) sf[q] = A.faces[q];
-    __syncthreads();
-    const uint32_t wave = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-    if (wave >= __builtin_amdgcn_readfirstlane(*A.nchunks)) return;
-    const uint32_t b = __builtin_amdgcn_readfirstlane(gld(A.chunk_bucket + wave));
-    const uint4 it = gld(A.items + (size_t)wave * 64 + (threadIdx.x & 63));
-    if (it.y == kInvalidItem) return;
+    const int wib = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+    const uint32_t nch = __builtin_amdgcn_readfirstlane(*A.nchunks);
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(xcd_chunk(blockIdx.x, (uint32_t)wib, A.span_log2));
+    const bool wvalid = wave < nch;
+    const uint32_t b = wvalid ? __builtin_amdgcn_readfirstlane(gld(A.chunk_bucket + wave)) : 0xFFFFFFFFu;
+    const int o = (int)(b & 7), pair = (int)(b >> 3);
+    uint4 it;
+    uint32_t q;                 // position of the item in the work list
+    double dx, dy, dz;
+    if constexpr (!SORT) {
+        __syncthreads();
+        if (!wvalid) return;
+        q = wave * 64u + (uint32_t)lane;
+        it = gld(A.items + q);
+        if (it.y == kInvalidItem) return;
+        octant_direction(it.z, it.w, o, dx, dy, dz);
+    } else {
+        __shared__ uint32_t s_key[256];
+        __shared__ uint32_t s_bk[4];
+        __shared__ uint4 s_it[256];
+        __shared__ double s_d[3][256];
+        const uint4 it0 = wvalid ? gld(A.items + wave * 64u + (uint32_t)lane) : make_uint4(0u, kInvalidItem, 0u, 0u);
+        if (lane == 0) s_bk[wib] = b;
+        __syncthreads();
+        uint32_t seg = 0;           // buckets are contiguous in chunk order
+        for (int w = 1; w <= wib; ++w) seg += s_bk[w] != s_bk[w - 1] ? 1u : 0u;
+        if (!wvalid) seg = 7;
+        uint32_t ckey = 127;        // padding items last within their segment
+        if (wvalid && it0.y != kInvalidItem) {
+            const SnapDesc &D0 = A.snaps[MULTI ? (int)((it0.y >> 16) & 0x7FFF) : 0];
+            const RayGeo G0 = ray_geo(D0, sf);
+            double ex, ey, ez;
+            octant_direction(it0.z, it0.w, o, ex, ey, ez);
+            const int i0 = (int)(it0.x & 1023), j0 = (int)((it0.x >> 10) & 1023), k0 = (int)((it0.x >> 20) & 1023);
+            ckey = 63u - ray_len_class<Real>(D0, G0, pair, i0, j0, k0, ex, ey, ez, A.log_inv_tol);
+            s_d[0][threadIdx.x] = ex;
+            s_d[1][threadIdx.x] = ey;
+            s_d[2][threadIdx.x] = ez;
+        }
+        s_it[threadIdx.x] = it0;
+        s_key[threadIdx.x] = (seg << 16) | (ckey << 8) | threadIdx.x;
+        for (uint32_t kk = 2; kk <= 256; kk <<= 1)
+            for (uint32_t jj = kk >> 1; jj > 0; jj >>= 1) {
+                __syncthreads();
+                const uint32_t t = threadIdx.x, pt = t ^ jj;
+                if (pt > t) {
+                    const uint32_t ka = s_key[t], kb = s_key[pt];
+                    if ((ka > kb) == ((t & kk) == 0)) {
+                        s_key[t] = kb;
+                        s_key[pt] = ka;
+                    }
+                }
+            }
+        __syncthreads();
+        const uint32_t src = s_key[threadIdx.x] & 255u;
+        if (!wvalid) return;
+        it = s_it[src];
+        if (it.y == kInvalidItem) return;
+        dx = s_d[0][src];
+        dy = s_d[1][src];
+        dz = s_d[2][src];
+        q = xcd_chunk(blockIdx.x, src >> 6, A.span_log2) * 64u + (src & 63u);
+    }
     const int s = MULTI ? (int)((it.y >> 16) & 0x7FFF) : 0;
     const SnapDesc &D = A.snaps[s];
     const RayGeo G = ray_geo(D, sf);
@@ -577,13 +699,10 @@ __global__ void __launch_bounds__(256) k_march_lane(MarchArgs<Real> A)
     U.hz = D.hz;
     const int i = (int)(it.x & 1023), j = (int)((it.x >> 10) & 1023), k = (int)((it.x >> 20) & 1023);
     const int r = (int)(it.y & 255);
-    const int o = (int)(b & 7), pair = (int)(b >> 3);
     const int n = pair / A.ng;
     const Real *K = reinterpret_cast<const Real *>(D.kap) + (size_t)pair * D.ncpad;
     const double *Ipl = D.Ipl + (size_t)n * D.ncpad;
     const uint32_t c = (uint32_t)(((uint64_t)i * D.ny + j) * D.nz + k);
-    double dx, dy, dz;
-    octant_direction(it.z, it.w, o, dx, dy, dz);
     Ray<Real, INC_XZ> R;
     Real kap_src;
     double Isrc;
@@ -593,7 +712,7 @@ __global__ void __launch_bounds__(256) k_march_lane(MarchArgs<Real> A)
         const uint32_t idx = atomicAdd(A.cont_count, 1u);
         if (idx < A.cont_cap) {
             ContRec rc;
-            rc.q = (uint32_t)((size_t)wave * 64 + (threadIdx.x & 63));
+            rc.q = q;
             rc.i = R.i; rc.j = R.j; rc.k = R.k; rc.steps = R.steps;
             rc.tau = R.tau; rc.acc = R.acc;
             rc.t = R.t; rc.tx = R.tx; rc.ty = R.ty; rc.tz = R.tz;
@@ -604,14 +723,14 @@ __global__ void __launch_bounds__(256) k_march_lane(MarchArgs<Real> A)
         ray_march(R, G, K, Ipl, D.Iw + n, D.Iw + A.nb + n, A.tol, A.max_steps, gld(K + cell), gld(Ipl + cell),
                   A.max_steps);
     }
+    const size_t slot = (size_t)c * A.R + r;
     double w;
     if constexpr (!PDF) {
         w = gld(D.W + b);
     } else {
-        const double p = gld(D.cpdf + ((size_t)c * A.nb * A.ng + pair) * 8 + o);
+        const double p = gld(D.dprob + slot);
         w = 4.0 * M_PI * A.dnu[n] * A.wg[pair - n * A.ng] / (8.0 * p);
     }
-    const size_t slot = (size_t)c * A.R + r;
     reinterpret_cast<Real *>(D.Y)[slot] = (Real)(w * (double)kap_src * (double)R.acc);
     D.st[slot] = (uint32_t)R.steps | ((uint32_t)R.end << 28);
 }
@@ -804,22 +923,25 @@ __global__ void __launch_bounds__(256) k_march_long(MarchArgs<float> A)
             // fixed-order wave sum of the contributions
             for (int off = 32; off > 0; off >>= 1) contrib += __shfl_xor(contrib, off);
             if (lane == lstar) {
+                const size_t slot = (size_t)c * A.R + r;
                 double w;
                 if constexpr (!PDF) {
                     w = gld(D.W + b);
                 } else {
-                    const double p = gld(D.cpdf + ((size_t)c * A.nb * A.ng + pair) * 8 + o);
+                    const double p = gld(D.dprob + slot);
                     w = 4.0 * M_PI * A.dnu[n] * A.wg[pair - n * A.ng] / (8.0 * p);
                 }
                 const double acc = sacc + contrib;
-                const size_t slot = (size_t)c * A.R + r;
                 reinterpret_cast<float *>(D.Y)[slot] = (float)(w * (double)kap_src * acc);
                 D.st[slot] = (uint32_t)R.steps | ((uint32_t)R.end << 28);
+                atomicAdd(A.long_steps, (unsigned long long)(R.steps - rc.steps));
             }
             break;
         }
     }
 }
+
+#include "learn_kernels.inc"
 
 // --------------------------------------------------------------------------- trace
 template <class Real> struct TraceArgs {
@@ -838,7 +960,7 @@ template <class Real> struct TraceArgs {
 
 // All R rays of listed cells, drawn and marched with the same device functions as the
 // production path; one thread per ray (ordinal k recomputed from the earlier draws).
-template <class Real, bool PDF, bool INC_XZ>
+template <class Real, int SM, bool INC_XZ>
 __global__ void __launch_bounds__(256) k_trace(TraceArgs<Real> A)
 {
     extern __shared__ double sf[];
@@ -853,10 +975,10 @@ __global__ void __launch_bounds__(256) k_trace(TraceArgs<Real> A)
     const int i = (int)(c64 / ((int64_t)D.ny * D.nz));
     const int j = (int)((c64 / D.nz) % D.ny);
     const int k = (int)(c64 % D.nz);
-    const Draw d = draw_ray<PDF>(D, A.nb, A.ng, c, (uint32_t)r, A.k0, A.k1);
+    const Draw d = draw_ray<SM>(D, A.nb, A.ng, c, (uint32_t)r, A.k0, A.k1, A.R);
     uint32_t kord = 0;
     for (int r2 = 0; r2 < r; ++r2) {
-        const Draw e = draw_ray<PDF>(D, A.nb, A.ng, c, (uint32_t)r2, A.k0, A.k1);
+        const Draw e = draw_ray<SM>(D, A.nb, A.ng, c, (uint32_t)r2, A.k0, A.k1, A.R);
         kord += (e.n == d.n && e.g == d.g && e.o == d.o) ? 1u : 0u;
     }
     const int pair = d.n * A.ng + d.g;
@@ -1056,6 +1178,11 @@ struct rmc_ctx {
     // per-cell pdf mode
     bool have_q = false;
     DBuf q, cpdf, ccdf_b, ccdf_g, ccdf_o;
+    // learned allocation: network, features, per-ray draws, training state and scratch
+    bool have_alloc = false;
+    int adam_t = 0;
+    DBuf prm, musd, nu_c, gxs, kp, feat, fmask, bng, lfaces, dstrat, dprob, adam1, adam2;
+    DBuf tr_feat, tr_mask, tr_act, tr_del, tr_dz, tr_Lc, tr_scal, tr_err, tr_part, tr_grad;
     // pdf and fields of the last compute
     DBuf pdf_scratch, p, cdf_b, cdf_g, W, Iw, status;
     DBuf field, Iplane;     // kappa planes (march precision) and FP64 intensity planes
@@ -1064,7 +1191,7 @@ struct rmc_ctx {
     int slots_R = 0, slots_real = 0;
     // shared pipeline workspace (used when this context leads a batch)
     DBuf hist, bucket_total, bucket_start, nchunks, chunk_bucket, items, faces, snaps, tile_snap, counters,
-        outbuf;
+        outbuf, tune_out;
     DBuf trace_rec, trace_cells, border, kmin, cont, cont_count;
     std::vector<float> h_kmin;
     double Tmin_cells = 0;
@@ -1080,7 +1207,7 @@ struct rmc_ctx {
     // timing: a ring of event sets, one per compute in flight; counters[0..1] are the last
     // compute's steps / capped rays, counters[2] the steps accumulated since the last reset
     struct EvSet {
-        hipEvent_t e[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+        hipEvent_t e[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
         bool pending = false;
         int64_t rays = 0;
     };
@@ -1088,10 +1215,10 @@ struct rmc_ctx {
     size_t ring_head = 0;
     int last_set = -1;
     bool have_counters = false;
-    float last_ms[4] = {0, 0, 0, 0};
+    float last_ms[5] = {0, 0, 0, 0, 0};     // prep, alloc, lane march, long-ray march, reduce
     int64_t last_rays = 0;
     int64_t n_computes = 0, sum_rays = 0;
-    double sum_ms[4] = {0, 0, 0, 0};
+    double sum_ms[5] = {0, 0, 0, 0, 0};
 };
 
 namespace {
@@ -1119,14 +1246,17 @@ rmc_status check_options(const rmc_options *o)
     if (o->march != RMC_F32 && o->march != RMC_F64) return fail(RMC_INVALID_ARG, "march must be RMC_F32 or RMC_F64");
     if (o->accum != RMC_ACC_F64 && o->accum != RMC_ACC_COMP_F32 && o->accum != RMC_ACC_F32)
         return fail(RMC_INVALID_ARG, "bad accum");
-    if (o->sampling != RMC_SAMPLING_PLAIN && o->sampling != RMC_SAMPLING_PDF)
+    if (o->sampling != RMC_SAMPLING_PLAIN && o->sampling != RMC_SAMPLING_PDF && o->sampling != RMC_SAMPLING_LEARNED)
         return fail(RMC_INVALID_ARG, "bad sampling");
-    if (o->sampling == RMC_SAMPLING_PDF && !(o->mix_eps >= 0.0 && o->mix_eps <= 1.0))
+    if (o->sampling != RMC_SAMPLING_PLAIN && !(o->mix_eps >= 0.0 && o->mix_eps <= 1.0))
         return fail(RMC_INVALID_ARG, "mix_eps must be in [0, 1]");
     if (o->block_threads != 0 && o->block_threads != 256)
         return fail(RMC_UNSUPPORTED, "block_threads: only 0 (default) and 256 are built");
     if (o->long_ray_steps < 0) return fail(RMC_INVALID_ARG, "long_ray_steps must be >= 0");
-    for (int q = 0; q < 6; ++q)
+    if (o->xcd_span != 0 && (o->xcd_span < 4 || o->xcd_span > (1 << 20) || (o->xcd_span & (o->xcd_span - 1))))
+        return fail(RMC_INVALID_ARG, "xcd_span must be 0 or a power of two in [4, 2^20]");
+    if (o->length_sort != 0 && o->length_sort != 1) return fail(RMC_INVALID_ARG, "length_sort must be 0 or 1");
+    for (int q = 0; q < 4; ++q)
         if (o->reserved[q] != 0) return fail(RMC_INVALID_ARG, "reserved option fields must be zero");
     return RMC_OK;
 }
@@ -1139,6 +1269,8 @@ rmc_status check_ready(const rmc_ctx *c)
     if (!c->have_T) return fail(RMC_BAD_STATE, "rmc_set_temperature missing");
     if (!c->have_X) return fail(RMC_BAD_STATE, "rmc_set_species missing");
     if (c->opt.sampling == RMC_SAMPLING_PDF && !c->have_q) return fail(RMC_BAD_STATE, "rmc_set_cell_pdf missing");
+    if (c->opt.sampling == RMC_SAMPLING_LEARNED && !c->have_alloc)
+        return fail(RMC_BAD_STATE, "rmc_set_allocator missing");
     for (int s = 0; s < 2; ++s) {
         const double u = (c->Tw[s] - c->T0) / c->dT;
         if (!(u >= 0.0 && u <= (double)(c->nT - 1)))
@@ -1211,6 +1343,120 @@ void kappa_lower_bounds(const rmc_ctx *c, std::vector<float> &out)
     }
 }
 
+// ------------------------------------------------------------ learned allocation (host)
+// cells per workgroup of the allocation kernels and their LDS bytes (logits of all strata of
+// cpb cells, the per-cell half of layer 1, masks, then for the draw kernel FP64 band sums)
+struct NetLaunch {
+    int cpb;
+    size_t lds_logits, lds_draw;
+};
+
+NetLaunch net_launch(const rmc_ctx *c)
+{
+    NetLaunch L;
+    const int S = c->nb * c->ng * 8;
+    L.cpb = std::max(1, std::min(16, 16384 / S));
+    L.lds_logits = sizeof(float) * ((size_t)L.cpb * S + (size_t)L.cpb * kHid + ((L.cpb + 15) / 16) * 4);
+    L.lds_draw = L.lds_logits + sizeof(double) * (2 * (size_t)c->nb + 256);
+    return L;
+}
+
+// buffers of the features and of the per-ray draws; the face table for the features kernel
+rmc_status plan_features(rmc_ctx *c)
+{
+    rmc_status st;
+    const uint64_t nc = ncells_of(c);
+    const size_t nf = (size_t)c->nx + c->ny + c->nz + 3;
+    if ((st = c->kp.ensure(sizeof(double) * c->ns * c->nT)) || (st = c->feat.ensure(sizeof(float) * 3 * nc)) ||
+        (st = c->fmask.ensure(nc)) || (st = c->lfaces.ensure(sizeof(double) * nf)))
+        return st;
+    std::vector<double> f;
+    f.reserve(nf);
+    for (double v : c->xf) f.push_back(v);
+    for (double v : c->yf) f.push_back(v);
+    for (double v : c->zf) f.push_back(v);
+    HIPCHK(hipMemcpy(c->lfaces.p, f.data(), sizeof(double) * nf, hipMemcpyHostToDevice));
+    return RMC_OK;
+}
+
+rmc_status plan_learned(rmc_ctx *c)
+{
+    rmc_status st;
+    if ((st = plan_features(c))) return st;
+    if (net_launch(c).lds_draw > 64 * 1024) return fail(RMC_UNSUPPORTED, "nb * ng too large for the allocation kernel");
+    if ((st = c->bng.ensure(sizeof(float) * c->nb * c->ng * kHid)) ||
+        (st = c->dstrat.ensure(sizeof(uint32_t) * ncells_of(c) * c->opt.rays_per_cell)))
+        return st;
+    return RMC_OK;
+}
+
+rmc_status enqueue_features(rmc_ctx *c, hipStream_t s)
+{
+    const uint64_t nc = ncells_of(c);
+    hipLaunchKernelGGL(k_kp_tables, dim3((c->ns * c->nT + 255) / 256), dim3(256), 0, s, c->k64.as<double>(),
+                       c->Ib.as<double>(), c->dnu.as<double>(), c->wg.as<double>(), c->ns, c->nb, c->ng, c->nT, c->T0,
+                       c->dT, c->kp.as<double>());
+    HIPCHK(hipGetLastError());
+    FeatArgs F;
+    F.T = c->T.as<double>();
+    F.X = c->X.as<double>();
+    F.xf = c->lfaces.as<double>();
+    F.yf = F.xf + c->nx + 1;
+    F.zf = F.yf + c->ny + 1;
+    F.kp = c->kp.as<double>();
+    F.nx = c->nx; F.ny = c->ny; F.nz = c->nz; F.ns = c->ns; F.nT = c->nT;
+    F.T0 = c->T0; F.dT = c->dT; F.Tw0 = c->Tw[0]; F.Tw1 = c->Tw[1];
+    F.feat = c->feat.as<float>();
+    F.mask = c->fmask.as<uint8_t>();
+    hipLaunchKernelGGL(k_features, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, s, F);
+    HIPCHK(hipGetLastError());
+    return RMC_OK;
+}
+
+AllocNetArgs net_args(rmc_ctx *c)
+{
+    AllocNetArgs A{};
+    A.prm = c->prm.as<float>();
+    A.mu = c->musd.as<float>();
+    A.sd = A.mu + 5;
+    A.bng = c->bng.as<float>();
+    A.feat = c->feat.as<float>();
+    A.mask = c->fmask.as<uint8_t>();
+    A.P = c->nb * c->ng;
+    A.cpb = net_launch(c).cpb;
+    A.nb = c->nb; A.ng = c->ng; A.R = c->opt.rays_per_cell;
+    A.k0 = (uint32_t)c->opt.seed; A.k1 = (uint32_t)(c->opt.seed >> 32);
+    A.mix_eps = c->opt.mix_eps;
+    A.snap_id = c->opt.snapshot;
+    return A;
+}
+
+rmc_status enqueue_spec(rmc_ctx *c, hipStream_t s)
+{
+    const int n = c->nb * c->ng * kHid;
+    hipLaunchKernelGGL(k_mlp_spec, dim3((n + 255) / 256), dim3(256), 0, s, c->prm.as<float>(), c->musd.as<float>(),
+                       c->musd.as<float>() + 5, c->nu_c.as<double>(), c->gxs.as<double>(), c->nb, c->ng,
+                       c->bng.as<float>());
+    HIPCHK(hipGetLastError());
+    return RMC_OK;
+}
+
+// features, spectral half of layer 1, then the fused per-cell network + draws (kernels only)
+rmc_status enqueue_learned(rmc_ctx *c, hipStream_t s)
+{
+    rmc_status st;
+    if ((st = enqueue_features(c, s)) || (st = enqueue_spec(c, s))) return st;
+    AllocNetArgs A = net_args(c);
+    A.ncell = (int)ncells_of(c);
+    A.pplain = c->p.as<double>();
+    A.dstrat = c->dstrat.as<uint32_t>();
+    A.dprob = c->dprob.as<double>();
+    const NetLaunch NL = net_launch(c);
+    hipLaunchKernelGGL(k_alloc_draw, dim3((unsigned)((A.ncell + NL.cpb - 1) / NL.cpb)), dim3(256), NL.lds_draw, s, A);
+    HIPCHK(hipGetLastError());
+    return RMC_OK;
+}
+
 template <class Real> rmc_status plan_snapshot(rmc_ctx *c, SnapDesc &D)
 {
     rmc_status st;
@@ -1244,6 +1490,14 @@ template <class Real> rmc_status plan_snapshot(rmc_ctx *c, SnapDesc &D)
         D.cpdf = c->cpdf.as<double>(); D.ccdf_b = c->ccdf_b.as<double>();
         D.ccdf_g = c->ccdf_g.as<double>(); D.ccdf_o = c->ccdf_o.as<double>();
     }
+    if (c->opt.sampling != RMC_SAMPLING_PLAIN) {
+        if ((st = c->dprob.ensure(sizeof(double) * nc * R))) return st;
+        D.dprob = c->dprob.as<double>();
+    }
+    if (c->opt.sampling == RMC_SAMPLING_LEARNED) {
+        if ((st = plan_learned(c))) return st;
+        D.dstrat = c->dstrat.as<uint32_t>();
+    }
     D.kap = c->field.p;
     D.Ipl = c->Iplane.as<double>();
     D.Y = c->Y.p;
@@ -1256,6 +1510,7 @@ template <class Real> rmc_status plan_snapshot(rmc_ctx *c, SnapDesc &D)
 // per-snapshot work: spectral pdf, per-cell pdfs, property fields (kernels only)
 template <class Real> rmc_status enqueue_snapshot(rmc_ctx *c, const SnapDesc &D, hipStream_t s)
 {
+    rmc_status st;
     const int nb = c->nb, ng = c->ng;
     const uint64_t nc = ncells_of(c);
     PdfArgs A;
@@ -1273,6 +1528,7 @@ template <class Real> rmc_status enqueue_snapshot(rmc_ctx *c, const SnapDesc &D,
     A.W = c->W.as<double>(); A.Iw = c->Iw.as<double>(); A.status = c->status.as<int>();
     hipLaunchKernelGGL(k_plain_pdf, dim3(1), dim3(256), 0, s, A);
     HIPCHK(hipGetLastError());
+    if (c->opt.sampling == RMC_SAMPLING_LEARNED && (st = enqueue_learned(c, s))) return st;
     if (c->opt.sampling == RMC_SAMPLING_PDF) {
         hipLaunchKernelGGL(k_cell_pdf, dim3((unsigned)((nc + 127) / 128)), dim3(128), 0, s, c->q.as<double>(),
                            c->p.as<double>(), nc, nb, ng, c->opt.mix_eps, c->cpdf.as<double>(),
@@ -1291,14 +1547,14 @@ template <class Real> rmc_status enqueue_snapshot(rmc_ctx *c, const SnapDesc &D,
 // wait for one event set and fold its phase times into the accumulated statistics
 rmc_status harvest(rmc_ctx *L, rmc_ctx::EvSet &set)
 {
-    HIPCHK(hipEventSynchronize(set.e[4]));
-    float t[4];
-    for (int q = 0; q < 4; ++q) HIPCHK(hipEventElapsedTime(&t[q], set.e[q], set.e[q + 1]));
-    for (int q = 0; q < 4; ++q) L->sum_ms[q] += t[q];
+    HIPCHK(hipEventSynchronize(set.e[5]));
+    float t[5];
+    for (int q = 0; q < 5; ++q) HIPCHK(hipEventElapsedTime(&t[q], set.e[q], set.e[q + 1]));
+    for (int q = 0; q < 5; ++q) L->sum_ms[q] += t[q];
     ++L->n_computes;
     L->sum_rays += set.rays;
     if (&set == &L->ring[L->last_set]) {
-        for (int q = 0; q < 4; ++q) L->last_ms[q] = t[q];
+        for (int q = 0; q < 5; ++q) L->last_ms[q] = t[q];
         L->last_rays = set.rays;
     }
     set.pending = false;
@@ -1323,7 +1579,8 @@ struct Plan {
     std::vector<SnapDesc> D;
     int nfaces = 0, ntiles = 0, tile_cells = 0;
     uint64_t total_cells = 0, max_chunks = 0;
-    bool inc_xz = true, pdf_mode = false;
+    bool inc_xz = true, pdf_mode = false;   // pdf_mode: per-ray probabilities (modes 1 and 2)
+    int smode = 0;
     uint32_t cont_cap = 0;
 };
 
@@ -1336,7 +1593,8 @@ template <class Real> rmc_status plan_pipeline(rmc_ctx *const *ctxs, int nsnap, 
     const int nb = L->nb, ng = L->ng, nbucket = nb * ng * 8, R = O.rays_per_cell;
     P = Plan{};
     P.ctxs.assign(ctxs, ctxs + nsnap);
-    P.pdf_mode = O.sampling == RMC_SAMPLING_PDF;
+    P.smode = (int)O.sampling;
+    P.pdf_mode = P.smode != RMC_SAMPLING_PLAIN;
     P.D.resize(nsnap);
     uint64_t total_ncpad = 0;
     for (int q = 0; q < nsnap; ++q) {
@@ -1377,7 +1635,7 @@ template <class Real> rmc_status plan_pipeline(rmc_ctx *const *ctxs, int nsnap, 
         (st = L->items.ensure(sizeof(uint4) * max_items)) || (st = L->faces.ensure(sizeof(double) * P.nfaces)) ||
         (st = L->snaps.ensure(sizeof(SnapDesc) * nsnap)) || (st = L->tile_snap.ensure(sizeof(int) * P.ntiles)) ||
         (st = L->border.ensure(sizeof(uint32_t) * nbucket)) ||
-        (st = L->counters.ensure(sizeof(unsigned long long) * 3)) ||
+        (st = L->counters.ensure(sizeof(unsigned long long) * 4)) ||
         (st = L->kmin.ensure(sizeof(float) * nb * ng)) || (st = L->cont_count.ensure(sizeof(uint32_t))))
         return st;
     P.cont_cap = (uint32_t)std::min<uint64_t>(P.total_cells * R, 1u << 20);
@@ -1391,7 +1649,7 @@ template <class Real> rmc_status plan_pipeline(rmc_ctx *const *ctxs, int nsnap, 
         }
     }
     if (!L->have_counters) {
-        HIPCHK(hipMemsetAsync(L->counters.p, 0, sizeof(unsigned long long) * 3, s));
+        HIPCHK(hipMemsetAsync(L->counters.p, 0, sizeof(unsigned long long) * 4, s));
         L->have_counters = true;
     }
     L->h_snaps.resize(sizeof(SnapDesc) * nsnap);
@@ -1436,8 +1694,9 @@ rmc_status enqueue_pipeline(const Plan &P, double *const *divq, double *const *s
     AA.items = L->items.as<uint4>();
     const size_t lds_count = sizeof(uint32_t) * nbucket;
     const size_t lds_scatter = sizeof(uint32_t) * (nbucket + 256);
-    if (P.pdf_mode) hipLaunchKernelGGL(k_alloc_count<true>, dim3(P.ntiles), dim3(256), lds_count, s, AA);
-    else hipLaunchKernelGGL(k_alloc_count<false>, dim3(P.ntiles), dim3(256), lds_count, s, AA);
+    if (P.smode == 2) hipLaunchKernelGGL(k_alloc_count<2>, dim3(P.ntiles), dim3(256), lds_count, s, AA);
+    else if (P.smode == 1) hipLaunchKernelGGL(k_alloc_count<1>, dim3(P.ntiles), dim3(256), lds_count, s, AA);
+    else hipLaunchKernelGGL(k_alloc_count<0>, dim3(P.ntiles), dim3(256), lds_count, s, AA);
     HIPCHK(hipGetLastError());
     hipLaunchKernelGGL(k_bucket_scan, dim3(nbucket), dim3(64), 0, s, L->hist.as<uint32_t>(), P.ntiles,
                        L->bucket_total.as<uint32_t>());
@@ -1449,8 +1708,9 @@ rmc_status enqueue_pipeline(const Plan &P, double *const *divq, double *const *s
                        L->bucket_start.as<uint32_t>(), nbucket, L->chunk_bucket.as<uint32_t>(),
                        L->items.as<uint4>());
     HIPCHK(hipGetLastError());
-    if (P.pdf_mode) hipLaunchKernelGGL(k_alloc_scatter<true>, dim3(P.ntiles), dim3(256), lds_scatter, s, AA);
-    else hipLaunchKernelGGL(k_alloc_scatter<false>, dim3(P.ntiles), dim3(256), lds_scatter, s, AA);
+    if (P.smode == 2) hipLaunchKernelGGL(k_alloc_scatter<2>, dim3(P.ntiles), dim3(256), lds_scatter, s, AA);
+    else if (P.smode == 1) hipLaunchKernelGGL(k_alloc_scatter<1>, dim3(P.ntiles), dim3(256), lds_scatter, s, AA);
+    else hipLaunchKernelGGL(k_alloc_scatter<0>, dim3(P.ntiles), dim3(256), lds_scatter, s, AA);
     HIPCHK(hipGetLastError());
     if (EV) HIPCHK(hipEventRecord(EV->e[2], s));
 
@@ -1476,13 +1736,25 @@ rmc_status enqueue_pipeline(const Plan &P, double *const *divq, double *const *s
     MA.cont = L->cont.as<ContRec>();
     MA.cont_count = L->cont_count.as<uint32_t>();
     MA.cont_cap = P.cont_cap;
+    MA.long_steps = L->counters.as<unsigned long long>() + 3;
+    MA.log_inv_tol = O.tol > 0.0 ? (float)std::log(1.0 / O.tol) : 1e30f;
+    MA.span_log2 = 0;
+    for (int sp = O.xcd_span > 0 ? O.xcd_span : 256; sp > 1; sp >>= 1) ++MA.span_log2;
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, L->cont_count.as<uint32_t>(), 1);
     HIPCHK(hipGetLastError());
-    const unsigned mblocks = (unsigned)((P.max_chunks + 3) / 4);
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, L->counters.as<unsigned long long>() + 3, 1);
+    HIPCHK(hipGetLastError());
+    const unsigned mblocks = (unsigned)xcd_blocks(P.max_chunks, MA.span_log2);
     const size_t lds_faces = sizeof(double) * P.nfaces;
     const bool multi = nsnap > 1;
-#define RMC_MARCH(PDF_, INC_, MULTI_) \
-    hipLaunchKernelGGL((k_march_lane<Real, PDF_, INC_, MULTI_>), dim3(mblocks), dim3(256), lds_faces, s, MA)
+    const bool lsort = O.length_sort != 0;
+#define RMC_MARCH(PDF_, INC_, MULTI_)                                                                             \
+    do {                                                                                                        \
+        if (lsort) hipLaunchKernelGGL((k_march_lane<Real, PDF_, INC_, MULTI_, true>), dim3(mblocks), dim3(256), \
+                                      lds_faces, s, MA);                                                        \
+        else hipLaunchKernelGGL((k_march_lane<Real, PDF_, INC_, MULTI_, false>), dim3(mblocks), dim3(256),      \
+                                lds_faces, s, MA);                                                              \
+    } while (0)
     if (P.pdf_mode) {
         if (P.inc_xz) { if (multi) RMC_MARCH(true, true, true); else RMC_MARCH(true, true, false); }
         else { if (multi) RMC_MARCH(true, false, true); else RMC_MARCH(true, false, false); }
@@ -1492,6 +1764,7 @@ rmc_status enqueue_pipeline(const Plan &P, double *const *divq, double *const *s
     }
 #undef RMC_MARCH
     HIPCHK(hipGetLastError());
+    if (EV) HIPCHK(hipEventRecord(EV->e[3], s));
     if constexpr (sizeof(Real) == 4) {
         if (segment && MA.cap < O.max_steps) {
             if (P.pdf_mode) {
@@ -1504,7 +1777,7 @@ rmc_status enqueue_pipeline(const Plan &P, double *const *divq, double *const *s
             HIPCHK(hipGetLastError());
         }
     }
-    if (EV) HIPCHK(hipEventRecord(EV->e[3], s));
+    if (EV) HIPCHK(hipEventRecord(EV->e[4], s));
 
     // 5. per-cell reduction into the (device) output buffers
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, L->counters.as<unsigned long long>(), 2);
@@ -1518,7 +1791,7 @@ rmc_status enqueue_pipeline(const Plan &P, double *const *divq, double *const *s
                            se ? se[q] : nullptr, L->counters.as<unsigned long long>());
         HIPCHK(hipGetLastError());
     }
-    if (EV) HIPCHK(hipEventRecord(EV->e[4], s));
+    if (EV) HIPCHK(hipEventRecord(EV->e[5], s));
     return RMC_OK;
 }
 
@@ -1626,8 +1899,8 @@ std::vector<void *> buffer_ptrs(const rmc_ctx *c)
     const DBuf *b[] = {&c->k64, &c->Ib, &c->dnu, &c->wg, &c->T, &c->X, &c->scal, &c->q, &c->cpdf, &c->ccdf_b,
                        &c->ccdf_g, &c->ccdf_o, &c->pdf_scratch, &c->p, &c->cdf_b, &c->cdf_g, &c->W, &c->Iw,
                        &c->status, &c->field, &c->Iplane, &c->Y, &c->st, &c->hist, &c->bucket_total,
-                       &c->bucket_start, &c->nchunks, &c->chunk_bucket, &c->items, &c->faces, &c->snaps,
-                       &c->tile_snap, &c->border, &c->counters, &c->kmin, &c->cont, &c->cont_count};
+                       &c->bucket_start, &c->nchunks, &c->chunk_bucket, &c->items, &c->faces,
+                       &c->snaps, &c->tile_snap, &c->border, &c->counters, &c->kmin, &c->cont, &c->cont_count};
     std::vector<void *> v;
     for (const DBuf *d : b) v.push_back(d->p);
     return v;
@@ -1710,7 +1983,7 @@ void rmc_destroy(rmc_ctx *c)
                         &c->ccdf_g, &c->ccdf_o, &c->pdf_scratch, &c->p, &c->cdf_b, &c->cdf_g, &c->W, &c->Iw,
                         &c->status, &c->field, &c->Iplane, &c->Y, &c->st, &c->hist, &c->bucket_total, &c->bucket_start,
                         &c->nchunks, &c->chunk_bucket, &c->items, &c->faces, &c->snaps, &c->tile_snap,
-                        &c->counters, &c->outbuf, &c->trace_rec, &c->trace_cells, &c->border, &c->small, &c->scal,
+                        &c->counters, &c->outbuf, &c->tune_out, &c->trace_rec, &c->trace_cells, &c->border, &c->small, &c->scal,
                         &c->kmin, &c->cont, &c->cont_count};
         for (DBuf *b : bufs) b->release();
         for (auto &set : c->ring)
@@ -1807,6 +2080,7 @@ rmc_status rmc_set_kdist(rmc_ctx *c, int nb, int ng, int ns, int nT, double T0, 
     c->have_kdist = true;
     if (!same_range) c->have_T = false;   // temperatures must be re-validated against the new range
     c->have_q = false;
+    c->have_alloc = false;                // band centres and g abscissae belong to the tables
     ++c->config_version;
     return RMC_OK;
 }
@@ -1885,6 +2159,105 @@ rmc_status rmc_set_options(rmc_ctx *c, const rmc_options *o)
     if (rmc_status st = check_options(o)) return st;
     c->opt = *o;
     ++c->config_version;
+    return RMC_OK;
+}
+
+namespace {
+
+// Workload signature of an autotuning cache line: the device architecture and everything that
+// sets the amount and the shape of the work.
+std::string tune_signature(const rmc_ctx *c)
+{
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) arch = prop.gcnArchName;
+    for (char &ch : arch)
+        if (ch == ' ' || ch == ':') ch = '_';
+    char buf[256];
+    snprintf(buf, sizeof buf, "rmc-tune-1 %s %d %d %d %d %d %d %d %d %d %d %d", arch.c_str(), c->nx, c->ny, c->nz, c->nb,
+             c->ng, c->ns, c->opt.rays_per_cell, (int)c->opt.march, (int)c->opt.sampling, c->opt.long_ray_steps,
+             c->opt.max_steps);
+    return buf;
+}
+
+bool tune_cache_lookup(const char *path, const std::string &sig, int &span, int &sort)
+{
+    FILE *f = fopen(path, "r");
+    if (!f) return false;
+    char line[512];
+    bool hit = false;
+    while (fgets(line, sizeof line, f)) {
+        const char *sep = strstr(line, " : ");
+        if (!sep || (size_t)(sep - line) != sig.size() || strncmp(line, sig.c_str(), sig.size()) != 0) continue;
+        int a = 0, b = 0;
+        if (sscanf(sep + 3, "%d %d", &a, &b) == 2) { span = a; sort = b; hit = true; }   // last line wins
+    }
+    fclose(f);
+    return hit;
+}
+
+}  // namespace
+
+rmc_status rmc_autotune(rmc_ctx *c, int reps, const char *cache_path, rmc_options *out, void *stream)
+{
+    g_err.clear();
+    if (rmc_status st = check_ctx(c)) return st;
+    if (reps < 1 || reps > 100) return fail(RMC_INVALID_ARG, "reps must be in [1, 100]");
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(RMC_DEVICE_ERROR, "hipSetDevice(%d) failed", c->device);
+    const std::string sig = tune_signature(c);
+    rmc_options best = c->opt;
+    int span = 0, sort = 0;
+    if (cache_path && tune_cache_lookup(cache_path, sig, span, sort)) {
+        best.xcd_span = span;
+        best.length_sort = sort;
+        if (rmc_status st = check_options(&best)) return fail(st, "bad autotuning cache entry in %s", cache_path);
+    } else {
+        hipStream_t s = (hipStream_t)stream;
+        const uint64_t nc = ncells_of(c);
+        rmc_status st;
+        if ((st = c->tune_out.ensure(sizeof(double) * 2 * nc))) return st;
+        double *dq = c->tune_out.as<double>(), *se = dq + nc;
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        const rmc_options base = c->opt;
+        const int spans[] = {16, 64, 256, 1024};
+        float best_ms = 0.0f;
+        bool have = false;
+        for (int srt = 0; srt < 2 && !st; ++srt)
+            for (int sp : spans) {
+                rmc_options o = base;
+                o.xcd_span = sp;
+                o.length_sort = srt;
+                c->opt = o;
+                if ((st = rmc_compute_divergence(c, dq, se, RMC_DEVICE, stream))) break;   // warm-up
+                if (hipEventRecord(e0, s) != hipSuccess) { st = fail(RMC_DEVICE_ERROR, "hipEventRecord failed"); break; }
+                for (int q = 0; q < reps && !st; ++q) st = rmc_compute_divergence(c, dq, se, RMC_DEVICE, stream);
+                if (st) break;
+                float ms = 0.0f;
+                if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                    hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                    st = fail(RMC_DEVICE_ERROR, "timing the autotuning candidates failed");
+                    break;
+                }
+                if (!have || ms < best_ms) { best_ms = ms; best = o; have = true; }
+            }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        c->opt = base;
+        if (st) return st;
+        if (cache_path) {
+            FILE *f = fopen(cache_path, "a");
+            if (!f) return fail(RMC_INVALID_ARG, "cannot append to the autotuning cache %s", cache_path);
+            fprintf(f, "%s : %d %d\n", sig.c_str(), best.xcd_span, best.length_sort);
+            fclose(f);
+        }
+        if ((st = rmc_reset_stats(c))) return st;
+    }
+    c->opt = best;
+    ++c->config_version;
+    if (out) *out = best;
     return RMC_OK;
 }
 
@@ -2062,7 +2435,7 @@ rmc_status rmc_trace_cells(rmc_ctx *c, const int64_t *cells, int ncell, rmc_ray_
     hipStream_t s = (hipStream_t)stream;
     const int R = c->opt.rays_per_cell;
     const bool dbl = c->opt.march == RMC_F64;
-    const bool pdf_mode = c->opt.sampling == RMC_SAMPLING_PDF;
+    const int smode = (int)c->opt.sampling;
     SnapDesc D;
     rmc_status st = dbl ? plan_snapshot<double>(c, D) : plan_snapshot<float>(c, D);
     if (st) return st;
@@ -2089,18 +2462,21 @@ rmc_status rmc_trace_cells(rmc_ctx *c, const int64_t *cells, int ncell, rmc_ray_
         TraceArgs<double> A{c->snaps.as<SnapDesc>(), c->faces.as<double>(), nfaces, c->trace_cells.as<int64_t>(),
                             ncell, c->dnu.as<double>(), c->wg.as<double>(), c->nb, c->ng, R, k0, k1,
                             c->opt.tol, c->opt.max_steps, c->trace_rec.as<rmc_ray_record>()};
-        if (pdf_mode) hipLaunchKernelGGL((k_trace<double, true, false>), dim3(blocks), dim3(256), 8 * nfaces, s, A);
-        else hipLaunchKernelGGL((k_trace<double, false, false>), dim3(blocks), dim3(256), 8 * nfaces, s, A);
+        if (smode == 2) hipLaunchKernelGGL((k_trace<double, 2, false>), dim3(blocks), dim3(256), 8 * nfaces, s, A);
+        else if (smode == 1) hipLaunchKernelGGL((k_trace<double, 1, false>), dim3(blocks), dim3(256), 8 * nfaces, s, A);
+        else hipLaunchKernelGGL((k_trace<double, 0, false>), dim3(blocks), dim3(256), 8 * nfaces, s, A);
     } else {
         TraceArgs<float> A{c->snaps.as<SnapDesc>(), c->faces.as<double>(), nfaces, c->trace_cells.as<int64_t>(),
                            ncell, c->dnu.as<double>(), c->wg.as<double>(), c->nb, c->ng, R, k0, k1,
                            (float)c->opt.tol, c->opt.max_steps, c->trace_rec.as<rmc_ray_record>()};
         if (inc_xz) {
-            if (pdf_mode) hipLaunchKernelGGL((k_trace<float, true, true>), dim3(blocks), dim3(256), 8 * nfaces, s, A);
-            else hipLaunchKernelGGL((k_trace<float, false, true>), dim3(blocks), dim3(256), 8 * nfaces, s, A);
+            if (smode == 2) hipLaunchKernelGGL((k_trace<float, 2, true>), dim3(blocks), dim3(256), 8 * nfaces, s, A);
+            else if (smode == 1) hipLaunchKernelGGL((k_trace<float, 1, true>), dim3(blocks), dim3(256), 8 * nfaces, s, A);
+            else hipLaunchKernelGGL((k_trace<float, 0, true>), dim3(blocks), dim3(256), 8 * nfaces, s, A);
         } else {
-            if (pdf_mode) hipLaunchKernelGGL((k_trace<float, true, false>), dim3(blocks), dim3(256), 8 * nfaces, s, A);
-            else hipLaunchKernelGGL((k_trace<float, false, false>), dim3(blocks), dim3(256), 8 * nfaces, s, A);
+            if (smode == 2) hipLaunchKernelGGL((k_trace<float, 2, false>), dim3(blocks), dim3(256), 8 * nfaces, s, A);
+            else if (smode == 1) hipLaunchKernelGGL((k_trace<float, 1, false>), dim3(blocks), dim3(256), 8 * nfaces, s, A);
+            else hipLaunchKernelGGL((k_trace<float, 0, false>), dim3(blocks), dim3(256), 8 * nfaces, s, A);
         }
     }
     HIPCHK(hipGetLastError());
@@ -2137,7 +2513,7 @@ rmc_status rmc_get_stats(rmc_ctx *c, rmc_stats *out)
     DeviceGuard g(c->device);
     if (!g.ok) return fail(RMC_DEVICE_ERROR, "hipSetDevice(%d) failed", c->device);
     if (rmc_status st = harvest_all(c)) return st;
-    unsigned long long cnt[3] = {0, 0, 0};
+    unsigned long long cnt[4] = {0, 0, 0, 0};
     HIPCHK(hipMemcpy(cnt, c->counters.p, sizeof cnt, hipMemcpyDeviceToHost));
     memset(out, 0, sizeof *out);
     out->rays = c->last_rays;
@@ -2145,16 +2521,19 @@ rmc_status rmc_get_stats(rmc_ctx *c, rmc_stats *out)
     out->capped_rays = (int64_t)cnt[1];
     out->ms_prep = c->last_ms[0];
     out->ms_alloc = c->last_ms[1];
-    out->ms_march = c->last_ms[2];
-    out->ms_reduce = c->last_ms[3];
-    out->ms_total = c->last_ms[0] + c->last_ms[1] + c->last_ms[2] + c->last_ms[3];
+    out->ms_march = c->last_ms[2] + c->last_ms[3];
+    out->ms_reduce = c->last_ms[4];
+    out->ms_total = c->last_ms[0] + c->last_ms[1] + c->last_ms[2] + c->last_ms[3] + c->last_ms[4];
+    out->long_steps = (int64_t)cnt[3];
+    out->ms_march_lane = c->last_ms[2];
+    out->sum_ms_march_lane = c->sum_ms[2];
     out->computes = c->n_computes;
     out->sum_rays = c->sum_rays;
     out->sum_steps = (int64_t)cnt[2];
     out->sum_ms_prep = c->sum_ms[0];
     out->sum_ms_alloc = c->sum_ms[1];
-    out->sum_ms_march = c->sum_ms[2];
-    out->sum_ms_reduce = c->sum_ms[3];
+    out->sum_ms_march = c->sum_ms[2] + c->sum_ms[3];
+    out->sum_ms_reduce = c->sum_ms[4];
     return RMC_OK;
 }
 
@@ -2176,3 +2555,5 @@ rmc_status rmc_reset_stats(rmc_ctx *c)
 }
 
 }  // extern "C"
+
+#include "learn_api.inc"

@@ -21,7 +21,8 @@ RMC_OK, RMC_INVALID_ARG, RMC_BAD_STATE, RMC_OUT_OF_RANGE, RMC_UNSUPPORTED, RMC_D
 F32, F64, BF16 = 0, 1, 2
 HOST, DEVICE = 0, 1
 ACC = {"f64": 0, "comp32": 1, "f32": 2}
-SAMPLING_PLAIN, SAMPLING_PDF = 0, 1
+SAMPLING_PLAIN, SAMPLING_PDF, SAMPLING_LEARNED = 0, 1, 2
+MLP_PARAMS = 9224
 
 STATUS_NAMES = {0: "RMC_OK", 1: "RMC_INVALID_ARG", 2: "RMC_BAD_STATE", 3: "RMC_OUT_OF_RANGE",
                 4: "RMC_UNSUPPORTED", 5: "RMC_DEVICE_ERROR", 6: "RMC_OUT_OF_MEMORY"}
@@ -32,7 +33,8 @@ class Options(C.Structure):
                 ("tol", C.c_double), ("max_steps", C.c_int32), ("march", C.c_int),
                 ("accum", C.c_int), ("sampling", C.c_int), ("mix_eps", C.c_double),
                 ("block_threads", C.c_int32), ("long_ray_steps", C.c_int32),
-                ("reserved", C.c_int32 * 6)]
+                ("xcd_span", C.c_int32), ("length_sort", C.c_int32),
+                ("reserved", C.c_int32 * 4)]
 
 
 class Stats(C.Structure):
@@ -41,7 +43,8 @@ class Stats(C.Structure):
                 ("ms_reduce", C.c_double), ("ms_total", C.c_double),
                 ("computes", C.c_int64), ("sum_rays", C.c_int64), ("sum_steps", C.c_int64),
                 ("sum_ms_prep", C.c_double), ("sum_ms_alloc", C.c_double),
-                ("sum_ms_march", C.c_double), ("sum_ms_reduce", C.c_double)]
+                ("sum_ms_march", C.c_double), ("sum_ms_reduce", C.c_double),
+                ("long_steps", C.c_int64), ("ms_march_lane", C.c_double), ("sum_ms_march_lane", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -50,6 +53,12 @@ class Stats(C.Structure):
 class RayRecord(C.Structure):
     _fields_ = [("Y", C.c_double), ("p", C.c_double), ("n", C.c_int32), ("g", C.c_int32),
                 ("o", C.c_int32), ("k", C.c_int32), ("steps", C.c_int32), ("end", C.c_int32)]
+
+
+class TrainBatch(C.Structure):
+    _fields_ = [("ncell", C.c_int32), ("nsamp", C.c_int32), ("feat", C.c_void_p), ("mask", C.c_void_p),
+                ("pplain", C.c_void_p), ("cell_of", C.c_void_p), ("stratum", C.c_void_p),
+                ("h", C.c_void_p), ("p0", C.c_void_p)]
 
 
 RAY_DTYPE = np.dtype([("Y", "f8"), ("p", "f8"), ("n", "i4"), ("g", "i4"), ("o", "i4"),
@@ -79,10 +88,18 @@ SIGNATURES = {
     "rmc_get_pdf": (C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP]),
     "rmc_get_stats": (C.c_int, [_VP, C.POINTER(Stats)]),
     "rmc_reset_stats": (C.c_int, [_VP]),
+    "rmc_autotune": (C.c_int, [_VP, C.c_int, C.c_char_p, C.POINTER(Options), _VP]),
     "rmc_graph_capture": (C.c_int, [C.POINTER(_VP), C.c_int, C.POINTER(_VP), C.POINTER(_VP), _VP,
                                     C.POINTER(_VP)]),
     "rmc_graph_launch": (C.c_int, [_VP, _VP]),
     "rmc_graph_destroy": (None, [_VP]),
+    "rmc_set_allocator": (C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP]),
+    "rmc_get_allocator": (C.c_int, [_VP, _VP]),
+    "rmc_get_features": (C.c_int, [_VP, _VP, _VP, C.c_int, _VP]),
+    "rmc_allocator_logits": (C.c_int, [_VP, _VP, C.c_int, _VP, _VP]),
+    "rmc_get_ray_draws": (C.c_int, [_VP, _VP, C.c_int, _VP, _VP, _VP]),
+    "rmc_train_grad": (C.c_int, [_VP, C.POINTER(TrainBatch), C.POINTER(C.c_double), _VP, _VP]),
+    "rmc_train_step": (C.c_int, [_VP, C.POINTER(TrainBatch), C.c_float, C.POINTER(C.c_double), _VP]),
 }
 
 
@@ -296,6 +313,80 @@ class Solver:
 
     def reset_stats(self):
         _check(LIB.rmc_reset_stats(self.h))
+
+    # ------------------------------------------------------------ learned allocation
+    def set_allocator(self, params, mu, sd, nu_c, gx):
+        p = np.ascontiguousarray(params, dtype=np.float32).ravel()
+        if p.size != MLP_PARAMS:
+            raise ValueError(f"params must hold {MLP_PARAMS} values")
+        m = np.ascontiguousarray(mu, dtype=np.float32)
+        d = np.ascontiguousarray(sd, dtype=np.float32)
+        nu = np.ascontiguousarray(nu_c, dtype=np.float64)
+        g = np.ascontiguousarray(gx, dtype=np.float64)
+        _check(LIB.rmc_set_allocator(self.h, p.ctypes.data, m.ctypes.data, d.ctypes.data, nu.ctypes.data,
+                                     g.ctypes.data))
+
+    def get_allocator(self) -> np.ndarray:
+        p = np.zeros(MLP_PARAMS, dtype=np.float32)
+        _check(LIB.rmc_get_allocator(self.h, p.ctypes.data))
+        return p
+
+    def features(self, feat=None, mask=None, stream=None):
+        """Raw cell features and gradient masks: numpy outputs by default, or device tensors."""
+        if feat is None:
+            feat = np.zeros((self.ncells, 3), dtype=np.float32)
+            mask = np.zeros(self.ncells, dtype=np.uint8)
+        fb, mb = _buf(feat), _buf(mask)
+        st = _stream(stream) if fb[1] == DEVICE else stream
+        _check(LIB.rmc_get_features(self.h, fb[0], mb[0], fb[1], st))
+        return feat, mask
+
+    def allocator_logits(self, cells, stream=None) -> np.ndarray:
+        c = np.ascontiguousarray(cells, dtype=np.int64)
+        z = np.zeros((len(c), self.nb, self.ng, 8), dtype=np.float32)
+        _check(LIB.rmc_allocator_logits(self.h, c.ctypes.data, len(c), z.ctypes.data, stream))
+        return z
+
+    def ray_draws(self, cells, stream=None):
+        c = np.ascontiguousarray(cells, dtype=np.int64)
+        R = self.R
+        st = np.zeros((len(c), R), dtype=np.int32)
+        p = np.zeros((len(c), R), dtype=np.float64)
+        _check(LIB.rmc_get_ray_draws(self.h, c.ctypes.data, len(c), st.ctypes.data, p.ctypes.data, stream))
+        return st, p
+
+    def train_grad(self, batch: TrainBatch, stream=None):
+        loss = C.c_double()
+        g = np.zeros(MLP_PARAMS, dtype=np.float32)
+        _check(LIB.rmc_train_grad(self.h, C.byref(batch), C.byref(loss), g.ctypes.data, _stream(stream)))
+        return loss.value, g
+
+    def train_step(self, batch: TrainBatch, lr: float, stream=None) -> float:
+        loss = C.c_double()
+        _check(LIB.rmc_train_step(self.h, C.byref(batch), float(lr), C.byref(loss), _stream(stream)))
+        return loss.value
+
+    def autotune(self, reps: int = 3, cache_path: Optional[str] = None, stream=None) -> dict:
+        """rmc_autotune: time the schedule candidates on the current workload, keep the
+        fastest; returns the chosen {xcd_span, length_sort}."""
+        o = Options()
+        path = cache_path.encode() if cache_path else None
+        _check(LIB.rmc_autotune(self.h, int(reps), path, C.byref(o), _stream(stream)))
+        return {"xcd_span": o.xcd_span, "length_sort": o.length_sort}
+
+
+def train_batch(feat, mask, pplain, cell_of, stratum, h, p0):
+    """A TrainBatch over device tensors (feat float32 [ncell, 3], mask uint8 [ncell], pplain
+    float64 [nb*ng], cell_of / stratum int32 [nsamp] sorted by cell, h / p0 float64 [nsamp]);
+    returns (batch, keep-alive list)."""
+    import torch
+    ts = [feat, mask, pplain, cell_of, stratum, h, p0]
+    want = [torch.float32, torch.uint8, torch.float64, torch.int32, torch.int32, torch.float64, torch.float64]
+    for t, d in zip(ts, want):
+        if not (t.is_cuda and t.dtype == d and t.is_contiguous()):
+            raise ValueError("training batch tensors: contiguous device tensors of the documented dtypes")
+    b = TrainBatch(int(feat.shape[0]), int(cell_of.shape[0]), *[t.data_ptr() for t in ts])
+    return b, ts
 
 
 class Graph:

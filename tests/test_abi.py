@@ -49,7 +49,8 @@ def test_struct_layouts_match_the_header(lib, tmp_path):
     """sizeof and field offsets of the header's structs, as a C compiler lays them out."""
     import subprocess
     from paper_1810_00188_amd import rmc
-    structs = {"rmc_options": rmc.Options, "rmc_stats": rmc.Stats, "rmc_ray_record": rmc.RayRecord}
+    structs = {"rmc_options": rmc.Options, "rmc_stats": rmc.Stats, "rmc_ray_record": rmc.RayRecord,
+               "rmc_train_batch": rmc.TrainBatch}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "rmc.h"', 'int main(void){']
     for cname, cls in structs.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')

@@ -1,0 +1,88 @@
+"""GPU parity at the full sizes of the two large workloads, in the launch configuration the
+library uses by default: sampled cells' ray slots against the oracle (which computes rays one
+by one), and properties that hold at any size.
+
+* DNS-size snapshot: 256 x 128 x 128, tanh-stretched y, 100 bands x 16 g (BF16-rounded
+  tables), H2O + CO2 fluctuating +-20 %, R = 64, FP32 march; compensated FP32 against FP64
+  per-cell sums on the same ray values.
+* Batch: 12 snapshots of uneven grids (64^3, 96x64x64, 128^3, 192x96x96), 50 bands x 8 g,
+  R = 32, one pass of the pipeline.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no ROCm GPU visible", allow_module_level=True)
+
+import oracle  # noqa: E402
+from paper_1810_00188_amd import inputs, rmc  # noqa: E402
+from test_gpu_parity import _check_fp32_rays, say  # noqa: E402
+
+
+def _options(w, **over):
+    kw = dict(rays_per_cell=w.R, seed=w.seed, snapshot=w.snap, tol=w.tol, max_steps=w.max_steps,
+              march=rmc.F64 if w.march == "f64" else rmc.F32, accum=rmc.ACC[w.accum])
+    kw.update(over)
+    return rmc.default_options(**kw)
+
+
+def test_dns256_sampled_and_compensated_sums():
+    w = inputs.dns256()
+    say(f"dns256 {w.name}: {w.ncells} cells, {w.kd.nb} x {w.kd.ng}, R = {w.R}")
+    s = rmc.Solver(0)
+    s.set_workload(w, device_fields=True)
+    dev = torch.device("cuda", 0)
+    dq = torch.zeros(w.ncells, dtype=torch.float64, device=dev)
+    se = torch.zeros_like(dq)
+    s.compute(dq, se)
+    torch.cuda.synchronize()
+    st = s.stats()
+    say(f"dns256 stats {st}")
+    # a handful of grazing rays in nearly transparent g-points reach the step cap (65536
+    # steps) with tau > tol, exactly as in the oracle, which applies the same cap
+    assert st["rays"] == w.ncells * w.R and st["capped_rays"] < 100
+    rng = np.random.default_rng(11)
+    cells = np.unique(np.concatenate([rng.choice(w.ncells, 192, replace=False), [0, w.ncells - 1]]))
+    Y, S = s.ray_values(cells)
+    ref = oracle.trace_cells(oracle.Problem(w), cells)
+    say(f"dns256 sampled rays: oracle steps max {ref['steps'].max()} mean {ref['steps'].mean():.1f}")
+    _check_fp32_rays(w, cells, Y, S, ref)
+    # the same ray values summed in compensated FP32: within 1e-6 of the FP64 sums, relative
+    # to the mean |ray value| of the cell
+    d64 = dq.cpu().numpy()
+    s.set_options(_options(w, accum=rmc.ACC["comp32"]))
+    dq32 = torch.zeros_like(dq)
+    s.compute(dq32)
+    torch.cuda.synchronize()
+    Yall, _ = s.ray_values(cells)
+    scale = np.abs(Yall).mean(axis=1) + 1e-300
+    d32 = dq32.cpu().numpy()
+    rel = np.abs(d32[cells] - d64[cells]) / scale
+    say(f"dns256 comp32 vs f64: max {rel.max():.2e} over sampled cells")
+    assert rel.max() < 1e-6
+    assert np.all(np.isfinite(d32)) and np.abs(d32 - d64).max() <= 1e-6 * np.abs(d64).max()
+
+
+def test_batch12_one_pass_sampled():
+    ws = inputs.batch12()
+    say(f"batch of {len(ws)}: {sum(x.ncells for x in ws)} cells, {ws[0].kd.nb} x {ws[0].kd.ng}, R = {ws[0].R}")
+    solvers = []
+    for x in ws:
+        s = rmc.Solver(0)
+        s.set_workload(x, device_fields=True)
+        solvers.append(s)
+    dev = torch.device("cuda", 0)
+    outs = [torch.zeros(x.ncells, dtype=torch.float64, device=dev) for x in ws]
+    rmc.compute_batch(solvers, outs)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(12)
+    for q, (x, s) in enumerate(zip(ws, solvers)):
+        cells = np.unique(np.concatenate([rng.choice(x.ncells, 24, replace=False), [0, x.ncells - 1]]))
+        Y, S = s.ray_values(cells)
+        ref = oracle.trace_cells(oracle.Problem(x), cells)
+        say(f"batch snapshot {q} ({x.nx}x{x.ny}x{x.nz})")
+        _check_fp32_rays(x, cells, Y, S, ref)
+        assert torch.isfinite(outs[q]).all()
