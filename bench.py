@@ -53,6 +53,17 @@ def parse():
     return ap.parse_args()
 
 
+def kernel_source_hash():
+    """sha256 over the HIP sources (the traffic counters are valid for that code only)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1810_00188_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def cpu_baseline(w, target_s):
     """The oracle, as it stands, on whole passes over the same workload, repeated with fresh
     snapshot numbers (fresh random streams) until about target_s seconds have elapsed."""
@@ -130,7 +141,9 @@ def main():
     achieved = bytes_launch / (lane_ms * 1e-3) / 1e9
     traffic = None
     if a.traffic_json and os.path.exists(a.traffic_json):
-        traffic = json.load(open(a.traffic_json)).get("k_march_lane", {}).get("bytes_per_launch")
+        rec = json.load(open(a.traffic_json)).get("k_march_lane", {})
+        if rec.get("source_sha256") == kernel_source_hash():   # counters of this very code only
+            traffic = rec.get("bytes_per_launch")
     out = {
         "metric": "ray-cell steps/s",
         "value": value,

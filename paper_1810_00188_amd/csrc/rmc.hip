@@ -37,8 +37,9 @@ struct SnapDesc {
     const double *Ipl;          // [nb][ncpad] I_n planes, bricked
     const double *W;            // [nbucket] plain ray weight 4 pi dnu w / (8 p(n,g,o))
     const double *Iw;           // [2][nb] wall intensities
-    void *Y;                    // Real [ncells * R] ray values, slot c * R + r
-    uint32_t *st;               // [ncells * R] steps | end << 28
+    void *Y;                    // ray slots c * R + r: FP32 march {value bits, steps | end << 28} as
+                                // one 8-byte record; FP64 march the double values, with
+    uint32_t *st;               // [ncells * R] steps | end << 28 (FP64 march only)
     const double *p;            // [nb*ng] plain pdf
     const double *cdf_b;        // [nb]
     const double *cdf_g;        // [nb*ng]
@@ -529,6 +530,18 @@ __global__ void __launch_bounds__(256) k_alloc_scatter(AllocArgs A)
 }
 
 // -------------------------------------------------------------------------- march
+// Ray slot write: one 8-byte store per ray in the FP32 march (a ray's slot is a scattered
+// address, so two 4-byte stores would cost two partial-line writes).
+template <class Real> __device__ __forceinline__ void store_slot(const SnapDesc &D, size_t slot, double y, uint32_t sw)
+{
+    if constexpr (sizeof(Real) == 4) {
+        reinterpret_cast<uint2 *>(D.Y)[slot] = make_uint2(__float_as_uint((float)y), sw);
+    } else {
+        reinterpret_cast<double *>(D.Y)[slot] = y;
+        D.st[slot] = sw;
+    }
+}
+
 template <class Real> struct MarchArgs {
     const SnapDesc *snaps;
     const double *faces;        // all snapshots' face tables, staged into LDS
@@ -731,8 +744,7 @@ __global__ void __launch_bounds__(256) k_march_lane(MarchArgs<Real> A)
         const double p = gld(D.dprob + slot);
         w = 4.0 * M_PI * A.dnu[n] * A.wg[pair - n * A.ng] / (8.0 * p);
     }
-    reinterpret_cast<Real *>(D.Y)[slot] = (Real)(w * (double)kap_src * (double)R.acc);
-    D.st[slot] = (uint32_t)R.steps | ((uint32_t)R.end << 28);
+    store_slot<Real>(D, slot, w * (double)kap_src * (double)R.acc, (uint32_t)R.steps | ((uint32_t)R.end << 28));
 }
 
 // Long rays (FP32 march, uniform periodic x and z): one wavefront per ray handed over by the
@@ -932,8 +944,7 @@ __global__ void __launch_bounds__(256) k_march_long(MarchArgs<float> A)
                     w = 4.0 * M_PI * A.dnu[n] * A.wg[pair - n * A.ng] / (8.0 * p);
                 }
                 const double acc = sacc + contrib;
-                reinterpret_cast<float *>(D.Y)[slot] = (float)(w * (double)kap_src * acc);
-                D.st[slot] = (uint32_t)R.steps | ((uint32_t)R.end << 28);
+                store_slot<float>(D, slot, w * (double)kap_src * acc, (uint32_t)R.steps | ((uint32_t)R.end << 28));
                 atomicAdd(A.long_steps, (unsigned long long)(R.steps - rc.steps));
             }
             break;
@@ -1016,7 +1027,7 @@ constexpr int kRedVals = 4096;
 __device__ __forceinline__ int red_pad(int q) { return q + (q >> 5); }
 
 template <class Real>
-__global__ void __launch_bounds__(256) k_reduce(const Real *__restrict__ Y, const uint32_t *__restrict__ st,
+__global__ void __launch_bounds__(256) k_reduce(const void *__restrict__ Yv, const uint32_t *__restrict__ st,
                                                 uint64_t nc, int R, int accum, double *__restrict__ divq,
                                                 double *__restrict__ se, unsigned long long *counters)
 {
@@ -1027,11 +1038,20 @@ __global__ void __launch_bounds__(256) k_reduce(const Real *__restrict__ Y, cons
     for (uint64_t base = (uint64_t)blockIdx.x * cpg; base < nc; base += (uint64_t)gridDim.x * cpg) {
         const int ncell = (int)min((uint64_t)cpg, nc - base);
         const int nval = ncell * R;
-        const Real *yb = Y + base * R;
-        const uint32_t *sb = st + base * R;
-        for (int q = threadIdx.x; q < nval; q += blockDim.x) {
-            ys[red_pad(q)] = yb[q];
-            ss[red_pad(q)] = sb[q];
+        if constexpr (sizeof(Real) == 4) {
+            const uint2 *yb = reinterpret_cast<const uint2 *>(Yv) + base * R;
+            for (int q = threadIdx.x; q < nval; q += blockDim.x) {
+                const uint2 v = yb[q];
+                ys[red_pad(q)] = __uint_as_float(v.x);
+                ss[red_pad(q)] = v.y;
+            }
+        } else {
+            const double *yb = reinterpret_cast<const double *>(Yv) + base * R;
+            const uint32_t *sb = st + base * R;
+            for (int q = threadIdx.x; q < nval; q += blockDim.x) {
+                ys[red_pad(q)] = yb[q];
+                ss[red_pad(q)] = sb[q];
+            }
         }
         __syncthreads();
         for (int cq = threadIdx.x; cq < ncell; cq += blockDim.x) {
@@ -1469,7 +1489,8 @@ template <class Real> rmc_status plan_snapshot(rmc_ctx *c, SnapDesc &D)
         (st = c->status.ensure(sizeof(int))) ||
         (st = c->field.ensure(sizeof(Real) * ncpad_of(c) * (uint64_t)(nb * ng))) ||
         (st = c->Iplane.ensure(sizeof(double) * ncpad_of(c) * (uint64_t)nb)) ||
-        (st = c->Y.ensure(sizeof(Real) * nc * R)) || (st = c->st.ensure(sizeof(uint32_t) * nc * R)))
+        (st = c->Y.ensure(sizeof(uint64_t) * nc * R)) ||
+        (sizeof(Real) == 8 && (st = c->st.ensure(sizeof(uint32_t) * nc * R))))
         return st;
     D = SnapDesc{};
     D.nx = c->nx; D.ny = c->ny; D.nz = c->nz;
@@ -1501,7 +1522,7 @@ template <class Real> rmc_status plan_snapshot(rmc_ctx *c, SnapDesc &D)
     D.kap = c->field.p;
     D.Ipl = c->Iplane.as<double>();
     D.Y = c->Y.p;
-    D.st = c->st.as<uint32_t>();
+    D.st = sizeof(Real) == 8 ? c->st.as<uint32_t>() : nullptr;
     c->slots_R = R;
     c->slots_real = (int)sizeof(Real);
     return RMC_OK;
@@ -1787,7 +1808,7 @@ rmc_status enqueue_pipeline(const Plan &P, double *const *divq, double *const *s
         const uint64_t nc = ncells_of(c);
         const uint64_t groups = (nc + (kRedVals / R) - 1) / (kRedVals / R);
         hipLaunchKernelGGL(k_reduce<Real>, dim3((unsigned)std::min<uint64_t>(groups, 2048)), dim3(256), 0, s,
-                           c->Y.as<Real>(), c->st.as<uint32_t>(), nc, R, (int)O.accum, divq[q],
+                           c->Y.p, sizeof(Real) == 8 ? c->st.as<uint32_t>() : nullptr, nc, R, (int)O.accum, divq[q],
                            se ? se[q] : nullptr, L->counters.as<unsigned long long>());
         HIPCHK(hipGetLastError());
     }
@@ -2404,17 +2425,28 @@ rmc_status rmc_get_ray_values(rmc_ctx *c, const int64_t *cells, int ncell, doubl
     hipStream_t s = (hipStream_t)stream;
     HIPCHK(hipStreamSynchronize(s));
     const int R = c->slots_R;
-    std::vector<char> tmp((size_t)R * 8);
+    std::vector<uint64_t> tmp(R);
     std::vector<uint32_t> st(R);
     for (int q = 0; q < ncell; ++q) {
         const size_t off = (size_t)cells[q] * R;
-        HIPCHK(hipMemcpy(tmp.data(), c->Y.as<char>() + off * c->slots_real, (size_t)R * c->slots_real,
-                         hipMemcpyDeviceToHost));
-        HIPCHK(hipMemcpy(st.data(), c->st.as<uint32_t>() + off, sizeof(uint32_t) * R, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(tmp.data(), c->Y.as<uint64_t>() + off, sizeof(uint64_t) * R, hipMemcpyDeviceToHost));
+        if (c->slots_real == 8)
+            HIPCHK(hipMemcpy(st.data(), c->st.as<uint32_t>() + off, sizeof(uint32_t) * R, hipMemcpyDeviceToHost));
         for (int r = 0; r < R; ++r) {
-            Y[(size_t)q * R + r] = c->slots_real == 4 ? (double)((const float *)tmp.data())[r]
-                                                       : ((const double *)tmp.data())[r];
-            if (steps) steps[(size_t)q * R + r] = (int32_t)(st[r] & 0x0FFFFFFFu);
+            double y;
+            uint32_t w;
+            if (c->slots_real == 4) {   // {value bits, steps | end << 28}
+                float f;
+                const uint32_t lo = (uint32_t)tmp[r];
+                memcpy(&f, &lo, 4);
+                y = (double)f;
+                w = (uint32_t)(tmp[r] >> 32);
+            } else {
+                memcpy(&y, &tmp[r], 8);
+                w = st[r];
+            }
+            Y[(size_t)q * R + r] = y;
+            if (steps) steps[(size_t)q * R + r] = (int32_t)(w & 0x0FFFFFFFu);
         }
     }
     return RMC_OK;
