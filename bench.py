@@ -48,6 +48,12 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (the "
                          "reference point that scales rocprofv3 FETCH_SIZE / WRITE_SIZE)")
+    ap.add_argument("--learned", choices=["channel64", "dns256"], default=None,
+                    help="instead of the throughput benchmark: train the allocation network on plain "
+                         "runs and report the wall time to 1 %% RMS error, learned vs plain")
+    ap.add_argument("--train-seeds", type=int, default=0, help="training fields (0: per workload)")
+    ap.add_argument("--eval-seeds", type=int, default=0, help="held-out evaluation fields (0: per workload)")
+    ap.add_argument("--train-steps", type=int, default=0, help="Adam steps (0: per workload)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "march_traffic.json"),
                     help="HBM bytes per march launch measured by rocprofv3 (optional)")
     return ap.parse_args()
@@ -85,12 +91,88 @@ def cpu_baseline(w, target_s):
                       f"{steps} steps in {dt:.1f} s"}
 
 
+def say(msg):
+    print(f"[learned] {msg}", flush=True)
+
+
+def learned_bench(a):
+    """Wall time to 1 % RMS error of the heat source, learned vs plain allocation (median over
+    held-out fields), with the network trained by the library's kernels on plain runs."""
+    import numpy as np
+    import torch
+    from paper_1810_00188_amd import inputs, learned, rmc
+
+    cfg = {"channel64": dict(gen=inputs.channel64, train=8, eval=4, steps=1500, cells=16384, batch=64,
+                             Rs=(16, 32, 64, 128)),
+           "dns256": dict(gen=inputs.dns256, train=12, eval=6, steps=1500, cells=32768, batch=16,
+                          Rs=(16, 32, 64, 128))}[a.learned]
+    n_train = a.train_seeds or cfg["train"]
+    n_eval = a.eval_seeds or cfg["eval"]
+    steps = a.train_steps or cfg["steps"]
+    eps, lr = 0.1, 2e-3
+    t_start = time.perf_counter()
+    w0 = cfg["gen"](field_seed=1)
+    kd = w0.kd
+    nu_c, gx = learned.spectral_inputs(kd)
+    s = rmc.Solver(0)
+    s.set_workload(w0, device_fields=True, mix_eps=eps)
+    rng = np.random.default_rng(7)
+    runs, feats = [], []
+    for k in range(1, n_train + 1):
+        w = w0 if k == 1 else cfg["gen"](field_seed=k)
+        s.set_temperature(np.ascontiguousarray(w.T, dtype=np.float32))
+        s.set_species(np.ascontiguousarray(w.X, dtype=np.float32))
+        s.set_options(rmc.default_options(rays_per_cell=w.R, seed=w.seed, snapshot=k, tol=w.tol,
+                                          max_steps=w.max_steps, march=rmc.F32, mix_eps=eps))
+        cells = np.sort(rng.choice(w.ncells, min(cfg["cells"], w.ncells), replace=False))
+        runs.append(learned.plain_samples(s, cells))
+        feats.append(runs[-1].feat.cpu().numpy())
+        say(f"training field {k}: {len(cells)} cells x {w.R} rays")
+    mu, sd = learned.standardisation(feats, kd)
+    s.set_allocator(learned.init_params(0), mu, sd, nu_c, gx)
+    t_train = time.perf_counter()
+    losses = learned.train(s, runs, steps, lr, cfg["batch"], log=say)
+    t_train = time.perf_counter() - t_train
+    params = s.get_allocator()
+    del runs
+    s_plain = rmc.Solver(0)
+    s_learn = rmc.Solver(0)
+    results = []
+    for e in range(n_eval):
+        w = cfg["gen"](field_seed=1000 + e)
+        s_plain.set_workload(w, device_fields=True)
+        s_learn.set_workload(w, device_fields=True, sampling=rmc.SAMPLING_LEARNED, mix_eps=eps)
+        s_learn.set_allocator(params, mu, sd, nu_c, gx)
+        say(f"evaluation field {1000 + e}")
+        results.append(learned.time_to_error(w, s_plain, s_learn, eps, Rs=cfg["Rs"], log=say))
+    tp = np.array([r["plain"]["time_to_target_s"] for r in results])
+    tl = np.array([r["learned"]["time_to_target_s"] for r in results])
+    out = {
+        "metric": "wall time to 1% RMS divq error, learned vs plain",
+        "value": float(np.median(tl)), "unit": "s", "higher_is_better": False,
+        "plain_s": float(np.median(tp)), "speedup_vs_plain": float(np.median(tp / tl)),
+        "learned_wins": int(np.sum(tl < tp)), "eval_fields": n_eval,
+        "n_gpus": 1, "dtype": "f32", "data": "synthetic", "vs_baseline": None,
+        "config": {"workload": w0.name, "grid": [w0.nx, w0.ny, w0.nz], "bands": kd.nb, "g_points": kd.ng,
+                   "train_fields": n_train, "train_cells_per_field": cfg["cells"], "train_steps": steps,
+                   "batch_cells": cfg["batch"], "mix_eps": eps, "R": list(cfg["Rs"]),
+                   "reference_rays_per_cell": results[0]["ref_rays_per_cell"]},
+        "train_loss_first_last": [float(np.mean(losses[:50])), float(np.mean(losses[-50:]))],
+        "train_s": t_train, "total_s": time.perf_counter() - t_start,
+        "per_field": [{"plain": r["plain"], "learned": r["learned"]} for r in results],
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": a.gpus}))
         sys.exit(2)
+    if a.learned:
+        learned_bench(a)
+        return
     import numpy as np
     import torch
     from paper_1810_00188_amd import inputs, rmc

@@ -1373,12 +1373,17 @@ struct NetLaunch {
 
 NetLaunch net_launch(const rmc_ctx *c)
 {
-    NetLaunch L;
     const int S = c->nb * c->ng * 8;
-    L.cpb = std::max(1, std::min(16, 16384 / S));
-    L.lds_logits = sizeof(float) * ((size_t)L.cpb * S + (size_t)L.cpb * kHid + ((L.cpb + 15) / 16) * 4);
-    L.lds_draw = L.lds_logits + sizeof(double) * (2 * (size_t)c->nb + 256);
-    return L;
+    auto size = [&](int cpb) {
+        NetLaunch L;
+        L.cpb = cpb;
+        L.lds_logits = sizeof(float) * ((size_t)cpb * S + (size_t)cpb * kHid + ((cpb + 15) / 16) * 4);
+        L.lds_draw = L.lds_logits + sizeof(double) * (2 * (size_t)c->nb + 256);
+        return L;
+    };
+    int cpb = 16;   // as many cells as fit in 64 KiB of LDS
+    while (cpb > 1 && size(cpb).lds_draw > 64 * 1024) --cpb;
+    return size(cpb);
 }
 
 // buffers of the features and of the per-ray draws; the face table for the features kernel

@@ -212,11 +212,13 @@ def fourier_field(xc, yc, zc, Lx, Lz, ylo, yhi, nmodes: int, seed: int) -> np.nd
     b = rng.integers(-8, 9, nmodes)
     c = rng.integers(0, 5, nmodes)
     ph = rng.uniform(0.0, 2.0 * np.pi, nmodes)
-    X, Y, Z = np.meshgrid(xc, yc, zc, indexing="ij")
-    S = np.zeros(X.shape)
-    for m in range(nmodes):
-        S += np.cos(2.0 * np.pi * (a[m] * X / Lx + b[m] * Z / Lz)
-                    + c[m] * np.pi * (Y - ylo) / (yhi - ylo) + ph[m])
+    # each mode is separable, cos(u + v + w) = Re(e^{iu} e^{iv} e^{iw}), so the sum over modes
+    # is one matrix product: S[(i, j), k] = Re(sum_m A[(i, j), m] E[m, k])
+    ex = np.exp(1j * 2.0 * np.pi * np.outer(xc / Lx, a))                                   # [nx, m]
+    ey = np.exp(1j * (np.outer((yc - ylo) / (yhi - ylo), c) * np.pi + ph[None, :]))      # [ny, m]
+    ez = np.exp(1j * 2.0 * np.pi * np.outer(b, zc / Lz))                                   # [m, nz]
+    A = (ex[:, None, :] * ey[None, :, :]).reshape(len(xc) * len(yc), nmodes)
+    S = np.real(A @ ez).reshape(len(xc), len(yc), len(zc))
     mx = np.max(np.abs(S))
     return (S / mx if mx > 0 else S).reshape(-1)
 

@@ -120,9 +120,12 @@ def _plain_cdf_inverse_check(P, u0, u1, u2, nb, ng):
     return (n * ng + g) * 8 + o, min(np.abs(cb - u0).min(), np.abs(cg - u1).min(), np.abs(co - u2).min())
 
 
-def test_learned_draws_and_rays_match_oracle():
+@pytest.mark.parametrize("tables", [(5, 3), (20, 7)])
+def test_learned_draws_and_rays_match_oracle(tables):
+    """Draws and ray values of the learned mode; the larger table set puts several cells'
+    logits in one workgroup's LDS (12 cells of 1120 strata)."""
     eps = 0.15
-    w = _workload(R=24)
+    w = _workload(R=24, nb=tables[0], ng=tables[1])
     say(f"learned sampling {w.name}")
     s = _solver(w)
     feat, mask = s.features()

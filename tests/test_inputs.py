@@ -113,3 +113,16 @@ def test_channel_fields_in_range():
     assert np.all(w.T == w.T.astype(np.float32))
     assert w.X.shape == (2, 512)
     assert np.all(np.abs(w.X / 0.1 - 1.0) <= 0.2 + 1e-6)
+
+
+def test_fourier_field_equals_the_direct_sum():
+    """The matrix-product evaluation of the separable modes equals the sum of cosines."""
+    xc, yc, zc = np.linspace(0.1, 12, 7), np.linspace(-0.9, 0.9, 5), np.linspace(0.1, 6, 6)
+    f = inputs.fourier_field(xc, yc, zc, 4 * np.pi, 2 * np.pi, -1.0, 1.0, 8, 3)
+    rng = np.random.default_rng(3)
+    a, b, c = rng.integers(-8, 9, 8), rng.integers(-8, 9, 8), rng.integers(0, 5, 8)
+    ph = rng.uniform(0, 2 * np.pi, 8)
+    X, Y, Z = np.meshgrid(xc, yc, zc, indexing="ij")
+    S = sum(np.cos(2 * np.pi * (a[m] * X / (4 * np.pi) + b[m] * Z / (2 * np.pi)) + c[m] * np.pi * (Y + 1) / 2 + ph[m])
+            for m in range(8))
+    assert np.abs(f - (S / np.abs(S).max()).ravel()).max() < 1e-13
