@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--learned", choices=["channel64", "dns256"], default=None,
                     help="instead of the throughput benchmark: train the allocation network on plain "
                          "runs and report the wall time to 1 %% RMS error, learned vs plain")
+    ap.add_argument("--no-cost", action="store_true",
+                    help="train on the second moment alone (no per-(n, g) ray cost in the loss)")
     ap.add_argument("--train-seeds", type=int, default=0, help="training fields (0: per workload)")
     ap.add_argument("--eval-seeds", type=int, default=0, help="held-out evaluation fields (0: per workload)")
     ap.add_argument("--train-steps", type=int, default=0, help="Adam steps (0: per workload)")
@@ -131,10 +133,12 @@ def learned_bench(a):
     mu, sd = learned.standardisation(feats, kd)
     s.set_allocator(learned.init_params(0), mu, sd, nu_c, gx)
     t_train = time.perf_counter()
-    losses = learned.train(s, runs, steps, lr, cfg["batch"], log=say)
+    cost = None if a.no_cost else learned.pair_costs(runs, kd.nb * kd.ng)
+    losses = learned.train(s, runs, steps, lr, cfg["batch"], log=say, cost=cost)
     t_train = time.perf_counter() - t_train
     params = s.get_allocator()
     del runs
+    s.close()
     s_plain = rmc.Solver(0)
     s_learn = rmc.Solver(0)
     results = []
@@ -156,6 +160,7 @@ def learned_bench(a):
         "config": {"workload": w0.name, "grid": [w0.nx, w0.ny, w0.nz], "bands": kd.nb, "g_points": kd.ng,
                    "train_fields": n_train, "train_cells_per_field": cfg["cells"], "train_steps": steps,
                    "batch_cells": cfg["batch"], "mix_eps": eps, "R": list(cfg["Rs"]),
+                   "loss": "second moment" if a.no_cost else "second moment x ray cost",
                    "reference_rays_per_cell": results[0]["ref_rays_per_cell"]},
         "train_loss_first_last": [float(np.mean(losses[:50])), float(np.mean(losses[-50:]))],
         "train_s": t_train, "total_s": time.perf_counter() - t_start,

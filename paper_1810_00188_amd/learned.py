@@ -72,6 +72,7 @@ class RunSamples:
     p0: object
     ncell: int
     R: int
+    steps: np.ndarray = None    # host: step count of every ray
 
 
 def plain_samples(s: rmc.Solver, cells: np.ndarray) -> RunSamples:
@@ -87,10 +88,26 @@ def plain_samples(s: rmc.Solver, cells: np.ndarray) -> RunSamples:
     p, _, _, _ = s.pdf()
     T = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(device=dev, dtype=dt)  # noqa: E731
     return RunSamples(T(feat[cells], torch.float32), T(mask[cells], torch.uint8), T(p.ravel(), torch.float64),
-                      T(strata, torch.int32), T(h, torch.float64), T(p0, torch.float64), len(cells), s.R)
+                      T(strata, torch.int32), T(h, torch.float64), T(p0, torch.float64), len(cells), s.R,
+                      rec["steps"].ravel().astype(np.float64))
 
 
-def batch_of(run: RunSamples, sel: np.ndarray):
+def pair_costs(runs: List[RunSamples], P: int, overhead: float = 5.0) -> np.ndarray:
+    """Cost of a ray of each (n, g): its mean number of steps in the training rays plus a fixed
+    overhead (allocation, set-up and reduction of a ray, in step equivalents); pairs never
+    sampled get the largest cost."""
+    tot = np.zeros(P)
+    cnt = np.zeros(P)
+    for r in runs:
+        pair = r.strata.cpu().numpy() >> 3
+        tot += np.bincount(pair, weights=r.steps, minlength=P)
+        cnt += np.bincount(pair, minlength=P)
+    c = np.where(cnt > 0, tot / np.maximum(cnt, 1), np.nan)
+    c = np.where(np.isnan(c), np.nanmax(c), c)
+    return c + overhead
+
+
+def batch_of(run: RunSamples, sel: np.ndarray, cost=None):
     """TrainBatch of the selected cells (indices into the run, sorted) and its keep-alive list."""
     import torch
     dev = run.feat.device
@@ -99,20 +116,26 @@ def batch_of(run: RunSamples, sel: np.ndarray):
     cell_of = torch.arange(len(sel), device=dev, dtype=torch.int32).repeat_interleave(run.R)
     return rmc.train_batch(run.feat[sel_t].contiguous(), run.mask[sel_t].contiguous(), run.pplain,
                            cell_of.contiguous(), run.strata[ridx].contiguous(), run.h[ridx].contiguous(),
-                           run.p0[ridx].contiguous())
+                           run.p0[ridx].contiguous(), cost=cost)
 
 
 def train(s: rmc.Solver, runs: List[RunSamples], steps: int, lr: float, batch_cells: int, seed: int = 0,
-          log: Optional[Callable[[str], None]] = None, lr_final: Optional[float] = None) -> List[float]:
+          log: Optional[Callable[[str], None]] = None, lr_final: Optional[float] = None,
+          cost: Optional[np.ndarray] = None) -> List[float]:
     """Adam steps on batches of cells drawn from the runs in turn; the learning rate decays
-    geometrically to lr_final (default lr / 10).  Returns the batch losses."""
+    geometrically to lr_final (default lr / 10).  With a per-(n, g) ray cost the loss is the
+    work-normalised second moment.  Returns the batch losses."""
     rng = np.random.default_rng(seed)
+    cost_t = None
+    if cost is not None:
+        import torch
+        cost_t = torch.from_numpy(np.ascontiguousarray(cost, dtype=np.float64)).to(runs[0].feat.device)
     lr_final = lr / 10.0 if lr_final is None else lr_final
     losses = []
     for t in range(steps):
         run = runs[t % len(runs)]
         sel = np.sort(rng.choice(run.ncell, min(batch_cells, run.ncell), replace=False))
-        batch, keep = batch_of(run, sel)
+        batch, keep = batch_of(run, sel, cost_t)
         a = lr * (lr_final / lr) ** (t / max(steps - 1, 1))
         losses.append(s.train_step(batch, a))
         if log and (t % max(steps // 10, 1) == 0 or t == steps - 1):
@@ -170,18 +193,20 @@ def time_to_error(w, s_plain: rmc.Solver, s_learn: rmc.Solver, mix_eps: float, R
     out = {"ref_rays_per_cell": ref_runs * ref_R}
     for name, s, sampling in (("plain", s_plain, rmc.SAMPLING_PLAIN), ("learned", s_learn, rmc.SAMPLING_LEARNED)):
         eps = mix_eps if sampling == rmc.SAMPLING_LEARNED else 0.0
-        es, ts = [], []
+        es, ts, spr = [], [], []
         for R in Rs:
             set_opts(s, R, snap_base + 100 + R, sampling, eps)
             ts.append(timed_compute(s, dq, reps))
             es.append(rel_error(dq.cpu().numpy(), qref, se_ref))
+            st = s.stats()
+            spr.append(st["steps"] / max(st["rays"], 1))
         Rs_a, es_a, ts_a = np.array(Rs, dtype=float), np.array(es), np.array(ts)
         slope = float(np.polyfit(np.log(Rs_a), np.log(np.maximum(es_a, 1e-300)), 1)[0])
         R1 = float(np.median(Rs_a * (es_a / target) ** 2))
         t1, t0 = np.polyfit(Rs_a, ts_a, 1)
-        out[name] = {"R": list(Rs), "rel_err": es, "t_s": ts, "err_slope": slope, "R_target": R1,
+        out[name] = {"R": list(Rs), "rel_err": es, "t_s": ts, "steps_per_ray": spr, "err_slope": slope, "R_target": R1,
                      "t0_s": float(t0), "t_per_ray_s": float(t1), "time_to_target_s": float(t0 + t1 * R1)}
         if log:
-            log(f"{name}: err {np.round(es_a, 5).tolist()} slope {slope:.2f} R_1% {R1:.0f} "
+            log(f"{name}: err {np.round(es_a, 5).tolist()} slope {slope:.2f} R_1% {R1:.0f} steps/ray {spr[-1]:.1f} "
                 f"t(R) {np.round(ts_a * 1e3, 2).tolist()} ms -> {out[name]['time_to_target_s']:.3f} s")
     return out

@@ -83,6 +83,58 @@ def test_loss_minimiser_is_sqrt_second_moment():
     np.testing.assert_allclose(p, target, rtol=2e-3)
 
 
+def test_cost_loss_gradient_matches_finite_differences():
+    rng = np.random.default_rng(11)
+    nc, nb, ng = 5, 3, 2
+    zg = rng.normal(size=(nc, nb, ng, 8))
+    p_plain = rng.uniform(0.2, 1.0, (nb, ng))
+    p_plain /= p_plain.sum()
+    cost = rng.uniform(1.0, 30.0, (nb, ng))
+    cell_of = np.sort(rng.integers(0, nc, 40))
+    strata = rng.integers(0, nb * ng * 8, 40)
+    h = rng.normal(size=40)
+    p0 = rng.uniform(0.01, 0.2, 40)
+    L, dz = mlp.allocation_loss(zg, p_plain, 0.1, cell_of, strata, h, p0, cost=cost)
+    v = zg.ravel()
+    for q in rng.choice(v.size, 60, replace=False):
+        a, b = v.copy(), v.copy()
+        a[q] += 1e-6
+        b[q] -= 1e-6
+        fd = (mlp.allocation_loss(a.reshape(zg.shape), p_plain, 0.1, cell_of, strata, h, p0, cost=cost)[0]
+              - mlp.allocation_loss(b.reshape(zg.shape), p_plain, 0.1, cell_of, strata, h, p0, cost=cost)[0]) / 2e-6
+        assert abs(fd - dz.ravel()[q]) <= 1e-6 * (1 + abs(fd))
+    # a unit cost is the plain second moment
+    L1, d1 = mlp.allocation_loss(zg, p_plain, 0.1, cell_of, strata, h, p0, cost=np.ones((nb, ng)))
+    L2, d2 = mlp.allocation_loss(zg, p_plain, 0.1, cell_of, strata, h, p0)
+    assert abs(L1 - L2) < 1e-14 * abs(L2) and np.allclose(d1, d2, rtol=1e-12, atol=1e-16)
+
+
+def test_cost_loss_minimiser_is_work_normalised():
+    """With exact expectations, the minimiser of second moment x expected cost is
+    p_s = sqrt(H_s / c_s) / sum sqrt(H / c) (Cauchy-Schwarz)."""
+    nb, ng = 2, 2
+    S = nb * ng * 8
+    rng = np.random.default_rng(6)
+    H = rng.uniform(0.01, 4.0, S)
+    cost = rng.uniform(1.0, 20.0, (nb, ng))
+    cs = np.repeat(cost.ravel(), 8)
+    p_plain = np.full((nb, ng), 1.0 / (nb * ng))
+    strata = np.arange(S)
+    p0 = np.full(S, 1.0 / S)
+    h = np.sqrt(H) * p0
+    cell_of = np.zeros(S, dtype=int)
+    z = np.zeros((1, nb, ng, 8))
+    m = np.zeros_like(z)
+    s2 = np.zeros_like(z)
+    for t in range(1, 8001):
+        L, dz = mlp.allocation_loss(z, p_plain, 0.0, cell_of, strata, h, p0, cost=cost)
+        v, m, s2 = mlp.adam_step(z.ravel(), dz.ravel(), m.ravel(), s2.ravel(), t, lr=0.02)
+        z, m, s2 = v.reshape(z.shape), m.reshape(z.shape), s2.reshape(z.shape)
+    p = mlp.cell_pdf(z, p_plain, 0.0).ravel()
+    target = np.sqrt(H / cs) / np.sqrt(H / cs).sum()
+    np.testing.assert_allclose(p, target, rtol=3e-3)
+
+
 def test_octant_frame_and_pdf_normalisation():
     rng = np.random.default_rng(2)
     z = rng.normal(size=(4, 2, 3, 8))
