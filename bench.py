@@ -53,6 +53,7 @@ def parse():
                          "runs and report the wall time to 1 %% RMS error, learned vs plain")
     ap.add_argument("--no-cost", action="store_true",
                     help="train on the second moment alone (no per-(n, g) ray cost in the loss)")
+    ap.add_argument("--train-rays", type=int, default=0, help="rays per training cell (0: the workload's R)")
     ap.add_argument("--train-seeds", type=int, default=0, help="training fields (0: per workload)")
     ap.add_argument("--eval-seeds", type=int, default=0, help="held-out evaluation fields (0: per workload)")
     ap.add_argument("--train-steps", type=int, default=0, help="Adam steps (0: per workload)")
@@ -104,9 +105,9 @@ def learned_bench(a):
     import torch
     from paper_1810_00188_amd import inputs, learned, rmc
 
-    cfg = {"channel64": dict(gen=inputs.channel64, train=8, eval=4, steps=1500, cells=16384, batch=64,
+    cfg = {"channel64": dict(gen=inputs.channel64, train=8, eval=4, steps=3000, cells=16384, batch=64,
                              Rs=(16, 32, 64, 128)),
-           "dns256": dict(gen=inputs.dns256, train=12, eval=6, steps=1500, cells=32768, batch=16,
+           "dns256": dict(gen=inputs.dns256, train=12, eval=6, steps=5000, cells=32768, batch=16,
                           Rs=(16, 32, 64, 128))}[a.learned]
     n_train = a.train_seeds or cfg["train"]
     n_eval = a.eval_seeds or cfg["eval"]
@@ -124,17 +125,16 @@ def learned_bench(a):
         w = w0 if k == 1 else cfg["gen"](field_seed=k)
         s.set_temperature(np.ascontiguousarray(w.T, dtype=np.float32))
         s.set_species(np.ascontiguousarray(w.X, dtype=np.float32))
-        s.set_options(rmc.default_options(rays_per_cell=w.R, seed=w.seed, snapshot=k, tol=w.tol,
+        s.set_options(rmc.default_options(rays_per_cell=a.train_rays or w.R, seed=w.seed, snapshot=k, tol=w.tol,
                                           max_steps=w.max_steps, march=rmc.F32, mix_eps=eps))
         cells = np.sort(rng.choice(w.ncells, min(cfg["cells"], w.ncells), replace=False))
         runs.append(learned.plain_samples(s, cells))
         feats.append(runs[-1].feat.cpu().numpy())
-        say(f"training field {k}: {len(cells)} cells x {w.R} rays")
+        say(f"training field {k}: {len(cells)} cells x {s.R} rays")
     mu, sd = learned.standardisation(feats, kd)
     s.set_allocator(learned.init_params(0), mu, sd, nu_c, gx)
     t_train = time.perf_counter()
-    cost = None if a.no_cost else learned.pair_costs(runs, kd.nb * kd.ng)
-    losses = learned.train(s, runs, steps, lr, cfg["batch"], log=say, cost=cost)
+    losses = learned.train(s, runs, steps, lr, cfg["batch"], log=say, use_cost=not a.no_cost)
     t_train = time.perf_counter() - t_train
     params = s.get_allocator()
     del runs

@@ -278,8 +278,8 @@ rmc_status rmc_get_ray_draws(rmc_ctx *ctx, const int64_t *cells, int ncell, int3
  * came from; nsamp rays drawn with that plain pdf, sorted by cell: ray i belongs to cell
  * cell_of[i] (0 <= cell_of < ncell, non-decreasing), lies in stratum[i] = (n*ng + g)*8 + o,
  * and has h[i] = Y_i p0_i (its value times the probability p0[i] it was drawn with).  At most
- * 1024 rays per cell.  cost[nb * ng] (nullable): the cost of a ray of each (n, g), for
- * instance its mean number of steps plus a fixed overhead. */
+ * 1024 rays per cell.  ray_cost[nsamp] (nullable): the cost of each ray, for instance its
+ * number of steps plus a fixed overhead. */
 typedef struct {
     int32_t ncell, nsamp;
     const float *feat;
@@ -287,17 +287,18 @@ typedef struct {
     const double *pplain;
     const int32_t *cell_of, *stratum;
     const double *h, *p0;
-    const double *cost;
+    const double *ray_cost;
 } rmc_train_batch;
 
 /* Loss of the batch under the current parameters and its gradient (host float
  * grad[RMC_MLP_PARAMS], nullable), from the FP32 training kernels.  The loss is averaged over
- * the cells with samples; for cell c
- *   L_c = [mean_i h_i^2 / (p0_i p_c(s_i))] C(p_c) / ([mean_i (h_i / p0_i)^2] C(p_plain / 8)),
- * C(p) = sum_s p_s cost(n, g) (1 without a cost): the second moment of the cell's estimator
- * were its rays drawn from p_c (an unbiased estimate from the plain rays) times the expected
- * cost of a ray, relative to the plain allocation's.  Its minimiser over pdfs is p_s
- * proportional to sqrt(E[h^2 | s] / cost_s): the allocation that reaches a given variance in
+ * the cells with samples; for cell c, i over its rays,
+ *   L_c = [mean_i h_i^2 / (p0_i p_c(s_i))] [mean_i c_i p_c(s_i) / p0_i]
+ *         / ([mean_i (h_i / p0_i)^2] [mean_i c_i])
+ * (the cost factors are 1 without ray_cost): the second moment of the cell's estimator were
+ * its rays drawn from p_c times the expected cost of a ray, both estimated without bias from
+ * the plain rays, relative to the plain allocation's.  Its minimiser over pdfs is p_s
+ * proportional to sqrt(E[h^2 | s] / E[c | s]): the allocation that reaches a given variance in
  * the least time.  Synchronises.  RMC_INVALID_ARG if the samples are not sorted by cell. */
 rmc_status rmc_train_grad(rmc_ctx *ctx, const rmc_train_batch *batch, double *loss, float *grad, void *stream);
 /* One Adam step (Kingma & Ba; beta 0.9 / 0.999, eps 1e-8) of learning rate lr on the batch;

@@ -14,16 +14,17 @@ Model (one evaluation per cell and (n, g), eight octant logits each):
     network sees octants in a frame oriented by the local temperature gradient
     q_c = softmax over all (n, g, o);  p_c = (1 - eps) q_c + eps p_plain(n, g) / 8
 
-Training objective per cell, from rays i drawn with the plain pdf p0 (value Y_i = h_i / p0_i):
-    M_c(p) = mean_i h_i^2 / (p0_i p_{s_i})
-an unbiased estimate of sum_s E[h^2 | s] / p_s, the second moment of the cell's estimator
-when its rays are drawn from p, which is minimised over pdfs by p_s proportional to
-sqrt(E[h^2 | s]).  It is divided by the plain second moment mean_i (h_i / p0_i)^2 so every
-cell weighs equally.  With a per-(n, g) ray cost c (for instance the mean number of steps of
-its rays), the objective is the work-normalised second moment
-    L_c(p) = M_c(p) C(p) / (M_c(p0) C(p0)),   C(p) = sum_s p_s c_s,
-whose minimiser over pdfs is p_s proportional to sqrt(E[h^2 | s] / c_s) (Cauchy-Schwarz):
-the allocation that reaches a given variance in the least time.
+Training objective, from rays i drawn with the plain pdf p0 (value Y_i = h_i / p0_i), for a
+batch of cells c:
+    M_c(p) = mean_{i in c} h_i^2 / (p0_i p_c(s_i))       (an unbiased estimate of E[Y^2] under p_c)
+    C_c(p) = mean_{i in c} c_i p_c(s_i) / p0_i            (of the expected cost of a ray, c_i = 1
+                                                          without costs)
+    L(p)   = [sum_c M_c(p)] [sum_c C_c(p)] / ([sum_c M_c(p0)] [sum_c C_c(p0)]).
+With R rays per cell the squared error of the field is sum_c Var_c / R and the work is
+R sum_c C_c, so L is the work to reach a given RMS error relative to the plain allocation
+(E[Y^2] and Var differ by the squared mean, which no unbiased allocation changes).  For one
+cell the minimiser over pdfs is p_s proportional to sqrt(E[h^2 | s] / E[c | s])
+(Cauchy-Schwarz).
 """
 from __future__ import annotations
 
@@ -172,11 +173,9 @@ def cell_pdf(zg: np.ndarray, p_plain: np.ndarray, eps: float) -> np.ndarray:
     return (1.0 - eps) * q + eps * (p_plain[None, :, :, None] / 8.0)
 
 
-def allocation_loss(zg, p_plain, eps, cell_of, strata, h, p0, cost=None):
-    """Relative (work-normalised, with cost) second moment, averaged over cells: for each cell c
-    L_c = [mean_i h_i^2 / (p0_i p_c(s_i))] C(p_c) / ([mean_i (h_i / p0_i)^2] C(p_plain / 8)),
-    i over its sampled rays, C(p) = sum_s p_s cost(s) (cost per (n, g) pair, or 1).
-    Returns (mean_c L_c, dL/dzg)."""
+def allocation_loss(zg, p_plain, eps, cell_of, strata, h, p0, ray_cost=None):
+    """L = [sum_c M_c(p)] [sum_c C_c(p)] / ([sum_c M_c(p0)] [sum_c C_c(p0)]) over the cells with
+    samples (the cost factors are dropped without ray_cost).  Returns (L, dL/dzg)."""
     nc = zg.shape[0]
     shp = zg.shape
     flat = zg.reshape(nc, -1)
@@ -184,23 +183,27 @@ def allocation_loss(zg, p_plain, eps, cell_of, strata, h, p0, cost=None):
     sig = e / e.sum(axis=1, keepdims=True)
     pp = np.repeat(p_plain.reshape(-1), 8) / 8.0
     p = (1.0 - eps) * sig + eps * pp[None, :]
-    cs = np.ones(flat.shape[1]) if cost is None else np.repeat(np.asarray(cost, dtype=np.float64).reshape(-1), 8)
-    C = p @ cs                                                              # [nc]
-    C0 = pp @ cs
+    c = np.ones(len(h)) if ray_cost is None else np.asarray(ray_cost, dtype=np.float64)
     cnt = np.bincount(cell_of, minlength=nc).astype(float)
-    v0 = np.bincount(cell_of, weights=(h / p0) ** 2, minlength=nc) / np.maximum(cnt, 1)
-    ok = (cnt > 0) & (v0 > 0)
-    scale = np.where(ok, 1.0 / np.maximum(cnt * v0 * C0, 1e-300), 0.0)    # 1 / (N_c V0_c C0)
+    inv = np.where(cnt > 0, 1.0 / np.maximum(cnt, 1), 0.0)
     ps = p[cell_of, strata]
     num = h ** 2 / (p0 * ps)
-    Msum = np.bincount(cell_of, weights=num, minlength=nc)                 # N_c M_c
-    Lc = Msum * C * scale
-    G = np.zeros_like(p)                                                   # dL_c / dp_s
-    np.add.at(G, (cell_of, strata), -num / ps * (C * scale)[cell_of])
-    G += (Msum * scale)[:, None] * cs[None, :]
+    Mt = (np.bincount(cell_of, weights=num, minlength=nc) * inv).sum()
+    M0 = (np.bincount(cell_of, weights=(h / p0) ** 2, minlength=nc) * inv).sum()
+    if ray_cost is None:
+        Ct = C0 = 1.0
+    else:
+        Ct = (np.bincount(cell_of, weights=c * ps / p0, minlength=nc) * inv).sum()
+        C0 = (np.bincount(cell_of, weights=c, minlength=nc) * inv).sum()
+    if not (M0 > 0 and C0 > 0):
+        return 0.0, np.zeros(shp)
+    L = Mt * Ct / (M0 * C0)
+    G = np.zeros_like(p)                                                   # dL / dp_{c,s}
+    np.add.at(G, (cell_of, strata), -num / ps * inv[cell_of] * Ct / (M0 * C0))
+    if ray_cost is not None:
+        np.add.at(G, (cell_of, strata), c / p0 * inv[cell_of] * Mt / (M0 * C0))
     dz = (1.0 - eps) * sig * (G - (G * sig).sum(axis=1, keepdims=True))
-    nval = max(int(ok.sum()), 1)
-    return Lc[ok].sum() / nval, (dz / nval).reshape(shp)
+    return L, dz.reshape(shp)
 
 
 def adam_step(v, g, m, s, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):

@@ -72,11 +72,13 @@ class RunSamples:
     p0: object
     ncell: int
     R: int
-    steps: np.ndarray = None    # host: step count of every ray
+    cost: object = None         # device: cost of every ray (steps + a fixed overhead)
 
 
-def plain_samples(s: rmc.Solver, cells: np.ndarray) -> RunSamples:
-    """Rays of the listed cells under the solver's current fields and plain sampling."""
+def plain_samples(s: rmc.Solver, cells: np.ndarray, overhead: float = 5.0) -> RunSamples:
+    """Rays of the listed cells under the solver's current fields and plain sampling; the cost
+    of a ray is its number of steps plus `overhead` (allocation, set-up and reduction of a
+    ray, in step equivalents)."""
     import torch
     dev = torch.device("cuda", s.device)
     rec = s.trace(cells)
@@ -89,25 +91,10 @@ def plain_samples(s: rmc.Solver, cells: np.ndarray) -> RunSamples:
     T = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(device=dev, dtype=dt)  # noqa: E731
     return RunSamples(T(feat[cells], torch.float32), T(mask[cells], torch.uint8), T(p.ravel(), torch.float64),
                       T(strata, torch.int32), T(h, torch.float64), T(p0, torch.float64), len(cells), s.R,
-                      rec["steps"].ravel().astype(np.float64))
+                      T(rec["steps"].ravel().astype(np.float64) + overhead, torch.float64))
 
 
-def pair_costs(runs: List[RunSamples], P: int, overhead: float = 5.0) -> np.ndarray:
-    """Cost of a ray of each (n, g): its mean number of steps in the training rays plus a fixed
-    overhead (allocation, set-up and reduction of a ray, in step equivalents); pairs never
-    sampled get the largest cost."""
-    tot = np.zeros(P)
-    cnt = np.zeros(P)
-    for r in runs:
-        pair = r.strata.cpu().numpy() >> 3
-        tot += np.bincount(pair, weights=r.steps, minlength=P)
-        cnt += np.bincount(pair, minlength=P)
-    c = np.where(cnt > 0, tot / np.maximum(cnt, 1), np.nan)
-    c = np.where(np.isnan(c), np.nanmax(c), c)
-    return c + overhead
-
-
-def batch_of(run: RunSamples, sel: np.ndarray, cost=None):
+def batch_of(run: RunSamples, sel: np.ndarray, use_cost: bool = True):
     """TrainBatch of the selected cells (indices into the run, sorted) and its keep-alive list."""
     import torch
     dev = run.feat.device
@@ -116,26 +103,23 @@ def batch_of(run: RunSamples, sel: np.ndarray, cost=None):
     cell_of = torch.arange(len(sel), device=dev, dtype=torch.int32).repeat_interleave(run.R)
     return rmc.train_batch(run.feat[sel_t].contiguous(), run.mask[sel_t].contiguous(), run.pplain,
                            cell_of.contiguous(), run.strata[ridx].contiguous(), run.h[ridx].contiguous(),
-                           run.p0[ridx].contiguous(), cost=cost)
+                           run.p0[ridx].contiguous(),
+                           ray_cost=run.cost[ridx].contiguous() if use_cost else None)
 
 
 def train(s: rmc.Solver, runs: List[RunSamples], steps: int, lr: float, batch_cells: int, seed: int = 0,
           log: Optional[Callable[[str], None]] = None, lr_final: Optional[float] = None,
-          cost: Optional[np.ndarray] = None) -> List[float]:
+          use_cost: bool = True) -> List[float]:
     """Adam steps on batches of cells drawn from the runs in turn; the learning rate decays
-    geometrically to lr_final (default lr / 10).  With a per-(n, g) ray cost the loss is the
-    work-normalised second moment.  Returns the batch losses."""
+    geometrically to lr_final (default lr / 10).  With use_cost the loss is the
+    work-normalised second moment (the rays' costs weigh in).  Returns the batch losses."""
     rng = np.random.default_rng(seed)
-    cost_t = None
-    if cost is not None:
-        import torch
-        cost_t = torch.from_numpy(np.ascontiguousarray(cost, dtype=np.float64)).to(runs[0].feat.device)
     lr_final = lr / 10.0 if lr_final is None else lr_final
     losses = []
     for t in range(steps):
         run = runs[t % len(runs)]
         sel = np.sort(rng.choice(run.ncell, min(batch_cells, run.ncell), replace=False))
-        batch, keep = batch_of(run, sel, cost_t)
+        batch, keep = batch_of(run, sel, use_cost)
         a = lr * (lr_final / lr) ** (t / max(steps - 1, 1))
         losses.append(s.train_step(batch, a))
         if log and (t % max(steps // 10, 1) == 0 or t == steps - 1):

@@ -58,7 +58,7 @@ class RayRecord(C.Structure):
 class TrainBatch(C.Structure):
     _fields_ = [("ncell", C.c_int32), ("nsamp", C.c_int32), ("feat", C.c_void_p), ("mask", C.c_void_p),
                 ("pplain", C.c_void_p), ("cell_of", C.c_void_p), ("stratum", C.c_void_p),
-                ("h", C.c_void_p), ("p0", C.c_void_p), ("cost", C.c_void_p)]
+                ("h", C.c_void_p), ("p0", C.c_void_p), ("ray_cost", C.c_void_p)]
 
 
 RAY_DTYPE = np.dtype([("Y", "f8"), ("p", "f8"), ("n", "i4"), ("g", "i4"), ("o", "i4"),
@@ -375,18 +375,18 @@ class Solver:
         return {"xcd_span": o.xcd_span, "length_sort": o.length_sort}
 
 
-def train_batch(feat, mask, pplain, cell_of, stratum, h, p0, cost=None):
+def train_batch(feat, mask, pplain, cell_of, stratum, h, p0, ray_cost=None):
     """A TrainBatch over device tensors (feat float32 [ncell, 3], mask uint8 [ncell], pplain
     float64 [nb*ng], cell_of / stratum int32 [nsamp] sorted by cell, h / p0 float64 [nsamp],
-    cost float64 [nb*ng] or None); returns (batch, keep-alive list)."""
+    ray_cost float64 [nsamp] or None); returns (batch, keep-alive list)."""
     import torch
-    ts = [feat, mask, pplain, cell_of, stratum, h, p0] + ([cost] if cost is not None else [])
+    ts = [feat, mask, pplain, cell_of, stratum, h, p0] + ([ray_cost] if ray_cost is not None else [])
     want = [torch.float32, torch.uint8, torch.float64, torch.int32, torch.int32, torch.float64, torch.float64,
             torch.float64]
     for t, d in zip(ts, want):
         if not (t.is_cuda and t.dtype == d and t.is_contiguous()):
             raise ValueError("training batch tensors: contiguous device tensors of the documented dtypes")
-    ptrs = [t.data_ptr() for t in ts] + ([None] if cost is None else [])
+    ptrs = [t.data_ptr() for t in ts] + ([None] if ray_cost is None else [])
     b = TrainBatch(int(feat.shape[0]), int(cell_of.shape[0]), *ptrs)
     return b, ts
 

@@ -196,14 +196,14 @@ def test_training_gradient_matches_oracle(with_cost):
     s.set_allocator(params, mu, sd, nu_c, gx)
     tens, H = _training_batch(w, s, ncell=40)
     kd = w.kd
-    cost = np.random.default_rng(2).uniform(2.0, 40.0, (kd.nb, kd.ng)) if with_cost else None
-    ct = torch.from_numpy(cost.ravel()).to("cuda:0") if with_cost else None
-    batch, keep = rmc.train_batch(*tens, cost=ct)
+    cost = np.random.default_rng(2).uniform(2.0, 40.0, len(H["h"])) if with_cost else None
+    ct = torch.from_numpy(cost).to("cuda:0") if with_cost else None
+    batch, keep = rmc.train_batch(*tens, ray_cost=ct)
     loss_g, grad_g = s.train_grad(batch)
     p, x, z, cache = _oracle_logits(w, params, mu, sd, H["feat"], H["mask"])
     zg = mlp.octant_logits(z, H["mask"])
     L, dzg = mlp.allocation_loss(zg, H["pplain"].reshape(kd.nb, kd.ng), eps, H["cell_of"], H["strata"], H["h"],
-                                 H["p0"], cost=cost)
+                                 H["p0"], ray_cost=cost)
     dz = mlp.octant_logits(dzg, H["mask"])
     g = mlp.flatten(mlp.backward(p, cache, dz))
     rel = np.linalg.norm(grad_g - g) / np.linalg.norm(g)

@@ -89,35 +89,36 @@ def test_cost_loss_gradient_matches_finite_differences():
     zg = rng.normal(size=(nc, nb, ng, 8))
     p_plain = rng.uniform(0.2, 1.0, (nb, ng))
     p_plain /= p_plain.sum()
-    cost = rng.uniform(1.0, 30.0, (nb, ng))
     cell_of = np.sort(rng.integers(0, nc, 40))
     strata = rng.integers(0, nb * ng * 8, 40)
     h = rng.normal(size=40)
     p0 = rng.uniform(0.01, 0.2, 40)
-    L, dz = mlp.allocation_loss(zg, p_plain, 0.1, cell_of, strata, h, p0, cost=cost)
+    cost = rng.uniform(1.0, 30.0, 40)
+    L, dz = mlp.allocation_loss(zg, p_plain, 0.1, cell_of, strata, h, p0, ray_cost=cost)
     v = zg.ravel()
     for q in rng.choice(v.size, 60, replace=False):
         a, b = v.copy(), v.copy()
         a[q] += 1e-6
         b[q] -= 1e-6
-        fd = (mlp.allocation_loss(a.reshape(zg.shape), p_plain, 0.1, cell_of, strata, h, p0, cost=cost)[0]
-              - mlp.allocation_loss(b.reshape(zg.shape), p_plain, 0.1, cell_of, strata, h, p0, cost=cost)[0]) / 2e-6
+        fd = (mlp.allocation_loss(a.reshape(zg.shape), p_plain, 0.1, cell_of, strata, h, p0, ray_cost=cost)[0]
+              - mlp.allocation_loss(b.reshape(zg.shape), p_plain, 0.1, cell_of, strata, h, p0, ray_cost=cost)[0]) / 2e-6
         assert abs(fd - dz.ravel()[q]) <= 1e-6 * (1 + abs(fd))
-    # a unit cost is the plain second moment
-    L1, d1 = mlp.allocation_loss(zg, p_plain, 0.1, cell_of, strata, h, p0, cost=np.ones((nb, ng)))
-    L2, d2 = mlp.allocation_loss(zg, p_plain, 0.1, cell_of, strata, h, p0)
-    assert abs(L1 - L2) < 1e-14 * abs(L2) and np.allclose(d1, d2, rtol=1e-12, atol=1e-16)
+    # rays drawn with the plain pdf and p = p_plain / 8 (eps = 1): the cost factor is exactly 1
+    pr = np.repeat(p_plain.ravel(), 8)[strata] / 8.0
+    L1, _ = mlp.allocation_loss(zg, p_plain, 1.0, cell_of, strata, h, pr, ray_cost=cost)
+    L2, _ = mlp.allocation_loss(zg, p_plain, 1.0, cell_of, strata, h, pr)
+    assert abs(L1 - L2) < 1e-12 * abs(L2)
 
 
 def test_cost_loss_minimiser_is_work_normalised():
-    """With exact expectations, the minimiser of second moment x expected cost is
-    p_s = sqrt(H_s / c_s) / sum sqrt(H / c) (Cauchy-Schwarz)."""
+    """With every stratum observed once per cell (exact expectations H_s and costs c_s), the
+    minimiser of second moment x expected cost is p_s = sqrt(H_s / c_s) / sum sqrt(H / c)
+    (Cauchy-Schwarz)."""
     nb, ng = 2, 2
     S = nb * ng * 8
     rng = np.random.default_rng(6)
     H = rng.uniform(0.01, 4.0, S)
-    cost = rng.uniform(1.0, 20.0, (nb, ng))
-    cs = np.repeat(cost.ravel(), 8)
+    cs = rng.uniform(1.0, 20.0, S)
     p_plain = np.full((nb, ng), 1.0 / (nb * ng))
     strata = np.arange(S)
     p0 = np.full(S, 1.0 / S)
@@ -127,12 +128,32 @@ def test_cost_loss_minimiser_is_work_normalised():
     m = np.zeros_like(z)
     s2 = np.zeros_like(z)
     for t in range(1, 8001):
-        L, dz = mlp.allocation_loss(z, p_plain, 0.0, cell_of, strata, h, p0, cost=cost)
+        L, dz = mlp.allocation_loss(z, p_plain, 0.0, cell_of, strata, h, p0, ray_cost=cs)
         v, m, s2 = mlp.adam_step(z.ravel(), dz.ravel(), m.ravel(), s2.ravel(), t, lr=0.02)
         z, m, s2 = v.reshape(z.shape), m.reshape(z.shape), s2.reshape(z.shape)
     p = mlp.cell_pdf(z, p_plain, 0.0).ravel()
     target = np.sqrt(H / cs) / np.sqrt(H / cs).sum()
     np.testing.assert_allclose(p, target, rtol=3e-3)
+
+
+def test_batch_objective_is_invariant_to_copies():
+    """The objective is a ratio of batch totals: a batch of identical copies of one cell has
+    the cell's value, and each copy receives the cell's gradient divided by the number of
+    copies."""
+    rng = np.random.default_rng(13)
+    nb, ng, k = 2, 3, 4
+    zg1 = rng.normal(size=(1, nb, ng, 8))
+    p_plain = rng.uniform(0.2, 1.0, (nb, ng))
+    p_plain /= p_plain.sum()
+    strata = rng.integers(0, nb * ng * 8, 12)
+    h = rng.normal(size=12)
+    p0 = rng.uniform(0.01, 0.2, 12)
+    cost = rng.uniform(1.0, 30.0, 12)
+    L1, d1 = mlp.allocation_loss(zg1, p_plain, 0.1, np.zeros(12, int), strata, h, p0, ray_cost=cost)
+    Lk, dk = mlp.allocation_loss(np.repeat(zg1, k, axis=0), p_plain, 0.1, np.repeat(np.arange(k), 12),
+                                 np.tile(strata, k), np.tile(h, k), np.tile(p0, k), ray_cost=np.tile(cost, k))
+    assert abs(Lk - L1) < 1e-13 * abs(L1)
+    np.testing.assert_allclose(dk, np.repeat(d1 / k, k, axis=0), rtol=1e-12, atol=1e-18)
 
 
 def test_octant_frame_and_pdf_normalisation():
