@@ -106,9 +106,9 @@ def learned_bench(a):
     from paper_1810_00188_amd import inputs, learned, rmc
 
     cfg = {"channel64": dict(gen=inputs.channel64, train=8, eval=4, steps=3000, cells=16384, batch=64,
-                             Rs=(16, 32, 64, 128)),
+                             rays=0, Rs=(16, 32, 64, 128)),
            "dns256": dict(gen=inputs.dns256, train=12, eval=6, steps=5000, cells=32768, batch=16,
-                          Rs=(16, 32, 64, 128))}[a.learned]
+                          rays=255, Rs=(16, 32, 64, 128))}[a.learned]
     n_train = a.train_seeds or cfg["train"]
     n_eval = a.eval_seeds or cfg["eval"]
     steps = a.train_steps or cfg["steps"]
@@ -125,7 +125,7 @@ def learned_bench(a):
         w = w0 if k == 1 else cfg["gen"](field_seed=k)
         s.set_temperature(np.ascontiguousarray(w.T, dtype=np.float32))
         s.set_species(np.ascontiguousarray(w.X, dtype=np.float32))
-        s.set_options(rmc.default_options(rays_per_cell=a.train_rays or w.R, seed=w.seed, snapshot=k, tol=w.tol,
+        s.set_options(rmc.default_options(rays_per_cell=a.train_rays or cfg["rays"] or w.R, seed=w.seed, snapshot=k, tol=w.tol,
                                           max_steps=w.max_steps, march=rmc.F32, mix_eps=eps))
         cells = np.sort(rng.choice(w.ncells, min(cfg["cells"], w.ncells), replace=False))
         runs.append(learned.plain_samples(s, cells))
@@ -159,6 +159,7 @@ def learned_bench(a):
         "n_gpus": 1, "dtype": "f32", "data": "synthetic", "vs_baseline": None,
         "config": {"workload": w0.name, "grid": [w0.nx, w0.ny, w0.nz], "bands": kd.nb, "g_points": kd.ng,
                    "train_fields": n_train, "train_cells_per_field": cfg["cells"], "train_steps": steps,
+                   "train_rays_per_cell": a.train_rays or cfg["rays"] or w0.R,
                    "batch_cells": cfg["batch"], "mix_eps": eps, "R": list(cfg["Rs"]),
                    "loss": "second moment" if a.no_cost else "second moment x ray cost",
                    "reference_rays_per_cell": results[0]["ref_rays_per_cell"]},
