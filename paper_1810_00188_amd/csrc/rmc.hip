@@ -400,8 +400,10 @@ __global__ void __launch_bounds__(256) k_fields(const double *__restrict__ T, co
 // ------------------------------------------------------------- allocation and buckets
 // Rays of one tile: cells [tile_begin.., +tile_cells) of the brick-linear order, all R rays
 // of each cell in one pass of the block (cells_per_pass = blockDim / R).
+constexpr int kAllocThreads = 1024;   // threads per tile: R rays of 1024 / R cells per pass
+
 template <int SM>
-__global__ void __launch_bounds__(256) k_alloc_count(AllocArgs A)
+__global__ void __launch_bounds__(kAllocThreads) k_alloc_count(AllocArgs A)
 {
     extern __shared__ uint32_t lh[];   // [nbucket]
     const int tile = blockIdx.x;
@@ -489,9 +491,9 @@ __global__ void k_chunk_map(const uint32_t *total, const uint32_t *start, int nb
 }
 
 template <int SM>
-__global__ void __launch_bounds__(256) k_alloc_scatter(AllocArgs A)
+__global__ void __launch_bounds__(kAllocThreads) k_alloc_scatter(AllocArgs A)
 {
-    extern __shared__ uint32_t lb[];   // [nbucket] next free position, then [256] bucket of each thread
+    extern __shared__ uint32_t lb[];   // [nbucket] next free position, then [blockDim] bucket of each thread
     uint32_t *sb = lb + A.nbucket;
     const int tile = blockIdx.x;
     for (int b = threadIdx.x; b < A.nbucket; b += blockDim.x)
@@ -1029,7 +1031,7 @@ __device__ __forceinline__ int red_pad(int q) { return q + (q >> 5); }
 template <class Real>
 __global__ void __launch_bounds__(256) k_reduce(const void *__restrict__ Yv, const uint32_t *__restrict__ st,
                                                 uint64_t nc, int R, int accum, double *__restrict__ divq,
-                                                double *__restrict__ se, unsigned long long *counters)
+                                                double *__restrict__ se, unsigned long long *part)
 {
     __shared__ Real ys[kRedVals + kRedVals / 32];
     __shared__ uint32_t ss[kRedVals + kRedVals / 32];
@@ -1089,14 +1091,44 @@ __global__ void __launch_bounds__(256) k_reduce(const void *__restrict__ Yv, con
         }
         __syncthreads();
     }
+    // the workgroup's step and capped-ray counts, summed later in block order (one counter
+    // updated by every wavefront would serialise them)
     for (int off = 32; off > 0; off >>= 1) {
         steps += __shfl_xor(steps, off);
         capped += __shfl_xor(capped, off);
     }
-    if ((threadIdx.x & 63) == 0 && (steps | capped)) {
-        atomicAdd(counters, steps);
-        atomicAdd(counters + 1, capped);
-        atomicAdd(counters + 2, steps);
+    __shared__ unsigned long long wsum[2][4];
+    if ((threadIdx.x & 63) == 0) {
+        wsum[0][threadIdx.x >> 6] = steps;
+        wsum[1][threadIdx.x >> 6] = capped;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long a = 0, b = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) { a += wsum[0][w]; b += wsum[1][w]; }
+        part[2 * blockIdx.x] = a;
+        part[2 * blockIdx.x + 1] = b;
+    }
+}
+
+// sums of the reduction's per-workgroup counts into the compute's counters (one workgroup)
+__global__ void __launch_bounds__(256) k_reduce_counts(const unsigned long long *__restrict__ part, int nblk,
+                                                       unsigned long long *counters)
+{
+    __shared__ unsigned long long sa[256], sb[256];
+    unsigned long long a = 0, b = 0;
+    for (int q = threadIdx.x; q < nblk; q += blockDim.x) { a += part[2 * q]; b += part[2 * q + 1]; }
+    sa[threadIdx.x] = a;
+    sb[threadIdx.x] = b;
+    __syncthreads();
+    for (int w = blockDim.x >> 1; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) { sa[threadIdx.x] += sa[threadIdx.x + w]; sb[threadIdx.x] += sb[threadIdx.x + w]; }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        counters[0] += sa[0];
+        counters[1] += sb[0];
+        counters[2] += sa[0];
     }
 }
 
@@ -1210,7 +1242,7 @@ struct rmc_ctx {
     DBuf Y, st;
     int slots_R = 0, slots_real = 0;
     // shared pipeline workspace (used when this context leads a batch)
-    DBuf hist, bucket_total, bucket_start, nchunks, chunk_bucket, items, faces, snaps, tile_snap, counters,
+    DBuf hist, bucket_total, bucket_start, nchunks, chunk_bucket, items, faces, snaps, tile_snap, counters, red_part,
         outbuf, tune_out;
     DBuf trace_rec, trace_cells, border, kmin, cont, cont_count;
     std::vector<float> h_kmin;
@@ -1662,6 +1694,7 @@ template <class Real> rmc_status plan_pipeline(rmc_ctx *const *ctxs, int nsnap, 
         (st = L->snaps.ensure(sizeof(SnapDesc) * nsnap)) || (st = L->tile_snap.ensure(sizeof(int) * P.ntiles)) ||
         (st = L->border.ensure(sizeof(uint32_t) * nbucket)) ||
         (st = L->counters.ensure(sizeof(unsigned long long) * 4)) ||
+        (st = L->red_part.ensure(sizeof(unsigned long long) * 2 * 2048)) ||
         (st = L->kmin.ensure(sizeof(float) * nb * ng)) || (st = L->cont_count.ensure(sizeof(uint32_t))))
         return st;
     P.cont_cap = (uint32_t)std::min<uint64_t>(P.total_cells * R, 1u << 20);
@@ -1719,10 +1752,12 @@ rmc_status enqueue_pipeline(const Plan &P, double *const *divq, double *const *s
     AA.bucket_start = L->bucket_start.as<uint32_t>();
     AA.items = L->items.as<uint4>();
     const size_t lds_count = sizeof(uint32_t) * nbucket;
-    const size_t lds_scatter = sizeof(uint32_t) * (nbucket + 256);
-    if (P.smode == 2) hipLaunchKernelGGL(k_alloc_count<2>, dim3(P.ntiles), dim3(256), lds_count, s, AA);
-    else if (P.smode == 1) hipLaunchKernelGGL(k_alloc_count<1>, dim3(P.ntiles), dim3(256), lds_count, s, AA);
-    else hipLaunchKernelGGL(k_alloc_count<0>, dim3(P.ntiles), dim3(256), lds_count, s, AA);
+    // 1024 threads per tile unless the bucket counters and the per-thread buckets overflow 64 KiB
+    const int at = sizeof(uint32_t) * (nbucket + kAllocThreads) <= 64 * 1024 ? kAllocThreads : 256;
+    const size_t lds_scatter = sizeof(uint32_t) * (nbucket + at);
+    if (P.smode == 2) hipLaunchKernelGGL(k_alloc_count<2>, dim3(P.ntiles), dim3(at), lds_count, s, AA);
+    else if (P.smode == 1) hipLaunchKernelGGL(k_alloc_count<1>, dim3(P.ntiles), dim3(at), lds_count, s, AA);
+    else hipLaunchKernelGGL(k_alloc_count<0>, dim3(P.ntiles), dim3(at), lds_count, s, AA);
     HIPCHK(hipGetLastError());
     hipLaunchKernelGGL(k_bucket_scan, dim3(nbucket), dim3(64), 0, s, L->hist.as<uint32_t>(), P.ntiles,
                        L->bucket_total.as<uint32_t>());
@@ -1734,9 +1769,9 @@ rmc_status enqueue_pipeline(const Plan &P, double *const *divq, double *const *s
                        L->bucket_start.as<uint32_t>(), nbucket, L->chunk_bucket.as<uint32_t>(),
                        L->items.as<uint4>());
     HIPCHK(hipGetLastError());
-    if (P.smode == 2) hipLaunchKernelGGL(k_alloc_scatter<2>, dim3(P.ntiles), dim3(256), lds_scatter, s, AA);
-    else if (P.smode == 1) hipLaunchKernelGGL(k_alloc_scatter<1>, dim3(P.ntiles), dim3(256), lds_scatter, s, AA);
-    else hipLaunchKernelGGL(k_alloc_scatter<0>, dim3(P.ntiles), dim3(256), lds_scatter, s, AA);
+    if (P.smode == 2) hipLaunchKernelGGL(k_alloc_scatter<2>, dim3(P.ntiles), dim3(at), lds_scatter, s, AA);
+    else if (P.smode == 1) hipLaunchKernelGGL(k_alloc_scatter<1>, dim3(P.ntiles), dim3(at), lds_scatter, s, AA);
+    else hipLaunchKernelGGL(k_alloc_scatter<0>, dim3(P.ntiles), dim3(at), lds_scatter, s, AA);
     HIPCHK(hipGetLastError());
     if (EV) HIPCHK(hipEventRecord(EV->e[2], s));
 
@@ -1812,9 +1847,13 @@ rmc_status enqueue_pipeline(const Plan &P, double *const *divq, double *const *s
         rmc_ctx *c = P.ctxs[q];
         const uint64_t nc = ncells_of(c);
         const uint64_t groups = (nc + (kRedVals / R) - 1) / (kRedVals / R);
-        hipLaunchKernelGGL(k_reduce<Real>, dim3((unsigned)std::min<uint64_t>(groups, 2048)), dim3(256), 0, s,
-                           c->Y.p, sizeof(Real) == 8 ? c->st.as<uint32_t>() : nullptr, nc, R, (int)O.accum, divq[q],
-                           se ? se[q] : nullptr, L->counters.as<unsigned long long>());
+        const int nblk = (int)std::min<uint64_t>(groups, 2048);
+        hipLaunchKernelGGL(k_reduce<Real>, dim3((unsigned)nblk), dim3(256), 0, s, c->Y.p,
+                           sizeof(Real) == 8 ? c->st.as<uint32_t>() : nullptr, nc, R, (int)O.accum, divq[q],
+                           se ? se[q] : nullptr, L->red_part.as<unsigned long long>());
+        HIPCHK(hipGetLastError());
+        hipLaunchKernelGGL(k_reduce_counts, dim3(1), dim3(256), 0, s, L->red_part.as<unsigned long long>(), nblk,
+                           L->counters.as<unsigned long long>());
         HIPCHK(hipGetLastError());
     }
     if (EV) HIPCHK(hipEventRecord(EV->e[5], s));
@@ -1926,7 +1965,7 @@ std::vector<void *> buffer_ptrs(const rmc_ctx *c)
                        &c->ccdf_g, &c->ccdf_o, &c->pdf_scratch, &c->p, &c->cdf_b, &c->cdf_g, &c->W, &c->Iw,
                        &c->status, &c->field, &c->Iplane, &c->Y, &c->st, &c->hist, &c->bucket_total,
                        &c->bucket_start, &c->nchunks, &c->chunk_bucket, &c->items, &c->faces,
-                       &c->snaps, &c->tile_snap, &c->border, &c->counters, &c->kmin, &c->cont, &c->cont_count};
+                       &c->snaps, &c->tile_snap, &c->border, &c->counters, &c->red_part, &c->kmin, &c->cont, &c->cont_count};
     std::vector<void *> v;
     for (const DBuf *d : b) v.push_back(d->p);
     return v;
@@ -2009,7 +2048,7 @@ void rmc_destroy(rmc_ctx *c)
                         &c->ccdf_g, &c->ccdf_o, &c->pdf_scratch, &c->p, &c->cdf_b, &c->cdf_g, &c->W, &c->Iw,
                         &c->status, &c->field, &c->Iplane, &c->Y, &c->st, &c->hist, &c->bucket_total, &c->bucket_start,
                         &c->nchunks, &c->chunk_bucket, &c->items, &c->faces, &c->snaps, &c->tile_snap,
-                        &c->counters, &c->outbuf, &c->tune_out, &c->trace_rec, &c->trace_cells, &c->border, &c->small, &c->scal,
+                        &c->counters, &c->red_part, &c->outbuf, &c->tune_out, &c->trace_rec, &c->trace_cells, &c->border, &c->small, &c->scal,
                         &c->kmin, &c->cont, &c->cont_count};
         for (DBuf *b : bufs) b->release();
         for (auto &set : c->ring)
