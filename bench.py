@@ -45,6 +45,7 @@ def parse():
                     help="consecutive 64-ray chunks each XCD takes in turn (0: library default)")
     ap.add_argument("--length-sort", action="store_true",
                     help="reorder each march workgroup's rays by expected length")
+    ap.add_argument("--bucket-order", type=int, default=0, help="0: longest rays first, 1: band-major")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (the "
                          "reference point that scales rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -195,7 +196,8 @@ def main():
     w = inputs.channel64()
     s = rmc.Solver(0)
     overrides = {k: v for k, v in (("long_ray_steps", a.long_ray_steps), ("xcd_span", a.xcd_span),
-                                   ("length_sort", int(a.length_sort))) if v}
+                                   ("length_sort", int(a.length_sort)),
+                                   ("bucket_order", a.bucket_order)) if v}
     s.set_workload(w, **overrides)
     T = torch.from_numpy(np.ascontiguousarray(w.T, dtype=np.float32)).to(dev)
     X = torch.from_numpy(np.ascontiguousarray(w.X, dtype=np.float32)).to(dev)

@@ -88,7 +88,11 @@ typedef struct {
                                 class of their expected length first, so that a wavefront's rays
                                 end at similar times (fewer idle lanes, less gather coherence);
                                 0 (default): cell order.  Results are the same either way */
-    int32_t reserved[4];     /* must be zero */
+    int32_t bucket_order;    /* march order of the (n, g, octant) buckets: 0 (default) pairs by
+                                increasing kappa(T_max), the longest rays first; 1 band-major, the
+                                g-points of a band together (they share its intensity plane).
+                                Results are the same either way */
+    int32_t reserved[3];     /* must be zero */
 } rmc_options;
 
 typedef struct {

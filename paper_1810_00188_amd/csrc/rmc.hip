@@ -1308,7 +1308,8 @@ rmc_status check_options(const rmc_options *o)
     if (o->xcd_span != 0 && (o->xcd_span < 4 || o->xcd_span > (1 << 20) || (o->xcd_span & (o->xcd_span - 1))))
         return fail(RMC_INVALID_ARG, "xcd_span must be 0 or a power of two in [4, 2^20]");
     if (o->length_sort != 0 && o->length_sort != 1) return fail(RMC_INVALID_ARG, "length_sort must be 0 or 1");
-    for (int q = 0; q < 4; ++q)
+    if (o->bucket_order != 0 && o->bucket_order != 1) return fail(RMC_INVALID_ARG, "bucket_order must be 0 or 1");
+    for (int q = 0; q < 3; ++q)
         if (o->reserved[q] != 0) return fail(RMC_INVALID_ARG, "reserved option fields must be zero");
     return RMC_OK;
 }
@@ -1366,6 +1367,15 @@ void march_order(const rmc_ctx *c, std::vector<uint32_t> &order)
     std::stable_sort(key.begin(), key.end(), [](const std::pair<double, int> &a, const std::pair<double, int> &b) {
         return a.first < b.first;
     });
+    if (c->opt.bucket_order == 1) {
+        // band-major: the g-points of a band next to each other (they share the band's
+        // intensity plane), bands ordered by their smallest kappa
+        std::vector<int> rank(nb, nb * ng);
+        for (int q = 0; q < nb * ng; ++q) rank[key[q].second / ng] = std::min(rank[key[q].second / ng], q);
+        std::stable_sort(key.begin(), key.end(), [&](const std::pair<double, int> &a, const std::pair<double, int> &b) {
+            return rank[a.second / ng] < rank[b.second / ng];
+        });
+    }
     order.resize((size_t)nb * ng * 8);
     for (int q = 0; q < nb * ng; ++q)
         for (int o = 0; o < 8; ++o) order[(size_t)q * 8 + o] = (uint32_t)(key[q].second * 8 + o);

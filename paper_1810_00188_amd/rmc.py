@@ -34,7 +34,7 @@ class Options(C.Structure):
                 ("accum", C.c_int), ("sampling", C.c_int), ("mix_eps", C.c_double),
                 ("block_threads", C.c_int32), ("long_ray_steps", C.c_int32),
                 ("xcd_span", C.c_int32), ("length_sort", C.c_int32),
-                ("reserved", C.c_int32 * 4)]
+                ("bucket_order", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 class Stats(C.Structure):

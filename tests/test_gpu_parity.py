@@ -245,8 +245,8 @@ def test_launch_order_does_not_change_results():
     w = _small_channel(march="f32", nx=24, ny=16, nz=20, R=16)
     say(f"xcd spans {w.name}")
     out = []
-    for span, lsort in ((4, 0), (4, 1), (16, 1), (1024, 0)):
-        s = _solver(w, xcd_span=span, length_sort=lsort)
+    for span, lsort, border in ((4, 0, 0), (4, 1, 0), (16, 1, 1), (1024, 0, 1)):
+        s = _solver(w, xcd_span=span, length_sort=lsort, bucket_order=border)
         dq, se = s.compute()
         Y, S = s.ray_values(np.arange(w.ncells))
         out.append((dq, se, Y, S))
