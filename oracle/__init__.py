@@ -57,6 +57,10 @@ def lib():
                                      C.c_void_p, C.c_int]
         L.orc_march.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
                                 C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
+        L.orc_march_mg.argtypes = L.orc_march.argtypes
+        L.orc_level_count.argtypes = [C.c_int, C.c_int, C.c_int]
+        L.orc_level_count.restype = C.c_int
+        L.orc_coarse_fields.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
         L.orc_max_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -72,7 +76,8 @@ class _Problem(C.Structure):
                 ("dnu", C.c_void_p), ("wg", C.c_void_p), ("k", C.c_void_p), ("Ib", C.c_void_p),
                 ("R", C.c_int), ("seed", C.c_uint64), ("snap", C.c_uint32),
                 ("tol", C.c_double), ("max_steps", C.c_int),
-                ("q_cell", C.c_void_p), ("mix_eps", C.c_double)]
+                ("q_cell", C.c_void_p), ("mix_eps", C.c_double),
+                ("mg_levels", C.c_int), ("mg_steps", C.c_int)]
 
 
 class _MarchOut(C.Structure):
@@ -101,10 +106,12 @@ class Problem:
 
     Any object with the attributes xf, yf, zf, T, X, kd, T_walls, eps_walls, R, seed, snap,
     tol, max_steps works; ``q_cell`` ([ncells, nb, ng, 8]) switches to a per-cell
-    allocation pdf mixed with ``mix_eps`` of the plain one.
+    allocation pdf mixed with ``mix_eps`` of the plain one.  ``mg_levels`` / ``mg_steps``
+    (default: the workload's, else the DNS grid alone) select the multigrid march.
     """
 
-    def __init__(self, w, q_cell: Optional[np.ndarray] = None, mix_eps: float = 0.0):
+    def __init__(self, w, q_cell: Optional[np.ndarray] = None, mix_eps: float = 0.0,
+                 mg_levels: Optional[int] = None, mg_steps: Optional[int] = None):
         kd = w.kd
         self._keep = dict(xf=_f64(w.xf), yf=_f64(w.yf), zf=_f64(w.zf), T=_f64(w.T),
                           X=_f64(np.atleast_2d(w.X)), dnu=_f64(kd.dnu), wg=_f64(kd.wg),
@@ -128,6 +135,8 @@ class Problem:
         s.tol, s.max_steps = float(w.tol), int(w.max_steps)
         s.q_cell = K["q"].ctypes.data if q_cell is not None else None
         s.mix_eps = float(mix_eps)
+        s.mg_levels = int(getattr(w, "mg_levels", 1) if mg_levels is None else mg_levels)
+        s.mg_steps = int(getattr(w, "mg_steps", 5) if mg_steps is None else mg_steps)
         self.s = s
         self.nx, self.ny, self.nz = s.nx, s.ny, s.nz
         self.ncells = s.nx * s.ny * s.nz
@@ -190,24 +199,44 @@ def divergence(prob: Problem, cells=None, nthreads: int = 0):
     return dq, se, st.value
 
 
-def march(prob: Problem, cell_ijk, n: int, g: int, d, record: int = 0):
+def march(prob: Problem, cell_ijk, n: int, g: int, d, record: int = 0, multigrid: bool = False):
     """March one ray of band n, g-point g from the centre of cell (i, j, k) along d.
 
     Returns dict(acc, absacc, steps, end[, cells, ds]) -- the accumulated
-    sum tau alpha (I_c - I_j) (+ wall and residual terms) before the ray weight."""
+    sum tau alpha (I_c - I_j) (+ wall and residual terms) before the ray weight.  With
+    ``multigrid`` the ray takes the multigrid march of the problem's mg_levels / mg_steps and
+    the recorded cells are (level, natural index within that level) pairs."""
     d = _f64(d)
     m = _MarchOut()
     rc = np.zeros(max(record, 1), dtype=np.int64)
     rd = np.zeros(max(record, 1))
     i, j, k = (int(x) for x in cell_ijk)
-    _check(lib().orc_march(prob.ptr, i, j, k, int(n), int(g), d.ctypes.data, C.addressof(m),
-                           rc.ctypes.data if record else None, rd.ctypes.data if record else None,
-                           int(record)))
+    fn = lib().orc_march_mg if multigrid else lib().orc_march
+    _check(fn(prob.ptr, i, j, k, int(n), int(g), d.ctypes.data, C.addressof(m),
+              rc.ctypes.data if record else None, rd.ctypes.data if record else None, int(record)))
     out = dict(acc=m.acc, absacc=m.absacc, steps=m.steps, end=m.end)
     if record:
-        out["cells"] = rc[:min(m.steps, record)]
+        cells = rc[:min(m.steps, record)]
+        if multigrid:
+            out["level"] = (cells >> 48).astype(np.int64)
+            cells = cells & ((1 << 48) - 1)
+        out["cells"] = cells
         out["ds"] = rd[:min(m.steps, record)]
     return out
+
+
+def level_count(nx: int, ny: int, nz: int) -> int:
+    """Number of overlaid grid levels the multigrid march can use on an nx x ny x nz grid."""
+    return int(lib().orc_level_count(int(nx), int(ny), int(nz)))
+
+
+def coarse_fields(prob: Problem, level: int):
+    """(T, X) of grid level ``level``: [ncells_L] and [ns, ncells_L], natural order of the level."""
+    nl = (prob.nx >> level) * (prob.ny >> level) * (prob.nz >> level)
+    T = np.zeros(nl)
+    X = np.zeros((prob.s.ns, nl))
+    _check(lib().orc_coarse_fields(prob.ptr, int(level), T.ctypes.data, X.ctypes.data))
+    return T, X
 
 
 def max_threads() -> int:

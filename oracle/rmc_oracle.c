@@ -45,6 +45,20 @@
  *       and its direction is drawn inside that octant; together isotropic;
  *   R13 if nothing emits at T_max (sum of e_{n,g} is zero) the pdf is uniform over (n,g):
  *       every ray value is then zero and any positive pdf gives that exactly.
+ *
+ * Multigrid march (Sec. 4.3 and the grid counts of Sec. 5), readings:
+ *   M1 levels: coarsening ratio 2 on every axis together; a further level exists while every
+ *      axis of the current level has an even number of cells whose half is at least 3 (this
+ *      reproduces the paper's grid counts: 3 for 16^3, 4 for 32^3, 5 for 48^3 and 64^3, 6 for
+ *      96^3 to 160^3, 7 for 192^3).  Level L has every 2^L-th face of the DNS grid;
+ *   M2 coarse-cell temperature and mole fractions: volume-weighted means over the 2^L x 2^L
+ *      x 2^L DNS cells the coarse cell covers (on uniform spacing this is also the trilinear
+ *      interpolation at the coarse cell centre); properties from the tables at those values;
+ *   M3 a ray takes mg_steps steps on each level (the source cell's step counts on the DNS
+ *      level), then continues from its current point on the next coarser level (the coarse
+ *      cell holding the DNS cell it is in, next-face parameters from that level's faces);
+ *      on the last level it runs to depletion.  Source intensity and source kappa stay the
+ *      DNS cell's; the residual uses the last cell marched, on whatever level.
  */
 #include <math.h>
 #include <stdint.h>
@@ -82,6 +96,8 @@ typedef struct {
     int max_steps;
     const double *q_cell;         /* optional [ncells][nb][ng][8] allocation pdf per cell */
     double mix_eps;               /* weight of the plain pdf mixed into q_cell */
+    int mg_levels;                /* grid levels of the multigrid march (M1); <= 1: DNS grid only */
+    int mg_steps;                 /* steps per level before the next coarser one (M3) */
 } orc_problem;
 
 typedef struct {
@@ -332,6 +348,205 @@ int orc_march(const orc_problem *P, int ci, int cj, int ck, int n, int g, const 
     return ORC_OK;
 }
 
+/* ------------------------------------------- multigrid march (Sec. 4.3, readings M1-M3) */
+#define ORC_MAX_LEV 8
+
+typedef struct {
+    int nlev;
+    int n[ORC_MAX_LEV][3];        /* cells per axis of each level */
+    const double *f[ORC_MAX_LEV][3];  /* face coordinates of each level */
+    const double *T[ORC_MAX_LEV];     /* cell temperatures, natural order of the level */
+    const double *X[ORC_MAX_LEV];     /* [ns][cells of the level] */
+    double *owned[ORC_MAX_LEV][5];    /* coarse-level arrays allocated here */
+} orc_levels;
+
+/* M1: number of levels the grid allows. */
+int orc_level_count(int nx, int ny, int nz)
+{
+    int L = 1;
+    while (L < ORC_MAX_LEV && nx % 2 == 0 && ny % 2 == 0 && nz % 2 == 0 && nx / 2 >= 3 && ny / 2 >= 3 &&
+           nz / 2 >= 3) {
+        nx /= 2; ny /= 2; nz /= 2;
+        ++L;
+    }
+    return L;
+}
+
+/* M2: volume-weighted mean of T and of each mole fraction over the DNS cells of every cell of
+ * level L (written out over the DNS cells, not level by level). */
+static void coarse_fields(const orc_problem *P, int L, double *T_out, double *X_out)
+{
+    const int b = 1 << L, mx = P->nx >> L, my = P->ny >> L, mz = P->nz >> L;
+    const size_t nc = ncells_of(P), ncl = (size_t)mx * my * mz;
+    for (int I = 0; I < mx; ++I)
+        for (int J = 0; J < my; ++J)
+            for (int K = 0; K < mz; ++K) {
+                double vs = 0.0, ts = 0.0, xs[8] = {0};
+                for (int i = I * b; i < (I + 1) * b; ++i)
+                    for (int j = J * b; j < (J + 1) * b; ++j)
+                        for (int k = K * b; k < (K + 1) * b; ++k) {
+                            double v = (P->xf[i + 1] - P->xf[i]) * (P->yf[j + 1] - P->yf[j]) *
+                                       (P->zf[k + 1] - P->zf[k]);
+                            size_t c = ((size_t)i * P->ny + j) * P->nz + k;
+                            vs += v;
+                            ts += v * P->T[c];
+                            for (int s = 0; s < P->ns && s < 8; ++s) xs[s] += v * P->X[(size_t)s * nc + c];
+                        }
+                size_t cl = ((size_t)I * my + J) * mz + K;
+                T_out[cl] = ts / vs;
+                for (int s = 0; s < P->ns && s < 8; ++s) X_out[(size_t)s * ncl + cl] = xs[s] / vs;
+            }
+}
+
+int orc_coarse_fields(const orc_problem *P, int L, double *T_out, double *X_out)
+{
+    if (L < 0 || L >= orc_level_count(P->nx, P->ny, P->nz) || P->ns > 8) return ORC_INVALID;
+    coarse_fields(P, L, T_out, X_out);
+    return ORC_OK;
+}
+
+static void free_levels(orc_levels *G)
+{
+    for (int L = 0; L < ORC_MAX_LEV; ++L)
+        for (int q = 0; q < 5; ++q) {
+            free(G->owned[L][q]);
+            G->owned[L][q] = 0;
+        }
+}
+
+static int build_levels(const orc_problem *P, orc_levels *G)
+{
+    memset(G, 0, sizeof *G);
+    int nl = P->mg_levels < 1 ? 1 : P->mg_levels;
+    if (nl > orc_level_count(P->nx, P->ny, P->nz) || P->ns > 8) return ORC_INVALID;
+    G->nlev = nl;
+    for (int L = 0; L < nl; ++L) {
+        int n[3] = {P->nx >> L, P->ny >> L, P->nz >> L};
+        const double *f0[3] = {P->xf, P->yf, P->zf};
+        for (int a = 0; a < 3; ++a) G->n[L][a] = n[a];
+        if (L == 0) {
+            for (int a = 0; a < 3; ++a) G->f[0][a] = f0[a];
+            G->T[0] = P->T;
+            G->X[0] = P->X;
+            continue;
+        }
+        for (int a = 0; a < 3; ++a) {
+            double *f = malloc(sizeof(double) * (n[a] + 1));
+            for (int q = 0; q <= n[a]; ++q) f[q] = f0[a][q << L];
+            G->owned[L][a] = f;
+            G->f[L][a] = f;
+        }
+        size_t ncl = (size_t)n[0] * n[1] * n[2];
+        double *T = malloc(sizeof(double) * ncl), *X = malloc(sizeof(double) * ncl * P->ns);
+        coarse_fields(P, L, T, X);
+        G->owned[L][3] = T;
+        G->owned[L][4] = X;
+        G->T[L] = T;
+        G->X[L] = X;
+    }
+    return ORC_OK;
+}
+
+/* March of one ray on the overlaid grids (M3); otherwise step for step the march of
+ * orc_march.  Recorded cells carry their level in bits 48 and up. */
+static int march_levels(const orc_problem *P, const orc_levels *G, int ci, int cj, int ck, int n, int g,
+                        const double d[3], orc_march_out *res, int64_t *rec_cells, double *rec_ds, int rec_max)
+{
+    int L = 0, lsteps = 0;
+    int nx = G->n[0][0], ny = G->n[0][1], nz = G->n[0][2];
+    const double *xf = G->f[0][0], *yf = G->f[0][1], *zf = G->f[0][2];
+    size_t csrc = ((size_t)ci * P->ny + cj) * P->nz + ck;
+    double o[3] = {0.5 * (P->xf[ci] + P->xf[ci + 1]), 0.5 * (P->yf[cj] + P->yf[cj + 1]),
+                   0.5 * (P->zf[ck] + P->zf[ck + 1])};
+    int sx = d[0] > 0.0 ? 1 : -1, sy = d[1] > 0.0 ? 1 : -1, sz = d[2] > 0.0 ? 1 : -1;
+    int i = ci, j = cj, kk = ck, wi = 0, wk = 0;
+    double tx = (face_coord(xf, nx, i + (sx > 0), wi) - o[0]) / d[0];
+    double ty = (yf[j + (sy > 0)] - o[1]) / d[1];
+    double tz = (face_coord(zf, nz, kk + (sz > 0), wk) - o[2]) / d[2];
+    double Isrc, Ilast, t = 0.0, tau = 1.0, acc = 0.0, absacc = 0.0;
+    int e = cell_planck(P, csrc, n, &Isrc);
+    if (e) return e;
+    Ilast = Isrc;
+    int steps = 0, end = 0;
+    while (tau > P->tol && steps < P->max_steps) {
+        if (L + 1 < G->nlev && lsteps == P->mg_steps) {         /* M3: fall onto the coarser grid */
+            ++L;
+            lsteps = 0;
+            nx = G->n[L][0]; ny = G->n[L][1]; nz = G->n[L][2];
+            xf = G->f[L][0]; yf = G->f[L][1]; zf = G->f[L][2];
+            i /= 2; j /= 2; kk /= 2;
+            tx = (face_coord(xf, nx, i + (sx > 0), wi) - o[0]) / d[0];
+            ty = (yf[j + (sy > 0)] - o[1]) / d[1];
+            tz = (face_coord(zf, nz, kk + (sz > 0), wk) - o[2]) / d[2];
+        }
+        double te = tx < ty ? tx : ty;
+        if (tz < te) te = tz;
+        double ds = te - t;
+        size_t c = ((size_t)i * ny + j) * nz + kk, ncl = (size_t)nx * ny * nz;
+        double kap, Ij;
+        if ((e = kappa_at(P, n, g, G->T[L][c], G->X[L] + c, ncl, &kap)) ||
+            (e = planck_at(P, n, G->T[L][c], &Ij)))
+            return e;
+        double alpha = -expm1(-kap * ds);                        /* Eq. 2, R10 */
+        acc += tau * alpha * (Isrc - Ij);
+        absacc += tau * alpha * fabs(Isrc - Ij);
+        tau *= 1.0 - alpha;                                      /* Eq. 3 */
+        if (rec_cells && steps < rec_max) { rec_cells[steps] = (int64_t)c | ((int64_t)L << 48); rec_ds[steps] = ds; }
+        ++steps;
+        ++lsteps;
+        t = te;
+        Ilast = Ij;
+        int wall = 0;
+        if (tx == te) {                                          /* R5 */
+            i += sx;
+            if (i == nx) { i = 0; ++wi; }
+            if (i < 0) { i = nx - 1; --wi; }
+            tx = (face_coord(xf, nx, i + (sx > 0), wi) - o[0]) / d[0];
+        }
+        if (ty == te) {
+            j += sy;
+            if (j < 0) wall = 1;
+            else if (j >= ny) wall = 2;
+            else ty = (yf[j + (sy > 0)] - o[1]) / d[1];
+        }
+        if (tz == te) {
+            kk += sz;
+            if (kk == nz) { kk = 0; ++wk; }
+            if (kk < 0) { kk = nz - 1; --wk; }
+            tz = (face_coord(zf, nz, kk + (sz > 0), wk) - o[2]) / d[2];
+        }
+        if (wall) {                                              /* R4 */
+            double Iw, eps = P->epsw[wall - 1];
+            if ((e = planck_at(P, n, P->Tw[wall - 1], &Iw))) return e;
+            acc += tau * eps * (Isrc - Iw);
+            absacc += tau * eps * fabs(Isrc - Iw);
+            tau *= 1.0 - eps;
+            end = wall;
+            break;
+        }
+    }
+    if (end == 0 && steps >= P->max_steps && tau > P->tol) end = 3;
+    acc += tau * (Isrc - Ilast);                                 /* R11 */
+    absacc += tau * fabs(Isrc - Ilast);
+    res->acc = acc;
+    res->absacc = absacc;
+    res->steps = steps;
+    res->end = end;
+    return ORC_OK;
+}
+
+/* One ray of the multigrid march with the problem's mg_levels / mg_steps (levels built per
+ * call: for tests of single rays). */
+int orc_march_mg(const orc_problem *P, int ci, int cj, int ck, int n, int g, const double d[3],
+                 orc_march_out *res, int64_t *rec_cells, double *rec_ds, int rec_max)
+{
+    orc_levels G;
+    int e = build_levels(P, &G);
+    if (!e) e = march_levels(P, &G, ci, cj, ck, n, g, d, res, rec_cells, rec_ds, rec_max);
+    free_levels(&G);
+    return e;
+}
+
 /* ------------------------------------------------------------ ray sampling per cell */
 typedef struct {
     const double *p, *cdf_b, *cdf_g;   /* plain pdf and its cumulative sums */
@@ -380,8 +595,8 @@ static void cell_pdf(const orc_problem *P, const orc_plain *pl, size_t c, double
 }
 
 /* All R rays of cell (ci,cj,ck): draws (Algorithm 1, Initialize), march, ray value. */
-static int trace_cell(const orc_problem *P, const orc_plain *pl, int ci, int cj, int ck, orc_ray *out,
-                      double *work)
+static int trace_cell(const orc_problem *P, const orc_plain *pl, const orc_levels *G, int ci, int cj, int ck,
+                      orc_ray *out, double *work)
 {
     const int nb = P->nb, ng = P->ng, R = P->R;
     size_t c = ((size_t)ci * P->ny + cj) * P->nz + ck;
@@ -431,7 +646,8 @@ static int trace_cell(const orc_problem *P, const orc_plain *pl, int ci, int cj,
         if (ry->o & 2) d[1] = -d[1];
         if (ry->o & 4) d[2] = -d[2];
         orc_march_out m;
-        int e = orc_march(P, ci, cj, ck, ry->n, ry->g, d, &m, 0, 0, 0);
+        int e = G->nlev > 1 ? march_levels(P, G, ci, cj, ck, ry->n, ry->g, d, &m, 0, 0, 0)
+                            : orc_march(P, ci, cj, ck, ry->n, ry->g, d, &m, 0, 0, 0);
         if (e) return e;
         if ((e = cell_kappa(P, c, ry->n, ry->g, &kap_src))) return e;
         /* Eq. 14 with R9: w = 4 pi dnu_n w_g / (8 p(n,g,o)) over the octant-resolved pdf */
@@ -448,7 +664,8 @@ static int check_problem(const orc_problem *P)
 {
     if (P->nx < 1 || P->ny < 1 || P->nz < 1 || P->nb < 1 || P->ng < 1 || P->ng > 255 ||
         P->nb > 65535 || P->ns < 1 || P->nT < 2 || P->R < 1 || !(P->dT > 0.0) ||
-        P->max_steps < 1 || !(P->tol >= 0.0))
+        P->max_steps < 1 || !(P->tol >= 0.0) || P->mg_levels > orc_level_count(P->nx, P->ny, P->nz) ||
+        (P->mg_levels > 1 && (P->mg_steps < 1 || P->ns > 8)))
         return ORC_INVALID;
     if (P->epsw[0] != 1.0 || P->epsw[1] != 1.0) return ORC_UNSUPPORTED;   /* R4 */
     return ORC_OK;
@@ -463,6 +680,9 @@ int orc_trace_cells(const orc_problem *P, int ncell, const int64_t *cells, orc_r
            *cg = malloc(sizeof(double) * P->nb * P->ng);
     err = orc_plain_pdf(P, p, cb, cg, 0);
     orc_plain pl = {p, cb, cg};
+    orc_levels G;
+    if (!err) err = build_levels(P, &G);
+    else memset(&G, 0, sizeof G);
     size_t wsz = P->q_cell ? (size_t)P->nb * P->ng * 8 * 2 + P->nb + P->nb * P->ng : 1;
     if (!err) {
 #pragma omp parallel
@@ -475,7 +695,7 @@ int orc_trace_cells(const orc_problem *P, int ncell, const int64_t *cells, orc_r
                 int ci = (int)(c / ((int64_t)P->ny * P->nz));
                 int cj = (int)((c / P->nz) % P->ny);
                 int ck = (int)(c % P->nz);
-                int e = trace_cell(P, &pl, ci, cj, ck, out + (size_t)q * P->R, work);
+                int e = trace_cell(P, &pl, &G, ci, cj, ck, out + (size_t)q * P->R, work);
                 if (e) myerr = e;
             }
 #pragma omp critical
@@ -483,6 +703,7 @@ int orc_trace_cells(const orc_problem *P, int ncell, const int64_t *cells, orc_r
             free(work);
         }
     }
+    free_levels(&G);
     free(p); free(cb); free(cg);
     return err;
 }
@@ -499,6 +720,9 @@ int orc_divergence(const orc_problem *P, int ncell, const int64_t *cells, double
            *cg = malloc(sizeof(double) * P->nb * P->ng);
     err = orc_plain_pdf(P, p, cb, cg, 0);
     orc_plain pl = {p, cb, cg};
+    orc_levels G;
+    if (!err) err = build_levels(P, &G);
+    else memset(&G, 0, sizeof G);
     size_t wsz = P->q_cell ? (size_t)P->nb * P->ng * 8 * 2 + P->nb + P->nb * P->ng : 1;
     int64_t steps = 0;
 #ifdef _OPENMP
@@ -516,7 +740,7 @@ int orc_divergence(const orc_problem *P, int ncell, const int64_t *cells, double
                 int ci = (int)(c / ((int64_t)P->ny * P->nz));
                 int cj = (int)((c / P->nz) % P->ny);
                 int ck = (int)(c % P->nz);
-                int e = trace_cell(P, &pl, ci, cj, ck, rays, work);
+                int e = trace_cell(P, &pl, &G, ci, cj, ck, rays, work);
                 if (e) { myerr = e; continue; }
                 double sum = 0.0;
                 for (int r = 0; r < P->R; ++r) { sum += rays[r].Y; steps += rays[r].steps; }
@@ -531,6 +755,7 @@ int orc_divergence(const orc_problem *P, int ncell, const int64_t *cells, double
         }
     }
     if (steps_total) *steps_total = steps;
+    free_levels(&G);
     free(p); free(cb); free(cg);
     return err;
 }

@@ -249,6 +249,8 @@ class Workload:
     march: str = "f64"         # "f64" or "f32" ray marching
     accum: str = "f64"         # per-cell sum: "f64", "comp32" (Neumaier FP32) or "f32"
     field_dtype: str = "f64"   # dtype the T / X fields are handed over in
+    mg_levels: int = 1         # overlaid grid levels of the multigrid march (1: DNS grid only)
+    mg_steps: int = 5          # steps per level before the ray falls onto the next coarser grid
 
     @property
     def nx(self): return len(self.xf) - 1
