@@ -46,6 +46,12 @@ def parse():
     ap.add_argument("--length-sort", action="store_true",
                     help="reorder each march workgroup's rays by expected length")
     ap.add_argument("--bucket-order", type=int, default=0, help="0: longest rays first, 1: band-major")
+    ap.add_argument("--mg-levels", type=int, default=0,
+                    help="multigrid march: grid levels (-1: all the grid allows; 0/1: DNS grid only)")
+    ap.add_argument("--mg-steps", type=int, default=0, help="multigrid march: steps per grid (0: 5)")
+    ap.add_argument("--mg-study", choices=["channel64", "dns256"], default=None,
+                    help="multigrid time and accuracy against the single-grid march, 1..all levels")
+    ap.add_argument("--mg-snaps", type=int, default=0, help="snapshots (random streams) per study row")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (the "
                          "reference point that scales rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -171,6 +177,83 @@ def learned_bench(a):
     print(json.dumps(out), flush=True)
 
 
+def grid_levels(nx, ny, nz):
+    """Grid levels the multigrid march can use (coarsening ratio 2, axes even, halves >= 3)."""
+    L = 1
+    while L < 8 and all(n % 2 == 0 and n // 2 >= 3 for n in (nx, ny, nz)):
+        nx, ny, nz = nx // 2, ny // 2, nz // 2
+        L += 1
+    return L
+
+
+def mg_study(a):
+    """Multigrid march (Sec. 4.3) against the single-grid march on one field: wall time per
+    compute and speedup for 1 .. all grid levels (5 steps per grid, then 10 and 20 on all
+    levels), and the accuracy of the estimate.  Every row uses the same seeds, so the rays
+    (band, g, octant, direction) are the same and the difference of the estimates is the
+    multigrid approximation plus a small residue of noise; it is averaged over several
+    snapshots (random streams) and compared with the Monte Carlo standard error of one
+    compute."""
+    import numpy as np
+    import torch
+    from paper_1810_00188_amd import inputs, rmc
+
+    gen = {"channel64": inputs.channel64, "dns256": inputs.dns256}[a.mg_study]
+    w = gen()
+    nmax = grid_levels(w.nx, w.ny, w.nz)
+    K = a.mg_snaps or (8 if a.mg_study == "channel64" else 3)
+    dev = torch.device("cuda", 0)
+    s = rmc.Solver(0)
+    s.set_workload(w, device_fields=True)
+    dq = torch.zeros(w.ncells, dtype=torch.float64, device=dev)
+    se = torch.zeros_like(dq)
+    rows_cfg = [(1, 5)] + [(L, 5) for L in range(2, nmax + 1)] + [(nmax, 10), (nmax, 20)]
+    rows, base = [], None
+    for L, S in rows_cfg:
+        def opts(k):
+            return rmc.default_options(rays_per_cell=w.R, seed=w.seed, snapshot=100 + k, tol=w.tol,
+                                       max_steps=w.max_steps, march=rmc.F32, accum=rmc.ACC[w.accum],
+                                       mg_levels=L, mg_steps=S)
+        s.set_options(opts(0))
+        for _ in range(2):
+            s.compute(dq, se)
+        torch.cuda.synchronize()
+        qs, ses, t_tot, steps, march = [], [], 0.0, 0, 0.0
+        for k in range(K):
+            s.set_options(opts(k))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.compute(dq, se)
+            torch.cuda.synchronize()
+            t_tot += time.perf_counter() - t0
+            st = s.stats()
+            steps += st["steps"]
+            march += st["ms_march"]
+            qs.append(dq.cpu().numpy())
+            ses.append(se.cpu().numpy())
+        q = np.mean(qs, axis=0)
+        se_rms = float(np.sqrt(np.mean(np.square(ses))))
+        row = {"levels": L, "steps_per_grid": S, "ms_per_compute": 1e3 * t_tot / K, "march_ms": march / K,
+               "steps_per_ray": steps / (K * w.ncells * w.R)}
+        if base is None:
+            base = dict(q=q, ms=row["ms_per_compute"], se=se_rms)
+        rms_q = float(np.sqrt(np.mean(base["q"] ** 2)))
+        row["speedup"] = base["ms"] / row["ms_per_compute"]
+        row["rms_diff_vs_single_rel"] = float(np.sqrt(np.mean((q - base["q"]) ** 2))) / rms_q
+        row["mean_diff_vs_single_rel"] = float(np.mean(q - base["q"])) / rms_q
+        row["stderr_one_compute_rel"] = se_rms / rms_q
+        row["stderr_ratio_vs_single"] = se_rms / base["se"]
+        rows.append(row)
+        print(f"[mg] {json.dumps(row)}", flush=True)
+    out = {"metric": "multigrid march: time per compute and accuracy vs the single-grid march",
+           "unit": "ms", "n_gpus": 1, "dtype": "f32", "data": "synthetic", "vs_baseline": None,
+           "config": {"workload": w.name, "grid": [w.nx, w.ny, w.nz], "bands": w.kd.nb, "g_points": w.kd.ng,
+                      "rays_per_cell": w.R, "snapshots_per_row": K, "grid_levels_allowed": nmax},
+           "rows": rows}
+    print(json.dumps(out), flush=True)
+    s.close()
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -179,6 +262,9 @@ def main():
         sys.exit(2)
     if a.learned:
         learned_bench(a)
+        return
+    if a.mg_study:
+        mg_study(a)
         return
     import numpy as np
     import torch
@@ -197,7 +283,9 @@ def main():
     s = rmc.Solver(0)
     overrides = {k: v for k, v in (("long_ray_steps", a.long_ray_steps), ("xcd_span", a.xcd_span),
                                    ("length_sort", int(a.length_sort)),
-                                   ("bucket_order", a.bucket_order)) if v}
+                                   ("bucket_order", a.bucket_order), ("mg_levels", a.mg_levels),
+                                   ("mg_steps", a.mg_steps)) if v}
+    mg = a.mg_levels not in (0, 1)
     s.set_workload(w, **overrides)
     T = torch.from_numpy(np.ascontiguousarray(w.T, dtype=np.float32)).to(dev)
     X = torch.from_numpy(np.ascontiguousarray(w.X, dtype=np.float32)).to(dev)
@@ -232,7 +320,7 @@ def main():
     traffic = None
     if a.traffic_json and os.path.exists(a.traffic_json):
         rec = json.load(open(a.traffic_json)).get("k_march_lane", {})
-        if rec.get("source_sha256") == kernel_source_hash():   # counters of this very code only
+        if rec.get("source_sha256") == kernel_source_hash() and not mg:   # counters of this very code only
             traffic = rec.get("bytes_per_launch")
     out = {
         "metric": "ray-cell steps/s",
@@ -248,21 +336,23 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "non-grey channel 64x64x64, 20 bands x 7 g, 32 rays/cell, "
-                               "FP32 march, FP64 sums",
+                               "FP32 march, FP64 sums" + (f", multigrid march {a.mg_levels} levels x "
+                                                          f"{a.mg_steps or 5} steps" if mg else ""),
                    "grid": [w.nx, w.ny, w.nz], "bands": w.kd.nb, "g_points": w.kd.ng,
                    "rays_per_cell": w.R, "rays_per_step": st["rays"],
                    "ray_cell_steps_per_step": st["steps"], "parallelism": "1 GPU"},
         "phases_ms": {"prep": st["sum_ms_prep"] / a.steps, "alloc": st["sum_ms_alloc"] / a.steps,
                       "march": march_ms, "reduce": st["sum_ms_reduce"] / a.steps},
         "march_steps_per_s": st["steps"] / (march_ms * 1e-3),
-        "roofline": {"kernel": "k_march_lane", "bound": "hbm", "achieved": achieved,
+        "roofline": {"kernel": "k_march_mg" if mg else "k_march_lane", "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "ms_per_launch": lane_ms,
                      "algorithmic_bytes_per_launch": bytes_launch,
                      "steps_per_launch": lane_steps, "rays_per_launch": st["rays"]},
     }
     if a.cpu_seconds > 0:
-        out["cpu_baseline"] = cpu_baseline(w, a.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(w.replace(mg_levels=a.mg_levels, mg_steps=a.mg_steps or 5) if mg else w,
+                                           a.cpu_seconds)
     print(json.dumps(out), flush=True)
     s.close()
 

@@ -92,7 +92,18 @@ typedef struct {
                                 increasing kappa(T_max), the longest rays first; 1 band-major, the
                                 g-points of a band together (they share its intensity plane).
                                 Results are the same either way */
-    int32_t reserved[3];     /* must be zero */
+    int32_t mg_levels;       /* multigrid march (Sec. 4.3): number of overlaid grids; grid L has
+                                every 2^L-th face of the DNS grid (coarsening ratio 2 on every axis,
+                                possible while each axis is even with a half of at least 3 cells)
+                                and cells with the volume-weighted mean temperature and mole
+                                fractions of the DNS cells they cover.  0 or 1: DNS grid only
+                                (default); -1: every level the grid allows; more levels than the
+                                grid allows is RMC_INVALID_ARG at compute.  Changes the result:
+                                the coarse grids approximate the medium far from the source */
+    int32_t mg_steps;        /* multigrid: steps a ray takes on each grid before it continues on
+                                the next coarser one (the source cell's step counts on the DNS
+                                grid); the last grid runs to depletion.  0 = default 5 */
+    int32_t reserved[1];     /* must be zero */
 } rmc_options;
 
 typedef struct {

@@ -32,6 +32,8 @@ using namespace rmc;
 // ============================================================================ device side
 namespace {
 
+constexpr int kMaxLev = 8;      // grid levels of the multigrid march
+
 struct SnapDesc {
     const void *kap;            // Real [nb*ng][ncpad] kappa_{n,g} planes, bricked
     const double *Ipl;          // [nb][ncpad] I_n planes, bricked
@@ -57,6 +59,15 @@ struct SnapDesc {
     int tile_begin, ntiles;
     double Lx, Lz;
     double hx, hz;              // cell widths along x and z when those axes are uniform
+    // multigrid march (Sec. 4.3): level L has (nx >> L) x (ny >> L) x (nz >> L) cells with
+    // every 2^L-th face; its planes follow the same bricked layout
+    int nlev;                   // grid levels (1: the DNS grid only)
+    int mg_steps;               // steps per level before the next coarser one
+    int lev_face[kMaxLev];      // face tables of each level in the staged face array
+    uint64_t lev_off[kMaxLev];  // offset of level L >= 1 within a coarse plane
+    uint64_t mg_stride;         // cells per coarse plane (all levels >= 1)
+    const void *mg_kap;         // Real [nb*ng][mg_stride] kappa planes of the coarse levels
+    const double *mg_I;         // [nb][mg_stride] I planes of the coarse levels
 };
 
 struct AllocArgs {
@@ -360,7 +371,7 @@ __global__ void __launch_bounds__(256) k_fields(const double *__restrict__ T, co
                                                 uint64_t nc, const double *__restrict__ k64,
                                                 const double *__restrict__ Ib, int nb, int ng, int nT, double T0,
                                                 double dT, SnapDesc D, Real *__restrict__ kap_out,
-                                                double *__restrict__ I_out)
+                                                double *__restrict__ I_out, uint64_t stride)
 {
     const uint64_t bc = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
     if (bc >= D.ncpad) return;
@@ -383,7 +394,7 @@ __global__ void __launch_bounds__(256) k_fields(const double *__restrict__ T, co
             const double *ib = Ib + (size_t)n * nT;
             I = ib[t] + f * (ib[t + 1] - ib[t]);
         }
-        I_out[(size_t)n * D.ncpad + bc] = I;
+        I_out[(size_t)n * stride + bc] = I;
         for (int g = 0; g < ng; ++g) {
             double kap = 0.0;
             if (valid)
@@ -392,9 +403,37 @@ __global__ void __launch_bounds__(256) k_fields(const double *__restrict__ T, co
                     const double ks = tab[t] + f * (tab[t + 1] - tab[t]);
                     kap += x[sp] * ks;
                 }
-            kap_out[((size_t)n * ng + g) * D.ncpad + bc] = (Real)kap;
+            kap_out[((size_t)n * ng + g) * stride + bc] = (Real)kap;
         }
     }
+}
+
+// Fields of the next coarser grid (multigrid march, Sec. 4.3): each coarse cell takes the
+// volume-weighted mean temperature and mole fractions of the 2 x 2 x 2 cells of the level
+// below (nx x ny x nz cells with faces xf, yf, zf), natural order.
+__global__ void __launch_bounds__(256) k_coarsen(const double *__restrict__ T, const double *__restrict__ X, int ns,
+                                                 int nx, int ny, int nz, const double *__restrict__ xf,
+                                                 const double *__restrict__ yf, const double *__restrict__ zf,
+                                                 double *__restrict__ Tc, double *__restrict__ Xc)
+{
+    const int cx = nx >> 1, cy = ny >> 1, cz = nz >> 1;
+    const uint64_t ncc = (uint64_t)cx * cy * cz, nc = (uint64_t)nx * ny * nz;
+    const uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (q >= ncc) return;
+    const int K = (int)(q % cz), J = (int)((q / cz) % cy), I = (int)(q / ((uint64_t)cz * cy));
+    double vs = 0.0, ts = 0.0, xs[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int e = 0; e < 2; ++e) {
+                const int i = 2 * I + a, j = 2 * J + b, k = 2 * K + e;
+                const double v = (xf[i + 1] - xf[i]) * (yf[j + 1] - yf[j]) * (zf[k + 1] - zf[k]);
+                const uint64_t c = ((uint64_t)i * ny + j) * nz + k;
+                vs += v;
+                ts += v * T[c];
+                for (int sp = 0; sp < ns; ++sp) xs[sp] += v * X[(size_t)sp * nc + c];
+            }
+    Tc[q] = ts / vs;
+    for (int sp = 0; sp < ns; ++sp) Xc[(size_t)sp * ncc + q] = xs[sp] / vs;
 }
 
 // ------------------------------------------------------------- allocation and buckets
@@ -610,6 +649,45 @@ __device__ __forceinline__ RayGeo ray_geo(const SnapDesc &D, const double *sf)
     return G;
 }
 
+// Geometry of grid level L (faces staged per level; level 0 is ray_geo's).
+__device__ __forceinline__ RayGeo ray_geo_level(const SnapDesc &D, const double *sf, int L)
+{
+    RayGeo G;
+    G.nx = D.nx >> L; G.ny = D.ny >> L; G.nz = D.nz >> L;
+    G.xf = sf + D.lev_face[L];
+    G.yf = G.xf + G.nx + 1;
+    G.zf = G.yf + G.ny + 1;
+    const int nby = (G.ny + 3) >> 2, nbz = (G.nz + 3) >> 2;
+    G.bsx = nby * nbz * 64;
+    G.bsy = nbz * 64;
+    G.Lx = D.Lx;
+    G.Lz = D.Lz;
+    return G;
+}
+
+// Multigrid march (Sec. 4.3): mg_steps steps on each grid, then the ray goes on from its
+// current point in the coarser cell that holds its cell, and runs to depletion on the last
+// grid.  Source kappa and intensity stay those of the DNS cell (k0, I0 on entry).
+template <class Real, bool INC_XZ>
+__device__ __forceinline__ void march_levels(Ray<Real, INC_XZ> &R, const SnapDesc &D, const double *sf, int pair,
+                                             int n, int nb, Real tol, int max_steps, Real k0, double I0)
+{
+    RayGeo G = ray_geo(D, sf);
+    const Real *K = reinterpret_cast<const Real *>(D.kap) + (size_t)pair * D.ncpad;
+    const double *Ipl = D.Ipl + (size_t)n * D.ncpad;
+    for (int L = 0;; ++L) {
+        const int cap = L + 1 < D.nlev ? D.mg_steps * (L + 1) : max_steps;
+        if (ray_march(R, G, K, Ipl, D.Iw + n, D.Iw + nb + n, tol, max_steps, k0, I0, cap)) return;
+        G = ray_geo_level(D, sf, L + 1);
+        ray_descend(R, G);
+        K = reinterpret_cast<const Real *>(D.mg_kap) + (size_t)pair * D.mg_stride + D.lev_off[L + 1];
+        Ipl = D.mg_I + (size_t)n * D.mg_stride + D.lev_off[L + 1];
+        const int cell = R.px + R.py + R.pz;
+        k0 = gld(K + cell);
+        I0 = gld(Ipl + cell);
+    }
+}
+
 // Expected-length class of a ray (quarter octaves of its estimated step count; larger is
 // longer).  The estimate counts the face crossings of the straight path until it reaches the
 // wall it heads for or the optical depth ln(1/tol) at the source cell's kappa:
@@ -738,6 +816,53 @@ __global__ void __launch_bounds__(256) k_march_lane(MarchArgs<Real> A)
         ray_march(R, G, K, Ipl, D.Iw + n, D.Iw + A.nb + n, A.tol, A.max_steps, gld(K + cell), gld(Ipl + cell),
                   A.max_steps);
     }
+    const size_t slot = (size_t)c * A.R + r;
+    double w;
+    if constexpr (!PDF) {
+        w = gld(D.W + b);
+    } else {
+        const double p = gld(D.dprob + slot);
+        w = 4.0 * M_PI * A.dnu[n] * A.wg[pair - n * A.ng] / (8.0 * p);
+    }
+    store_slot<Real>(D, slot, w * (double)kap_src * (double)R.acc, (uint32_t)R.steps | ((uint32_t)R.end << 28));
+}
+
+// Multigrid march: one ray per lane as in k_march_lane (no length sort, no long-ray hand-off:
+// the coarse grids keep even the least absorbed rays short).
+template <class Real, bool PDF, bool INC_XZ, bool MULTI>
+__global__ void __launch_bounds__(256) k_march_mg(MarchArgs<Real> A)
+{
+    extern __shared__ double sf[];
+    for (int q = threadIdx.x; q < A.nfaces; q += blockDim.x) sf[q] = A.faces[q];
+    const int wib = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+    const uint32_t nch = __builtin_amdgcn_readfirstlane(*A.nchunks);
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(xcd_chunk(blockIdx.x, (uint32_t)wib, A.span_log2));
+    __syncthreads();
+    if (wave >= nch) return;
+    const uint32_t b = __builtin_amdgcn_readfirstlane(gld(A.chunk_bucket + wave));
+    const int o = (int)(b & 7), pair = (int)(b >> 3);
+    const uint32_t q = wave * 64u + (uint32_t)lane;
+    const uint4 it = gld(A.items + q);
+    if (it.y == kInvalidItem) return;
+    double dx, dy, dz;
+    octant_direction(it.z, it.w, o, dx, dy, dz);
+    const int s = MULTI ? (int)((it.y >> 16) & 0x7FFF) : 0;
+    const SnapDesc &D = A.snaps[s];
+    const RayGeo G = ray_geo(D, sf);
+    XzUniform U;
+    U.hx = D.hx;
+    U.hz = D.hz;
+    const int i = (int)(it.x & 1023), j = (int)((it.x >> 10) & 1023), k = (int)((it.x >> 20) & 1023);
+    const int r = (int)(it.y & 255);
+    const int n = pair / A.ng;
+    const Real *K = reinterpret_cast<const Real *>(D.kap) + (size_t)pair * D.ncpad;
+    const double *Ipl = D.Ipl + (size_t)n * D.ncpad;
+    const uint32_t c = (uint32_t)(((uint64_t)i * D.ny + j) * D.nz + k);
+    Ray<Real, INC_XZ> R;
+    Real kap_src;
+    double Isrc;
+    ray_init(R, G, U, K, Ipl, i, j, k, dx, dy, dz, kap_src, Isrc);
+    march_levels(R, D, sf, pair, n, A.nb, A.tol, A.max_steps, kap_src, Isrc);
     const size_t slot = (size_t)c * A.R + r;
     double w;
     if constexpr (!PDF) {
@@ -1010,7 +1135,8 @@ __global__ void __launch_bounds__(256) k_trace(TraceArgs<Real> A)
     Real kap_src;
     double Isrc;
     ray_init(R, G, U, K, Ipl, i, j, k, dx, dy, dz, kap_src, Isrc);
-    ray_march(R, G, K, Ipl, D.Iw + d.n, D.Iw + A.nb + d.n, A.tol, A.max_steps, kap_src, Isrc, A.max_steps);
+    if (D.nlev > 1) march_levels(R, D, sf, pair, d.n, A.nb, A.tol, A.max_steps, kap_src, Isrc);
+    else ray_march(R, G, K, Ipl, D.Iw + d.n, D.Iw + A.nb + d.n, A.tol, A.max_steps, kap_src, Isrc, A.max_steps);
     const double w = 4.0 * M_PI * A.dnu[d.n] * A.wg[d.g] / (8.0 * d.p);
     rmc_ray_record rec;
     rec.Y = w * (double)kap_src * (double)R.acc;
@@ -1238,6 +1364,7 @@ struct rmc_ctx {
     // pdf and fields of the last compute
     DBuf pdf_scratch, p, cdf_b, cdf_g, W, Iw, status;
     DBuf field, Iplane;     // kappa planes (march precision) and FP64 intensity planes
+    DBuf mgT, mgX, mgfield, mgI;   // multigrid: coarse-level fields and planes
     // slots
     DBuf Y, st;
     int slots_R = 0, slots_real = 0;
@@ -1309,7 +1436,10 @@ rmc_status check_options(const rmc_options *o)
         return fail(RMC_INVALID_ARG, "xcd_span must be 0 or a power of two in [4, 2^20]");
     if (o->length_sort != 0 && o->length_sort != 1) return fail(RMC_INVALID_ARG, "length_sort must be 0 or 1");
     if (o->bucket_order != 0 && o->bucket_order != 1) return fail(RMC_INVALID_ARG, "bucket_order must be 0 or 1");
-    for (int q = 0; q < 3; ++q)
+    if (o->mg_levels < -1 || o->mg_levels > kMaxLev)
+        return fail(RMC_INVALID_ARG, "mg_levels must be -1 (all the grid allows), 0, 1 or up to %d", kMaxLev);
+    if (o->mg_steps < 0 || o->mg_steps > (1 << 24)) return fail(RMC_INVALID_ARG, "mg_steps must be in [0, 2^24]");
+    for (int q = 0; q < 1; ++q)
         if (o->reserved[q] != 0) return fail(RMC_INVALID_ARG, "reserved option fields must be zero");
     return RMC_OK;
 }
@@ -1332,6 +1462,36 @@ rmc_status check_ready(const rmc_ctx *c)
     if ((uint64_t)ncells_of(c) * c->opt.rays_per_cell >= (1ull << 32))
         return fail(RMC_UNSUPPORTED, "ncells * R must stay below 2^32");
     return RMC_OK;
+}
+
+// Grid levels an nx x ny x nz grid allows: halve every axis while each is even and its half
+// at least 3 (the paper's coarsening ratio 2 down to 3^3 meshes).
+int level_count(int nx, int ny, int nz)
+{
+    int L = 1;
+    while (L < kMaxLev && nx % 2 == 0 && ny % 2 == 0 && nz % 2 == 0 && nx / 2 >= 3 && ny / 2 >= 3 && nz / 2 >= 3) {
+        nx /= 2; ny /= 2; nz /= 2;
+        ++L;
+    }
+    return L;
+}
+
+uint64_t ncpad_level(const rmc_ctx *c, int L)
+{
+    return (uint64_t)round_up(c->nx >> L, 4) * round_up(c->ny >> L, 4) * round_up(c->nz >> L, 4);
+}
+
+// Face tables of every grid level of a snapshot, appended to `faces` (level L: every 2^L-th
+// face); records their offsets in D.
+void append_faces(const rmc_ctx *c, SnapDesc &D, std::vector<double> &faces)
+{
+    D.face_off = (int)faces.size();
+    for (int L = 0; L < D.nlev; ++L) {
+        D.lev_face[L] = (int)faces.size();
+        for (int q = 0; q <= (c->nx >> L); ++q) faces.push_back(c->xf[(size_t)q << L]);
+        for (int q = 0; q <= (c->ny >> L); ++q) faces.push_back(c->yf[(size_t)q << L]);
+        for (int q = 0; q <= (c->nz >> L); ++q) faces.push_back(c->zf[(size_t)q << L]);
+    }
 }
 
 // width of a uniformly spaced axis (faces equal to f0 + q h within 1e-12 of the length), else 0
@@ -1568,6 +1728,28 @@ template <class Real> rmc_status plan_snapshot(rmc_ctx *c, SnapDesc &D)
     }
     D.kap = c->field.p;
     D.Ipl = c->Iplane.as<double>();
+    // multigrid levels
+    const int allowed = level_count(c->nx, c->ny, c->nz);
+    D.nlev = c->opt.mg_levels < 0 ? allowed : std::max(1, c->opt.mg_levels);
+    if (D.nlev > allowed)
+        return fail(RMC_INVALID_ARG, "mg_levels %d exceeds the %d grid levels a %dx%dx%d grid allows", D.nlev, allowed,
+                    c->nx, c->ny, c->nz);
+    D.mg_steps = c->opt.mg_steps > 0 ? c->opt.mg_steps : 5;
+    if (D.nlev > 1) {
+        uint64_t off = 0, cells = 0;
+        for (int L = 1; L < D.nlev; ++L) {
+            D.lev_off[L] = off;
+            off += ncpad_level(c, L);
+            cells += (uint64_t)(c->nx >> L) * (c->ny >> L) * (c->nz >> L);
+        }
+        D.mg_stride = off;
+        if ((st = c->mgT.ensure(sizeof(double) * cells)) || (st = c->mgX.ensure(sizeof(double) * cells * c->ns)) ||
+            (st = c->mgfield.ensure(sizeof(Real) * off * (uint64_t)(nb * ng))) ||
+            (st = c->mgI.ensure(sizeof(double) * off * (uint64_t)nb)))
+            return st;
+        D.mg_kap = c->mgfield.p;
+        D.mg_I = c->mgI.as<double>();
+    }
     D.Y = c->Y.p;
     D.st = sizeof(Real) == 8 ? c->st.as<uint32_t>() : nullptr;
     c->slots_R = R;
@@ -1576,7 +1758,8 @@ template <class Real> rmc_status plan_snapshot(rmc_ctx *c, SnapDesc &D)
 }
 
 // per-snapshot work: spectral pdf, per-cell pdfs, property fields (kernels only)
-template <class Real> rmc_status enqueue_snapshot(rmc_ctx *c, const SnapDesc &D, hipStream_t s)
+template <class Real>
+rmc_status enqueue_snapshot(rmc_ctx *c, const SnapDesc &D, const double *dfaces, hipStream_t s)
 {
     rmc_status st;
     const int nb = c->nb, ng = c->ng;
@@ -1607,8 +1790,32 @@ template <class Real> rmc_status enqueue_snapshot(rmc_ctx *c, const SnapDesc &D,
     dim3 grid((unsigned)((ncpad + 255) / 256), (unsigned)std::min(c->nb, 65535));
     hipLaunchKernelGGL(k_fields<Real>, grid, dim3(256), 0, s, c->T.as<double>(), c->X.as<double>(), c->ns, nc,
                        c->k64.as<double>(), c->Ib.as<double>(), c->nb, c->ng, c->nT, c->T0, c->dT, D,
-                       c->field.as<Real>(), c->Iplane.as<double>());
+                       c->field.as<Real>(), c->Iplane.as<double>(), ncpad);
     HIPCHK(hipGetLastError());
+    // multigrid: fields of each coarser level from the one below, then its property planes
+    const double *Tin = c->T.as<double>(), *Xin = c->X.as<double>();
+    uint64_t toff = 0;
+    for (int L = 1; L < D.nlev; ++L) {
+        const int px = c->nx >> (L - 1), py = c->ny >> (L - 1), pz = c->nz >> (L - 1);
+        const uint64_t ncc = (uint64_t)(px >> 1) * (py >> 1) * (pz >> 1);
+        double *Tc = c->mgT.as<double>() + toff, *Xc = c->mgX.as<double>() + toff * c->ns;
+        const double *xf = dfaces + D.lev_face[L - 1];
+        hipLaunchKernelGGL(k_coarsen, dim3((unsigned)((ncc + 255) / 256)), dim3(256), 0, s, Tin, Xin, c->ns, px, py,
+                           pz, xf, xf + px + 1, xf + px + py + 2, Tc, Xc);
+        HIPCHK(hipGetLastError());
+        SnapDesc Dl = D;
+        Dl.nx = px >> 1; Dl.ny = py >> 1; Dl.nz = pz >> 1;
+        Dl.nbx = round_up(Dl.nx, 4) / 4; Dl.nby = round_up(Dl.ny, 4) / 4; Dl.nbz = round_up(Dl.nz, 4) / 4;
+        Dl.ncpad = ncpad_level(c, L);
+        dim3 lgrid((unsigned)((Dl.ncpad + 255) / 256), (unsigned)std::min(c->nb, 65535));
+        hipLaunchKernelGGL(k_fields<Real>, lgrid, dim3(256), 0, s, Tc, Xc, c->ns, ncc, c->k64.as<double>(),
+                           c->Ib.as<double>(), c->nb, c->ng, c->nT, c->T0, c->dT, Dl,
+                           c->mgfield.as<Real>() + D.lev_off[L], c->mgI.as<double>() + D.lev_off[L], D.mg_stride);
+        HIPCHK(hipGetLastError());
+        Tin = Tc;
+        Xin = Xc;
+        toff += ncc;
+    }
     return RMC_OK;
 }
 
@@ -1648,6 +1855,7 @@ struct Plan {
     int nfaces = 0, ntiles = 0, tile_cells = 0;
     uint64_t total_cells = 0, max_chunks = 0;
     bool inc_xz = true, pdf_mode = false;   // pdf_mode: per-ray probabilities (modes 1 and 2)
+    bool multigrid = false;                 // some snapshot marches on more than one grid
     int smode = 0;
     uint32_t cont_cap = 0;
 };
@@ -1665,13 +1873,16 @@ template <class Real> rmc_status plan_pipeline(rmc_ctx *const *ctxs, int nsnap, 
     P.pdf_mode = P.smode != RMC_SAMPLING_PLAIN;
     P.D.resize(nsnap);
     uint64_t total_ncpad = 0;
+    std::vector<double> &faces = L->h_faces;
+    faces.clear();
     for (int q = 0; q < nsnap; ++q) {
         if ((st = plan_snapshot<Real>(ctxs[q], P.D[q]))) return st;
-        P.D[q].face_off = P.nfaces;
-        P.nfaces += ctxs[q]->nx + ctxs[q]->ny + ctxs[q]->nz + 3;
+        append_faces(ctxs[q], P.D[q], faces);
         P.total_cells += ncells_of(ctxs[q]);
         total_ncpad += P.D[q].ncpad;
+        P.multigrid = P.multigrid || P.D[q].nlev > 1;
     }
+    P.nfaces = (int)faces.size();
     if ((size_t)P.nfaces * sizeof(double) > 48 * 1024)
         return fail(RMC_UNSUPPORTED, "face tables of all snapshots exceed 48 KiB of LDS");
     // tiles: about 1024 in total, whole bricks
@@ -1684,13 +1895,6 @@ template <class Real> rmc_status plan_pipeline(rmc_ctx *const *ctxs, int nsnap, 
         P.ntiles += P.D[q].ntiles;
         for (int t = 0; t < P.D[q].ntiles; ++t) tile_snap.push_back(q);
         P.inc_xz = P.inc_xz && P.D[q].hx > 0.0 && P.D[q].hz > 0.0;
-    }
-    std::vector<double> &faces = L->h_faces;
-    faces.clear();
-    for (int q = 0; q < nsnap; ++q) {
-        for (double v : ctxs[q]->xf) faces.push_back(v);
-        for (double v : ctxs[q]->yf) faces.push_back(v);
-        for (double v : ctxs[q]->zf) faces.push_back(v);
     }
     const uint64_t max_items = (P.total_cells * R + (uint64_t)nbucket * 63 + 63) / 64 * 64;
     P.max_chunks = max_items / 64;
@@ -1747,7 +1951,7 @@ rmc_status enqueue_pipeline(const Plan &P, double *const *divq, double *const *s
     if (EV) HIPCHK(hipEventRecord(EV->e[0], s));
     // 1-2. per-snapshot pdf and property fields
     for (int q = 0; q < nsnap; ++q)
-        if ((st = enqueue_snapshot<Real>(P.ctxs[q], P.D[q], s))) return st;
+        if ((st = enqueue_snapshot<Real>(P.ctxs[q], P.D[q], L->faces.as<double>(), s))) return st;
     if (EV) HIPCHK(hipEventRecord(EV->e[1], s));
 
     // 3. allocation: histogram per tile, scan per bucket, layout, scatter
@@ -1826,7 +2030,17 @@ rmc_status enqueue_pipeline(const Plan &P, double *const *divq, double *const *s
         else hipLaunchKernelGGL((k_march_lane<Real, PDF_, INC_, MULTI_, false>), dim3(mblocks), dim3(256),      \
                                 lds_faces, s, MA);                                                              \
     } while (0)
-    if (P.pdf_mode) {
+#define RMC_MARCH_MG(PDF_, INC_, MULTI_) \
+    hipLaunchKernelGGL((k_march_mg<Real, PDF_, INC_, MULTI_>), dim3(mblocks), dim3(256), lds_faces, s, MA)
+    if (P.multigrid) {
+        if (P.pdf_mode) {
+            if (P.inc_xz) { if (multi) RMC_MARCH_MG(true, true, true); else RMC_MARCH_MG(true, true, false); }
+            else { if (multi) RMC_MARCH_MG(true, false, true); else RMC_MARCH_MG(true, false, false); }
+        } else {
+            if (P.inc_xz) { if (multi) RMC_MARCH_MG(false, true, true); else RMC_MARCH_MG(false, true, false); }
+            else { if (multi) RMC_MARCH_MG(false, false, true); else RMC_MARCH_MG(false, false, false); }
+        }
+    } else if (P.pdf_mode) {
         if (P.inc_xz) { if (multi) RMC_MARCH(true, true, true); else RMC_MARCH(true, true, false); }
         else { if (multi) RMC_MARCH(true, false, true); else RMC_MARCH(true, false, false); }
     } else {
@@ -1834,10 +2048,11 @@ rmc_status enqueue_pipeline(const Plan &P, double *const *divq, double *const *s
         else { if (multi) RMC_MARCH(false, false, true); else RMC_MARCH(false, false, false); }
     }
 #undef RMC_MARCH
+#undef RMC_MARCH_MG
     HIPCHK(hipGetLastError());
     if (EV) HIPCHK(hipEventRecord(EV->e[3], s));
     if constexpr (sizeof(Real) == 4) {
-        if (segment && MA.cap < O.max_steps) {
+        if (segment && MA.cap < O.max_steps && !P.multigrid) {
             if (P.pdf_mode) {
                 if (multi) hipLaunchKernelGGL((k_march_long<true, true>), dim3(1024), dim3(256), lds_faces, s, MA);
                 else hipLaunchKernelGGL((k_march_long<true, false>), dim3(1024), dim3(256), lds_faces, s, MA);
@@ -2525,14 +2740,11 @@ rmc_status rmc_trace_cells(rmc_ctx *c, const int64_t *cells, int ncell, rmc_ray_
     SnapDesc D;
     rmc_status st = dbl ? plan_snapshot<double>(c, D) : plan_snapshot<float>(c, D);
     if (st) return st;
-    if ((st = dbl ? enqueue_snapshot<double>(c, D, s) : enqueue_snapshot<float>(c, D, s))) return st;
     const bool inc_xz = D.hx > 0.0 && D.hz > 0.0;
-    const int nfaces = c->nx + c->ny + c->nz + 3;
-    D.face_off = 0;
-    std::vector<double> fd;
-    for (double v : c->xf) fd.push_back(v);
-    for (double v : c->yf) fd.push_back(v);
-    for (double v : c->zf) fd.push_back(v);
+    std::vector<double> &fd = c->h_faces;
+    fd.clear();
+    append_faces(c, D, fd);
+    const int nfaces = (int)fd.size();
     const size_t nrec = (size_t)ncell * R;
     if ((st = c->faces.ensure(sizeof(double) * nfaces)) || (st = c->snaps.ensure(sizeof(SnapDesc))) ||
         (st = c->trace_cells.ensure(sizeof(int64_t) * ncell)) ||
@@ -2540,6 +2752,9 @@ rmc_status rmc_trace_cells(rmc_ctx *c, const int64_t *cells, int ncell, rmc_ray_
         return st;
     if (nfaces * 8 > 48 * 1024) return fail(RMC_UNSUPPORTED, "face tables exceed 48 KiB of LDS");
     HIPCHK(hipMemcpyAsync(c->faces.p, fd.data(), (size_t)nfaces * 8, hipMemcpyHostToDevice, s));
+    if ((st = dbl ? enqueue_snapshot<double>(c, D, c->faces.as<double>(), s)
+                  : enqueue_snapshot<float>(c, D, c->faces.as<double>(), s)))
+        return st;
     HIPCHK(hipMemcpyAsync(c->snaps.p, &D, sizeof(SnapDesc), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(c->trace_cells.p, cells, sizeof(int64_t) * ncell, hipMemcpyHostToDevice, s));
     const unsigned blocks = (unsigned)((nrec + 255) / 256);

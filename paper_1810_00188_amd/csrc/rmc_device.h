@@ -325,4 +325,42 @@ __device__ __forceinline__ bool ray_march(Ray<Real, INC_XZ> &R, const RayGeo &G,
     }
 }
 
+// Move a ray that stopped after its steps on one grid onto the next coarser grid G1 (every
+// other face of the current one; multigrid march of Sec. 4.3).  The ray stays at its point
+// on the face it last crossed; its cell becomes the coarse cell holding the current one.  A
+// next face of odd index is not a face of G1: the next G1 face along that axis lies one
+// current cell further.  With INC_XZ the x / z parameters advance by the current cell
+// increment and the increments double; otherwise all three are recomputed from G1's faces.
+template <class Real, bool INC_XZ>
+__device__ __forceinline__ void ray_descend(Ray<Real, INC_XZ> &R, const RayGeo &G1)
+{
+    if constexpr (sizeof(Real) == 4 && INC_XZ) {
+        if ((R.i + ((R.sgn & 1) ? 0 : 1)) & 1) R.tx += R.dtx;
+        if ((R.k + ((R.sgn & 4) ? 0 : 1)) & 1) R.tz += R.dtz;
+        R.dtx *= 2.0;
+        R.dtz *= 2.0;
+        R.i >>= 1;
+        R.k >>= 1;
+    } else {
+        R.i >>= 1;
+        R.k >>= 1;
+        const double fx = G1.xf[R.i + 1 - (R.sgn & 1)] + (double)R.wi * G1.Lx - R.ox;
+        const double fz = G1.zf[R.k + 1 - ((R.sgn >> 2) & 1)] + (double)R.wk * G1.Lz - R.oz;
+        if constexpr (sizeof(Real) == 4) {
+            R.tx = fx * R.rx;
+            R.tz = fz * R.rz;
+        } else {
+            R.tx = fx / R.rx;
+            R.tz = fz / R.rz;
+        }
+    }
+    R.j >>= 1;
+    const double fy = G1.yf[R.j + 1 - ((R.sgn >> 1) & 1)] - R.oy;
+    if constexpr (sizeof(Real) == 4) R.ty = fy * R.ry;
+    else R.ty = fy / R.ry;
+    R.px = brick_x(R.i, G1.bsx);
+    R.py = brick_y(R.j, G1.bsy);
+    R.pz = brick_z(R.k);
+}
+
 }  // namespace rmc

@@ -34,7 +34,8 @@ class Options(C.Structure):
                 ("accum", C.c_int), ("sampling", C.c_int), ("mix_eps", C.c_double),
                 ("block_threads", C.c_int32), ("long_ray_steps", C.c_int32),
                 ("xcd_span", C.c_int32), ("length_sort", C.c_int32),
-                ("bucket_order", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("bucket_order", C.c_int32), ("mg_levels", C.c_int32), ("mg_steps", C.c_int32),
+                ("reserved", C.c_int32 * 1)]
 
 
 class Stats(C.Structure):
@@ -262,7 +263,7 @@ class Solver:
         self.set_species(X)
         kw = dict(rays_per_cell=w.R, seed=w.seed, snapshot=w.snap, tol=w.tol,
                   max_steps=w.max_steps, march=F64 if w.march == "f64" else F32,
-                  accum=ACC[w.accum])
+                  accum=ACC[w.accum], mg_levels=getattr(w, "mg_levels", 1), mg_steps=getattr(w, "mg_steps", 5))
         kw.update(opt_overrides)
         self.set_options(default_options(**kw))
 

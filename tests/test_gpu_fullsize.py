@@ -19,7 +19,7 @@ if not torch.cuda.is_available():
 
 import oracle  # noqa: E402
 from paper_1810_00188_amd import inputs, rmc  # noqa: E402
-from test_gpu_parity import _check_fp32_rays, say  # noqa: E402
+from _parity import _check_fp32_rays, say  # noqa: E402
 
 
 def _options(w, **over):

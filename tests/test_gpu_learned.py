@@ -26,7 +26,7 @@ if not torch.cuda.is_available():
 import oracle  # noqa: E402
 from oracle import mlp  # noqa: E402
 from paper_1810_00188_amd import inputs, rmc  # noqa: E402
-from test_gpu_parity import say  # noqa: E402
+from _parity import say  # noqa: E402
 
 U_BF16 = 2.0 ** -8
 

@@ -14,84 +14,8 @@ if not torch.cuda.is_available():
 import oracle  # noqa: E402
 from paper_1810_00188_amd import inputs, rmc  # noqa: E402
 
-TOL64 = 1e-12
-TOL32 = 1e-5
-
-
-def say(msg):
-    print(f"[gpu-case] {msg}", flush=True)
-
-
-def _solver(w, **kw):
-    s = rmc.Solver(0)
-    s.set_workload(w, **kw)
-    return s
-
-
-def _ray_errors(Yg, ref):
-    scale = np.maximum(ref["absY"], 1e-300)
-    return np.abs(Yg - ref["Y"]) / scale
-
-
-def _threshold_scale(w, ref, cells):
-    """Per ray, tol * w * kappa_src * max_j |I_src - I_j|: the most a ray's value can change
-    when the march takes one step more or less at the tau = tol threshold (the step count is
-    a float decision taken in FP32 by the kernel and in FP64 by the oracle)."""
-    from oracle.closed_forms import table_lerp
-    kd = w.kd
-    cells = np.asarray(cells)
-    Tc = w.T[cells][:, None]
-    n, g = ref["n"], ref["g"]
-    I_all = table_lerp(kd.Ib, kd.T0, kd.dT, np.concatenate([w.T, w.T_walls]))   # [nb, nc+2]
-    Imax, Imin = I_all.max(axis=1), I_all.min(axis=1)
-    Isrc = np.empty(n.shape)
-    kap = np.zeros(n.shape)
-    for b in range(kd.nb):
-        m = n == b
-        Isrc[m] = np.broadcast_to(table_lerp(kd.Ib[b], kd.T0, kd.dT, Tc), n.shape)[m]
-        for gg in range(kd.ng):
-            mg = m & (g == gg)
-            for sp in range(kd.ns):
-                ks = table_lerp(kd.k[sp, b, gg].astype(float), kd.T0, kd.dT, Tc)
-                kap[mg] += np.broadcast_to(w.X[sp][cells][:, None] * ks, n.shape)[mg]
-    dI = np.maximum(np.abs(Imax[n] - Isrc), np.abs(Isrc - Imin[n]))
-    wgt = 4 * np.pi * kd.dnu[n] * kd.wg[g] / (8 * ref["p"])
-    return w.tol * wgt * kap * dI
-
-
-def _check_fp32_rays(w, cells, Yg, steps_g, ref):
-    """Rays with the oracle's step count: within TOL32 of their scale, plus a rounding floor
-    of 2^-52 w kappa max|dI|: the oracle updates tau as tau (1 - alpha) (Eq. 3), which is
-    exactly 0 once alpha rounds to 1 in FP64 (e^-x < 2^-54), where the FP32 march keeps
-    the transmission e^-x itself, so a later term (a wall, the residual) may differ by at
-    most that much.  Rays whose count differs (threshold or exact-tie cases): rare, and
-    within TOL32 plus 2x the threshold scale."""
-    err = _ray_errors(Yg, ref)
-    same = steps_g == ref["steps"]
-    thr = _threshold_scale(w, ref, cells)
-    floor = thr * (2.0 ** -52 / w.tol)
-    diff = np.abs(Yg - ref["Y"])
-    bad_same = np.sum(diff[same] > TOL32 * ref["absY"][same] + floor[same])
-    bad_diff = np.sum(diff[~same] > TOL32 * ref["absY"][~same] + 2 * thr[~same])
-    frac = np.mean(~same)
-    big = same & (ref["absY"] > 1e-12 * ref["absY"].max())
-    say(f"fp32 rays: same-step max rel err {err[big].max() if big.any() else 0.0:.3e}, step mismatches {frac:.2e} "
-        f"({np.sum(~same)}), out of bound: {bad_same} + {bad_diff}")
-    bad = np.argwhere((same & (diff > TOL32 * ref["absY"] + floor)) |
-                      (~same & (diff > TOL32 * ref["absY"] + 2 * thr)))
-    for a, r in bad[:8]:
-        x = ref[a, r]
-        say(f"  cell {np.asarray(cells)[a]} ray {r}: gpu {Yg[a, r]!r} steps {steps_g[a, r]} | oracle Y {x['Y']!r} "
-            f"absY {x['absY']!r} steps {x['steps']} n {x['n']} g {x['g']} o {x['o']} k {x['k']} end {x['end']}")
-    assert bad_same == 0 and bad_diff == 0
-    assert frac < 1e-3
-
-
-def _small_channel(march="f64", **kw):
-    base = dict(nx=10, ny=7, nz=6, R=12, nb=5, ng=3, amp=0.1, stretch=2.0, species_amp=0.2,
-                co2=True, march=march)
-    base.update(kw)
-    return inputs.channel(**base).replace(T_walls=(350.0, 900.0))
+from _parity import (TOL32, TOL64, _check_fp32_rays, _ray_errors, _small_channel,  # noqa: E402
+                     _solver, say)
 
 
 # ----------------------------------------------------------------------- spectral pdf
@@ -342,7 +266,7 @@ def test_errors_are_reported_not_fatal():
         s.set_species(X)
     assert e.value.status == rmc.RMC_OUT_OF_RANGE
     for bad in (dict(rays_per_cell=0), dict(xcd_span=2), dict(xcd_span=48), dict(long_ray_steps=-1),
-                dict(length_sort=2)):
+                dict(length_sort=2), dict(mg_levels=-2), dict(mg_levels=9), dict(mg_steps=-1)):
         with pytest.raises(rmc.RmcError) as e:
             s.set_options(rmc.default_options(**bad))
         assert e.value.status == rmc.RMC_INVALID_ARG, bad
