@@ -630,7 +630,8 @@ inline uint64_t xcd_blocks(uint64_t max_chunks, int span_log2)
 // State of a ray handed from the lane kernel to k_march_long after `steps` steps.
 struct ContRec {
     uint32_t q;                 // work item index
-    int i, j, k, steps;         // cell of the next step
+    int lev;                    // grid level the ray is on (multigrid march; 0 otherwise)
+    int i, j, k, steps;         // cell of the next step (on that level)
     double tau, acc;
     double t, tx, ty, tz;       // current parameter, next-face parameters
 };
@@ -665,23 +666,42 @@ __device__ __forceinline__ RayGeo ray_geo_level(const SnapDesc &D, const double 
     return G;
 }
 
+// Property planes of grid level L for (band, g) pair `pair` of band n.
+template <class Real>
+__device__ __forceinline__ void level_planes(const SnapDesc &D, int L, int pair, int n, const Real *&K,
+                                             const double *&Ipl)
+{
+    if (L == 0) {
+        K = reinterpret_cast<const Real *>(D.kap) + (size_t)pair * D.ncpad;
+        Ipl = D.Ipl + (size_t)n * D.ncpad;
+    } else {
+        K = reinterpret_cast<const Real *>(D.mg_kap) + (size_t)pair * D.mg_stride + D.lev_off[L];
+        Ipl = D.mg_I + (size_t)n * D.mg_stride + D.lev_off[L];
+    }
+}
+
 // Multigrid march (Sec. 4.3): mg_steps steps on each grid, then the ray goes on from its
 // current point in the coarser cell that holds its cell, and runs to depletion on the last
-// grid.  Source kappa and intensity stay those of the DNS cell (k0, I0 on entry).
+// grid.  Source kappa and intensity stay those of the DNS cell (k0, I0 on entry).  On the
+// last grid the ray stops after last_cap steps in all (returns false; R then holds its state
+// on that grid), else returns true when finished.
 template <class Real, bool INC_XZ>
-__device__ __forceinline__ void march_levels(Ray<Real, INC_XZ> &R, const SnapDesc &D, const double *sf, int pair,
-                                             int n, int nb, Real tol, int max_steps, Real k0, double I0)
+__device__ __forceinline__ bool march_levels(Ray<Real, INC_XZ> &R, const SnapDesc &D, const double *sf, int pair,
+                                             int n, int nb, Real tol, int max_steps, Real k0, double I0,
+                                             int last_cap)
 {
     RayGeo G = ray_geo(D, sf);
-    const Real *K = reinterpret_cast<const Real *>(D.kap) + (size_t)pair * D.ncpad;
-    const double *Ipl = D.Ipl + (size_t)n * D.ncpad;
+    const Real *K;
+    const double *Ipl;
+    level_planes<Real>(D, 0, pair, n, K, Ipl);
     for (int L = 0;; ++L) {
-        const int cap = L + 1 < D.nlev ? D.mg_steps * (L + 1) : max_steps;
-        if (ray_march(R, G, K, Ipl, D.Iw + n, D.Iw + nb + n, tol, max_steps, k0, I0, cap)) return;
+        const bool last = L + 1 >= D.nlev;
+        const int cap = last ? last_cap : D.mg_steps * (L + 1);
+        if (ray_march(R, G, K, Ipl, D.Iw + n, D.Iw + nb + n, tol, max_steps, k0, I0, cap)) return true;
+        if (last) return false;
         G = ray_geo_level(D, sf, L + 1);
         ray_descend(R, G);
-        K = reinterpret_cast<const Real *>(D.mg_kap) + (size_t)pair * D.mg_stride + D.lev_off[L + 1];
-        Ipl = D.mg_I + (size_t)n * D.mg_stride + D.lev_off[L + 1];
+        level_planes<Real>(D, L + 1, pair, n, K, Ipl);
         const int cell = R.px + R.py + R.pz;
         k0 = gld(K + cell);
         I0 = gld(Ipl + cell);
@@ -806,6 +826,7 @@ __global__ void __launch_bounds__(256) k_march_lane(MarchArgs<Real> A)
         if (idx < A.cont_cap) {
             ContRec rc;
             rc.q = q;
+            rc.lev = 0;
             rc.i = R.i; rc.j = R.j; rc.k = R.k; rc.steps = R.steps;
             rc.tau = R.tau; rc.acc = R.acc;
             rc.t = R.t; rc.tx = R.tx; rc.ty = R.ty; rc.tz = R.tz;
@@ -827,8 +848,8 @@ __global__ void __launch_bounds__(256) k_march_lane(MarchArgs<Real> A)
     store_slot<Real>(D, slot, w * (double)kap_src * (double)R.acc, (uint32_t)R.steps | ((uint32_t)R.end << 28));
 }
 
-// Multigrid march: one ray per lane as in k_march_lane (no length sort, no long-ray hand-off:
-// the coarse grids keep even the least absorbed rays short).
+// Multigrid march: one ray per lane as in k_march_lane (no length sort).  A ray still marching
+// after `cap` steps on the last grid is handed to k_march_long, which continues it there.
 template <class Real, bool PDF, bool INC_XZ, bool MULTI>
 __global__ void __launch_bounds__(256) k_march_mg(MarchArgs<Real> A)
 {
@@ -862,7 +883,25 @@ __global__ void __launch_bounds__(256) k_march_mg(MarchArgs<Real> A)
     Real kap_src;
     double Isrc;
     ray_init(R, G, U, K, Ipl, i, j, k, dx, dy, dz, kap_src, Isrc);
-    march_levels(R, D, sf, pair, n, A.nb, A.tol, A.max_steps, kap_src, Isrc);
+    const int last_cap = (int)min((long)A.cap + (long)D.mg_steps * (D.nlev - 1), (long)A.max_steps);
+    if (!march_levels(R, D, sf, pair, n, A.nb, A.tol, A.max_steps, kap_src, Isrc, last_cap)) {
+        const uint32_t idx = atomicAdd(A.cont_count, 1u);
+        if (idx < A.cont_cap) {
+            ContRec rc;
+            rc.q = q;
+            rc.lev = D.nlev - 1;
+            rc.i = R.i; rc.j = R.j; rc.k = R.k; rc.steps = R.steps;
+            rc.tau = R.tau; rc.acc = R.acc;
+            rc.t = R.t; rc.tx = R.tx; rc.ty = R.ty; rc.tz = R.tz;
+            A.cont[idx] = rc;
+            return;
+        }
+        const RayGeo GL = ray_geo_level(D, sf, D.nlev - 1);
+        level_planes<Real>(D, D.nlev - 1, pair, n, K, Ipl);
+        const int cell = R.px + R.py + R.pz;
+        ray_march(R, GL, K, Ipl, D.Iw + n, D.Iw + A.nb + n, A.tol, A.max_steps, gld(K + cell), gld(Ipl + cell),
+                  A.max_steps);
+    }
     const size_t slot = (size_t)c * A.R + r;
     double w;
     if constexpr (!PDF) {
@@ -903,7 +942,7 @@ __global__ void __launch_bounds__(256) k_march_long(MarchArgs<float> A)
         const uint32_t b = gld(A.chunk_bucket + (rc.q >> 6));
         const int s = MULTI ? (int)((it.y >> 16) & 0x7FFF) : 0;
         const SnapDesc &D = A.snaps[s];
-        const RayGeo G = ray_geo(D, sf);
+        const RayGeo G0 = ray_geo(D, sf);
         XzUniform U;
         U.hx = D.hx;
         U.hz = D.hz;
@@ -911,15 +950,26 @@ __global__ void __launch_bounds__(256) k_march_long(MarchArgs<float> A)
         const int r = (int)(it.y & 255);
         const int o = (int)(b & 7), pair = (int)(b >> 3);
         const int n = pair / A.ng;
-        const float *K = reinterpret_cast<const float *>(D.kap) + (size_t)pair * D.ncpad;
-        const double *Ipl = D.Ipl + (size_t)n * D.ncpad;
+        const float *K;
+        const double *Ipl;
+        level_planes<float>(D, 0, pair, n, K, Ipl);
         const uint32_t c = (uint32_t)(((uint64_t)ci * D.ny + cj) * D.nz + ck);
         double dx, dy, dz;
         octant_direction(it.z, it.w, o, dx, dy, dz);
         Ray<float, true> R;
         float kap_src;
         double Isrc;
-        ray_init(R, G, U, K, Ipl, ci, cj, ck, dx, dy, dz, kap_src, Isrc);
+        ray_init(R, G0, U, K, Ipl, ci, cj, ck, dx, dy, dz, kap_src, Isrc);
+        // continue on the ray's grid level (multigrid): its geometry, planes and increments
+        const RayGeo G = rc.lev ? ray_geo_level(D, sf, rc.lev) : G0;
+        if (rc.lev) {
+            level_planes<float>(D, rc.lev, pair, n, K, Ipl);
+            const double sc = (double)(1 << rc.lev);
+            U.hx *= sc;
+            U.hz *= sc;
+            R.dtx *= sc;
+            R.dtz *= sc;
+        }
         const bool ax = fabs(dx) >= fabs(dz);            // the crossing axis
         const double dta = ax ? R.dtx : R.dtz;
         const double tw = (((dy > 0.0) ? G.yf[G.ny] : G.yf[0]) - R.oy) * R.ry;   // the wall
@@ -1135,7 +1185,7 @@ __global__ void __launch_bounds__(256) k_trace(TraceArgs<Real> A)
     Real kap_src;
     double Isrc;
     ray_init(R, G, U, K, Ipl, i, j, k, dx, dy, dz, kap_src, Isrc);
-    if (D.nlev > 1) march_levels(R, D, sf, pair, d.n, A.nb, A.tol, A.max_steps, kap_src, Isrc);
+    if (D.nlev > 1) march_levels(R, D, sf, pair, d.n, A.nb, A.tol, A.max_steps, kap_src, Isrc, A.max_steps);
     else ray_march(R, G, K, Ipl, D.Iw + d.n, D.Iw + A.nb + d.n, A.tol, A.max_steps, kap_src, Isrc, A.max_steps);
     const double w = 4.0 * M_PI * A.dnu[d.n] * A.wg[d.g] / (8.0 * d.p);
     rmc_ray_record rec;
@@ -2052,7 +2102,7 @@ rmc_status enqueue_pipeline(const Plan &P, double *const *divq, double *const *s
     HIPCHK(hipGetLastError());
     if (EV) HIPCHK(hipEventRecord(EV->e[3], s));
     if constexpr (sizeof(Real) == 4) {
-        if (segment && MA.cap < O.max_steps && !P.multigrid) {
+        if (segment && MA.cap < O.max_steps) {
             if (P.pdf_mode) {
                 if (multi) hipLaunchKernelGGL((k_march_long<true, true>), dim3(1024), dim3(256), lds_faces, s, MA);
                 else hipLaunchKernelGGL((k_march_long<true, false>), dim3(1024), dim3(256), lds_faces, s, MA);
