@@ -32,7 +32,7 @@ GCC_CMD = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-ffp-contract=off", "-fop
            "-fPIC", "-shared", "-Wall", SRC, "-o", LIB, "-lm"]
 
 ERRORS = {0: "ok", 1: "invalid argument", 3: "temperature outside the table range",
-          4: "unsupported (non-black wall)"}
+          4: "unsupported"}
 
 
 def build() -> str:
@@ -77,7 +77,9 @@ class _Problem(C.Structure):
                 ("R", C.c_int), ("seed", C.c_uint64), ("snap", C.c_uint32),
                 ("tol", C.c_double), ("max_steps", C.c_int),
                 ("q_cell", C.c_void_p), ("mix_eps", C.c_double),
-                ("mg_levels", C.c_int), ("mg_steps", C.c_int)]
+                ("mg_levels", C.c_int), ("mg_steps", C.c_int),
+                ("closed", C.c_int), ("Tx", C.c_double * 2), ("epsx", C.c_double * 2),
+                ("Tz", C.c_double * 2), ("epsz", C.c_double * 2)]
 
 
 class _MarchOut(C.Structure):
@@ -137,6 +139,11 @@ class Problem:
         s.mix_eps = float(mix_eps)
         s.mg_levels = int(getattr(w, "mg_levels", 1) if mg_levels is None else mg_levels)
         s.mg_steps = int(getattr(w, "mg_steps", 5) if mg_steps is None else mg_steps)
+        s.closed = int(bool(getattr(w, "closed", False)))
+        if s.closed:
+            for q in range(2):
+                s.Tx[q], s.epsx[q] = float(w.T_walls_x[q]), float(w.eps_walls_x[q])
+                s.Tz[q], s.epsz[q] = float(w.T_walls_z[q]), float(w.eps_walls_z[q])
         self.s = s
         self.nx, self.ny, self.nz = s.nx, s.ny, s.nz
         self.ncells = s.nx * s.ny * s.nz

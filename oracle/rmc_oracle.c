@@ -31,7 +31,10 @@
  *      U_a(w) = (w + 0.5) 2^-32 (exact in double, decisions taken in double); the direction
  *      draws use U_d(w) = ((w >> 9) + 0.5) 2^-23, exact in float and double; neither is
  *      ever 0 or 1;
- *   R4 walls (y = y_0, y = y_ny) are black: one wall term with alpha = 1, I = I_b(T_wall);
+ *   R4 walls (y = y_0 and y = y_ny; in a closed box also x and z, R15) absorb the fraction
+ *      eps_w of the transmissivity that reaches them and emit I_b(T_wall): one wall term
+ *      tau eps_w (I_src - I_b(T_wall)), then tau *= 1 - eps_w (the wall factor of Eq. 3);
+ *      a black wall (eps_w = 1) ends the ray;
  *   R5 ties between face crossings step all tied axes together (vector compare);
  *   R6 temperatures outside the table range are an error (no clamping);
  *   R7 mixture: kappa_{n,g} = sum_s x_s k^s_{n,g}(T) on a shared g grid;
@@ -45,6 +48,12 @@
  *       and its direction is drawn inside that octant; together isotropic;
  *   R13 if nothing emits at T_max (sum of e_{n,g} is zero) the pdf is uniform over (n,g):
  *       every ray value is then zero and any positive pdf gives that exactly.
+ *   R14 the reflection law of Eq. 3 is not stated: the part 1 - eps_w of a ray goes on by
+ *       specular reflection -- the origin and the direction component are mirrored on the
+ *       wall plane, so the ray keeps its parameter and goes on from the point it hit, in the
+ *       cell next to the wall; walls hit at the same point are taken in the order x, y, z;
+ *   R15 closed box (Cases 3-4 and 12 of Table 1): x and z bounded by walls as y is, each of
+ *       the six walls with its own temperature and emissivity; otherwise x and z are periodic.
  *
  * Multigrid march (Sec. 4.3 and the grid counts of Sec. 5), readings:
  *   M1 levels: coarsening ratio 2 on every axis together; a further level exists while every
@@ -98,6 +107,9 @@ typedef struct {
     double mix_eps;               /* weight of the plain pdf mixed into q_cell */
     int mg_levels;                /* grid levels of the multigrid march (M1); <= 1: DNS grid only */
     int mg_steps;                 /* steps per level before the next coarser one (M3) */
+    int closed;                   /* R15: walls on x and z too (else periodic) */
+    double Tx[2], epsx[2];        /* closed box: walls at x = xf[0], x = xf[nx] */
+    double Tz[2], epsz[2];        /* closed box: walls at z = zf[0], z = zf[nz] */
 } orc_problem;
 
 typedef struct {
@@ -106,7 +118,8 @@ typedef struct {
     double p;        /* probability p(n,g,o) the ray was drawn with */
     int n, g, o, k;  /* band, g-point, octant, ordinal among equal (n,g,o) of the cell */
     int steps;       /* ray-cell steps (DDA segments) */
-    int end;         /* 0: tau <= tol, 1: wall at y0, 2: wall at y1, 3: step cap */
+    int end;         /* 0: tau <= tol, 1 / 2: black wall at y0 / y1, 3: step cap,
+                        4 / 5: black wall at x0 / x1, 6 / 7: black wall at z0 / z1 */
 } orc_ray;
 
 /* ------------------------------------------------------------------ Philox4x32-10
@@ -201,6 +214,11 @@ int orc_plain_pdf(const orc_problem *P, double *p, double *cdf_b, double *cdf_g,
 {
     size_t nc = ncells_of(P);
     double Tmax = P->Tw[0] > P->Tw[1] ? P->Tw[0] : P->Tw[1];
+    if (P->closed)
+        for (int q = 0; q < 2; ++q) {
+            if (P->Tx[q] > Tmax) Tmax = P->Tx[q];
+            if (P->Tz[q] > Tmax) Tmax = P->Tz[q];
+        }
     for (size_t c = 0; c < nc; ++c)
         if (P->T[c] > Tmax) Tmax = P->T[c];
     double *xhat = (double *)malloc(sizeof(double) * (P->ns > 0 ? P->ns : 1));
@@ -274,31 +292,72 @@ static double face_coord(const double *f, int n, int local, int wrap)
     return f[local] + (double)wrap * (f[n] - f[0]);
 }
 
+/* Wall (axis a: 0 x, 1 y, 2 z; side 0 low, 1 high): temperature, emissivity, end code. */
+static void wall_of(const orc_problem *P, int a, int side, double *Tw, double *eps, int *code)
+{
+    if (a == 1) { *Tw = P->Tw[side]; *eps = P->epsw[side]; *code = 1 + side; }
+    else if (a == 0) { *Tw = P->Tx[side]; *eps = P->epsx[side]; *code = 4 + side; }
+    else { *Tw = P->Tz[side]; *eps = P->epsz[side]; *code = 6 + side; }
+}
+
+/* Wall terms of the walls the last step ended on (hit[a]: 0 none, 1 low, 2 high), in the
+ * order x, y, z (R4, R14): tau eps (I_src - I_w) each, tau *= 1 - eps; the ray is mirrored
+ * on every reflecting wall (cell index back to the wall cell, origin and direction component
+ * mirrored, next-face parameter of that axis from the mirrored origin).  Returns 1 when a
+ * black wall ends the ray (*end set), 0 otherwise, or an error code in *err. */
+static int walls(const orc_problem *P, int n, const int hit[3], const int nn[3], const double *const f[3],
+                 int idx[3], const int wrap[3], double o[3], double dd[3], int sg[3], double tn[3], double Isrc,
+                 double *tau, double *acc, double *absacc, int *end, int *err)
+{
+    for (int a = 0; a < 3; ++a) {
+        if (!hit[a]) continue;
+        const int side = hit[a] - 1;
+        double Tw, eps, Iw;
+        int code;
+        wall_of(P, a, side, &Tw, &eps, &code);
+        if ((*err = planck_at(P, n, Tw, &Iw))) return 0;
+        *acc += *tau * eps * (Isrc - Iw);
+        *absacc += *tau * eps * fabs(Isrc - Iw);
+        *tau *= 1.0 - eps;
+        if (eps == 1.0) { *end = code; return 1; }
+        idx[a] = side ? nn[a] - 1 : 0;                          /* R14 */
+        o[a] = 2.0 * f[a][side ? nn[a] : 0] - o[a];
+        dd[a] = -dd[a];
+        sg[a] = -sg[a];
+        tn[a] = (face_coord(f[a], nn[a], idx[a] + (sg[a] > 0), wrap[a]) - o[a]) / dd[a];
+    }
+    return 0;
+}
+
 /* March one ray from the centre of cell (ci,cj,ck) (R1) along unit direction d for band n,
- * g-point g.  x and z are periodic, y is bounded by black walls (R4).  If rec_cells is
- * non-null, the natural index and the segment length of each step are recorded. */
+ * g-point g.  x and z are periodic unless the box is closed (R15); walls per R4 and R14.  If
+ * rec_cells is non-null, the natural index and the segment length of each step are
+ * recorded. */
 int orc_march(const orc_problem *P, int ci, int cj, int ck, int n, int g, const double d[3],
               orc_march_out *res, int64_t *rec_cells, double *rec_ds, int rec_max)
 {
-    const int nx = P->nx, ny = P->ny, nz = P->nz;
-    size_t csrc = ((size_t)ci * ny + cj) * nz + ck;
+    const int nn[3] = {P->nx, P->ny, P->nz};
+    const double *const f[3] = {P->xf, P->yf, P->zf};
+    const int per[3] = {!P->closed, 0, !P->closed};
+    size_t csrc = ((size_t)ci * nn[1] + cj) * nn[2] + ck;
     double o[3] = {0.5 * (P->xf[ci] + P->xf[ci + 1]), 0.5 * (P->yf[cj] + P->yf[cj + 1]),
                    0.5 * (P->zf[ck] + P->zf[ck + 1])};
-    int sx = d[0] > 0.0 ? 1 : -1, sy = d[1] > 0.0 ? 1 : -1, sz = d[2] > 0.0 ? 1 : -1;
-    int i = ci, j = cj, kk = ck, wi = 0, wk = 0;
-    double tx = (face_coord(P->xf, nx, i + (sx > 0), wi) - o[0]) / d[0];
-    double ty = (P->yf[j + (sy > 0)] - o[1]) / d[1];
-    double tz = (face_coord(P->zf, nz, kk + (sz > 0), wk) - o[2]) / d[2];
+    double dd[3] = {d[0], d[1], d[2]}, tn[3];
+    int idx[3] = {ci, cj, ck}, wrap[3] = {0, 0, 0}, sg[3];
+    for (int a = 0; a < 3; ++a) {
+        sg[a] = dd[a] > 0.0 ? 1 : -1;
+        tn[a] = (face_coord(f[a], nn[a], idx[a] + (sg[a] > 0), wrap[a]) - o[a]) / dd[a];
+    }
     double Isrc, Ilast, t = 0.0, tau = 1.0, acc = 0.0, absacc = 0.0;
     int e = cell_planck(P, csrc, n, &Isrc);
     if (e) return e;
     Ilast = Isrc;
     int steps = 0, end = 0;
     while (tau > P->tol && steps < P->max_steps) {
-        double te = tx < ty ? tx : ty;
-        if (tz < te) te = tz;
+        double te = tn[0] < tn[1] ? tn[0] : tn[1];
+        if (tn[2] < te) te = tn[2];
         double ds = te - t;
-        size_t c = ((size_t)i * ny + j) * nz + kk;
+        size_t c = ((size_t)idx[0] * nn[1] + idx[1]) * nn[2] + idx[2];
         double kap, Ij;
         if ((e = cell_kappa(P, c, n, g, &kap)) || (e = cell_planck(P, c, n, &Ij))) return e;
         double alpha = -expm1(-kap * ds);                        /* Eq. 2, R10 */
@@ -309,33 +368,23 @@ int orc_march(const orc_problem *P, int ci, int cj, int ck, int n, int g, const 
         ++steps;
         t = te;
         Ilast = Ij;
-        int wall = 0;
-        if (tx == te) {                                          /* R5 */
-            i += sx;
-            if (i == nx) { i = 0; ++wi; }
-            if (i < 0) { i = nx - 1; --wi; }
-            tx = (face_coord(P->xf, nx, i + (sx > 0), wi) - o[0]) / d[0];
+        int hit[3] = {0, 0, 0};
+        for (int a = 0; a < 3; ++a) {                            /* R5: every tied axis steps */
+            if (tn[a] != te) continue;
+            idx[a] += sg[a];
+            if (per[a]) {
+                if (idx[a] == nn[a]) { idx[a] = 0; ++wrap[a]; }
+                if (idx[a] < 0) { idx[a] = nn[a] - 1; --wrap[a]; }
+            } else if (idx[a] < 0 || idx[a] >= nn[a]) {
+                hit[a] = idx[a] < 0 ? 1 : 2;
+                continue;
+            }
+            tn[a] = (face_coord(f[a], nn[a], idx[a] + (sg[a] > 0), wrap[a]) - o[a]) / dd[a];
         }
-        if (ty == te) {
-            j += sy;
-            if (j < 0) wall = 1;
-            else if (j >= ny) wall = 2;
-            else ty = (P->yf[j + (sy > 0)] - o[1]) / d[1];
-        }
-        if (tz == te) {
-            kk += sz;
-            if (kk == nz) { kk = 0; ++wk; }
-            if (kk < 0) { kk = nz - 1; --wk; }
-            tz = (face_coord(P->zf, nz, kk + (sz > 0), wk) - o[2]) / d[2];
-        }
-        if (wall) {                                              /* R4, Eq. 3 wall factor */
-            double Iw, eps = P->epsw[wall - 1];
-            if ((e = planck_at(P, n, P->Tw[wall - 1], &Iw))) return e;
-            acc += tau * eps * (Isrc - Iw);
-            absacc += tau * eps * fabs(Isrc - Iw);
-            tau *= 1.0 - eps;
-            end = wall;
-            break;
+        if (hit[0] | hit[1] | hit[2]) {
+            int stop = walls(P, n, hit, nn, f, idx, wrap, o, dd, sg, tn, Isrc, &tau, &acc, &absacc, &end, &e);
+            if (e) return e;
+            if (stop) break;
         }
     }
     if (end == 0 && steps >= P->max_steps && tau > P->tol) end = 3;
@@ -453,16 +502,18 @@ static int march_levels(const orc_problem *P, const orc_levels *G, int ci, int c
                         const double d[3], orc_march_out *res, int64_t *rec_cells, double *rec_ds, int rec_max)
 {
     int L = 0, lsteps = 0;
-    int nx = G->n[0][0], ny = G->n[0][1], nz = G->n[0][2];
-    const double *xf = G->f[0][0], *yf = G->f[0][1], *zf = G->f[0][2];
+    int nn[3] = {G->n[0][0], G->n[0][1], G->n[0][2]};
+    const double *f[3] = {G->f[0][0], G->f[0][1], G->f[0][2]};
+    const int per[3] = {!P->closed, 0, !P->closed};
     size_t csrc = ((size_t)ci * P->ny + cj) * P->nz + ck;
     double o[3] = {0.5 * (P->xf[ci] + P->xf[ci + 1]), 0.5 * (P->yf[cj] + P->yf[cj + 1]),
                    0.5 * (P->zf[ck] + P->zf[ck + 1])};
-    int sx = d[0] > 0.0 ? 1 : -1, sy = d[1] > 0.0 ? 1 : -1, sz = d[2] > 0.0 ? 1 : -1;
-    int i = ci, j = cj, kk = ck, wi = 0, wk = 0;
-    double tx = (face_coord(xf, nx, i + (sx > 0), wi) - o[0]) / d[0];
-    double ty = (yf[j + (sy > 0)] - o[1]) / d[1];
-    double tz = (face_coord(zf, nz, kk + (sz > 0), wk) - o[2]) / d[2];
+    double dd[3] = {d[0], d[1], d[2]}, tn[3];
+    int idx[3] = {ci, cj, ck}, wrap[3] = {0, 0, 0}, sg[3];
+    for (int a = 0; a < 3; ++a) {
+        sg[a] = dd[a] > 0.0 ? 1 : -1;
+        tn[a] = (face_coord(f[a], nn[a], idx[a] + (sg[a] > 0), wrap[a]) - o[a]) / dd[a];
+    }
     double Isrc, Ilast, t = 0.0, tau = 1.0, acc = 0.0, absacc = 0.0;
     int e = cell_planck(P, csrc, n, &Isrc);
     if (e) return e;
@@ -472,17 +523,17 @@ static int march_levels(const orc_problem *P, const orc_levels *G, int ci, int c
         if (L + 1 < G->nlev && lsteps == P->mg_steps) {         /* M3: fall onto the coarser grid */
             ++L;
             lsteps = 0;
-            nx = G->n[L][0]; ny = G->n[L][1]; nz = G->n[L][2];
-            xf = G->f[L][0]; yf = G->f[L][1]; zf = G->f[L][2];
-            i /= 2; j /= 2; kk /= 2;
-            tx = (face_coord(xf, nx, i + (sx > 0), wi) - o[0]) / d[0];
-            ty = (yf[j + (sy > 0)] - o[1]) / d[1];
-            tz = (face_coord(zf, nz, kk + (sz > 0), wk) - o[2]) / d[2];
+            for (int a = 0; a < 3; ++a) {
+                nn[a] = G->n[L][a];
+                f[a] = G->f[L][a];
+                idx[a] /= 2;
+                tn[a] = (face_coord(f[a], nn[a], idx[a] + (sg[a] > 0), wrap[a]) - o[a]) / dd[a];
+            }
         }
-        double te = tx < ty ? tx : ty;
-        if (tz < te) te = tz;
+        double te = tn[0] < tn[1] ? tn[0] : tn[1];
+        if (tn[2] < te) te = tn[2];
         double ds = te - t;
-        size_t c = ((size_t)i * ny + j) * nz + kk, ncl = (size_t)nx * ny * nz;
+        size_t c = ((size_t)idx[0] * nn[1] + idx[1]) * nn[2] + idx[2], ncl = (size_t)nn[0] * nn[1] * nn[2];
         double kap, Ij;
         if ((e = kappa_at(P, n, g, G->T[L][c], G->X[L] + c, ncl, &kap)) ||
             (e = planck_at(P, n, G->T[L][c], &Ij)))
@@ -496,33 +547,23 @@ static int march_levels(const orc_problem *P, const orc_levels *G, int ci, int c
         ++lsteps;
         t = te;
         Ilast = Ij;
-        int wall = 0;
-        if (tx == te) {                                          /* R5 */
-            i += sx;
-            if (i == nx) { i = 0; ++wi; }
-            if (i < 0) { i = nx - 1; --wi; }
-            tx = (face_coord(xf, nx, i + (sx > 0), wi) - o[0]) / d[0];
+        int hit[3] = {0, 0, 0};
+        for (int a = 0; a < 3; ++a) {                            /* R5 */
+            if (tn[a] != te) continue;
+            idx[a] += sg[a];
+            if (per[a]) {
+                if (idx[a] == nn[a]) { idx[a] = 0; ++wrap[a]; }
+                if (idx[a] < 0) { idx[a] = nn[a] - 1; --wrap[a]; }
+            } else if (idx[a] < 0 || idx[a] >= nn[a]) {
+                hit[a] = idx[a] < 0 ? 1 : 2;
+                continue;
+            }
+            tn[a] = (face_coord(f[a], nn[a], idx[a] + (sg[a] > 0), wrap[a]) - o[a]) / dd[a];
         }
-        if (ty == te) {
-            j += sy;
-            if (j < 0) wall = 1;
-            else if (j >= ny) wall = 2;
-            else ty = (yf[j + (sy > 0)] - o[1]) / d[1];
-        }
-        if (tz == te) {
-            kk += sz;
-            if (kk == nz) { kk = 0; ++wk; }
-            if (kk < 0) { kk = nz - 1; --wk; }
-            tz = (face_coord(zf, nz, kk + (sz > 0), wk) - o[2]) / d[2];
-        }
-        if (wall) {                                              /* R4 */
-            double Iw, eps = P->epsw[wall - 1];
-            if ((e = planck_at(P, n, P->Tw[wall - 1], &Iw))) return e;
-            acc += tau * eps * (Isrc - Iw);
-            absacc += tau * eps * fabs(Isrc - Iw);
-            tau *= 1.0 - eps;
-            end = wall;
-            break;
+        if (hit[0] | hit[1] | hit[2]) {
+            int stop = walls(P, n, hit, nn, f, idx, wrap, o, dd, sg, tn, Isrc, &tau, &acc, &absacc, &end, &e);
+            if (e) return e;
+            if (stop) break;
         }
     }
     if (end == 0 && steps >= P->max_steps && tau > P->tol) end = 3;
@@ -667,7 +708,10 @@ static int check_problem(const orc_problem *P)
         P->max_steps < 1 || !(P->tol >= 0.0) || P->mg_levels > orc_level_count(P->nx, P->ny, P->nz) ||
         (P->mg_levels > 1 && (P->mg_steps < 1 || P->ns > 8)))
         return ORC_INVALID;
-    if (P->epsw[0] != 1.0 || P->epsw[1] != 1.0) return ORC_UNSUPPORTED;   /* R4 */
+    for (int q = 0; q < 2; ++q)                                  /* R4: 0 <= eps <= 1 */
+        if (!(P->epsw[q] >= 0.0 && P->epsw[q] <= 1.0) ||
+            (P->closed && !(P->epsx[q] >= 0.0 && P->epsx[q] <= 1.0 && P->epsz[q] >= 0.0 && P->epsz[q] <= 1.0)))
+            return ORC_INVALID;
     return ORC_OK;
 }
 

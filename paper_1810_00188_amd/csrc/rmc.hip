@@ -2514,9 +2514,9 @@ std::string tune_signature(const rmc_ctx *c)
     for (char &ch : arch)
         if (ch == ' ' || ch == ':') ch = '_';
     char buf[256];
-    snprintf(buf, sizeof buf, "rmc-tune-1 %s %d %d %d %d %d %d %d %d %d %d %d", arch.c_str(), c->nx, c->ny, c->nz, c->nb,
-             c->ng, c->ns, c->opt.rays_per_cell, (int)c->opt.march, (int)c->opt.sampling, c->opt.long_ray_steps,
-             c->opt.max_steps);
+    snprintf(buf, sizeof buf, "rmc-tune-1 %s %d %d %d %d %d %d %d %d %d %d %d %d %d", arch.c_str(), c->nx, c->ny, c->nz,
+             c->nb, c->ng, c->ns, c->opt.rays_per_cell, (int)c->opt.march, (int)c->opt.sampling, c->opt.long_ray_steps,
+             c->opt.max_steps, c->opt.mg_levels, c->opt.mg_steps);
     return buf;
 }
 

@@ -251,6 +251,11 @@ class Workload:
     field_dtype: str = "f64"   # dtype the T / X fields are handed over in
     mg_levels: int = 1         # overlaid grid levels of the multigrid march (1: DNS grid only)
     mg_steps: int = 5          # steps per level before the ray falls onto the next coarser grid
+    closed: bool = False       # walls on x and z too (closed box) instead of periodic x / z
+    T_walls_x: Tuple[float, float] = (0.0, 0.0)     # closed box: walls at x = xf[0], x = xf[-1]
+    eps_walls_x: Tuple[float, float] = (1.0, 1.0)
+    T_walls_z: Tuple[float, float] = (0.0, 0.0)     # closed box: walls at z = zf[0], z = zf[-1]
+    eps_walls_z: Tuple[float, float] = (1.0, 1.0)
 
     @property
     def nx(self): return len(self.xf) - 1
@@ -282,6 +287,34 @@ def grey_slab(n: int = 32, R: int = 16, T: float = 1000.0, kappa: float = 1.0,
     return Workload(name=f"grey_slab_{n}x{ny}x{n}", xf=xf, yf=yf, zf=zf,
                     T=np.full(nc, T), X=np.ones((1, nc)), kd=grey_kdist(kappa),
                     T_walls=tuple(T_walls), R=R, seed=seed, march="f64", accum="f64")
+
+
+def grey_box(n: int = 16, R: int = 16, T: float = 1000.0, kappa: float = 1.0, L: float = 1.0,
+             T_walls6=(0.0,) * 6, eps_walls6=(1.0,) * 6, seed: int = 0) -> Workload:
+    """Closed cube of side L with n^3 cells, walls on all six faces (temperatures and
+    emissivities in the order x0, x1, y0, y1, z0, z1), uniform T, grey kappa, FP64 march."""
+    f = uniform_faces(n, L)
+    nc = n ** 3
+    return Workload(name=f"grey_box_{n}", xf=f, yf=f.copy(), zf=f.copy(), T=np.full(nc, T), X=np.ones((1, nc)),
+                    kd=grey_kdist(kappa), T_walls=(T_walls6[2], T_walls6[3]), eps_walls=(eps_walls6[2], eps_walls6[3]),
+                    R=R, seed=seed, march="f64", accum="f64", closed=True,
+                    T_walls_x=(T_walls6[0], T_walls6[1]), eps_walls_x=(eps_walls6[0], eps_walls6[1]),
+                    T_walls_z=(T_walls6[4], T_walls6[5]), eps_walls_z=(eps_walls6[4], eps_walls6[5]))
+
+
+def sin_cube(n: int = 20, kappa: float = 0.5, R: int = 64, seed: int = 0) -> Workload:
+    """Cases 3 and 4 of Table 1: a 1 m cube with cold black walls, grey kappa (0.5 or 5),
+    T = (sin(pi x) sin(pi y) sin(pi z) pi / sigma)^(1/4) at the cell centres, so that
+    sigma T^4 / pi = sin(pi x) sin(pi y) sin(pi z).  The Planck table has 0.5 K nodes up to
+    200 K (the field peaks at 86.3 K)."""
+    f = uniform_faces(n, 1.0)
+    c = centres(f)
+    S = np.sin(np.pi * c)
+    T = (np.einsum("i,j,k->ijk", S, S, S).reshape(-1) * np.pi / SIGMA) ** 0.25
+    nc = n ** 3
+    return Workload(name=f"sin_cube_{n}_k{kappa:g}", xf=f, yf=f.copy(), zf=f.copy(), T=T, X=np.ones((1, nc)),
+                    kd=grey_kdist(kappa, nT=401, T0=0.0, dT=0.5), T_walls=(0.0, 0.0), R=R, seed=seed,
+                    march="f64", accum="f64", closed=True)
 
 
 def channel(nx: int = 64, ny: int = 64, nz: int = 64, R: int = 32, nb: int = 20,

@@ -322,5 +322,6 @@ def test_out_of_range_temperature_is_an_error(orc):
     T[3] = np.nan
     with pytest.raises(oracle.OracleError):
         orc.divergence(oracle.Problem(w.replace(T=T)))
-    with pytest.raises(oracle.OracleError):
-        orc.divergence(oracle.Problem(w.replace(eps_walls=(0.5, 1.0))))
+    for eps in ((1.5, 1.0), (1.0, -0.1), (np.nan, 1.0)):       # emissivity outside [0, 1]
+        with pytest.raises(oracle.OracleError):
+            orc.divergence(oracle.Problem(w.replace(eps_walls=eps)))
