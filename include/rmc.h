@@ -147,10 +147,23 @@ const char *rmc_last_error(void);
 rmc_status rmc_set_grid(rmc_ctx *ctx, int nx, int ny, int nz,
                         const double *xf, const double *yf, const double *zf);
 
-/* Wall temperatures at y = yf[0] and y = yf[ny] and their emissivities.  Only black walls
- * (eps = 1, Eq. 3 with a single absorbing wall) are supported: anything else returns
- * RMC_UNSUPPORTED. */
+/* Wall temperatures at y = yf[0] and y = yf[ny] and their emissivities eps in [0, 1]
+ * (RMC_INVALID_ARG otherwise).  Eq. 3: a ray reaching a wall leaves there the fraction eps
+ * of its transmissivity tau (the term tau eps (I_b(T_source) - I_b(T_wall)) of the ray
+ * value) and goes on with tau (1 - eps); the reflection law is not stated in the paper and
+ * is taken specular (the ray is mirrored on the wall plane).  eps = 1 ends the ray.
+ * Walls with eps < 1 turn off the parallel-segment long-ray march (rays then run in the
+ * lane kernel to the end). */
 rmc_status rmc_set_walls(rmc_ctx *ctx, double T_y0, double T_y1, double eps_y0, double eps_y1);
+
+/* Closed box (Cases 3-4 and 12 of Table 1): walls at x = xf[0], x = xf[nx], z = zf[0] and
+ * z = zf[nz] as well, with temperatures T[4] and emissivities eps[4] in that order (host
+ * arrays, copied), the same wall law as rmc_set_walls.  T = NULL restores periodic x and z
+ * (the default).  Errors: RMC_INVALID_ARG for negative or non-finite temperatures or
+ * emissivities outside [0, 1]; temperatures outside the table range are RMC_OUT_OF_RANGE at
+ * compute.  A closed box marches with per-face parameters on all three axes and without the
+ * long-ray segments; the learned allocation is not available in it (RMC_UNSUPPORTED). */
+rmc_status rmc_set_box_walls(rmc_ctx *ctx, const double *T, const double *eps);
 
 /* Narrow-band correlated-k tables on the uniform temperature grid T0 + t * dT, t < nT
  * (Sec. 2.1, precomputed tables of Sec. 2.2).  All host pointers:

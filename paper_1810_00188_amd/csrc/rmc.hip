@@ -38,7 +38,7 @@ struct SnapDesc {
     const void *kap;            // Real [nb*ng][ncpad] kappa_{n,g} planes, bricked
     const double *Ipl;          // [nb][ncpad] I_n planes, bricked
     const double *W;            // [nbucket] plain ray weight 4 pi dnu w / (8 p(n,g,o))
-    const double *Iw;           // [2][nb] wall intensities
+    const double *Iw;           // [6][nb] wall intensities, walls x0, x1, y0, y1, z0, z1
     void *Y;                    // ray slots c * R + r: FP32 march {value bits, steps | end << 28} as
                                 // one 8-byte record; FP64 march the double values, with
     uint32_t *st;               // [ncells * R] steps | end << 28 (FP64 march only)
@@ -68,6 +68,9 @@ struct SnapDesc {
     uint64_t mg_stride;         // cells per coarse plane (all levels >= 1)
     const void *mg_kap;         // Real [nb*ng][mg_stride] kappa planes of the coarse levels
     const double *mg_I;         // [nb][mg_stride] I planes of the coarse levels
+    double epsw[6];             // wall emissivities, walls x0, x1, y0, y1, z0, z1
+    int closed;                 // walls on x and z (closed box), else x and z periodic
+    int reflect;                // some wall has emissivity below one
 };
 
 struct AllocArgs {
@@ -235,7 +238,9 @@ struct PdfArgs {
     const double *Ib;           // [nb][nT]
     const double *dnu, *wg;
     int nb, ng, ns, nT;
-    double T0, dT, Tw0, Tw1;
+    double T0, dT;
+    double Tw[6];               // wall temperatures x0, x1, y0, y1, z0, z1 (x / z: copies of y0
+                                // unless the box is closed)
     const double *scal;         // [0]: max cell temperature, [1..ns]: largest mole fractions
     double *e;                  // scratch [nb*ng]
     double *eb;                 // scratch [nb]
@@ -251,7 +256,9 @@ __global__ void __launch_bounds__(256) k_plain_pdf(PdfArgs A)
 {
     const int nb = A.nb, ng = A.ng, npair = nb * ng;
     __shared__ double E_sh;
-    double Tmax = A.Tw0 > A.Tw1 ? A.Tw0 : A.Tw1;
+    double Tmax = A.Tw[2] > A.Tw[3] ? A.Tw[2] : A.Tw[3];
+    for (int w = 0; w < 6; ++w)
+        if (A.Tw[w] > Tmax) Tmax = A.Tw[w];
     if (A.scal[0] > Tmax) Tmax = A.scal[0];
     for (int pr = threadIdx.x; pr < npair; pr += blockDim.x) {
         const int n = pr / ng, g = pr - (pr / ng) * ng;
@@ -268,8 +275,7 @@ __global__ void __launch_bounds__(256) k_plain_pdf(PdfArgs A)
         double eb = 0.0;
         for (int g = 0; g < ng; ++g) eb += A.e[n * ng + g];
         A.eb[n] = eb;
-        A.Iw[n] = lerp_tab(A.Ib + (size_t)n * A.nT, A.nT, A.T0, A.dT, A.Tw0);
-        A.Iw[nb + n] = lerp_tab(A.Ib + (size_t)n * A.nT, A.nT, A.T0, A.dT, A.Tw1);
+        for (int w = 0; w < 6; ++w) A.Iw[w * nb + n] = lerp_tab(A.Ib + (size_t)n * A.nT, A.nT, A.T0, A.dT, A.Tw[w]);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -647,7 +653,19 @@ __device__ __forceinline__ RayGeo ray_geo(const SnapDesc &D, const double *sf)
     G.bsy = D.nbz * 64;
     G.Lx = D.Lx;
     G.Lz = D.Lz;
+    G.closed = D.closed != 0;
+    G.reflect = D.reflect != 0;
     return G;
+}
+
+// Walls as seen by the rays of band n.
+__device__ __forceinline__ Walls walls_of(const SnapDesc &D, int n, int nb)
+{
+    Walls W;
+    W.I = D.Iw + n;
+    W.stride = nb;
+    W.eps = D.epsw;
+    return W;
 }
 
 // Geometry of grid level L (faces staged per level; level 0 is ray_geo's).
@@ -663,6 +681,8 @@ __device__ __forceinline__ RayGeo ray_geo_level(const SnapDesc &D, const double 
     G.bsy = nbz * 64;
     G.Lx = D.Lx;
     G.Lz = D.Lz;
+    G.closed = D.closed != 0;
+    G.reflect = D.reflect != 0;
     return G;
 }
 
@@ -697,7 +717,7 @@ __device__ __forceinline__ bool march_levels(Ray<Real, INC_XZ> &R, const SnapDes
     for (int L = 0;; ++L) {
         const bool last = L + 1 >= D.nlev;
         const int cap = last ? last_cap : D.mg_steps * (L + 1);
-        if (ray_march(R, G, K, Ipl, D.Iw + n, D.Iw + nb + n, tol, max_steps, k0, I0, cap)) return true;
+        if (ray_march(R, G, K, Ipl, walls_of(D, n, nb), tol, max_steps, k0, I0, cap)) return true;
         if (last) return false;
         G = ray_geo_level(D, sf, L + 1);
         ray_descend(R, G);
@@ -820,7 +840,7 @@ __global__ void __launch_bounds__(256) k_march_lane(MarchArgs<Real> A)
     Real kap_src;
     double Isrc;
     ray_init(R, G, U, K, Ipl, i, j, k, dx, dy, dz, kap_src, Isrc);
-    if (!ray_march(R, G, K, Ipl, D.Iw + n, D.Iw + A.nb + n, A.tol, A.max_steps, kap_src, Isrc, A.cap)) {
+    if (!ray_march(R, G, K, Ipl, walls_of(D, n, A.nb), A.tol, A.max_steps, kap_src, Isrc, A.cap)) {
         // long ray: hand its state to k_march_long (or, if the list is full, finish it here)
         const uint32_t idx = atomicAdd(A.cont_count, 1u);
         if (idx < A.cont_cap) {
@@ -834,7 +854,7 @@ __global__ void __launch_bounds__(256) k_march_lane(MarchArgs<Real> A)
             return;
         }
         const int cell = R.px + R.py + R.pz;
-        ray_march(R, G, K, Ipl, D.Iw + n, D.Iw + A.nb + n, A.tol, A.max_steps, gld(K + cell), gld(Ipl + cell),
+        ray_march(R, G, K, Ipl, walls_of(D, n, A.nb), A.tol, A.max_steps, gld(K + cell), gld(Ipl + cell),
                   A.max_steps);
     }
     const size_t slot = (size_t)c * A.R + r;
@@ -899,7 +919,7 @@ __global__ void __launch_bounds__(256) k_march_mg(MarchArgs<Real> A)
         const RayGeo GL = ray_geo_level(D, sf, D.nlev - 1);
         level_planes<Real>(D, D.nlev - 1, pair, n, K, Ipl);
         const int cell = R.px + R.py + R.pz;
-        ray_march(R, GL, K, Ipl, D.Iw + n, D.Iw + A.nb + n, A.tol, A.max_steps, gld(K + cell), gld(Ipl + cell),
+        ray_march(R, GL, K, Ipl, walls_of(D, n, A.nb), A.tol, A.max_steps, gld(K + cell), gld(Ipl + cell),
                   A.max_steps);
     }
     const size_t slot = (size_t)c * A.R + r;
@@ -1045,7 +1065,7 @@ __global__ void __launch_bounds__(256) k_march_long(MarchArgs<float> A)
                     const double te = R.tx < R.ty ? (R.tz < R.tx ? R.tz : R.tx) : (R.tz < R.ty ? R.tz : R.ty);
                     const bool cross = (ax ? R.tx : R.tz) == te;
                     double ds;
-                    bool wall;
+                    int wall;
                     const int cell = ray_advance(R, G, ds, wall);
                     const float x = kc * (float)ds;
                     float a, e;
@@ -1053,8 +1073,10 @@ __global__ void __launch_bounds__(256) k_march_long(MarchArgs<float> A)
                     R.acc += (double)((float)R.tau * a * (float)(Isrc - Ic));
                     R.tau *= x < 0.25f ? 1.0 - (double)a : (double)e;
                     ++R.steps;
-                    if (wall) {
-                        R.acc += R.tau * (Isrc - gld(R.end == kEndWallLo ? D.Iw + n : D.Iw + A.nb + n));
+                    if (wall) {   // black y walls only on this path (no reflection, x and z periodic)
+                        const int w = ((wall >> kWallY0) & 1) ? kWallY0 : kWallY1;
+                        R.end = wall_end_code(w);
+                        R.acc += R.tau * (Isrc - gld(D.Iw + (size_t)w * A.nb + n));
                         R.tau = 0.0;
                         wall_end = true;
                         break;
@@ -1105,7 +1127,7 @@ __global__ void __launch_bounds__(256) k_march_long(MarchArgs<float> A)
                 R.steps = steps_in;
                 R.end = kEndTol;
                 const int cur = R.px + R.py + R.pz;
-                ray_march(R, G, K, Ipl, D.Iw + n, D.Iw + A.nb + n, A.tol, A.max_steps, gld(K + cur),
+                ray_march(R, G, K, Ipl, walls_of(D, n, A.nb), A.tol, A.max_steps, gld(K + cur),
                           gld(Ipl + cur), A.max_steps);
                 contrib = R.acc;
             }
@@ -1186,7 +1208,7 @@ __global__ void __launch_bounds__(256) k_trace(TraceArgs<Real> A)
     double Isrc;
     ray_init(R, G, U, K, Ipl, i, j, k, dx, dy, dz, kap_src, Isrc);
     if (D.nlev > 1) march_levels(R, D, sf, pair, d.n, A.nb, A.tol, A.max_steps, kap_src, Isrc, A.max_steps);
-    else ray_march(R, G, K, Ipl, D.Iw + d.n, D.Iw + A.nb + d.n, A.tol, A.max_steps, kap_src, Isrc, A.max_steps);
+    else ray_march(R, G, K, Ipl, walls_of(D, d.n, A.nb), A.tol, A.max_steps, kap_src, Isrc, A.max_steps);
     const double w = 4.0 * M_PI * A.dnu[d.n] * A.wg[d.g] / (8.0 * d.p);
     rmc_ray_record rec;
     rec.Y = w * (double)kap_src * (double)R.acc;
@@ -1386,9 +1408,11 @@ struct rmc_ctx {
     bool have_grid = false;
     int nx = 0, ny = 0, nz = 0;
     std::vector<double> xf, yf, zf;
-    // walls
+    // walls: y always; x and z in a closed box
     bool have_walls = false;
-    double Tw[2] = {0, 0};
+    double Tw[2] = {0, 0}, epsw[2] = {1, 1};
+    bool closed = false;
+    double Tbox[4] = {0, 0, 0, 0}, epsbox[4] = {1, 1, 1, 1};   // x0, x1, z0, z1
     // tables
     bool have_kdist = false;
     int nb = 0, ng = 0, ns = 0, nT = 0;
@@ -1458,6 +1482,29 @@ uint64_t ncpad_of(const rmc_ctx *c)
     return (uint64_t)round_up(c->nx, 4) * round_up(c->ny, 4) * round_up(c->nz, 4);
 }
 
+// Temperature and emissivity of wall w (x0, x1, y0, y1, z0, z1); in a periodic box the x and z
+// entries repeat the y0 wall (never hit, but kept inside the table range).
+double wall_T(const rmc_ctx *c, int w)
+{
+    if (w == 2 || w == 3) return c->Tw[w - 2];
+    if (!c->closed) return c->Tw[0];
+    return c->Tbox[w < 2 ? w : w - 2];
+}
+
+double walls_Tmax(const rmc_ctx *c)
+{
+    double m = 0.0;
+    for (int w = 0; w < 6; ++w) m = std::max(m, wall_T(c, w));
+    return m;
+}
+
+double wall_eps(const rmc_ctx *c, int w)
+{
+    if (w == 2 || w == 3) return c->epsw[w - 2];
+    if (!c->closed) return 1.0;
+    return c->epsbox[w < 2 ? w : w - 2];
+}
+
 rmc_status check_ctx(const rmc_ctx *c)
 {
     if (!c) return fail(RMC_INVALID_ARG, "null context");
@@ -1504,11 +1551,13 @@ rmc_status check_ready(const rmc_ctx *c)
     if (c->opt.sampling == RMC_SAMPLING_PDF && !c->have_q) return fail(RMC_BAD_STATE, "rmc_set_cell_pdf missing");
     if (c->opt.sampling == RMC_SAMPLING_LEARNED && !c->have_alloc)
         return fail(RMC_BAD_STATE, "rmc_set_allocator missing");
-    for (int s = 0; s < 2; ++s) {
-        const double u = (c->Tw[s] - c->T0) / c->dT;
+    for (int w = 0; w < 6; ++w) {
+        const double u = (wall_T(c, w) - c->T0) / c->dT;
         if (!(u >= 0.0 && u <= (double)(c->nT - 1)))
-            return fail(RMC_OUT_OF_RANGE, "wall temperature %g outside the table range", c->Tw[s]);
+            return fail(RMC_OUT_OF_RANGE, "wall temperature %g outside the table range", wall_T(c, w));
     }
+    if (c->closed && c->opt.sampling == RMC_SAMPLING_LEARNED)
+        return fail(RMC_UNSUPPORTED, "the learned allocation's features assume periodic x and z (no closed box)");
     if ((uint64_t)ncells_of(c) * c->opt.rays_per_cell >= (1ull << 32))
         return fail(RMC_UNSUPPORTED, "ncells * R must stay below 2^32");
     return RMC_OK;
@@ -1559,7 +1608,7 @@ double uniform_width(const std::vector<double> &f)
 void march_order(const rmc_ctx *c, std::vector<uint32_t> &order)
 {
     const int nb = c->nb, ng = c->ng;
-    const double Tmax = std::max(c->Tmax_cells, std::max(c->Tw[0], c->Tw[1]));
+    const double Tmax = std::max(c->Tmax_cells, walls_Tmax(c));
     const double u = (Tmax - c->T0) / c->dT;
     int t = (int)std::floor(u);
     if (t > c->nT - 2) t = c->nT - 2;
@@ -1742,7 +1791,7 @@ template <class Real> rmc_status plan_snapshot(rmc_ctx *c, SnapDesc &D)
     const int R = c->opt.rays_per_cell;
     if ((st = c->pdf_scratch.ensure(sizeof(double) * (nb * ng + nb))) || (st = c->p.ensure(sizeof(double) * nb * ng)) ||
         (st = c->cdf_b.ensure(sizeof(double) * nb)) || (st = c->cdf_g.ensure(sizeof(double) * nb * ng)) ||
-        (st = c->W.ensure(sizeof(double) * nbucket)) || (st = c->Iw.ensure(sizeof(double) * 2 * nb)) ||
+        (st = c->W.ensure(sizeof(double) * nbucket)) || (st = c->Iw.ensure(sizeof(double) * 6 * nb)) ||
         (st = c->status.ensure(sizeof(int))) ||
         (st = c->field.ensure(sizeof(Real) * ncpad_of(c) * (uint64_t)(nb * ng))) ||
         (st = c->Iplane.ensure(sizeof(double) * ncpad_of(c) * (uint64_t)nb)) ||
@@ -1759,6 +1808,10 @@ template <class Real> rmc_status plan_snapshot(rmc_ctx *c, SnapDesc &D)
     D.hx = uniform_width(c->xf);
     D.hz = uniform_width(c->zf);
     D.W = c->W.as<double>(); D.Iw = c->Iw.as<double>();
+    for (int w = 0; w < 6; ++w) D.epsw[w] = wall_eps(c, w);
+    D.closed = c->closed ? 1 : 0;
+    D.reflect = 0;
+    for (int w = 0; w < 6; ++w) D.reflect |= D.epsw[w] < 1.0 ? 1 : 0;
     D.p = c->p.as<double>(); D.cdf_b = c->cdf_b.as<double>(); D.cdf_g = c->cdf_g.as<double>();
     if (c->opt.sampling == RMC_SAMPLING_PDF) {
         const uint64_t m = (uint64_t)nb * ng * 8;
@@ -1821,7 +1874,7 @@ rmc_status enqueue_snapshot(rmc_ctx *c, const SnapDesc &D, const double *dfaces,
     A.wg = c->wg.as<double>();
     A.nb = nb; A.ng = ng; A.ns = c->ns; A.nT = c->nT;
     A.T0 = c->T0; A.dT = c->dT;
-    A.Tw0 = c->Tw[0]; A.Tw1 = c->Tw[1];
+    for (int w = 0; w < 6; ++w) A.Tw[w] = wall_T(c, w);
     A.scal = c->scal.as<double>();
     A.e = c->pdf_scratch.as<double>();
     A.eb = A.e + nb * ng;
@@ -1906,6 +1959,7 @@ struct Plan {
     uint64_t total_cells = 0, max_chunks = 0;
     bool inc_xz = true, pdf_mode = false;   // pdf_mode: per-ray probabilities (modes 1 and 2)
     bool multigrid = false;                 // some snapshot marches on more than one grid
+    bool walls_plain = true;                // every snapshot: periodic x / z, black y walls
     int smode = 0;
     uint32_t cont_cap = 0;
 };
@@ -1944,7 +1998,8 @@ template <class Real> rmc_status plan_pipeline(rmc_ctx *const *ctxs, int nsnap, 
         P.D[q].ntiles = (int)((P.D[q].ncpad + P.tile_cells - 1) / P.tile_cells);
         P.ntiles += P.D[q].ntiles;
         for (int t = 0; t < P.D[q].ntiles; ++t) tile_snap.push_back(q);
-        P.inc_xz = P.inc_xz && P.D[q].hx > 0.0 && P.D[q].hz > 0.0;
+        P.inc_xz = P.inc_xz && P.D[q].hx > 0.0 && P.D[q].hz > 0.0 && !P.D[q].closed;
+        P.walls_plain = P.walls_plain && !P.D[q].closed && !P.D[q].reflect;
     }
     const uint64_t max_items = (P.total_cells * R + (uint64_t)nbucket * 63 + 63) / 64 * 64;
     P.max_chunks = max_items / 64;
@@ -2054,7 +2109,7 @@ rmc_status enqueue_pipeline(const Plan &P, double *const *divq, double *const *s
     MA.tol = (Real)O.tol;
     MA.max_steps = O.max_steps;
     // long rays are segmented only in the FP32 march over uniform periodic x and z
-    const bool segment = sizeof(Real) == 4 && P.inc_xz;
+    const bool segment = sizeof(Real) == 4 && P.inc_xz && P.walls_plain;
     const int lrs = O.long_ray_steps > 0 ? O.long_ray_steps : 256;
     MA.cap = segment ? std::min(lrs, O.max_steps) : O.max_steps;
     MA.kmin = L->kmin.as<float>();
@@ -2362,10 +2417,36 @@ rmc_status rmc_set_walls(rmc_ctx *c, double T0, double T1, double e0, double e1)
     if (rmc_status st = check_ctx(c)) return st;
     if (!std::isfinite(T0) || !std::isfinite(T1) || T0 < 0 || T1 < 0)
         return fail(RMC_INVALID_ARG, "wall temperatures must be finite and >= 0");
-    if (e0 != 1.0 || e1 != 1.0) return fail(RMC_UNSUPPORTED, "only black walls (emissivity 1) are supported");
+    if (!(e0 >= 0.0 && e0 <= 1.0) || !(e1 >= 0.0 && e1 <= 1.0))
+        return fail(RMC_INVALID_ARG, "wall emissivities must lie in [0, 1]");
     c->Tw[0] = T0;
     c->Tw[1] = T1;
+    c->epsw[0] = e0;
+    c->epsw[1] = e1;
     c->have_walls = true;
+    ++c->config_version;
+    return RMC_OK;
+}
+
+rmc_status rmc_set_box_walls(rmc_ctx *c, const double *T, const double *eps)
+{
+    g_err.clear();
+    if (rmc_status st = check_ctx(c)) return st;
+    if (!T) {
+        c->closed = false;
+        ++c->config_version;
+        return RMC_OK;
+    }
+    if (!eps) return fail(RMC_INVALID_ARG, "eps must be given with T");
+    for (int q = 0; q < 4; ++q) {
+        if (!std::isfinite(T[q]) || T[q] < 0) return fail(RMC_INVALID_ARG, "wall temperatures must be finite and >= 0");
+        if (!(eps[q] >= 0.0 && eps[q] <= 1.0)) return fail(RMC_INVALID_ARG, "wall emissivities must lie in [0, 1]");
+    }
+    for (int q = 0; q < 4; ++q) {
+        c->Tbox[q] = T[q];
+        c->epsbox[q] = eps[q];
+    }
+    c->closed = true;
     ++c->config_version;
     return RMC_OK;
 }
@@ -2790,7 +2871,7 @@ rmc_status rmc_trace_cells(rmc_ctx *c, const int64_t *cells, int ncell, rmc_ray_
     SnapDesc D;
     rmc_status st = dbl ? plan_snapshot<double>(c, D) : plan_snapshot<float>(c, D);
     if (st) return st;
-    const bool inc_xz = D.hx > 0.0 && D.hz > 0.0;
+    const bool inc_xz = D.hx > 0.0 && D.hz > 0.0 && !D.closed;
     std::vector<double> &fd = c->h_faces;
     fd.clear();
     append_faces(c, D, fd);
@@ -2851,7 +2932,7 @@ rmc_status rmc_get_pdf(rmc_ctx *c, double *p, double *cdf_b, double *cdf_g, doub
     if (p) HIPCHK(hipMemcpy(p, c->p.p, sizeof(double) * c->nb * c->ng, hipMemcpyDeviceToHost));
     if (cdf_b) HIPCHK(hipMemcpy(cdf_b, c->cdf_b.p, sizeof(double) * c->nb, hipMemcpyDeviceToHost));
     if (cdf_g) HIPCHK(hipMemcpy(cdf_g, c->cdf_g.p, sizeof(double) * c->nb * c->ng, hipMemcpyDeviceToHost));
-    if (T_max) *T_max = std::max(c->Tmax_cells, std::max(c->Tw[0], c->Tw[1]));
+    if (T_max) *T_max = std::max(c->Tmax_cells, walls_Tmax(c));
     return RMC_OK;
 }
 

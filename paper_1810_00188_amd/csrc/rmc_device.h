@@ -15,7 +15,11 @@ namespace rmc {
 constexpr uint32_t kTagAlloc = 1u;      // random stream of the (band, g, octant) draws
 constexpr uint32_t kTagDir = 2u;        // random stream of the direction draws
 constexpr uint32_t kInvalidItem = 0xFFFFFFFFu;
-constexpr int kEndTol = 0, kEndWallLo = 1, kEndWallHi = 2, kEndCap = 3;
+constexpr int kEndTol = 0, kEndWallLo = 1, kEndWallHi = 2, kEndCap = 3;   // y walls, step cap
+// Walls, in the order their terms are taken (x, y, z; low side first): bit / index w of a
+// wall mask, and the end code of a ray that a black wall w stops.
+constexpr int kWallX0 = 0, kWallX1 = 1, kWallY0 = 2, kWallY1 = 3, kWallZ0 = 4, kWallZ1 = 5;
+__device__ __forceinline__ int wall_end_code(int w) { return w < 2 ? 4 + w : (w < 4 ? w - 1 : w + 2); }
 
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds, each two 32x32->64 bit products of
 // counter words with fixed multipliers, xor-mixed with the other words and the round key;
@@ -106,6 +110,16 @@ struct RayGeo {
     int nx, ny, nz;
     int bsx, bsy;               // brick strides of the x and y brick index (in cells)
     double Lx, Lz;              // periodic lengths
+    bool closed;                // walls on x and z too (else x and z are periodic)
+    bool reflect;               // some wall has emissivity below one: rays reflect
+};
+
+// Walls seen by the rays of one band: wall w has the band's intensity I[w * stride] and the
+// emissivity eps[w].
+struct Walls {
+    const double *I;
+    int stride;
+    const double *eps;
 };
 
 // FP32 cell absorption: alpha = 1 - exp(-x) and the transmission factor exp(-x) of a
@@ -206,16 +220,56 @@ template <class Real> __device__ __forceinline__ bool march_starts(Real tol, int
     return (Real)1 > tol && max_steps > 0;
 }
 
-// Geometry of a step: the segment length ds in the current cell, the axis steps, the wall
-// flag; returns the brick offset of the next cell (the current one at a wall, so that the
-// caller's load stays in bounds).
+// Specular reflection on wall `side` (0 low, 1 high) of the y axis: the ray goes on from the
+// point it hit, in the wall cell, with origin and direction mirrored on the wall plane (its
+// parameter t continues).  Same for x and z (closed box; there the wrap count is zero).
 template <class Real, bool INC_XZ>
-__device__ __forceinline__ int ray_advance(Ray<Real, INC_XZ> &R, const RayGeo &G, double &ds, bool &wall)
+__device__ __forceinline__ void reflect_y(Ray<Real, INC_XZ> &R, const RayGeo &G, int side)
+{
+    R.j = side ? G.ny - 1 : 0;
+    R.oy = 2.0 * G.yf[side ? G.ny : 0] - R.oy;
+    R.ry = -R.ry;
+    R.sgn ^= 2;
+    const double f = G.yf[R.j + 1 - ((R.sgn >> 1) & 1)] - R.oy;
+    if constexpr (sizeof(Real) == 4) R.ty = f * R.ry;
+    else R.ty = f / R.ry;
+}
+
+template <class Real, bool INC_XZ>
+__device__ __forceinline__ void reflect_x(Ray<Real, INC_XZ> &R, const RayGeo &G, int side)
+{
+    R.i = side ? G.nx - 1 : 0;
+    R.ox = 2.0 * G.xf[side ? G.nx : 0] - R.ox;
+    R.rx = -R.rx;
+    R.sgn ^= 1;
+    const double f = G.xf[R.i + 1 - (R.sgn & 1)] + (double)R.wi * G.Lx - R.ox;
+    if constexpr (sizeof(Real) == 4) R.tx = f * R.rx;
+    else R.tx = f / R.rx;
+}
+
+template <class Real, bool INC_XZ>
+__device__ __forceinline__ void reflect_z(Ray<Real, INC_XZ> &R, const RayGeo &G, int side)
+{
+    R.k = side ? G.nz - 1 : 0;
+    R.oz = 2.0 * G.zf[side ? G.nz : 0] - R.oz;
+    R.rz = -R.rz;
+    R.sgn ^= 4;
+    const double f = G.zf[R.k + 1 - ((R.sgn >> 2) & 1)] + (double)R.wk * G.Lz - R.oz;
+    if constexpr (sizeof(Real) == 4) R.tz = f * R.rz;
+    else R.tz = f / R.rz;
+}
+
+// Geometry of a step: the segment length ds in the current cell, the axis steps, the walls
+// the step ends on (mask of wall bits); returns the brick offset of the next cell.  With
+// reflecting walls the ray is mirrored here and goes on in the wall cell; with black walls
+// the offset is the current cell's (the caller's load stays in bounds; the ray ends).
+template <class Real, bool INC_XZ>
+__device__ __forceinline__ int ray_advance(Ray<Real, INC_XZ> &R, const RayGeo &G, double &ds, int &wall)
 {
     const double te = R.tx < R.ty ? (R.tz < R.tx ? R.tz : R.tx) : (R.tz < R.ty ? R.tz : R.ty);
     ds = te - R.t;
     R.t = te;
-    wall = false;
+    wall = 0;
     const int cur = R.px + R.py + R.pz;
     if constexpr (sizeof(Real) == 4 && INC_XZ) {
         // uniform periodic x and z: branch-free updates
@@ -233,43 +287,58 @@ __device__ __forceinline__ int ray_advance(Ray<Real, INC_XZ> &R, const RayGeo &G
     } else {
         if (R.tx == te) {
             R.i += (R.sgn & 1) ? -1 : 1;
-            if (R.i == G.nx) { R.i = 0; ++R.wi; }
-            if (R.i < 0) { R.i = G.nx - 1; --R.wi; }
-            R.px = brick_x(R.i, G.bsx);
-            const double f = G.xf[R.i + 1 - (R.sgn & 1)] + (double)R.wi * G.Lx - R.ox;
-            if constexpr (sizeof(Real) == 4) R.tx = f * R.rx;
-            else R.tx = f / R.rx;
+            if (G.closed && (R.i < 0 || R.i >= G.nx)) {
+                const int side = R.i < 0 ? 0 : 1;
+                wall |= 1 << (kWallX0 + side);
+                if (G.reflect) reflect_x(R, G, side);
+            } else {
+                if (R.i == G.nx) { R.i = 0; ++R.wi; }
+                if (R.i < 0) { R.i = G.nx - 1; --R.wi; }
+                R.px = brick_x(R.i, G.bsx);
+                const double f = G.xf[R.i + 1 - (R.sgn & 1)] + (double)R.wi * G.Lx - R.ox;
+                if constexpr (sizeof(Real) == 4) R.tx = f * R.rx;
+                else R.tx = f / R.rx;
+            }
         }
         if (R.tz == te) {
             R.k += (R.sgn & 4) ? -1 : 1;
-            if (R.k == G.nz) { R.k = 0; ++R.wk; }
-            if (R.k < 0) { R.k = G.nz - 1; --R.wk; }
-            R.pz = brick_z(R.k);
-            const double f = G.zf[R.k + 1 - ((R.sgn >> 2) & 1)] + (double)R.wk * G.Lz - R.oz;
-            if constexpr (sizeof(Real) == 4) R.tz = f * R.rz;
-            else R.tz = f / R.rz;
+            if (G.closed && (R.k < 0 || R.k >= G.nz)) {
+                const int side = R.k < 0 ? 0 : 1;
+                wall |= 1 << (kWallZ0 + side);
+                if (G.reflect) reflect_z(R, G, side);
+            } else {
+                if (R.k == G.nz) { R.k = 0; ++R.wk; }
+                if (R.k < 0) { R.k = G.nz - 1; --R.wk; }
+                R.pz = brick_z(R.k);
+                const double f = G.zf[R.k + 1 - ((R.sgn >> 2) & 1)] + (double)R.wk * G.Lz - R.oz;
+                if constexpr (sizeof(Real) == 4) R.tz = f * R.rz;
+                else R.tz = f / R.rz;
+            }
         }
     }
     if (R.ty == te) {
         R.j += (R.sgn & 2) ? -1 : 1;
-        if (R.j < 0) { wall = true; R.end = kEndWallLo; }
-        else if (R.j >= G.ny) { wall = true; R.end = kEndWallHi; }
-        else {
+        if (R.j < 0 || R.j >= G.ny) {
+            const int side = R.j < 0 ? 0 : 1;
+            wall |= 1 << (kWallY0 + side);
+            if (G.reflect) reflect_y(R, G, side);
+        } else {
             R.py = brick_y(R.j, G.bsy);
             const double f = G.yf[R.j + 1 - ((R.sgn >> 1) & 1)] - R.oy;
             if constexpr (sizeof(Real) == 4) R.ty = f * R.ry;
             else R.ty = f / R.ry;
         }
     }
-    return wall ? cur : R.px + R.py + R.pz;
+    return (wall && !G.reflect) ? cur : R.px + R.py + R.pz;
 }
 
 // Absorption of a step in the current cell (kappa kc, intensity Ic, length ds); adds the
-// wall term when the step ended on a wall and the residual when the ray stops.  Returns
-// true when the ray is finished.  Iw0 / Iw1 point at the band's wall intensities.
+// terms of the walls the step ended on (mask `wall`, in the order x, y, z: tau eps (I_src -
+// I_w), then tau *= 1 - eps, Eq. 3) and the residual when the ray stops.  Returns true when
+// the ray is finished (a black wall ends it).
 template <class Real, bool INC_XZ>
-__device__ __forceinline__ bool ray_absorb(Ray<Real, INC_XZ> &R, Real kc, double Ic, double ds, bool wall,
-                                           const double *Iw0, const double *Iw1, Real tol, int max_steps)
+__device__ __forceinline__ bool ray_absorb(Ray<Real, INC_XZ> &R, Real kc, double Ic, double ds, int wall,
+                                           const Walls &W, Real tol, int max_steps)
 {
     if constexpr (sizeof(Real) == 8) {
         const double dI = R.Isrc - Ic;
@@ -285,11 +354,18 @@ __device__ __forceinline__ bool ray_absorb(Ray<Real, INC_XZ> &R, Real kc, double
     }
     ++R.steps;
     if (wall) {
-        const double dw = R.Isrc - gld(R.end == kEndWallLo ? Iw0 : Iw1);
-        R.acc += R.tau * dw;
-        R.tau = 0.0;
-        R.acc += R.tau * (R.Isrc - Ic);   // residual of a finished ray: zero
-        return true;
+        for (int w = 0; w < 6; ++w) {
+            if (!((wall >> w) & 1)) continue;
+            const double e = gld(W.eps + w);
+            const double dw = R.Isrc - gld(W.I + w * W.stride);
+            R.acc += R.tau * e * dw;
+            R.tau *= 1.0 - e;
+            if (e == 1.0) {
+                R.end = wall_end_code(w);
+                R.acc += R.tau * (R.Isrc - Ic);   // residual of a finished ray: zero
+                return true;
+            }
+        }
     }
     if (!(R.tau > (double)tol && R.steps < max_steps)) {
         if (R.steps >= max_steps && R.tau > (double)tol) R.end = kEndCap;
@@ -304,23 +380,23 @@ __device__ __forceinline__ bool ray_absorb(Ray<Real, INC_XZ> &R, Real kc, double
 // state at the start of the next step (its cell, parameter and next-face parameters).
 template <class Real, bool INC_XZ>
 __device__ __forceinline__ bool ray_march(Ray<Real, INC_XZ> &R, const RayGeo &G, const Real *__restrict__ K,
-                                          const double *__restrict__ Ipl, const double *Iw0, const double *Iw1,
-                                          Real tol, int max_steps, Real k0, double I0, int cap)
+                                          const double *__restrict__ Ipl, const Walls &W, Real tol, int max_steps,
+                                          Real k0, double I0, int cap)
 {
     if (!march_starts(tol, max_steps)) return true;
     Real k1;
     double I1, ds;
-    bool wall;
+    int wall;
     while (true) {
         int cell = ray_advance(R, G, ds, wall);
         k1 = gld(K + cell);
         I1 = gld(Ipl + cell);
-        if (ray_absorb(R, k0, I0, ds, wall, Iw0, Iw1, tol, max_steps)) return true;
+        if (ray_absorb(R, k0, I0, ds, wall, W, tol, max_steps)) return true;
         if (R.steps >= cap) return false;
         cell = ray_advance(R, G, ds, wall);
         k0 = gld(K + cell);
         I0 = gld(Ipl + cell);
-        if (ray_absorb(R, k1, I1, ds, wall, Iw0, Iw1, tol, max_steps)) return true;
+        if (ray_absorb(R, k1, I1, ds, wall, W, tol, max_steps)) return true;
         if (R.steps >= cap) return false;
     }
 }

@@ -74,6 +74,7 @@ SIGNATURES = {
     "rmc_last_error": (C.c_char_p, []),
     "rmc_set_grid": (C.c_int, [_VP, C.c_int, C.c_int, C.c_int, _VP, _VP, _VP]),
     "rmc_set_walls": (C.c_int, [_VP, C.c_double, C.c_double, C.c_double, C.c_double]),
+    "rmc_set_box_walls": (C.c_int, [_VP, _VP, _VP]),
     "rmc_set_kdist": (C.c_int, [_VP, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
                                 _VP, _VP, _VP, C.c_int, _VP]),
     "rmc_set_temperature": (C.c_int, [_VP, _VP, C.c_int, C.c_int, _VP]),
@@ -209,6 +210,18 @@ class Solver:
     def set_walls(self, T0, T1, eps0=1.0, eps1=1.0):
         _check(LIB.rmc_set_walls(self.h, float(T0), float(T1), float(eps0), float(eps1)))
 
+    def set_box_walls(self, T=None, eps=None):
+        """Closed box: walls x0, x1, z0, z1 with temperatures T[4] and emissivities eps[4];
+        T = None restores periodic x and z."""
+        if T is None:
+            _check(LIB.rmc_set_box_walls(self.h, None, None))
+            return
+        t = np.ascontiguousarray(T, dtype=np.float64)
+        e = np.ascontiguousarray(eps if eps is not None else np.ones(4), dtype=np.float64)
+        if t.shape != (4,) or e.shape != (4,):
+            raise ValueError("T and eps need 4 entries (x0, x1, z0, z1)")
+        _check(LIB.rmc_set_box_walls(self.h, t.ctypes.data, e.ctypes.data))
+
     def set_kdist(self, kd):
         if kd.k_dtype == "bf16":
             from .inputs import bf16_bits
@@ -251,6 +264,11 @@ class Solver:
         """Load a paper_1810_00188_amd.inputs.Workload (fields in the dtype it declares)."""
         self.set_grid(w.xf, w.yf, w.zf)
         self.set_walls(*w.T_walls, *w.eps_walls)
+        if getattr(w, "closed", False):
+            self.set_box_walls([w.T_walls_x[0], w.T_walls_x[1], w.T_walls_z[0], w.T_walls_z[1]],
+                               [w.eps_walls_x[0], w.eps_walls_x[1], w.eps_walls_z[0], w.eps_walls_z[1]])
+        else:
+            self.set_box_walls(None)
         self.set_kdist(w.kd)
         fdt = np.float32 if w.field_dtype == "f32" else np.float64
         T = np.ascontiguousarray(w.T, dtype=fdt)

@@ -27,12 +27,18 @@ def _threshold_scale(w, ref, cells):
     """Per ray, tol * w * kappa_src * max_j |I_src - I_j|: the most a ray's value can change
     when the march takes one step more or less at the tau = tol threshold (the step count is
     a float decision taken in FP32 by the kernel and in FP64 by the oracle)."""
+    return w.tol * _wall_scale(w, ref, cells)
+
+
+def _wall_scale(w, ref, cells):
+    """Per ray, w * kappa_src * max_j |I_src - I_j| over the field and every wall."""
     from oracle.closed_forms import table_lerp
     kd = w.kd
     cells = np.asarray(cells)
     Tc = w.T[cells][:, None]
     n, g = ref["n"], ref["g"]
-    I_all = table_lerp(kd.Ib, kd.T0, kd.dT, np.concatenate([w.T, w.T_walls]))   # [nb, nc+2]
+    Tw = list(w.T_walls) + (list(w.T_walls_x) + list(w.T_walls_z) if getattr(w, "closed", False) else [])
+    I_all = table_lerp(kd.Ib, kd.T0, kd.dT, np.concatenate([w.T, Tw]))   # [nb, nc + walls]
     Imax, Imin = I_all.max(axis=1), I_all.min(axis=1)
     Isrc = np.empty(n.shape)
     kap = np.zeros(n.shape)
@@ -46,7 +52,23 @@ def _threshold_scale(w, ref, cells):
                 kap[mg] += np.broadcast_to(w.X[sp][cells][:, None] * ks, n.shape)[mg]
     dI = np.maximum(np.abs(Imax[n] - Isrc), np.abs(Isrc - Imin[n]))
     wgt = 4 * np.pi * kd.dnu[n] * kd.wg[g] / (8 * ref["p"])
-    return w.tol * wgt * kap * dI
+    return wgt * kap * dI
+
+
+def _check_fp64_rays(w, cells, Yg, ref):
+    """FP64 march: per ray within TOL64 of the ray's scale, plus a rounding floor of
+    2^-52 w kappa max|dI|.  The floor: where kappa ds is so large that 1 - alpha (Eq. 2) is
+    a few ulps, the device's expm1 and the host's may round alpha one ulp apart (alpha = 1
+    exactly on one side), so tau after that step -- and every later term, a wall or the
+    residual -- may differ by up to 2^-52 of the scale."""
+    diff = np.abs(Yg - ref["Y"])
+    floor = 2.0 ** -52 * _wall_scale(w, ref, cells)
+    bad = diff > TOL64 * ref["absY"] + floor
+    for a, r in np.argwhere(bad)[:8]:
+        x = ref[a, r]
+        say(f"  cell {np.asarray(cells)[a]} ray {r}: gpu {Yg[a, r]!r} | oracle Y {x['Y']!r} absY {x['absY']!r} "
+            f"steps {x['steps']} end {x['end']}")
+    assert not bad.any()
 
 
 def _check_fp32_rays(w, cells, Yg, steps_g, ref):

@@ -14,7 +14,7 @@ if not torch.cuda.is_available():
 
 import oracle  # noqa: E402
 from paper_1810_00188_amd import inputs, rmc  # noqa: E402
-from _parity import TOL64, _check_fp32_rays, _ray_errors, _small_channel, _solver, say  # noqa: E402
+from _parity import TOL64, _check_fp32_rays, _check_fp64_rays, _small_channel, _solver, say  # noqa: E402
 
 
 @pytest.mark.parametrize("shape,levels,steps", [((24, 12, 12), 3, 2), ((24, 12, 12), -1, 5),
@@ -29,7 +29,7 @@ def test_trace_fp64_multigrid_per_ray(shape, levels, steps):
     ref = oracle.trace_cells(oracle.Problem(w, mg_levels=nl), cells)
     for f in ("n", "g", "o", "k", "steps", "end"):
         np.testing.assert_array_equal(got[f], ref[f], err_msg=f)
-    assert _ray_errors(got["Y"], ref).max() < TOL64
+    _check_fp64_rays(w, cells, got["Y"], ref)
 
 
 def test_compute_fp64_multigrid_matches_oracle():
@@ -42,7 +42,7 @@ def test_compute_fp64_multigrid_matches_oracle():
     ref = oracle.trace_cells(P, np.arange(w.ncells))
     Y, S = s.ray_values(np.arange(w.ncells))
     np.testing.assert_array_equal(S, ref["steps"])
-    assert _ray_errors(Y, ref).max() < TOL64
+    _check_fp64_rays(w, np.arange(w.ncells), Y, ref)
     cell_scale = ref["absY"].mean(axis=1) + 1e-300
     assert (np.abs(dq - rdq) / cell_scale).max() < TOL64
     assert (np.abs(se - rse) / cell_scale).max() < 1e-9

@@ -14,7 +14,7 @@ if not torch.cuda.is_available():
 import oracle  # noqa: E402
 from paper_1810_00188_amd import inputs, rmc  # noqa: E402
 
-from _parity import (TOL32, TOL64, _check_fp32_rays, _ray_errors, _small_channel,  # noqa: E402
+from _parity import (TOL64, _check_fp32_rays, _check_fp64_rays, _small_channel,  # noqa: E402
                      _solver, say)
 
 
@@ -42,7 +42,7 @@ def test_trace_fp64_matches_oracle_per_ray(shape):
     for f in ("n", "g", "o", "k", "steps", "end"):
         np.testing.assert_array_equal(got[f], ref[f], err_msg=f)
     assert np.array_equal(got["p"], ref["p"])
-    assert _ray_errors(got["Y"], ref).max() < TOL64
+    _check_fp64_rays(w, cells, got["Y"], ref)
 
 
 def test_compute_fp64_matches_oracle():
@@ -57,7 +57,7 @@ def test_compute_fp64_matches_oracle():
     ref = oracle.trace_cells(P, np.arange(w.ncells))
     Y, S = s.ray_values(np.arange(w.ncells))
     np.testing.assert_array_equal(S, ref["steps"])
-    assert _ray_errors(Y, ref).max() < TOL64
+    _check_fp64_rays(w, np.arange(w.ncells), Y, ref)
     cell_scale = ref["absY"].mean(axis=1) + 1e-300
     assert (np.abs(dq - rdq) / cell_scale).max() < TOL64
     assert (np.abs(se - rse) / cell_scale).max() < 1e-9
@@ -247,9 +247,10 @@ def test_errors_are_reported_not_fatal():
     assert e.value.status == rmc.RMC_BAD_STATE
     s.set_grid(w.xf, w.yf, w.zf)
     s.set_walls(*w.T_walls)
-    with pytest.raises(rmc.RmcError) as e:
-        s.set_walls(300.0, 300.0, 0.5, 1.0)
-    assert e.value.status == rmc.RMC_UNSUPPORTED
+    for bad in ((300.0, 300.0, 1.5, 1.0), (300.0, 300.0, 1.0, -0.2)):
+        with pytest.raises(rmc.RmcError) as e:
+            s.set_walls(*bad)
+        assert e.value.status == rmc.RMC_INVALID_ARG
     s.set_kdist(w.kd)
     T = w.T.copy()
     T[5] = 5000.0
@@ -293,7 +294,7 @@ def test_cell_pdf_mode_matches_oracle():
     for f in ("n", "g", "o", "k", "steps", "end"):
         np.testing.assert_array_equal(got[f], ref[f], err_msg=f)
     assert np.array_equal(got["p"], ref["p"])
-    assert _ray_errors(got["Y"], ref).max() < TOL64
+    _check_fp64_rays(w, cells, got["Y"], ref)
     dq, _ = s.compute()
     rdq, _, _ = oracle.divergence(P)
     assert (np.abs(dq - rdq) / (ref["absY"].mean(axis=1) + 1e-300)).max() < TOL64
