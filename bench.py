@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--mg-study", choices=["channel64", "dns256"], default=None,
                     help="multigrid time and accuracy against the single-grid march, 1..all levels")
     ap.add_argument("--mg-snaps", type=int, default=0, help="snapshots (random streams) per study row")
+    ap.add_argument("--walls-study", action="store_true",
+                    help="time per compute with reflecting walls and closed boxes (64^3 workloads)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (the "
                          "reference point that scales rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -254,6 +256,47 @@ def mg_study(a):
     s.close()
 
 
+def walls_study(a):
+    """Wall rows (Eq. 3's wall factor with specular reflection, closed boxes of Table 1): time
+    per compute, steps per ray and ray-cell steps per second on 64^3 workloads, black walls
+    against reflecting ones.  Fields resident on the GPU; 2 warm-up and 5 timed computes."""
+    import numpy as np
+    import torch
+    from paper_1810_00188_amd import inputs, rmc
+
+    cases = [("channel 64^3, black walls (benchmark workload)", inputs.channel64()),
+             ("channel 64^3, walls eps = 0.5", inputs.channel64().replace(eps_walls=(0.5, 0.5))),
+             ("channel 64^3, walls eps = 0.1", inputs.channel64().replace(eps_walls=(0.1, 0.1))),
+             ("cube 64^3 Case 12 field, black walls", inputs.cube_3dimens(64)),
+             ("cube 64^3 Case 12 field, walls eps = 0.5", inputs.cube_3dimens(64, eps_walls=0.5)),
+             ("cube 64^3 Case 3 (sin field, grey kappa 0.5), black walls, FP32",
+              inputs.sin_cube(64, kappa=0.5, R=32).replace(march="f32"))]
+    dev = torch.device("cuda", 0)
+    rows = []
+    for name, w in cases:
+        s = rmc.Solver(0)
+        s.set_workload(w, device_fields=True)
+        dq = torch.zeros(w.ncells, dtype=torch.float64, device=dev)
+        for _ in range(2):
+            s.compute(dq)
+        torch.cuda.synchronize()
+        s.reset_stats()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            s.compute(dq)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / 5
+        st = s.stats()
+        row = {"case": name, "ms_per_compute": 1e3 * dt, "march_ms": st["sum_ms_march"] / 5,
+               "steps_per_ray": st["sum_steps"] / (5 * w.ncells * w.R), "steps_per_s": st["sum_steps"] / (5 * dt),
+               "long_steps_share": st["long_steps"] / max(st["steps"], 1)}
+        rows.append(row)
+        print(f"[walls] {json.dumps(row)}", flush=True)
+        s.close()
+    print(json.dumps({"metric": "walls: time per compute and ray-cell steps/s", "unit": "ms", "n_gpus": 1,
+                      "dtype": "f32", "data": "synthetic", "vs_baseline": None, "rows": rows}), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -265,6 +308,9 @@ def main():
         return
     if a.mg_study:
         mg_study(a)
+        return
+    if a.walls_study:
+        walls_study(a)
         return
     import numpy as np
     import torch

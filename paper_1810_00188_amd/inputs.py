@@ -317,6 +317,24 @@ def sin_cube(n: int = 20, kappa: float = 0.5, R: int = 64, seed: int = 0) -> Wor
                     march="f64", accum="f64", closed=True)
 
 
+def cube_3dimens(n: int = 64, R: int = 32, nb: int = 20, ng: int = 7, kP: float = 10.0, table_seed: int = 0,
+                 eps_walls: float = 1.0, march: str = "f32", seed: int = 0) -> Workload:
+    """Case 12 of Table 1: a 1 m cube of H2O at 1 atm with walls at 500 K on all six faces,
+    T = 500 - 2000 (x y z)^2 + 2000 x y z at the cell centres.  Seeded synthetic correlated-k
+    tables (nb bands x ng g-points, Planck mean kP at 1000 K) stand in for the H2O data."""
+    f = uniform_faces(n, 1.0)
+    c = centres(f)
+    P = np.einsum("i,j,k->ijk", c, c, c).reshape(-1)
+    T = as_f32_exact(500.0 - 2000.0 * P ** 2 + 2000.0 * P)
+    kd = synthetic_kdist(nb, ng, [table_seed * 16], [kP / 1.0], k_dtype="f32")
+    nc = n ** 3
+    e = (eps_walls, eps_walls)
+    return Workload(name=f"cube_3dimens_{n}_nb{nb}_ng{ng}", xf=f, yf=f.copy(), zf=f.copy(), T=T,
+                    X=np.ones((1, nc)), kd=kd, T_walls=(500.0, 500.0), eps_walls=e, R=R, seed=seed, march=march,
+                    accum="f64", field_dtype="f32", closed=True, T_walls_x=(500.0, 500.0), eps_walls_x=e,
+                    T_walls_z=(500.0, 500.0), eps_walls_z=e)
+
+
 def channel(nx: int = 64, ny: int = 64, nz: int = 64, R: int = 32, nb: int = 20,
             ng: int = 7, nmodes: int = 8, amp: float = 0.05, field_seed: int = 0,
             table_seed: int = 0, stretch: Optional[float] = None, x_h2o: float = 0.1,
