@@ -638,8 +638,10 @@ struct ContRec {
     uint32_t q;                 // work item index
     int lev;                    // grid level the ray is on (multigrid march; 0 otherwise)
     int i, j, k, steps;         // cell of the next step (on that level)
+    int sgn;                    // direction sign bits (y flips at reflecting walls)
     double tau, acc;
     double t, tx, ty, tz;       // current parameter, next-face parameters
+    double oy;                  // origin y, mirrored at every reflection
 };
 
 __device__ __forceinline__ RayGeo ray_geo(const SnapDesc &D, const double *sf)
@@ -848,6 +850,8 @@ __global__ void __launch_bounds__(256) k_march_lane(MarchArgs<Real> A)
             rc.q = q;
             rc.lev = 0;
             rc.i = R.i; rc.j = R.j; rc.k = R.k; rc.steps = R.steps;
+            rc.sgn = R.sgn;
+            rc.oy = R.oy;
             rc.tau = R.tau; rc.acc = R.acc;
             rc.t = R.t; rc.tx = R.tx; rc.ty = R.ty; rc.tz = R.tz;
             A.cont[idx] = rc;
@@ -911,6 +915,8 @@ __global__ void __launch_bounds__(256) k_march_mg(MarchArgs<Real> A)
             rc.q = q;
             rc.lev = D.nlev - 1;
             rc.i = R.i; rc.j = R.j; rc.k = R.k; rc.steps = R.steps;
+            rc.sgn = R.sgn;
+            rc.oy = R.oy;
             rc.tau = R.tau; rc.acc = R.acc;
             rc.t = R.t; rc.tx = R.tx; rc.ty = R.ty; rc.tz = R.tz;
             A.cont[idx] = rc;
@@ -945,7 +951,11 @@ __global__ void __launch_bounds__(256) k_march_mg(MarchArgs<Real> A)
 // incoming tau and step count, and the ray value is
 //   acc = acc_before + sum_{l < l*} tau_in(l) acc_l + acc(l*).
 // When no segment stops, the contributions are added and the next round starts where the
-// last segment ended.
+// last segment ended.  Reflecting y walls keep the crossings of x and z evenly spaced: the
+// range is then bounded by the black wall a ray reaches within two wall-to-wall traversals,
+// or by the wall losses added to the smallest kappa, and a segment's start state replays the
+// reflections before it with the sequential march's own arithmetic (mirrored origin, flipped
+// direction), so that every segment starts where the sequential march would be.
 template <bool PDF, bool MULTI>
 __global__ void __launch_bounds__(256) k_march_long(MarchArgs<float> A)
 {
@@ -994,13 +1004,28 @@ __global__ void __launch_bounds__(256) k_march_long(MarchArgs<float> A)
         const double dta = ax ? R.dtx : R.dtz;
         const double tw = (((dy > 0.0) ? G.yf[G.ny] : G.yf[0]) - R.oy) * R.ry;   // the wall
         const float km = gld(A.kmin + pair);
+        // reflecting y walls: the ray reaches a black wall within two wall-to-wall traversals,
+        // and every traversal leaves at most the factor sqrt((1 - eps0) (1 - eps1)) of tau
+        const double ry0 = R.ry;
+        const int sgn0 = R.sgn;
+        double tblack = INFINITY, kwall = 0.0;
+        if (G.reflect) {
+            const double e0 = gld(D.epsw + kWallY0), e1 = gld(D.epsw + kWallY1);
+            const double H = G.yf[G.ny] - G.yf[0];
+            if (e0 == 1.0 || e1 == 1.0) tblack = 2.0 * H * fabs(ry0);
+            else if (e0 > 0.0 || e1 > 0.0) kwall = -log((1.0 - e0) * (1.0 - e1)) * fabs(dy) / (2.0 * H);
+        }
         // wave-uniform state of the ray at the start of a round
-        int si = rc.i, sj = rc.j, sk = rc.k, ssteps = rc.steps;
-        double st = rc.t, stx = rc.tx, sty = rc.ty, stz = rc.tz, stau = rc.tau, sacc = rc.acc;
+        int si = rc.i, sj = rc.j, sk = rc.k, ssteps = rc.steps, ssgn = rc.sgn;
+        double st = rc.t, stx = rc.tx, sty = rc.ty, stz = rc.tz, stau = rc.tau, sacc = rc.acc, soy = rc.oy;
         while (true) {
-            double tend = tw;
+            double tend = G.reflect ? st + tblack : tw;
             const double od = log(stau / (double)A.tol);  // optical depth left (> 0: the ray goes on)
-            if (km > 0.0f) tend = fmin(tend, st + od / (double)km);
+            if (!G.reflect) {
+                if (km > 0.0f) tend = fmin(tend, st + od / (double)km);
+            } else if ((double)km + kwall > 0.0) {
+                tend = fmin(tend, st + od / ((double)km + kwall));
+            }
             const double kobs = st > 0.0 ? -log(stau) / st : 0.0;
             if (kobs > 0.0) tend = fmin(tend, st + 1.25 * od / kobs);
             const double ta0 = ax ? stx : stz;
@@ -1015,10 +1040,29 @@ __global__ void __launch_bounds__(256) k_march_long(MarchArgs<float> A)
             if (B0 == 0) {
                 R.i = si; R.j = sj; R.k = sk;
                 R.t = st; R.tx = stx; R.ty = sty; R.tz = stz;
+                R.oy = soy;
+                R.sgn = ssgn;
+                R.ry = ((ssgn ^ sgn0) & 2) ? -ry0 : ry0;
             } else {
                 const long m0 = B0 - 1;                   // the crossing the segment starts on
                 const double ts = ta0 + (double)m0 * dta;
                 R.t = ts;
+                // the y reflections before ts, replayed with the sequential march's arithmetic
+                double oyk = soy;
+                int sgk = ssgn;
+                if (G.reflect)
+                    for (int guard = 0; guard < (1 << 24); ++guard) {
+                        const int side = (sgk & 2) ? 0 : 1;
+                        const double yw = G.yf[side ? G.ny : 0];
+                        const double th = (yw - oyk) * (((sgk ^ sgn0) & 2) ? -ry0 : ry0);
+                        if (!(th <= ts)) break;
+                        oyk = 2.0 * yw - oyk;
+                        sgk ^= 2;
+                    }
+                R.oy = oyk;
+                R.sgn = (R.sgn & ~2) | (sgk & 2);
+                R.ry = ((sgk ^ sgn0) & 2) ? -ry0 : ry0;
+                const double dyk = ((sgk ^ sgn0) & 2) ? -dy : dy;
                 if (ax) {
                     int ii = (int)(((long)si + ((R.sgn & 1) ? -(m0 + 1) : (m0 + 1))) % G.nx);
                     R.i = ii < 0 ? ii + G.nx : ii;
@@ -1040,19 +1084,20 @@ __global__ void __launch_bounds__(256) k_march_long(MarchArgs<float> A)
                     int ii = (int)(ib % G.nx);
                     R.i = ii < 0 ? ii + G.nx : ii;
                 }
-                const double y = R.oy + ts * dy;
-                int lo = 0, hi = G.ny - 1;                // cell containing y, entered in direction dy
+                const double y = R.oy + ts * dyk;
+                int lo = 0, hi = G.ny - 1;                // cell containing y, entered in direction dyk
                 while (lo < hi) {
                     const int mid = (lo + hi + 1) >> 1;
-                    const bool below = (dy > 0.0) ? (G.yf[mid] <= y) : (G.yf[mid] < y);
+                    const bool below = (dyk > 0.0) ? (G.yf[mid] <= y) : (G.yf[mid] < y);
                     if (below) lo = mid; else hi = mid - 1;
                 }
                 R.j = lo;
                 R.ty = (G.yf[lo + ((R.sgn & 2) ? 0 : 1)] - R.oy) * R.ry;
             }
             R.px = brick_x(R.i, G.bsx); R.py = brick_y(R.j, G.bsy); R.pz = brick_z(R.k);
-            const int start_i = R.i, start_j = R.j, start_k = R.k;
+            const int start_i = R.i, start_j = R.j, start_k = R.k, start_sgn = R.sgn;
             const double start_t = R.t, start_tx = R.tx, start_ty = R.ty, start_tz = R.tz;
+            const double start_oy = R.oy, start_ry = R.ry;
             // local march of the segment with tau = 1: lanes below 63 end on their last
             // crossing, lane 63 at tend
             bool wall_end = false;
@@ -1073,13 +1118,19 @@ __global__ void __launch_bounds__(256) k_march_long(MarchArgs<float> A)
                     R.acc += (double)((float)R.tau * a * (float)(Isrc - Ic));
                     R.tau *= x < 0.25f ? 1.0 - (double)a : (double)e;
                     ++R.steps;
-                    if (wall) {   // black y walls only on this path (no reflection, x and z periodic)
-                        const int w = ((wall >> kWallY0) & 1) ? kWallY0 : kWallY1;
-                        R.end = wall_end_code(w);
-                        R.acc += R.tau * (Isrc - gld(D.Iw + (size_t)w * A.nb + n));
-                        R.tau = 0.0;
-                        wall_end = true;
-                        break;
+                    if (wall) {   // y walls only on this path (x and z periodic); reflection done
+                        for (int w = kWallY0; w <= kWallY1; ++w) {
+                            if (!((wall >> w) & 1)) continue;
+                            const double ew = gld(D.epsw + w);
+                            R.acc += R.tau * ew * (Isrc - gld(D.Iw + (size_t)w * A.nb + n));
+                            R.tau *= 1.0 - ew;
+                            if (ew == 1.0) {
+                                R.end = wall_end_code(w);
+                                wall_end = true;
+                                break;
+                            }
+                        }
+                        if (wall_end) break;
                     }
                     if (!(R.tau > (double)A.tol)) break;
                     if (lane < 63 ? (cross && ++next == B1) : (R.t >= tend)) break;
@@ -1113,6 +1164,8 @@ __global__ void __launch_bounds__(256) k_march_long(MarchArgs<float> A)
                 ssteps = __shfl(steps_in + R.steps, 63);
                 si = __shfl(R.i, 63); sj = __shfl(R.j, 63); sk = __shfl(R.k, 63);
                 st = __shfl(R.t, 63); stx = __shfl(R.tx, 63); sty = __shfl(R.ty, 63); stz = __shfl(R.tz, 63);
+                soy = __shfl(R.oy, 63);
+                ssgn = __shfl(R.sgn, 63);
                 continue;
             }
             const int lstar = __ffsll((long long)sm) - 1;
@@ -1121,6 +1174,7 @@ __global__ void __launch_bounds__(256) k_march_long(MarchArgs<float> A)
                 // re-march the stopping segment with its true incoming tau and step count
                 R.i = start_i; R.j = start_j; R.k = start_k;
                 R.t = start_t; R.tx = start_tx; R.ty = start_ty; R.tz = start_tz;
+                R.oy = start_oy; R.ry = start_ry; R.sgn = start_sgn;
                 R.px = brick_x(R.i, G.bsx); R.py = brick_y(R.j, G.bsy); R.pz = brick_z(R.k);
                 R.tau = tau_in;
                 R.acc = 0.0;
@@ -1959,7 +2013,7 @@ struct Plan {
     uint64_t total_cells = 0, max_chunks = 0;
     bool inc_xz = true, pdf_mode = false;   // pdf_mode: per-ray probabilities (modes 1 and 2)
     bool multigrid = false;                 // some snapshot marches on more than one grid
-    bool walls_plain = true;                // every snapshot: periodic x / z, black y walls
+    bool periodic_xz = true;                // every snapshot periodic in x and z (no closed box)
     int smode = 0;
     uint32_t cont_cap = 0;
 };
@@ -1999,7 +2053,7 @@ template <class Real> rmc_status plan_pipeline(rmc_ctx *const *ctxs, int nsnap, 
         P.ntiles += P.D[q].ntiles;
         for (int t = 0; t < P.D[q].ntiles; ++t) tile_snap.push_back(q);
         P.inc_xz = P.inc_xz && P.D[q].hx > 0.0 && P.D[q].hz > 0.0 && !P.D[q].closed;
-        P.walls_plain = P.walls_plain && !P.D[q].closed && !P.D[q].reflect;
+        P.periodic_xz = P.periodic_xz && !P.D[q].closed;
     }
     const uint64_t max_items = (P.total_cells * R + (uint64_t)nbucket * 63 + 63) / 64 * 64;
     P.max_chunks = max_items / 64;
@@ -2109,7 +2163,7 @@ rmc_status enqueue_pipeline(const Plan &P, double *const *divq, double *const *s
     MA.tol = (Real)O.tol;
     MA.max_steps = O.max_steps;
     // long rays are segmented only in the FP32 march over uniform periodic x and z
-    const bool segment = sizeof(Real) == 4 && P.inc_xz && P.walls_plain;
+    const bool segment = sizeof(Real) == 4 && P.inc_xz && P.periodic_xz;
     const int lrs = O.long_ray_steps > 0 ? O.long_ray_steps : 256;
     MA.cap = segment ? std::min(lrs, O.max_steps) : O.max_steps;
     MA.kmin = L->kmin.as<float>();
