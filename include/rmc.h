@@ -260,8 +260,11 @@ rmc_status rmc_get_pdf(rmc_ctx *ctx, double *p, double *cdf_b, double *cdf_g, do
  * importance weight of Eq. 14 with the probability it was drawn with, so the estimate stays
  * unbiased for any positive pdf (the argument that lets the T_max pdf stand in for a cell's
  * own emission pdf, Eqs. 13-14).  With RMC_SAMPLING_LEARNED the rays of cell c are drawn from
- *   p_c(n,g,o) = (1 - mix_eps) softmax over all (n,g,o) of zg_c + mix_eps p_plain(n,g) / 8,
- * zg_c(n,g,o) = z(x_{c,n,g})[o xor m_c], where z is the network below and m_c the sign bits
+ *   p_c(n,g,o) = (1 - mix_eps) softmax over all (n,g,o) of [zg_c + log p_plain(n,g)]
+ *                + mix_eps p_plain(n,g) / 8,
+ * so that a network whose logits are all equal reproduces the plain (T_max) allocation and
+ * the network learns corrections to it; zg_c(n,g,o) = z(x_{c,n,g})[o xor m_c] (returned by
+ * rmc_allocator_logits, without the prior), where z is the network below and m_c the sign bits
  * (x: 1, y: 2, z: 4) of the cell's temperature gradient, so that the network sees octants in
  * the frame of the local gradient.  The draws use the cell's allocation stream exactly as the
  * other modes (band, then g within the band, then octant, by inversion of cumulative sums

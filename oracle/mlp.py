@@ -12,7 +12,10 @@ Model (one evaluation per cell and (n, g), eight octant logits each):
     h1 = relu(W1 x + b1), h2 = relu(W2 h1 + b2), h3 = relu(W3 h2 + b3), z = W4 h3 + b4
     octant logit of global octant o: z[o xor m_c], m_c = sign bits of grad T (x, y, z), so the
     network sees octants in a frame oriented by the local temperature gradient
-    q_c = softmax over all (n, g, o);  p_c = (1 - eps) q_c + eps p_plain(n, g) / 8
+    q_c = softmax over all (n, g, o) of z + log p_plain(n, g)   (the plain pdf as the prior:
+          a network that outputs zero reproduces the plain allocation, and training learns
+          corrections to it)
+    p_c = (1 - eps) q_c + eps p_plain(n, g) / 8
 
 Training objective, from rays i drawn with the plain pdf p0 (value Y_i = h_i / p0_i), for a
 batch of cells c:
@@ -164,10 +167,17 @@ def octant_logits(z: np.ndarray, m: np.ndarray) -> np.ndarray:
     return np.take_along_axis(z, idx[:, None, None, :], axis=-1)
 
 
+def prior_logits(zg: np.ndarray, p_plain: np.ndarray) -> np.ndarray:
+    """zg + log p_plain(n, g), the arguments of the allocation softmax."""
+    with np.errstate(divide="ignore"):
+        return zg + np.log(np.asarray(p_plain, dtype=np.float64))[None, :, :, None]
+
+
 def cell_pdf(zg: np.ndarray, p_plain: np.ndarray, eps: float) -> np.ndarray:
-    """p_c(n,g,o) = (1 - eps) softmax_{(n,g,o)}(zg_c) + eps p_plain(n,g)/8, shape of zg."""
+    """p_c(n,g,o) = (1 - eps) softmax_{(n,g,o)}(zg_c + log p_plain(n,g)) + eps p_plain(n,g)/8,
+    shape of zg."""
     nc = zg.shape[0]
-    flat = zg.reshape(nc, -1)
+    flat = prior_logits(zg, p_plain).reshape(nc, -1)
     e = np.exp(flat - flat.max(axis=1, keepdims=True))
     q = (e / e.sum(axis=1, keepdims=True)).reshape(zg.shape)
     return (1.0 - eps) * q + eps * (p_plain[None, :, :, None] / 8.0)
@@ -178,7 +188,7 @@ def allocation_loss(zg, p_plain, eps, cell_of, strata, h, p0, ray_cost=None):
     samples (the cost factors are dropped without ray_cost).  Returns (L, dL/dzg)."""
     nc = zg.shape[0]
     shp = zg.shape
-    flat = zg.reshape(nc, -1)
+    flat = prior_logits(zg, p_plain).reshape(nc, -1)
     e = np.exp(flat - flat.max(axis=1, keepdims=True))
     sig = e / e.sum(axis=1, keepdims=True)
     pp = np.repeat(p_plain.reshape(-1), 8) / 8.0

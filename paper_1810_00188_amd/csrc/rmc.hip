@@ -1487,7 +1487,7 @@ struct rmc_ctx {
     // learned allocation: network, features, per-ray draws, training state and scratch
     bool have_alloc = false;
     int adam_t = 0;
-    DBuf prm, musd, nu_c, gxs, kp, feat, fmask, bng, lfaces, dstrat, dprob, adam1, adam2;
+    DBuf prm, musd, nu_c, gxs, kp, feat, fmask, bng, lfaces, dstrat, dprob, adam1, adam2, lpp;
     DBuf tr_feat, tr_mask, tr_act, tr_del, tr_dz, tr_Lc, tr_scal, tr_err, tr_part, tr_grad;
     // pdf and fields of the last compute
     DBuf pdf_scratch, p, cdf_b, cdf_g, W, Iw, status;
@@ -1764,7 +1764,7 @@ rmc_status plan_learned(rmc_ctx *c)
     rmc_status st;
     if ((st = plan_features(c))) return st;
     if (net_launch(c).lds_draw > 64 * 1024) return fail(RMC_UNSUPPORTED, "nb * ng too large for the allocation kernel");
-    if ((st = c->bng.ensure(sizeof(float) * c->nb * c->ng * kHid)) ||
+    if ((st = c->bng.ensure(sizeof(float) * c->nb * c->ng * kHid)) || (st = c->lpp.ensure(sizeof(double) * c->nb * c->ng)) ||
         (st = c->dstrat.ensure(sizeof(uint32_t) * ncells_of(c) * c->opt.rays_per_cell)))
         return st;
     return RMC_OK;
@@ -1826,9 +1826,13 @@ rmc_status enqueue_learned(rmc_ctx *c, hipStream_t s)
 {
     rmc_status st;
     if ((st = enqueue_features(c, s)) || (st = enqueue_spec(c, s))) return st;
+    const int P = c->nb * c->ng;
+    hipLaunchKernelGGL(k_log_pdf, dim3((P + 255) / 256), dim3(256), 0, s, c->p.as<double>(), P, c->lpp.as<double>());
+    HIPCHK(hipGetLastError());
     AllocNetArgs A = net_args(c);
     A.ncell = (int)ncells_of(c);
     A.pplain = c->p.as<double>();
+    A.lpp = c->lpp.as<double>();
     A.dstrat = c->dstrat.as<uint32_t>();
     A.dprob = c->dprob.as<double>();
     const NetLaunch NL = net_launch(c);

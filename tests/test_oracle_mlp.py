@@ -183,3 +183,23 @@ def test_features_and_gradient():
     assert kpt.shape == (1, w.kd.nT)
     assert kpt[0, 100] == pytest.approx(10.0 / 0.1, rel=1e-6)   # table scaled to 10 m^-1 at x = 0.1
     assert g.shape == (3, 6, 5, 4)
+
+
+def test_zero_network_output_is_the_plain_allocation():
+    """The allocation softmax runs over the network's logits plus log p_plain(n, g): logits
+    that are equal for every stratum give exactly the plain pdf p_plain(n, g) / 8 for any
+    mixture weight, and the training objective of rays drawn from it is exactly 1."""
+    rng = np.random.default_rng(2)
+    nb, ng, nc = 4, 3, 6
+    p_plain = rng.uniform(0.01, 1.0, (nb, ng))
+    p_plain /= p_plain.sum()
+    for eps in (0.0, 0.3, 1.0):
+        zg = np.full((nc, nb, ng, 8), rng.normal())
+        p = mlp.cell_pdf(zg, p_plain, eps)
+        np.testing.assert_allclose(p, np.broadcast_to(p_plain[None, :, :, None] / 8, p.shape), rtol=1e-14)
+    strata = rng.integers(0, nb * ng * 8, 50)
+    p0 = np.repeat(p_plain.ravel(), 8)[strata] / 8.0
+    cell_of = np.sort(rng.integers(0, nc, 50))
+    L, dz = mlp.allocation_loss(np.zeros((nc, nb, ng, 8)), p_plain, 0.1, cell_of, strata, rng.normal(size=50), p0,
+                                ray_cost=rng.uniform(1, 5, 50))
+    assert abs(L - 1.0) < 1e-13
