@@ -240,3 +240,46 @@ def test_training_lowers_the_loss():
     say(f"training: loss {first:.4f} -> {last:.4f}")
     assert last < 0.9 * first
     assert np.all(np.isfinite(s.get_allocator()))
+
+
+def test_trained_network_gains_over_plain_on_held_out_field():
+    """What the trained network gains: trained by the library's kernels on two fields, on a
+    held-out field it reaches a given RMS error of the heat source with less work (error^2 x
+    steps per ray at equal R) than the plain allocation, and its error keeps falling as
+    R^-1/2 (the importance weights keep it unbiased: no error floor)."""
+    from paper_1810_00188_amd import learned
+    eps = 0.1
+
+    def gen(fs):
+        return inputs.channel(nx=16, ny=16, nz=16, R=32, nb=5, ng=3, amp=0.1, field_seed=fs)
+
+    w0 = gen(1)
+    say(f"learned gain {w0.name}")
+    s = _solver(w0, mix_eps=eps)
+    runs, feats = [], []
+    for k, fs in enumerate((1, 2)):
+        w = gen(fs)
+        s.set_temperature(np.ascontiguousarray(w.T, dtype=np.float32))
+        s.set_species(np.ascontiguousarray(w.X, dtype=np.float32))
+        s.set_options(rmc.default_options(rays_per_cell=64, seed=w.seed, snapshot=k + 1, tol=w.tol,
+                                          max_steps=w.max_steps, march=rmc.F32, mix_eps=eps))
+        runs.append(learned.plain_samples(s, np.arange(w.ncells)))
+        feats.append(runs[-1].feat.cpu().numpy())
+    nu_c, gx = learned.spectral_inputs(w0.kd)
+    mu, sd = learned.standardisation(feats, w0.kd)
+    s.set_allocator(learned.init_params(0), mu, sd, nu_c, gx)
+    losses = learned.train(s, runs, 600, 2e-3, 64)
+    params = s.get_allocator()
+    s.close()
+    w = gen(1000)
+    s_plain = _solver(w)
+    s_learn = _solver(w, sampling=rmc.SAMPLING_LEARNED, mix_eps=eps)
+    s_learn.set_allocator(params, mu, sd, nu_c, gx)
+    out = learned.time_to_error(w, s_plain, s_learn, eps, Rs=(16, 64), ref_runs=8, ref_R=255, reps=1)
+    pl, le = out["plain"], out["learned"]
+    work = [(x["rel_err"][1] ** 2) * x["steps_per_ray"][1] for x in (pl, le)]
+    say(f"training loss {np.mean(losses[:20]):.3f} -> {np.mean(losses[-20:]):.3f}; error at R = 64: plain "
+        f"{pl['rel_err'][1]:.4f}, learned {le['rel_err'][1]:.4f}; steps/ray {pl['steps_per_ray'][1]:.1f} vs "
+        f"{le['steps_per_ray'][1]:.1f}; work ratio {work[1] / work[0]:.3f}; error slope {le['err_slope']:.3f}")
+    assert work[1] < 0.85 * work[0]
+    assert -0.6 < le["err_slope"] < -0.4
