@@ -1733,7 +1733,7 @@ NetLaunch net_launch(const rmc_ctx *c)
         NetLaunch L;
         L.cpb = cpb;
         L.lds_logits = sizeof(float) * ((size_t)cpb * S + (size_t)cpb * kHid + ((cpb + 15) / 16) * 4);
-        L.lds_draw = L.lds_logits + sizeof(double) * (2 * (size_t)c->nb + 256);
+        L.lds_draw = L.lds_logits + sizeof(double) * (4 * (size_t)c->nb + 256);
         return L;
     };
     int cpb = 16;   // as many cells as fit in 64 KiB of LDS

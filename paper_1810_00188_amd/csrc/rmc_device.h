@@ -58,6 +58,14 @@ __device__ __forceinline__ uint4 gld(const uint4 *p)
     return make_uint4(v.x, v.y, v.z, v.w);
 }
 
+__device__ __forceinline__ float4 gld(const float4 *p)
+{
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    typedef const __attribute__((address_space(1))) v4f gv4f;
+    const v4f v = *(gv4f *)(p);
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+
 // Spectral / octant variate: all 32 bits, (w + 1/2) 2^-32, exact in double, in (0, 1).
 __device__ __forceinline__ double unif_alloc(uint32_t w) { return ((double)w + 0.5) * 0x1p-32; }
 
