@@ -368,6 +368,12 @@ def main():
         rec = json.load(open(a.traffic_json)).get("k_march_lane", {})
         if rec.get("source_sha256") == kernel_source_hash() and not mg:   # counters of this very code only
             traffic = rec.get("bytes_per_launch")
+    # the march's access pattern alone (no physics): the gather bandwidth it can reach
+    probe_steps = max(1, int(round(lane_steps / max(st["rays"], 1))))
+    pms, pbytes = s.gather_probe(probe_steps)
+    s.gather_probe(probe_steps)
+    pms2, _ = s.gather_probe(probe_steps)
+    achievable = pbytes / (min(pms, pms2) * 1e-3) / 1e9
     out = {
         "metric": "ray-cell steps/s",
         "value": value,
@@ -394,7 +400,10 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "ms_per_launch": lane_ms,
                      "algorithmic_bytes_per_launch": bytes_launch,
-                     "steps_per_launch": lane_steps, "rays_per_launch": st["rays"]},
+                     "steps_per_launch": lane_steps, "rays_per_launch": st["rays"],
+                     "achievable_gather_gbs": achievable, "frac_of_achievable": achieved / achievable,
+                     "achievable_probe": f"rmc_gather_probe: {st['rays']} lanes x {probe_steps} steps of the "
+                                         f"march's access pattern without the physics"},
     }
     if a.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(w.replace(mg_levels=a.mg_levels, mg_steps=a.mg_steps or 5) if mg else w,

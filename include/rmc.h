@@ -204,6 +204,17 @@ rmc_status rmc_set_options(rmc_ctx *ctx, const rmc_options *opt);
  * Resets the statistics (rmc_reset_stats) after timing.  Synchronises the stream. */
 rmc_status rmc_autotune(rmc_ctx *ctx, int reps, const char *cache_path, rmc_options *out, void *stream);
 
+/* Measurement aid (the roofline of the march, not part of the method): the march's memory
+ * access alone.  Every lane of ncells x R walks a straight ray of `steps` unit cells (x and z
+ * periodic, y reflected) from a cell of its wavefront's tile region and reads per step the
+ * FP32 kappa and the FP64 intensity of its cell from the planes of the last compute, with the
+ * march's XCD-aware launch order and one (n, g) pair per run of chunks, but no physics.
+ * *ms receives the kernel time (HIP events on `stream`, synchronised), *bytes the bytes it
+ * gathers (12 per step) and writes (8 per wavefront): bytes / ms is the gather bandwidth the
+ * march's access pattern can reach.  Needs a previous compute with the FP32 march
+ * (RMC_BAD_STATE otherwise); steps in [1, 65536]. */
+rmc_status rmc_gather_probe(rmc_ctx *ctx, int steps, double *ms, double *bytes, void *stream);
+
 /* Per-cell allocation pdf over (n, g, octant) for RMC_SAMPLING_PDF: q[ncells][nb][ng][8]
  * (double, >= 0, not necessarily normalised, host or device).  The rays of cell c are
  * drawn from (1 - mix_eps) q_c / sum q_c + mix_eps p_plain(n, g) / 8 and weighted by the

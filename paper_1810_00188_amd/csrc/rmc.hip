@@ -1207,6 +1207,68 @@ __global__ void __launch_bounds__(256) k_march_long(MarchArgs<float> A)
 
 #include "learn_kernels.inc"
 
+// ------------------------------------------------------------------------ gather probe
+// The memory side of the march alone, for the denominator of its roofline: every lane walks a
+// straight ray of `steps` cells and reads per step the FP32 kappa and the FP64 intensity of
+// its cell from the planes of the last compute, with the march's launch order (XCD-aware
+// chunks; the chunks of one (n, g) pair in a row, each starting in the tile region its
+// position in the pair's share points to, lanes at cells of one 256-cell tile) -- without the
+// physics.  Unit cells, x and z periodic, y reflected at the walls; directions from a hash.
+__device__ __forceinline__ uint32_t probe_hash(uint32_t x)
+{
+    x ^= x >> 16; x *= 0x7FEB352Du; x ^= x >> 15; x *= 0x846CA68Bu; x ^= x >> 16;
+    return x;
+}
+
+__global__ void __launch_bounds__(256) k_gather_probe(const float *__restrict__ kap, const double *__restrict__ Ipl,
+                                                      SnapDesc D, int npairs, int ng, int steps, uint32_t nchunks,
+                                                      int span_log2, double *__restrict__ out)
+{
+    const int wib = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+    const uint32_t chunk = __builtin_amdgcn_readfirstlane(xcd_chunk(blockIdx.x, (uint32_t)wib, span_log2));
+    if (chunk >= nchunks) return;
+    const int pair = (int)((uint64_t)chunk * npairs / nchunks), n = pair / ng;
+    const uint64_t c0 = ((uint64_t)pair * nchunks + npairs - 1) / npairs;      // first chunk of the pair
+    const uint64_t c1 = ((uint64_t)(pair + 1) * nchunks + npairs - 1) / npairs;
+    const float *K = kap + (size_t)pair * D.ncpad;
+    const double *I = Ipl + (size_t)n * D.ncpad;
+    const uint64_t tiles = (D.ncpad + 255) / 256;
+    const uint64_t tile = (chunk - c0) * tiles / (c1 > c0 ? c1 - c0 : 1);
+    const uint32_t h0 = probe_hash(chunk * 64u + (uint32_t)lane);
+    int i, j, k;
+    if (!brick_cell(D, min(tile * 256 + (h0 & 255u), D.ncpad - 1), i, j, k)) {
+        i = min(i, D.nx - 1); j = min(j, D.ny - 1); k = min(k, D.nz - 1);
+    }
+    const uint32_t h1 = probe_hash(h0 ^ 0x9E3779B9u), h2 = probe_hash(h1 + 0x632BE5ABu);
+    const float dx = (float)(h0 >> 8) * 0x1p-24f - 0.5f, dy = (float)(h1 >> 8) * 0x1p-24f - 0.5f,
+                dz = (float)(h2 >> 8) * 0x1p-24f - 0.5f;
+    const float ax = 1.0f / fmaxf(fabsf(dx), 1e-6f), ay = 1.0f / fmaxf(fabsf(dy), 1e-6f),
+                az = 1.0f / fmaxf(fabsf(dz), 1e-6f);
+    int sx = dx > 0.0f ? 1 : -1, sy = dy > 0.0f ? 1 : -1, sz = dz > 0.0f ? 1 : -1;
+    float tx = 0.5f * ax, ty = 0.5f * ay, tz = 0.5f * az;
+    const int bsx = D.nby * D.nbz * 64, bsy = D.nbz * 64;
+    double acc = 0.0;
+    for (int st = 0; st < steps; ++st) {
+        const int cell = brick_x(i, bsx) + brick_y(j, bsy) + brick_z(k);
+        acc += (double)gld(K + cell) * gld(I + cell);
+        if (tx <= ty && tx <= tz) {
+            i += sx;
+            i = i == D.nx ? 0 : (i < 0 ? D.nx - 1 : i);
+            tx += ax;
+        } else if (ty <= tz) {
+            j += sy;
+            if (j < 0 || j >= D.ny) { j -= sy; sy = -sy; }
+            ty += ay;
+        } else {
+            k += sz;
+            k = k == D.nz ? 0 : (k < 0 ? D.nz - 1 : k);
+            tz += az;
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (lane == 0) out[chunk] = acc;
+}
+
 // --------------------------------------------------------------------------- trace
 template <class Real> struct TraceArgs {
     const SnapDesc *snaps;
@@ -1499,7 +1561,7 @@ struct rmc_ctx {
     // shared pipeline workspace (used when this context leads a batch)
     DBuf hist, bucket_total, bucket_start, nchunks, chunk_bucket, items, faces, snaps, tile_snap, counters, red_part,
         outbuf, tune_out;
-    DBuf trace_rec, trace_cells, border, kmin, cont, cont_count;
+    DBuf trace_rec, trace_cells, border, kmin, cont, cont_count, probe;
     std::vector<float> h_kmin;
     double Tmin_cells = 0;
     double xmin[8] = {0};
@@ -3024,6 +3086,46 @@ rmc_status rmc_get_stats(rmc_ctx *c, rmc_stats *out)
     out->sum_ms_alloc = c->sum_ms[1];
     out->sum_ms_march = c->sum_ms[2] + c->sum_ms[3];
     out->sum_ms_reduce = c->sum_ms[4];
+    return RMC_OK;
+}
+
+rmc_status rmc_gather_probe(rmc_ctx *c, int steps, double *ms, double *bytes, void *stream)
+{
+    g_err.clear();
+    if (rmc_status st = check_ctx(c)) return st;
+    if (steps < 1 || steps > 65536 || !ms || !bytes) return fail(RMC_INVALID_ARG, "bad arguments");
+    if (!c->field.p || c->slots_real != 4 || c->slots_R < 1)
+        return fail(RMC_BAD_STATE, "the probe reads the FP32 planes of a previous compute with the FP32 march");
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(RMC_DEVICE_ERROR, "hipSetDevice(%d) failed", c->device);
+    hipStream_t s = (hipStream_t)stream;
+    SnapDesc D{};
+    D.nx = c->nx; D.ny = c->ny; D.nz = c->nz;
+    D.nbx = round_up(c->nx, 4) / 4; D.nby = round_up(c->ny, 4) / 4; D.nbz = round_up(c->nz, 4) / 4;
+    D.ncpad = ncpad_of(c);
+    const uint64_t lanes = ncells_of(c) * (uint64_t)c->slots_R;
+    const uint32_t nchunks = (uint32_t)((lanes + 63) / 64);
+    int span_log2 = 0;
+    for (int sp = c->opt.xcd_span > 0 ? c->opt.xcd_span : 256; sp > 1; sp >>= 1) ++span_log2;
+    rmc_status st;
+    if ((st = c->probe.ensure(sizeof(double) * nchunks))) return st;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, s));
+    hipLaunchKernelGGL(k_gather_probe, dim3((unsigned)xcd_blocks(nchunks, span_log2)), dim3(256), 0, s,
+                       c->field.as<float>(), c->Iplane.as<double>(), D, c->nb * c->ng, c->ng, steps, nchunks,
+                       span_log2, c->probe.as<double>());
+    const hipError_t le = hipGetLastError();
+    HIPCHK(hipEventRecord(e1, s));
+    HIPCHK(hipEventSynchronize(e1));
+    float t = 0.0f;
+    HIPCHK(hipEventElapsedTime(&t, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIPCHK(le);
+    *ms = t;
+    *bytes = (double)lanes * steps * (sizeof(float) + sizeof(double)) + (double)nchunks * sizeof(double);
     return RMC_OK;
 }
 

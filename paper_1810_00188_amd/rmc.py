@@ -75,6 +75,7 @@ SIGNATURES = {
     "rmc_set_grid": (C.c_int, [_VP, C.c_int, C.c_int, C.c_int, _VP, _VP, _VP]),
     "rmc_set_walls": (C.c_int, [_VP, C.c_double, C.c_double, C.c_double, C.c_double]),
     "rmc_set_box_walls": (C.c_int, [_VP, _VP, _VP]),
+    "rmc_gather_probe": (C.c_int, [_VP, C.c_int, _VP, _VP, _VP]),
     "rmc_set_kdist": (C.c_int, [_VP, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
                                 _VP, _VP, _VP, C.c_int, _VP]),
     "rmc_set_temperature": (C.c_int, [_VP, _VP, C.c_int, C.c_int, _VP]),
@@ -209,6 +210,12 @@ class Solver:
 
     def set_walls(self, T0, T1, eps0=1.0, eps1=1.0):
         _check(LIB.rmc_set_walls(self.h, float(T0), float(T1), float(eps0), float(eps1)))
+
+    def gather_probe(self, steps, stream=None):
+        """(ms, bytes) of the march's memory access pattern alone (see rmc_gather_probe)."""
+        ms, by = C.c_double(), C.c_double()
+        _check(LIB.rmc_gather_probe(self.h, int(steps), C.byref(ms), C.byref(by), _stream(stream)))
+        return ms.value, by.value
 
     def set_box_walls(self, T=None, eps=None):
         """Closed box: walls x0, x1, z0, z1 with temperatures T[4] and emissivities eps[4];
