@@ -2703,6 +2703,8 @@ rmc_status rmc_set_options(rmc_ctx *c, const rmc_options *o)
     return RMC_OK;
 }
 
+}  // extern "C"
+
 namespace {
 
 // Workload signature of an autotuning cache line: the device architecture and everything that
@@ -2738,6 +2740,8 @@ bool tune_cache_lookup(const char *path, const std::string &sig, int &span, int 
 }
 
 }  // namespace
+
+extern "C" {
 
 rmc_status rmc_autotune(rmc_ctx *c, int reps, const char *cache_path, rmc_options *out, void *stream)
 {
