@@ -999,6 +999,8 @@ __global__ void __launch_bounds__(256) k_march_long(MarchArgs<float> A)
             U.hz *= sc;
             R.dtx *= sc;
             R.dtz *= sc;
+            R.wx = R.stx > 0 ? 0 : G.nx - 1;
+            R.wz = R.stz > 0 ? 0 : G.nz - 1;
         }
         const bool ax = fabs(dx) >= fabs(dz);            // the crossing axis
         const double dta = ax ? R.dtx : R.dtz;

@@ -177,6 +177,7 @@ template <class Real, bool INC_XZ> struct Ray {
     int i, j, k, wi, wk;        // current cell (x, z local index and wrap count)
     int px, py, pz;             // brick offsets of the current cell
     int sgn;                    // bit 0/1/2: x/y/z direction negative
+    int stx, stz, wx, wz;       // INC_XZ: x / z step (+-1) and the index a step past the edge wraps to
     int steps, end;
 };
 
@@ -194,6 +195,12 @@ __device__ __forceinline__ void ray_init(Ray<Real, INC_XZ> &R, const RayGeo &G, 
     R.oy = 0.5 * (G.yf[cj] + G.yf[cj + 1]);
     R.oz = 0.5 * (G.zf[ck] + G.zf[ck + 1]);
     R.sgn = (dx > 0.0 ? 0 : 1) | (dy > 0.0 ? 0 : 2) | (dz > 0.0 ? 0 : 4);
+    if constexpr (sizeof(Real) == 4 && INC_XZ) {
+        R.stx = dx > 0.0 ? 1 : -1;
+        R.stz = dz > 0.0 ? 1 : -1;
+        R.wx = R.stx > 0 ? 0 : G.nx - 1;
+        R.wz = R.stz > 0 ? 0 : G.nz - 1;
+    }
     if constexpr (sizeof(Real) == 8) {
         R.rx = dx; R.ry = dy; R.rz = dz;
         R.tx = (G.xf[ci + (dx > 0.0)] - R.ox) / dx;
@@ -269,8 +276,9 @@ __device__ __forceinline__ void reflect_z(Ray<Real, INC_XZ> &R, const RayGeo &G,
 
 // Geometry of a step: the segment length ds in the current cell, the axis steps, the walls
 // the step ends on (mask of wall bits); returns the brick offset of the next cell.  With
-// reflecting walls the ray is mirrored here and goes on in the wall cell; with black walls
-// the offset is the current cell's (the caller's load stays in bounds; the ray ends).
+// reflecting walls the ray is mirrored here and goes on in the wall cell.  A step onto a
+// wall never updates that axis' brick offset, so the returned offset is always a cell of the
+// grid (at a black wall the caller's load stays in bounds and its value is not used).
 template <class Real, bool INC_XZ>
 __device__ __forceinline__ int ray_advance(Ray<Real, INC_XZ> &R, const RayGeo &G, double &ds, int &wall)
 {
@@ -278,17 +286,16 @@ __device__ __forceinline__ int ray_advance(Ray<Real, INC_XZ> &R, const RayGeo &G
     ds = te - R.t;
     R.t = te;
     wall = 0;
-    const int cur = R.px + R.py + R.pz;
     if constexpr (sizeof(Real) == 4 && INC_XZ) {
         // uniform periodic x and z: branch-free updates
         const bool mx = R.tx == te, mz = R.tz == te;
-        int i = R.i + (mx ? ((R.sgn & 1) ? -1 : 1) : 0);
-        i = i == G.nx ? 0 : (i < 0 ? G.nx - 1 : i);
+        int i = R.i + (mx ? R.stx : 0);
+        i = (unsigned)i >= (unsigned)G.nx ? R.wx : i;   // a step past either edge wraps
         R.i = i;
         R.px = brick_x(i, G.bsx);
         R.tx += mx ? R.dtx : 0.0;
-        int k = R.k + (mz ? ((R.sgn & 4) ? -1 : 1) : 0);
-        k = k == G.nz ? 0 : (k < 0 ? G.nz - 1 : k);
+        int k = R.k + (mz ? R.stz : 0);
+        k = (unsigned)k >= (unsigned)G.nz ? R.wz : k;
         R.k = k;
         R.pz = brick_z(k);
         R.tz += mz ? R.dtz : 0.0;
@@ -337,7 +344,7 @@ __device__ __forceinline__ int ray_advance(Ray<Real, INC_XZ> &R, const RayGeo &G
             else R.ty = f / R.ry;
         }
     }
-    return (wall && !G.reflect) ? cur : R.px + R.py + R.pz;
+    return R.px + R.py + R.pz;
 }
 
 // Absorption of a step in the current cell (kappa kc, intensity Ic, length ds); adds the
@@ -425,6 +432,8 @@ __device__ __forceinline__ void ray_descend(Ray<Real, INC_XZ> &R, const RayGeo &
         R.dtz *= 2.0;
         R.i >>= 1;
         R.k >>= 1;
+        R.wx = R.stx > 0 ? 0 : G1.nx - 1;
+        R.wz = R.stz > 0 ? 0 : G1.nz - 1;
     } else {
         R.i >>= 1;
         R.k >>= 1;
