@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--mg-study", choices=["channel64", "dns256"], default=None,
                     help="multigrid time and accuracy against the single-grid march, 1..all levels")
     ap.add_argument("--mg-snaps", type=int, default=0, help="snapshots (random streams) per study row")
+    ap.add_argument("--batch12", action="store_true",
+                    help="12 uneven snapshots (50 bands x 8 g) in one pass: autotuned, eager and HIP graph")
     ap.add_argument("--walls-study", action="store_true",
                     help="time per compute with reflecting walls and closed boxes (64^3 workloads)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -297,6 +299,64 @@ def walls_study(a):
                       "dtype": "f32", "data": "synthetic", "vs_baseline": None, "rows": rows}), flush=True)
 
 
+def batch12_bench(a):
+    """The batched configuration: 12 snapshots of uneven size (3 each of 64^3, 96x64x64, 128^3,
+    192x96x96; stretched y; 50 bands x 8 g; R = 32; FP32 march, FP64 sums) in one pipeline pass
+    -- one bucketing and one march launch over all of them -- with the launch schedule picked by
+    the autotuner, timed eagerly (rmc_compute_batch) and as a captured HIP graph replayed."""
+    import torch
+    from paper_1810_00188_amd import inputs, rmc
+
+    ws = inputs.batch12()
+    dev = torch.device("cuda", 0)
+    solvers = []
+    for w in ws:
+        s = rmc.Solver(0)
+        s.set_workload(w, device_fields=True)
+        solvers.append(s)
+    t0 = time.perf_counter()
+    choice = solvers[9].autotune(reps=2)
+    t_tune = time.perf_counter() - t0
+    for s, w in zip(solvers, ws):
+        s.set_workload(w, device_fields=True, xcd_span=choice["xcd_span"], length_sort=choice["length_sort"])
+    outs = [torch.zeros(w.ncells, dtype=torch.float64, device=dev) for w in ws]
+    for _ in range(2):
+        rmc.compute_batch(solvers, outs)
+    torch.cuda.synchronize()
+    solvers[0].reset_stats()
+    K = 5
+    t0 = time.perf_counter()
+    for _ in range(K):
+        rmc.compute_batch(solvers, outs)
+    torch.cuda.synchronize()
+    eager = (time.perf_counter() - t0) / K
+    st = solvers[0].stats()
+    steps, rays = st["steps"], st["rays"]
+    cs = torch.cuda.Stream()             # capture needs a stream of its own (default priority)
+    with torch.cuda.stream(cs):
+        g = rmc.Graph(solvers, outs)
+        g.launch()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(2 * K):
+            g.launch()
+        torch.cuda.synchronize()
+        graph = (time.perf_counter() - t0) / (2 * K)
+        g.close()
+    out = {"metric": "batched snapshots: ray-cell steps/s", "value": steps / graph, "unit": "ray-cell steps/s",
+           "higher_is_better": True, "n_gpus": 1, "dtype": "f32", "data": "synthetic", "vs_baseline": None,
+           "config": {"workload": "12 snapshots: 3 x 64^3, 3 x 96x64x64, 3 x 128^3, 3 x 192x96x96, stretched y, "
+                                  "50 bands x 8 g, 32 rays/cell, FP32 march, FP64 sums",
+                      "cells": sum(w.ncells for w in ws), "rays_per_batch": rays, "steps_per_batch": steps},
+           "ms_per_batch_graph": 1e3 * graph, "ms_per_batch_eager": 1e3 * eager,
+           "steps_per_s_eager": steps / eager, "autotune": choice, "autotune_s": t_tune,
+           "phases_ms_eager": {"prep": st["ms_prep"], "alloc": st["ms_alloc"], "march": st["ms_march"],
+                               "reduce": st["ms_reduce"]}}
+    print(json.dumps(out), flush=True)
+    for s in solvers:
+        s.close()
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -311,6 +371,9 @@ def main():
         return
     if a.walls_study:
         walls_study(a)
+        return
+    if a.batch12:
+        batch12_bench(a)
         return
     import numpy as np
     import torch
