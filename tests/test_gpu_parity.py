@@ -316,14 +316,22 @@ def test_batch_equals_single_snapshots():
 
 
 # ------------------------------------------------------------------------- HIP graphs
-def test_graph_replays_match_eager():
+@pytest.mark.parametrize("variant", ["plain", "multigrid_reflecting", "closed_box"])
+def test_graph_replays_match_eager(variant):
     """Capture one compute of a 2-snapshot batch, replay it several times with eager work and
     synchronisations between the replays, and with new temperature fields set between
-    replays; every replay equals an eager compute of the same fields."""
-    ws = [_small_channel(march="f32", nx=8, ny=6, nz=5, R=8, field_seed=q).replace(snap=q) for q in range(2)]
+    replays; every replay equals an eager compute of the same fields.  Also with the
+    multigrid march and reflecting walls (coarse-field kernels and segmented long rays in the
+    graph), and in closed boxes."""
+    ws = [_small_channel(march="f32", nx=8, ny=6, nz=6, R=8, field_seed=q).replace(snap=q) for q in range(2)]
     kd = ws[0].kd
     ws = [x.replace(kd=kd) for x in ws]
-    say("graph capture and replays")
+    if variant == "multigrid_reflecting":
+        ws = [x.replace(mg_levels=2, mg_steps=2, eps_walls=(0.4, 0.8)) for x in ws]
+    elif variant == "closed_box":
+        ws = [x.replace(closed=True, T_walls_x=(400.0, 700.0), eps_walls_x=(1.0, 0.5), T_walls_z=(500.0, 800.0),
+                        eps_walls_z=(0.3, 1.0)) for x in ws]
+    say(f"graph capture and replays ({variant})")
     dev = torch.device("cuda", 0)
     solvers = [_solver(x, device_fields=True) for x in ws]
     outs = [torch.zeros(x.ncells, dtype=torch.float64, device=dev) for x in ws]

@@ -165,3 +165,20 @@ def test_reflecting_walls_segmented_long_rays(after, eps, levels):
     say(f"oracle steps max {ref['steps'].max()} mean {ref['steps'].mean():.1f}; long steps {st['long_steps']}")
     assert st["long_steps"] > 0
     _check_fp32_rays(w, cells, Y, S, ref)
+
+
+def test_batch_with_walls_and_multigrid_equals_single_snapshots():
+    """Snapshots with different wall settings and grid counts in one batch: each equals its own
+    single-snapshot compute (per-snapshot wall emissivities, box flags and level tables)."""
+    base = _small_channel(march="f32", nx=12, ny=8, nz=8, R=8)
+    kd = base.kd
+    ws = [base.replace(snap=0, eps_walls=(0.5, 1.0)),
+          _box(base).replace(snap=1, kd=kd),
+          base.replace(snap=2, mg_levels=2, mg_steps=3, eps_walls=(0.2, 0.2))]
+    say("batch with walls and multigrid")
+    singles = [_solver(x).compute()[0] for x in ws]
+    solvers = [_solver(x) for x in ws]
+    outs = [np.zeros(x.ncells) for x in ws]
+    rmc.compute_batch(solvers, outs)
+    for a, b in zip(singles, outs):
+        assert np.array_equal(a, b)
