@@ -2012,7 +2012,9 @@ rmc_status enqueue_snapshot(rmc_ctx *c, const SnapDesc &D, const double *dfaces,
         HIPCHK(hipGetLastError());
     }
     const uint64_t ncpad = ncpad_of(c);
-    dim3 grid((unsigned)((ncpad + 255) / 256), (unsigned)std::min(c->nb, 65535));
+    // up to 16 bands per block row: each block reuses its cells' T, x and table positions for
+    // nb / 16 bands (measured best between one band per block and four rows)
+    dim3 grid((unsigned)((ncpad + 255) / 256), (unsigned)std::min(c->nb, 16));
     hipLaunchKernelGGL(k_fields<Real>, grid, dim3(256), 0, s, c->T.as<double>(), c->X.as<double>(), c->ns, nc,
                        c->k64.as<double>(), c->Ib.as<double>(), c->nb, c->ng, c->nT, c->T0, c->dT, D,
                        c->field.as<Real>(), c->Iplane.as<double>(), ncpad);
@@ -2032,7 +2034,7 @@ rmc_status enqueue_snapshot(rmc_ctx *c, const SnapDesc &D, const double *dfaces,
         Dl.nx = px >> 1; Dl.ny = py >> 1; Dl.nz = pz >> 1;
         Dl.nbx = round_up(Dl.nx, 4) / 4; Dl.nby = round_up(Dl.ny, 4) / 4; Dl.nbz = round_up(Dl.nz, 4) / 4;
         Dl.ncpad = ncpad_level(c, L);
-        dim3 lgrid((unsigned)((Dl.ncpad + 255) / 256), (unsigned)std::min(c->nb, 65535));
+        dim3 lgrid((unsigned)((Dl.ncpad + 255) / 256), (unsigned)std::min(c->nb, 16));
         hipLaunchKernelGGL(k_fields<Real>, lgrid, dim3(256), 0, s, Tc, Xc, c->ns, ncc, c->k64.as<double>(),
                            c->Ib.as<double>(), c->nb, c->ng, c->nT, c->T0, c->dT, Dl,
                            c->mgfield.as<Real>() + D.lev_off[L], c->mgI.as<double>() + D.lev_off[L], D.mg_stride);
