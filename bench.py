@@ -43,6 +43,8 @@ def parse():
                          "kernel continues it (0: library default)")
     ap.add_argument("--xcd-span", type=int, default=0,
                     help="consecutive 64-ray chunks each XCD takes in turn (0: library default)")
+    ap.add_argument("--alloc-tile", type=int, default=0,
+                    help="cells per allocation tile (0: library default, about 1024 tiles)")
     ap.add_argument("--length-sort", action="store_true",
                     help="reorder each march workgroup's rays by expected length")
     ap.add_argument("--bucket-order", type=int, default=0, help="0: longest rays first, 1: band-major")
@@ -315,10 +317,8 @@ def batch12_bench(a):
         s.set_workload(w, device_fields=True)
         solvers.append(s)
     t0 = time.perf_counter()
-    choice = solvers[9].autotune(reps=2)
+    choice = rmc.autotune_batch(solvers, reps=1)
     t_tune = time.perf_counter() - t0
-    for s, w in zip(solvers, ws):
-        s.set_workload(w, device_fields=True, xcd_span=choice["xcd_span"], length_sort=choice["length_sort"])
     outs = [torch.zeros(w.ncells, dtype=torch.float64, device=dev) for w in ws]
     for _ in range(2):
         rmc.compute_batch(solvers, outs)
@@ -393,7 +393,7 @@ def main():
     overrides = {k: v for k, v in (("long_ray_steps", a.long_ray_steps), ("xcd_span", a.xcd_span),
                                    ("length_sort", int(a.length_sort)),
                                    ("bucket_order", a.bucket_order), ("mg_levels", a.mg_levels),
-                                   ("mg_steps", a.mg_steps)) if v}
+                                   ("mg_steps", a.mg_steps), ("alloc_tile", a.alloc_tile)) if v}
     mg = a.mg_levels not in (0, 1)
     s.set_workload(w, **overrides)
     T = torch.from_numpy(np.ascontiguousarray(w.T, dtype=np.float32)).to(dev)

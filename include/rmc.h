@@ -103,7 +103,11 @@ typedef struct {
     int32_t mg_steps;        /* multigrid: steps a ray takes on each grid before it continues on
                                 the next coarser one (the source cell's step counts on the DNS
                                 grid); the last grid runs to depletion.  0 = default 5 */
-    int32_t reserved[1];     /* must be zero */
+    int32_t alloc_tile;      /* cells per allocation tile, the unit in which rays are counted into
+                                and scattered to their buckets: a multiple of 64 in [256, 65536];
+                                0 (default) = about 1024 tiles over the pass (256 to 8192 cells).
+                                Larger tiles mean fewer per-tile histograms; results are the same
+                                either way */
 } rmc_options;
 
 typedef struct {
@@ -192,17 +196,29 @@ rmc_status rmc_set_species(rmc_ctx *ctx, int ns, const void *X, rmc_dtype dtype,
  * (R = 16, seed 0, tol 1e-6, max_steps 65536, F32 march, F64 sums, plain sampling). */
 void rmc_default_options(rmc_options *opt);
 rmc_status rmc_set_options(rmc_ctx *ctx, const rmc_options *opt);
+/* The context's current options (as set, or as the autotuner left them) into *opt. */
+rmc_status rmc_get_options(const rmc_ctx *ctx, rmc_options *opt);
 
 /* Autotuner of the launch schedule, an addition to the paper's method (its kernels run with
  * fixed launch shapes, Sec. 3): times `reps` computes of the context's current workload on
- * `stream` (HIP events, after one warm-up each) for every combination of xcd_span in
- * {16, 64, 256, 1024} and length_sort in {0, 1}, and keeps the fastest in the context's
- * options (out, nullable, receives them).  Only knobs that reorder work are tuned: results
- * are bitwise the same for every candidate.  Needs grid, walls, tables, fields and options
- * set.  cache_path (nullable): a text file of "signature : xcd_span length_sort" lines; a
- * line for this workload and device skips the timing, otherwise the result is appended.
+ * `stream` (HIP events, after one warm-up each), first for every combination of xcd_span in
+ * {16, 64, 256, 1024} and length_sort in {0, 1} at the automatic tile size, then for
+ * alloc_tile at half and twice the automatic size (kept within [256, 16384]) with the best
+ * of those, and keeps the fastest in the context's options (out, nullable, receives them).
+ * Only knobs that reorder work are tuned: results are bitwise the same for every candidate.
+ * Needs grid, walls, tables, fields and options set.  cache_path (nullable): a text file of
+ * "signature : xcd_span length_sort alloc_tile" lines; a line for this workload and device
+ * skips the timing, otherwise the result is appended.
  * Resets the statistics (rmc_reset_stats) after timing.  Synchronises the stream. */
 rmc_status rmc_autotune(rmc_ctx *ctx, int reps, const char *cache_path, rmc_options *out, void *stream);
+
+/* rmc_autotune for a batch (the contexts rmc_compute_batch accepts): times rmc_compute_batch
+ * over all of them for the same candidates, the automatic tile size taken over the whole
+ * pass, and writes the chosen xcd_span, length_sort and alloc_tile into every context's
+ * options (the other fields, snapshot ids included, stay).  The signature of a cache line
+ * lists every grid of the batch.  out (nullable) receives the first context's options. */
+rmc_status rmc_autotune_batch(rmc_ctx *const *ctxs, int nsnap, int reps, const char *cache_path,
+                              rmc_options *out, void *stream);
 
 /* Measurement aid (the roofline of the march, not part of the method): the march's memory
  * access alone.  Every lane of ncells x R walks a straight ray of `steps` unit cells (x and z

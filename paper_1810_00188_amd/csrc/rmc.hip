@@ -1600,6 +1600,12 @@ uint64_t ncpad_of(const rmc_ctx *c)
     return (uint64_t)round_up(c->nx, 4) * round_up(c->ny, 4) * round_up(c->nz, 4);
 }
 
+// Default allocation tile: about 1024 tiles over the pass, whole bricks, 256 to 8192 cells.
+int auto_tile_cells(uint64_t total_ncpad)
+{
+    return (int)std::min<uint64_t>(8192, std::max<uint64_t>(256, (total_ncpad / 1024 + 63) / 64 * 64));
+}
+
 // Temperature and emissivity of wall w (x0, x1, y0, y1, z0, z1); in a periodic box the x and z
 // entries repeat the y0 wall (never hit, but kept inside the table range).
 double wall_T(const rmc_ctx *c, int w)
@@ -1654,8 +1660,8 @@ rmc_status check_options(const rmc_options *o)
     if (o->mg_levels < -1 || o->mg_levels > kMaxLev)
         return fail(RMC_INVALID_ARG, "mg_levels must be -1 (all the grid allows), 0, 1 or up to %d", kMaxLev);
     if (o->mg_steps < 0 || o->mg_steps > (1 << 24)) return fail(RMC_INVALID_ARG, "mg_steps must be in [0, 2^24]");
-    for (int q = 0; q < 1; ++q)
-        if (o->reserved[q] != 0) return fail(RMC_INVALID_ARG, "reserved option fields must be zero");
+    if (o->alloc_tile != 0 && (o->alloc_tile < 256 || o->alloc_tile > 65536 || o->alloc_tile % 64))
+        return fail(RMC_INVALID_ARG, "alloc_tile must be 0 or a multiple of 64 in [256, 65536]");
     return RMC_OK;
 }
 
@@ -2113,8 +2119,8 @@ template <class Real> rmc_status plan_pipeline(rmc_ctx *const *ctxs, int nsnap, 
     P.nfaces = (int)faces.size();
     if ((size_t)P.nfaces * sizeof(double) > 48 * 1024)
         return fail(RMC_UNSUPPORTED, "face tables of all snapshots exceed 48 KiB of LDS");
-    // tiles: about 1024 in total, whole bricks
-    P.tile_cells = (int)std::min<uint64_t>(8192, std::max<uint64_t>(256, (total_ncpad / 1024 + 63) / 64 * 64));
+    // tiles: whole bricks; about 1024 in total unless the options fix the size
+    P.tile_cells = O.alloc_tile > 0 ? O.alloc_tile : auto_tile_cells(total_ncpad);
     std::vector<int> &tile_snap = L->h_tile_snap;
     tile_snap.clear();
     for (int q = 0; q < nsnap; ++q) {
@@ -2128,6 +2134,8 @@ template <class Real> rmc_status plan_pipeline(rmc_ctx *const *ctxs, int nsnap, 
     const uint64_t max_items = (P.total_cells * R + (uint64_t)nbucket * 63 + 63) / 64 * 64;
     P.max_chunks = max_items / 64;
     if (max_items >= (1ull << 32)) return fail(RMC_UNSUPPORTED, "more than 2^32 rays in one pass");
+    if ((uint64_t)nbucket * P.ntiles > (1ull << 30))
+        return fail(RMC_UNSUPPORTED, "per-tile bucket histograms above 2^30 counters: choose a larger alloc_tile");
     if ((st = L->hist.ensure(sizeof(uint32_t) * (uint64_t)nbucket * P.ntiles)) ||
         (st = L->bucket_total.ensure(sizeof(uint32_t) * nbucket)) ||
         (st = L->bucket_start.ensure(sizeof(uint32_t) * (nbucket + 1))) ||
@@ -2707,37 +2715,53 @@ rmc_status rmc_set_options(rmc_ctx *c, const rmc_options *o)
     return RMC_OK;
 }
 
+rmc_status rmc_get_options(const rmc_ctx *c, rmc_options *o)
+{
+    g_err.clear();
+    if (rmc_status st = check_ctx(c)) return st;
+    if (!o) return fail(RMC_INVALID_ARG, "null options");
+    *o = c->opt;
+    return RMC_OK;
+}
+
 }  // extern "C"
 
 namespace {
 
 // Workload signature of an autotuning cache line: the device architecture and everything that
-// sets the amount and the shape of the work.
-std::string tune_signature(const rmc_ctx *c)
+// sets the amount and the shape of the work (every grid of a batch).
+std::string tune_signature(rmc_ctx *const *ctxs, int nsnap)
 {
+    const rmc_ctx *c = ctxs[0];
     hipDeviceProp_t prop;
     std::string arch = "unknown";
     if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) arch = prop.gcnArchName;
     for (char &ch : arch)
         if (ch == ' ' || ch == ':') ch = '_';
     char buf[256];
-    snprintf(buf, sizeof buf, "rmc-tune-1 %s %d %d %d %d %d %d %d %d %d %d %d %d %d", arch.c_str(), c->nx, c->ny, c->nz,
-             c->nb, c->ng, c->ns, c->opt.rays_per_cell, (int)c->opt.march, (int)c->opt.sampling, c->opt.long_ray_steps,
-             c->opt.max_steps, c->opt.mg_levels, c->opt.mg_steps);
-    return buf;
+    snprintf(buf, sizeof buf, "rmc-tune-2 %s %d %d %d %d %d %d %d %d %d %d %d", arch.c_str(), c->nb, c->ng, c->ns,
+             c->opt.rays_per_cell, (int)c->opt.march, (int)c->opt.sampling, c->opt.long_ray_steps, c->opt.max_steps,
+             c->opt.mg_levels, c->opt.mg_steps, nsnap);
+    std::string sig = buf;
+    for (int q = 0; q < nsnap; ++q) {
+        snprintf(buf, sizeof buf, " %dx%dx%d", ctxs[q]->nx, ctxs[q]->ny, ctxs[q]->nz);
+        sig += buf;
+    }
+    return sig;
 }
 
-bool tune_cache_lookup(const char *path, const std::string &sig, int &span, int &sort)
+bool tune_cache_lookup(const char *path, const std::string &sig, int &span, int &sort, int &tile)
 {
     FILE *f = fopen(path, "r");
     if (!f) return false;
-    char line[512];
+    std::vector<char> line(sig.size() + 256);
     bool hit = false;
-    while (fgets(line, sizeof line, f)) {
-        const char *sep = strstr(line, " : ");
-        if (!sep || (size_t)(sep - line) != sig.size() || strncmp(line, sig.c_str(), sig.size()) != 0) continue;
-        int a = 0, b = 0;
-        if (sscanf(sep + 3, "%d %d", &a, &b) == 2) { span = a; sort = b; hit = true; }   // last line wins
+    while (fgets(line.data(), (int)line.size(), f)) {
+        const char *sep = strstr(line.data(), " : ");
+        if (!sep || (size_t)(sep - line.data()) != sig.size() || strncmp(line.data(), sig.c_str(), sig.size()) != 0)
+            continue;
+        int a = 0, b = 0, t = 0;
+        if (sscanf(sep + 3, "%d %d %d", &a, &b, &t) == 3) { span = a; sort = b; tile = t; hit = true; }   // last line wins
     }
     fclose(f);
     return hit;
@@ -2747,51 +2771,74 @@ bool tune_cache_lookup(const char *path, const std::string &sig, int &span, int 
 
 extern "C" {
 
-rmc_status rmc_autotune(rmc_ctx *c, int reps, const char *cache_path, rmc_options *out, void *stream)
+rmc_status rmc_autotune_batch(rmc_ctx *const *ctxs, int nsnap, int reps, const char *cache_path, rmc_options *out,
+                              void *stream)
 {
     g_err.clear();
-    if (rmc_status st = check_ctx(c)) return st;
+    if (rmc_status st = check_batch(ctxs, nsnap)) return st;
     if (reps < 1 || reps > 100) return fail(RMC_INVALID_ARG, "reps must be in [1, 100]");
+    rmc_ctx *c = ctxs[0];   // the leader's options govern the schedule of a batch
     DeviceGuard g(c->device);
     if (!g.ok) return fail(RMC_DEVICE_ERROR, "hipSetDevice(%d) failed", c->device);
-    const std::string sig = tune_signature(c);
+    const std::string sig = tune_signature(ctxs, nsnap);
     rmc_options best = c->opt;
-    int span = 0, sort = 0;
-    if (cache_path && tune_cache_lookup(cache_path, sig, span, sort)) {
+    int span = 0, sort = 0, tile = 0;
+    if (cache_path && tune_cache_lookup(cache_path, sig, span, sort, tile)) {
         best.xcd_span = span;
         best.length_sort = sort;
+        best.alloc_tile = tile;
         if (rmc_status st = check_options(&best)) return fail(st, "bad autotuning cache entry in %s", cache_path);
     } else {
         hipStream_t s = (hipStream_t)stream;
-        const uint64_t nc = ncells_of(c);
         rmc_status st;
-        if ((st = c->tune_out.ensure(sizeof(double) * 2 * nc))) return st;
-        double *dq = c->tune_out.as<double>(), *se = dq + nc;
+        std::vector<double *> dq(nsnap), se(nsnap);
+        uint64_t total_ncpad = 0;
+        for (int q = 0; q < nsnap; ++q) {
+            const uint64_t nc = ncells_of(ctxs[q]);
+            if ((st = ctxs[q]->tune_out.ensure(sizeof(double) * 2 * nc))) return st;
+            dq[q] = ctxs[q]->tune_out.as<double>();
+            se[q] = dq[q] + nc;
+            total_ncpad += ncpad_of(ctxs[q]);
+        }
         hipEvent_t e0, e1;
         HIPCHK(hipEventCreate(&e0));
         HIPCHK(hipEventCreate(&e1));
         const rmc_options base = c->opt;
-        const int spans[] = {16, 64, 256, 1024};
         float best_ms = 0.0f;
         bool have = false;
+        auto time_candidate = [&](const rmc_options &o) -> rmc_status {
+            c->opt = o;
+            rmc_status r = rmc_compute_batch(ctxs, nsnap, dq.data(), se.data(), RMC_DEVICE, stream);   // warm-up
+            if (r) return r;
+            if (hipEventRecord(e0, s) != hipSuccess) return fail(RMC_DEVICE_ERROR, "hipEventRecord failed");
+            for (int q = 0; q < reps && !r; ++q) r = rmc_compute_batch(ctxs, nsnap, dq.data(), se.data(), RMC_DEVICE, stream);
+            if (r) return r;
+            float ms = 0.0f;
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+                return fail(RMC_DEVICE_ERROR, "timing the autotuning candidates failed");
+            if (!have || ms < best_ms) { best_ms = ms; best = o; have = true; }
+            return RMC_OK;
+        };
+        // stage 1: chunk order and length sort at the automatic tile size
+        const int spans[] = {16, 64, 256, 1024};
         for (int srt = 0; srt < 2 && !st; ++srt)
             for (int sp : spans) {
                 rmc_options o = base;
                 o.xcd_span = sp;
                 o.length_sort = srt;
-                c->opt = o;
-                if ((st = rmc_compute_divergence(c, dq, se, RMC_DEVICE, stream))) break;   // warm-up
-                if (hipEventRecord(e0, s) != hipSuccess) { st = fail(RMC_DEVICE_ERROR, "hipEventRecord failed"); break; }
-                for (int q = 0; q < reps && !st; ++q) st = rmc_compute_divergence(c, dq, se, RMC_DEVICE, stream);
-                if (st) break;
-                float ms = 0.0f;
-                if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                    hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-                    st = fail(RMC_DEVICE_ERROR, "timing the autotuning candidates failed");
-                    break;
-                }
-                if (!have || ms < best_ms) { best_ms = ms; best = o; have = true; }
+                o.alloc_tile = 0;
+                if ((st = time_candidate(o))) break;
             }
+        // stage 2: the tile size at the best schedule of stage 1
+        const int t0 = auto_tile_cells(total_ncpad);
+        for (int t : {t0 / 2 / 64 * 64, 2 * t0}) {
+            if (st) break;
+            if (t < 256 || t > 16384) continue;
+            rmc_options o = best;
+            o.alloc_tile = t;
+            st = time_candidate(o);
+        }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         c->opt = base;
@@ -2799,15 +2846,29 @@ rmc_status rmc_autotune(rmc_ctx *c, int reps, const char *cache_path, rmc_option
         if (cache_path) {
             FILE *f = fopen(cache_path, "a");
             if (!f) return fail(RMC_INVALID_ARG, "cannot append to the autotuning cache %s", cache_path);
-            fprintf(f, "%s : %d %d\n", sig.c_str(), best.xcd_span, best.length_sort);
+            fprintf(f, "%s : %d %d %d\n", sig.c_str(), best.xcd_span, best.length_sort, best.alloc_tile);
             fclose(f);
         }
-        if ((st = rmc_reset_stats(c))) return st;
+        for (int q = 0; q < nsnap; ++q)
+            if ((st = rmc_reset_stats(ctxs[q]))) return st;
     }
-    c->opt = best;
-    ++c->config_version;
-    if (out) *out = best;
+    for (int q = 0; q < nsnap; ++q) {   // schedule knobs only: snapshot ids stay per context
+        rmc_options &o = ctxs[q]->opt;
+        o.xcd_span = best.xcd_span;
+        o.length_sort = best.length_sort;
+        o.alloc_tile = best.alloc_tile;
+        ++ctxs[q]->config_version;
+    }
+    if (out) *out = c->opt;
     return RMC_OK;
+}
+
+rmc_status rmc_autotune(rmc_ctx *c, int reps, const char *cache_path, rmc_options *out, void *stream)
+{
+    g_err.clear();
+    if (rmc_status st = check_ctx(c)) return st;
+    rmc_ctx *cs[1] = {c};
+    return rmc_autotune_batch(cs, 1, reps, cache_path, out, stream);
 }
 
 rmc_status rmc_set_cell_pdf(rmc_ctx *c, const double *q, rmc_mem mem, void *stream)

@@ -35,7 +35,7 @@ class Options(C.Structure):
                 ("block_threads", C.c_int32), ("long_ray_steps", C.c_int32),
                 ("xcd_span", C.c_int32), ("length_sort", C.c_int32),
                 ("bucket_order", C.c_int32), ("mg_levels", C.c_int32), ("mg_steps", C.c_int32),
-                ("reserved", C.c_int32 * 1)]
+                ("alloc_tile", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -82,6 +82,7 @@ SIGNATURES = {
     "rmc_set_species": (C.c_int, [_VP, C.c_int, _VP, C.c_int, C.c_int, _VP]),
     "rmc_default_options": (None, [C.POINTER(Options)]),
     "rmc_set_options": (C.c_int, [_VP, C.POINTER(Options)]),
+    "rmc_get_options": (C.c_int, [_VP, C.POINTER(Options)]),
     "rmc_set_cell_pdf": (C.c_int, [_VP, _VP, C.c_int, _VP]),
     "rmc_compute_divergence": (C.c_int, [_VP, _VP, _VP, C.c_int, _VP]),
     "rmc_compute_batch": (C.c_int, [C.POINTER(_VP), C.c_int, C.POINTER(_VP), C.POINTER(_VP),
@@ -92,6 +93,7 @@ SIGNATURES = {
     "rmc_get_stats": (C.c_int, [_VP, C.POINTER(Stats)]),
     "rmc_reset_stats": (C.c_int, [_VP]),
     "rmc_autotune": (C.c_int, [_VP, C.c_int, C.c_char_p, C.POINTER(Options), _VP]),
+    "rmc_autotune_batch": (C.c_int, [C.POINTER(_VP), C.c_int, C.c_int, C.c_char_p, C.POINTER(Options), _VP]),
     "rmc_graph_capture": (C.c_int, [C.POINTER(_VP), C.c_int, C.POINTER(_VP), C.POINTER(_VP), _VP,
                                     C.POINTER(_VP)]),
     "rmc_graph_launch": (C.c_int, [_VP, _VP]),
@@ -262,6 +264,12 @@ class Solver:
         self.R = opt.rays_per_cell
         self.opt = opt
 
+    def options(self) -> Options:
+        """rmc_get_options: the options in force (after an autotune, its choice)."""
+        o = Options()
+        _check(LIB.rmc_get_options(self.h, C.byref(o)))
+        return o
+
     def set_cell_pdf(self, q, stream=None):
         p, mem, keep = _buf(q, np.float64)
         self._keep = [keep]
@@ -394,11 +402,11 @@ class Solver:
 
     def autotune(self, reps: int = 3, cache_path: Optional[str] = None, stream=None) -> dict:
         """rmc_autotune: time the schedule candidates on the current workload, keep the
-        fastest; returns the chosen {xcd_span, length_sort}."""
+        fastest; returns the chosen {xcd_span, length_sort, alloc_tile}."""
         o = Options()
         path = cache_path.encode() if cache_path else None
         _check(LIB.rmc_autotune(self.h, int(reps), path, C.byref(o), _stream(stream)))
-        return {"xcd_span": o.xcd_span, "length_sort": o.length_sort}
+        return {"xcd_span": o.xcd_span, "length_sort": o.length_sort, "alloc_tile": o.alloc_tile}
 
 
 def train_batch(feat, mask, pplain, cell_of, stratum, h, p0, ray_cost=None):
@@ -444,6 +452,18 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+def autotune_batch(solvers: Sequence[Solver], reps: int = 3, cache_path: Optional[str] = None,
+                   stream=None) -> dict:
+    """rmc_autotune_batch: time the schedule candidates on one batched pass over the solvers'
+    snapshots and set the fastest on all of them; returns {xcd_span, length_sort, alloc_tile}."""
+    n = len(solvers)
+    hs = (C.c_void_p * n)(*[s.h.value for s in solvers])
+    o = Options()
+    path = cache_path.encode() if cache_path else None
+    _check(LIB.rmc_autotune_batch(hs, n, int(reps), path, C.byref(o), _stream(stream)))
+    return {"xcd_span": o.xcd_span, "length_sort": o.length_sort, "alloc_tile": o.alloc_tile}
 
 
 def compute_batch(solvers: Sequence[Solver], divq: Sequence, stderr: Optional[Sequence] = None,

@@ -163,14 +163,14 @@ def test_rerun_is_bitwise_identical():
 
 
 def test_launch_order_does_not_change_results():
-    """The XCD-aware chunk order (and the plain order it reduces to) and the sort of each
-    bucket's rays by expected length only reschedule rays: ray values, step counts and cell
-    estimates are bitwise the same."""
+    """The XCD-aware chunk order (and the plain order it reduces to), the sort of each
+    bucket's rays by expected length and the allocation tile size only reschedule rays: ray
+    values, step counts and cell estimates are bitwise the same."""
     w = _small_channel(march="f32", nx=24, ny=16, nz=20, R=16)
     say(f"xcd spans {w.name}")
     out = []
-    for span, lsort, border in ((4, 0, 0), (4, 1, 0), (16, 1, 1), (1024, 0, 1)):
-        s = _solver(w, xcd_span=span, length_sort=lsort, bucket_order=border)
+    for span, lsort, border, tile in ((4, 0, 0, 0), (4, 1, 0, 512), (16, 1, 1, 320), (1024, 0, 1, 65536)):
+        s = _solver(w, xcd_span=span, length_sort=lsort, bucket_order=border, alloc_tile=tile)
         dq, se = s.compute()
         Y, S = s.ray_values(np.arange(w.ncells))
         out.append((dq, se, Y, S))
@@ -189,10 +189,11 @@ def test_autotune_keeps_results_and_caches(tmp_path):
     cache = str(tmp_path / "tune.txt")
     got = s.autotune(reps=1, cache_path=cache)
     assert got["xcd_span"] in (16, 64, 256, 1024) and got["length_sort"] in (0, 1)
+    assert got["alloc_tile"] in (0, 512)          # 3840 padded cells: automatic tile 256
     after, _ = s.compute()
     assert np.array_equal(before, after)
     lines = open(cache).read().splitlines()
-    assert len(lines) == 1 and lines[0].endswith(f": {got['xcd_span']} {got['length_sort']}")
+    assert len(lines) == 1 and lines[0].endswith(f": {got['xcd_span']} {got['length_sort']} {got['alloc_tile']}")
     s2 = _solver(w)
     assert s2.autotune(reps=1, cache_path=cache) == got          # a cache hit: no new line
     assert len(open(cache).read().splitlines()) == 1
@@ -267,7 +268,8 @@ def test_errors_are_reported_not_fatal():
         s.set_species(X)
     assert e.value.status == rmc.RMC_OUT_OF_RANGE
     for bad in (dict(rays_per_cell=0), dict(xcd_span=2), dict(xcd_span=48), dict(long_ray_steps=-1),
-                dict(length_sort=2), dict(mg_levels=-2), dict(mg_levels=9), dict(mg_steps=-1)):
+                dict(length_sort=2), dict(mg_levels=-2), dict(mg_levels=9), dict(mg_steps=-1),
+                dict(alloc_tile=192), dict(alloc_tile=300), dict(alloc_tile=65600)):
         with pytest.raises(rmc.RmcError) as e:
             s.set_options(rmc.default_options(**bad))
         assert e.value.status == rmc.RMC_INVALID_ARG, bad
@@ -313,6 +315,33 @@ def test_batch_equals_single_snapshots():
     rmc.compute_batch(solvers, outs)
     for a, b in zip(singles, outs):
         assert np.array_equal(a, b)
+
+
+def test_batch_autotune_keeps_results_and_sets_every_context(tmp_path):
+    """The batch autotuner times batched passes, writes one cache line naming every grid, and
+    sets the chosen schedule on every context; the batched estimate is bitwise unchanged."""
+    ws = [_small_channel(march="f32", nx=12 + 4 * q, ny=8, nz=6 + 2 * q, R=8, field_seed=q)
+          .replace(snap=q) for q in range(3)]
+    kd = ws[0].kd
+    ws = [x.replace(kd=kd) for x in ws]
+    say("batch autotune of 3")
+    solvers = [_solver(x) for x in ws]
+    before = [np.zeros(x.ncells) for x in ws]
+    rmc.compute_batch(solvers, before)
+    cache = str(tmp_path / "tune.txt")
+    got = rmc.autotune_batch(solvers, reps=1, cache_path=cache)
+    for s in solvers:
+        o = s.options()
+        assert (o.xcd_span, o.length_sort, o.alloc_tile) == (got["xcd_span"], got["length_sort"], got["alloc_tile"])
+    assert [s.options().snapshot for s in solvers] == [0, 1, 2]
+    after = [np.zeros(x.ncells) for x in ws]
+    rmc.compute_batch(solvers, after)
+    for a, b in zip(before, after):
+        assert np.array_equal(a, b)
+    lines = open(cache).read().splitlines()
+    assert len(lines) == 1 and " 12x8x6 16x8x8 20x8x10 : " in lines[0]
+    assert rmc.autotune_batch(solvers, reps=1, cache_path=cache) == got
+    assert len(open(cache).read().splitlines()) == 1
 
 
 # ------------------------------------------------------------------------- HIP graphs
