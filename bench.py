@@ -459,6 +459,7 @@ def main():
         "phases_ms": {"prep": st["sum_ms_prep"] / a.steps, "alloc": st["sum_ms_alloc"] / a.steps,
                       "march": march_ms, "reduce": st["sum_ms_reduce"] / a.steps},
         "march_steps_per_s": st["steps"] / (march_ms * 1e-3),
+        "march_steps_split": {"lane": lane_steps, "long": st["long_steps"]},
         "roofline": {"kernel": "k_march_mg" if mg else "k_march_lane", "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "ms_per_launch": lane_ms,

@@ -51,6 +51,8 @@ struct SnapDesc {
     const double *ccdf_o;       // [ncells][nb*ng*8]
     const uint32_t *dstrat;     // learned sampling: [ncells * R] drawn stratum (n*ng + g)*8 + o
     double *dprob;              // per-cell pdf or learned sampling: [ncells * R] probability of each ray
+    uint32_t *rbkt;             // [ncells * R] bucket (n*ng + g)*8 + o of each ray: written by the
+                                // counting pass (learned sampling: the drawn strata themselves)
     uint64_t ncpad;             // cells per bricked field plane
     int nx, ny, nz;
     int nbx, nby, nbz;
@@ -82,6 +84,8 @@ struct AllocArgs {
     uint32_t *hist;             // [nbucket][ntiles]
     const uint32_t *bucket_start;
     uint4 *items;               // (i | j<<10 | k<<20, r | k_ord<<8 | snapshot<<16, dir word 0, dir word 1)
+    int lds_bricks;             // the tile's bricks are decoded into LDS (else per cell from the index)
+    int lds_cdf;                // plain sampling: the cdfs are staged in LDS by the counting pass
 };
 
 struct Draw {
@@ -93,7 +97,8 @@ struct Draw {
 // allocation (draws made per cell by k_alloc_draw, read back here).
 template <int SM>
 __device__ __forceinline__ Draw draw_ray(const SnapDesc &D, int nb, int ng, uint32_t c, uint32_t r,
-                                         uint32_t k0, uint32_t k1, int R)
+                                         uint32_t k0, uint32_t k1, int R, const double *cdf_b = nullptr,
+                                         const double *cdf_g = nullptr)
 {
     if constexpr (SM == 2) {
         const size_t slot = (size_t)c * R + r;
@@ -110,8 +115,8 @@ __device__ __forceinline__ Draw draw_ray(const SnapDesc &D, int nb, int ng, uint
     const double u0 = unif_alloc(w[0]), u1 = unif_alloc(w[1]), u2 = unif_alloc(w[2]);
     Draw d;
     if constexpr (SM == 0) {
-        d.n = cdf_search(D.cdf_b, nb, u0);
-        d.g = cdf_search(D.cdf_g + (size_t)d.n * ng, ng, u1);
+        d.n = cdf_search(cdf_b ? cdf_b : D.cdf_b, nb, u0);   // the caller may pass copies staged in LDS
+        d.g = cdf_search((cdf_g ? cdf_g : D.cdf_g) + (size_t)d.n * ng, ng, u1);
         d.o = (int)floor(8.0 * u2);
         d.p = D.p[d.n * ng + d.g] / 8.0;
     } else {
@@ -447,23 +452,79 @@ __global__ void __launch_bounds__(256) k_coarsen(const double *__restrict__ T, c
 // of each cell in one pass of the block (cells_per_pass = blockDim / R).
 constexpr int kAllocThreads = 1024;   // threads per tile: R rays of 1024 / R cells per pass
 
+// The bricks of a tile (tile_cells is a multiple of 64: whole bricks), decoded once into LDS as
+// bi | bj << 10 | bk << 20, or ~0 past the last brick of the snapshot.
+__device__ __forceinline__ void tile_bricks(const SnapDesc &D, uint64_t first, int tile_cells, uint32_t *bt)
+{
+    const uint32_t nbt = (uint32_t)tile_cells >> 6, b0 = (uint32_t)(first >> 6);
+    const uint32_t nbricks = (uint32_t)(D.ncpad >> 6);
+    for (uint32_t q = threadIdx.x; q < nbt; q += blockDim.x) {
+        const uint32_t b = b0 + q;
+        uint32_t v = 0xFFFFFFFFu;
+        if (b < nbricks) {
+            const uint32_t bk = b % (uint32_t)D.nbz, t = b / (uint32_t)D.nbz;
+            v = (t / (uint32_t)D.nby) | ((t % (uint32_t)D.nby) << 10) | (bk << 20);
+        }
+        bt[q] = v;
+    }
+}
+
+// Cell (i, j, k) at position p of the tile (the same order as brick_cell); false outside the grid.
+__device__ __forceinline__ bool tile_cell(const SnapDesc &D, const uint32_t *bt, int p, int &i, int &j, int &k)
+{
+    const uint32_t v = bt[p >> 6];
+    const int w = p & 63;
+    i = (int)(v & 1023u) * 4 + ((w >> 2) & 1) + (((w >> 5) & 1) << 1);
+    j = (int)((v >> 10) & 1023u) * 4 + ((w >> 1) & 1) + (((w >> 4) & 1) << 1);
+    k = (int)(v >> 20) * 4 + (w & 1) + (((w >> 3) & 1) << 1);
+    return v != 0xFFFFFFFFu && i < D.nx && j < D.ny && k < D.nz;
+}
+
+// LDS of k_alloc_count: the plain cdfs (nb + nb*ng doubles, if staged), then nbucket counters,
+// then the tile's bricks (if decoded there).
+inline size_t alloc_count_lds(bool cdf, bool bricks, int nb, int ng, int nbucket, int tile_cells)
+{
+    return sizeof(double) * (cdf ? nb + nb * ng : 0) + sizeof(uint32_t) * (nbucket + (bricks ? tile_cells / 64 : 0));
+}
+
+// Cell at position p of the tile, from the decoded bricks or from the brick-linear index.
+__device__ __forceinline__ bool alloc_cell(const SnapDesc &D, const uint32_t *bt, uint64_t first, int p, int &i,
+                                           int &j, int &k)
+{
+    return bt ? tile_cell(D, bt, p, i, j, k) : brick_cell(D, first + p, i, j, k);
+}
+
 template <int SM>
 __global__ void __launch_bounds__(kAllocThreads) k_alloc_count(AllocArgs A)
 {
-    extern __shared__ uint32_t lh[];   // [nbucket]
+    extern __shared__ double lds_d[];
+    const bool cdf = SM == 0 && A.lds_cdf;
+    const int ncdf = cdf ? A.nb + A.nb * A.ng : 0;
+    uint32_t *lh = reinterpret_cast<uint32_t *>(lds_d + ncdf);   // [nbucket]
+    uint32_t *bt = A.lds_bricks ? lh + A.nbucket : nullptr;        // [tile_cells / 64]
     const int tile = blockIdx.x;
-    for (int b = threadIdx.x; b < A.nbucket; b += blockDim.x) lh[b] = 0;
-    __syncthreads();
     const SnapDesc &D = A.snaps[A.tile_snap[tile]];
     const uint64_t first = (uint64_t)(tile - D.tile_begin) * A.tile_cells;
+    for (int b = threadIdx.x; b < A.nbucket; b += blockDim.x) lh[b] = 0;
+    if (cdf) {
+        for (int q = threadIdx.x; q < A.nb; q += blockDim.x) lds_d[q] = D.cdf_b[q];
+        for (int q = threadIdx.x; q < A.nb * A.ng; q += blockDim.x) lds_d[A.nb + q] = D.cdf_g[q];
+    }
+    if (bt) tile_bricks(D, first, A.tile_cells, bt);
+    __syncthreads();
     const int cpp = blockDim.x / A.R;
     const int cq = threadIdx.x / A.R, r = threadIdx.x - cq * A.R;
     for (int base = 0; base < A.tile_cells; base += cpp) {
         int i, j, k;
-        if (cq < cpp && base + cq < A.tile_cells && brick_cell(D, first + base + cq, i, j, k)) {
+        if (cq < cpp && base + cq < A.tile_cells && alloc_cell(D, bt, first, base + cq, i, j, k)) {
             const uint32_t c = (uint32_t)(((uint64_t)i * D.ny + j) * D.nz + k);
-            const Draw d = draw_ray<SM>(D, A.nb, A.ng, c, (uint32_t)r, A.k0, A.k1, A.R);
-            atomicAdd(&lh[(d.n * A.ng + d.g) * 8 + d.o], 1u);
+            const Draw d = draw_ray<SM>(D, A.nb, A.ng, c, (uint32_t)r, A.k0, A.k1, A.R, cdf ? lds_d : nullptr,
+                                        cdf ? lds_d + A.nb : nullptr);
+            const uint32_t bucket = (uint32_t)((d.n * A.ng + d.g) * 8 + d.o);
+            atomicAdd(&lh[bucket], 1u);
+            const size_t slot = (size_t)c * A.R + r;
+            if constexpr (SM != 2) D.rbkt[slot] = bucket;   // learned sampling: rbkt already holds it
+            if constexpr (SM == 1) D.dprob[slot] = d.p;      // the march's weight
         }
     }
     __syncthreads();
@@ -535,35 +596,60 @@ __global__ void k_chunk_map(const uint32_t *total, const uint32_t *start, int nb
     for (uint32_t q = used + threadIdx.x; q < e; q += blockDim.x) items[q] = make_uint4(0u, kInvalidItem, 0u, 0u);
 }
 
+// LDS of k_alloc_scatter: nbucket positions, the bucket of each thread, the tile's bricks (if
+// decoded there).
+inline size_t alloc_scatter_lds(bool bricks, int nbucket, int threads, int tile_cells)
+{
+    return sizeof(uint32_t) * (nbucket + threads + (bricks ? tile_cells / 64 : 0));
+}
+
+// Rank of a ray among the earlier rays of its cell drawn into the same bucket: threads s0 ..
+// s0 + r - 1 hold those rays' buckets in sb.  Four at a time when s0 is a multiple of 4.
+__device__ __forceinline__ uint32_t same_bucket_before(const uint32_t *sb, int s0, int r, uint32_t bucket,
+                                                       bool by4)
+{
+    uint32_t kord = 0;
+    int q = 0;
+    if (by4) {
+        const uint4 *sb4 = reinterpret_cast<const uint4 *>(sb + s0);
+        for (; q + 4 <= r; q += 4) {
+            const uint4 v = sb4[q >> 2];
+            kord += (v.x == bucket ? 1u : 0u) + (v.y == bucket ? 1u : 0u) + (v.z == bucket ? 1u : 0u) +
+                    (v.w == bucket ? 1u : 0u);
+        }
+    }
+    for (; q < r; ++q) kord += sb[s0 + q] == bucket ? 1u : 0u;
+    return kord;
+}
+
 template <int SM>
 __global__ void __launch_bounds__(kAllocThreads) k_alloc_scatter(AllocArgs A)
 {
-    extern __shared__ uint32_t lb[];   // [nbucket] next free position, then [blockDim] bucket of each thread
-    uint32_t *sb = lb + A.nbucket;
+    extern __shared__ uint32_t lb[];   // [nbucket] next free position, [blockDim] bucket of each thread, bricks
+    uint32_t *sb = lb + A.nbucket, *bt = A.lds_bricks ? sb + blockDim.x : nullptr;
     const int tile = blockIdx.x;
-    for (int b = threadIdx.x; b < A.nbucket; b += blockDim.x)
-        lb[b] = A.bucket_start[b] + A.hist[(size_t)b * A.ntiles + tile];
-    __syncthreads();
     const int s = A.tile_snap[tile];
     const SnapDesc &D = A.snaps[s];
     const uint64_t first = (uint64_t)(tile - D.tile_begin) * A.tile_cells;
+    for (int b = threadIdx.x; b < A.nbucket; b += blockDim.x)
+        lb[b] = A.bucket_start[b] + A.hist[(size_t)b * A.ntiles + tile];
+    if (bt) tile_bricks(D, first, A.tile_cells, bt);
+    __syncthreads();
     const int cpp = blockDim.x / A.R;
     const int cq = threadIdx.x / A.R, r = threadIdx.x - cq * A.R;
+    const bool by4 = (A.R & 3) == 0 && (A.nbucket & 3) == 0;   // sb + cq * R is 16-byte aligned
     for (int base = 0; base < A.tile_cells; base += cpp) {
         int i = 0, j = 0, k = 0;
-        const bool live = cq < cpp && base + cq < A.tile_cells && brick_cell(D, first + base + cq, i, j, k);
+        const bool live = cq < cpp && base + cq < A.tile_cells && alloc_cell(D, bt, first, base + cq, i, j, k);
         uint32_t bucket = 0xFFFFFFFFu, c = 0;
         if (live) {
             c = (uint32_t)(((uint64_t)i * D.ny + j) * D.nz + k);
-            const Draw d = draw_ray<SM>(D, A.nb, A.ng, c, (uint32_t)r, A.k0, A.k1, A.R);
-            bucket = (uint32_t)((d.n * A.ng + d.g) * 8 + d.o);
-            if constexpr (SM == 1) D.dprob[(size_t)c * A.R + r] = d.p;   // the march's weight
+            bucket = D.rbkt[(size_t)c * A.R + r];   // drawn by the counting pass
         }
         sb[threadIdx.x] = bucket;
         __syncthreads();
         if (live) {
-            uint32_t kord = 0;
-            for (int q = threadIdx.x - r; q < (int)threadIdx.x; ++q) kord += sb[q] == bucket ? 1u : 0u;
+            const uint32_t kord = same_bucket_before(sb, threadIdx.x - r, r, bucket, by4);
             // direction stream of the ray, keyed by (cell, band, g, octant, ordinal)
             const uint32_t n = (bucket >> 3) / (uint32_t)A.ng, g = (bucket >> 3) - n * (uint32_t)A.ng;
             uint32_t v[4];
@@ -643,6 +729,20 @@ struct ContRec {
     double t, tx, ty, tz;       // current parameter, next-face parameters
     double oy;                  // origin y, mirrored at every reflection
 };
+
+template <class Real, bool INC_XZ>
+__device__ __forceinline__ ContRec cont_rec(uint32_t q, int lev, const Ray<Real, INC_XZ> &R)
+{
+    ContRec rc;
+    rc.q = q;
+    rc.lev = lev;
+    rc.i = R.i; rc.j = R.j; rc.k = R.k; rc.steps = R.steps;
+    rc.sgn = R.sgn;
+    rc.oy = R.oy;
+    rc.tau = R.tau; rc.acc = R.acc;
+    rc.t = R.t; rc.tx = R.tx; rc.ty = R.ty; rc.tz = R.tz;
+    return rc;
+}
 
 __device__ __forceinline__ RayGeo ray_geo(const SnapDesc &D, const double *sf)
 {
@@ -846,15 +946,7 @@ __global__ void __launch_bounds__(256) k_march_lane(MarchArgs<Real> A)
         // long ray: hand its state to k_march_long (or, if the list is full, finish it here)
         const uint32_t idx = atomicAdd(A.cont_count, 1u);
         if (idx < A.cont_cap) {
-            ContRec rc;
-            rc.q = q;
-            rc.lev = 0;
-            rc.i = R.i; rc.j = R.j; rc.k = R.k; rc.steps = R.steps;
-            rc.sgn = R.sgn;
-            rc.oy = R.oy;
-            rc.tau = R.tau; rc.acc = R.acc;
-            rc.t = R.t; rc.tx = R.tx; rc.ty = R.ty; rc.tz = R.tz;
-            A.cont[idx] = rc;
+            A.cont[idx] = cont_rec(q, 0, R);
             return;
         }
         const int cell = R.px + R.py + R.pz;
@@ -911,15 +1003,7 @@ __global__ void __launch_bounds__(256) k_march_mg(MarchArgs<Real> A)
     if (!march_levels(R, D, sf, pair, n, A.nb, A.tol, A.max_steps, kap_src, Isrc, last_cap)) {
         const uint32_t idx = atomicAdd(A.cont_count, 1u);
         if (idx < A.cont_cap) {
-            ContRec rc;
-            rc.q = q;
-            rc.lev = D.nlev - 1;
-            rc.i = R.i; rc.j = R.j; rc.k = R.k; rc.steps = R.steps;
-            rc.sgn = R.sgn;
-            rc.oy = R.oy;
-            rc.tau = R.tau; rc.acc = R.acc;
-            rc.t = R.t; rc.tx = R.tx; rc.ty = R.ty; rc.tz = R.tz;
-            A.cont[idx] = rc;
+            A.cont[idx] = cont_rec(q, D.nlev - 1, R);
             return;
         }
         const RayGeo GL = ray_geo_level(D, sf, D.nlev - 1);
@@ -1559,6 +1643,7 @@ struct rmc_ctx {
     DBuf mgT, mgX, mgfield, mgI;   // multigrid: coarse-level fields and planes
     // slots
     DBuf Y, st;
+    DBuf rbkt;              // bucket of each ray (counting pass -> scatter pass)
     int slots_R = 0, slots_real = 0;
     // shared pipeline workspace (used when this context leads a batch)
     DBuf hist, bucket_total, bucket_start, nchunks, chunk_bucket, items, faces, snaps, tile_snap, counters, red_part,
@@ -1956,6 +2041,10 @@ template <class Real> rmc_status plan_snapshot(rmc_ctx *c, SnapDesc &D)
     if (c->opt.sampling == RMC_SAMPLING_LEARNED) {
         if ((st = plan_learned(c))) return st;
         D.dstrat = c->dstrat.as<uint32_t>();
+        D.rbkt = c->dstrat.as<uint32_t>();   // the drawn strata are the buckets
+    } else {
+        if ((st = c->rbkt.ensure(sizeof(uint32_t) * nc * R))) return st;
+        D.rbkt = c->rbkt.as<uint32_t>();
     }
     D.kap = c->field.p;
     D.Ipl = c->Iplane.as<double>();
@@ -2202,10 +2291,14 @@ rmc_status enqueue_pipeline(const Plan &P, double *const *divq, double *const *s
     AA.hist = L->hist.as<uint32_t>();
     AA.bucket_start = L->bucket_start.as<uint32_t>();
     AA.items = L->items.as<uint4>();
-    const size_t lds_count = sizeof(uint32_t) * nbucket;
-    // 1024 threads per tile unless the bucket counters and the per-thread buckets overflow 64 KiB
-    const int at = sizeof(uint32_t) * (nbucket + kAllocThreads) <= 64 * 1024 ? kAllocThreads : 256;
-    const size_t lds_scatter = sizeof(uint32_t) * (nbucket + at);
+    // 1024 threads per tile unless the bucket counters and the per-thread buckets overflow 64 KiB;
+    // the tile's bricks and the plain cdfs go to LDS where they fit beside them
+    constexpr size_t kLds = 64 * 1024;
+    const int at = sizeof(uint32_t) * (nbucket + kAllocThreads) <= kLds ? kAllocThreads : 256;
+    AA.lds_bricks = alloc_scatter_lds(true, nbucket, at, P.tile_cells) <= kLds ? 1 : 0;
+    AA.lds_cdf = P.smode == 0 && alloc_count_lds(true, AA.lds_bricks, nb, ng, nbucket, P.tile_cells) <= kLds ? 1 : 0;
+    const size_t lds_count = alloc_count_lds(AA.lds_cdf, AA.lds_bricks, nb, ng, nbucket, P.tile_cells);
+    const size_t lds_scatter = alloc_scatter_lds(AA.lds_bricks, nbucket, at, P.tile_cells);
     if (P.smode == 2) hipLaunchKernelGGL(k_alloc_count<2>, dim3(P.ntiles), dim3(at), lds_count, s, AA);
     else if (P.smode == 1) hipLaunchKernelGGL(k_alloc_count<1>, dim3(P.ntiles), dim3(at), lds_count, s, AA);
     else hipLaunchKernelGGL(k_alloc_count<0>, dim3(P.ntiles), dim3(at), lds_count, s, AA);
