@@ -1023,35 +1023,51 @@ __global__ void __launch_bounds__(256) k_march_mg(MarchArgs<Real> A)
     store_slot<Real>(D, slot, w * (double)kap_src * (double)R.acc, (uint32_t)R.steps | ((uint32_t)R.end << 28));
 }
 
-// Long rays (FP32 march, uniform periodic x and z): one wavefront per ray handed over by the
+// Long rays (FP32 march, uniform periodic x and z): one workgroup per ray handed over by the
 // lane kernel.  The path is continued in rounds.  A round covers the parameter range up to
 // tend (the wall, the distance at which even the smallest kappa of the field would bring tau
 // to tol, 1.25 times the distance the optical depth seen so far predicts, and the step cap,
 // whichever is first) and splits it at the crossings of the axis (x or z) the ray advances
-// fastest along into 64 segments, one per lane.  Each lane marches its segment with tau = 1
+// fastest along into 256 segments, one per thread.  Each thread marches its segment with tau = 1
 // (same geometry and absorption as the sequential march); a prefix product of the segment
 // transmissivities gives every segment's incoming tau.  The first segment in which the ray
 // stops (tau <= tol, the wall, or the step cap) is re-marched sequentially with its true
 // incoming tau and step count, and the ray value is
 //   acc = acc_before + sum_{l < l*} tau_in(l) acc_l + acc(l*).
+// Products and sums over the segments run in a fixed order (within each wavefront, then over
+// the four wavefronts), so results do not depend on timing.
 // When no segment stops, the contributions are added and the next round starts where the
 // last segment ended.  Reflecting y walls keep the crossings of x and z evenly spaced: the
 // range is then bounded by the black wall a ray reaches within two wall-to-wall traversals,
 // or by the wall losses added to the smallest kappa, and a segment's start state replays the
 // reflections before it with the sequential march's own arithmetic (mirrored origin, flipped
 // direction), so that every segment starts where the sequential march would be.
-template <bool PDF, bool MULTI>
+constexpr int kLongSeg = 256;   // segments per round: the threads of one workgroup
+
+// State at the end of the last segment of a round, passed on through LDS.
+struct LongTail {
+    double tau, t, tx, ty, tz, oy;
+    int steps, i, j, k, sgn;
+};
+
+template <bool PDF, bool MULTI, bool WG>
 __global__ void __launch_bounds__(256) k_march_long(MarchArgs<float> A)
 {
+    constexpr int NSEG = WG ? kLongSeg : 64;
     extern __shared__ double sf[];
+    __shared__ double s_tau[4], s_acc[4];
+    __shared__ int s_steps[4], s_first[4];
+    __shared__ LongTail s_tail;
     for (int q = threadIdx.x; q < A.nfaces; q += blockDim.x) sf[q] = A.faces[q];
     __syncthreads();
-    const int lane = (int)(threadIdx.x & 63);
+    const int lane = (int)(threadIdx.x & 63), wid = (int)(threadIdx.x >> 6);
+    const int seg = WG ? (int)threadIdx.x : lane;
     const uint32_t nrec = min(__builtin_amdgcn_readfirstlane(*A.cont_count), A.cont_cap);
-    const uint32_t nwaves = gridDim.x * (blockDim.x >> 6);
-    for (uint32_t wv = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) >> 6); wv < nrec;
-         wv += nwaves) {
-        const ContRec rc = A.cont[wv];
+    const uint32_t first = WG ? blockIdx.x
+                              : __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    const uint32_t stride = WG ? gridDim.x : gridDim.x * (blockDim.x >> 6);
+    for (uint32_t rec = first; rec < nrec; rec += stride) {
+        const ContRec rc = A.cont[rec];
         const uint4 it = gld(A.items + rc.q);
         const uint32_t b = gld(A.chunk_bucket + (rc.q >> 6));
         const int s = MULTI ? (int)((it.y >> 16) & 0x7FFF) : 0;
@@ -1101,7 +1117,7 @@ __global__ void __launch_bounds__(256) k_march_long(MarchArgs<float> A)
             if (e0 == 1.0 || e1 == 1.0) tblack = 2.0 * H * fabs(ry0);
             else if (e0 > 0.0 || e1 > 0.0) kwall = -log((1.0 - e0) * (1.0 - e1)) * fabs(dy) / (2.0 * H);
         }
-        // wave-uniform state of the ray at the start of a round
+        // workgroup-uniform state of the ray at the start of a round
         int si = rc.i, sj = rc.j, sk = rc.k, ssteps = rc.steps, ssgn = rc.sgn;
         double st = rc.t, stx = rc.tx, sty = rc.ty, stz = rc.tz, stau = rc.tau, sacc = rc.acc, soy = rc.oy;
         while (true) {
@@ -1117,8 +1133,8 @@ __global__ void __launch_bounds__(256) k_march_long(MarchArgs<float> A)
             const double ta0 = ax ? stx : stz;
             tend = fmin(tend, ta0 + (double)(A.max_steps - ssteps) * dta);   // every crossing is a step
             const long M = ta0 < tend ? (long)floor((tend - ta0) / dta) + 1 : 0;
-            const long B0 = (M * lane) / 64, B1 = (M * (lane + 1)) / 64;
-            const bool empty = lane < 63 && B1 == B0;
+            const long B0 = (M * seg) / NSEG, B1 = (M * (seg + 1)) / NSEG;
+            const bool empty = seg < NSEG - 1 && B1 == B0;
             R.tau = 1.0;
             R.acc = 0.0;
             R.steps = 0;
@@ -1184,8 +1200,8 @@ __global__ void __launch_bounds__(256) k_march_long(MarchArgs<float> A)
             const int start_i = R.i, start_j = R.j, start_k = R.k, start_sgn = R.sgn;
             const double start_t = R.t, start_tx = R.tx, start_ty = R.ty, start_tz = R.tz;
             const double start_oy = R.oy, start_ry = R.ry;
-            // local march of the segment with tau = 1: lanes below 63 end on their last
-            // crossing, lane 63 at tend
+            // local march of the segment with tau = 1: segments but the last end on their last
+            // crossing, the last at tend
             bool wall_end = false;
             if (!empty) {
                 long next = B0;
@@ -1219,44 +1235,80 @@ __global__ void __launch_bounds__(256) k_march_long(MarchArgs<float> A)
                         if (wall_end) break;
                     }
                     if (!(R.tau > (double)A.tol)) break;
-                    if (lane < 63 ? (cross && ++next == B1) : (R.t >= tend)) break;
+                    if (seg < NSEG - 1 ? (cross && ++next == B1) : (R.t >= tend)) break;
                     if (R.steps >= A.max_steps) break;
                     kc = gld(K + cell);
                     Ic = gld(Ipl + cell);
                 }
             }
-            // incoming tau and steps of every segment
-            double pin = R.tau;                // inclusive prefix product over lanes
-            int sin_ = R.steps;                // inclusive prefix sum of steps
+            // incoming tau and steps of every segment: inclusive prefix product and sum within
+            // each wavefront, then (a workgroup per ray) the totals of the wavefronts before
+            double pin = R.tau;
+            int sin_ = R.steps;
             for (int off = 1; off < 64; off <<= 1) {
                 const double pv = __shfl_up(pin, off);
                 const int sv = __shfl_up(sin_, off);
                 if (lane >= off) { pin *= pv; sin_ += sv; }
             }
+            double before = 1.0;
+            int sbefore = 0;
+            if constexpr (WG) {
+                if (lane == 63) { s_tau[wid] = pin; s_steps[wid] = sin_; }
+                __syncthreads();
+                for (int w = 0; w < wid; ++w) { before *= s_tau[w]; sbefore += s_steps[w]; }
+            }
             double tau_in = __shfl_up(pin, 1);
             int steps_in = __shfl_up(sin_, 1);
             if (lane == 0) { tau_in = 1.0; steps_in = 0; }
-            tau_in *= stau;
-            steps_in += ssteps;
+            tau_in = stau * (before * tau_in);
+            steps_in += ssteps + sbefore;
             const bool stops = !empty && (wall_end || !(tau_in * R.tau > (double)A.tol) ||
                                           steps_in + R.steps >= A.max_steps);
             const uint64_t sm = __ballot(stops);
-            if (sm == 0) {
-                // nothing stopped: add the contributions, continue from the end of lane 63
+            int lstar;
+            if constexpr (WG) {
+                if (lane == 0) s_first[wid] = sm ? wid * 64 + __ffsll((long long)sm) - 1 : NSEG;
+                __syncthreads();
+                lstar = min(min(s_first[0], s_first[1]), min(s_first[2], s_first[3]));
+            } else {
+                lstar = sm ? __ffsll((long long)sm) - 1 : NSEG;
+            }
+            if (lstar == NSEG) {
+                // nothing stopped: add the contributions, continue from the end of the last segment
                 double contrib = tau_in * R.acc;
                 for (int off = 32; off > 0; off >>= 1) contrib += __shfl_xor(contrib, off);
-                sacc += contrib;
-                stau = __shfl(tau_in * R.tau, 63);
-                ssteps = __shfl(steps_in + R.steps, 63);
-                si = __shfl(R.i, 63); sj = __shfl(R.j, 63); sk = __shfl(R.k, 63);
-                st = __shfl(R.t, 63); stx = __shfl(R.tx, 63); sty = __shfl(R.ty, 63); stz = __shfl(R.tz, 63);
-                soy = __shfl(R.oy, 63);
-                ssgn = __shfl(R.sgn, 63);
+                if constexpr (WG) {
+                    if (lane == 0) s_acc[wid] = contrib;
+                    if (seg == NSEG - 1) {
+                        s_tail.tau = tau_in * R.tau;
+                        s_tail.steps = steps_in + R.steps;
+                        s_tail.i = R.i; s_tail.j = R.j; s_tail.k = R.k;
+                        s_tail.t = R.t; s_tail.tx = R.tx; s_tail.ty = R.ty; s_tail.tz = R.tz;
+                        s_tail.oy = R.oy;
+                        s_tail.sgn = R.sgn;
+                    }
+                    __syncthreads();
+                    sacc += ((s_acc[0] + s_acc[1]) + s_acc[2]) + s_acc[3];
+                    stau = s_tail.tau;
+                    ssteps = s_tail.steps;
+                    si = s_tail.i; sj = s_tail.j; sk = s_tail.k;
+                    st = s_tail.t; stx = s_tail.tx; sty = s_tail.ty; stz = s_tail.tz;
+                    soy = s_tail.oy;
+                    ssgn = s_tail.sgn;
+                    __syncthreads();   // the LDS values are read before the next round writes them
+                } else {
+                    sacc += contrib;
+                    stau = __shfl(tau_in * R.tau, 63);
+                    ssteps = __shfl(steps_in + R.steps, 63);
+                    si = __shfl(R.i, 63); sj = __shfl(R.j, 63); sk = __shfl(R.k, 63);
+                    st = __shfl(R.t, 63); stx = __shfl(R.tx, 63); sty = __shfl(R.ty, 63); stz = __shfl(R.tz, 63);
+                    soy = __shfl(R.oy, 63);
+                    ssgn = __shfl(R.sgn, 63);
+                }
                 continue;
             }
-            const int lstar = __ffsll((long long)sm) - 1;
-            double contrib = (lane < lstar) ? tau_in * R.acc : 0.0;
-            if (lane == lstar) {
+            double contrib = (seg < lstar) ? tau_in * R.acc : 0.0;
+            if (seg == lstar) {
                 // re-march the stopping segment with its true incoming tau and step count
                 R.i = start_i; R.j = start_j; R.k = start_k;
                 R.t = start_t; R.tx = start_tx; R.ty = start_ty; R.tz = start_tz;
@@ -1271,9 +1323,15 @@ __global__ void __launch_bounds__(256) k_march_long(MarchArgs<float> A)
                           gld(Ipl + cur), A.max_steps);
                 contrib = R.acc;
             }
-            // fixed-order wave sum of the contributions
+            // fixed-order sum of the contributions over the wavefront (and the workgroup)
             for (int off = 32; off > 0; off >>= 1) contrib += __shfl_xor(contrib, off);
-            if (lane == lstar) {
+            double total = contrib;
+            if constexpr (WG) {
+                if (lane == 0) s_acc[wid] = contrib;
+                __syncthreads();
+                total = ((s_acc[0] + s_acc[1]) + s_acc[2]) + s_acc[3];
+            }
+            if (seg == lstar) {
                 const size_t slot = (size_t)c * A.R + r;
                 double w;
                 if constexpr (!PDF) {
@@ -1282,10 +1340,11 @@ __global__ void __launch_bounds__(256) k_march_long(MarchArgs<float> A)
                     const double p = gld(D.dprob + slot);
                     w = 4.0 * M_PI * A.dnu[n] * A.wg[pair - n * A.ng] / (8.0 * p);
                 }
-                const double acc = sacc + contrib;
+                const double acc = sacc + total;
                 store_slot<float>(D, slot, w * (double)kap_src * acc, (uint32_t)R.steps | ((uint32_t)R.end << 28));
                 atomicAdd(A.long_steps, (unsigned long long)(R.steps - rc.steps));
             }
+            if constexpr (WG) __syncthreads();   // the LDS values are read before the next ray writes them
             break;
         }
     }
@@ -2383,13 +2442,25 @@ rmc_status enqueue_pipeline(const Plan &P, double *const *divq, double *const *s
     if (EV) HIPCHK(hipEventRecord(EV->e[3], s));
     if constexpr (sizeof(Real) == 4) {
         if (segment && MA.cap < O.max_steps) {
+            // black walls: few long rays, their latency sets the time -- one workgroup (256
+            // segments) per ray, the workgroups past the device's count of them exit at once.
+            // Reflecting walls: many long rays -- one wavefront (64 segments) each.
+            bool refl = false;
+            for (const SnapDesc &d : P.D) refl = refl || d.reflect != 0;
+            const dim3 lg(refl ? 1024u : std::min<uint32_t>(P.cont_cap, 4096)), lb(256);
+#define RMC_LONG(PDF_, MULTI_)                                                                                   \
+    do {                                                                                                       \
+        if (refl) hipLaunchKernelGGL((k_march_long<PDF_, MULTI_, false>), lg, lb, lds_faces, s, MA);          \
+        else hipLaunchKernelGGL((k_march_long<PDF_, MULTI_, true>), lg, lb, lds_faces, s, MA);                \
+    } while (0)
             if (P.pdf_mode) {
-                if (multi) hipLaunchKernelGGL((k_march_long<true, true>), dim3(1024), dim3(256), lds_faces, s, MA);
-                else hipLaunchKernelGGL((k_march_long<true, false>), dim3(1024), dim3(256), lds_faces, s, MA);
+                if (multi) RMC_LONG(true, true);
+                else RMC_LONG(true, false);
             } else {
-                if (multi) hipLaunchKernelGGL((k_march_long<false, true>), dim3(1024), dim3(256), lds_faces, s, MA);
-                else hipLaunchKernelGGL((k_march_long<false, false>), dim3(1024), dim3(256), lds_faces, s, MA);
+                if (multi) RMC_LONG(false, true);
+                else RMC_LONG(false, false);
             }
+#undef RMC_LONG
             HIPCHK(hipGetLastError());
         }
     }
