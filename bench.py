@@ -402,8 +402,7 @@ def main():
     se = torch.zeros_like(dq)
 
     def step():
-        s.set_temperature(T)
-        s.set_species(X)
+        s.set_fields(T, X)          # ingest of the snapshot's fields (one synchronisation)
         s.compute(dq, se)
 
     for _ in range(a.warmup):

@@ -192,6 +192,13 @@ rmc_status rmc_set_temperature(rmc_ctx *ctx, const void *T, rmc_dtype dtype, rmc
 rmc_status rmc_set_species(rmc_ctx *ctx, int ns, const void *X, rmc_dtype dtype, rmc_mem mem,
                            void *stream);
 
+/* rmc_set_temperature and rmc_set_species in one call (the per-snapshot ingest of a DNS loop):
+ * both fields are converted and checked by kernels enqueued together and the stream is
+ * synchronised once.  Same arguments, layouts and errors as the two calls (a temperature error
+ * is reported first; each field is kept or rejected on its own). */
+rmc_status rmc_set_fields(rmc_ctx *ctx, const void *T, rmc_dtype T_dtype, int ns, const void *X,
+                          rmc_dtype X_dtype, rmc_mem mem, void *stream);
+
 /* Solver options; see rmc_options.  rmc_default_options fills the defaults
  * (R = 16, seed 0, tol 1e-6, max_steps 65536, F32 march, F64 sums, plain sampling). */
 void rmc_default_options(rmc_options *opt);

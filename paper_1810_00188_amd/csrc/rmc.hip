@@ -198,6 +198,21 @@ __global__ void __launch_bounds__(256) k_ingest_T(const Tin *__restrict__ in, do
     block_min_atomic(mn, maxbits + 2);
 }
 
+// Reduction slots of the ingest kernels in the context's `small` buffer (64-bit words):
+// mole fractions max [0, 8), min [8, 16), flag 16; temperature max 24, flag 25, min 26.
+// Maxima start at 0, minima at a huge double (0x7F7F...), flags at 0.
+constexpr int kSmallX = 0, kSmallT = 24, kSmallWords = 27;
+
+__global__ void k_small_init(unsigned long long *small, int x, int t)
+{
+    const int q = (int)threadIdx.x;
+    if (q >= kSmallWords) return;
+    const bool in_x = x && q < 17, in_t = t && q >= kSmallT;
+    if (!in_x && !in_t) return;
+    const bool is_min = (q >= kSmallX + 8 && q < kSmallX + 16) || q == kSmallT + 2;
+    small[q] = is_min ? 0x7F7F7F7F7F7F7F7Full : 0ull;
+}
+
 template <class Tin>
 __global__ void __launch_bounds__(256) k_ingest_X(const Tin *__restrict__ in, double *__restrict__ out, uint64_t nc,
                                                   int ns, unsigned long long *maxbits, unsigned int *flag)
@@ -1643,6 +1658,38 @@ struct DBuf {
         p = nullptr;
         bytes = 0;
     }
+    DBuf() = default;
+    DBuf(const DBuf &) = delete;
+    DBuf &operator=(const DBuf &) = delete;
+    ~DBuf() { release(); }   // with the owning context's device current (rmc_destroy)
+};
+
+// Pinned host memory (hipHostMalloc): readbacks of the ingest kernels and the per-compute
+// descriptor uploads, so that those copies are plain DMA transfers.
+struct PinBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    rmc_status ensure(size_t want)
+    {
+        if (want <= bytes && p) return RMC_OK;
+        if (p) { (void)hipHostFree(p); p = nullptr; bytes = 0; }
+        hipError_t e = hipHostMalloc(&p, want < 256 ? 256 : want, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+            return fail(RMC_OUT_OF_MEMORY, "hipHostMalloc of %zu bytes failed: %s", want, hipGetErrorString(e));
+        }
+        bytes = want < 256 ? 256 : want;
+        return RMC_OK;
+    }
+    template <class T> T *as() const { return static_cast<T *>(p); }
+    PinBuf() = default;
+    PinBuf(const PinBuf &) = delete;
+    PinBuf &operator=(const PinBuf &) = delete;
+    ~PinBuf()
+    {
+        if (p) (void)hipHostFree(p);
+    }
 };
 
 struct DeviceGuard {
@@ -1682,7 +1729,7 @@ struct rmc_ctx {
     std::vector<double> k64_host;   // for the march order heuristic (kappa at T_max per (n, g))
     // fields
     bool have_T = false, have_X = false;
-    DBuf T, X, stage;
+    DBuf T, X, stage, stage2;
     double Tmax_cells = 0;
     double xhat[8] = {0};
     int graphs = 0;         // live graphs capturing this context
@@ -1703,6 +1750,9 @@ struct rmc_ctx {
     // slots
     DBuf Y, st;
     DBuf rbkt;              // bucket of each ray (counting pass -> scatter pass)
+    PinBuf hread, hup;      // pinned readback of the ingest kernels; pinned descriptor uploads
+    hipEvent_t up_evt = nullptr;   // the last descriptor upload from hup (hup is reused after it)
+    bool up_pending = false;
     int slots_R = 0, slots_real = 0;
     // shared pipeline workspace (used when this context leads a batch)
     DBuf hist, bucket_total, bucket_start, nchunks, chunk_bucket, items, faces, snaps, tile_snap, counters, red_part,
@@ -2313,11 +2363,29 @@ template <class Real> rmc_status plan_pipeline(rmc_ctx *const *ctxs, int nsnap, 
     L->h_snaps.resize(sizeof(SnapDesc) * nsnap);
     memcpy(L->h_snaps.data(), P.D.data(), sizeof(SnapDesc) * nsnap);
     march_order(L, L->h_order);
-    HIPCHK(hipMemcpyAsync(L->faces.p, faces.data(), sizeof(double) * P.nfaces, hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(L->snaps.p, L->h_snaps.data(), sizeof(SnapDesc) * nsnap, hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(L->tile_snap.p, tile_snap.data(), sizeof(int) * P.ntiles, hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(L->border.p, L->h_order.data(), sizeof(uint32_t) * nbucket, hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(L->kmin.p, L->h_kmin.data(), sizeof(float) * nb * ng, hipMemcpyHostToDevice, s));
+    // descriptor uploads from one pinned staging buffer (reused once the last upload is done)
+    const size_t sz[5] = {sizeof(double) * P.nfaces, sizeof(SnapDesc) * nsnap, sizeof(int) * P.ntiles,
+                          sizeof(uint32_t) * nbucket, sizeof(float) * nb * ng};
+    const void *src[5] = {faces.data(), L->h_snaps.data(), tile_snap.data(), L->h_order.data(), L->h_kmin.data()};
+    void *dst[5] = {L->faces.p, L->snaps.p, L->tile_snap.p, L->border.p, L->kmin.p};
+    size_t off[5], total = 0;
+    for (int u = 0; u < 5; ++u) {
+        off[u] = total;
+        total += (sz[u] + 255) & ~(size_t)255;
+    }
+    if (L->up_pending) {
+        HIPCHK(hipEventSynchronize(L->up_evt));
+        L->up_pending = false;
+    }
+    if ((st = L->hup.ensure(total))) return st;
+    if (!L->up_evt) HIPCHK(hipEventCreateWithFlags(&L->up_evt, hipEventDisableTiming));
+    unsigned char *stage = L->hup.as<unsigned char>();
+    for (int u = 0; u < 5; ++u) {
+        memcpy(stage + off[u], src[u], sz[u]);
+        HIPCHK(hipMemcpyAsync(dst[u], stage + off[u], sz[u], hipMemcpyHostToDevice, s));
+    }
+    HIPCHK(hipEventRecord(L->up_evt, s));
+    L->up_pending = true;
     return RMC_OK;
 }
 
@@ -2528,12 +2596,15 @@ rmc_status run_pipeline(rmc_ctx *const *ctxs, int nsnap, double *const *divq, do
     return RMC_OK;
 }
 
-rmc_status validate_T(rmc_ctx *c, const void *src, rmc_dtype dt, rmc_mem mem, hipStream_t s)
+// Temperature ingest, enqueued: conversion to FP64, range check, maximum and minimum into the
+// context's reduction slots and (pinned) readback; ingest_T_finish reads them after a sync.
+rmc_status ingest_T_enqueue(rmc_ctx *c, const void *src, rmc_dtype dt, rmc_mem mem, hipStream_t s)
 {
     const uint64_t nc = ncells_of(c);
     const size_t esz = dt == RMC_F32 ? 4 : 8;
     rmc_status st;
-    if ((st = c->T.ensure(sizeof(double) * nc)) || (st = c->small.ensure(64)) || (st = c->scal.ensure(sizeof(double) * 9)))
+    if ((st = c->T.ensure(sizeof(double) * nc)) || (st = c->small.ensure(256)) ||
+        (st = c->scal.ensure(sizeof(double) * 9)) || (st = c->hread.ensure(256)))
         return st;
     const void *dsrc = src;
     if (mem == RMC_HOST) {
@@ -2541,10 +2612,9 @@ rmc_status validate_T(rmc_ctx *c, const void *src, rmc_dtype dt, rmc_mem mem, hi
         HIPCHK(hipMemcpyAsync(c->stage.p, src, esz * nc, hipMemcpyHostToDevice, s));
         dsrc = c->stage.p;
     }
-    HIPCHK(hipMemsetAsync(c->small.p, 0, 64, s));
-    HIPCHK(hipMemsetAsync(c->small.as<unsigned long long>() + 2, 0x7F, 8, s));   // min slot: a huge double
-    unsigned long long *mx = c->small.as<unsigned long long>();
+    unsigned long long *mx = c->small.as<unsigned long long>() + kSmallT;
     unsigned int *flag = reinterpret_cast<unsigned int *>(mx + 1);
+    hipLaunchKernelGGL(k_small_init, dim3(1), dim3(64), 0, s, c->small.as<unsigned long long>(), 0, 1);
     const unsigned blocks = (unsigned)std::min<uint64_t>(512, (nc + 255) / 256);
     if (dt == RMC_F32)
         hipLaunchKernelGGL(k_ingest_T<float>, dim3(blocks), dim3(256), 0, s, (const float *)dsrc, c->T.as<double>(),
@@ -2553,21 +2623,73 @@ rmc_status validate_T(rmc_ctx *c, const void *src, rmc_dtype dt, rmc_mem mem, hi
         hipLaunchKernelGGL(k_ingest_T<double>, dim3(blocks), dim3(256), 0, s, (const double *)dsrc,
                            c->T.as<double>(), nc, c->T0, c->dT, c->nT, mx, flag);
     HIPCHK(hipGetLastError());
-    unsigned long long host[3] = {0, 0, 0};
-    HIPCHK(hipMemcpyAsync(host, c->small.p, 24, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipMemcpyAsync(c->hread.as<unsigned long long>() + kSmallT, mx, 24, hipMemcpyDeviceToHost, s));
+    return RMC_OK;
+}
+
+rmc_status ingest_T_finish(rmc_ctx *c, hipStream_t s)
+{
+    const unsigned long long *host = c->hread.as<unsigned long long>() + kSmallT;
     if ((unsigned)host[1] & 1u) {
         c->have_T = false;
         return fail(RMC_OUT_OF_RANGE, "temperature outside the table range [%g, %g] or NaN", c->T0,
                     c->T0 + c->dT * (c->nT - 1));
     }
-    double m;
-    memcpy(&m, &host[0], 8);
-    c->Tmax_cells = m;
+    memcpy(&c->Tmax_cells, &host[0], 8);
     memcpy(&c->Tmin_cells, &host[2], 8);
-    HIPCHK(hipMemcpyAsync(c->scal.p, &c->Tmax_cells, sizeof(double), hipMemcpyHostToDevice, s));
-    HIPCHK(hipStreamSynchronize(s));
+    // the maximum's bits are the double itself: copied on the device, stream-ordered
+    HIPCHK(hipMemcpyAsync(c->scal.p, c->small.as<unsigned long long>() + kSmallT, sizeof(double),
+                          hipMemcpyDeviceToDevice, s));
     c->have_T = true;
+    return RMC_OK;
+}
+
+// Mole-fraction ingest, enqueued (see ingest_T_enqueue); maxima x-hat and minima per species.
+rmc_status ingest_X_enqueue(rmc_ctx *c, int ns, const void *X, rmc_dtype dt, rmc_mem mem, hipStream_t s)
+{
+    const uint64_t nc = ncells_of(c);
+    const size_t esz = dt == RMC_F32 ? 4 : 8;
+    rmc_status st;
+    if ((st = c->X.ensure(sizeof(double) * nc * ns)) || (st = c->small.ensure(256)) ||
+        (st = c->scal.ensure(sizeof(double) * 9)) || (st = c->hread.ensure(256)))
+        return st;
+    const void *dsrc = X;
+    if (mem == RMC_HOST) {
+        if ((st = c->stage2.ensure(esz * nc * ns))) return st;
+        HIPCHK(hipMemcpyAsync(c->stage2.p, X, esz * nc * ns, hipMemcpyHostToDevice, s));
+        dsrc = c->stage2.p;
+    }
+    unsigned long long *mx = c->small.as<unsigned long long>() + kSmallX;
+    unsigned int *flag = reinterpret_cast<unsigned int *>(mx + 16);
+    hipLaunchKernelGGL(k_small_init, dim3(1), dim3(64), 0, s, c->small.as<unsigned long long>(), 1, 0);
+    const unsigned blocks = (unsigned)std::min<uint64_t>(512, (nc + 255) / 256);
+    if (dt == RMC_F32)
+        hipLaunchKernelGGL(k_ingest_X<float>, dim3(blocks), dim3(256), 0, s, (const float *)dsrc, c->X.as<double>(),
+                           nc, ns, mx, flag);
+    else
+        hipLaunchKernelGGL(k_ingest_X<double>, dim3(blocks), dim3(256), 0, s, (const double *)dsrc,
+                           c->X.as<double>(), nc, ns, mx, flag);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(c->hread.as<unsigned long long>() + kSmallX, mx, sizeof(unsigned long long) * 17,
+                          hipMemcpyDeviceToHost, s));
+    return RMC_OK;
+}
+
+rmc_status ingest_X_finish(rmc_ctx *c, int ns, hipStream_t s)
+{
+    const unsigned long long *host = c->hread.as<unsigned long long>() + kSmallX;
+    if ((unsigned)host[16] & 1u) {
+        c->have_X = false;
+        return fail(RMC_OUT_OF_RANGE, "mole fractions must be finite and >= 0");
+    }
+    for (int q = 0; q < ns; ++q) {
+        memcpy(&c->xhat[q], &host[q], 8);
+        memcpy(&c->xmin[q], &host[8 + q], 8);
+    }
+    // the maxima's bits are the doubles themselves: copied on the device, stream-ordered
+    HIPCHK(hipMemcpyAsync(c->scal.as<double>() + 1, c->small.as<unsigned long long>() + kSmallX,
+                          sizeof(double) * ns, hipMemcpyDeviceToDevice, s));
+    c->have_X = true;
     return RMC_OK;
 }
 
@@ -2670,7 +2792,7 @@ void rmc_destroy(rmc_ctx *c)
     {
         DeviceGuard g(c->device);
         (void)hipDeviceSynchronize();
-        DBuf *bufs[] = {&c->k64, &c->Ib, &c->dnu, &c->wg, &c->T, &c->X, &c->stage, &c->q, &c->cpdf, &c->ccdf_b,
+        DBuf *bufs[] = {&c->k64, &c->Ib, &c->dnu, &c->wg, &c->T, &c->X, &c->stage, &c->stage2, &c->q, &c->cpdf, &c->ccdf_b,
                         &c->ccdf_g, &c->ccdf_o, &c->pdf_scratch, &c->p, &c->cdf_b, &c->cdf_g, &c->W, &c->Iw,
                         &c->status, &c->field, &c->Iplane, &c->Y, &c->st, &c->hist, &c->bucket_total, &c->bucket_start,
                         &c->nchunks, &c->chunk_bucket, &c->items, &c->faces, &c->snaps, &c->tile_snap,
@@ -2679,8 +2801,9 @@ void rmc_destroy(rmc_ctx *c)
         for (DBuf *b : bufs) b->release();
         for (auto &set : c->ring)
             for (auto &ev : set.e) (void)hipEventDestroy(ev);
+        if (c->up_evt) (void)hipEventDestroy(c->up_evt);
+        delete c;   // the remaining buffers are released with the device still current
     }
-    delete c;
 }
 
 rmc_status rmc_set_grid(rmc_ctx *c, int nx, int ny, int nz, const double *xf, const double *yf, const double *zf)
@@ -2812,7 +2935,10 @@ rmc_status rmc_set_temperature(rmc_ctx *c, const void *T, rmc_dtype dt, rmc_mem 
     if (mem != RMC_HOST && mem != RMC_DEVICE) return fail(RMC_INVALID_ARG, "bad memory kind");
     DeviceGuard g(c->device);
     if (!g.ok) return fail(RMC_DEVICE_ERROR, "hipSetDevice(%d) failed", c->device);
-    return validate_T(c, T, dt, mem, (hipStream_t)stream);
+    hipStream_t s = (hipStream_t)stream;
+    if (rmc_status st = ingest_T_enqueue(c, T, dt, mem, s)) return st;
+    HIPCHK(hipStreamSynchronize(s));
+    return ingest_T_finish(c, s);
 }
 
 rmc_status rmc_set_species(rmc_ctx *c, int ns, const void *X, rmc_dtype dt, rmc_mem mem, void *stream)
@@ -2827,45 +2953,37 @@ rmc_status rmc_set_species(rmc_ctx *c, int ns, const void *X, rmc_dtype dt, rmc_
     DeviceGuard g(c->device);
     if (!g.ok) return fail(RMC_DEVICE_ERROR, "hipSetDevice(%d) failed", c->device);
     hipStream_t s = (hipStream_t)stream;
-    const uint64_t nc = ncells_of(c);
-    const size_t esz = dt == RMC_F32 ? 4 : 8;
-    rmc_status st;
-    if ((st = c->X.ensure(sizeof(double) * nc * ns)) || (st = c->small.ensure(256)) ||
-        (st = c->scal.ensure(sizeof(double) * 9)))
-        return st;
-    const void *dsrc = X;
-    if (mem == RMC_HOST) {
-        if ((st = c->stage.ensure(esz * nc * ns))) return st;
-        HIPCHK(hipMemcpyAsync(c->stage.p, X, esz * nc * ns, hipMemcpyHostToDevice, s));
-        dsrc = c->stage.p;
-    }
-    HIPCHK(hipMemsetAsync(c->small.p, 0, 256, s));
-    HIPCHK(hipMemsetAsync(c->small.as<unsigned long long>() + 8, 0x7F, 64, s));   // min slots: huge doubles
-    unsigned long long *mx = c->small.as<unsigned long long>();
-    unsigned int *flag = reinterpret_cast<unsigned int *>(mx + 16);
-    const unsigned blocks = (unsigned)std::min<uint64_t>(512, (nc + 255) / 256);
-    if (dt == RMC_F32)
-        hipLaunchKernelGGL(k_ingest_X<float>, dim3(blocks), dim3(256), 0, s, (const float *)dsrc, c->X.as<double>(),
-                           nc, ns, mx, flag);
-    else
-        hipLaunchKernelGGL(k_ingest_X<double>, dim3(blocks), dim3(256), 0, s, (const double *)dsrc,
-                           c->X.as<double>(), nc, ns, mx, flag);
-    HIPCHK(hipGetLastError());
-    unsigned long long host[17] = {0};
-    HIPCHK(hipMemcpyAsync(host, c->small.p, sizeof host, hipMemcpyDeviceToHost, s));
+    if (rmc_status st = ingest_X_enqueue(c, ns, X, dt, mem, s)) return st;
     HIPCHK(hipStreamSynchronize(s));
-    if ((unsigned)host[16] & 1u) {
-        c->have_X = false;
-        return fail(RMC_OUT_OF_RANGE, "mole fractions must be finite and >= 0");
-    }
-    for (int q = 0; q < ns; ++q) {
-        memcpy(&c->xhat[q], &host[q], 8);
-        memcpy(&c->xmin[q], &host[8 + q], 8);
-    }
-    HIPCHK(hipMemcpyAsync(c->scal.as<double>() + 1, c->xhat, sizeof(double) * ns, hipMemcpyHostToDevice, s));
+    return ingest_X_finish(c, ns, s);
+}
+
+rmc_status rmc_set_fields(rmc_ctx *c, const void *T, rmc_dtype T_dtype, int ns, const void *X, rmc_dtype X_dtype,
+                          rmc_mem mem, void *stream)
+{
+    g_err.clear();
+    if (rmc_status st = check_ctx(c)) return st;
+    if (!c->have_grid || !c->have_kdist) return fail(RMC_BAD_STATE, "set_grid and set_kdist must come first");
+    if (!T) return fail(RMC_INVALID_ARG, "null temperature pointer");
+    if (!X) return fail(RMC_INVALID_ARG, "null species pointer");
+    if (ns != c->ns) return fail(RMC_INVALID_ARG, "ns = %d does not match the tables (%d)", ns, c->ns);
+    if ((T_dtype != RMC_F32 && T_dtype != RMC_F64) || (X_dtype != RMC_F32 && X_dtype != RMC_F64))
+        return fail(RMC_INVALID_ARG, "field dtypes must be RMC_F32 or RMC_F64");
+    if (mem != RMC_HOST && mem != RMC_DEVICE) return fail(RMC_INVALID_ARG, "bad memory kind");
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(RMC_DEVICE_ERROR, "hipSetDevice(%d) failed", c->device);
+    hipStream_t s = (hipStream_t)stream;
+    if (rmc_status st = ingest_T_enqueue(c, T, T_dtype, mem, s)) return st;
+    if (rmc_status st = ingest_X_enqueue(c, ns, X, X_dtype, mem, s)) return st;
     HIPCHK(hipStreamSynchronize(s));
-    c->have_X = true;
-    return RMC_OK;
+    const rmc_status st_T = ingest_T_finish(c, s);
+    const std::string err_T = g_err;
+    const rmc_status st_X = ingest_X_finish(c, ns, s);
+    if (st_T) {   // report the temperature's error first
+        g_err = err_T;
+        return st_T;
+    }
+    return st_X;
 }
 
 rmc_status rmc_set_options(rmc_ctx *c, const rmc_options *o)

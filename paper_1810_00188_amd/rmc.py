@@ -80,6 +80,7 @@ SIGNATURES = {
                                 _VP, _VP, _VP, C.c_int, _VP]),
     "rmc_set_temperature": (C.c_int, [_VP, _VP, C.c_int, C.c_int, _VP]),
     "rmc_set_species": (C.c_int, [_VP, C.c_int, _VP, C.c_int, C.c_int, _VP]),
+    "rmc_set_fields": (C.c_int, [_VP, _VP, C.c_int, C.c_int, _VP, C.c_int, C.c_int, _VP]),
     "rmc_default_options": (None, [C.POINTER(Options)]),
     "rmc_set_options": (C.c_int, [_VP, C.POINTER(Options)]),
     "rmc_get_options": (C.c_int, [_VP, C.POINTER(Options)]),
@@ -252,6 +253,17 @@ class Solver:
         p, mem, keep = _buf(T)
         _check(LIB.rmc_set_temperature(self.h, p, _dtype_code(keep), mem,
                                        _stream(stream) if mem == DEVICE else stream))
+
+    def set_fields(self, T, X, stream=None):
+        """rmc_set_fields: temperature and mole fractions in one call (one synchronisation);
+        both in host memory or both on the device."""
+        pt, mt, kt = _buf(T)
+        px, mx, kx = _buf(X)
+        if mt != mx:
+            raise ValueError("T and X must both be host arrays or both device tensors")
+        ns = kx.shape[0] if kx.ndim == 2 else 1
+        _check(LIB.rmc_set_fields(self.h, pt, _dtype_code(kt), ns, px, _dtype_code(kx), mt,
+                                  _stream(stream) if mt == DEVICE else stream))
 
     def set_species(self, X, stream=None):
         p, mem, keep = _buf(X)

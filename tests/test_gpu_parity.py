@@ -179,6 +179,40 @@ def test_launch_order_does_not_change_results():
         assert np.array_equal(Y, out[0][2]) and np.array_equal(S, out[0][3])
 
 
+def test_set_fields_equals_separate_ingest():
+    """rmc_set_fields (both fields, one synchronisation) gives the compute of
+    set_temperature + set_species bitwise, from host arrays and from device tensors; its
+    range errors name the field and leave the context usable."""
+    import torch
+    w = _small_channel(march="f32", nx=12, ny=10, nz=8, R=8)
+    say(f"set_fields {w.name}")
+    s = _solver(w)
+    ref, _ = s.compute()
+    T = np.ascontiguousarray(w.T, dtype=np.float32)
+    X = np.ascontiguousarray(np.atleast_2d(w.X), dtype=np.float32)
+    s.set_temperature(np.full_like(T, 500.0))          # something else in between
+    s.set_fields(T, X)
+    got, _ = s.compute()
+    assert np.array_equal(got, ref)
+    dev = torch.device("cuda", 0)
+    s.set_fields(torch.from_numpy(T).to(dev), torch.from_numpy(X).to(dev))
+    got, _ = s.compute()
+    assert np.array_equal(got, ref)
+    Tbad = T.copy()
+    Tbad[3] = np.nan
+    with pytest.raises(rmc.RmcError) as e:
+        s.set_fields(Tbad, X)
+    assert e.value.status == rmc.RMC_OUT_OF_RANGE and "temperature" in str(e.value)
+    Xbad = X.copy()
+    Xbad[0, 5] = -1.0
+    with pytest.raises(rmc.RmcError) as e:
+        s.set_fields(T, Xbad)
+    assert e.value.status == rmc.RMC_OUT_OF_RANGE and "mole fractions" in str(e.value)
+    s.set_fields(T, X)
+    got, _ = s.compute()
+    assert np.array_equal(got, ref)
+
+
 def test_autotune_keeps_results_and_caches(tmp_path):
     """The autotuner only picks schedule knobs: the estimate after tuning is bitwise the
     estimate before; its choice is written to the cache and read back."""
