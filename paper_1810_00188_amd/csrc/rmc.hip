@@ -1066,18 +1066,14 @@ struct LongTail {
 };
 
 template <bool PDF, bool MULTI, bool WG>
-__global__ void __launch_bounds__(256) k_march_long(MarchArgs<float> A)
+__device__ __forceinline__ void long_rays(const MarchArgs<float> &A, const double *sf, uint32_t nrec)
 {
     constexpr int NSEG = WG ? kLongSeg : 64;
-    extern __shared__ double sf[];
     __shared__ double s_tau[4], s_acc[4];
     __shared__ int s_steps[4], s_first[4];
     __shared__ LongTail s_tail;
-    for (int q = threadIdx.x; q < A.nfaces; q += blockDim.x) sf[q] = A.faces[q];
-    __syncthreads();
     const int lane = (int)(threadIdx.x & 63), wid = (int)(threadIdx.x >> 6);
     const int seg = WG ? (int)threadIdx.x : lane;
-    const uint32_t nrec = min(__builtin_amdgcn_readfirstlane(*A.cont_count), A.cont_cap);
     const uint32_t first = WG ? blockIdx.x
                               : __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
     const uint32_t stride = WG ? gridDim.x : gridDim.x * (blockDim.x >> 6);
@@ -1363,6 +1359,23 @@ __global__ void __launch_bounds__(256) k_march_long(MarchArgs<float> A)
             break;
         }
     }
+}
+
+// Few long rays (black walls: the rare grazing ones) are latency-bound: a workgroup and 256
+// segments each.  Many (reflecting walls, large grids at high R) are throughput-bound: a
+// wavefront and 64 segments each.  The count is known on the device only; the branch is
+// uniform over the launch.
+constexpr uint32_t kLongWgMax = 8192;
+
+template <bool PDF, bool MULTI>
+__global__ void __launch_bounds__(256) k_march_long(MarchArgs<float> A)
+{
+    extern __shared__ double sf[];
+    for (int q = threadIdx.x; q < A.nfaces; q += blockDim.x) sf[q] = A.faces[q];
+    __syncthreads();
+    const uint32_t nrec = min(__builtin_amdgcn_readfirstlane(*A.cont_count), A.cont_cap);
+    if (nrec <= kLongWgMax) long_rays<PDF, MULTI, true>(A, sf, nrec);
+    else long_rays<PDF, MULTI, false>(A, sf, nrec);
 }
 
 #include "learn_kernels.inc"
@@ -2510,25 +2523,16 @@ rmc_status enqueue_pipeline(const Plan &P, double *const *divq, double *const *s
     if (EV) HIPCHK(hipEventRecord(EV->e[3], s));
     if constexpr (sizeof(Real) == 4) {
         if (segment && MA.cap < O.max_steps) {
-            // black walls: few long rays, their latency sets the time -- one workgroup (256
-            // segments) per ray, the workgroups past the device's count of them exit at once.
-            // Reflecting walls: many long rays -- one wavefront (64 segments) each.
-            bool refl = false;
-            for (const SnapDesc &d : P.D) refl = refl || d.reflect != 0;
-            const dim3 lg(refl ? 1024u : std::min<uint32_t>(P.cont_cap, 4096)), lb(256);
-#define RMC_LONG(PDF_, MULTI_)                                                                                   \
-    do {                                                                                                       \
-        if (refl) hipLaunchKernelGGL((k_march_long<PDF_, MULTI_, false>), lg, lb, lds_faces, s, MA);          \
-        else hipLaunchKernelGGL((k_march_long<PDF_, MULTI_, true>), lg, lb, lds_faces, s, MA);                \
-    } while (0)
+            // a workgroup or a wavefront per long ray (chosen on the device by their count);
+            // the workgroups past the work exit at once
+            const dim3 lg(4096), lb(256);
             if (P.pdf_mode) {
-                if (multi) RMC_LONG(true, true);
-                else RMC_LONG(true, false);
+                if (multi) hipLaunchKernelGGL((k_march_long<true, true>), lg, lb, lds_faces, s, MA);
+                else hipLaunchKernelGGL((k_march_long<true, false>), lg, lb, lds_faces, s, MA);
             } else {
-                if (multi) RMC_LONG(false, true);
-                else RMC_LONG(false, false);
+                if (multi) hipLaunchKernelGGL((k_march_long<false, true>), lg, lb, lds_faces, s, MA);
+                else hipLaunchKernelGGL((k_march_long<false, false>), lg, lb, lds_faces, s, MA);
             }
-#undef RMC_LONG
             HIPCHK(hipGetLastError());
         }
     }
