@@ -108,6 +108,12 @@ typedef struct {
                                 0 (default) = about 1024 tiles over the pass (256 to 8192 cells).
                                 Larger tiles mean fewer per-tile histograms; results are the same
                                 either way */
+    int32_t long_ray_form;   /* long-ray kernel (FP32 march, periodic x and z): 0 (default) picks
+                                on the device by the number of long rays -- up to 8192, one
+                                workgroup of 256 parallel segments per ray (their latency sets
+                                the time), more, one wavefront of 64 (throughput); 1 always
+                                workgroups; 2 always wavefronts.  The segments' products round
+                                differently, so the forms agree within the FP32 tolerance */
 } rmc_options;
 
 typedef struct {

@@ -710,6 +710,7 @@ template <class Real> struct MarchArgs {
     unsigned long long *long_steps;   // steps taken by k_march_long in this compute
     int span_log2;              // log2 of the run of consecutive chunks an XCD takes in turn
     float log_inv_tol;          // ln(1 / tol), for the expected-length estimate
+    int long_form;              // k_march_long: 0 by the count of long rays, 1 workgroups, 2 wavefronts
 };
 
 // Workgroups of a launch are dealt to the XCDs in turn (workgroup b runs on XCD b mod 8) and
@@ -1374,7 +1375,7 @@ __global__ void __launch_bounds__(256) k_march_long(MarchArgs<float> A)
     for (int q = threadIdx.x; q < A.nfaces; q += blockDim.x) sf[q] = A.faces[q];
     __syncthreads();
     const uint32_t nrec = min(__builtin_amdgcn_readfirstlane(*A.cont_count), A.cont_cap);
-    if (nrec <= kLongWgMax) long_rays<PDF, MULTI, true>(A, sf, nrec);
+    if (A.long_form == 1 || (A.long_form == 0 && nrec <= kLongWgMax)) long_rays<PDF, MULTI, true>(A, sf, nrec);
     else long_rays<PDF, MULTI, false>(A, sf, nrec);
 }
 
@@ -1869,6 +1870,7 @@ rmc_status check_options(const rmc_options *o)
     if (o->mg_steps < 0 || o->mg_steps > (1 << 24)) return fail(RMC_INVALID_ARG, "mg_steps must be in [0, 2^24]");
     if (o->alloc_tile != 0 && (o->alloc_tile < 256 || o->alloc_tile > 65536 || o->alloc_tile % 64))
         return fail(RMC_INVALID_ARG, "alloc_tile must be 0 or a multiple of 64 in [256, 65536]");
+    if (o->long_ray_form < 0 || o->long_ray_form > 2) return fail(RMC_INVALID_ARG, "long_ray_form must be 0, 1 or 2");
     return RMC_OK;
 }
 
@@ -2483,6 +2485,7 @@ rmc_status enqueue_pipeline(const Plan &P, double *const *divq, double *const *s
     MA.cont_cap = P.cont_cap;
     MA.long_steps = L->counters.as<unsigned long long>() + 3;
     MA.log_inv_tol = O.tol > 0.0 ? (float)std::log(1.0 / O.tol) : 1e30f;
+    MA.long_form = O.long_ray_form;
     MA.span_log2 = 0;
     for (int sp = O.xcd_span > 0 ? O.xcd_span : 256; sp > 1; sp >>= 1) ++MA.span_log2;
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, L->cont_count.as<uint32_t>(), 1);
@@ -2628,10 +2631,13 @@ rmc_status ingest_T_enqueue(rmc_ctx *c, const void *src, rmc_dtype dt, rmc_mem m
                            c->T.as<double>(), nc, c->T0, c->dT, c->nT, mx, flag);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(c->hread.as<unsigned long long>() + kSmallT, mx, 24, hipMemcpyDeviceToHost, s));
+    // the maximum's bits are the double itself: copied on the device before the caller's sync
+    // (a rejected field is never used, so the copy needs no check)
+    HIPCHK(hipMemcpyAsync(c->scal.p, mx, sizeof(double), hipMemcpyDeviceToDevice, s));
     return RMC_OK;
 }
 
-rmc_status ingest_T_finish(rmc_ctx *c, hipStream_t s)
+rmc_status ingest_T_finish(rmc_ctx *c)
 {
     const unsigned long long *host = c->hread.as<unsigned long long>() + kSmallT;
     if ((unsigned)host[1] & 1u) {
@@ -2641,9 +2647,6 @@ rmc_status ingest_T_finish(rmc_ctx *c, hipStream_t s)
     }
     memcpy(&c->Tmax_cells, &host[0], 8);
     memcpy(&c->Tmin_cells, &host[2], 8);
-    // the maximum's bits are the double itself: copied on the device, stream-ordered
-    HIPCHK(hipMemcpyAsync(c->scal.p, c->small.as<unsigned long long>() + kSmallT, sizeof(double),
-                          hipMemcpyDeviceToDevice, s));
     c->have_T = true;
     return RMC_OK;
 }
@@ -2676,10 +2679,12 @@ rmc_status ingest_X_enqueue(rmc_ctx *c, int ns, const void *X, rmc_dtype dt, rmc
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(c->hread.as<unsigned long long>() + kSmallX, mx, sizeof(unsigned long long) * 17,
                           hipMemcpyDeviceToHost, s));
+    // the maxima's bits are the doubles themselves: copied on the device before the caller's sync
+    HIPCHK(hipMemcpyAsync(c->scal.as<double>() + 1, mx, sizeof(double) * ns, hipMemcpyDeviceToDevice, s));
     return RMC_OK;
 }
 
-rmc_status ingest_X_finish(rmc_ctx *c, int ns, hipStream_t s)
+rmc_status ingest_X_finish(rmc_ctx *c, int ns)
 {
     const unsigned long long *host = c->hread.as<unsigned long long>() + kSmallX;
     if ((unsigned)host[16] & 1u) {
@@ -2690,9 +2695,6 @@ rmc_status ingest_X_finish(rmc_ctx *c, int ns, hipStream_t s)
         memcpy(&c->xhat[q], &host[q], 8);
         memcpy(&c->xmin[q], &host[8 + q], 8);
     }
-    // the maxima's bits are the doubles themselves: copied on the device, stream-ordered
-    HIPCHK(hipMemcpyAsync(c->scal.as<double>() + 1, c->small.as<unsigned long long>() + kSmallX,
-                          sizeof(double) * ns, hipMemcpyDeviceToDevice, s));
     c->have_X = true;
     return RMC_OK;
 }
@@ -2942,7 +2944,7 @@ rmc_status rmc_set_temperature(rmc_ctx *c, const void *T, rmc_dtype dt, rmc_mem 
     hipStream_t s = (hipStream_t)stream;
     if (rmc_status st = ingest_T_enqueue(c, T, dt, mem, s)) return st;
     HIPCHK(hipStreamSynchronize(s));
-    return ingest_T_finish(c, s);
+    return ingest_T_finish(c);
 }
 
 rmc_status rmc_set_species(rmc_ctx *c, int ns, const void *X, rmc_dtype dt, rmc_mem mem, void *stream)
@@ -2959,7 +2961,7 @@ rmc_status rmc_set_species(rmc_ctx *c, int ns, const void *X, rmc_dtype dt, rmc_
     hipStream_t s = (hipStream_t)stream;
     if (rmc_status st = ingest_X_enqueue(c, ns, X, dt, mem, s)) return st;
     HIPCHK(hipStreamSynchronize(s));
-    return ingest_X_finish(c, ns, s);
+    return ingest_X_finish(c, ns);
 }
 
 rmc_status rmc_set_fields(rmc_ctx *c, const void *T, rmc_dtype T_dtype, int ns, const void *X, rmc_dtype X_dtype,
@@ -2980,9 +2982,9 @@ rmc_status rmc_set_fields(rmc_ctx *c, const void *T, rmc_dtype T_dtype, int ns, 
     if (rmc_status st = ingest_T_enqueue(c, T, T_dtype, mem, s)) return st;
     if (rmc_status st = ingest_X_enqueue(c, ns, X, X_dtype, mem, s)) return st;
     HIPCHK(hipStreamSynchronize(s));
-    const rmc_status st_T = ingest_T_finish(c, s);
+    const rmc_status st_T = ingest_T_finish(c);
     const std::string err_T = g_err;
-    const rmc_status st_X = ingest_X_finish(c, ns, s);
+    const rmc_status st_X = ingest_X_finish(c, ns);
     if (st_T) {   // report the temperature's error first
         g_err = err_T;
         return st_T;

@@ -115,15 +115,16 @@ def test_channel64_sampled_production_launch():
     assert st["rays"] == w.ncells * w.R
 
 
-@pytest.mark.parametrize("after", [1, 4, 37])
-def test_segmented_long_rays_match_oracle(after):
-    """Rays still marching after `after` steps are finished by 64 lanes in parallel segments:
-    with a tiny threshold nearly every ray takes that path; all must match the oracle."""
+@pytest.mark.parametrize("after,form", [(1, 0), (4, 0), (37, 0), (1, 1), (37, 1), (1, 2), (37, 2)])
+def test_segmented_long_rays_match_oracle(after, form):
+    """Rays still marching after `after` steps are finished in parallel segments (form 1: a
+    workgroup and 256 segments per ray, 2: a wavefront and 64, 0: by their count): with a tiny
+    threshold nearly every ray takes that path; all must match the oracle."""
     w = _small_channel(march="f32", nx=12, ny=10, nz=8, R=16, amp=0.05)
     import dataclasses
     w = w.replace(kd=dataclasses.replace(w.kd, k=w.kd.k * np.float32(0.05)))   # long paths
-    say(f"segmented march after {after} steps")
-    s = _solver(w, long_ray_steps=after)
+    say(f"segmented march after {after} steps, form {form}")
+    s = _solver(w, long_ray_steps=after, long_ray_form=form)
     s.compute()
     cells = np.arange(w.ncells)
     Y, S = s.ray_values(cells)
@@ -303,7 +304,7 @@ def test_errors_are_reported_not_fatal():
     assert e.value.status == rmc.RMC_OUT_OF_RANGE
     for bad in (dict(rays_per_cell=0), dict(xcd_span=2), dict(xcd_span=48), dict(long_ray_steps=-1),
                 dict(length_sort=2), dict(mg_levels=-2), dict(mg_levels=9), dict(mg_steps=-1),
-                dict(alloc_tile=192), dict(alloc_tile=300), dict(alloc_tile=65600)):
+                dict(alloc_tile=192), dict(alloc_tile=300), dict(alloc_tile=65600), dict(long_ray_form=3)):
         with pytest.raises(rmc.RmcError) as e:
             s.set_options(rmc.default_options(**bad))
         assert e.value.status == rmc.RMC_INVALID_ARG, bad

@@ -146,17 +146,18 @@ def test_wall_errors():
     assert np.all(np.isfinite(dq))
 
 
-@pytest.mark.parametrize("after,eps,levels", [(1, (0.3, 0.7), 1), (4, (0.0, 1.0), 1), (37, (0.1, 0.1), 1),
-                                              (3, (0.5, 0.2), 3)])
-def test_reflecting_walls_segmented_long_rays(after, eps, levels):
+@pytest.mark.parametrize("after,eps,levels,form", [(1, (0.3, 0.7), 1, 0), (4, (0.0, 1.0), 1, 0),
+                                                   (37, (0.1, 0.1), 1, 0), (3, (0.5, 0.2), 3, 0),
+                                                   (1, (0.3, 0.7), 1, 1), (4, (0.0, 1.0), 1, 2)])
+def test_reflecting_walls_segmented_long_rays(after, eps, levels, form):
     """Rays still marching after `after` steps go to the parallel-segment kernel, which
     replays the y reflections before each segment (weak absorption: long, bouncing paths)."""
     import dataclasses
     w = _small_channel(march="f32", nx=24, ny=12, nz=16, R=16, amp=0.05)
     w = w.replace(kd=dataclasses.replace(w.kd, k=w.kd.k * np.float32(0.05)), eps_walls=eps,
                   mg_levels=levels, mg_steps=3)
-    say(f"reflecting walls {eps}, segmented after {after} steps, {levels} levels")
-    s = _solver(w, long_ray_steps=after)
+    say(f"reflecting walls {eps}, segmented after {after} steps, {levels} levels, form {form}")
+    s = _solver(w, long_ray_steps=after, long_ray_form=form)
     s.compute()
     cells = np.arange(w.ncells)
     Y, S = s.ray_values(cells)
