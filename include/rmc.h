@@ -256,6 +256,19 @@ rmc_status rmc_set_cell_pdf(rmc_ctx *ctx, const double *q, rmc_mem mem, void *st
 rmc_status rmc_compute_divergence(rmc_ctx *ctx, double *divq, double *stderr_out, rmc_mem mem,
                                   void *stream);
 
+/* rmc_compute_divergence plus the wall flux: q_wall receives, per wall face element, the net
+ * radiative flux from the gas into the wall [W m^-2] -- the sum over every ray that ended on
+ * that element of its wall term w kappa_src tau_w (I_src - I_w) (Eq. 3's wall factor with
+ * emissivity 1, Eq. 14's weight), times the source cell's volume / (R x the element's area).
+ * Exchange between walls is not part of it (rays start in gas cells).  Layout, doubles:
+ * x0 [ny][nz], x1 [ny][nz], y0 [nx][nz], y1 [nx][nz], z0 [nx][ny], z1 [nx][ny] (the x and z
+ * walls of a periodic box stay zero); in `mem` memory like divq.  Needs every wall black and
+ * one grid (mg_levels 0 or 1): else RMC_UNSUPPORTED.  The face sums use FP64 atomics, so
+ * they are reproducible to rounding, not bitwise; divq and stderr are those of
+ * rmc_compute_divergence, bitwise.  Enqueued on `stream`; nothing is synchronised. */
+rmc_status rmc_compute_wall_flux(rmc_ctx *ctx, double *divq, double *stderr_out, double *q_wall, rmc_mem mem,
+                                 void *stream);
+
 /* Several snapshots (contexts on one device with identical tables, options and walls;
  * grids and fields may differ) in one pass of the pipeline: the rays of all snapshots are
  * bucketed together and marched by one kernel launch.  divq[s] / stderr[s] (nullable)

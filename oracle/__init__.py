@@ -58,6 +58,7 @@ def lib():
         L.orc_march.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
                                 C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
         L.orc_march_mg.argtypes = L.orc_march.argtypes
+        L.orc_wall_flux.argtypes = [C.c_void_p, C.c_void_p]
         L.orc_level_count.argtypes = [C.c_int, C.c_int, C.c_int]
         L.orc_level_count.restype = C.c_int
         L.orc_coarse_fields.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
@@ -83,7 +84,8 @@ class _Problem(C.Structure):
 
 
 class _MarchOut(C.Structure):
-    _fields_ = [("acc", C.c_double), ("absacc", C.c_double), ("steps", C.c_int), ("end", C.c_int)]
+    _fields_ = [("acc", C.c_double), ("absacc", C.c_double), ("steps", C.c_int), ("end", C.c_int),
+                ("wacc", C.c_double), ("wall", C.c_int), ("wface", C.c_int)]
 
 
 RAY_DTYPE = np.dtype([("Y", "f8"), ("absY", "f8"), ("p", "f8"), ("n", "i4"), ("g", "i4"),
@@ -206,11 +208,30 @@ def divergence(prob: Problem, cells=None, nthreads: int = 0):
     return dq, se, st.value
 
 
+def wall_flux(prob: Problem) -> np.ndarray:
+    """Net radiative flux from the gas into every wall face element [W m^-2] (black walls, one
+    grid), flat: x0 [ny*nz], x1, y0 [nx*nz], y1, z0 [nx*ny], z1 (see split_walls)."""
+    q = np.zeros(2 * (prob.ny * prob.nz + prob.nx * prob.nz + prob.nx * prob.ny))
+    _check(lib().orc_wall_flux(prob.ptr, q.ctypes.data))
+    return q
+
+
+def split_walls(prob: Problem, q) -> dict:
+    """The six wall arrays of a flat wall-flux vector: x0, x1 [ny, nz], y0, y1 [nx, nz], z0, z1 [nx, ny]."""
+    nx, ny, nz = prob.nx, prob.ny, prob.nz
+    sizes = [ny * nz, ny * nz, nx * nz, nx * nz, nx * ny, nx * ny]
+    shapes = [(ny, nz), (ny, nz), (nx, nz), (nx, nz), (nx, ny), (nx, ny)]
+    o = np.concatenate([[0], np.cumsum(sizes)])
+    return {k: np.asarray(q)[o[u]:o[u + 1]].reshape(shapes[u]) for u, k in enumerate(("x0", "x1", "y0", "y1", "z0", "z1"))}
+
+
 def march(prob: Problem, cell_ijk, n: int, g: int, d, record: int = 0, multigrid: bool = False):
     """March one ray of band n, g-point g from the centre of cell (i, j, k) along d.
 
-    Returns dict(acc, absacc, steps, end[, cells, ds]) -- the accumulated
-    sum tau alpha (I_c - I_j) (+ wall and residual terms) before the ray weight.  With
+    Returns dict(acc, absacc, steps, end, wall, wface, wacc[, cells, ds]) -- the accumulated
+    sum tau alpha (I_c - I_j) (+ wall and residual terms) before the ray weight; wall / wface /
+    wacc: the black wall (0..5: x0, x1, y0, y1, z0, z1; -1 none) that ended the ray, the face
+    element it reached there and the wall term of acc.  With
     ``multigrid`` the ray takes the multigrid march of the problem's mg_levels / mg_steps and
     the recorded cells are (level, natural index within that level) pairs."""
     d = _f64(d)
@@ -221,7 +242,7 @@ def march(prob: Problem, cell_ijk, n: int, g: int, d, record: int = 0, multigrid
     fn = lib().orc_march_mg if multigrid else lib().orc_march
     _check(fn(prob.ptr, i, j, k, int(n), int(g), d.ctypes.data, C.addressof(m),
               rc.ctypes.data if record else None, rd.ctypes.data if record else None, int(record)))
-    out = dict(acc=m.acc, absacc=m.absacc, steps=m.steps, end=m.end)
+    out = dict(acc=m.acc, absacc=m.absacc, steps=m.steps, end=m.end, wall=m.wall, wface=m.wface, wacc=m.wacc)
     if record:
         cells = rc[:min(m.steps, record)]
         if multigrid:

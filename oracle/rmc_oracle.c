@@ -285,6 +285,9 @@ static int search_cdf(const double *cdf, int n, double u)
 typedef struct {
     double acc, absacc;
     int steps, end;
+    double wacc;     /* wall term tau_w eps (I_src - I_w) of the black wall that ended the ray */
+    int wall;        /* that wall: 0 x0, 1 x1, 2 y0, 3 y1, 4 z0, 5 z1; -1 none */
+    int wface;       /* its face element: (j, k) on x walls, (i, k) on y, (i, j) on z, row-major */
 } orc_march_out;
 
 static double face_coord(const double *f, int n, int local, int wrap)
@@ -307,7 +310,7 @@ static void wall_of(const orc_problem *P, int a, int side, double *Tw, double *e
  * black wall ends the ray (*end set), 0 otherwise, or an error code in *err. */
 static int walls(const orc_problem *P, int n, const int hit[3], const int nn[3], const double *const f[3],
                  int idx[3], const int wrap[3], double o[3], double dd[3], int sg[3], double tn[3], double Isrc,
-                 double *tau, double *acc, double *absacc, int *end, int *err)
+                 double *tau, double *acc, double *absacc, int *end, double *wacc, int *wall, int *err)
 {
     for (int a = 0; a < 3; ++a) {
         if (!hit[a]) continue;
@@ -316,10 +319,11 @@ static int walls(const orc_problem *P, int n, const int hit[3], const int nn[3],
         int code;
         wall_of(P, a, side, &Tw, &eps, &code);
         if ((*err = planck_at(P, n, Tw, &Iw))) return 0;
-        *acc += *tau * eps * (Isrc - Iw);
+        const double term = *tau * eps * (Isrc - Iw);
+        *acc += term;
         *absacc += *tau * eps * fabs(Isrc - Iw);
         *tau *= 1.0 - eps;
-        if (eps == 1.0) { *end = code; return 1; }
+        if (eps == 1.0) { *end = code; *wacc = term; *wall = 2 * a + side; return 1; }
         idx[a] = side ? nn[a] - 1 : 0;                          /* R14 */
         o[a] = 2.0 * f[a][side ? nn[a] : 0] - o[a];
         dd[a] = -dd[a];
@@ -348,7 +352,8 @@ int orc_march(const orc_problem *P, int ci, int cj, int ck, int n, int g, const 
         sg[a] = dd[a] > 0.0 ? 1 : -1;
         tn[a] = (face_coord(f[a], nn[a], idx[a] + (sg[a] > 0), wrap[a]) - o[a]) / dd[a];
     }
-    double Isrc, Ilast, t = 0.0, tau = 1.0, acc = 0.0, absacc = 0.0;
+    double Isrc, Ilast, t = 0.0, tau = 1.0, acc = 0.0, absacc = 0.0, wacc = 0.0;
+    int wall = -1;
     int e = cell_planck(P, csrc, n, &Isrc);
     if (e) return e;
     Ilast = Isrc;
@@ -382,11 +387,22 @@ int orc_march(const orc_problem *P, int ci, int cj, int ck, int n, int g, const 
             tn[a] = (face_coord(f[a], nn[a], idx[a] + (sg[a] > 0), wrap[a]) - o[a]) / dd[a];
         }
         if (hit[0] | hit[1] | hit[2]) {
-            int stop = walls(P, n, hit, nn, f, idx, wrap, o, dd, sg, tn, Isrc, &tau, &acc, &absacc, &end, &e);
+            int stop = walls(P, n, hit, nn, f, idx, wrap, o, dd, sg, tn, Isrc, &tau, &acc, &absacc, &end, &wacc,
+                             &wall, &e);
             if (e) return e;
             if (stop) break;
         }
     }
+    if (wall >= 0) {   /* the face element the ray reached: in-plane indices, clamped to the grid */
+        int cl[3];
+        for (int a = 0; a < 3; ++a) cl[a] = idx[a] < 0 ? 0 : (idx[a] >= nn[a] ? nn[a] - 1 : idx[a]);
+        const int a = wall / 2;
+        res->wface = a == 0 ? cl[1] * nn[2] + cl[2] : (a == 1 ? cl[0] * nn[2] + cl[2] : cl[0] * nn[1] + cl[1]);
+    } else {
+        res->wface = -1;
+    }
+    res->wacc = wacc;
+    res->wall = wall;
     if (end == 0 && steps >= P->max_steps && tau > P->tol) end = 3;
     acc += tau * (Isrc - Ilast);                                 /* residual dump, R11 */
     absacc += tau * fabs(Isrc - Ilast);
@@ -514,7 +530,8 @@ static int march_levels(const orc_problem *P, const orc_levels *G, int ci, int c
         sg[a] = dd[a] > 0.0 ? 1 : -1;
         tn[a] = (face_coord(f[a], nn[a], idx[a] + (sg[a] > 0), wrap[a]) - o[a]) / dd[a];
     }
-    double Isrc, Ilast, t = 0.0, tau = 1.0, acc = 0.0, absacc = 0.0;
+    double Isrc, Ilast, t = 0.0, tau = 1.0, acc = 0.0, absacc = 0.0, wacc = 0.0;
+    int wall = -1;
     int e = cell_planck(P, csrc, n, &Isrc);
     if (e) return e;
     Ilast = Isrc;
@@ -561,11 +578,22 @@ static int march_levels(const orc_problem *P, const orc_levels *G, int ci, int c
             tn[a] = (face_coord(f[a], nn[a], idx[a] + (sg[a] > 0), wrap[a]) - o[a]) / dd[a];
         }
         if (hit[0] | hit[1] | hit[2]) {
-            int stop = walls(P, n, hit, nn, f, idx, wrap, o, dd, sg, tn, Isrc, &tau, &acc, &absacc, &end, &e);
+            int stop = walls(P, n, hit, nn, f, idx, wrap, o, dd, sg, tn, Isrc, &tau, &acc, &absacc, &end, &wacc,
+                             &wall, &e);
             if (e) return e;
             if (stop) break;
         }
     }
+    if (wall >= 0) {   /* the face element the ray reached: in-plane indices, clamped to the grid */
+        int cl[3];
+        for (int a = 0; a < 3; ++a) cl[a] = idx[a] < 0 ? 0 : (idx[a] >= nn[a] ? nn[a] - 1 : idx[a]);
+        const int a = wall / 2;
+        res->wface = a == 0 ? cl[1] * nn[2] + cl[2] : (a == 1 ? cl[0] * nn[2] + cl[2] : cl[0] * nn[1] + cl[1]);
+    } else {
+        res->wface = -1;
+    }
+    res->wacc = wacc;
+    res->wall = wall;
     if (end == 0 && steps >= P->max_steps && tau > P->tol) end = 3;
     acc += tau * (Isrc - Ilast);                                 /* R11 */
     absacc += tau * fabs(Isrc - Ilast);
@@ -635,9 +663,18 @@ static void cell_pdf(const orc_problem *P, const orc_plain *pl, size_t c, double
     for (int i = 0; i < nb * ng * 8; ++i) pc[i] /= tot;
 }
 
+/* Start of wall w's face elements in the flat wall-flux layout x0 [ny][nz], x1, y0 [nx][nz],
+ * y1, z0 [nx][ny], z1. */
+static int wall_offset(const orc_problem *P, int w)
+{
+    const int fx = P->ny * P->nz, fy = P->nx * P->nz, fz = P->nx * P->ny;
+    const int a = w / 2, side = w % 2;
+    return a == 0 ? side * fx : (a == 1 ? 2 * fx + side * fy : 2 * fx + 2 * fy + side * fz);
+}
+
 /* All R rays of cell (ci,cj,ck): draws (Algorithm 1, Initialize), march, ray value. */
 static int trace_cell(const orc_problem *P, const orc_plain *pl, const orc_levels *G, int ci, int cj, int ck,
-                      orc_ray *out, double *work)
+                      orc_ray *out, double *work, double *yw_out, int *wf_out)
 {
     const int nb = P->nb, ng = P->ng, R = P->R;
     size_t c = ((size_t)ci * P->ny + cj) * P->nz + ck;
@@ -697,6 +734,10 @@ static int trace_cell(const orc_problem *P, const orc_plain *pl, const orc_level
         ry->absY = wgt * kap_src * m.absacc;
         ry->steps = m.steps;
         ry->end = m.end;
+        if (yw_out) {   /* the wall part of the ray value and the wall face element it went to */
+            yw_out[r] = m.wall >= 0 ? wgt * kap_src * m.wacc : 0.0;
+            wf_out[r] = m.wall >= 0 ? wall_offset(P, m.wall) + m.wface : -1;
+        }
     }
     return ORC_OK;
 }
@@ -739,7 +780,7 @@ int orc_trace_cells(const orc_problem *P, int ncell, const int64_t *cells, orc_r
                 int ci = (int)(c / ((int64_t)P->ny * P->nz));
                 int cj = (int)((c / P->nz) % P->ny);
                 int ck = (int)(c % P->nz);
-                int e = trace_cell(P, &pl, &G, ci, cj, ck, out + (size_t)q * P->R, work);
+                int e = trace_cell(P, &pl, &G, ci, cj, ck, out + (size_t)q * P->R, work, 0, 0);
                 if (e) myerr = e;
             }
 #pragma omp critical
@@ -784,7 +825,7 @@ int orc_divergence(const orc_problem *P, int ncell, const int64_t *cells, double
                 int ci = (int)(c / ((int64_t)P->ny * P->nz));
                 int cj = (int)((c / P->nz) % P->ny);
                 int ck = (int)(c % P->nz);
-                int e = trace_cell(P, &pl, &G, ci, cj, ck, rays, work);
+                int e = trace_cell(P, &pl, &G, ci, cj, ck, rays, work, 0, 0);
                 if (e) { myerr = e; continue; }
                 double sum = 0.0;
                 for (int r = 0; r < P->R; ++r) { sum += rays[r].Y; steps += rays[r].steps; }
@@ -801,6 +842,84 @@ int orc_divergence(const orc_problem *P, int ncell, const int64_t *cells, double
     if (steps_total) *steps_total = steps;
     free_levels(&G);
     free(p); free(cb); free(cg);
+    return err;
+}
+
+/* Net radiative flux from the gas into every wall face element [W m^-2] (black walls, one
+ * grid): each ray that ended on a black wall carries the wall part of its value, Y_w = w
+ * kappa_src tau_w (I_src - I_w) (the wall factor of Eq. 3 with emissivity 1, the weight of
+ * Eq. 14); the element receives V_c Y_w / (R A_f) from it, V_c its source cell's volume and
+ * A_f the element's area -- the cell's net power exchange with that element, whose expected
+ * sum over the gas is the gas-to-wall part of the wall's net radiative flux.  Sums run over the
+ * cells in natural order and their rays in order.  q: 2 (ny nz + nx nz + nx ny) doubles,
+ * layout of wall_offset.  Reflecting walls or multigrid: ORC_UNSUPPORTED. */
+int orc_wall_flux(const orc_problem *P, double *q)
+{
+    int err = check_problem(P);
+    if (err) return err;
+    for (int w = 0; w < 2; ++w)
+        if (P->epsw[w] != 1.0 || (P->closed && (P->epsx[w] != 1.0 || P->epsz[w] != 1.0)))
+            return ORC_UNSUPPORTED;
+    if (P->mg_levels > 1) return ORC_UNSUPPORTED;
+    const size_t nc = ncells_of(P);
+    const int R = P->R;
+    double *p = malloc(sizeof(double) * P->nb * P->ng), *cb = malloc(sizeof(double) * P->nb),
+           *cg = malloc(sizeof(double) * P->nb * P->ng);
+    double *yw = malloc(sizeof(double) * nc * R);
+    int *wf = malloc(sizeof(int) * nc * R);
+    err = orc_plain_pdf(P, p, cb, cg, 0);
+    orc_plain pl = {p, cb, cg};
+    orc_levels G;
+    if (!err) err = build_levels(P, &G);
+    else memset(&G, 0, sizeof G);
+    size_t wsz = P->q_cell ? (size_t)P->nb * P->ng * 8 * 2 + P->nb + P->nb * P->ng : 1;
+    if (!err) {
+#pragma omp parallel
+        {
+            orc_ray *rays = malloc(sizeof(orc_ray) * R);
+            double *work = malloc(sizeof(double) * wsz);
+            int myerr = 0;
+#pragma omp for schedule(dynamic, 16)
+            for (int64_t c = 0; c < (int64_t)nc; ++c) {
+                int ci = (int)(c / ((int64_t)P->ny * P->nz));
+                int cj = (int)((c / P->nz) % P->ny);
+                int ck = (int)(c % P->nz);
+                int e = trace_cell(P, &pl, &G, ci, cj, ck, rays, work, yw + c * R, wf + c * R);
+                if (e) myerr = e;
+            }
+#pragma omp critical
+            if (myerr && !err) err = myerr;
+            free(rays); free(work);
+        }
+    }
+    if (!err) {
+        const int fx = P->ny * P->nz, fy = P->nx * P->nz, fz = P->nx * P->ny;
+        memset(q, 0, sizeof(double) * 2 * (fx + fy + fz));
+        for (size_t c = 0; c < nc; ++c) {
+            const int ci = (int)(c / ((size_t)P->ny * P->nz)), cj = (int)((c / P->nz) % P->ny),
+                      ck = (int)(c % P->nz);
+            const double vc = (P->xf[ci + 1] - P->xf[ci]) * (P->yf[cj + 1] - P->yf[cj]) * (P->zf[ck + 1] - P->zf[ck]);
+            for (int r = 0; r < R; ++r) {
+                const int f = wf[c * R + r];
+                if (f < 0) continue;
+                /* the element's area from its in-plane cell widths */
+                double area;
+                if (f < 2 * fx) {
+                    const int e = f % fx, j = e / P->nz, k = e % P->nz;
+                    area = (P->yf[j + 1] - P->yf[j]) * (P->zf[k + 1] - P->zf[k]);
+                } else if (f < 2 * fx + 2 * fy) {
+                    const int e = (f - 2 * fx) % fy, i = e / P->nz, k = e % P->nz;
+                    area = (P->xf[i + 1] - P->xf[i]) * (P->zf[k + 1] - P->zf[k]);
+                } else {
+                    const int e = (f - 2 * fx - 2 * fy) % fz, i = e / P->ny, j = e % P->ny;
+                    area = (P->xf[i + 1] - P->xf[i]) * (P->yf[j + 1] - P->yf[j]);
+                }
+                q[f] += vc * yw[c * R + r] / ((double)R * area);
+            }
+        }
+    }
+    free_levels(&G);
+    free(p); free(cb); free(cg); free(yw); free(wf);
     return err;
 }
 

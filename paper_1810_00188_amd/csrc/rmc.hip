@@ -73,6 +73,8 @@ struct SnapDesc {
     double epsw[6];             // wall emissivities, walls x0, x1, y0, y1, z0, z1
     int closed;                 // walls on x and z (closed box), else x and z periodic
     int reflect;                // some wall has emissivity below one
+    double *wallq;              // wall flux tally (black walls, one grid) or null: x0 [ny][nz], x1,
+                                // y0 [nx][nz], y1, z0 [nx][ny], z1
 };
 
 struct AllocArgs {
@@ -236,6 +238,12 @@ __global__ void __launch_bounds__(256) k_ingest_X(const Tin *__restrict__ in, do
 __global__ void k_zero_u64(unsigned long long *p, int n)
 {
     if ((int)threadIdx.x < n) p[threadIdx.x] = 0ull;
+}
+
+__global__ void k_zero_f64(double *p, uint64_t n)
+{
+    const uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (q < n) p[q] = 0.0;
 }
 
 __global__ void k_zero_u32(uint32_t *p, int n)
@@ -867,6 +875,33 @@ __device__ __forceinline__ uint32_t ray_len_class(const SnapDesc &D, const RayGe
     return (uint32_t)(c < 0 ? 0 : (c > 63 ? 63 : c));
 }
 
+// Wall flux (black walls, one grid): a ray that ended on a black wall adds its wall term
+// w kappa_src tau_w (I_src - I_w), times its source cell's volume over R and over the area of
+// the wall face element it reached, to that element: the net radiative flux the wall receives
+// from the gas [W m^-2].  Face indices outside the grid (a ray through an edge) are clamped.
+// FP64 atomics: the sums are reproducible to rounding, not bitwise.
+template <class Real, bool INC_XZ>
+__device__ __forceinline__ void tally_wall(const SnapDesc &D, const RayGeo &G, const Ray<Real, INC_XZ> &R, int n,
+                                           int nb, int nrays, double wk, uint32_t c)
+{
+    const int w = wall_of_end(R.end);
+    if (w < 0) return;
+    const int ck = (int)(c % (uint32_t)G.nz), cj = (int)((c / (uint32_t)G.nz) % (uint32_t)G.ny),
+              ci = (int)(c / ((uint32_t)G.nz * (uint32_t)G.ny));   // the source cell (natural index)
+    const double Iw = gld(D.Iw + (size_t)w * nb + n);
+    const double yw = wk * ((R.tau * 1.0) * (R.Isrc - Iw));
+    const int i = min(max(R.i, 0), G.nx - 1), j = min(max(R.j, 0), G.ny - 1), k = min(max(R.k, 0), G.nz - 1);
+    const double dx = G.xf[i + 1] - G.xf[i], dy = G.yf[j + 1] - G.yf[j], dz = G.zf[k + 1] - G.zf[k];
+    const double vc = (G.xf[ci + 1] - G.xf[ci]) * (G.yf[cj + 1] - G.yf[cj]) * (G.zf[ck + 1] - G.zf[ck]);
+    const size_t fx = (size_t)G.ny * G.nz, fy = (size_t)G.nx * G.nz, fz = (size_t)G.nx * G.ny;
+    size_t off;
+    double area;
+    if (w < 2) { off = w * fx + (size_t)j * G.nz + k; area = dy * dz; }
+    else if (w < 4) { off = 2 * fx + (w - 2) * fy + (size_t)i * G.nz + k; area = dx * dz; }
+    else { off = 2 * fx + 2 * fy + (w - 4) * fz + (size_t)i * G.ny + j; area = dx * dy; }
+    atomicAdd(D.wallq + off, vc * yw / ((double)nrays * area));
+}
+
 // One ray per lane, no refill: every wavefront marches 64 work items of one bucket and
 // retires when its longest ray ends; the hardware scheduler balances the many short-lived
 // wavefronts.  With SORT, the workgroup first reorders the 256 items of its four chunks by
@@ -978,6 +1013,7 @@ __global__ void __launch_bounds__(256) k_march_lane(MarchArgs<Real> A)
         w = 4.0 * M_PI * A.dnu[n] * A.wg[pair - n * A.ng] / (8.0 * p);
     }
     store_slot<Real>(D, slot, w * (double)kap_src * (double)R.acc, (uint32_t)R.steps | ((uint32_t)R.end << 28));
+    if (D.wallq) tally_wall(D, G, R, n, A.nb, A.R, w * (double)kap_src, c);
 }
 
 // Multigrid march: one ray per lane as in k_march_lane (no length sort).  A ray still marching
@@ -1355,6 +1391,7 @@ __device__ __forceinline__ void long_rays(const MarchArgs<float> &A, const doubl
                 const double acc = sacc + total;
                 store_slot<float>(D, slot, w * (double)kap_src * acc, (uint32_t)R.steps | ((uint32_t)R.end << 28));
                 atomicAdd(A.long_steps, (unsigned long long)(R.steps - rc.steps));
+                if (D.wallq) tally_wall(D, G, R, n, A.nb, A.R, w * (double)kap_src, c);
             }
             if constexpr (WG) __syncthreads();   // the LDS values are read before the next ray writes them
             break;
@@ -1764,6 +1801,8 @@ struct rmc_ctx {
     // slots
     DBuf Y, st;
     DBuf rbkt;              // bucket of each ray (counting pass -> scatter pass)
+    double *wall_dev = nullptr;   // wall flux tally of the compute in progress (rmc_compute_wall_flux)
+    DBuf wallbuf;           // its device buffer for host outputs
     PinBuf hread, hup;      // pinned readback of the ingest kernels; pinned descriptor uploads
     hipEvent_t up_evt = nullptr;   // the last descriptor upload from hup (hup is reused after it)
     bool up_pending = false;
@@ -2172,6 +2211,7 @@ template <class Real> rmc_status plan_snapshot(rmc_ctx *c, SnapDesc &D)
     }
     D.kap = c->field.p;
     D.Ipl = c->Iplane.as<double>();
+    D.wallq = c->wall_dev;
     // multigrid levels
     const int allowed = level_count(c->nx, c->ny, c->nz);
     D.nlev = c->opt.mg_levels < 0 ? allowed : std::max(1, c->opt.mg_levels);
@@ -2179,6 +2219,8 @@ template <class Real> rmc_status plan_snapshot(rmc_ctx *c, SnapDesc &D)
         return fail(RMC_INVALID_ARG, "mg_levels %d exceeds the %d grid levels a %dx%dx%d grid allows", D.nlev, allowed,
                     c->nx, c->ny, c->nz);
     D.mg_steps = c->opt.mg_steps > 0 ? c->opt.mg_steps : 5;
+    if (D.wallq && (D.nlev > 1 || D.reflect))
+        return fail(RMC_UNSUPPORTED, "the wall flux needs black walls and the DNS grid only (no multigrid)");
     if (D.nlev > 1) {
         uint64_t off = 0, cells = 0;
         for (int L = 1; L < D.nlev; ++L) {
@@ -2488,6 +2530,11 @@ rmc_status enqueue_pipeline(const Plan &P, double *const *divq, double *const *s
     MA.long_form = O.long_ray_form;
     MA.span_log2 = 0;
     for (int sp = O.xcd_span > 0 ? O.xcd_span : 256; sp > 1; sp >>= 1) ++MA.span_log2;
+    for (const SnapDesc &d : P.D)
+        if (d.wallq) {   // wall flux tally of this compute (a fill kernel: no memset, graph-safe)
+            const uint64_t nw = 2 * ((uint64_t)d.ny * d.nz + (uint64_t)d.nx * d.nz + (uint64_t)d.nx * d.ny);
+            hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s, d.wallq, nw);
+        }
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, L->cont_count.as<uint32_t>(), 1);
     HIPCHK(hipGetLastError());
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, L->counters.as<unsigned long long>() + 3, 1);
@@ -3203,6 +3250,29 @@ rmc_status rmc_compute_divergence(rmc_ctx *c, double *divq, double *se, rmc_mem 
     double *d[1] = {divq};
     double *e[1] = {se};
     return rmc_compute_batch(cs, 1, d, e, mem, stream);
+}
+
+rmc_status rmc_compute_wall_flux(rmc_ctx *c, double *divq, double *se, double *q_wall, rmc_mem mem, void *stream)
+{
+    g_err.clear();
+    if (rmc_status st = check_ctx(c)) return st;
+    if (!divq || !q_wall) return fail(RMC_INVALID_ARG, "null output");
+    if (mem != RMC_HOST && mem != RMC_DEVICE) return fail(RMC_INVALID_ARG, "bad memory kind");
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(RMC_DEVICE_ERROR, "hipSetDevice(%d) failed", c->device);
+    const size_t nw = 2 * ((size_t)c->ny * c->nz + (size_t)c->nx * c->nz + (size_t)c->nx * c->ny);
+    double *dev = q_wall;
+    if (mem == RMC_HOST) {
+        if (rmc_status st = c->wallbuf.ensure(sizeof(double) * nw)) return st;
+        dev = c->wallbuf.as<double>();
+    }
+    c->wall_dev = dev;
+    const rmc_status st = rmc_compute_divergence(c, divq, se, mem, stream);
+    c->wall_dev = nullptr;
+    if (st) return st;
+    if (mem == RMC_HOST)
+        HIPCHK(hipMemcpyAsync(q_wall, dev, sizeof(double) * nw, hipMemcpyDeviceToHost, (hipStream_t)stream));
+    return RMC_OK;
 }
 
 rmc_status rmc_graph_capture(rmc_ctx *const *ctxs, int nsnap, double *const *divq, double *const *se, void *stream,

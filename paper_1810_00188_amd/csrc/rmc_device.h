@@ -20,6 +20,11 @@ constexpr int kEndTol = 0, kEndWallLo = 1, kEndWallHi = 2, kEndCap = 3;   // y w
 // wall mask, and the end code of a ray that a black wall w stops.
 constexpr int kWallX0 = 0, kWallX1 = 1, kWallY0 = 2, kWallY1 = 3, kWallZ0 = 4, kWallZ1 = 5;
 __device__ __forceinline__ int wall_end_code(int w) { return w < 2 ? 4 + w : (w < 4 ? w - 1 : w + 2); }
+// ...and back: the wall (x0, x1, y0, y1, z0, z1) a ray ended on, -1 if it did not end on a wall
+__device__ __forceinline__ int wall_of_end(int end)
+{
+    return end == 1 || end == 2 ? end + 1 : (end == 4 || end == 5 ? end - 4 : (end == 6 || end == 7 ? end - 2 : -1));
+}
 
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds, each two 32x32->64 bit products of
 // counter words with fixed multipliers, xor-mixed with the other words and the round key;
@@ -373,11 +378,13 @@ __device__ __forceinline__ bool ray_absorb(Ray<Real, INC_XZ> &R, Real kc, double
             if (!((wall >> w) & 1)) continue;
             const double e = gld(W.eps + w);
             const double dw = R.Isrc - gld(W.I + w * W.stride);
+            const double tw = R.tau;
             R.acc += R.tau * e * dw;
             R.tau *= 1.0 - e;
             if (e == 1.0) {
                 R.end = wall_end_code(w);
                 R.acc += R.tau * (R.Isrc - Ic);   // residual of a finished ray: zero
+                R.tau = tw;                        // kept: the transmissivity the black wall received
                 return true;
             }
         }

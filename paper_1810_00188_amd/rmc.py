@@ -86,6 +86,7 @@ SIGNATURES = {
     "rmc_get_options": (C.c_int, [_VP, C.POINTER(Options)]),
     "rmc_set_cell_pdf": (C.c_int, [_VP, _VP, C.c_int, _VP]),
     "rmc_compute_divergence": (C.c_int, [_VP, _VP, _VP, C.c_int, _VP]),
+    "rmc_compute_wall_flux": (C.c_int, [_VP, _VP, _VP, _VP, C.c_int, _VP]),
     "rmc_compute_batch": (C.c_int, [C.POINTER(_VP), C.c_int, C.POINTER(_VP), C.POINTER(_VP),
                                     C.c_int, _VP]),
     "rmc_get_ray_values": (C.c_int, [_VP, _VP, C.c_int, _VP, _VP, _VP]),
@@ -328,6 +329,40 @@ class Solver:
             import torch
             torch.cuda.synchronize(self.device)
         return divq, stderr
+
+    def wall_elements(self) -> int:
+        return 2 * (self.ny * self.nz + self.nx * self.nz + self.nx * self.ny)
+
+    def compute_wall_flux(self, divq=None, stderr=None, q_wall=None, stream=None):
+        """rmc_compute_wall_flux: compute() plus the net flux from the gas into each wall face
+        element [W m^-2] (black walls, one grid).  Returns (divq, stderr, q_wall); q_wall in the
+        layout x0 [ny,nz], x1, y0 [nx,nz], y1, z0 [nx,ny], z1 (see split_walls)."""
+        if divq is None:
+            divq = np.zeros(self.ncells)
+            if stderr is None:
+                stderr = np.zeros(self.ncells)
+        if q_wall is None:
+            q_wall = np.zeros(self.wall_elements())
+        pd, mem, kd = _buf(divq)
+        ps, _, ks = _buf(stderr) if stderr is not None else (None, mem, None)
+        pw, mw, kw = _buf(q_wall)
+        if mw != mem:
+            raise ValueError("divq and q_wall must both be host arrays or both device tensors")
+        st = _stream(stream) if mem == DEVICE else stream
+        _check(LIB.rmc_compute_wall_flux(self.h, pd, ps, pw, mem, st))
+        if mem == HOST:
+            import torch
+            torch.cuda.synchronize(self.device)
+        return divq, stderr, q_wall
+
+    def split_walls(self, q_wall) -> dict:
+        """The six wall arrays of a flat q_wall: x0, x1 [ny, nz], y0, y1 [nx, nz], z0, z1 [nx, ny]."""
+        q = np.asarray(q_wall)
+        fx, fy, fz = self.ny * self.nz, self.nx * self.nz, self.nx * self.ny
+        o = np.cumsum([0, fx, fx, fy, fy, fz])
+        shp = [(self.ny, self.nz)] * 2 + [(self.nx, self.nz)] * 2 + [(self.nx, self.ny)] * 2
+        return {k: q[o[u]:o[u] + shp[u][0] * shp[u][1]].reshape(shp[u])
+                for u, k in enumerate(("x0", "x1", "y0", "y1", "z0", "z1"))}
 
     def ray_values(self, cells, stream=None):
         cells = np.ascontiguousarray(cells, dtype=np.int64)

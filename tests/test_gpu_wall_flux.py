@@ -1,0 +1,103 @@
+"""GPU parity of the wall flux (rmc_compute_wall_flux) against the oracle's orc_wall_flux:
+per wall face element, FP64 and FP32 march, periodic channel and closed box; the isothermal
+energy balance (wall power = gas power); divq unchanged; the unsupported cases refused."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1810_00188_amd import inputs, rmc
+
+from _parity import say, _solver, _small_channel
+
+pytestmark = pytest.mark.gpu
+
+
+def _compare(w, rel):
+    s = _solver(w)
+    dq, _, qw = s.compute_wall_flux()
+    ref = oracle.wall_flux(oracle.Problem(w))
+    scale = np.abs(ref).max()
+    assert scale > 0.0
+    err = np.abs(qw - ref).max() / scale
+    say(f"{w.name}: wall flux max |gpu - oracle| / max|q| = {err:.3e}")
+    assert err < rel, err
+    # the same elements are reached (no contribution lost or misplaced)
+    assert np.array_equal(qw != 0.0, ref != 0.0)
+    return s, dq, qw
+
+
+@pytest.mark.parametrize("march,rel", [("f64", 1e-11), ("f32", 2e-5)])
+def test_channel_wall_flux_matches_oracle(march, rel):
+    w = _small_channel(march=march, nx=12, ny=9, nz=8, R=16)
+    say(f"wall flux channel {march}")
+    s, dq, _ = _compare(w, rel)
+    # divq of the wall-flux compute is the plain compute's, bitwise
+    dq2, _ = s.compute()
+    assert np.array_equal(dq, dq2)
+
+
+@pytest.mark.parametrize("march,rel", [("f64", 1e-11), ("f32", 2e-5)])
+def test_closed_box_wall_flux_matches_oracle(march, rel):
+    w = inputs.cube_3dimens(n=10, R=16, nb=4, ng=3).replace(march=march)
+    say(f"wall flux closed box {march}")
+    s, _, qw = _compare(w, rel)
+    q = s.split_walls(qw)
+    assert all(q[k].any() for k in q)
+
+
+def test_long_rays_wall_flux_matches_oracle():
+    """Rays finished by the parallel-segment kernel (both forms) add their wall terms too."""
+    import dataclasses
+    w = _small_channel(march="f32", nx=12, ny=10, nz=8, R=16, amp=0.05)
+    w = w.replace(kd=dataclasses.replace(w.kd, k=w.kd.k * np.float32(0.05)))
+    ref = oracle.wall_flux(oracle.Problem(w))
+    for form in (1, 2):
+        s = _solver(w, long_ray_steps=3, long_ray_form=form)
+        _, _, qw = s.compute_wall_flux()
+        assert s.stats()["long_steps"] > 0
+        err = np.abs(qw - ref).max() / np.abs(ref).max()
+        say(f"long-ray form {form}: wall flux rel err {err:.3e}")
+        assert err < 2e-5
+
+
+def test_isothermal_wall_power_equals_gas_power():
+    w = inputs.grey_box(n=12, R=16, kappa=0.7, T=900.0)
+    s = _solver(w)
+    dq, _, qw = s.compute_wall_flux()
+    q = s.split_walls(qw)
+    dx, dy, dz = np.diff(w.xf), np.diff(w.yf), np.diff(w.zf)
+    V = (dx[:, None, None] * dy[None, :, None] * dz[None, None, :]).reshape(-1)
+    A = {"x0": np.outer(dy, dz), "x1": np.outer(dy, dz), "y0": np.outer(dx, dz), "y1": np.outer(dx, dz),
+         "z0": np.outer(dx, dy), "z1": np.outer(dx, dy)}
+    wall = sum(float((A[k] * q[k]).sum()) for k in q)
+    gas = float((V * dq).sum())
+    say(f"isothermal box: wall power {wall:.6e} gas power {gas:.6e}")
+    assert wall == pytest.approx(gas, rel=1e-10)
+
+
+def test_device_outputs_and_repeat():
+    import torch
+    w = _small_channel(march="f32", nx=10, ny=8, nz=6, R=8)
+    s = _solver(w)
+    _, _, q_host = s.compute_wall_flux()
+    dev = torch.device("cuda", 0)
+    dq = torch.zeros(w.ncells, dtype=torch.float64, device=dev)
+    qw = torch.full((s.wall_elements(),), 7.0, dtype=torch.float64, device=dev)   # cleared by the compute
+    s.compute_wall_flux(dq, None, qw)
+    torch.cuda.synchronize()
+    got = qw.cpu().numpy()
+    assert np.allclose(got, q_host, rtol=1e-12, atol=0.0)
+    # a plain compute afterwards leaves the tally alone
+    s.compute(dq)
+    torch.cuda.synchronize()
+    assert np.array_equal(qw.cpu().numpy(), got)
+
+
+def test_unsupported_cases_refused():
+    w = _small_channel(march="f32", nx=10, ny=8, nz=6, R=8)
+    for case in (dict(eps_walls=(0.5, 1.0)), dict(mg_levels=2)):
+        s = _solver(w.replace(**case))
+        with pytest.raises(rmc.RmcError) as e:
+            s.compute_wall_flux()
+        assert e.value.status == rmc.RMC_UNSUPPORTED, case
+        s.compute()          # still usable
