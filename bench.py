@@ -102,9 +102,26 @@ def cpu_baseline(w, target_s):
         dt = time.perf_counter() - t0
         if dt >= target_s:
             break
-    return {"value": steps / dt, "unit": "ray-cell steps/s", "cores": threads, "kind": "oracle",
-            "sample": f"{passes} whole passes of the 64^3 channel ({w.ncells} cells x {w.R} rays), "
-                      f"{steps} steps in {dt:.1f} s"}
+    out = {"value": steps / dt, "unit": "ray-cell steps/s", "cores": threads, "kind": "oracle",
+           "sample": f"{passes} whole passes of the 64^3 channel ({w.ncells} cells x {w.R} rays), "
+                     f"{steps} steps in {dt:.1f} s"}
+    # the same oracle on one core: every 16th cell of the grid, passes for about a quarter of the time
+    import numpy as np
+    cells = np.arange(0, w.ncells, 16)
+    steps1 = passes1 = 0
+    t0 = time.perf_counter()
+    while True:
+        P = oracle.Problem(w.replace(snap=w.snap + 1 + passes1))
+        _, _, st = oracle.divergence(P, cells=cells, nthreads=1)
+        steps1 += st
+        passes1 += 1
+        dt1 = time.perf_counter() - t0
+        if dt1 >= target_s / 4:
+            break
+    out["value_1core"] = steps1 / dt1
+    out["sample_1core"] = (f"{passes1} passes over every 16th cell ({len(cells)} cells x {w.R} rays) on one thread, "
+                           f"{steps1} steps in {dt1:.1f} s")
+    return out
 
 
 def say(msg):
