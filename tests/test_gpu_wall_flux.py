@@ -4,12 +4,15 @@ energy balance (wall power = gas power); divq unchanged; the unsupported cases r
 import numpy as np
 import pytest
 
-import oracle
-from paper_1810_00188_amd import inputs, rmc
-
-from _parity import say, _solver, _small_channel
-
 pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no ROCm GPU visible", allow_module_level=True)
+
+import oracle  # noqa: E402
+from paper_1810_00188_amd import inputs, rmc  # noqa: E402
+from _parity import say, _solver, _small_channel  # noqa: E402
 
 
 def _compare(w, rel):
@@ -76,7 +79,6 @@ def test_isothermal_wall_power_equals_gas_power():
 
 
 def test_device_outputs_and_repeat():
-    import torch
     w = _small_channel(march="f32", nx=10, ny=8, nz=6, R=8)
     s = _solver(w)
     _, _, q_host = s.compute_wall_flux()
