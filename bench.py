@@ -135,9 +135,9 @@ def learned_bench(a):
     import torch
     from paper_1810_00188_amd import inputs, learned, rmc
 
-    cfg = {"channel64": dict(gen=inputs.channel64, train=8, eval=20, steps=3000, cells=16384, batch=64,
+    cfg = {"channel64": dict(gen=inputs.channel64, train=32, eval=20, steps=12000, cells=16384, batch=64,
                              rays=0, Rs=(16, 32, 64, 128)),
-           "dns256": dict(gen=inputs.dns256, train=24, eval=20, steps=10000, cells=32768, batch=16,
+           "dns256": dict(gen=inputs.dns256, train=48, eval=20, steps=20000, cells=32768, batch=16,
                           rays=255, Rs=(16, 32, 64, 128))}[a.learned]
     n_train = a.train_seeds or cfg["train"]
     n_eval = a.eval_seeds or cfg["eval"]
