@@ -135,7 +135,7 @@ def learned_bench(a):
     import torch
     from paper_1810_00188_amd import inputs, learned, rmc
 
-    cfg = {"channel64": dict(gen=inputs.channel64, train=32, eval=20, steps=12000, cells=16384, batch=64,
+    cfg = {"channel64": dict(gen=inputs.channel64, train=64, eval=20, steps=20000, cells=16384, batch=64,
                              rays=0, Rs=(16, 32, 64, 128)),
            "dns256": dict(gen=inputs.dns256, train=48, eval=20, steps=20000, cells=32768, batch=16,
                           rays=255, Rs=(16, 32, 64, 128))}[a.learned]
