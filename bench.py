@@ -70,6 +70,8 @@ def parse():
     ap.add_argument("--train-seeds", type=int, default=0, help="training fields (0: per workload)")
     ap.add_argument("--eval-seeds", type=int, default=0, help="held-out evaluation fields (0: per workload)")
     ap.add_argument("--train-steps", type=int, default=0, help="Adam steps (0: per workload)")
+    ap.add_argument("--mix-eps", type=float, default=0.1,
+                    help="weight of the plain pdf mixed into the learned one (defensive mixture)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "march_traffic.json"),
                     help="HBM bytes per march launch measured by rocprofv3 (optional)")
     return ap.parse_args()
@@ -142,7 +144,7 @@ def learned_bench(a):
     n_train = a.train_seeds or cfg["train"]
     n_eval = a.eval_seeds or cfg["eval"]
     steps = a.train_steps or cfg["steps"]
-    eps, lr = 0.1, 2e-3
+    eps, lr = a.mix_eps, 2e-3
     t_start = time.perf_counter()
     w0 = cfg["gen"](field_seed=1)
     kd = w0.kd
