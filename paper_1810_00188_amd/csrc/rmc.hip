@@ -2347,6 +2347,14 @@ struct Plan {
     bool periodic_xz = true;                // every snapshot periodic in x and z (no closed box)
     int smode = 0;
     uint32_t cont_cap = 0;
+    // device copies of the host-built tables the kernels read: the leader's buffers, or for a
+    // captured graph its own copies (later computes or traces led by the same context rewrite
+    // the leader's buffers)
+    double *d_faces = nullptr;
+    SnapDesc *d_snaps = nullptr;
+    int *d_tile_snap = nullptr;
+    uint32_t *d_border = nullptr;
+    float *d_kmin = nullptr;
 };
 
 // Host part of a compute: buffers (allocated or grown), descriptors and their upload on s.
@@ -2424,7 +2432,12 @@ template <class Real> rmc_status plan_pipeline(rmc_ctx *const *ctxs, int nsnap, 
     const size_t sz[5] = {sizeof(double) * P.nfaces, sizeof(SnapDesc) * nsnap, sizeof(int) * P.ntiles,
                           sizeof(uint32_t) * nbucket, sizeof(float) * nb * ng};
     const void *src[5] = {faces.data(), L->h_snaps.data(), tile_snap.data(), L->h_order.data(), L->h_kmin.data()};
-    void *dst[5] = {L->faces.p, L->snaps.p, L->tile_snap.p, L->border.p, L->kmin.p};
+    P.d_faces = L->faces.as<double>();
+    P.d_snaps = L->snaps.as<SnapDesc>();
+    P.d_tile_snap = L->tile_snap.as<int>();
+    P.d_border = L->border.as<uint32_t>();
+    P.d_kmin = L->kmin.as<float>();
+    void *dst[5] = {P.d_faces, P.d_snaps, P.d_tile_snap, P.d_border, P.d_kmin};
     size_t off[5], total = 0;
     for (int u = 0; u < 5; ++u) {
         off[u] = total;
@@ -2461,13 +2474,13 @@ rmc_status enqueue_pipeline(const Plan &P, double *const *divq, double *const *s
     if (EV) HIPCHK(hipEventRecord(EV->e[0], s));
     // 1-2. per-snapshot pdf and property fields
     for (int q = 0; q < nsnap; ++q)
-        if ((st = enqueue_snapshot<Real>(P.ctxs[q], P.D[q], L->faces.as<double>(), s))) return st;
+        if ((st = enqueue_snapshot<Real>(P.ctxs[q], P.D[q], P.d_faces, s))) return st;
     if (EV) HIPCHK(hipEventRecord(EV->e[1], s));
 
     // 3. allocation: histogram per tile, scan per bucket, layout, scatter
     AllocArgs AA;
-    AA.snaps = L->snaps.as<SnapDesc>();
-    AA.tile_snap = L->tile_snap.as<int>();
+    AA.snaps = P.d_snaps;
+    AA.tile_snap = P.d_tile_snap;
     AA.ntiles = P.ntiles;
     AA.tile_cells = P.tile_cells;
     AA.nb = nb; AA.ng = ng; AA.nbucket = nbucket; AA.R = R;
@@ -2491,7 +2504,7 @@ rmc_status enqueue_pipeline(const Plan &P, double *const *divq, double *const *s
                        L->bucket_total.as<uint32_t>());
     HIPCHK(hipGetLastError());
     hipLaunchKernelGGL(k_bucket_layout, dim3(1), dim3(1024), 0, s, L->bucket_total.as<uint32_t>(),
-                       L->border.as<uint32_t>(), nbucket, L->bucket_start.as<uint32_t>(), L->nchunks.as<uint32_t>());
+                       P.d_border, nbucket, L->bucket_start.as<uint32_t>(), L->nchunks.as<uint32_t>());
     HIPCHK(hipGetLastError());
     hipLaunchKernelGGL(k_chunk_map, dim3((nbucket + 3) / 4), dim3(64, 4), 0, s, L->bucket_total.as<uint32_t>(),
                        L->bucket_start.as<uint32_t>(), nbucket, L->chunk_bucket.as<uint32_t>(),
@@ -2505,8 +2518,8 @@ rmc_status enqueue_pipeline(const Plan &P, double *const *divq, double *const *s
 
     // 4. march: one wavefront per 64-ray chunk
     MarchArgs<Real> MA;
-    MA.snaps = L->snaps.as<SnapDesc>();
-    MA.faces = L->faces.as<double>();
+    MA.snaps = P.d_snaps;
+    MA.faces = P.d_faces;
     MA.nfaces = P.nfaces;
     MA.items = L->items.as<uint4>();
     MA.chunk_bucket = L->chunk_bucket.as<uint32_t>();
@@ -2521,7 +2534,7 @@ rmc_status enqueue_pipeline(const Plan &P, double *const *divq, double *const *s
     const bool segment = sizeof(Real) == 4 && P.inc_xz && P.periodic_xz;
     const int lrs = O.long_ray_steps > 0 ? O.long_ray_steps : 256;
     MA.cap = segment ? std::min(lrs, O.max_steps) : O.max_steps;
-    MA.kmin = L->kmin.as<float>();
+    MA.kmin = P.d_kmin;
     MA.cont = L->cont.as<ContRec>();
     MA.cont_count = L->cont_count.as<uint32_t>();
     MA.cont_cap = P.cont_cap;
@@ -2755,6 +2768,7 @@ struct rmc_graph {
     std::vector<std::vector<void *>> ptrs;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    DBuf faces, snaps, tile_snap, border, kmin;   // the graph's own copies of the planned tables
 };
 
 namespace {
@@ -2766,7 +2780,9 @@ std::vector<void *> buffer_ptrs(const rmc_ctx *c)
                        &c->ccdf_g, &c->ccdf_o, &c->pdf_scratch, &c->p, &c->cdf_b, &c->cdf_g, &c->W, &c->Iw,
                        &c->status, &c->field, &c->Iplane, &c->Y, &c->st, &c->hist, &c->bucket_total,
                        &c->bucket_start, &c->nchunks, &c->chunk_bucket, &c->items, &c->faces,
-                       &c->snaps, &c->tile_snap, &c->border, &c->counters, &c->red_part, &c->kmin, &c->cont, &c->cont_count};
+                       &c->snaps, &c->tile_snap, &c->border, &c->counters, &c->red_part, &c->kmin, &c->cont, &c->cont_count,
+                       &c->rbkt, &c->mgT, &c->mgX, &c->mgfield, &c->mgI, &c->dprob, &c->dstrat, &c->lpp, &c->prm,
+                       &c->musd, &c->nu_c, &c->gxs, &c->kp, &c->feat, &c->fmask, &c->bng, &c->lfaces};
     std::vector<void *> v;
     for (const DBuf *d : b) v.push_back(d->p);
     return v;
@@ -3294,14 +3310,39 @@ rmc_status rmc_graph_capture(rmc_ctx *const *ctxs, int nsnap, double *const *div
     Plan P;
     rmc_status st = dbl ? plan_pipeline<double>(ctxs, nsnap, P, s) : plan_pipeline<float>(ctxs, nsnap, P, s);
     if (st) return st;
-    HIPCHK(hipStreamSynchronize(s));
-    HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    rmc_graph *G = new (std::nothrow) rmc_graph();
+    if (!G) return fail(RMC_OUT_OF_MEMORY, "graph allocation failed");
+    {   // the graph reads its own copies of the planned tables
+        const size_t nb_ = (size_t)L->nb * L->ng;
+        const size_t sz[5] = {sizeof(double) * P.nfaces, sizeof(SnapDesc) * nsnap, sizeof(int) * P.ntiles,
+                              sizeof(uint32_t) * nb_ * 8, sizeof(float) * nb_};
+        DBuf *dst[5] = {&G->faces, &G->snaps, &G->tile_snap, &G->border, &G->kmin};
+        const void *src[5] = {P.d_faces, P.d_snaps, P.d_tile_snap, P.d_border, P.d_kmin};
+        for (int u = 0; u < 5; ++u) {
+            if ((st = dst[u]->ensure(sz[u]))) { delete G; return st; }
+            if (hipMemcpyAsync(dst[u]->p, src[u], sz[u], hipMemcpyDeviceToDevice, s) != hipSuccess) {
+                delete G;
+                return fail(RMC_DEVICE_ERROR, "copy of the planned tables failed");
+            }
+        }
+        P.d_faces = G->faces.as<double>();
+        P.d_snaps = G->snaps.as<SnapDesc>();
+        P.d_tile_snap = G->tile_snap.as<int>();
+        P.d_border = G->border.as<uint32_t>();
+        P.d_kmin = G->kmin.as<float>();
+    }
+    if (hipStreamSynchronize(s) != hipSuccess) { delete G; return fail(RMC_DEVICE_ERROR, "hipStreamSynchronize failed"); }
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        delete G;
+        return fail(RMC_DEVICE_ERROR, "hipStreamBeginCapture failed");
+    }
     st = dbl ? enqueue_pipeline<double>(P, divq, se, s, nullptr) : enqueue_pipeline<float>(P, divq, se, s, nullptr);
     hipGraph_t graph = nullptr;
     const hipError_t ec = hipStreamEndCapture(s, &graph);
     if (st || ec != hipSuccess) {
         if (graph) (void)hipGraphDestroy(graph);
         (void)hipGetLastError();
+        delete G;
         if (st) return st;
         return fail(RMC_DEVICE_ERROR, "hipStreamEndCapture failed: %s", hipGetErrorString(ec));
     }
@@ -3310,13 +3351,8 @@ rmc_status rmc_graph_capture(rmc_ctx *const *ctxs, int nsnap, double *const *div
     if (ei != hipSuccess) {
         (void)hipGraphDestroy(graph);
         (void)hipGetLastError();
+        delete G;
         return fail(RMC_DEVICE_ERROR, "hipGraphInstantiate failed: %s", hipGetErrorString(ei));
-    }
-    rmc_graph *G = new (std::nothrow) rmc_graph();
-    if (!G) {
-        (void)hipGraphExecDestroy(exec);
-        (void)hipGraphDestroy(graph);
-        return fail(RMC_OUT_OF_MEMORY, "graph allocation failed");
     }
     G->device = L->device;
     G->ctxs.assign(ctxs, ctxs + nsnap);
@@ -3350,12 +3386,10 @@ void rmc_graph_destroy(rmc_graph *G)
 {
     if (!G) return;
     for (rmc_ctx *c : G->ctxs) --c->graphs;
-    {
-        DeviceGuard g(G->device);
-        if (G->exec) (void)hipGraphExecDestroy(G->exec);
-        if (G->graph) (void)hipGraphDestroy(G->graph);
-    }
-    delete G;
+    DeviceGuard g(G->device);
+    if (G->exec) (void)hipGraphExecDestroy(G->exec);
+    if (G->graph) (void)hipGraphDestroy(G->graph);
+    delete G;   // its table copies are released with the device current
 }
 
 rmc_status rmc_get_ray_values(rmc_ctx *c, const int64_t *cells, int ncell, double *Y, int32_t *steps, void *stream)

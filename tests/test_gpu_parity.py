@@ -426,6 +426,38 @@ def test_graph_replays_match_eager(variant):
     g.close()
 
 
+def test_graph_keeps_its_tables_when_the_leader_works_eagerly():
+    """A captured 2-snapshot graph reads its own copies of the planned tables (snapshot
+    descriptors, faces, tile map, bucket order, kappa bounds): a trace, a single-snapshot
+    compute and a wall-flux compute led by its first context between replays (which rewrite
+    that context's tables) leave every replay equal to an eager compute."""
+    ws = [_small_channel(march="f32", nx=8 + 4 * q, ny=6, nz=6, R=8, field_seed=q).replace(snap=q) for q in range(2)]
+    kd = ws[0].kd
+    ws = [x.replace(kd=kd) for x in ws]
+    say("graph tables vs eager work of the leader")
+    dev = torch.device("cuda", 0)
+    solvers = [_solver(x, device_fields=True) for x in ws]
+    outs = [torch.zeros(x.ncells, dtype=torch.float64, device=dev) for x in ws]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        g = rmc.Graph(solvers, outs)
+    refs = [_solver(x).compute()[0] for x in ws]
+    for rep in range(3):
+        if rep == 0:
+            solvers[0].trace(np.arange(5))
+        elif rep == 1:
+            solvers[0].compute()
+        else:
+            solvers[0].compute_wall_flux()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            g.launch()
+        stream.synchronize()
+        for q in range(2):
+            assert np.array_equal(outs[q].cpu().numpy(), refs[q]), (rep, q)
+    g.close()
+
+
 def test_gather_probe_reports_the_access_pattern_rate():
     """The measurement aid of the roofline: needs a previous FP32 compute, then returns the
     kernel time and the bytes of ncells x R lanes x steps gathers (12 bytes per step)."""
