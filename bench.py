@@ -139,7 +139,7 @@ def learned_bench(a):
 
     cfg = {"channel64": dict(gen=inputs.channel64, train=64, eval=20, steps=20000, cells=16384, batch=64,
                              rays=0, Rs=(16, 32, 64, 128)),
-           "dns256": dict(gen=inputs.dns256, train=96, eval=20, steps=60000, cells=32768, batch=16,
+           "dns256": dict(gen=inputs.dns256, train=96, eval=20, steps=120000, cells=32768, batch=16,
                           rays=255, Rs=(16, 32, 64, 128))}[a.learned]
     n_train = a.train_seeds or cfg["train"]
     n_eval = a.eval_seeds or cfg["eval"]
