@@ -44,7 +44,9 @@ typedef enum {
     RMC_INVALID_ARG = 1,     /* bad pointer, size or enum value */
     RMC_BAD_STATE = 2,       /* a required set_* call is missing */
     RMC_OUT_OF_RANGE = 3,    /* temperature outside the table, NaN, negative mole fraction */
-    RMC_UNSUPPORTED = 4,     /* e.g. wall emissivity other than 1 */
+    RMC_UNSUPPORTED = 4,     /* a combination this build does not run, e.g. the learned
+                                allocation in a closed box, or the wall flux with a reflecting
+                                wall or the multigrid march */
     RMC_DEVICE_ERROR = 5,    /* a HIP runtime call failed */
     RMC_OUT_OF_MEMORY = 6
 } rmc_status;
@@ -142,7 +144,9 @@ typedef struct {
     double p;                /* probability p(n, g, o) the ray was drawn with */
     int32_t n, g, o, k;      /* band, g-point, octant, ordinal among equal (n, g, o) in the cell */
     int32_t steps;           /* ray-cell steps */
-    int32_t end;             /* 0: tau <= tol, 1: wall y0, 2: wall y1, 3: step cap */
+    int32_t end;             /* how the ray ended: 0 tau <= tol, 3 step cap, or the black wall
+                                that stopped it: 1 y0, 2 y1, 4 x0, 5 x1, 6 z0, 7 z1 (x and z walls
+                                only in a closed box, rmc_set_box_walls) */
 } rmc_ray_record;
 
 /* Create a context on HIP device `device` (>= 0).  Allocates nothing large. */
@@ -375,15 +379,16 @@ typedef struct {
 } rmc_train_batch;
 
 /* Loss of the batch under the current parameters and its gradient (host float
- * grad[RMC_MLP_PARAMS], nullable), from the FP32 training kernels.  The loss is averaged over
- * the cells with samples; for cell c, i over its rays,
- *   L_c = [mean_i h_i^2 / (p0_i p_c(s_i))] [mean_i c_i p_c(s_i) / p0_i]
- *         / ([mean_i (h_i / p0_i)^2] [mean_i c_i])
- * (the cost factors are 1 without ray_cost): the second moment of the cell's estimator were
- * its rays drawn from p_c times the expected cost of a ray, both estimated without bias from
- * the plain rays, relative to the plain allocation's.  Its minimiser over pdfs is p_s
- * proportional to sqrt(E[h^2 | s] / E[c | s]): the allocation that reaches a given variance in
- * the least time.  Synchronises.  RMC_INVALID_ARG if the samples are not sorted by cell. */
+ * grad[RMC_MLP_PARAMS], nullable), from the FP32 training kernels.  Per cell c with samples
+ * (i over its rays, p_c the learned pdf above, c_i = ray_cost[i] or 1 without ray_cost):
+ *   M_c(p) = mean_i h_i^2 / (p0_i p(s_i)),   C_c(p) = mean_i c_i p(s_i) / p0_i,
+ * unbiased estimates, from the plain rays, of the second moment of the cell's ray value and of
+ * the expected cost of a ray were its rays drawn from p; and over the batch the ratio
+ *   L = [sum_c M_c(p_c)] [sum_c C_c(p_c)] / ([sum_c M_c(p0)] [sum_c C_c(p0)])
+ * (C = 1 without ray_cost): the work to reach a given RMS error of the whole field (squared
+ * error sum_c Var_c / R, work R sum_c C_c) relative to the plain allocation's.  For one cell
+ * its minimiser over pdfs is p_s proportional to sqrt(E[h^2 | s] / E[c | s]).  Synchronises.
+ * RMC_INVALID_ARG if the samples are not sorted by cell. */
 rmc_status rmc_train_grad(rmc_ctx *ctx, const rmc_train_batch *batch, double *loss, float *grad, void *stream);
 /* One Adam step (Kingma & Ba; beta 0.9 / 0.999, eps 1e-8) of learning rate lr on the batch;
  * loss (nullable) is the loss before the step.  Synchronises. */
