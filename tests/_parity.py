@@ -35,21 +35,21 @@ def _wall_scale(w, ref, cells):
     from oracle.closed_forms import table_lerp
     kd = w.kd
     cells = np.asarray(cells)
-    Tc = w.T[cells][:, None]
     n, g = ref["n"], ref["g"]
     Tw = list(w.T_walls) + (list(w.T_walls_x) + list(w.T_walls_z) if getattr(w, "closed", False) else [])
     I_all = table_lerp(kd.Ib, kd.T0, kd.dT, np.concatenate([w.T, Tw]))   # [nb, nc + walls]
     Imax, Imin = I_all.max(axis=1), I_all.min(axis=1)
-    Isrc = np.empty(n.shape)
+    # source-cell table position, broadcast over the cell's rays
+    u = (np.asarray(w.T, dtype=np.float64)[cells] - kd.T0) / kd.dT
+    t = np.minimum(np.floor(u).astype(np.int64), kd.nT - 2)[:, None]
+    f = (u - np.floor(u).clip(max=kd.nT - 2))[:, None]
+    Ib = np.asarray(kd.Ib, dtype=np.float64)
+    Isrc = Ib[n, t] + f * (Ib[n, t + 1] - Ib[n, t])
     kap = np.zeros(n.shape)
-    for b in range(kd.nb):
-        m = n == b
-        Isrc[m] = np.broadcast_to(table_lerp(kd.Ib[b], kd.T0, kd.dT, Tc), n.shape)[m]
-        for gg in range(kd.ng):
-            mg = m & (g == gg)
-            for sp in range(kd.ns):
-                ks = table_lerp(kd.k[sp, b, gg].astype(float), kd.T0, kd.dT, Tc)
-                kap[mg] += np.broadcast_to(w.X[sp][cells][:, None] * ks, n.shape)[mg]
+    for sp in range(kd.ns):
+        k = np.asarray(kd.k[sp], dtype=np.float64)
+        lo, hi = k[n, g, t], k[n, g, t + 1]
+        kap += np.asarray(w.X[sp], dtype=np.float64)[cells][:, None] * (lo + f * (hi - lo))
     dI = np.maximum(np.abs(Imax[n] - Isrc), np.abs(Isrc - Imin[n]))
     wgt = 4 * np.pi * kd.dnu[n] * kd.wg[g] / (8 * ref["p"])
     return wgt * kap * dI

@@ -78,8 +78,9 @@ def test_features_match_oracle():
     assert np.array_equal(mask, m.astype(np.uint8))
 
 
-def test_logits_within_bf16_bound():
-    w = _workload()
+@pytest.mark.parametrize("tables", [(5, 3), (100, 16)])
+def test_logits_within_bf16_bound(tables):
+    w = _workload(nb=tables[0], ng=tables[1])
     say(f"logits {w.name}")
     s = _solver(w)
     feat, mask = s.features()
@@ -120,10 +121,12 @@ def _plain_cdf_inverse_check(P, u0, u1, u2, nb, ng):
     return (n * ng + g) * 8 + o, min(np.abs(cb - u0).min(), np.abs(cg - u1).min(), np.abs(co - u2).min())
 
 
-@pytest.mark.parametrize("tables", [(5, 3), (20, 7)])
+@pytest.mark.parametrize("tables", [(5, 3), (20, 7), (100, 16)])
 def test_learned_draws_and_rays_match_oracle(tables):
-    """Draws and ray values of the learned mode; the larger table set puts several cells'
-    logits in one workgroup's LDS (12 cells of 1120 strata)."""
+    """Draws and ray values of the learned mode.  The table sets cover the kernel's layouts:
+    5 x 3 and 20 x 7 put several cells' logits in one workgroup's LDS (16 cells of 120, 12
+    cells of 1120 strata); 100 x 16, the DNS-size tables (12,800 strata per cell), leaves room
+    for one cell per workgroup with 100-band sums."""
     eps = 0.15
     w = _workload(R=24, nb=tables[0], ng=tables[1])
     say(f"learned sampling {w.name}")
@@ -222,6 +225,42 @@ def test_training_gradient_matches_oracle(with_cost):
     with pytest.raises(rmc.RmcError) as e:
         s.train_grad(b2)
     assert e.value.status == rmc.RMC_INVALID_ARG
+
+
+def test_adam_steps_match_oracle():
+    """Two rmc_train_step calls from a freshly set allocator (zero Adam moments) against
+    oracle.mlp.adam_step (Kingma & Ba) fed the gradient rmc_train_grad returns at the same
+    parameters (the training kernels are deterministic, so it is the gradient the step uses).
+    Step 1 checks the bias-corrected update from zero moments, step 2 the moment recursions
+    (the reference carries its own FP64 moments).  Bar per parameter: FP32 rounding of the
+    update and of the stored parameter, 2^-23 |v| + 1e-5 lr (1 + |update| / lr)."""
+    eps = 0.1
+    lr = float(np.float32(2e-3))
+    w = _workload(R=16)
+    say(f"adam steps {w.name}")
+    s = _solver(w, sampling=rmc.SAMPLING_PLAIN, mix_eps=eps)
+    feat, _ = s.features()
+    params, mu, sd, nu_c, gx = _network(w, feat, out_scale=3.0)
+    s.set_allocator(params, mu, sd, nu_c, gx)
+    tens, H = _training_batch(w, s, ncell=40)
+    cost = torch.from_numpy(np.random.default_rng(6).uniform(2.0, 40.0, len(H["h"]))).to("cuda:0")
+    batch, keep = rmc.train_batch(*tens, ray_cost=cost)
+    m = np.zeros(rmc.MLP_PARAMS)
+    q = np.zeros(rmc.MLP_PARAMS)
+    for t in (1, 2):
+        cur = s.get_allocator().astype(np.float64)
+        loss_g, g = s.train_grad(batch)
+        loss_s = s.train_step(batch, lr)
+        got = s.get_allocator().astype(np.float64)
+        ref, m, q = mlp.adam_step(cur, g.astype(np.float64), m, q, t, lr=lr)
+        upd = np.abs(ref - cur)
+        bar = 2.0 ** -23 * np.abs(ref) + 1e-5 * (lr + upd)
+        err = np.abs(got - ref)
+        say(f"adam step {t}: loss {loss_s:.6f}, max |update| / lr {upd.max() / lr:.3f}, "
+            f"max err / bar {np.max(err / bar):.3f}")
+        assert loss_s == loss_g
+        assert np.all(err <= bar)
+        assert np.count_nonzero(upd) > rmc.MLP_PARAMS // 2
 
 
 def test_training_lowers_the_loss():

@@ -14,8 +14,8 @@ if not torch.cuda.is_available():
 import oracle  # noqa: E402
 from paper_1810_00188_amd import inputs, rmc  # noqa: E402
 
-from _parity import (TOL64, _check_fp32_rays, _check_fp64_rays, _small_channel,  # noqa: E402
-                     _solver, say)
+from _parity import (TOL32, TOL64, _check_fp32_rays, _check_fp64_rays, _small_channel,  # noqa: E402
+                     _solver, _wall_scale, say)
 
 
 # ----------------------------------------------------------------------- spectral pdf
@@ -91,8 +91,10 @@ def test_trace_fp32_within_1e5():
 
 def test_channel64_sampled_production_launch():
     """Non-grey channel at full size (64^3, 20 bands x 7 g, R = 32, FP32 march, FP64 sums),
-    in the launch configuration the benchmark times: sampled cells' ray slots against the
-    oracle, and all cells' estimates against the oracle's full run within FP32 tolerance."""
+    in the launch configuration the benchmark times: every ray slot of all 262,144 cells
+    against the oracle's trace (per-ray FP32 bar), and every cell estimate and standard error
+    against the oracle's own full run (oracle.divergence) within the mean, respectively the
+    propagated, per-ray bar of the cell's rays."""
     w = inputs.channel64()
     say(f"channel64 {w.name}")
     s = _solver(w, device_fields=True)
@@ -100,19 +102,32 @@ def test_channel64_sampled_production_launch():
     se = torch.zeros_like(dq)
     s.compute(dq, se)
     torch.cuda.synchronize()
-    rng = np.random.default_rng(5)
     P = oracle.Problem(w)
-    steps_all = oracle.trace_cells(P, np.arange(w.ncells))["steps"]
-    longest = np.argsort(-steps_all.max(axis=1))[:64]          # cells holding the longest rays
-    cells = np.unique(np.concatenate([rng.choice(w.ncells, 300, replace=False), longest,
-                                      [0, w.ncells - 1]]))
-    Y, S = s.ray_values(cells)
+    cells = np.arange(w.ncells)
     ref = oracle.trace_cells(P, cells)
-    say(f"channel64 longest ray {steps_all.max()} steps")
+    say(f"channel64 longest ray {ref['steps'].max()} steps")
+    Y, S = s.ray_values(cells)
     _check_fp32_rays(w, cells, Y, S, ref)
+    # cell estimates: the mean of R rays, each within its per-ray bar b_r, is within mean_r b_r
+    # of the oracle's mean; the standard error (a 1-Lipschitz function of the centred ray
+    # vector in the l2 norm, over sqrt(R (R - 1))) within ||b||_2 / sqrt(R (R - 1))
+    thr = w.tol * _wall_scale(w, ref, cells)
+    same = S == ref["steps"]
+    b = TOL32 * ref["absY"] + np.where(same, thr * (2.0 ** -52 / w.tol), 2.0 * thr)
+    rdq, rse, rsteps = oracle.divergence(P)
+    got, got_se = dq.cpu().numpy(), se.cpu().numpy()
+    R = w.R
+    bar_q = b.mean(axis=1) * (1 + 1e-9) + 1e-300
+    bar_se = np.sqrt((b ** 2).sum(axis=1) / (R * (R - 1))) * (1 + 1e-9) + 1e-300
+    eq, ese = np.abs(got - rdq), np.abs(got_se - rse)
+    rms = np.sqrt(np.mean(rdq ** 2))
+    say(f"channel64 cells: max |dq - oracle| / bar {np.max(eq / bar_q):.3f}, / rms(q) {eq.max() / rms:.2e}; "
+        f"max |se - oracle| / bar {np.max(ese / bar_se):.3f}")
+    assert np.all(eq <= bar_q) and np.all(ese <= bar_se)
     st = s.stats()
-    say(f"channel64 stats {st}")
+    say(f"channel64 stats {st}; oracle steps {rsteps}")
     assert st["rays"] == w.ncells * w.R
+    assert abs(st["steps"] - rsteps) <= np.sum(np.abs(S - ref["steps"]))
 
 
 @pytest.mark.parametrize("after,form", [(1, 0), (4, 0), (37, 0), (1, 1), (37, 1), (1, 2), (37, 2)])
