@@ -393,6 +393,16 @@ rmc_status rmc_train_grad(rmc_ctx *ctx, const rmc_train_batch *batch, double *lo
 /* One Adam step (Kingma & Ba; beta 0.9 / 0.999, eps 1e-8) of learning rate lr on the batch;
  * loss (nullable) is the loss before the step.  Synchronises. */
 rmc_status rmc_train_step(rmc_ctx *ctx, const rmc_train_batch *batch, float lr, double *loss, void *stream);
+/* nstep Adam steps in one call: step i takes batches[i] (device data as for rmc_train_step,
+ * every pointer valid until the call returns) with learning rate lr[i] (host array); losses
+ * (host, nullable) receives the loss of each batch before its step.  The steps are enqueued
+ * back to back on `stream` with no synchronisation in between; the call synchronises once at
+ * the end.  The host checks of every batch run before anything is enqueued; a batch that
+ * fails the device-side sample checks (unsorted, out of range, more than 1024 rays in a cell)
+ * makes the call return that error after all steps ran (the parameters then hold the steps'
+ * result and should be reset with rmc_set_allocator). */
+rmc_status rmc_train_steps(rmc_ctx *ctx, const rmc_train_batch *batches, int nstep, const float *lr,
+                           double *losses, void *stream);
 
 /* Counters and phase timings of the last compute and accumulated since the last reset.
  * Waits for every compute enqueued so far to finish. */

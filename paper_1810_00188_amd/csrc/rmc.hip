@@ -1793,7 +1793,7 @@ struct rmc_ctx {
     bool have_alloc = false;
     int adam_t = 0;
     DBuf prm, musd, nu_c, gxs, kp, feat, fmask, bng, lfaces, dstrat, dprob, adam1, adam2, lpp;
-    DBuf tr_feat, tr_mask, tr_act, tr_del, tr_dz, tr_Lc, tr_scal, tr_err, tr_part, tr_grad;
+    DBuf tr_feat, tr_mask, tr_act, tr_del, tr_dz, tr_Lc, tr_scal, tr_err, tr_part, tr_grad, tr_loss;
     // pdf and fields of the last compute
     DBuf pdf_scratch, p, cdf_b, cdf_g, W, Iw, status;
     DBuf field, Iplane;     // kappa planes (march precision) and FP64 intensity planes

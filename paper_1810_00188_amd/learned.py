@@ -107,23 +107,64 @@ def batch_of(run: RunSamples, sel: np.ndarray, use_cost: bool = True):
                            ray_cost=run.cost[ridx].contiguous() if use_cost else None)
 
 
+def shuffle_run(run: RunSamples, rng) -> list:
+    """Reorder a run's cells (with their rays) by a random permutation, in place; returns the
+    tensors it held before (kept alive by the caller while queued work may still read them)."""
+    import torch
+    dev = run.feat.device
+    perm = torch.from_numpy(rng.permutation(run.ncell)).to(dev)
+    ridx = (perm[:, None] * run.R + torch.arange(run.R, device=dev)[None, :]).reshape(-1)
+    old = [run.feat, run.mask, run.strata, run.h, run.p0, run.cost]
+    run.feat, run.mask = run.feat[perm].contiguous(), run.mask[perm].contiguous()
+    run.strata, run.h, run.p0 = run.strata[ridx].contiguous(), run.h[ridx].contiguous(), run.p0[ridx].contiguous()
+    if run.cost is not None:
+        run.cost = run.cost[ridx].contiguous()
+    return old
+
+
 def train(s: rmc.Solver, runs: List[RunSamples], steps: int, lr: float, batch_cells: int, seed: int = 0,
           log: Optional[Callable[[str], None]] = None, lr_final: Optional[float] = None,
-          use_cost: bool = True) -> List[float]:
-    """Adam steps on batches of cells drawn from the runs in turn; the learning rate decays
-    geometrically to lr_final (default lr / 10).  With use_cost the loss is the
-    work-normalised second moment (the rays' costs weigh in).  Returns the batch losses."""
+          use_cost: bool = True, chunk: int = 256) -> List[float]:
+    """Adam steps on batches of batch_cells cells taken from the runs in turn; each run's cells
+    are visited in a random order, reshuffled at every pass over the run (a batch is then a
+    contiguous slice of the run: no per-step gathers).  The learning rate decays geometrically
+    to lr_final (default lr / 10).  With use_cost the loss is the work-normalised second
+    moment (the rays' costs weigh in).  The steps go to the library `chunk` at a time
+    (rmc_train_steps: no synchronisation between them).  Returns the batch losses."""
+    import torch
     rng = np.random.default_rng(seed)
     lr_final = lr / 10.0 if lr_final is None else lr_final
-    losses = []
-    for t in range(steps):
-        run = runs[t % len(runs)]
-        sel = np.sort(rng.choice(run.ncell, min(batch_cells, run.ncell), replace=False))
-        batch, keep = batch_of(run, sel, use_cost)
-        a = lr * (lr_final / lr) ** (t / max(steps - 1, 1))
-        losses.append(s.train_step(batch, a))
-        if log and (t % max(steps // 10, 1) == 0 or t == steps - 1):
-            log(f"train step {t}: loss {np.mean(losses[-max(steps // 10, 1):]):.4f} lr {a:.2e}")
+    B = {id(r): min(batch_cells, r.ncell) for r in runs}
+    pos = {id(r): None for r in runs}
+    cell_of = {}
+    losses: List[float] = []
+    t = 0
+    while t < steps:
+        n = min(chunk, steps - t)
+        batches, keep, lrs = [], [], []
+        for q in range(t, t + n):
+            run = runs[q % len(runs)]
+            b = B[id(run)]
+            if pos[id(run)] is None or pos[id(run)] + b > run.ncell:
+                keep.append(shuffle_run(run, rng))
+                pos[id(run)] = 0
+            a0 = pos[id(run)]
+            pos[id(run)] = a0 + b
+            key = (b, run.R)
+            if key not in cell_of:
+                cell_of[key] = torch.arange(b, device=run.feat.device, dtype=torch.int32).repeat_interleave(run.R)
+            r0, r1 = a0 * run.R, (a0 + b) * run.R
+            bt, kp = rmc.train_batch(run.feat[a0:a0 + b], run.mask[a0:a0 + b], run.pplain, cell_of[key],
+                                     run.strata[r0:r1], run.h[r0:r1], run.p0[r0:r1],
+                                     ray_cost=run.cost[r0:r1] if use_cost else None)
+            batches.append(bt)
+            keep.append(kp)
+            lrs.append(lr * (lr_final / lr) ** (q / max(steps - 1, 1)))
+        losses.extend(s.train_steps(batches, lrs).tolist())
+        t += n
+        if log and (t // chunk) % max(steps // chunk // 10, 1) == 0 or (log and t == steps):
+            m = max(min(steps // 10, len(losses)), 1)
+            log(f"train step {t}: loss {np.mean(losses[-m:]):.4f} lr {lrs[-1]:.2e}")
     return losses
 
 

@@ -107,6 +107,7 @@ SIGNATURES = {
     "rmc_get_ray_draws": (C.c_int, [_VP, _VP, C.c_int, _VP, _VP, _VP]),
     "rmc_train_grad": (C.c_int, [_VP, C.POINTER(TrainBatch), C.POINTER(C.c_double), _VP, _VP]),
     "rmc_train_step": (C.c_int, [_VP, C.POINTER(TrainBatch), C.c_float, C.POINTER(C.c_double), _VP]),
+    "rmc_train_steps": (C.c_int, [_VP, C.POINTER(TrainBatch), C.c_int, _VP, _VP, _VP]),
 }
 
 
@@ -446,6 +447,18 @@ class Solver:
         loss = C.c_double()
         _check(LIB.rmc_train_step(self.h, C.byref(batch), float(lr), C.byref(loss), _stream(stream)))
         return loss.value
+
+    def train_steps(self, batches, lrs, stream=None) -> np.ndarray:
+        """rmc_train_steps: one Adam step per batch (a sequence of TrainBatch, whose device data
+        the caller keeps alive), learning rates lrs; returns the loss before each step."""
+        n = len(batches)
+        arr = (TrainBatch * max(n, 1))(*batches)
+        lr = np.ascontiguousarray(lrs, dtype=np.float32)
+        if lr.shape != (n,):
+            raise ValueError("one learning rate per batch")
+        losses = np.zeros(max(n, 1))
+        _check(LIB.rmc_train_steps(self.h, arr, n, lr.ctypes.data, losses.ctypes.data, _stream(stream)))
+        return losses[:n]
 
     def autotune(self, reps: int = 3, cache_path: Optional[str] = None, stream=None) -> dict:
         """rmc_autotune: time the schedule candidates on the current workload, keep the
