@@ -1,18 +1,26 @@
-"""Benchmark: ray-cell steps per second of the ERMC radiative heat source on one MI355X.
+"""Benchmark: ray-cell steps per second of the ERMC radiative heat source on one MI355X, and
+the wall time to 1 % RMS error of the learned ray allocation against the plain one.
 
 One step = one full pass of the hot path on one synthetic snapshot whose fields are already
 resident in HBM: ingest of the temperature and mole-fraction fields, T_max spectral pdf,
 property fields, ray allocation and bucketing, march, per-cell reduction (FP64).
 
-Workload: the non-grey channel -- 64 x 64 x 64 cells on the 4 pi x 2 x 2 pi box, periodic x/z,
-black walls at 300 K, T = 600 + 400 (1 - y^2) K with 8 Fourier modes of 5 %, H2O at 0.1,
-seeded synthetic correlated-k tables with 20 bands x 7 g-points, 32 rays per cell, FP32 march
-(double ray geometry and intensity differences), FP64 per-cell sums.
+Default workload: the DNS-size snapshot -- 256 x 128 x 128 cells on the 4 pi x 2 x 2 pi box
+with tanh-stretched y (gamma 2), periodic x/z, black walls at 300 K, T = 600 + 400 (1 - y^2) K
+with 64 Fourier modes of 10 %, H2O and CO2 at 0.1 each with independent +-20 % fluctuations,
+seeded synthetic correlated-k tables with 100 bands x 16 g-points rounded to BF16, 64 rays per
+cell, FP32 march (double ray geometry and intensity differences), FP64 per-cell sums.
+`--workload channel64` runs the 64^3 non-grey channel instead.
 
 Prints one JSON line.  The roofline is that of the dominant kernel, the lane march
 (k_march_lane): its duration is the HIP-event time the library records around its launch on
 the compute stream, summed over the timed steps; its algorithmic bytes count the steps it
-takes (all steps minus those of the long-ray kernel, which the library counts).
+takes (all steps minus those of the long-ray kernel, which the library counts) at 8 bytes per
+ray-cell step (an FP32 kappa_{n,g} and an FP32 I_n value of the cell) plus 12 bytes per ray
+(an 8-byte work item and a 4-byte ray value).  The kernel itself gathers an FP64 intensity
+(12 bytes per step) and moves 16-byte items and 8-byte slots; that figure is reported beside.
+The `learned` block evaluates the allocation network committed with the package against the
+plain allocation on held-out fields of the same generator.
 """
 import argparse
 import json
@@ -25,17 +33,28 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes of the march: per ray-cell step one FP32 kappa_{n,g} and one FP64 I_n
-# gather; per ray one 16-byte work item read, one FP32 ray value and one 32-bit step count write
-BYTES_PER_STEP = 4 + 8
-BYTES_PER_RAY = 16 + 4 + 4
+# algorithmic bytes of the march: per ray-cell step one FP32 kappa_{n,g} and one FP32 I_n
+# value of the cell; per ray an 8-byte work item and a 4-byte ray value
+BYTES_PER_STEP = 4 + 4
+BYTES_PER_RAY = 8 + 4
+# what the kernel moves: an FP32 kappa and an FP64 intensity per step, a 16-byte work item and
+# an 8-byte slot record {value, steps | end} per ray
+KERNEL_BYTES_PER_STEP = 4 + 8
+KERNEL_BYTES_PER_RAY = 16 + 8
+L2_PER_XCD_MB = 4.0
+MALL_MB = 256.0
+ALLOCATOR_DIR = os.path.join(ROOT, "paper_1810_00188_amd", "allocators")
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", choices=["dns256", "channel64"], default="dns256",
+                    help="throughput workload (default: the DNS-size snapshot)")
+    ap.add_argument("--learned-fields", type=int, default=5,
+                    help="held-out fields of the learned-vs-plain block of the throughput line (0: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle baseline sample (0 disables it)")
     ap.add_argument("--long-ray-steps", type=int, default=0,
@@ -70,6 +89,9 @@ def parse():
     ap.add_argument("--train-seeds", type=int, default=0, help="training fields (0: per workload)")
     ap.add_argument("--eval-seeds", type=int, default=0, help="held-out evaluation fields (0: per workload)")
     ap.add_argument("--train-steps", type=int, default=0, help="Adam steps (0: per workload)")
+    ap.add_argument("--batch-cells", type=int, default=0, help="cells per Adam step (0: per workload)")
+    ap.add_argument("--save-allocator", action="store_true",
+                    help="store the trained network with the package (allocators/<workload>.npz)")
     ap.add_argument("--mix-eps", type=float, default=0.1,
                     help="weight of the plain pdf mixed into the learned one (defensive mixture)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "march_traffic.json"),
@@ -88,41 +110,39 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def cpu_baseline(w, target_s):
-    """The oracle, as it stands, on whole passes over the same workload, repeated with fresh
-    snapshot numbers (fresh random streams) until about target_s seconds have elapsed."""
+def cpu_baseline(w, target_s, stride=1, stride_1core=16):
+    """The oracle, as it stands, on a bounded sample of the same workload: every stride-th cell
+    of the grid (all R rays of each) on all host threads, in passes with fresh snapshot numbers
+    (fresh random streams) until about target_s seconds have elapsed (at least one), then every
+    stride_1core-th cell on one thread for about a quarter of that."""
+    import numpy as np
     import oracle
     threads = oracle.max_threads()
-    steps = 0
-    passes = 0
-    t0 = time.perf_counter()
-    while True:
-        P = oracle.Problem(w.replace(snap=w.snap + 1 + passes))
-        _, _, st = oracle.divergence(P, nthreads=threads)
-        steps += st
-        passes += 1
-        dt = time.perf_counter() - t0
-        if dt >= target_s:
-            break
+
+    def run(cells, nthreads, budget):
+        steps = passes = 0
+        t0 = time.perf_counter()
+        while True:
+            P = oracle.Problem(w.replace(snap=w.snap + 1 + passes))
+            _, _, st = oracle.divergence(P, cells=cells, nthreads=nthreads)
+            steps += st
+            passes += 1
+            dt = time.perf_counter() - t0
+            if dt >= budget:
+                return steps, passes, dt
+
+    cells = None if stride == 1 else np.arange(0, w.ncells, stride)
+    nsel = w.ncells if cells is None else len(cells)
+    steps, passes, dt = run(cells, threads, target_s)
+    what = "whole grid" if stride == 1 else f"every {stride}th cell"
     out = {"value": steps / dt, "unit": "ray-cell steps/s", "cores": threads, "kind": "oracle",
-           "sample": f"{passes} whole passes of the 64^3 channel ({w.ncells} cells x {w.R} rays), "
-                     f"{steps} steps in {dt:.1f} s"}
-    # the same oracle on one core: every 16th cell of the grid, passes for about a quarter of the time
-    import numpy as np
-    cells = np.arange(0, w.ncells, 16)
-    steps1 = passes1 = 0
-    t0 = time.perf_counter()
-    while True:
-        P = oracle.Problem(w.replace(snap=w.snap + 1 + passes1))
-        _, _, st = oracle.divergence(P, cells=cells, nthreads=1)
-        steps1 += st
-        passes1 += 1
-        dt1 = time.perf_counter() - t0
-        if dt1 >= target_s / 4:
-            break
+           "sample": f"{passes} pass(es) of the same workload over {what} ({nsel} of {w.ncells} cells x {w.R} "
+                     f"rays, all {threads} host threads), {steps} steps in {dt:.1f} s"}
+    cells1 = np.arange(0, w.ncells, stride_1core)
+    steps1, passes1, dt1 = run(cells1, 1, target_s / 4)
     out["value_1core"] = steps1 / dt1
-    out["sample_1core"] = (f"{passes1} passes over every 16th cell ({len(cells)} cells x {w.R} rays) on one thread, "
-                           f"{steps1} steps in {dt1:.1f} s")
+    out["sample_1core"] = (f"{passes1} pass(es) over every {stride_1core}th cell ({len(cells1)} cells x {w.R} rays) "
+                           f"on one thread, {steps1} steps in {dt1:.1f} s")
     return out
 
 
@@ -137,10 +157,10 @@ def learned_bench(a):
     import torch
     from paper_1810_00188_amd import inputs, learned, rmc
 
-    cfg = {"channel64": dict(gen=inputs.channel64, train=64, eval=20, steps=20000, cells=16384, batch=64,
+    cfg = {"channel64": dict(gen=inputs.channel64, train=64, eval=20, steps=12000, cells=16384, batch=256,
                              rays=0, Rs=(16, 32, 64, 128)),
-           "dns256": dict(gen=inputs.dns256, train=96, eval=20, steps=120000, cells=32768, batch=16,
-                          rays=255, Rs=(16, 32, 64, 128))}[a.learned]
+           "dns256": dict(gen=inputs.dns256, train=200, eval=20, steps=40000, cells=65536, batch=256,
+                          rays=0, Rs=(16, 32, 64, 128))}[a.learned]
     n_train = a.train_seeds or cfg["train"]
     n_eval = a.eval_seeds or cfg["eval"]
     steps = a.train_steps or cfg["steps"]
@@ -166,9 +186,21 @@ def learned_bench(a):
     mu, sd = learned.standardisation(feats, kd)
     s.set_allocator(learned.init_params(0), mu, sd, nu_c, gx)
     t_train = time.perf_counter()
-    losses = learned.train(s, runs, steps, lr, cfg["batch"], log=say, use_cost=not a.no_cost)
+    batch_cells = a.batch_cells or cfg["batch"]
+    losses = learned.train(s, runs, steps, lr, batch_cells, log=say, use_cost=not a.no_cost)
     t_train = time.perf_counter() - t_train
     params = s.get_allocator()
+    curve = [float(np.mean(losses[max(0, q - 200):q + 1])) for q in
+             sorted(set([min(len(losses) - 1, int(len(losses) * f)) for f in (0.0, 0.05, 0.1, 0.25, 0.5, 0.75, 1.0)]))]
+    info = {"workload": a.learned, "train_fields": n_train, "train_field_seeds": [1, n_train],
+            "train_cells_per_field": cfg["cells"], "train_rays_per_cell": a.train_rays or cfg["rays"] or w0.R,
+            "adam_steps": steps, "batch_cells": batch_cells, "lr": [lr, lr / 10.0], "mix_eps": eps,
+            "loss": "second moment" if a.no_cost else "second moment x ray cost",
+            "loss_curve_steps_frac": [0.0, 0.05, 0.1, 0.25, 0.5, 0.75, 1.0], "loss_curve": curve,
+            "train_s": t_train}
+    if a.save_allocator:
+        from paper_1810_00188_amd import allocators
+        say(f"saved {allocators.save(a.learned, params, mu, sd, eps, info)}")
     del runs
     s.close()
     s_plain = rmc.Solver(0)
@@ -192,10 +224,11 @@ def learned_bench(a):
         "config": {"workload": w0.name, "grid": [w0.nx, w0.ny, w0.nz], "bands": kd.nb, "g_points": kd.ng,
                    "train_fields": n_train, "train_cells_per_field": cfg["cells"], "train_steps": steps,
                    "train_rays_per_cell": a.train_rays or cfg["rays"] or w0.R,
-                   "batch_cells": cfg["batch"], "mix_eps": eps, "R": list(cfg["Rs"]),
+                   "batch_cells": batch_cells, "mix_eps": eps, "R": list(cfg["Rs"]),
                    "loss": "second moment" if a.no_cost else "second moment x ray cost",
                    "reference_rays_per_cell": results[0]["ref_rays_per_cell"]},
         "train_loss_first_last": [float(np.mean(losses[:50])), float(np.mean(losses[-50:]))],
+        "train_loss_curve": curve,
         "train_s": t_train, "total_s": time.perf_counter() - t_start,
         "per_field": [{"plain": r["plain"], "learned": r["learned"]} for r in results],
     }
@@ -394,9 +427,7 @@ def main():
     if a.batch12:
         batch12_bench(a)
         return
-    import numpy as np
     import torch
-    from paper_1810_00188_amd import inputs, rmc
 
     dev = torch.device("cuda", 0)
     if a.copy_probe:
@@ -407,7 +438,42 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_each_way": src.numel() * 4, "copies": 3}), flush=True)
         return
-    w = inputs.channel64()
+    throughput(a)
+
+
+WORKLOADS = {
+    "dns256": ("DNS-size snapshot 256x128x128, tanh-stretched y, 64 modes at 10 %, H2O + CO2 +-20 %, "
+               "100 bands x 16 g (BF16-rounded tables), 64 rays/cell, FP32 march, FP64 sums",
+               dict(cpu_stride=4, cpu_stride_1core=256)),
+    "channel64": ("non-grey channel 64x64x64, 20 bands x 7 g, 32 rays/cell, FP32 march, FP64 sums",
+                  dict(cpu_stride=1, cpu_stride_1core=16)),
+}
+
+
+def workload_of(name):
+    from paper_1810_00188_amd import inputs
+    return {"dns256": inputs.dns256, "channel64": inputs.channel64}[name]()
+
+
+def traffic_record(path, workload):
+    """HBM bytes per k_march_lane launch measured by rocprofv3 for this workload, if the record
+    was taken on the current HIP sources (else None)."""
+    if not (path and os.path.exists(path)):
+        return None
+    rec = json.load(open(path)).get("k_march_lane", {}).get(workload)
+    if not rec or rec.get("source_sha256") != kernel_source_hash():
+        return None
+    return rec
+
+
+def throughput(a):
+    import numpy as np
+    import torch
+    from paper_1810_00188_amd import rmc
+
+    dev = torch.device("cuda", 0)
+    desc, wcfg = WORKLOADS[a.workload]
+    w = workload_of(a.workload)
     s = rmc.Solver(0)
     overrides = {k: v for k, v in (("long_ray_steps", a.long_ray_steps), ("xcd_span", a.xcd_span),
                                    ("length_sort", int(a.length_sort)),
@@ -442,19 +508,19 @@ def main():
     march_ms = st["sum_ms_march"] / a.steps
     lane_ms = st["sum_ms_march_lane"] / a.steps
     lane_steps = st["steps"] - st["long_steps"]
-    bytes_launch = BYTES_PER_STEP * lane_steps + BYTES_PER_RAY * st["rays"]
+    rays = st["rays"]
+    bytes_launch = BYTES_PER_STEP * lane_steps + BYTES_PER_RAY * rays
+    kbytes_launch = KERNEL_BYTES_PER_STEP * lane_steps + KERNEL_BYTES_PER_RAY * rays
     achieved = bytes_launch / (lane_ms * 1e-3) / 1e9
-    traffic = None
-    if a.traffic_json and os.path.exists(a.traffic_json):
-        rec = json.load(open(a.traffic_json)).get("k_march_lane", {})
-        if rec.get("source_sha256") == kernel_source_hash() and not mg:   # counters of this very code only
-            traffic = rec.get("bytes_per_launch")
-    # the march's access pattern alone (no physics): the gather bandwidth it can reach
-    probe_steps = max(1, int(round(lane_steps / max(st["rays"], 1))))
-    pms, pbytes = s.gather_probe(probe_steps)
-    s.gather_probe(probe_steps)
-    pms2, _ = s.gather_probe(probe_steps)
-    achievable = pbytes / (min(pms, pms2) * 1e-3) / 1e9
+    rec = None if mg else traffic_record(a.traffic_json, a.workload)
+    # the march's access pattern alone (no physics): the gather rate it can reach, in steps/s
+    probe_steps = max(1, int(round(lane_steps / max(rays, 1))))
+    pms = min(s.gather_probe(probe_steps)[0] for _ in range(3))
+    probe_rate = rays * probe_steps / (pms * 1e-3)
+    lane_rate = lane_steps / (lane_ms * 1e-3)
+    ncpad = 64 * ((w.nx + 3) // 4) * ((w.ny + 3) // 4) * ((w.nz + 3) // 4)
+    ws_mb = ncpad * (4 + 8) / 1e6      # one FP32 kappa plane and one FP64 intensity plane
+    level = "L2" if ws_mb <= L2_PER_XCD_MB else ("MALL" if ws_mb <= MALL_MB else "HBM")
     out = {
         "metric": "ray-cell steps/s",
         "value": value,
@@ -468,11 +534,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "non-grey channel 64x64x64, 20 bands x 7 g, 32 rays/cell, "
-                               "FP32 march, FP64 sums" + (f", multigrid march {a.mg_levels} levels x "
-                                                          f"{a.mg_steps or 5} steps" if mg else ""),
+        "config": {"workload": desc + (f", multigrid march {a.mg_levels} levels x {a.mg_steps or 5} steps"
+                                       if mg else ""),
                    "grid": [w.nx, w.ny, w.nz], "bands": w.kd.nb, "g_points": w.kd.ng,
-                   "rays_per_cell": w.R, "rays_per_step": st["rays"],
+                   "rays_per_cell": w.R, "rays_per_step": rays,
                    "ray_cell_steps_per_step": st["steps"], "parallelism": "1 GPU"},
         "phases_ms": {"prep": st["sum_ms_prep"] / a.steps, "alloc": st["sum_ms_alloc"] / a.steps,
                       "march": march_ms, "reduce": st["sum_ms_reduce"] / a.steps},
@@ -480,18 +545,77 @@ def main():
         "march_steps_split": {"lane": lane_steps, "long": st["long_steps"]},
         "roofline": {"kernel": "k_march_mg" if mg else "k_march_lane", "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "ms_per_launch": lane_ms,
+                     "traffic": rec["bytes_per_launch"] if rec else None,
+                     "ms_per_launch": lane_ms,
                      "algorithmic_bytes_per_launch": bytes_launch,
-                     "steps_per_launch": lane_steps, "rays_per_launch": st["rays"],
-                     "achievable_gather_gbs": achievable, "frac_of_achievable": achieved / achievable,
-                     "achievable_probe": f"rmc_gather_probe: {st['rays']} lanes x {probe_steps} steps of the "
-                                         f"march's access pattern without the physics"},
+                     "bytes_model": f"{BYTES_PER_STEP} B per ray-cell step + {BYTES_PER_RAY} B per ray",
+                     "steps_per_launch": lane_steps, "rays_per_launch": rays,
+                     "kernel_bytes_per_launch": kbytes_launch,
+                     "kernel_gbs": kbytes_launch / (lane_ms * 1e-3) / 1e9,
+                     "working_set_mb_per_pair": ws_mb, "working_set_level": level,
+                     "lane_steps_per_s": lane_rate,
+                     "probe_steps_per_s": probe_rate,
+                     "frac_of_achievable_steps": lane_rate / probe_rate,
+                     "achievable_probe": f"rmc_gather_probe: {rays} lanes x {probe_steps} steps of the "
+                                         f"march's access pattern without the physics, {pms:.3f} ms"},
     }
-    if a.cpu_seconds > 0:
-        out["cpu_baseline"] = cpu_baseline(w.replace(mg_levels=a.mg_levels, mg_steps=a.mg_steps or 5) if mg else w,
-                                           a.cpu_seconds)
-    print(json.dumps(out), flush=True)
     s.close()
+    del T, X, dq, se
+    torch.cuda.empty_cache()
+    if a.learned_fields > 0 and not mg:
+        out["learned"] = learned_block(a, w)
+    if a.cpu_seconds > 0:
+        wc = w.replace(mg_levels=a.mg_levels, mg_steps=a.mg_steps or 5) if mg else w
+        out["cpu_baseline"] = cpu_baseline(wc, a.cpu_seconds, wcfg["cpu_stride"], wcfg["cpu_stride_1core"])
+    print(json.dumps(out), flush=True)
+
+
+def learned_block(a, w):
+    """Time to 1 % RMS error, learned vs plain, with the allocation network committed for this
+    workload (trained by `bench.py --learned <workload>`), on held-out fields 1000, 1001, ..."""
+    import numpy as np
+    from paper_1810_00188_amd import allocators, inputs, learned, rmc
+
+    try:
+        net = allocators.load(a.workload)
+    except FileNotFoundError as e:
+        return {"error": str(e)}
+    gen = {"dns256": inputs.dns256, "channel64": inputs.channel64}[a.workload]
+    nu_c, gx = learned.spectral_inputs(w.kd)
+    s_plain = rmc.Solver(0)
+    s_learn = rmc.Solver(0)
+    results = []
+    t_start = time.perf_counter()
+    for e in range(a.learned_fields):
+        we = gen(field_seed=1000 + e)
+        s_plain.set_workload(we, device_fields=True)
+        s_learn.set_workload(we, device_fields=True, sampling=rmc.SAMPLING_LEARNED, mix_eps=net["mix_eps"])
+        s_learn.set_allocator(net["params"], net["mu"], net["sd"], nu_c, gx)
+        r = learned.time_to_error(we, s_plain, s_learn, net["mix_eps"], Rs=(16, 32, 64, 128))
+        results.append(r)
+        print(f"[learned] field {1000 + e}: plain {r['plain']['time_to_target_s']:.1f} s, learned "
+              f"{r['learned']['time_to_target_s']:.1f} s to 1 %", file=sys.stderr, flush=True)
+    s_plain.close()
+    s_learn.close()
+    tp = np.array([r["plain"]["time_to_target_s"] for r in results])
+    tl = np.array([r["learned"]["time_to_target_s"] for r in results])
+    med = lambda k, m: float(np.median([r[m][k] for r in results]))  # noqa: E731
+    return {"metric": "wall time to 1% RMS divq error (extrapolated from R = 16..128 as t0 + t1 R_1%)",
+            "unit": "s", "higher_is_better": False,
+            "learned_s": float(np.median(tl)), "plain_s": float(np.median(tp)),
+            "speedup_vs_plain": float(np.median(tp / tl)), "learned_wins": int(np.sum(tl < tp)),
+            "eval_fields": len(results), "field_seeds": [1000 + e for e in range(len(results))],
+            "R_1pct": {"plain": med("R_target", "plain"), "learned": med("R_target", "learned")},
+            "t0_s": {"plain": med("t0_s", "plain"), "learned": med("t0_s", "learned")},
+            "err_slope": {"plain": med("err_slope", "plain"), "learned": med("err_slope", "learned")},
+            "rel_err_R64": {"plain": med_i(results, "plain", 2), "learned": med_i(results, "learned", 2)},
+            "reference_rays_per_cell": results[0]["ref_rays_per_cell"],
+            "network": net["info"], "eval_s": time.perf_counter() - t_start}
+
+
+def med_i(results, m, i):
+    import numpy as np
+    return float(np.median([r[m]["rel_err"][i] for r in results]))
 
 
 if __name__ == "__main__":
