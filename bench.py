@@ -75,6 +75,8 @@ def parse():
     ap.add_argument("--mg-snaps", type=int, default=0, help="snapshots (random streams) per study row")
     ap.add_argument("--batch12", action="store_true",
                     help="12 uneven snapshots (50 bands x 8 g) in one pass: autotuned, eager and HIP graph")
+    ap.add_argument("--precision-study", choices=["channel64", "dns256"], default=None,
+                    help="errors of the FP32 march and of compensated / plain FP32 sums against FP64")
     ap.add_argument("--walls-study", action="store_true",
                     help="time per compute with reflecting walls and closed boxes (64^3 workloads)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -312,6 +314,74 @@ def mg_study(a):
     s.close()
 
 
+def precision_study(a):
+    """Errors of the reduced-precision paths against FP64 on one field, same seeds (so the
+    same rays: band, g, octant and direction are drawn in FP64 either way):
+    - ray values of the FP32 march against the FP64 march (sampled cells, all their rays),
+      with the share of rays whose step count differs (tau crossing tol within rounding);
+    - cell estimates of the FP32 march against the FP64 march (FP64 sums on both sides);
+    - per-cell sums of the FP32 march's rays in compensated FP32 and in plain FP32 against
+      FP64 sums of the same rays.
+    Errors are stated relative to the RMS of the FP64 quantity and, for cell estimates, to
+    the Monte Carlo standard error of the compute."""
+    import numpy as np
+    import torch
+    from paper_1810_00188_amd import inputs, rmc
+
+    gen = {"channel64": inputs.channel64, "dns256": inputs.dns256}[a.precision_study]
+    w = gen()
+    dev = torch.device("cuda", 0)
+    s = rmc.Solver(0)
+    s.set_workload(w, device_fields=True)
+    dq = torch.zeros(w.ncells, dtype=torch.float64, device=dev)
+    se = torch.zeros_like(dq)
+    stride = 1 if w.ncells <= 262144 else 16
+    cells = np.arange(0, w.ncells, stride)
+
+    def run(march, accum):
+        s.set_options(rmc.default_options(rays_per_cell=w.R, seed=w.seed, snapshot=w.snap, tol=w.tol,
+                                          max_steps=w.max_steps, march=march, accum=rmc.ACC[accum]))
+        s.compute(dq, se)
+        torch.cuda.synchronize()
+        return dq.cpu().numpy().copy(), se.cpu().numpy().copy()
+
+    q64, se64 = run(rmc.F64, "f64")
+    Y64, S64 = s.ray_values(cells)
+    q32, se32 = run(rmc.F32, "f64")
+    Y32, S32 = s.ray_values(cells)
+    qc, _ = run(rmc.F32, "comp32")
+    qf, _ = run(rmc.F32, "f32")
+    rms = lambda v: float(np.sqrt(np.mean(np.square(v))))  # noqa: E731
+    dY = Y32 - Y64
+    same = S32 == S64
+    rmsY, rmsQ, rms_se = rms(Y64), rms(q64), rms(se64)
+    out = {"metric": "errors of reduced precision against FP64", "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": w.name, "grid": [w.nx, w.ny, w.nz], "bands": w.kd.nb, "g_points": w.kd.ng,
+                      "rays_per_cell": w.R, "ray_sample": f"every {stride}th cell, all its rays ({Y64.size} rays)"},
+           "ray_fp32_march_vs_fp64": {
+               "max_abs_over_rms": float(np.abs(dY).max()) / rmsY,
+               "rms_over_rms": rms(dY) / rmsY,
+               "max_abs_over_rms_same_steps": float(np.abs(dY[same]).max()) / rmsY if same.any() else None,
+               "rel_err_max_where_abs_Y_above_rms": float((np.abs(dY) / np.abs(Y64))[np.abs(Y64) > rmsY].max()),
+               "rays_with_other_step_count": int((~same).sum()),
+               "share_other_step_count": float((~same).mean())},
+           "cell_fp32_march_vs_fp64": {
+               "max_abs_over_rms": float(np.abs(q32 - q64).max()) / rmsQ,
+               "rms_over_rms": rms(q32 - q64) / rmsQ,
+               "rms_over_mc_stderr": rms(q32 - q64) / rms_se},
+           "cell_sums_comp_fp32_vs_fp64": {
+               "max_abs_over_rms": float(np.abs(qc - q32).max()) / rmsQ,
+               "rms_over_rms": rms(qc - q32) / rmsQ,
+               "max_rel_where_abs_above_rms": float((np.abs(qc - q32) / np.abs(q32))[np.abs(q32) > rmsQ].max())},
+           "cell_sums_plain_fp32_vs_fp64": {
+               "max_abs_over_rms": float(np.abs(qf - q32).max()) / rmsQ,
+               "rms_over_rms": rms(qf - q32) / rmsQ,
+               "max_rel_where_abs_above_rms": float((np.abs(qf - q32) / np.abs(q32))[np.abs(q32) > rmsQ].max())},
+           "mc_stderr_rms_over_rms_q": rms_se / rmsQ}
+    print(json.dumps(out), flush=True)
+    s.close()
+
+
 def walls_study(a):
     """Wall rows (Eq. 3's wall factor with specular reflection, closed boxes of Table 1): time
     per compute, steps per ray and ray-cell steps per second on 64^3 workloads, black walls
@@ -423,6 +493,9 @@ def main():
         return
     if a.walls_study:
         walls_study(a)
+        return
+    if a.precision_study:
+        precision_study(a)
         return
     if a.batch12:
         batch12_bench(a)

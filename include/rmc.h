@@ -185,7 +185,11 @@ rmc_status rmc_set_box_walls(rmc_ctx *ctx, const double *T, const double *eps);
  *   k[ns][nb][ng][nT] absorption coefficient per unit mole fraction, RMC_F32 floats or
  *     RMC_BF16 raw bfloat16 bit patterns (uint16),
  *   Ib[nb][nT] band-averaged blackbody intensity (double).
- * Limits: 1 <= nb <= 4096, 1 <= ng <= 255, 1 <= ns <= 8, 2 <= nT, nb * ng <= 2000. */
+ * Limits: 1 <= nb <= 4096, 1 <= ng <= 255, 1 <= ns <= 8, 2 <= nT, nb * ng <= 2000.  The
+ * march stages the tables of four (band, g) pairs in LDS beside the face tables of the grids
+ * it marches: 8 (nfaces + 4 (nT + ns nT / 2)) bytes must stay within 52 KiB (nfaces: the face
+ * coordinates of every grid level of every snapshot of a pass), else the compute returns
+ * RMC_UNSUPPORTED. */
 rmc_status rmc_set_kdist(rmc_ctx *ctx, int nb, int ng, int ns, int nT, double T0, double dT,
                          const double *dnu, const double *wg, const void *k, rmc_dtype k_dtype,
                          const double *Ib);
@@ -240,12 +244,12 @@ rmc_status rmc_autotune_batch(rmc_ctx *const *ctxs, int nsnap, int reps, const c
 /* Measurement aid (the roofline of the march, not part of the method): the march's memory
  * access alone.  Every lane of ncells x R walks a straight ray of `steps` unit cells (x and z
  * periodic, y reflected) from a cell of its wavefront's tile region and reads per step the
- * FP32 kappa and the FP64 intensity of its cell from the planes of the last compute, with the
- * march's XCD-aware launch order and one (n, g) pair per run of chunks, but no physics.
- * *ms receives the kernel time (HIP events on `stream`, synchronised), *bytes the bytes it
- * gathers (12 per step) and writes (8 per wavefront): bytes / ms is the gather bandwidth the
- * march's access pattern can reach.  Needs a previous compute with the FP32 march
- * (RMC_BAD_STATE otherwise); steps in [1, 65536]. */
+ * 16-byte record of its cell (table coordinate of T, mole fractions) from the field of the
+ * last compute, with the march's XCD-aware launch order and one (n, g) pair per run of
+ * chunks, but no physics and no table lookups.  *ms receives the kernel time (HIP events on
+ * `stream`, synchronised), *bytes the bytes it gathers (16 per step) and writes (8 per
+ * wavefront): bytes / ms is the gather bandwidth the march's access pattern can reach.  Needs
+ * a previous compute with the FP32 march (RMC_BAD_STATE otherwise); steps in [1, 65536]. */
 rmc_status rmc_gather_probe(rmc_ctx *ctx, int steps, double *ms, double *bytes, void *stream);
 
 /* Per-cell allocation pdf over (n, g, octant) for RMC_SAMPLING_PDF: q[ncells][nb][ng][8]

@@ -35,8 +35,8 @@ namespace {
 constexpr int kMaxLev = 8;      // grid levels of the multigrid march
 
 struct SnapDesc {
-    const void *kap;            // Real [nb*ng][ncpad] kappa_{n,g} planes, bricked
-    const double *Ipl;          // [nb][ncpad] I_n planes, bricked
+    const uint4 *rec;           // [ncpad << rw_log2] cell records (table coordinate, mole fractions), bricked
+    int rw_log2;                // 16-byte words per record, log2
     const double *W;            // [nbucket] plain ray weight 4 pi dnu w / (8 p(n,g,o))
     const double *Iw;           // [6][nb] wall intensities, walls x0, x1, y0, y1, z0, z1
     void *Y;                    // ray slots c * R + r: FP32 march {value bits, steps | end << 28} as
@@ -62,14 +62,13 @@ struct SnapDesc {
     double Lx, Lz;
     double hx, hz;              // cell widths along x and z when those axes are uniform
     // multigrid march (Sec. 4.3): level L has (nx >> L) x (ny >> L) x (nz >> L) cells with
-    // every 2^L-th face; its planes follow the same bricked layout
+    // every 2^L-th face; its records follow the same bricked layout
     int nlev;                   // grid levels (1: the DNS grid only)
     int mg_steps;               // steps per level before the next coarser one
     int lev_face[kMaxLev];      // face tables of each level in the staged face array
-    uint64_t lev_off[kMaxLev];  // offset of level L >= 1 within a coarse plane
-    uint64_t mg_stride;         // cells per coarse plane (all levels >= 1)
-    const void *mg_kap;         // Real [nb*ng][mg_stride] kappa planes of the coarse levels
-    const double *mg_I;         // [nb][mg_stride] I planes of the coarse levels
+    uint64_t lev_off[kMaxLev];  // first cell of level L >= 1 in the coarse records
+    uint64_t mg_stride;         // cells of all coarse levels
+    const uint4 *mg_rec;        // records of the coarse levels
     double epsw[6];             // wall emissivities, walls x0, x1, y0, y1, z0, z1
     int closed;                 // walls on x and z (closed box), else x and z periodic
     int reflect;                // some wall has emissivity below one
@@ -397,49 +396,45 @@ __global__ void k_cell_pdf(const double *__restrict__ q, const double *__restric
     for (int i = 0; i < m; ++i) pc[i] /= tot;
 }
 
-// ------------------------------------------------------------------ property fields
-// field[(n*ng + g)][brick(i,j,k)] = {kappa_{n,g}(T_c, x_c), I_n(T_c)}: linear interpolation
-// of the tables in T (Sec. 2.2), mixture kappa = sum_s x_s k^s (FP64, then rounded to Real).
+// ------------------------------------------------------------------ cell records
+// rec[brick(i,j,k)] = {u = (T_c - T0) / dT (FP64), x_s(c) in march precision}: the table
+// coordinate of the linear interpolation in T (Sec. 2.2) and the mole fractions of the mixture,
+// from which the march interpolates kappa_{n,g} and I_n of any (band, g) pair.  Padding cells
+// hold zeros (never read).
 template <class Real>
-__global__ void __launch_bounds__(256) k_fields(const double *__restrict__ T, const double *__restrict__ X, int ns,
-                                                uint64_t nc, const double *__restrict__ k64,
-                                                const double *__restrict__ Ib, int nb, int ng, int nT, double T0,
-                                                double dT, SnapDesc D, Real *__restrict__ kap_out,
-                                                double *__restrict__ I_out, uint64_t stride)
+__global__ void __launch_bounds__(256) k_records(const double *__restrict__ T, const double *__restrict__ X, int ns,
+                                                 uint64_t nc, double T0, double dT, SnapDesc D,
+                                                 uint4 *__restrict__ rec)
 {
     const uint64_t bc = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
     if (bc >= D.ncpad) return;
     int i, j, k;
     const bool valid = brick_cell(D, bc, i, j, k);
-    int t = 0;
-    double f = 0.0;
-    double x[8];
+    const int rw = 1 << D.rw_log2;
+    uint32_t w[32];
+#pragma unroll
+    for (int q = 0; q < 32; ++q) w[q] = 0u;
     if (valid) {
         const uint64_t c = ((uint64_t)i * D.ny + j) * D.nz + k;
         const double u = (T[c] - T0) / dT;
-        t = (int)floor(u);
-        if (t > nT - 2) t = nT - 2;
-        f = u - (double)t;
-        for (int sp = 0; sp < ns; ++sp) x[sp] = X[(size_t)sp * nc + c];
-    }
-    for (int n = blockIdx.y; n < nb; n += gridDim.y) {
-        double I = 0.0;
-        if (valid) {
-            const double *ib = Ib + (size_t)n * nT;
-            I = ib[t] + f * (ib[t + 1] - ib[t]);
-        }
-        I_out[(size_t)n * stride + bc] = I;
-        for (int g = 0; g < ng; ++g) {
-            double kap = 0.0;
-            if (valid)
-                for (int sp = 0; sp < ns; ++sp) {
-                    const double *tab = k64 + (((size_t)sp * nb + n) * ng + g) * nT;
-                    const double ks = tab[t] + f * (tab[t + 1] - tab[t]);
-                    kap += x[sp] * ks;
-                }
-            kap_out[((size_t)n * ng + g) * stride + bc] = (Real)kap;
+        w[0] = (uint32_t)__double2loint(u);
+        w[1] = (uint32_t)__double2hiint(u);
+#pragma unroll
+        for (int sp = 0; sp < 8; ++sp) {
+            if (sp >= ns) break;
+            const double x = X[(size_t)sp * nc + c];
+            if constexpr (sizeof(Real) == 4) {
+                w[2 + sp] = __float_as_uint((float)x);
+            } else {
+                w[2 + 2 * sp] = (uint32_t)__double2loint(x);
+                w[3 + 2 * sp] = (uint32_t)__double2hiint(x);
+            }
         }
     }
+    uint4 *out = rec + (bc << D.rw_log2);
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+        if (q < rw) out[q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
 }
 
 // Fields of the next coarser grid (multigrid march, Sec. 4.3): each coarse cell takes the
@@ -719,7 +714,69 @@ template <class Real> struct MarchArgs {
     int span_log2;              // log2 of the run of consecutive chunks an XCD takes in turn
     float log_inv_tol;          // ln(1 / tol), for the expected-length estimate
     int long_form;              // k_march_long: 0 by the count of long rays, 1 workgroups, 2 wavefronts
+    const double *Ib;           // I_n at the table nodes [nb][nT]
+    const float *k32;           // k^s_{n,g} at the table nodes [ns][nb * ng][nT] (FP32-exact values)
+    int nT, ns;
+    int tab_off;                // LDS: first double of the table slots, after the face tables
+    int slot_dbl;               // LDS: doubles per table slot
 };
+
+// Doubles of an LDS table slot: I_n at the nT nodes, then ns x nT FP32 k values (16-byte
+// multiple).
+inline int table_slot_doubles(int nT, int ns) { return (nT + (ns * nT + 1) / 2 + 1) & ~1; }
+
+// Dynamic LDS of the march kernels: the face tables, then four table slots.
+inline size_t march_lds_bytes(int nfaces, int nT, int ns)
+{
+    return sizeof(double) * ((size_t)((nfaces + 1) & ~1) + 4 * (size_t)table_slot_doubles(nT, ns));
+}
+constexpr size_t kMarchLds = 52 * 1024;
+
+// Tables of (band, g) pair `pair` into an LDS slot: I_n at the nodes (FP64), then k^s_{n,g}
+// at the nodes (FP32) species after species; filled by `nt` threads from thread t0 on.
+template <class Real>
+__device__ __forceinline__ void stage_tables(double *slot, const MarchArgs<Real> &A, int pair, int t0, int nt)
+{
+    const int n = pair / A.ng, npairs = A.nb * A.ng;
+    for (int q = t0; q < A.nT; q += nt) slot[q] = gld(A.Ib + (size_t)n * A.nT + q);
+    float *ks = reinterpret_cast<float *>(slot + A.nT);
+    for (int sp = 0; sp < A.ns; ++sp)
+        for (int q = t0; q < A.nT; q += nt) ks[sp * A.nT + q] = gld(A.k32 + ((size_t)sp * npairs + pair) * A.nT + q);
+}
+
+template <class Real>
+__device__ __forceinline__ Props<Real> slot_props(const double *slot, const MarchArgs<Real> &A, const uint4 *rec,
+                                                  int rw_log2)
+{
+    Props<Real> P;
+    P.rec = rec;
+    P.ib = slot;
+    P.k = reinterpret_cast<const float *>(slot + A.nT);
+    P.kstride = A.nT;
+    P.ns = A.ns;
+    P.tmax = A.nT - 2;
+    P.rw_log2 = rw_log2;
+    return P;
+}
+
+// Table slots of the four wavefronts of a workgroup (s_pair[w]: the pair of wavefront w, -1
+// without work): wavefront w uses the slot of the first wavefront with the same pair (buckets
+// are contiguous in chunk order, so the four usually share one), and all threads stage the
+// distinct ones.  Returns the slot of wavefront wib; the caller synchronises before reading.
+template <class Real>
+__device__ __forceinline__ int stage_wave_tables(double *tabs, const MarchArgs<Real> &A, const int *s_pair, int wib)
+{
+    int mine = wib;
+    for (int w = 0; w < 4; ++w) {
+        const int pw = s_pair[w];
+        int first = w;
+        for (int v = 0; v < w; ++v)
+            if (s_pair[v] == pw) { first = v; break; }
+        if (pw >= 0 && first == w) stage_tables(tabs + w * A.slot_dbl, A, pw, (int)threadIdx.x, (int)blockDim.x);
+        if (w == wib) mine = first;
+    }
+    return mine;
+}
 
 // Workgroups of a launch are dealt to the XCDs in turn (workgroup b runs on XCD b mod 8) and
 // each XCD starts its workgroups in order.  Wavefront `wib` of workgroup b = 8 k + x takes
@@ -812,18 +869,11 @@ __device__ __forceinline__ RayGeo ray_geo_level(const SnapDesc &D, const double 
     return G;
 }
 
-// Property planes of grid level L for (band, g) pair `pair` of band n.
-template <class Real>
-__device__ __forceinline__ void level_planes(const SnapDesc &D, int L, int pair, int n, const Real *&K,
-                                             const double *&Ipl)
+// The ray's properties on grid level L: the level's records, the same tables.
+template <class Real> __device__ __forceinline__ Props<Real> level_props(const SnapDesc &D, int L, Props<Real> P)
 {
-    if (L == 0) {
-        K = reinterpret_cast<const Real *>(D.kap) + (size_t)pair * D.ncpad;
-        Ipl = D.Ipl + (size_t)n * D.ncpad;
-    } else {
-        K = reinterpret_cast<const Real *>(D.mg_kap) + (size_t)pair * D.mg_stride + D.lev_off[L];
-        Ipl = D.mg_I + (size_t)n * D.mg_stride + D.lev_off[L];
-    }
+    P.rec = L == 0 ? D.rec : D.mg_rec + (D.lev_off[L] << D.rw_log2);
+    return P;
 }
 
 // Multigrid march (Sec. 4.3): mg_steps steps on each grid, then the ray goes on from its
@@ -832,25 +882,21 @@ __device__ __forceinline__ void level_planes(const SnapDesc &D, int L, int pair,
 // last grid the ray stops after last_cap steps in all (returns false; R then holds its state
 // on that grid), else returns true when finished.
 template <class Real, bool INC_XZ>
-__device__ __forceinline__ bool march_levels(Ray<Real, INC_XZ> &R, const SnapDesc &D, const double *sf, int pair,
-                                             int n, int nb, Real tol, int max_steps, Real k0, double I0,
-                                             int last_cap)
+__device__ __forceinline__ bool march_levels(Ray<Real, INC_XZ> &R, const SnapDesc &D, const double *sf,
+                                             const Props<Real> &P0, int n, int nb, Real tol, int max_steps, Real k0,
+                                             double I0, int last_cap)
 {
     RayGeo G = ray_geo(D, sf);
-    const Real *K;
-    const double *Ipl;
-    level_planes<Real>(D, 0, pair, n, K, Ipl);
+    Props<Real> P = P0;
     for (int L = 0;; ++L) {
         const bool last = L + 1 >= D.nlev;
         const int cap = last ? last_cap : D.mg_steps * (L + 1);
-        if (ray_march(R, G, K, Ipl, walls_of(D, n, nb), tol, max_steps, k0, I0, cap)) return true;
+        if (ray_march(R, G, P, walls_of(D, n, nb), tol, max_steps, k0, I0, cap)) return true;
         if (last) return false;
         G = ray_geo_level(D, sf, L + 1);
         ray_descend(R, G);
-        level_planes<Real>(D, L + 1, pair, n, K, Ipl);
-        const int cell = R.px + R.py + R.pz;
-        k0 = gld(K + cell);
-        I0 = gld(Ipl + cell);
+        P = level_props(D, L + 1, P0);
+        prop_load(P, R.px + R.py + R.pz, k0, I0);
     }
 }
 
@@ -860,11 +906,13 @@ __device__ __forceinline__ bool march_levels(Ray<Real, INC_XZ> &R, const SnapDes
 //   E = 1 + min(L_wall, ln(1/tol) / kappa_src) (|d_x| n_x / L_x + |d_y| n_y / L_y + |d_z| n_z / L_z).
 // It only orders work; no result depends on it.
 template <class Real>
-__device__ __forceinline__ uint32_t ray_len_class(const SnapDesc &D, const RayGeo &G, int pair, int i, int j, int k,
-                                                  double dx, double dy, double dz, float log_inv_tol)
+__device__ __forceinline__ uint32_t ray_len_class(const SnapDesc &D, const RayGeo &G, const Props<Real> &P, int i,
+                                                  int j, int k, double dx, double dy, double dz, float log_inv_tol)
 {
-    const Real *K = reinterpret_cast<const Real *>(D.kap) + (size_t)pair * D.ncpad;
-    const float kap = (float)gld(K + brick_x(i, G.bsx) + brick_y(j, G.bsy) + brick_z(k));
+    Real kr;
+    double Ir;
+    prop_load(P, brick_x(i, G.bsx) + brick_y(j, G.bsy) + brick_z(k), kr, Ir);
+    const float kap = (float)kr;
     const double yc = 0.5 * (G.yf[j] + G.yf[j + 1]);
     const float lw = (float)(((dy > 0.0) ? G.yf[G.ny] - yc : yc - G.yf[0]) / fabs(dy));
     const float L = kap > 0.0f ? fminf(lw, log_inv_tol / kap) : lw;
@@ -920,11 +968,15 @@ __global__ void __launch_bounds__(256) k_march_lane(MarchArgs<Real> A)
     const bool wvalid = wave < nch;
     const uint32_t b = wvalid ? __builtin_amdgcn_readfirstlane(gld(A.chunk_bucket + wave)) : 0xFFFFFFFFu;
     const int o = (int)(b & 7), pair = (int)(b >> 3);
+    __shared__ int s_pair[4];
+    if (lane == 0) s_pair[wib] = wvalid ? pair : -1;
+    __syncthreads();
+    const double *tab = sf + A.tab_off + stage_wave_tables(sf + A.tab_off, A, s_pair, wib) * A.slot_dbl;
+    __syncthreads();
     uint4 it;
     uint32_t q;                 // position of the item in the work list
     double dx, dy, dz;
     if constexpr (!SORT) {
-        __syncthreads();
         if (!wvalid) return;
         q = wave * 64u + (uint32_t)lane;
         it = gld(A.items + q);
@@ -948,7 +1000,8 @@ __global__ void __launch_bounds__(256) k_march_lane(MarchArgs<Real> A)
             double ex, ey, ez;
             octant_direction(it0.z, it0.w, o, ex, ey, ez);
             const int i0 = (int)(it0.x & 1023), j0 = (int)((it0.x >> 10) & 1023), k0 = (int)((it0.x >> 20) & 1023);
-            ckey = 63u - ray_len_class<Real>(D0, G0, pair, i0, j0, k0, ex, ey, ez, A.log_inv_tol);
+            ckey = 63u - ray_len_class<Real>(D0, G0, slot_props(tab, A, D0.rec, D0.rw_log2), i0, j0, k0, ex, ey, ez,
+                                             A.log_inv_tol);
             s_d[0][threadIdx.x] = ex;
             s_d[1][threadIdx.x] = ey;
             s_d[2][threadIdx.x] = ez;
@@ -986,23 +1039,23 @@ __global__ void __launch_bounds__(256) k_march_lane(MarchArgs<Real> A)
     const int i = (int)(it.x & 1023), j = (int)((it.x >> 10) & 1023), k = (int)((it.x >> 20) & 1023);
     const int r = (int)(it.y & 255);
     const int n = pair / A.ng;
-    const Real *K = reinterpret_cast<const Real *>(D.kap) + (size_t)pair * D.ncpad;
-    const double *Ipl = D.Ipl + (size_t)n * D.ncpad;
+    const Props<Real> P = slot_props(tab, A, D.rec, D.rw_log2);
     const uint32_t c = (uint32_t)(((uint64_t)i * D.ny + j) * D.nz + k);
     Ray<Real, INC_XZ> R;
     Real kap_src;
     double Isrc;
-    ray_init(R, G, U, K, Ipl, i, j, k, dx, dy, dz, kap_src, Isrc);
-    if (!ray_march(R, G, K, Ipl, walls_of(D, n, A.nb), A.tol, A.max_steps, kap_src, Isrc, A.cap)) {
+    ray_init(R, G, U, P, i, j, k, dx, dy, dz, kap_src, Isrc);
+    if (!ray_march(R, G, P, walls_of(D, n, A.nb), A.tol, A.max_steps, kap_src, Isrc, A.cap)) {
         // long ray: hand its state to k_march_long (or, if the list is full, finish it here)
         const uint32_t idx = atomicAdd(A.cont_count, 1u);
         if (idx < A.cont_cap) {
             A.cont[idx] = cont_rec(q, 0, R);
             return;
         }
-        const int cell = R.px + R.py + R.pz;
-        ray_march(R, G, K, Ipl, walls_of(D, n, A.nb), A.tol, A.max_steps, gld(K + cell), gld(Ipl + cell),
-                  A.max_steps);
+        Real kc;
+        double Ic;
+        prop_load(P, R.px + R.py + R.pz, kc, Ic);
+        ray_march(R, G, P, walls_of(D, n, A.nb), A.tol, A.max_steps, kc, Ic, A.max_steps);
     }
     const size_t slot = (size_t)c * A.R + r;
     double w;
@@ -1026,10 +1079,15 @@ __global__ void __launch_bounds__(256) k_march_mg(MarchArgs<Real> A)
     const int wib = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
     const uint32_t nch = __builtin_amdgcn_readfirstlane(*A.nchunks);
     const uint32_t wave = __builtin_amdgcn_readfirstlane(xcd_chunk(blockIdx.x, (uint32_t)wib, A.span_log2));
-    __syncthreads();
-    if (wave >= nch) return;
-    const uint32_t b = __builtin_amdgcn_readfirstlane(gld(A.chunk_bucket + wave));
+    const bool wvalid = wave < nch;
+    const uint32_t b = wvalid ? __builtin_amdgcn_readfirstlane(gld(A.chunk_bucket + wave)) : 0xFFFFFFFFu;
     const int o = (int)(b & 7), pair = (int)(b >> 3);
+    __shared__ int s_pair[4];
+    if (lane == 0) s_pair[wib] = wvalid ? pair : -1;
+    __syncthreads();
+    const double *tab = sf + A.tab_off + stage_wave_tables(sf + A.tab_off, A, s_pair, wib) * A.slot_dbl;
+    __syncthreads();
+    if (!wvalid) return;
     const uint32_t q = wave * 64u + (uint32_t)lane;
     const uint4 it = gld(A.items + q);
     if (it.y == kInvalidItem) return;
@@ -1044,25 +1102,25 @@ __global__ void __launch_bounds__(256) k_march_mg(MarchArgs<Real> A)
     const int i = (int)(it.x & 1023), j = (int)((it.x >> 10) & 1023), k = (int)((it.x >> 20) & 1023);
     const int r = (int)(it.y & 255);
     const int n = pair / A.ng;
-    const Real *K = reinterpret_cast<const Real *>(D.kap) + (size_t)pair * D.ncpad;
-    const double *Ipl = D.Ipl + (size_t)n * D.ncpad;
+    const Props<Real> P = slot_props(tab, A, D.rec, D.rw_log2);
     const uint32_t c = (uint32_t)(((uint64_t)i * D.ny + j) * D.nz + k);
     Ray<Real, INC_XZ> R;
     Real kap_src;
     double Isrc;
-    ray_init(R, G, U, K, Ipl, i, j, k, dx, dy, dz, kap_src, Isrc);
+    ray_init(R, G, U, P, i, j, k, dx, dy, dz, kap_src, Isrc);
     const int last_cap = (int)min((long)A.cap + (long)D.mg_steps * (D.nlev - 1), (long)A.max_steps);
-    if (!march_levels(R, D, sf, pair, n, A.nb, A.tol, A.max_steps, kap_src, Isrc, last_cap)) {
+    if (!march_levels(R, D, sf, P, n, A.nb, A.tol, A.max_steps, kap_src, Isrc, last_cap)) {
         const uint32_t idx = atomicAdd(A.cont_count, 1u);
         if (idx < A.cont_cap) {
             A.cont[idx] = cont_rec(q, D.nlev - 1, R);
             return;
         }
         const RayGeo GL = ray_geo_level(D, sf, D.nlev - 1);
-        level_planes<Real>(D, D.nlev - 1, pair, n, K, Ipl);
-        const int cell = R.px + R.py + R.pz;
-        ray_march(R, GL, K, Ipl, walls_of(D, n, A.nb), A.tol, A.max_steps, gld(K + cell), gld(Ipl + cell),
-                  A.max_steps);
+        const Props<Real> PL = level_props(D, D.nlev - 1, P);
+        Real kc;
+        double Ic;
+        prop_load(PL, R.px + R.py + R.pz, kc, Ic);
+        ray_march(R, GL, PL, walls_of(D, n, A.nb), A.tol, A.max_steps, kc, Ic, A.max_steps);
     }
     const size_t slot = (size_t)c * A.R + r;
     double w;
@@ -1102,8 +1160,16 @@ struct LongTail {
     int steps, i, j, k, sgn;
 };
 
+// Orders a wavefront's LDS accesses before and after (its lanes write, then read, a slot).
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <bool PDF, bool MULTI, bool WG>
-__device__ __forceinline__ void long_rays(const MarchArgs<float> &A, const double *sf, uint32_t nrec)
+__device__ __forceinline__ void long_rays(const MarchArgs<float> &A, double *sf, uint32_t nrec)
 {
     constexpr int NSEG = WG ? kLongSeg : 64;
     __shared__ double s_tau[4], s_acc[4];
@@ -1128,20 +1194,29 @@ __device__ __forceinline__ void long_rays(const MarchArgs<float> &A, const doubl
         const int r = (int)(it.y & 255);
         const int o = (int)(b & 7), pair = (int)(b >> 3);
         const int n = pair / A.ng;
-        const float *K;
-        const double *Ipl;
-        level_planes<float>(D, 0, pair, n, K, Ipl);
+        // the ray's tables: a slot per workgroup (one ray) or per wavefront (one ray each)
+        double *slot = sf + A.tab_off + (WG ? 0 : wid) * A.slot_dbl;
+        if constexpr (WG) {
+            stage_tables(slot, A, pair, (int)threadIdx.x, (int)blockDim.x);
+            __syncthreads();
+        } else {
+            wave_lds_sync();   // the previous ray's reads of the slot are done
+            stage_tables(slot, A, pair, lane, 64);
+            wave_lds_sync();
+        }
+        const Props<float> P0 = slot_props(slot, A, D.rec, D.rw_log2);
+        Props<float> P = P0;
         const uint32_t c = (uint32_t)(((uint64_t)ci * D.ny + cj) * D.nz + ck);
         double dx, dy, dz;
         octant_direction(it.z, it.w, o, dx, dy, dz);
         Ray<float, true> R;
         float kap_src;
         double Isrc;
-        ray_init(R, G0, U, K, Ipl, ci, cj, ck, dx, dy, dz, kap_src, Isrc);
-        // continue on the ray's grid level (multigrid): its geometry, planes and increments
+        ray_init(R, G0, U, P0, ci, cj, ck, dx, dy, dz, kap_src, Isrc);
+        // continue on the ray's grid level (multigrid): its geometry, records and increments
         const RayGeo G = rc.lev ? ray_geo_level(D, sf, rc.lev) : G0;
         if (rc.lev) {
-            level_planes<float>(D, rc.lev, pair, n, K, Ipl);
+            P = level_props(D, rc.lev, P0);
             const double sc = (double)(1 << rc.lev);
             U.hx *= sc;
             U.hz *= sc;
@@ -1253,15 +1328,16 @@ __device__ __forceinline__ void long_rays(const MarchArgs<float> &A, const doubl
             bool wall_end = false;
             if (!empty) {
                 long next = B0;
-                const int cur0 = R.px + R.py + R.pz;
-                float kc = gld(K + cur0);
-                double Ic = gld(Ipl + cur0);
+                float kc;
+                double Ic;
+                prop_load(P, R.px + R.py + R.pz, kc, Ic);
                 while (true) {
                     const double te = R.tx < R.ty ? (R.tz < R.tx ? R.tz : R.tx) : (R.tz < R.ty ? R.tz : R.ty);
                     const bool cross = (ax ? R.tx : R.tz) == te;
                     double ds;
                     int wall;
                     const int cell = ray_advance(R, G, ds, wall);
+                    const uint4 vn = prop_fetch(P, cell);
                     const float x = kc * (float)ds;
                     float a, e;
                     absorb_f32(x, a, e);
@@ -1285,8 +1361,7 @@ __device__ __forceinline__ void long_rays(const MarchArgs<float> &A, const doubl
                     if (!(R.tau > (double)A.tol)) break;
                     if (seg < NSEG - 1 ? (cross && ++next == B1) : (R.t >= tend)) break;
                     if (R.steps >= A.max_steps) break;
-                    kc = gld(K + cell);
-                    Ic = gld(Ipl + cell);
+                    prop_eval(P, vn, cell, kc, Ic);
                 }
             }
             // incoming tau and steps of every segment: inclusive prefix product and sum within
@@ -1366,9 +1441,10 @@ __device__ __forceinline__ void long_rays(const MarchArgs<float> &A, const doubl
                 R.acc = 0.0;
                 R.steps = steps_in;
                 R.end = kEndTol;
-                const int cur = R.px + R.py + R.pz;
-                ray_march(R, G, K, Ipl, walls_of(D, n, A.nb), A.tol, A.max_steps, gld(K + cur),
-                          gld(Ipl + cur), A.max_steps);
+                float kc;
+                double Ic;
+                prop_load(P, R.px + R.py + R.pz, kc, Ic);
+                ray_march(R, G, P, walls_of(D, n, A.nb), A.tol, A.max_steps, kc, Ic, A.max_steps);
                 contrib = R.acc;
             }
             // fixed-order sum of the contributions over the wavefront (and the workgroup)
@@ -1420,29 +1496,27 @@ __global__ void __launch_bounds__(256) k_march_long(MarchArgs<float> A)
 
 // ------------------------------------------------------------------------ gather probe
 // The memory side of the march alone, for the denominator of its roofline: every lane walks a
-// straight ray of `steps` cells and reads per step the FP32 kappa and the FP64 intensity of
-// its cell from the planes of the last compute, with the march's launch order (XCD-aware
-// chunks; the chunks of one (n, g) pair in a row, each starting in the tile region its
-// position in the pair's share points to, lanes at cells of one 256-cell tile) -- without the
-// physics.  Unit cells, x and z periodic, y reflected at the walls; directions from a hash.
+// straight ray of `steps` cells and reads per step the record of its cell (the first 16-byte
+// word) from the field of the last compute, with the march's launch order (XCD-aware chunks;
+// the chunks of one (n, g) pair in a row, each starting in the tile region its position in the
+// pair's share points to, lanes at cells of one 256-cell tile) -- without the physics and the
+// table lookups.  Unit cells, x and z periodic, y reflected at the walls; directions from a
+// hash.
 __device__ __forceinline__ uint32_t probe_hash(uint32_t x)
 {
     x ^= x >> 16; x *= 0x7FEB352Du; x ^= x >> 15; x *= 0x846CA68Bu; x ^= x >> 16;
     return x;
 }
 
-__global__ void __launch_bounds__(256) k_gather_probe(const float *__restrict__ kap, const double *__restrict__ Ipl,
-                                                      SnapDesc D, int npairs, int ng, int steps, uint32_t nchunks,
+__global__ void __launch_bounds__(256) k_gather_probe(SnapDesc D, int npairs, int steps, uint32_t nchunks,
                                                       int span_log2, double *__restrict__ out)
 {
     const int wib = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
     const uint32_t chunk = __builtin_amdgcn_readfirstlane(xcd_chunk(blockIdx.x, (uint32_t)wib, span_log2));
     if (chunk >= nchunks) return;
-    const int pair = (int)((uint64_t)chunk * npairs / nchunks), n = pair / ng;
+    const int pair = (int)((uint64_t)chunk * npairs / nchunks);
     const uint64_t c0 = ((uint64_t)pair * nchunks + npairs - 1) / npairs;      // first chunk of the pair
     const uint64_t c1 = ((uint64_t)(pair + 1) * nchunks + npairs - 1) / npairs;
-    const float *K = kap + (size_t)pair * D.ncpad;
-    const double *I = Ipl + (size_t)n * D.ncpad;
     const uint64_t tiles = (D.ncpad + 255) / 256;
     const uint64_t tile = (chunk - c0) * tiles / (c1 > c0 ? c1 - c0 : 1);
     const uint32_t h0 = probe_hash(chunk * 64u + (uint32_t)lane);
@@ -1461,7 +1535,8 @@ __global__ void __launch_bounds__(256) k_gather_probe(const float *__restrict__ 
     double acc = 0.0;
     for (int st = 0; st < steps; ++st) {
         const int cell = brick_x(i, bsx) + brick_y(j, bsy) + brick_z(k);
-        acc += (double)gld(K + cell) * gld(I + cell);
+        const uint4 v = gld(D.rec + ((size_t)(uint32_t)cell << D.rw_log2));
+        acc += __hiloint2double((int)v.y, (int)v.x) * (double)__uint_as_float(v.z);
         if (tx <= ty && tx <= tz) {
             i += sx;
             i = i == D.nx ? 0 : (i < 0 ? D.nx - 1 : i);
@@ -1493,6 +1568,9 @@ template <class Real> struct TraceArgs {
     Real tol;
     int max_steps;
     rmc_ray_record *out;
+    const double *Ib;           // I_n at the table nodes [nb][nT]
+    const float *k32;           // k^s_{n,g} at the table nodes [ns][nb * ng][nT]
+    int nT, ns;
 };
 
 // All R rays of listed cells, drawn and marched with the same device functions as the
@@ -1519,8 +1597,14 @@ __global__ void __launch_bounds__(256) k_trace(TraceArgs<Real> A)
         kord += (e.n == d.n && e.g == d.g && e.o == d.o) ? 1u : 0u;
     }
     const int pair = d.n * A.ng + d.g;
-    const Real *K = reinterpret_cast<const Real *>(D.kap) + (size_t)pair * D.ncpad;
-    const double *Ipl = D.Ipl + (size_t)d.n * D.ncpad;
+    Props<Real> P;              // every thread its own pair: the tables are read from global memory
+    P.rec = D.rec;
+    P.ib = A.Ib + (size_t)d.n * A.nT;
+    P.k = A.k32 + (size_t)pair * A.nT;
+    P.kstride = A.nb * A.ng * A.nT;
+    P.ns = A.ns;
+    P.tmax = A.nT - 2;
+    P.rw_log2 = D.rw_log2;
     uint32_t v[4];
     philox4x32_10(c, ((uint32_t)d.n << 16) | ((uint32_t)d.g << 8) | (uint32_t)d.o, kord,
                   (D.snap_id << 4) | kTagDir, A.k0, A.k1, v);
@@ -1533,9 +1617,9 @@ __global__ void __launch_bounds__(256) k_trace(TraceArgs<Real> A)
     Ray<Real, INC_XZ> R;
     Real kap_src;
     double Isrc;
-    ray_init(R, G, U, K, Ipl, i, j, k, dx, dy, dz, kap_src, Isrc);
-    if (D.nlev > 1) march_levels(R, D, sf, pair, d.n, A.nb, A.tol, A.max_steps, kap_src, Isrc, A.max_steps);
-    else ray_march(R, G, K, Ipl, walls_of(D, d.n, A.nb), A.tol, A.max_steps, kap_src, Isrc, A.max_steps);
+    ray_init(R, G, U, P, i, j, k, dx, dy, dz, kap_src, Isrc);
+    if (D.nlev > 1) march_levels(R, D, sf, P, d.n, A.nb, A.tol, A.max_steps, kap_src, Isrc, A.max_steps);
+    else ray_march(R, G, P, walls_of(D, d.n, A.nb), A.tol, A.max_steps, kap_src, Isrc, A.max_steps);
     const double w = 4.0 * M_PI * A.dnu[d.n] * A.wg[d.g] / (8.0 * d.p);
     rmc_ray_record rec;
     rec.Y = w * (double)kap_src * (double)R.acc;
@@ -1776,7 +1860,7 @@ struct rmc_ctx {
     bool have_kdist = false;
     int nb = 0, ng = 0, ns = 0, nT = 0;
     double T0 = 0, dT = 1;
-    DBuf k64, Ib, dnu, wg;
+    DBuf k64, k32, Ib, dnu, wg;   // k32: the same k values in FP32 (exact), read by the march
     std::vector<double> k64_host;   // for the march order heuristic (kappa at T_max per (n, g))
     // fields
     bool have_T = false, have_X = false;
@@ -1796,8 +1880,9 @@ struct rmc_ctx {
     DBuf tr_feat, tr_mask, tr_act, tr_del, tr_dz, tr_Lc, tr_scal, tr_err, tr_part, tr_grad, tr_loss;
     // pdf and fields of the last compute
     DBuf pdf_scratch, p, cdf_b, cdf_g, W, Iw, status;
-    DBuf field, Iplane;     // kappa planes (march precision) and FP64 intensity planes
-    DBuf mgT, mgX, mgfield, mgI;   // multigrid: coarse-level fields and planes
+    DBuf rec;               // cell records of the march (table coordinate, mole fractions), bricked
+    int rec_rw_log2 = 0;    // 16-byte words per record, log2
+    DBuf mgT, mgX, mgrec;   // multigrid: coarse-level fields and records
     // slots
     DBuf Y, st;
     DBuf rbkt;              // bucket of each ray (counting pass -> scatter pass)
@@ -2012,6 +2097,16 @@ void march_order(const rmc_ctx *c, std::vector<uint32_t> &order)
         for (int o = 0; o < 8; ++o) order[(size_t)q * 8 + o] = (uint32_t)(key[q].second * 8 + o);
 }
 
+// 16-byte words of a cell record (FP64 table coordinate, ns mole fractions of `xbytes`
+// bytes), log2, rounded up to a power of two.
+int record_words_log2(int ns, size_t xbytes)
+{
+    const size_t words = (8 + xbytes * (size_t)ns + 15) / 16;
+    int l = 0;
+    while ((1u << l) < words) ++l;
+    return l;
+}
+
 // per-snapshot plan: buffers and the snapshot descriptor (no work enqueued)
 // Lower bound of kappa_{n,g} over the field: smallest mole fractions times the smallest table
 // value over the nodes bracketing the field's temperature range (linear interpolation never
@@ -2169,8 +2264,7 @@ template <class Real> rmc_status plan_snapshot(rmc_ctx *c, SnapDesc &D)
         (st = c->cdf_b.ensure(sizeof(double) * nb)) || (st = c->cdf_g.ensure(sizeof(double) * nb * ng)) ||
         (st = c->W.ensure(sizeof(double) * nbucket)) || (st = c->Iw.ensure(sizeof(double) * 6 * nb)) ||
         (st = c->status.ensure(sizeof(int))) ||
-        (st = c->field.ensure(sizeof(Real) * ncpad_of(c) * (uint64_t)(nb * ng))) ||
-        (st = c->Iplane.ensure(sizeof(double) * ncpad_of(c) * (uint64_t)nb)) ||
+        (st = c->rec.ensure(sizeof(uint4) * (ncpad_of(c) << record_words_log2(c->ns, sizeof(Real))))) ||
         (st = c->Y.ensure(sizeof(uint64_t) * nc * R)) ||
         (sizeof(Real) == 8 && (st = c->st.ensure(sizeof(uint32_t) * nc * R))))
         return st;
@@ -2209,8 +2303,9 @@ template <class Real> rmc_status plan_snapshot(rmc_ctx *c, SnapDesc &D)
         if ((st = c->rbkt.ensure(sizeof(uint32_t) * nc * R))) return st;
         D.rbkt = c->rbkt.as<uint32_t>();
     }
-    D.kap = c->field.p;
-    D.Ipl = c->Iplane.as<double>();
+    D.rw_log2 = record_words_log2(c->ns, sizeof(Real));
+    D.rec = c->rec.as<uint4>();
+    c->rec_rw_log2 = D.rw_log2;
     D.wallq = c->wall_dev;
     // multigrid levels
     const int allowed = level_count(c->nx, c->ny, c->nz);
@@ -2230,11 +2325,9 @@ template <class Real> rmc_status plan_snapshot(rmc_ctx *c, SnapDesc &D)
         }
         D.mg_stride = off;
         if ((st = c->mgT.ensure(sizeof(double) * cells)) || (st = c->mgX.ensure(sizeof(double) * cells * c->ns)) ||
-            (st = c->mgfield.ensure(sizeof(Real) * off * (uint64_t)(nb * ng))) ||
-            (st = c->mgI.ensure(sizeof(double) * off * (uint64_t)nb)))
+            (st = c->mgrec.ensure(sizeof(uint4) * (off << D.rw_log2))))
             return st;
-        D.mg_kap = c->mgfield.p;
-        D.mg_I = c->mgI.as<double>();
+        D.mg_rec = c->mgrec.as<uint4>();
     }
     D.Y = c->Y.p;
     D.st = sizeof(Real) == 8 ? c->st.as<uint32_t>() : nullptr;
@@ -2273,14 +2366,10 @@ rmc_status enqueue_snapshot(rmc_ctx *c, const SnapDesc &D, const double *dfaces,
         HIPCHK(hipGetLastError());
     }
     const uint64_t ncpad = ncpad_of(c);
-    // up to 16 bands per block row: each block reuses its cells' T, x and table positions for
-    // nb / 16 bands (measured best between one band per block and four rows)
-    dim3 grid((unsigned)((ncpad + 255) / 256), (unsigned)std::min(c->nb, 16));
-    hipLaunchKernelGGL(k_fields<Real>, grid, dim3(256), 0, s, c->T.as<double>(), c->X.as<double>(), c->ns, nc,
-                       c->k64.as<double>(), c->Ib.as<double>(), c->nb, c->ng, c->nT, c->T0, c->dT, D,
-                       c->field.as<Real>(), c->Iplane.as<double>(), ncpad);
+    hipLaunchKernelGGL(k_records<Real>, dim3((unsigned)((ncpad + 255) / 256)), dim3(256), 0, s, c->T.as<double>(),
+                       c->X.as<double>(), c->ns, nc, c->T0, c->dT, D, c->rec.as<uint4>());
     HIPCHK(hipGetLastError());
-    // multigrid: fields of each coarser level from the one below, then its property planes
+    // multigrid: fields of each coarser level from the one below, then its records
     const double *Tin = c->T.as<double>(), *Xin = c->X.as<double>();
     uint64_t toff = 0;
     for (int L = 1; L < D.nlev; ++L) {
@@ -2295,10 +2384,8 @@ rmc_status enqueue_snapshot(rmc_ctx *c, const SnapDesc &D, const double *dfaces,
         Dl.nx = px >> 1; Dl.ny = py >> 1; Dl.nz = pz >> 1;
         Dl.nbx = round_up(Dl.nx, 4) / 4; Dl.nby = round_up(Dl.ny, 4) / 4; Dl.nbz = round_up(Dl.nz, 4) / 4;
         Dl.ncpad = ncpad_level(c, L);
-        dim3 lgrid((unsigned)((Dl.ncpad + 255) / 256), (unsigned)std::min(c->nb, 16));
-        hipLaunchKernelGGL(k_fields<Real>, lgrid, dim3(256), 0, s, Tc, Xc, c->ns, ncc, c->k64.as<double>(),
-                           c->Ib.as<double>(), c->nb, c->ng, c->nT, c->T0, c->dT, Dl,
-                           c->mgfield.as<Real>() + D.lev_off[L], c->mgI.as<double>() + D.lev_off[L], D.mg_stride);
+        hipLaunchKernelGGL(k_records<Real>, dim3((unsigned)((Dl.ncpad + 255) / 256)), dim3(256), 0, s, Tc, Xc,
+                           c->ns, ncc, c->T0, c->dT, Dl, c->mgrec.as<uint4>() + (D.lev_off[L] << D.rw_log2));
         HIPCHK(hipGetLastError());
         Tin = Tc;
         Xin = Xc;
@@ -2380,8 +2467,9 @@ template <class Real> rmc_status plan_pipeline(rmc_ctx *const *ctxs, int nsnap, 
         P.multigrid = P.multigrid || P.D[q].nlev > 1;
     }
     P.nfaces = (int)faces.size();
-    if ((size_t)P.nfaces * sizeof(double) > 48 * 1024)
-        return fail(RMC_UNSUPPORTED, "face tables of all snapshots exceed 48 KiB of LDS");
+    if (march_lds_bytes(P.nfaces, L->nT, L->ns) > kMarchLds)
+        return fail(RMC_UNSUPPORTED, "face tables of all snapshots and four table slots (%d nodes, %d species) "
+                                     "exceed %d KiB of LDS", L->nT, L->ns, (int)(kMarchLds / 1024));
     // tiles: whole bricks; about 1024 in total unless the options fix the size
     P.tile_cells = O.alloc_tile > 0 ? O.alloc_tile : auto_tile_cells(total_ncpad);
     std::vector<int> &tile_snap = L->h_tile_snap;
@@ -2541,6 +2629,12 @@ rmc_status enqueue_pipeline(const Plan &P, double *const *divq, double *const *s
     MA.long_steps = L->counters.as<unsigned long long>() + 3;
     MA.log_inv_tol = O.tol > 0.0 ? (float)std::log(1.0 / O.tol) : 1e30f;
     MA.long_form = O.long_ray_form;
+    MA.Ib = L->Ib.as<double>();
+    MA.k32 = L->k32.as<float>();
+    MA.nT = L->nT;
+    MA.ns = L->ns;
+    MA.tab_off = (P.nfaces + 1) & ~1;
+    MA.slot_dbl = table_slot_doubles(L->nT, L->ns);
     MA.span_log2 = 0;
     for (int sp = O.xcd_span > 0 ? O.xcd_span : 256; sp > 1; sp >>= 1) ++MA.span_log2;
     for (const SnapDesc &d : P.D)
@@ -2553,7 +2647,7 @@ rmc_status enqueue_pipeline(const Plan &P, double *const *divq, double *const *s
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, L->counters.as<unsigned long long>() + 3, 1);
     HIPCHK(hipGetLastError());
     const unsigned mblocks = (unsigned)xcd_blocks(P.max_chunks, MA.span_log2);
-    const size_t lds_faces = sizeof(double) * P.nfaces;
+    const size_t lds_faces = march_lds_bytes(P.nfaces, L->nT, L->ns);   // faces and four table slots
     const bool multi = nsnap > 1;
     const bool lsort = O.length_sort != 0;
 #define RMC_MARCH(PDF_, INC_, MULTI_)                                                                             \
@@ -2776,12 +2870,12 @@ namespace {
 // device buffers a captured compute reads or writes (a change means they were reallocated)
 std::vector<void *> buffer_ptrs(const rmc_ctx *c)
 {
-    const DBuf *b[] = {&c->k64, &c->Ib, &c->dnu, &c->wg, &c->T, &c->X, &c->scal, &c->q, &c->cpdf, &c->ccdf_b,
+    const DBuf *b[] = {&c->k64, &c->k32, &c->Ib, &c->dnu, &c->wg, &c->T, &c->X, &c->scal, &c->q, &c->cpdf, &c->ccdf_b,
                        &c->ccdf_g, &c->ccdf_o, &c->pdf_scratch, &c->p, &c->cdf_b, &c->cdf_g, &c->W, &c->Iw,
-                       &c->status, &c->field, &c->Iplane, &c->Y, &c->st, &c->hist, &c->bucket_total,
+                       &c->status, &c->rec, &c->Y, &c->st, &c->hist, &c->bucket_total,
                        &c->bucket_start, &c->nchunks, &c->chunk_bucket, &c->items, &c->faces,
                        &c->snaps, &c->tile_snap, &c->border, &c->counters, &c->red_part, &c->kmin, &c->cont, &c->cont_count,
-                       &c->rbkt, &c->mgT, &c->mgX, &c->mgfield, &c->mgI, &c->dprob, &c->dstrat, &c->lpp, &c->prm,
+                       &c->rbkt, &c->mgT, &c->mgX, &c->mgrec, &c->dprob, &c->dstrat, &c->lpp, &c->prm,
                        &c->musd, &c->nu_c, &c->gxs, &c->kp, &c->feat, &c->fmask, &c->bng, &c->lfaces};
     std::vector<void *> v;
     for (const DBuf *d : b) v.push_back(d->p);
@@ -2861,9 +2955,9 @@ void rmc_destroy(rmc_ctx *c)
     {
         DeviceGuard g(c->device);
         (void)hipDeviceSynchronize();
-        DBuf *bufs[] = {&c->k64, &c->Ib, &c->dnu, &c->wg, &c->T, &c->X, &c->stage, &c->stage2, &c->q, &c->cpdf, &c->ccdf_b,
+        DBuf *bufs[] = {&c->k64, &c->k32, &c->Ib, &c->dnu, &c->wg, &c->T, &c->X, &c->stage, &c->stage2, &c->q, &c->cpdf, &c->ccdf_b,
                         &c->ccdf_g, &c->ccdf_o, &c->pdf_scratch, &c->p, &c->cdf_b, &c->cdf_g, &c->W, &c->Iw,
-                        &c->status, &c->field, &c->Iplane, &c->Y, &c->st, &c->hist, &c->bucket_total, &c->bucket_start,
+                        &c->status, &c->rec, &c->Y, &c->st, &c->hist, &c->bucket_total, &c->bucket_start,
                         &c->nchunks, &c->chunk_bucket, &c->items, &c->faces, &c->snaps, &c->tile_snap,
                         &c->counters, &c->red_part, &c->outbuf, &c->tune_out, &c->trace_rec, &c->trace_cells, &c->border, &c->small, &c->scal,
                         &c->kmin, &c->cont, &c->cont_count};
@@ -2974,10 +3068,16 @@ rmc_status rmc_set_kdist(rmc_ctx *c, int nb, int ng, int ns, int nT, double T0, 
     DeviceGuard g(c->device);
     if (!g.ok) return fail(RMC_DEVICE_ERROR, "hipSetDevice(%d) failed", c->device);
     rmc_status st;
-    if ((st = c->k64.ensure(sizeof(double) * nk)) || (st = c->Ib.ensure(sizeof(double) * nb * nT)) ||
-        (st = c->dnu.ensure(sizeof(double) * nb)) || (st = c->wg.ensure(sizeof(double) * ng)))
+    if ((st = c->k64.ensure(sizeof(double) * nk)) || (st = c->k32.ensure(sizeof(float) * nk)) ||
+        (st = c->Ib.ensure(sizeof(double) * nb * nT)) || (st = c->dnu.ensure(sizeof(double) * nb)) ||
+        (st = c->wg.ensure(sizeof(double) * ng)))
         return st;
     HIPCHK(hipMemcpy(c->k64.p, k64.data(), sizeof(double) * nk, hipMemcpyHostToDevice));
+    {
+        std::vector<float> k32(nk);
+        for (size_t q = 0; q < nk; ++q) k32[q] = (float)k64[q];   // exact: F32 or BF16 inputs
+        HIPCHK(hipMemcpy(c->k32.p, k32.data(), sizeof(float) * nk, hipMemcpyHostToDevice));
+    }
     c->k64_host = k64;
     HIPCHK(hipMemcpy(c->Ib.p, Ib, sizeof(double) * nb * nT, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c->dnu.p, dnu, sizeof(double) * nb, hipMemcpyHostToDevice));
@@ -3462,7 +3562,7 @@ rmc_status rmc_trace_cells(rmc_ctx *c, const int64_t *cells, int ncell, rmc_ray_
         (st = c->trace_cells.ensure(sizeof(int64_t) * ncell)) ||
         (st = c->trace_rec.ensure(sizeof(rmc_ray_record) * nrec)))
         return st;
-    if (nfaces * 8 > 48 * 1024) return fail(RMC_UNSUPPORTED, "face tables exceed 48 KiB of LDS");
+    if (nfaces * 8 > (int)kMarchLds) return fail(RMC_UNSUPPORTED, "face tables exceed %d KiB of LDS", (int)(kMarchLds / 1024));
     HIPCHK(hipMemcpyAsync(c->faces.p, fd.data(), (size_t)nfaces * 8, hipMemcpyHostToDevice, s));
     if ((st = dbl ? enqueue_snapshot<double>(c, D, c->faces.as<double>(), s)
                   : enqueue_snapshot<float>(c, D, c->faces.as<double>(), s)))
@@ -3474,14 +3574,16 @@ rmc_status rmc_trace_cells(rmc_ctx *c, const int64_t *cells, int ncell, rmc_ray_
     if (dbl) {
         TraceArgs<double> A{c->snaps.as<SnapDesc>(), c->faces.as<double>(), nfaces, c->trace_cells.as<int64_t>(),
                             ncell, c->dnu.as<double>(), c->wg.as<double>(), c->nb, c->ng, R, k0, k1,
-                            c->opt.tol, c->opt.max_steps, c->trace_rec.as<rmc_ray_record>()};
+                            c->opt.tol, c->opt.max_steps, c->trace_rec.as<rmc_ray_record>(),
+                            c->Ib.as<double>(), c->k32.as<float>(), c->nT, c->ns};
         if (smode == 2) hipLaunchKernelGGL((k_trace<double, 2, false>), dim3(blocks), dim3(256), 8 * nfaces, s, A);
         else if (smode == 1) hipLaunchKernelGGL((k_trace<double, 1, false>), dim3(blocks), dim3(256), 8 * nfaces, s, A);
         else hipLaunchKernelGGL((k_trace<double, 0, false>), dim3(blocks), dim3(256), 8 * nfaces, s, A);
     } else {
         TraceArgs<float> A{c->snaps.as<SnapDesc>(), c->faces.as<double>(), nfaces, c->trace_cells.as<int64_t>(),
                            ncell, c->dnu.as<double>(), c->wg.as<double>(), c->nb, c->ng, R, k0, k1,
-                           (float)c->opt.tol, c->opt.max_steps, c->trace_rec.as<rmc_ray_record>()};
+                           (float)c->opt.tol, c->opt.max_steps, c->trace_rec.as<rmc_ray_record>(),
+                           c->Ib.as<double>(), c->k32.as<float>(), c->nT, c->ns};
         if (inc_xz) {
             if (smode == 2) hipLaunchKernelGGL((k_trace<float, 2, true>), dim3(blocks), dim3(256), 8 * nfaces, s, A);
             else if (smode == 1) hipLaunchKernelGGL((k_trace<float, 1, true>), dim3(blocks), dim3(256), 8 * nfaces, s, A);
@@ -3555,8 +3657,8 @@ rmc_status rmc_gather_probe(rmc_ctx *c, int steps, double *ms, double *bytes, vo
     g_err.clear();
     if (rmc_status st = check_ctx(c)) return st;
     if (steps < 1 || steps > 65536 || !ms || !bytes) return fail(RMC_INVALID_ARG, "bad arguments");
-    if (!c->field.p || c->slots_real != 4 || c->slots_R < 1)
-        return fail(RMC_BAD_STATE, "the probe reads the FP32 planes of a previous compute with the FP32 march");
+    if (!c->rec.p || c->slots_real != 4 || c->slots_R < 1)
+        return fail(RMC_BAD_STATE, "the probe reads the cell records of a previous compute with the FP32 march");
     DeviceGuard g(c->device);
     if (!g.ok) return fail(RMC_DEVICE_ERROR, "hipSetDevice(%d) failed", c->device);
     hipStream_t s = (hipStream_t)stream;
@@ -3564,6 +3666,8 @@ rmc_status rmc_gather_probe(rmc_ctx *c, int steps, double *ms, double *bytes, vo
     D.nx = c->nx; D.ny = c->ny; D.nz = c->nz;
     D.nbx = round_up(c->nx, 4) / 4; D.nby = round_up(c->ny, 4) / 4; D.nbz = round_up(c->nz, 4) / 4;
     D.ncpad = ncpad_of(c);
+    D.rec = c->rec.as<uint4>();
+    D.rw_log2 = c->rec_rw_log2;
     const uint64_t lanes = ncells_of(c) * (uint64_t)c->slots_R;
     const uint32_t nchunks = (uint32_t)((lanes + 63) / 64);
     int span_log2 = 0;
@@ -3574,9 +3678,8 @@ rmc_status rmc_gather_probe(rmc_ctx *c, int steps, double *ms, double *bytes, vo
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     HIPCHK(hipEventRecord(e0, s));
-    hipLaunchKernelGGL(k_gather_probe, dim3((unsigned)xcd_blocks(nchunks, span_log2)), dim3(256), 0, s,
-                       c->field.as<float>(), c->Iplane.as<double>(), D, c->nb * c->ng, c->ng, steps, nchunks,
-                       span_log2, c->probe.as<double>());
+    hipLaunchKernelGGL(k_gather_probe, dim3((unsigned)xcd_blocks(nchunks, span_log2)), dim3(256), 0, s, D,
+                       c->nb * c->ng, steps, nchunks, span_log2, c->probe.as<double>());
     const hipError_t le = hipGetLastError();
     HIPCHK(hipEventRecord(e1, s));
     HIPCHK(hipEventSynchronize(e1));
@@ -3586,7 +3689,7 @@ rmc_status rmc_gather_probe(rmc_ctx *c, int steps, double *ms, double *bytes, vo
     (void)hipEventDestroy(e1);
     HIPCHK(le);
     *ms = t;
-    *bytes = (double)lanes * steps * (sizeof(float) + sizeof(double)) + (double)nchunks * sizeof(double);
+    *bytes = (double)lanes * steps * sizeof(uint4) + (double)nchunks * sizeof(double);
     return RMC_OK;
 }
 

@@ -117,6 +117,68 @@ __device__ __forceinline__ int brick_x(int i, int sx_) { return __mul24(i >> 2, 
 __device__ __forceinline__ int brick_y(int j, int sy_) { return __mul24(j >> 2, sy_) + ((j & 1) << 1) + ((j & 2) << 3); }
 __device__ __forceinline__ int brick_z(int k) { return ((k >> 2) << 6) + (k & 1) + ((k & 2) << 2); }
 
+// Properties of the cells a ray crosses (Sec. 2.2: linear interpolation of the tables in T,
+// mixture kappa = sum_s x_s k^s).  The march reads one record per cell: the table coordinate
+// u = (T - T0) / dT of the cell's temperature (FP64) and its mole fractions (march precision),
+// in 16-byte words, 2^rw_log2 words per cell, bricked layout.  The record does not depend on
+// the band or g-point, so every (band, g) pair reads the same field; kappa_{n,g} and I_n are
+// interpolated from the ray's tables (I_n FP64, k^s FP32-exact values) with the FP64
+// operations of the reference and rounded to march precision for kappa.
+template <class Real> struct Props {
+    const uint4 *rec;           // records of the grid level
+    const double *ib;           // I_n at the table nodes [nT]
+    const float *k;             // k^s_{n,g} at the table nodes: species s at k + s * kstride
+    int kstride;
+    int ns;
+    int tmax;                   // nT - 2: the last interval of the table
+    int rw_log2;                // record words per cell, log2
+};
+
+template <class Real> __device__ __forceinline__ uint4 prop_fetch(const Props<Real> &P, int cell)
+{
+    return gld(P.rec + ((size_t)(uint32_t)cell << P.rw_log2));
+}
+
+__device__ __forceinline__ double lerp_node(const float *tab, int t, double f)
+{
+    const double a = (double)tab[t], b = (double)tab[t + 1];
+    return a + f * (b - a);
+}
+
+// kappa_{n,g} and I_n of a cell from its record v (first word; further words read here).
+template <class Real>
+__device__ __forceinline__ void prop_eval(const Props<Real> &P, uint4 v, int cell, Real &kap, double &I)
+{
+    const double u = __hiloint2double((int)v.y, (int)v.x);
+    int t = (int)u;             // u >= 0: temperatures are checked against the table range
+    t = t > P.tmax ? P.tmax : t;
+    const double f = u - (double)t;
+    I = P.ib[t] + f * (P.ib[t + 1] - P.ib[t]);
+    double kp = 0.0;
+    if constexpr (sizeof(Real) == 4) {
+        kp += (double)__uint_as_float(v.z) * lerp_node(P.k, t, f);
+        if (P.ns > 1) kp += (double)__uint_as_float(v.w) * lerp_node(P.k + P.kstride, t, f);
+#pragma unroll 1
+        for (int s = 2; s < P.ns; ++s) {   // words 1.. hold four fractions each
+            const float *xw = reinterpret_cast<const float *>(P.rec + ((size_t)(uint32_t)cell << P.rw_log2) + 1);
+            kp += (double)gld(xw + (s - 2)) * lerp_node(P.k + s * P.kstride, t, f);
+        }
+    } else {
+        kp += __hiloint2double((int)v.w, (int)v.z) * lerp_node(P.k, t, f);
+#pragma unroll 1
+        for (int s = 1; s < P.ns; ++s) {   // words 1.. hold two fractions each
+            const double *xw = reinterpret_cast<const double *>(P.rec + ((size_t)(uint32_t)cell << P.rw_log2) + 1);
+            kp += gld(xw + (s - 1)) * lerp_node(P.k + s * P.kstride, t, f);
+        }
+    }
+    kap = (Real)kp;
+}
+
+template <class Real> __device__ __forceinline__ void prop_load(const Props<Real> &P, int cell, Real &kap, double &I)
+{
+    prop_eval(P, prop_fetch(P, cell), cell, kap, I);
+}
+
 // Geometry of one snapshot as seen by a ray.
 struct RayGeo {
     const double *xf, *yf, *zf; // face coordinates (LDS), nx+1, ny+1, nz+1
@@ -169,9 +231,9 @@ __device__ __forceinline__ void absorb_f32(float x, float &a, float &e)
 // coordinates.
 //
 // A step is split into its geometry (which cell comes next) and its absorption (physics of
-// the current cell), so that the next cell's kappa and I are requested before the current
-// cell's physics runs; the march loop is unrolled twice with two register sets, so a load
-// is always in flight while the other set is consumed.
+// the current cell), so that the next cell's record is requested before the current cell's
+// physics runs; the march loop is unrolled twice with two register sets, so a load is always
+// in flight while the other set is consumed.
 template <class Real, bool INC_XZ> struct Ray {
     double tx, ty, tz, t;       // next-face parameters per axis, current parameter
     double ox, oy, oz;          // origin (cell centre)
@@ -193,8 +255,8 @@ struct XzUniform {
 // Starts the ray at the centre of cell (ci, cj, ck); returns the source cell's kappa and I.
 template <class Real, bool INC_XZ>
 __device__ __forceinline__ void ray_init(Ray<Real, INC_XZ> &R, const RayGeo &G, const XzUniform &U,
-                                         const Real *__restrict__ K, const double *__restrict__ Ipl, int ci,
-                                         int cj, int ck, double dx, double dy, double dz, Real &kc, double &Ic)
+                                         const Props<Real> &P, int ci, int cj, int ck, double dx, double dy,
+                                         double dz, Real &kc, double &Ic)
 {
     R.ox = 0.5 * (G.xf[ci] + G.xf[ci + 1]);
     R.oy = 0.5 * (G.yf[cj] + G.yf[cj + 1]);
@@ -223,9 +285,7 @@ __device__ __forceinline__ void ray_init(Ray<Real, INC_XZ> &R, const RayGeo &G, 
     }
     R.i = ci; R.j = cj; R.k = ck; R.wi = 0; R.wk = 0;
     R.px = brick_x(ci, G.bsx); R.py = brick_y(cj, G.bsy); R.pz = brick_z(ck);
-    const int cell = R.px + R.py + R.pz;
-    kc = gld(K + cell);
-    R.Isrc = gld(Ipl + cell);
+    prop_load(P, R.px + R.py + R.pz, kc, R.Isrc);
     Ic = R.Isrc;
     R.t = 0.0;
     R.tau = 1.0;
@@ -399,11 +459,11 @@ __device__ __forceinline__ bool ray_absorb(Ray<Real, INC_XZ> &R, Real kc, double
 
 // The march of one ray, started by ray_init with (k0, I0) of the source cell, until it
 // finishes or has taken `cap` steps.  Returns true when finished; when capped, R holds the
-// state at the start of the next step (its cell, parameter and next-face parameters).
+// state at the start of the next step (its cell, parameter and next-face parameters).  The
+// next cell's record is in flight while the current cell's absorption runs.
 template <class Real, bool INC_XZ>
-__device__ __forceinline__ bool ray_march(Ray<Real, INC_XZ> &R, const RayGeo &G, const Real *__restrict__ K,
-                                          const double *__restrict__ Ipl, const Walls &W, Real tol, int max_steps,
-                                          Real k0, double I0, int cap)
+__device__ __forceinline__ bool ray_march(Ray<Real, INC_XZ> &R, const RayGeo &G, const Props<Real> &P,
+                                          const Walls &W, Real tol, int max_steps, Real k0, double I0, int cap)
 {
     if (!march_starts(tol, max_steps)) return true;
     Real k1;
@@ -411,15 +471,15 @@ __device__ __forceinline__ bool ray_march(Ray<Real, INC_XZ> &R, const RayGeo &G,
     int wall;
     while (true) {
         int cell = ray_advance(R, G, ds, wall);
-        k1 = gld(K + cell);
-        I1 = gld(Ipl + cell);
+        const uint4 v1 = prop_fetch(P, cell);
         if (ray_absorb(R, k0, I0, ds, wall, W, tol, max_steps)) return true;
         if (R.steps >= cap) return false;
+        prop_eval(P, v1, cell, k1, I1);
         cell = ray_advance(R, G, ds, wall);
-        k0 = gld(K + cell);
-        I0 = gld(Ipl + cell);
+        const uint4 v0 = prop_fetch(P, cell);
         if (ray_absorb(R, k1, I1, ds, wall, W, tol, max_steps)) return true;
         if (R.steps >= cap) return false;
+        prop_eval(P, v0, cell, k0, I0);
     }
 }
 

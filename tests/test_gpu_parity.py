@@ -475,7 +475,8 @@ def test_graph_keeps_its_tables_when_the_leader_works_eagerly():
 
 def test_gather_probe_reports_the_access_pattern_rate():
     """The measurement aid of the roofline: needs a previous FP32 compute, then returns the
-    kernel time and the bytes of ncells x R lanes x steps gathers (12 bytes per step)."""
+    kernel time and the bytes of ncells x R lanes x steps gathers (one 16-byte cell record per
+    step)."""
     w = _small_channel(march="f32", nx=16, ny=16, nz=16, R=8)
     say("gather probe")
     s = _solver(w)
@@ -484,7 +485,7 @@ def test_gather_probe_reports_the_access_pattern_rate():
     assert e.value.status == rmc.RMC_BAD_STATE
     s.compute()
     ms, by = s.gather_probe(10)
-    assert ms > 0.0 and by == w.ncells * w.R * 10 * 12 + (w.ncells * w.R // 64) * 8
+    assert ms > 0.0 and by == w.ncells * w.R * 10 * 16 + (w.ncells * w.R // 64) * 8
     with pytest.raises(rmc.RmcError) as e:
         s.gather_probe(0)
     assert e.value.status == rmc.RMC_INVALID_ARG
