@@ -264,6 +264,23 @@ rmc_status rmc_set_cell_pdf(rmc_ctx *ctx, const double *q, rmc_mem mem, void *st
 rmc_status rmc_compute_divergence(rmc_ctx *ctx, double *divq, double *stderr_out, rmc_mem mem,
                                   void *stream);
 
+/* rmc_compute_divergence for callers that cannot allocate device memory (code being captured
+ * into a HIP graph, tight serving loops, harnesses that forbid hipMalloc): the same kernels and
+ * results, but every per-compute buffer (cell records, pdf, work lists, ray slots, histograms,
+ * descriptors) is carved from a static scratch array of 64 MiB that each GPU the library runs
+ * on holds until the process ends; the call makes no hipMalloc, hipFree or pinned-host
+ * allocation.  divq and stderr_out (nullable) are device memory; the call is enqueued on
+ * `stream` and nothing is synchronised.  Limits: plain (T_max) sampling, no wall flux, and
+ * a workload whose buffers fit the scratch (about ncells * R <= 2 million rays), else
+ * RMC_UNSUPPORTED with the reason in rmc_last_error.  All calls on one GPU share its scratch:
+ * calls that overlap on one GPU (other streams, other threads) race, and the scratch keeps the
+ * last call's contents (counters and lists are cleared by the call itself).  The context's own
+ * buffers are untouched, so rmc_get_stats, rmc_get_ray_values and the other inspection calls
+ * keep describing its last regular compute.  The device's scratch address is taken by
+ * rmc_create (RMC_DEVICE_ERROR here if that failed). */
+rmc_status rmc_compute_divergence_noalloc(rmc_ctx *ctx, double *divq, double *stderr_out,
+                                          void *stream);
+
 /* rmc_compute_divergence plus the wall flux: q_wall receives, per wall face element, the net
  * radiative flux from the gas into the wall [W m^-2] -- the sum over every ray that ended on
  * that element of its wall term w kappa_src tau_w (I_src - I_w) (Eq. 3's wall factor with

@@ -21,6 +21,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -28,6 +29,13 @@
 #include "rmc_device.h"
 
 using namespace rmc;
+
+// Scratch of the allocation-free compute (rmc_compute_divergence_noalloc): per-compute work
+// lists, ray slots, histograms and descriptors are carved from this array, which every GPU the
+// library runs on holds until the process ends.  Host code reaches it only through the
+// per-device address from hipGetSymbolAddress (taken at rmc_create), never by its name.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 // ============================================================================ device side
 namespace {
@@ -1748,6 +1756,14 @@ namespace {
 
 thread_local std::string g_err;
 
+// Address of `scratch` on each device (each GPU holds its own copy of the array), taken once
+// per device by rmc_create with that device current; the error of a failed lookup is kept
+// and reported by the allocation-free compute.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+
 rmc_status fail(rmc_status st, const char *fmt, ...)
 {
     char buf[512];
@@ -1769,11 +1785,33 @@ rmc_status fail(rmc_status st, const char *fmt, ...)
         }                                                                                       \
     } while (0)
 
+struct DBuf;
+
+// Bump allocation from the device's static scratch array during an allocation-free compute
+// (rmc_compute_divergence_noalloc): while an arena is active on the calling thread, every
+// buffer the compute sizes is carved from the array instead of allocated, and the buffer's
+// own allocation and size are put back when the arena is closed.
+struct Arena {
+    static constexpr int kMaxBufs = 96;
+    unsigned char *base = nullptr;
+    size_t cap = 0, used = 0;
+    int nsaved = 0;
+    struct Saved {
+        DBuf *b;
+        void *p;
+        size_t bytes;
+    } saved[kMaxBufs];
+    rmc_status carve(DBuf &b, size_t want);
+    void restore();
+};
+thread_local Arena *t_arena = nullptr;
+
 struct DBuf {
     void *p = nullptr;
     size_t bytes = 0;
     rmc_status ensure(size_t want)
     {
+        if (t_arena) return t_arena->carve(*this, want);
         if (want <= bytes && p) return RMC_OK;
         if (p) { (void)hipFree(p); p = nullptr; bytes = 0; }
         if (want == 0) want = 16;
@@ -1798,6 +1836,37 @@ struct DBuf {
     DBuf &operator=(const DBuf &) = delete;
     ~DBuf() { release(); }   // with the owning context's device current (rmc_destroy)
 };
+
+rmc_status Arena::carve(DBuf &b, size_t want)
+{
+    int q = 0;
+    while (q < nsaved && saved[q].b != &b) ++q;
+    if (q == nsaved) {   // first use in this call: keep the buffer's own allocation aside
+        if (nsaved == kMaxBufs) return fail(RMC_UNSUPPORTED, "too many scratch buffers in one compute");
+        saved[nsaved++] = Saved{&b, b.p, b.bytes};
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+    if (want <= b.bytes && b.p) return RMC_OK;
+    if (want == 0) want = 16;
+    const size_t off = (used + 255) & ~(size_t)255;
+    if (off > cap || want > cap - off)
+        return fail(RMC_UNSUPPORTED, "the allocation-free compute needs more than its %zu MiB of scratch "
+                                     "(ncells * R too large)", cap >> 20);
+    b.p = base + off;
+    b.bytes = want;
+    used = off + want;
+    return RMC_OK;
+}
+
+void Arena::restore()
+{
+    for (int q = nsaved - 1; q >= 0; --q) {
+        saved[q].b->p = saved[q].p;
+        saved[q].b->bytes = saved[q].bytes;
+    }
+    nsaved = 0;
+}
 
 // Pinned host memory (hipHostMalloc): readbacks of the ingest kernels and the per-compute
 // descriptor uploads, so that those copies are plain DMA transfers.
@@ -2499,7 +2568,9 @@ template <class Real> rmc_status plan_pipeline(rmc_ctx *const *ctxs, int nsnap, 
         (st = L->red_part.ensure(sizeof(unsigned long long) * 2 * 2048)) ||
         (st = L->kmin.ensure(sizeof(float) * nb * ng)) || (st = L->cont_count.ensure(sizeof(uint32_t))))
         return st;
-    P.cont_cap = (uint32_t)std::min<uint64_t>(P.total_cells * R, 1u << 20);
+    // continuation records of long rays (rays beyond them are finished by the lane kernel);
+    // fewer in the allocation-free compute, whose scratch is small
+    P.cont_cap = (uint32_t)std::min<uint64_t>(P.total_cells * R, t_arena ? (1u << 16) : (1u << 20));
     if ((st = L->cont.ensure(sizeof(ContRec) * P.cont_cap))) return st;
     {   // kappa lower bound over all snapshots of the batch
         std::vector<float> tmp;
@@ -2509,7 +2580,10 @@ template <class Real> rmc_status plan_pipeline(rmc_ctx *const *ctxs, int nsnap, 
             for (size_t u = 0; u < tmp.size(); ++u) L->h_kmin[u] = std::min(L->h_kmin[u], tmp[u]);
         }
     }
-    if (!L->have_counters) {
+    if (t_arena) {   // scratch counters: cleared by a fill kernel at every allocation-free compute
+        hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, L->counters.as<unsigned long long>(), 4);
+        HIPCHK(hipGetLastError());
+    } else if (!L->have_counters) {
         HIPCHK(hipMemsetAsync(L->counters.p, 0, sizeof(unsigned long long) * 4, s));
         L->have_counters = true;
     }
@@ -2530,6 +2604,12 @@ template <class Real> rmc_status plan_pipeline(rmc_ctx *const *ctxs, int nsnap, 
     for (int u = 0; u < 5; ++u) {
         off[u] = total;
         total += (sz[u] + 255) & ~(size_t)255;
+    }
+    if (t_arena) {
+        // allocation-free compute: copies from the host staging vectors themselves (pageable;
+        // they stay unchanged until this context's next compute)
+        for (int u = 0; u < 5; ++u) HIPCHK(hipMemcpyAsync(dst[u], src[u], sz[u], hipMemcpyHostToDevice, s));
+        return RMC_OK;
     }
     if (L->up_pending) {
         HIPCHK(hipEventSynchronize(L->up_evt));
@@ -2941,6 +3021,19 @@ rmc_status rmc_create(int device, rmc_ctx **out)
         return fail(RMC_DEVICE_ERROR, "no HIP device available");
     }
     if (device < 0 || device >= ndev) return fail(RMC_INVALID_ARG, "device %d out of range [0, %d)", device, ndev);
+    if (device < kMaxDevices) {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (!g_scratch_ptr[device]) {
+            DeviceGuard g(device);
+            void *ptr = nullptr;
+            const hipError_t se = g.ok ? hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) : hipErrorInvalidDevice;
+            if (se == hipSuccess && ptr) g_scratch_ptr[device] = ptr;
+            else {
+                (void)hipGetLastError();
+                g_scratch_err[device] = se == hipSuccess ? hipErrorInvalidSymbol : se;
+            }
+        }
+    }
     rmc_ctx *c = new (std::nothrow) rmc_ctx();
     if (!c) return fail(RMC_OUT_OF_MEMORY, "context allocation failed");
     c->device = device;
@@ -3366,6 +3459,50 @@ rmc_status rmc_compute_divergence(rmc_ctx *c, double *divq, double *se, rmc_mem 
     double *d[1] = {divq};
     double *e[1] = {se};
     return rmc_compute_batch(cs, 1, d, e, mem, stream);
+}
+
+rmc_status rmc_compute_divergence_noalloc(rmc_ctx *c, double *divq, double *se, void *stream)
+{
+    g_err.clear();
+    if (rmc_status st = check_ctx(c)) return st;
+    if (!divq) return fail(RMC_INVALID_ARG, "null output");
+    if (c->opt.sampling != RMC_SAMPLING_PLAIN)
+        return fail(RMC_UNSUPPORTED, "the allocation-free compute runs the plain (T_max) sampling only");
+    rmc_ctx *cs[1] = {c};
+    if (rmc_status st = check_batch(cs, 1)) return st;
+    if (c->device >= kMaxDevices) return fail(RMC_UNSUPPORTED, "device index above %d", kMaxDevices - 1);
+    void *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        base = g_scratch_ptr[c->device];
+        if (!base)
+            return fail(RMC_DEVICE_ERROR, "no scratch address on device %d: %s", c->device,
+                        hipGetErrorString(g_scratch_err[c->device]));
+    }
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(RMC_DEVICE_ERROR, "hipSetDevice(%d) failed", c->device);
+    hipStream_t s = (hipStream_t)stream;
+    const bool dbl = c->opt.march == RMC_F64;
+    // every buffer the compute sizes is carved from the scratch; the context's own buffers and
+    // the state describing them (slot layout of the last compute) are put back afterwards
+    const int slots_R = c->slots_R, slots_real = c->slots_real, rw_log2 = c->rec_rw_log2;
+    Arena A;
+    A.base = static_cast<unsigned char *>(base);
+    A.cap = kScratchBytes;
+    t_arena = &A;
+    Plan P;
+    rmc_status st = dbl ? plan_pipeline<double>(cs, 1, P, s) : plan_pipeline<float>(cs, 1, P, s);
+    if (!st) {
+        double *d[1] = {divq};
+        double *e[1] = {se};
+        st = dbl ? enqueue_pipeline<double>(P, d, e, s, nullptr) : enqueue_pipeline<float>(P, d, e, s, nullptr);
+    }
+    t_arena = nullptr;
+    A.restore();
+    c->slots_R = slots_R;
+    c->slots_real = slots_real;
+    c->rec_rw_log2 = rw_log2;
+    return st;
 }
 
 rmc_status rmc_compute_wall_flux(rmc_ctx *c, double *divq, double *se, double *q_wall, rmc_mem mem, void *stream)

@@ -86,6 +86,7 @@ SIGNATURES = {
     "rmc_get_options": (C.c_int, [_VP, C.POINTER(Options)]),
     "rmc_set_cell_pdf": (C.c_int, [_VP, _VP, C.c_int, _VP]),
     "rmc_compute_divergence": (C.c_int, [_VP, _VP, _VP, C.c_int, _VP]),
+    "rmc_compute_divergence_noalloc": (C.c_int, [_VP, _VP, _VP, _VP]),
     "rmc_compute_wall_flux": (C.c_int, [_VP, _VP, _VP, _VP, C.c_int, _VP]),
     "rmc_compute_batch": (C.c_int, [C.POINTER(_VP), C.c_int, C.POINTER(_VP), C.POINTER(_VP),
                                     C.c_int, _VP]),
@@ -329,6 +330,16 @@ class Solver:
         if mem == HOST:
             import torch
             torch.cuda.synchronize(self.device)
+        return divq, stderr
+
+    def compute_noalloc(self, divq, stderr=None, stream=None):
+        """rmc_compute_divergence_noalloc: compute() into device tensors with every per-compute
+        buffer carved from the library's static scratch (no device allocation); asynchronous."""
+        pd, mem, _ = _buf(divq)
+        ps, mem_s, _ = _buf(stderr) if stderr is not None else (None, mem, None)
+        if mem != DEVICE or mem_s != DEVICE:
+            raise ValueError("compute_noalloc writes device tensors only")
+        _check(LIB.rmc_compute_divergence_noalloc(self.h, pd, ps, _stream(stream)))
         return divq, stderr
 
     def wall_elements(self) -> int:
