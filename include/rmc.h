@@ -79,7 +79,7 @@ typedef struct {
     double mix_eps;          /* PDF and LEARNED sampling: weight of the plain pdf in the mixture */
     int32_t block_threads;   /* march launch: threads per block (0 = default 256; only 256 is built) */
     int32_t long_ray_steps;  /* FP32 march on uniform x/z: rays still marching after this many steps
-                                are finished by 64 lanes in parallel segments (0 = default 256,
+                                are finished by 64 lanes in parallel segments (0 = default 512,
                                 >= max_steps disables it) */
     int32_t xcd_span;        /* march launch order: workgroups are dealt to the 8 XCDs in turn, and
                                 each XCD takes runs of this many consecutive 64-ray chunks of the

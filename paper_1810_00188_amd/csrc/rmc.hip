@@ -2700,7 +2700,7 @@ rmc_status enqueue_pipeline(const Plan &P, double *const *divq, double *const *s
     MA.max_steps = O.max_steps;
     // long rays are segmented only in the FP32 march over uniform periodic x and z
     const bool segment = sizeof(Real) == 4 && P.inc_xz && P.periodic_xz;
-    const int lrs = O.long_ray_steps > 0 ? O.long_ray_steps : 256;
+    const int lrs = O.long_ray_steps > 0 ? O.long_ray_steps : 512;
     MA.cap = segment ? std::min(lrs, O.max_steps) : O.max_steps;
     MA.kmin = P.d_kmin;
     MA.cont = L->cont.as<ContRec>();

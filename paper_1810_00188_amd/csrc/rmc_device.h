@@ -145,7 +145,11 @@ __device__ __forceinline__ double lerp_node(const float *tab, int t, double f)
     return a + f * (b - a);
 }
 
-// kappa_{n,g} and I_n of a cell from its record v (first word; further words read here).
+// kappa_{n,g} and I_n of a cell from its record v (first word; further words read here).  I_n
+// is interpolated in FP64 in both precisions (the ray sums differences of intensities of
+// near-isothermal cells).  The FP64 march interpolates kappa with the reference's FP64
+// operations; the FP32 march interpolates the FP32-exact table values in FP32 (a few ulp of
+// kappa, far below its parity bar) at a third of the instructions.
 template <class Real>
 __device__ __forceinline__ void prop_eval(const Props<Real> &P, uint4 v, int cell, Real &kap, double &I)
 {
@@ -153,25 +157,33 @@ __device__ __forceinline__ void prop_eval(const Props<Real> &P, uint4 v, int cel
     int t = (int)u;             // u >= 0: temperatures are checked against the table range
     t = t > P.tmax ? P.tmax : t;
     const double f = u - (double)t;
-    I = P.ib[t] + f * (P.ib[t + 1] - P.ib[t]);
-    double kp = 0.0;
+    const double i0 = P.ib[t], i1 = P.ib[t + 1];
     if constexpr (sizeof(Real) == 4) {
-        kp += (double)__uint_as_float(v.z) * lerp_node(P.k, t, f);
-        if (P.ns > 1) kp += (double)__uint_as_float(v.w) * lerp_node(P.k + P.kstride, t, f);
+        I = fma(f, i1 - i0, i0);
+        const float ff = (float)f;
+        const float *k0 = P.k + t;
+        float kp = __uint_as_float(v.z) * fmaf(ff, k0[1] - k0[0], k0[0]);
+        if (P.ns > 1) {
+            const float *k1 = k0 + P.kstride;
+            kp = fmaf(__uint_as_float(v.w), fmaf(ff, k1[1] - k1[0], k1[0]), kp);
+        }
 #pragma unroll 1
         for (int s = 2; s < P.ns; ++s) {   // words 1.. hold four fractions each
             const float *xw = reinterpret_cast<const float *>(P.rec + ((size_t)(uint32_t)cell << P.rw_log2) + 1);
-            kp += (double)gld(xw + (s - 2)) * lerp_node(P.k + s * P.kstride, t, f);
+            const float *ks = k0 + s * P.kstride;
+            kp = fmaf(gld(xw + (s - 2)), fmaf(ff, ks[1] - ks[0], ks[0]), kp);
         }
+        kap = kp;
     } else {
-        kp += __hiloint2double((int)v.w, (int)v.z) * lerp_node(P.k, t, f);
+        I = i0 + f * (i1 - i0);
+        double kp = __hiloint2double((int)v.w, (int)v.z) * lerp_node(P.k, t, f);
 #pragma unroll 1
         for (int s = 1; s < P.ns; ++s) {   // words 1.. hold two fractions each
             const double *xw = reinterpret_cast<const double *>(P.rec + ((size_t)(uint32_t)cell << P.rw_log2) + 1);
             kp += gld(xw + (s - 1)) * lerp_node(P.k + s * P.kstride, t, f);
         }
+        kap = kp;
     }
-    kap = (Real)kp;
 }
 
 template <class Real> __device__ __forceinline__ void prop_load(const Props<Real> &P, int cell, Real &kap, double &I)
