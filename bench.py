@@ -77,6 +77,9 @@ def parse():
                     help="12 uneven snapshots (50 bands x 8 g) in one pass: autotuned, eager and HIP graph")
     ap.add_argument("--precision-study", choices=["channel64", "dns256"], default=None,
                     help="errors of the FP32 march and of compensated / plain FP32 sums against FP64")
+    ap.add_argument("--learned-cost", choices=["channel64", "dns256"], default=None,
+                    help="time of a learned compute (features, network, draws, march) at the workload's R, "
+                         "with the committed network or, without one, an untrained one")
     ap.add_argument("--walls-study", action="store_true",
                     help="time per compute with reflecting walls and closed boxes (64^3 workloads)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -382,6 +385,50 @@ def precision_study(a):
     s.close()
 
 
+def learned_cost(a):
+    """Phase times of a compute with the learned allocation (the allocation network, softmax
+    and draws run in the prep phase) beside a plain compute of the same field."""
+    import numpy as np
+    import torch
+    from paper_1810_00188_amd import allocators, inputs, learned, rmc
+
+    gen = {"channel64": inputs.channel64, "dns256": inputs.dns256}[a.learned_cost]
+    w = gen(field_seed=1000)
+    try:
+        net = allocators.load(a.learned_cost)
+        params, mu, sd, eps, which = net["params"], net["mu"], net["sd"], net["mix_eps"], "committed network"
+    except FileNotFoundError:
+        params, which, eps = learned.init_params(0), "untrained network", 0.1
+        mu, sd = learned.standardisation([np.zeros((1, 3), np.float32)], w.kd)
+        sd[:3] = 1.0
+    nu_c, gx = learned.spectral_inputs(w.kd)
+    dev = torch.device("cuda", 0)
+    dq = torch.zeros(w.ncells, dtype=torch.float64, device=dev)
+    rows = {}
+    for name, sampling in (("plain", rmc.SAMPLING_PLAIN), ("learned", rmc.SAMPLING_LEARNED)):
+        s = rmc.Solver(0)
+        s.set_workload(w, device_fields=True, sampling=sampling, mix_eps=eps if sampling else 0.0)
+        if sampling:
+            s.set_allocator(params, mu, sd, nu_c, gx)
+        s.compute(dq)
+        torch.cuda.synchronize()
+        s.reset_stats()
+        K = 3
+        t0 = time.perf_counter()
+        for _ in range(K):
+            s.compute(dq)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / K
+        st = s.stats()
+        rows[name] = {"ms_per_compute": 1e3 * dt, "prep_ms": st["sum_ms_prep"] / K, "alloc_ms": st["sum_ms_alloc"] / K,
+                      "march_ms": st["sum_ms_march"] / K, "reduce_ms": st["sum_ms_reduce"] / K,
+                      "steps_per_ray": st["sum_steps"] / (K * w.ncells * w.R)}
+        print(f"[learned-cost] {name}: {json.dumps(rows[name])}", flush=True)
+        s.close()
+    print(json.dumps({"metric": "learned compute phase times", "unit": "ms", "network": which,
+                      "config": {"workload": w.name, "rays_per_cell": w.R}, "rows": rows}), flush=True)
+
+
 def walls_study(a):
     """Wall rows (Eq. 3's wall factor with specular reflection, closed boxes of Table 1): time
     per compute, steps per ray and ray-cell steps per second on 64^3 workloads, black walls
@@ -496,6 +543,9 @@ def main():
         return
     if a.precision_study:
         precision_study(a)
+        return
+    if a.learned_cost:
+        learned_cost(a)
         return
     if a.batch12:
         batch12_bench(a)

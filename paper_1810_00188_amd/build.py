@@ -1,8 +1,9 @@
 """Build step of the HIP library: compiles csrc/rmc.hip for gfx950 into librmc.so (in-tree).
 
 Flags: -O3, C++17, -ffp-contract=off (no implicit FMA contraction: the FP64 path keeps the
-operation order of the reference algorithm; the FP32 march writes its FMAs explicitly) and
-packed-FP32 instructions disabled.
+operation order of the reference algorithm; the FP32 march writes its FMAs explicitly),
+packed-FP32 instructions disabled, and matrix-core instructions in their VGPR form (the
+allocation network's accumulators then need no copies out of AGPRs).
 """
 import os
 import subprocess
@@ -15,7 +16,7 @@ OUT = os.path.join(HERE, "librmc.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
-         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-mllvm", "-amdgpu-mfma-vgpr-form",
          "-I" + os.path.join(ROOT, "include"), "-I" + os.path.join(HERE, "csrc")]
 
 

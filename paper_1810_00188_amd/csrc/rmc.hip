@@ -2201,27 +2201,9 @@ void kappa_lower_bounds(const rmc_ctx *c, std::vector<float> &out)
 }
 
 // ------------------------------------------------------------ learned allocation (host)
-// cells per workgroup of the allocation kernels and their LDS bytes (logits of all strata of
-// cpb cells, the per-cell half of layer 1, masks, then for the draw kernel FP64 band sums)
-struct NetLaunch {
-    int cpb;
-    size_t lds_logits, lds_draw;
-};
-
-NetLaunch net_launch(const rmc_ctx *c)
-{
-    const int S = c->nb * c->ng * 8;
-    auto size = [&](int cpb) {
-        NetLaunch L;
-        L.cpb = cpb;
-        L.lds_logits = sizeof(float) * ((size_t)cpb * S + (size_t)cpb * kHid + ((cpb + 15) / 16) * 4);
-        L.lds_draw = L.lds_logits + sizeof(double) * (4 * (size_t)c->nb + 256);
-        return L;
-    };
-    int cpb = 16;   // as many cells as fit in 64 KiB of LDS
-    while (cpb > 1 && size(cpb).lds_draw > 64 * 1024) --cpb;
-    return size(cpb);
-}
+// Workgroups of the allocation kernels: single wavefronts, one cell at a time each, in turn
+// over the cells (each holds the network's weights in registers once).
+constexpr unsigned kNetBlocks = 4096;
 
 // buffers of the features and of the per-ray draws; the face table for the features kernel
 rmc_status plan_features(rmc_ctx *c)
@@ -2245,7 +2227,8 @@ rmc_status plan_learned(rmc_ctx *c)
 {
     rmc_status st;
     if ((st = plan_features(c))) return st;
-    if (net_launch(c).lds_draw > 64 * 1024) return fail(RMC_UNSUPPORTED, "nb * ng too large for the allocation kernel");
+    if (net_wave_lds(c->nb * c->ng, c->nb) > 64 * 1024)
+        return fail(RMC_UNSUPPORTED, "nb * ng too large for the allocation kernel");
     if ((st = c->bng.ensure(sizeof(float) * c->nb * c->ng * kHid)) || (st = c->lpp.ensure(sizeof(double) * c->nb * c->ng)) ||
         (st = c->dstrat.ensure(sizeof(uint32_t) * ncells_of(c) * c->opt.rays_per_cell)))
         return st;
@@ -2285,7 +2268,6 @@ AllocNetArgs net_args(rmc_ctx *c)
     A.feat = c->feat.as<float>();
     A.mask = c->fmask.as<uint8_t>();
     A.P = c->nb * c->ng;
-    A.cpb = net_launch(c).cpb;
     A.nb = c->nb; A.ng = c->ng; A.R = c->opt.rays_per_cell;
     A.k0 = (uint32_t)c->opt.seed; A.k1 = (uint32_t)(c->opt.seed >> 32);
     A.mix_eps = c->opt.mix_eps;
@@ -2317,8 +2299,8 @@ rmc_status enqueue_learned(rmc_ctx *c, hipStream_t s)
     A.lpp = c->lpp.as<double>();
     A.dstrat = c->dstrat.as<uint32_t>();
     A.dprob = c->dprob.as<double>();
-    const NetLaunch NL = net_launch(c);
-    hipLaunchKernelGGL(k_alloc_draw, dim3((unsigned)((A.ncell + NL.cpb - 1) / NL.cpb)), dim3(256), NL.lds_draw, s, A);
+    hipLaunchKernelGGL(k_alloc_draw, dim3((unsigned)std::min<int64_t>(A.ncell, kNetBlocks)), dim3(64),
+                       net_wave_lds(A.P, A.nb), s, A);
     HIPCHK(hipGetLastError());
     return RMC_OK;
 }

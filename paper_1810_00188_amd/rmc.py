@@ -14,7 +14,7 @@ from typing import Optional, Sequence
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "librmc.so")
+LIB_PATH = os.environ.get("RMC_LIB", os.path.join(HERE, "librmc.so"))   # RMC_LIB: another build of it
 
 RMC_OK, RMC_INVALID_ARG, RMC_BAD_STATE, RMC_OUT_OF_RANGE, RMC_UNSUPPORTED, RMC_DEVICE_ERROR, \
     RMC_OUT_OF_MEMORY = range(7)

@@ -123,10 +123,10 @@ def _plain_cdf_inverse_check(P, u0, u1, u2, nb, ng):
 
 @pytest.mark.parametrize("tables", [(5, 3), (20, 7), (100, 16)])
 def test_learned_draws_and_rays_match_oracle(tables):
-    """Draws and ray values of the learned mode.  The table sets cover the kernel's layouts:
-    5 x 3 and 20 x 7 put several cells' logits in one workgroup's LDS (16 cells of 120, 12
-    cells of 1120 strata); 100 x 16, the DNS-size tables (12,800 strata per cell), leaves room
-    for one cell per workgroup with 100-band sums."""
+    """Draws and ray values of the learned mode.  The table sets cover the kernel's cases: 5 x 3
+    (one 16-row network tile per cell), 20 x 7 (9 tiles), and 100 x 16, the DNS-size tables
+    (100 tiles and 12,800 strata per cell, band sums and running sums over two 64-band
+    chunks)."""
     eps = 0.15
     w = _workload(R=24, nb=tables[0], ng=tables[1])
     say(f"learned sampling {w.name}")
