@@ -17,8 +17,10 @@ Prints one JSON line.  The roofline is that of the dominant kernel, the lane mar
 the compute stream, summed over the timed steps; its algorithmic bytes count the steps it
 takes (all steps minus those of the long-ray kernel, which the library counts) at 8 bytes per
 ray-cell step (an FP32 kappa_{n,g} and an FP32 I_n value of the cell) plus 12 bytes per ray
-(an 8-byte work item and a 4-byte ray value).  The kernel itself gathers an FP64 intensity
-(12 bytes per step) and moves 16-byte items and 8-byte slots; that figure is reported beside.
+(an 8-byte work item and a 4-byte ray value).  The kernel itself gathers one 16-byte cell
+record per step (the FP64 table coordinate of the temperature and the mole fractions, from
+which it interpolates kappa_{n,g} and I_n in LDS tables) and moves 16-byte items and 8-byte
+slots; that figure is reported beside.
 The `learned` block evaluates the allocation network committed with the package against the
 plain allocation on held-out fields of the same generator.
 """
@@ -37,9 +39,9 @@ HBM_PEAK_GBS = 8000.0
 # value of the cell; per ray an 8-byte work item and a 4-byte ray value
 BYTES_PER_STEP = 4 + 4
 BYTES_PER_RAY = 8 + 4
-# what the kernel moves: an FP32 kappa and an FP64 intensity per step, a 16-byte work item and
-# an 8-byte slot record {value, steps | end} per ray
-KERNEL_BYTES_PER_STEP = 4 + 8
+# what the kernel moves: a 16-byte cell record per step, a 16-byte work item and an 8-byte
+# slot record {value, steps | end} per ray
+KERNEL_BYTES_PER_STEP = 16
 KERNEL_BYTES_PER_RAY = 16 + 8
 L2_PER_XCD_MB = 4.0
 MALL_MB = 256.0
@@ -80,6 +82,11 @@ def parse():
     ap.add_argument("--learned-cost", choices=["channel64", "dns256"], default=None,
                     help="time of a learned compute (features, network, draws, march) at the workload's R, "
                          "with the committed network or, without one, an untrained one")
+    ap.add_argument("--confirm-r1", choices=["channel64", "dns256"], default=None,
+                    help="confirm the time to 1 %% RMS error on one held-out field by running the rays per "
+                         "cell it predicts, as merged computes of at most --r-max rays, for plain and learned")
+    ap.add_argument("--r-max", type=int, default=255, help="rays per cell of one compute in --confirm-r1")
+    ap.add_argument("--methods", default="plain,learned", help="--confirm-r1: methods to run (plain, learned)")
     ap.add_argument("--walls-study", action="store_true",
                     help="time per compute with reflecting walls and closed boxes (64^3 workloads)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -429,6 +436,79 @@ def learned_cost(a):
                       "config": {"workload": w.name, "rays_per_cell": w.R}, "rows": rows}), flush=True)
 
 
+def confirm_r1(a):
+    """Time to 1 % RMS error confirmed by running it.  On held-out field 1000: the protocol of
+    `learned.time_to_error` estimates R_1% (rays per cell for a 1 % error) and t(R) for each
+    method; then K = ceil(R_1% / r_max) computes of r_max rays per cell (distinct snapshot
+    streams) are enqueued back to back and summed on the device, alternately into halves A and
+    B.  The estimate Q averages all K, and the difference of the halves measures its error
+    without a reference: e = RMS(Q_A - Q_B) / (2 RMS(Q)) (each half carries twice the variance
+    of Q).  The wall time of the K computes is the measured time to 1 %."""
+    import math
+    import numpy as np
+    import torch
+    from paper_1810_00188_amd import allocators, inputs, learned, rmc
+
+    gen = {"channel64": inputs.channel64, "dns256": inputs.dns256}[a.confirm_r1]
+    net = allocators.load(a.confirm_r1)
+    w = gen(field_seed=1000)
+    nu_c, gx = learned.spectral_inputs(w.kd)
+    dev = torch.device("cuda", 0)
+    s_plain, s_learn = rmc.Solver(0), rmc.Solver(0)
+    s_plain.set_workload(w, device_fields=True)
+    s_learn.set_workload(w, device_fields=True, sampling=rmc.SAMPLING_LEARNED, mix_eps=net["mix_eps"])
+    s_learn.set_allocator(net["params"], net["mu"], net["sd"], nu_c, gx)
+    say = lambda m: print(f"[confirm] {m}", flush=True)  # noqa: E731
+    est = learned.time_to_error(w, s_plain, s_learn, net["mix_eps"], Rs=(16, 32, 64, 128), log=say)
+    dq = torch.zeros(w.ncells, dtype=torch.float64, device=dev)
+    rms = lambda v: float(np.sqrt(np.mean(np.square(v))))  # noqa: E731
+    rows = {}
+    for name, s, sampling in (("plain", s_plain, rmc.SAMPLING_PLAIN), ("learned", s_learn, rmc.SAMPLING_LEARNED)):
+        if name not in a.methods.split(","):
+            continue
+        R1 = est[name]["R_target"]
+        K = max(2, math.ceil(R1 / a.r_max))
+        halves = [torch.zeros_like(dq), torch.zeros_like(dq)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(K):
+            s.set_options(rmc.default_options(rays_per_cell=a.r_max, seed=w.seed, snapshot=20000 + k, tol=w.tol,
+                                              max_steps=w.max_steps, march=rmc.F32, accum=rmc.ACC[w.accum],
+                                              sampling=sampling, mix_eps=net["mix_eps"] if sampling else 0.0))
+            s.compute(dq)
+            halves[k & 1] += dq
+            if (k + 1) % max(1, K // 10) == 0:
+                torch.cuda.synchronize()
+                say(f"{name}: {k + 1} of {K} computes, {time.perf_counter() - t0:.1f} s")
+        torch.cuda.synchronize()
+        t_run = time.perf_counter() - t0
+        nA, nB = (K + 1) // 2, K // 2
+        qa, qb = (halves[0] / nA).cpu().numpy(), (halves[1] / nB).cpu().numpy()
+        q = (nA * qa + nB * qb) / K
+        # Var(Q_A - Q_B) = Var(Q) K^2 / (nA nB): scale the half difference to the error of Q
+        e = rms(qa - qb) * math.sqrt(nA * nB) / K / rms(q)
+        m = est[name]
+        rows[name] = {"R_1pct_estimated": R1, "computes": K, "rays_per_cell_per_compute": a.r_max,
+                      "rays_per_cell": K * a.r_max, "rel_err_measured": e,
+                      "rel_err_expected_at_these_rays": 0.01 * math.sqrt(R1 / (K * a.r_max)),
+                      "time_s_measured": t_run,
+                      "time_s_fit_single_compute": m["time_to_target_s"],
+                      "time_s_fit_merged": K * (m["t0_s"] + m["t_per_ray_s"] * a.r_max),
+                      "t0_s": m["t0_s"], "t_per_ray_s": m["t_per_ray_s"], "err_slope": m["err_slope"],
+                      "rel_err_R16_128": m["rel_err"], "t_s_R16_128": m["t_s"]}
+        say(f"{name}: {json.dumps(rows[name])}")
+    out = {"metric": "wall time to 1% RMS divq error, confirmed by merged computes", "unit": "s",
+           "higher_is_better": False, "n_gpus": 1, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": w.name, "grid": [w.nx, w.ny, w.nz], "field_seed": 1000,
+                      "network": net["info"], "r_max": a.r_max},
+           "rows": rows}
+    if len(rows) == 2:
+        out["speedup_vs_plain"] = rows["plain"]["time_s_measured"] / rows["learned"]["time_s_measured"]
+    print(json.dumps(out), flush=True)
+    s_plain.close()
+    s_learn.close()
+
+
 def walls_study(a):
     """Wall rows (Eq. 3's wall factor with specular reflection, closed boxes of Table 1): time
     per compute, steps per ray and ray-cell steps per second on 64^3 workloads, black walls
@@ -547,6 +627,9 @@ def main():
     if a.learned_cost:
         learned_cost(a)
         return
+    if a.confirm_r1:
+        confirm_r1(a)
+        return
     if a.batch12:
         batch12_bench(a)
         return
@@ -642,7 +725,7 @@ def throughput(a):
     probe_rate = rays * probe_steps / (pms * 1e-3)
     lane_rate = lane_steps / (lane_ms * 1e-3)
     ncpad = 64 * ((w.nx + 3) // 4) * ((w.ny + 3) // 4) * ((w.nz + 3) // 4)
-    ws_mb = ncpad * (4 + 8) / 1e6      # one FP32 kappa plane and one FP64 intensity plane
+    ws_mb = ncpad * 16 / 1e6           # the cell records, shared by every (band, g) pair
     level = "L2" if ws_mb <= L2_PER_XCD_MB else ("MALL" if ws_mb <= MALL_MB else "HBM")
     out = {
         "metric": "ray-cell steps/s",
@@ -675,7 +758,7 @@ def throughput(a):
                      "steps_per_launch": lane_steps, "rays_per_launch": rays,
                      "kernel_bytes_per_launch": kbytes_launch,
                      "kernel_gbs": kbytes_launch / (lane_ms * 1e-3) / 1e9,
-                     "working_set_mb_per_pair": ws_mb, "working_set_level": level,
+                     "working_set_mb": ws_mb, "working_set_level": level,
                      "lane_steps_per_s": lane_rate,
                      "probe_steps_per_s": probe_rate,
                      "frac_of_achievable_steps": lane_rate / probe_rate,
