@@ -224,14 +224,20 @@ def learned_bench(a):
         s_learn.set_workload(w, device_fields=True, sampling=rmc.SAMPLING_LEARNED, mix_eps=eps)
         s_learn.set_allocator(params, mu, sd, nu_c, gx)
         say(f"evaluation field {1000 + e}")
-        results.append(learned.time_to_error(w, s_plain, s_learn, eps, Rs=cfg["Rs"], log=say))
-    tp = np.array([r["plain"]["time_to_target_s"] for r in results])
-    tl = np.array([r["learned"]["time_to_target_s"] for r in results])
+        results.append(learned.time_to_error(w, s_plain, s_learn, eps, Rs=cfg["Rs"], log=say, alloc_cache=1))
+    tp = np.array([r["plain"]["time_to_target_merged_s"] for r in results])
+    tl = np.array([r["learned"]["time_to_target_merged_s"] for r in results])
+    tp1 = np.array([r["plain"]["time_to_target_s"] for r in results])
+    tl1 = np.array([r["learned"]["time_to_target_s"] for r in results])
     out = {
-        "metric": "wall time to 1% RMS divq error, learned vs plain",
+        "metric": "wall time to 1% RMS divq error, learned vs plain (computes of 255 rays per cell: "
+                  "ceil(R_1% / 255) (t0 + 255 t1))",
         "value": float(np.median(tl)), "unit": "s", "higher_is_better": False,
         "plain_s": float(np.median(tp)), "speedup_vs_plain": float(np.median(tp / tl)),
         "learned_wins": int(np.sum(tl < tp)), "eval_fields": n_eval,
+        "single_compute_model": {"learned_s": float(np.median(tl1)), "plain_s": float(np.median(tp1)),
+                                 "speedup_vs_plain": float(np.median(tp1 / tl1)), "learned_wins": int(np.sum(tl1 < tp1)),
+                                 "note": "t0 + t1 R_1%, as if one compute carried all R_1% rays per cell"},
         "n_gpus": 1, "dtype": "f32", "data": "synthetic", "vs_baseline": None,
         "config": {"workload": w0.name, "grid": [w0.nx, w0.ny, w0.nz], "bands": kd.nb, "g_points": kd.ng,
                    "train_fields": n_train, "train_cells_per_field": cfg["cells"], "train_steps": steps,
@@ -412,9 +418,10 @@ def learned_cost(a):
     dev = torch.device("cuda", 0)
     dq = torch.zeros(w.ncells, dtype=torch.float64, device=dev)
     rows = {}
-    for name, sampling in (("plain", rmc.SAMPLING_PLAIN), ("learned", rmc.SAMPLING_LEARNED)):
+    for name, sampling, cache in (("plain", rmc.SAMPLING_PLAIN, 0), ("learned", rmc.SAMPLING_LEARNED, 0),
+                                  ("learned, allocation cache", rmc.SAMPLING_LEARNED, 1)):
         s = rmc.Solver(0)
-        s.set_workload(w, device_fields=True, sampling=sampling, mix_eps=eps if sampling else 0.0)
+        s.set_workload(w, device_fields=True, sampling=sampling, mix_eps=eps if sampling else 0.0, alloc_cache=cache)
         if sampling:
             s.set_allocator(params, mu, sd, nu_c, gx)
         s.compute(dq)
@@ -459,7 +466,7 @@ def confirm_r1(a):
     s_learn.set_workload(w, device_fields=True, sampling=rmc.SAMPLING_LEARNED, mix_eps=net["mix_eps"])
     s_learn.set_allocator(net["params"], net["mu"], net["sd"], nu_c, gx)
     say = lambda m: print(f"[confirm] {m}", flush=True)  # noqa: E731
-    est = learned.time_to_error(w, s_plain, s_learn, net["mix_eps"], Rs=(16, 32, 64, 128), log=say)
+    est = learned.time_to_error(w, s_plain, s_learn, net["mix_eps"], Rs=(16, 32, 64, 128), log=say, alloc_cache=1)
     dq = torch.zeros(w.ncells, dtype=torch.float64, device=dev)
     rms = lambda v: float(np.sqrt(np.mean(np.square(v))))  # noqa: E731
     rows = {}
@@ -474,7 +481,8 @@ def confirm_r1(a):
         for k in range(K):
             s.set_options(rmc.default_options(rays_per_cell=a.r_max, seed=w.seed, snapshot=20000 + k, tol=w.tol,
                                               max_steps=w.max_steps, march=rmc.F32, accum=rmc.ACC[w.accum],
-                                              sampling=sampling, mix_eps=net["mix_eps"] if sampling else 0.0))
+                                              sampling=sampling, mix_eps=net["mix_eps"] if sampling else 0.0,
+                                              alloc_cache=1 if sampling else 0))
             s.compute(dq)
             halves[k & 1] += dq
             if (k + 1) % max(1, K // 10) == 0:
@@ -493,7 +501,7 @@ def confirm_r1(a):
                       "rel_err_expected_at_these_rays": 0.01 * math.sqrt(R1 / (K * a.r_max)),
                       "time_s_measured": t_run,
                       "time_s_fit_single_compute": m["time_to_target_s"],
-                      "time_s_fit_merged": K * (m["t0_s"] + m["t_per_ray_s"] * a.r_max),
+                      "time_s_fit_merged": m["t_first_s"] + K * (m["t0_s"] + m["t_per_ray_s"] * a.r_max),
                       "t0_s": m["t0_s"], "t_per_ray_s": m["t_per_ray_s"], "err_slope": m["err_slope"],
                       "rel_err_R16_128": m["rel_err"], "t_s_R16_128": m["t_s"]}
         say(f"{name}: {json.dumps(rows[name])}")
@@ -797,19 +805,25 @@ def learned_block(a, w):
         s_plain.set_workload(we, device_fields=True)
         s_learn.set_workload(we, device_fields=True, sampling=rmc.SAMPLING_LEARNED, mix_eps=net["mix_eps"])
         s_learn.set_allocator(net["params"], net["mu"], net["sd"], nu_c, gx)
-        r = learned.time_to_error(we, s_plain, s_learn, net["mix_eps"], Rs=(16, 32, 64, 128))
+        r = learned.time_to_error(we, s_plain, s_learn, net["mix_eps"], Rs=(16, 32, 64, 128), alloc_cache=1)
         results.append(r)
-        print(f"[learned] field {1000 + e}: plain {r['plain']['time_to_target_s']:.1f} s, learned "
-              f"{r['learned']['time_to_target_s']:.1f} s to 1 %", file=sys.stderr, flush=True)
+        print(f"[learned] field {1000 + e}: plain {r['plain']['time_to_target_merged_s']:.1f} s, learned "
+              f"{r['learned']['time_to_target_merged_s']:.1f} s to 1 %", file=sys.stderr, flush=True)
     s_plain.close()
     s_learn.close()
-    tp = np.array([r["plain"]["time_to_target_s"] for r in results])
-    tl = np.array([r["learned"]["time_to_target_s"] for r in results])
+    tp = np.array([r["plain"]["time_to_target_merged_s"] for r in results])
+    tl = np.array([r["learned"]["time_to_target_merged_s"] for r in results])
+    tp1 = np.array([r["plain"]["time_to_target_s"] for r in results])
+    tl1 = np.array([r["learned"]["time_to_target_s"] for r in results])
     med = lambda k, m: float(np.median([r[m][k] for r in results]))  # noqa: E731
-    return {"metric": "wall time to 1% RMS divq error (extrapolated from R = 16..128 as t0 + t1 R_1%)",
+    return {"metric": "wall time to 1% RMS divq error, as computes of 255 rays per cell: "
+                      "ceil(R_1% / 255) (t0 + 255 t1), R_1% and t(R) = t0 + t1 R measured at R = 16..128",
             "unit": "s", "higher_is_better": False,
             "learned_s": float(np.median(tl)), "plain_s": float(np.median(tp)),
             "speedup_vs_plain": float(np.median(tp / tl)), "learned_wins": int(np.sum(tl < tp)),
+            "single_compute_model": {"learned_s": float(np.median(tl1)), "plain_s": float(np.median(tp1)),
+                                     "speedup_vs_plain": float(np.median(tp1 / tl1)),
+                                     "note": "t0 + t1 R_1%, as if one compute carried all R_1% rays per cell"},
             "eval_fields": len(results), "field_seeds": [1000 + e for e in range(len(results))],
             "R_1pct": {"plain": med("R_target", "plain"), "learned": med("R_target", "learned")},
             "t0_s": {"plain": med("t0_s", "plain"), "learned": med("t0_s", "learned")},

@@ -83,8 +83,8 @@ typedef struct {
                                 >= max_steps disables it) */
     int32_t xcd_span;        /* march launch order: workgroups are dealt to the 8 XCDs in turn, and
                                 each XCD takes runs of this many consecutive 64-ray chunks of the
-                                bucketed work list, so that the rays in flight on one XCD share
-                                their property planes in its L2 (power of two in [4, 2^20];
+                                bucketed work list, so that the rays in flight on one XCD work on
+                                one (n, g) pair and nearby cells (power of two in [4, 2^20];
                                 0 = default 256; 4 = plain workgroup order) */
     int32_t length_sort;     /* 1: each march workgroup reorders the rays of its four chunks by a
                                 class of their expected length first, so that a wavefront's rays
@@ -92,7 +92,7 @@ typedef struct {
                                 0 (default): cell order.  Results are the same either way */
     int32_t bucket_order;    /* march order of the (n, g, octant) buckets: 0 (default) pairs by
                                 increasing kappa(T_max), the longest rays first; 1 band-major, the
-                                g-points of a band together (they share its intensity plane).
+                                g-points of a band together (they share its intensity table).
                                 Results are the same either way */
     int32_t mg_levels;       /* multigrid march (Sec. 4.3): number of overlaid grids; grid L has
                                 every 2^L-th face of the DNS grid (coarsening ratio 2 on every axis,
@@ -116,6 +116,14 @@ typedef struct {
                                 the time), more, one wavefront of 64 (throughput); 1 always
                                 workgroups; 2 always wavefronts.  The segments' products round
                                 differently, so the forms agree within the FP32 tolerance */
+    int32_t alloc_cache;     /* LEARNED sampling: 1 keeps each cell's pair sums of the allocation
+                                softmax (4 bytes per cell and (n, g) pair plus 12 per cell of device
+                                memory: 27 GB for 4.2 M cells x 1600 pairs) after a compute, and
+                                later computes of the unchanged field, walls, tables and network
+                                (any snapshot, R or mix_eps) draw from them, running the network
+                                only for the octants of the pairs they draw; the draws and values
+                                are the same as without it.  0 (default): the network runs over
+                                every pair at every compute.  Not in a captured graph */
 } rmc_options;
 
 typedef struct {
@@ -187,8 +195,9 @@ rmc_status rmc_set_box_walls(rmc_ctx *ctx, const double *T, const double *eps);
  *   Ib[nb][nT] band-averaged blackbody intensity (double).
  * Limits: 1 <= nb <= 4096, 1 <= ng <= 255, 1 <= ns <= 8, 2 <= nT, nb * ng <= 2000.  The
  * march stages the tables of four (band, g) pairs in LDS beside the face tables of the grids
- * it marches: 8 (nfaces + 4 (nT + ns nT / 2)) bytes must stay within 52 KiB (nfaces: the face
- * coordinates of every grid level of every snapshot of a pass), else the compute returns
+ * it marches: 8 (nfaces + 4 (nT + ns nT / 2)) bytes must stay within the device's LDS per
+ * workgroup less 12 KiB (nfaces: the face coordinates of every grid level of every distinct
+ * grid of a pass; snapshots of one grid share theirs), else the compute returns
  * RMC_UNSUPPORTED. */
 rmc_status rmc_set_kdist(rmc_ctx *ctx, int nb, int ng, int ns, int nT, double T0, double dT,
                          const double *dnu, const double *wg, const void *k, rmc_dtype k_dtype,

@@ -738,7 +738,8 @@ inline size_t march_lds_bytes(int nfaces, int nT, int ns)
 {
     return sizeof(double) * ((size_t)((nfaces + 1) & ~1) + 4 * (size_t)table_slot_doubles(nT, ns));
 }
-constexpr size_t kMarchLds = 52 * 1024;
+// what the march kernels' own arrays take besides (the length-sorting variant's is the largest)
+constexpr size_t kMarchStaticLds = 12 * 1024;
 
 // Tables of (band, g) pair `pair` into an LDS slot: I_n at the nodes (FP64), then k^s_{n,g}
 // at the nodes (FP32) species after species; filled by `nt` threads from thread t0 on.
@@ -1976,6 +1977,12 @@ struct rmc_ctx {
     DBuf small;             // ingest results
     DBuf scal;              // [0]: max cell temperature, [1..8]: largest mole fraction per species
     uint64_t config_version = 0;   // bumped by every set_* that changes sizes or kernel arguments
+    uint64_t input_version = 0;    // bumped by every set_* that changes the learned allocation's inputs
+    // learned allocation cache (alloc_cache): per cell and pair the softmax's pair sums, per cell
+    // the normaliser's inverse and the reference of the exponentials; valid for input_version
+    DBuf acache, acinv, acmax;
+    uint64_t acache_version = ~0ull;
+    size_t lds_max = 64 * 1024;     // LDS a workgroup may use on the device
     // timing: a ring of event sets, one per compute in flight; counters[0..1] are the last
     // compute's steps / capped rays, counters[2] the steps accumulated since the last reset
     struct EvSet {
@@ -1996,6 +2003,9 @@ struct rmc_ctx {
 namespace {
 
 uint64_t ncells_of(const rmc_ctx *c) { return (uint64_t)c->nx * c->ny * c->nz; }
+
+// LDS left to the march kernels' face tables and table slots on the context's device.
+size_t march_lds_budget(const rmc_ctx *c) { return c->lds_max - kMarchStaticLds; }
 uint64_t ncpad_of(const rmc_ctx *c)
 {
     return (uint64_t)round_up(c->nx, 4) * round_up(c->ny, 4) * round_up(c->nz, 4);
@@ -2064,6 +2074,7 @@ rmc_status check_options(const rmc_options *o)
     if (o->alloc_tile != 0 && (o->alloc_tile < 256 || o->alloc_tile > 65536 || o->alloc_tile % 64))
         return fail(RMC_INVALID_ARG, "alloc_tile must be 0 or a multiple of 64 in [256, 65536]");
     if (o->long_ray_form < 0 || o->long_ray_form > 2) return fail(RMC_INVALID_ARG, "long_ray_form must be 0, 1 or 2");
+    if (o->alloc_cache != 0 && o->alloc_cache != 1) return fail(RMC_INVALID_ARG, "alloc_cache must be 0 or 1");
     return RMC_OK;
 }
 
@@ -2106,17 +2117,31 @@ uint64_t ncpad_level(const rmc_ctx *c, int L)
     return (uint64_t)round_up(c->nx >> L, 4) * round_up(c->ny >> L, 4) * round_up(c->nz >> L, 4);
 }
 
-// Face tables of every grid level of a snapshot, appended to `faces` (level L: every 2^L-th
-// face); records their offsets in D.
-void append_faces(const rmc_ctx *c, SnapDesc &D, std::vector<double> &faces)
+// Face tables of every grid level of a snapshot (level L: every 2^L-th face), appended to
+// `faces` unless the same tables are already there (snapshots of one grid share them);
+// records their offsets in D.  `blocks` lists the (start, length) of the tables appended so far.
+void append_faces(const rmc_ctx *c, SnapDesc &D, std::vector<double> &faces,
+                  std::vector<std::pair<int, int>> &blocks)
 {
-    D.face_off = (int)faces.size();
+    const int start = (int)faces.size();
+    int lev[kMaxLev];
     for (int L = 0; L < D.nlev; ++L) {
-        D.lev_face[L] = (int)faces.size();
+        lev[L] = (int)faces.size() - start;
         for (int q = 0; q <= (c->nx >> L); ++q) faces.push_back(c->xf[(size_t)q << L]);
         for (int q = 0; q <= (c->ny >> L); ++q) faces.push_back(c->yf[(size_t)q << L]);
         for (int q = 0; q <= (c->nz >> L); ++q) faces.push_back(c->zf[(size_t)q << L]);
     }
+    const int len = (int)faces.size() - start;
+    int at = start;
+    for (const auto &b : blocks)   // same levels of the same grid: the same table layout
+        if (b.second == len && memcmp(faces.data() + b.first, faces.data() + start, sizeof(double) * len) == 0) {
+            at = b.first;
+            faces.resize(start);
+            break;
+        }
+    if (at == start) blocks.emplace_back(start, len);
+    D.face_off = at;
+    for (int L = 0; L < D.nlev; ++L) D.lev_face[L] = at + lev[L];
 }
 
 // width of a uniformly spaced axis (faces equal to f0 + q h within 1e-12 of the length), else 0
@@ -2232,6 +2257,14 @@ rmc_status plan_learned(rmc_ctx *c)
     if ((st = c->bng.ensure(sizeof(float) * c->nb * c->ng * kHid)) || (st = c->lpp.ensure(sizeof(double) * c->nb * c->ng)) ||
         (st = c->dstrat.ensure(sizeof(uint32_t) * ncells_of(c) * c->opt.rays_per_cell)))
         return st;
+    if (c->opt.alloc_cache) {
+        const uint64_t nc = ncells_of(c);
+        const void *before = c->acache.p;
+        if ((st = c->acache.ensure(sizeof(float) * nc * c->nb * c->ng)) || (st = c->acinv.ensure(sizeof(double) * nc)) ||
+            (st = c->acmax.ensure(sizeof(float) * nc)))
+            return st;
+        if (c->acache.p != before) c->acache_version = ~0ull;   // a new buffer holds nothing yet
+    }
     return RMC_OK;
 }
 
@@ -2299,8 +2332,21 @@ rmc_status enqueue_learned(rmc_ctx *c, hipStream_t s)
     A.lpp = c->lpp.as<double>();
     A.dstrat = c->dstrat.as<uint32_t>();
     A.dprob = c->dprob.as<double>();
-    hipLaunchKernelGGL(k_alloc_draw, dim3((unsigned)std::min<int64_t>(A.ncell, kNetBlocks)), dim3(64),
-                       net_wave_lds(A.P, A.nb), s, A);
+    const dim3 grid((unsigned)std::min<int64_t>(A.ncell, kNetBlocks)), block(64);
+    const size_t lds = net_wave_lds(A.P, A.nb);
+    if (!c->opt.alloc_cache) {
+        hipLaunchKernelGGL(k_alloc_draw<0>, grid, block, lds, s, A);
+    } else {
+        A.acache = c->acache.as<float>();
+        A.acinv = c->acinv.as<double>();
+        A.acmax = c->acmax.as<float>();
+        if (c->acache_version == c->input_version) {
+            hipLaunchKernelGGL(k_alloc_draw<2>, grid, block, lds, s, A);
+        } else {
+            hipLaunchKernelGGL(k_alloc_draw<1>, grid, block, lds, s, A);
+            c->acache_version = c->input_version;   // filled by this launch, ahead of any later one
+        }
+    }
     HIPCHK(hipGetLastError());
     return RMC_OK;
 }
@@ -2510,17 +2556,18 @@ template <class Real> rmc_status plan_pipeline(rmc_ctx *const *ctxs, int nsnap, 
     uint64_t total_ncpad = 0;
     std::vector<double> &faces = L->h_faces;
     faces.clear();
+    std::vector<std::pair<int, int>> blocks;
     for (int q = 0; q < nsnap; ++q) {
         if ((st = plan_snapshot<Real>(ctxs[q], P.D[q]))) return st;
-        append_faces(ctxs[q], P.D[q], faces);
+        append_faces(ctxs[q], P.D[q], faces, blocks);
         P.total_cells += ncells_of(ctxs[q]);
         total_ncpad += P.D[q].ncpad;
         P.multigrid = P.multigrid || P.D[q].nlev > 1;
     }
     P.nfaces = (int)faces.size();
-    if (march_lds_bytes(P.nfaces, L->nT, L->ns) > kMarchLds)
-        return fail(RMC_UNSUPPORTED, "face tables of all snapshots and four table slots (%d nodes, %d species) "
-                                     "exceed %d KiB of LDS", L->nT, L->ns, (int)(kMarchLds / 1024));
+    if (march_lds_bytes(P.nfaces, L->nT, L->ns) > march_lds_budget(L))
+        return fail(RMC_UNSUPPORTED, "face tables of all distinct grids and four table slots (%d nodes, %d species) "
+                                     "exceed %d KiB of LDS", L->nT, L->ns, (int)(march_lds_budget(L) / 1024));
     // tiles: whole bricks; about 1024 in total unless the options fix the size
     P.tile_cells = O.alloc_tile > 0 ? O.alloc_tile : auto_tile_cells(total_ncpad);
     std::vector<int> &tile_snap = L->h_tile_snap;
@@ -2823,6 +2870,7 @@ rmc_status run_pipeline(rmc_ctx *const *ctxs, int nsnap, double *const *divq, do
 // context's reduction slots and (pinned) readback; ingest_T_finish reads them after a sync.
 rmc_status ingest_T_enqueue(rmc_ctx *c, const void *src, rmc_dtype dt, rmc_mem mem, hipStream_t s)
 {
+    ++c->input_version;   // the fields change: the learned allocation cache is stale
     const uint64_t nc = ncells_of(c);
     const size_t esz = dt == RMC_F32 ? 4 : 8;
     rmc_status st;
@@ -2870,6 +2918,7 @@ rmc_status ingest_T_finish(rmc_ctx *c)
 // Mole-fraction ingest, enqueued (see ingest_T_enqueue); maxima x-hat and minima per species.
 rmc_status ingest_X_enqueue(rmc_ctx *c, int ns, const void *X, rmc_dtype dt, rmc_mem mem, hipStream_t s)
 {
+    ++c->input_version;   // the fields change: the learned allocation cache is stale
     const uint64_t nc = ncells_of(c);
     const size_t esz = dt == RMC_F32 ? 4 : 8;
     rmc_status st;
@@ -3019,6 +3068,13 @@ rmc_status rmc_create(int device, rmc_ctx **out)
     rmc_ctx *c = new (std::nothrow) rmc_ctx();
     if (!c) return fail(RMC_OUT_OF_MEMORY, "context allocation failed");
     c->device = device;
+    {
+        int lds = 0;
+        if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess &&
+            lds >= 64 * 1024)
+            c->lds_max = (size_t)lds;
+        (void)hipGetLastError();
+    }
     rmc_default_options(&c->opt);
     *out = c;
     return RMC_OK;
@@ -3048,6 +3104,7 @@ rmc_status rmc_set_grid(rmc_ctx *c, int nx, int ny, int nz, const double *xf, co
 {
     g_err.clear();
     if (rmc_status st = check_ctx(c)) return st;
+    ++c->input_version;
     if (nx < 1 || ny < 1 || nz < 1 || nx > 1023 || ny > 1023 || nz > 1023)
         return fail(RMC_INVALID_ARG, "grid dimensions must be in [1, 1023]");
     if (!xf || !yf || !zf) return fail(RMC_INVALID_ARG, "null face array");
@@ -3072,6 +3129,7 @@ rmc_status rmc_set_walls(rmc_ctx *c, double T0, double T1, double e0, double e1)
 {
     g_err.clear();
     if (rmc_status st = check_ctx(c)) return st;
+    ++c->input_version;
     if (!std::isfinite(T0) || !std::isfinite(T1) || T0 < 0 || T1 < 0)
         return fail(RMC_INVALID_ARG, "wall temperatures must be finite and >= 0");
     if (!(e0 >= 0.0 && e0 <= 1.0) || !(e1 >= 0.0 && e1 <= 1.0))
@@ -3089,6 +3147,7 @@ rmc_status rmc_set_box_walls(rmc_ctx *c, const double *T, const double *eps)
 {
     g_err.clear();
     if (rmc_status st = check_ctx(c)) return st;
+    ++c->input_version;
     if (!T) {
         c->closed = false;
         ++c->config_version;
@@ -3113,6 +3172,7 @@ rmc_status rmc_set_kdist(rmc_ctx *c, int nb, int ng, int ns, int nT, double T0, 
 {
     g_err.clear();
     if (rmc_status st = check_ctx(c)) return st;
+    ++c->input_version;
     if (nb < 1 || nb > 4096 || ng < 1 || ng > 255 || ns < 1 || ns > 8 || nT < 2)
         return fail(RMC_INVALID_ARG, "table sizes out of range");
     if (nb * ng > 2000) return fail(RMC_UNSUPPORTED, "nb * ng must not exceed 2000");
@@ -3520,6 +3580,9 @@ rmc_status rmc_graph_capture(rmc_ctx *const *ctxs, int nsnap, double *const *div
     if (!stream) return fail(RMC_INVALID_ARG, "graph capture needs a stream other than the null stream");
     if (rmc_status st = check_batch(ctxs, nsnap)) return st;
     for (int q = 0; q < nsnap; ++q)
+        if (ctxs[q]->opt.sampling == RMC_SAMPLING_LEARNED && ctxs[q]->opt.alloc_cache)
+            return fail(RMC_UNSUPPORTED, "alloc_cache cannot be captured (a replay cannot tell whether the field changed)");
+    for (int q = 0; q < nsnap; ++q)
         if (!divq[q]) return fail(RMC_INVALID_ARG, "null output in the batch");
     rmc_ctx *L = ctxs[0];
     DeviceGuard g(L->device);
@@ -3674,14 +3737,16 @@ rmc_status rmc_trace_cells(rmc_ctx *c, const int64_t *cells, int ncell, rmc_ray_
     const bool inc_xz = D.hx > 0.0 && D.hz > 0.0 && !D.closed;
     std::vector<double> &fd = c->h_faces;
     fd.clear();
-    append_faces(c, D, fd);
+    std::vector<std::pair<int, int>> fblocks;
+    append_faces(c, D, fd, fblocks);
     const int nfaces = (int)fd.size();
     const size_t nrec = (size_t)ncell * R;
     if ((st = c->faces.ensure(sizeof(double) * nfaces)) || (st = c->snaps.ensure(sizeof(SnapDesc))) ||
         (st = c->trace_cells.ensure(sizeof(int64_t) * ncell)) ||
         (st = c->trace_rec.ensure(sizeof(rmc_ray_record) * nrec)))
         return st;
-    if (nfaces * 8 > (int)kMarchLds) return fail(RMC_UNSUPPORTED, "face tables exceed %d KiB of LDS", (int)(kMarchLds / 1024));
+    if ((size_t)nfaces * 8 > march_lds_budget(c))
+        return fail(RMC_UNSUPPORTED, "face tables exceed %d KiB of LDS", (int)(march_lds_budget(c) / 1024));
     HIPCHK(hipMemcpyAsync(c->faces.p, fd.data(), (size_t)nfaces * 8, hipMemcpyHostToDevice, s));
     if ((st = dbl ? enqueue_snapshot<double>(c, D, c->faces.as<double>(), s)
                   : enqueue_snapshot<float>(c, D, c->faces.as<double>(), s)))

@@ -189,11 +189,17 @@ def timed_compute(s: rmc.Solver, dq, reps: int) -> float:
 
 def time_to_error(w, s_plain: rmc.Solver, s_learn: rmc.Solver, mix_eps: float, Rs=(16, 32, 64, 128),
                   ref_runs: int = 8, ref_R: int = 255, reps: int = 2, target: float = 0.01,
-                  snap_base: int = 1000, log: Optional[Callable[[str], None]] = None) -> dict:
+                  snap_base: int = 1000, log: Optional[Callable[[str], None]] = None, r_max: int = 255,
+                  alloc_cache: int = 0) -> dict:
     """Reference, errors and times at several R for both allocations on one field; the time
-    each needs for a `target` relative RMS error.  s_plain / s_learn carry the field, the
-    tables and their options (plain and learned sampling); their R and snapshot are changed
-    here."""
+    each needs for a `target` relative RMS error: t(R_1%) = t0 + t1 R_1% as if one compute
+    carried all R_1% rays per cell, and, as they are run, K = ceil(R_1% / r_max) computes of
+    r_max rays each: K (t0 + t1 r_max) (every compute pays t0, the allocation network's cost in
+    the learned mode).  With alloc_cache the learned computes reuse the field's allocation pair
+    sums (rmc_options.alloc_cache): the network's full pass is paid once per field (t_first, the
+    excess of the first compute over a cached one, added to the merged time) and t0 is the
+    cached computes' overhead.  s_plain / s_learn carry the field, the tables and their options
+    (plain and learned sampling); their R and snapshot are changed here."""
     import torch
     dev = torch.device("cuda", s_plain.device)
     dq = torch.zeros(w.ncells, dtype=torch.float64, device=dev)
@@ -202,7 +208,8 @@ def time_to_error(w, s_plain: rmc.Solver, s_learn: rmc.Solver, mix_eps: float, R
     def set_opts(s, R, snap, sampling, eps):
         s.set_options(rmc.default_options(rays_per_cell=R, seed=w.seed, snapshot=snap, tol=w.tol,
                                           max_steps=w.max_steps, march=rmc.F32, accum=rmc.ACC[w.accum],
-                                          sampling=sampling, mix_eps=eps))
+                                          sampling=sampling, mix_eps=eps,
+                                          alloc_cache=alloc_cache if sampling == rmc.SAMPLING_LEARNED else 0))
 
     # reference: ref_runs independent plain runs of ref_R rays (distinct snapshot streams)
     qsum = np.zeros(w.ncells)
@@ -219,6 +226,16 @@ def time_to_error(w, s_plain: rmc.Solver, s_learn: rmc.Solver, mix_eps: float, R
     for name, s, sampling in (("plain", s_plain, rmc.SAMPLING_PLAIN), ("learned", s_learn, rmc.SAMPLING_LEARNED)):
         eps = mix_eps if sampling == rmc.SAMPLING_LEARNED else 0.0
         es, ts, spr = [], [], []
+        t_first = 0.0
+        if alloc_cache and sampling == rmc.SAMPLING_LEARNED:
+            # the first compute of the field fills the cache: its excess over a cached compute
+            set_opts(s, Rs[0], snap_base + 99, sampling, eps)
+            torch.cuda.synchronize()
+            t0_ = time.perf_counter()
+            s.compute(dq)
+            torch.cuda.synchronize()
+            t_first = time.perf_counter() - t0_
+            t_first -= timed_compute(s, dq, reps)
         for R in Rs:
             set_opts(s, R, snap_base + 100 + R, sampling, eps)
             ts.append(timed_compute(s, dq, reps))
@@ -229,9 +246,13 @@ def time_to_error(w, s_plain: rmc.Solver, s_learn: rmc.Solver, mix_eps: float, R
         slope = float(np.polyfit(np.log(Rs_a), np.log(np.maximum(es_a, 1e-300)), 1)[0])
         R1 = float(np.median(Rs_a * (es_a / target) ** 2))
         t1, t0 = np.polyfit(Rs_a, ts_a, 1)
+        K = max(1, int(np.ceil(R1 / r_max)))
         out[name] = {"R": list(Rs), "rel_err": es, "t_s": ts, "steps_per_ray": spr, "err_slope": slope, "R_target": R1,
-                     "t0_s": float(t0), "t_per_ray_s": float(t1), "time_to_target_s": float(t0 + t1 * R1)}
+                     "t0_s": float(t0), "t_per_ray_s": float(t1), "time_to_target_s": float(t0 + t1 * R1),
+                     "computes_merged": K, "t_first_s": float(t_first),
+                     "time_to_target_merged_s": float(t_first + K * (t0 + t1 * r_max))}
         if log:
             log(f"{name}: err {np.round(es_a, 5).tolist()} slope {slope:.2f} R_1% {R1:.0f} steps/ray {spr[-1]:.1f} "
-                f"t(R) {np.round(ts_a * 1e3, 2).tolist()} ms -> {out[name]['time_to_target_s']:.3f} s")
+                f"t(R) {np.round(ts_a * 1e3, 2).tolist()} ms -> {out[name]['time_to_target_s']:.3f} s "
+                f"({K} computes of {r_max}: {out[name]['time_to_target_merged_s']:.3f} s)")
     return out

@@ -172,6 +172,51 @@ def test_learned_draws_and_rays_match_oracle(tables):
     assert np.array_equal((tr["n"] * w.kd.ng + tr["g"]) * 8 + tr["o"], strat[:20])
 
 
+def test_allocation_cache_gives_the_same_draws():
+    """alloc_cache: the compute that fills the cache and later ones that read it (another
+    snapshot, another R) draw exactly what computes without it draw; a new temperature field
+    rebuilds it; a captured graph refuses it."""
+    eps = 0.15
+    w = _workload(R=24, nb=20, ng=7, march="f32")
+    say(f"allocation cache {w.name}")
+    feat, _ = _solver(w).features()
+    params, mu, sd, nu_c, gx = _network(w, feat)
+    cells = np.arange(w.ncells)
+
+    def solver(cache):
+        s = _solver(w, sampling=rmc.SAMPLING_LEARNED, mix_eps=eps, alloc_cache=cache)
+        s.set_allocator(params, mu, sd, nu_c, gx)
+        return s
+
+    s_c, s_n = solver(1), solver(0)
+
+    def same(snap, R):
+        out = []
+        for s, cache in ((s_c, 1), (s_n, 0)):
+            s.set_options(rmc.default_options(rays_per_cell=R, seed=w.seed, snapshot=snap, tol=w.tol,
+                                              max_steps=w.max_steps, march=rmc.F32, sampling=rmc.SAMPLING_LEARNED,
+                                              mix_eps=eps, alloc_cache=cache))
+            dq, se = s.compute()
+            out.append((s.ray_draws(cells), dq))
+        (a_draw, a_q), (b_draw, b_q) = out
+        assert np.array_equal(a_draw[0], b_draw[0]) and np.array_equal(a_draw[1], b_draw[1]), (snap, R)
+        assert np.array_equal(a_q, b_q), (snap, R)
+
+    same(0, 24)      # fills the cache
+    same(5, 16)      # reads it
+    same(9, 40)
+    T2 = (np.asarray(w.T, dtype=np.float64) * 1.02).astype(np.float32)
+    for s in (s_c, s_n):
+        s.set_temperature(T2)
+    same(11, 24)     # the field changed: rebuilt
+    same(12, 24)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        with pytest.raises(rmc.RmcError) as e:
+            rmc.Graph([s_c], [torch.zeros(w.ncells, dtype=torch.float64, device="cuda:0")])
+    assert e.value.status == rmc.RMC_UNSUPPORTED
+
+
 def _training_batch(w, s, ncell, seed=4):
     """Plain-run rays of ncell sampled cells (oracle trace): device tensors of a TrainBatch and
     the host arrays the FP64 reference needs."""

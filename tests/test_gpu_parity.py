@@ -367,6 +367,39 @@ def test_batch_equals_single_snapshots():
         assert np.array_equal(a, b)
 
 
+def test_batch_of_one_grid_shares_its_face_tables():
+    """14 snapshots of one 1000 x 4 x 120 grid: 14 face tables would exceed the LDS a workgroup
+    has, one shared table fits; the batch equals the single-snapshot computes bitwise (one
+    long-ray form for all: the automatic choice depends on how many long rays a pass has)."""
+    ws = [_small_channel(march="f32", nx=1000, ny=4, nz=120, R=2, field_seed=q).replace(snap=q) for q in range(14)]
+    kd = ws[0].kd
+    ws = [x.replace(kd=kd) for x in ws]
+    say("batch of 14 snapshots of one grid")
+    singles = [_solver(x, long_ray_form=2).compute()[0] for x in ws]
+    solvers = [_solver(x, long_ray_form=2) for x in ws]
+    outs = [np.zeros(x.ncells) for x in ws]
+    rmc.compute_batch(solvers, outs)
+    for a, b in zip(singles, outs):
+        assert np.array_equal(a, b)
+
+
+def test_batch_of_distinct_grids_beyond_64_kib_of_lds():
+    """Seven distinct grids whose face tables and table slots need 73 KiB of LDS (more than the
+    64 KiB a workgroup had on earlier GPUs; the compute sizes its budget from the device):
+    the batch equals the single-snapshot computes bitwise (one long-ray form for all)."""
+    ws = [_small_channel(march="f32", nx=1000 - 8 * q, ny=4, nz=120, R=2, field_seed=q).replace(snap=q)
+          for q in range(7)]
+    kd = ws[0].kd
+    ws = [x.replace(kd=kd) for x in ws]
+    say("batch of 7 distinct grids, 73 KiB of LDS")
+    singles = [_solver(x, long_ray_form=2).compute()[0] for x in ws]
+    solvers = [_solver(x, long_ray_form=2) for x in ws]
+    outs = [np.zeros(x.ncells) for x in ws]
+    rmc.compute_batch(solvers, outs)
+    for a, b in zip(singles, outs):
+        assert np.array_equal(a, b)
+
+
 def test_batch_autotune_keeps_results_and_sets_every_context(tmp_path):
     """The batch autotuner times batched passes, writes one cache line naming every grid, and
     sets the chosen schedule on every context; the batched estimate is bitwise unchanged."""
