@@ -66,8 +66,9 @@ def parse():
                     help="consecutive 64-ray chunks each XCD takes in turn (0: library default)")
     ap.add_argument("--alloc-tile", type=int, default=0,
                     help="cells per allocation tile (0: library default, about 1024 tiles)")
-    ap.add_argument("--length-sort", action="store_true",
-                    help="reorder each march workgroup's rays by expected length")
+    ap.add_argument("--length-sort", type=int, default=-1,
+                    help="order of the rays in a bucket: 0 cell order, 1 each march workgroup reorders its "
+                         "rays by expected length (-1: library default)")
     ap.add_argument("--bucket-order", type=int, default=0, help="0: longest rays first, 1: band-major")
     ap.add_argument("--mg-levels", type=int, default=0,
                     help="multigrid march: grid levels (-1: all the grid allows; 0/1: DNS grid only)")
@@ -378,7 +379,7 @@ def precision_study(a):
                "max_abs_over_rms": float(np.abs(dY).max()) / rmsY,
                "rms_over_rms": rms(dY) / rmsY,
                "max_abs_over_rms_same_steps": float(np.abs(dY[same]).max()) / rmsY if same.any() else None,
-               "rel_err_max_where_abs_Y_above_rms": float((np.abs(dY) / np.abs(Y64))[np.abs(Y64) > rmsY].max()),
+               "rel_err_max_where_abs_Y_above_rms": float((np.abs(dY)[np.abs(Y64) > rmsY] / np.abs(Y64[np.abs(Y64) > rmsY])).max()),
                "rays_with_other_step_count": int((~same).sum()),
                "share_other_step_count": float((~same).mean())},
            "cell_fp32_march_vs_fp64": {
@@ -388,11 +389,11 @@ def precision_study(a):
            "cell_sums_comp_fp32_vs_fp64": {
                "max_abs_over_rms": float(np.abs(qc - q32).max()) / rmsQ,
                "rms_over_rms": rms(qc - q32) / rmsQ,
-               "max_rel_where_abs_above_rms": float((np.abs(qc - q32) / np.abs(q32))[np.abs(q32) > rmsQ].max())},
+               "max_rel_where_abs_above_rms": float((np.abs(qc - q32)[np.abs(q32) > rmsQ] / np.abs(q32[np.abs(q32) > rmsQ])).max())},
            "cell_sums_plain_fp32_vs_fp64": {
                "max_abs_over_rms": float(np.abs(qf - q32).max()) / rmsQ,
                "rms_over_rms": rms(qf - q32) / rmsQ,
-               "max_rel_where_abs_above_rms": float((np.abs(qf - q32) / np.abs(q32))[np.abs(q32) > rmsQ].max())},
+               "max_rel_where_abs_above_rms": float((np.abs(qf - q32)[np.abs(q32) > rmsQ] / np.abs(q32[np.abs(q32) > rmsQ])).max())},
            "mc_stderr_rms_over_rms_q": rms_se / rmsQ}
     print(json.dumps(out), flush=True)
     s.close()
@@ -449,8 +450,9 @@ def confirm_r1(a):
     method; then K = ceil(R_1% / r_max) computes of r_max rays per cell (distinct snapshot
     streams) are enqueued back to back and summed on the device, alternately into halves A and
     B.  The estimate Q averages all K, and the difference of the halves measures its error
-    without a reference: e = RMS(Q_A - Q_B) / (2 RMS(Q)) (each half carries twice the variance
-    of Q).  The wall time of the K computes is the measured time to 1 %."""
+    without a reference: Var(Q_A - Q_B) = Var(Q) K^2 / (n_A n_B), so
+    e = RMS(Q_A - Q_B) sqrt(n_A n_B) / K / RMS(Q) (RMS(Q_A - Q_B) / (2 RMS(Q)) for even K).
+    The wall time of the K computes is the measured time to 1 %."""
     import math
     import numpy as np
     import torch
@@ -690,9 +692,10 @@ def throughput(a):
     w = workload_of(a.workload)
     s = rmc.Solver(0)
     overrides = {k: v for k, v in (("long_ray_steps", a.long_ray_steps), ("xcd_span", a.xcd_span),
-                                   ("length_sort", int(a.length_sort)),
                                    ("bucket_order", a.bucket_order), ("mg_levels", a.mg_levels),
                                    ("mg_steps", a.mg_steps), ("alloc_tile", a.alloc_tile)) if v}
+    if a.length_sort >= 0:
+        overrides["length_sort"] = a.length_sort
     mg = a.mg_levels not in (0, 1)
     s.set_workload(w, **overrides)
     T = torch.from_numpy(np.ascontiguousarray(w.T, dtype=np.float32)).to(dev)
@@ -807,8 +810,12 @@ def learned_block(a, w):
         s_learn.set_allocator(net["params"], net["mu"], net["sd"], nu_c, gx)
         r = learned.time_to_error(we, s_plain, s_learn, net["mix_eps"], Rs=(16, 32, 64, 128), alloc_cache=1)
         results.append(r)
-        print(f"[learned] field {1000 + e}: plain {r['plain']['time_to_target_merged_s']:.1f} s, learned "
-              f"{r['learned']['time_to_target_merged_s']:.1f} s to 1 %", file=sys.stderr, flush=True)
+        row = {"field": 1000 + e}
+        for m in ("plain", "learned"):
+            row[m] = {k: r[m][k] for k in ("rel_err", "steps_per_ray", "err_slope", "R_target", "t0_s", "t_per_ray_s",
+                                           "time_to_target_s", "computes_merged", "t_first_s",
+                                           "time_to_target_merged_s")}
+        print(f"[learned] field {json.dumps(row)}", file=sys.stderr, flush=True)
     s_plain.close()
     s_learn.close()
     tp = np.array([r["plain"]["time_to_target_merged_s"] for r in results])
