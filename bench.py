@@ -70,6 +70,8 @@ def parse():
                     help="order of the rays in a bucket: 0 cell order, 1 each march workgroup reorders its "
                          "rays by expected length (-1: library default)")
     ap.add_argument("--bucket-order", type=int, default=0, help="0: longest rays first, 1: band-major")
+    ap.add_argument("--region-cells", type=int, default=0,
+                    help="cells per region of the march order (0: library default, -1: one region)")
     ap.add_argument("--mg-levels", type=int, default=0,
                     help="multigrid march: grid levels (-1: all the grid allows; 0/1: DNS grid only)")
     ap.add_argument("--mg-steps", type=int, default=0, help="multigrid march: steps per grid (0: 5)")
@@ -693,7 +695,8 @@ def throughput(a):
     s = rmc.Solver(0)
     overrides = {k: v for k, v in (("long_ray_steps", a.long_ray_steps), ("xcd_span", a.xcd_span),
                                    ("bucket_order", a.bucket_order), ("mg_levels", a.mg_levels),
-                                   ("mg_steps", a.mg_steps), ("alloc_tile", a.alloc_tile)) if v}
+                                   ("mg_steps", a.mg_steps), ("alloc_tile", a.alloc_tile),
+                                   ("region_cells", a.region_cells)) if v}
     if a.length_sort >= 0:
         overrides["length_sort"] = a.length_sort
     mg = a.mg_levels not in (0, 1)

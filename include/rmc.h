@@ -124,6 +124,16 @@ typedef struct {
                                 only for the octants of the pairs they draw; the draws and values
                                 are the same as without it.  0 (default): the network runs over
                                 every pair at every compute.  Not in a captured graph */
+    int32_t region_cells;    /* march order: the work list runs region by region -- groups of
+                                allocation tiles compact in x and y, spanning z, holding about this
+                                many cells -- and inside a region bucket by bucket, so that the rays
+                                in flight start in one region and gather its cell records from L2
+                                (an addition to the paper's narrow-band ordering of Sec. 4.2);
+                                0 = default: regions of 262144 cells in snapshots of at least twice
+                                that, one region in smaller ones; -1 = one region per snapshot
+                                (bucket-major order); >= 64: this many cells.  Each (region,
+                                bucket) run is padded to whole wavefronts.  Results are the same in
+                                every order */
 } rmc_options;
 
 typedef struct {

@@ -8,7 +8,9 @@
 //                      layout (table interpolation of Sec. 2.2 done once per cell, not per step).
 //   3. k_alloc_count   per tile of cells: histogram of the rays' (n, g, octant) buckets.
 //      k_bucket_scan   per bucket: exclusive scan over tiles (no global atomics).
-//      k_bucket_layout bucket starts padded to whole wavefronts, chunk -> bucket map.
+//      k_run_len / k_run_layout: the work list runs region by region (compact groups of tiles),
+//                      bucket by bucket inside a region; run starts padded to whole
+//                      wavefronts.  k_chunk_map: chunk -> bucket map.
 //      k_alloc_scatter per tile: ray work items into their bucket (narrow-band sorting of
 //                      Sec. 4.2: a wavefront marches rays of one (n, g, octant)).
 //   4. k_march         one lane per ray, Algorithm 1 march, ray value into its slot.
@@ -84,14 +86,25 @@ struct SnapDesc {
                                 // y0 [nx][nz], y1, z0 [nx][ny], z1
 };
 
+// An allocation tile: tile_cells consecutive cells of a snapshot's brick-linear order, and the
+// region of the march order it belongs to.  Tiles are numbered region by region.
+struct TileInfo {
+    int snap;                   // snapshot of the tile
+    uint32_t first;             // its first cell in the snapshot's brick-linear order
+    uint32_t region;            // its region (numbered over the whole pass)
+    uint32_t pad;
+};
+
 struct AllocArgs {
     const SnapDesc *snaps;
-    const int *tile_snap;       // [ntiles] snapshot of each tile
+    const TileInfo *tiles;      // [ntiles]
     int ntiles, tile_cells;
     int nb, ng, nbucket, R;
     uint32_t k0, k1;
-    uint32_t *hist;             // [nbucket][ntiles]
-    const uint32_t *bucket_start;
+    uint32_t *hist;             // [nbucket][ntiles], scanned per bucket over the tiles
+    const uint32_t *btotal;     // [nbucket] rays per bucket
+    const uint32_t *rtile0;     // [nregion + 1] first tile of each region
+    const uint32_t *rstart;     // [nregion][nbucket] start of each (region, bucket) run of the work list
     uint4 *items;               // (i | j<<10 | k<<20, r | k_ord<<8 | snapshot<<16, dir word 0, dir word 1)
     int lds_bricks;             // the tile's bricks are decoded into LDS (else per cell from the index)
     int lds_cdf;                // plain sampling: the cdfs are staged in LDS by the counting pass
@@ -529,8 +542,9 @@ __global__ void __launch_bounds__(kAllocThreads) k_alloc_count(AllocArgs A)
     uint32_t *lh = reinterpret_cast<uint32_t *>(lds_d + ncdf);   // [nbucket]
     uint32_t *bt = A.lds_bricks ? lh + A.nbucket : nullptr;        // [tile_cells / 64]
     const int tile = blockIdx.x;
-    const SnapDesc &D = A.snaps[A.tile_snap[tile]];
-    const uint64_t first = (uint64_t)(tile - D.tile_begin) * A.tile_cells;
+    const TileInfo TI = A.tiles[tile];
+    const SnapDesc &D = A.snaps[TI.snap];
+    const uint64_t first = TI.first;
     for (int b = threadIdx.x; b < A.nbucket; b += blockDim.x) lh[b] = 0;
     if (cdf) {
         for (int q = threadIdx.x; q < A.nb; q += blockDim.x) lds_d[q] = D.cdf_b[q];
@@ -578,19 +592,36 @@ __global__ void __launch_bounds__(64) k_bucket_scan(uint32_t *hist, int ntiles, 
     if (lane == 0) bucket_total[b] = carry;
 }
 
-// bucket starts padded to multiples of 64 (one wavefront never mixes buckets), total chunks
-// (buckets laid out in the given order: longest expected rays first)
-__global__ void __launch_bounds__(1024) k_bucket_layout(const uint32_t *total, const uint32_t *order, int nbucket,
-                                                         uint32_t *start, uint32_t *nchunks)
+// Scanned count of bucket b before tile t (t = ntiles: the bucket's total).
+__device__ __forceinline__ uint32_t hist_before(const uint32_t *hist, const uint32_t *total, int ntiles, int b, uint32_t t)
+{
+    return t < (uint32_t)ntiles ? hist[(size_t)b * ntiles + t] : total[b];
+}
+
+// Rays of run e = (region, bucket) of the work list, padded to whole wavefronts (one wavefront
+// never mixes buckets).
+__global__ void k_run_len(const uint32_t *hist, const uint32_t *total, int ntiles, const uint32_t *rtile0,
+                          int nbucket, uint64_t nrun, uint32_t *run_len)
+{
+    const uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (e >= nrun) return;
+    const uint32_t g = (uint32_t)(e / nbucket), b = (uint32_t)(e % nbucket);
+    const uint32_t n = hist_before(hist, total, ntiles, b, rtile0[g + 1]) - hist_before(hist, total, ntiles, b, rtile0[g]);
+    run_len[e] = (n + 63u) & ~63u;
+}
+
+// Run starts: regions in turn, inside a region the buckets in the given order (longest
+// expected rays first); exclusive scan of the padded lengths, total chunks.
+__global__ void __launch_bounds__(1024) k_run_layout(const uint32_t *run_len, const uint32_t *order, int nbucket,
+                                                      int nregion, uint32_t *rstart, uint32_t *nchunks)
 {
     __shared__ uint32_t part[1024];
     const int tid = threadIdx.x;
-    const int per = (nbucket + 1023) / 1024;
+    const uint64_t nrun = (uint64_t)nregion * nbucket;
+    const uint64_t per = (nrun + 1023) / 1024;
+    auto run_of = [&](uint64_t x) { return (x / nbucket) * nbucket + order[x % nbucket]; };
     uint32_t s = 0;
-    for (int q = 0; q < per; ++q) {
-        const int pos = tid * per + q;
-        if (pos < nbucket) s += (total[order[pos]] + 63u) & ~63u;
-    }
+    for (uint64_t x = tid * per; x < min(nrun, (tid + 1) * per); ++x) s += run_len[run_of(x)];
     part[tid] = s;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
@@ -600,24 +631,23 @@ __global__ void __launch_bounds__(1024) k_bucket_layout(const uint32_t *total, c
         __syncthreads();
     }
     uint32_t run = part[tid] - s;
-    for (int q = 0; q < per; ++q) {
-        const int pos = tid * per + q;
-        if (pos < nbucket) {
-            const uint32_t b = order[pos];
-            start[b] = run;
-            run += (total[b] + 63u) & ~63u;
-        }
+    for (uint64_t x = tid * per; x < min(nrun, (tid + 1) * per); ++x) {
+        const uint64_t e = run_of(x);
+        rstart[e] = run;
+        run += run_len[e];
     }
-    if (tid == 1023) { start[nbucket] = part[1023]; *nchunks = part[1023] / 64u; }
+    if (tid == 1023) { rstart[nrun] = part[1023]; *nchunks = part[1023] / 64u; }
 }
 
-// chunk -> bucket map and invalid markers on the padding of each bucket
-__global__ void k_chunk_map(const uint32_t *total, const uint32_t *start, int nbucket, uint32_t *chunk_bucket,
-                            uint4 *items)
+// chunk -> bucket map and invalid markers on the padding of each run
+__global__ void k_chunk_map(const uint32_t *hist, const uint32_t *total, int ntiles, const uint32_t *rtile0,
+                            const uint32_t *rstart, int nbucket, uint64_t nrun, uint32_t *chunk_bucket, uint4 *items)
 {
-    const int b = blockIdx.x * blockDim.y + threadIdx.y;
-    if (b >= nbucket) return;
-    const uint32_t s = start[b], e = s + ((total[b] + 63u) & ~63u), used = s + total[b];
+    const uint64_t r = blockIdx.x * (uint64_t)blockDim.y + threadIdx.y;
+    if (r >= nrun) return;
+    const uint32_t g = (uint32_t)(r / nbucket), b = (uint32_t)(r % nbucket);
+    const uint32_t n = hist_before(hist, total, ntiles, b, rtile0[g + 1]) - hist_before(hist, total, ntiles, b, rtile0[g]);
+    const uint32_t s = rstart[r], e = s + ((n + 63u) & ~63u), used = s + n;
     for (uint32_t q = s / 64 + threadIdx.x; q < e / 64; q += blockDim.x) chunk_bucket[q] = (uint32_t)b;
     for (uint32_t q = used + threadIdx.x; q < e; q += blockDim.x) items[q] = make_uint4(0u, kInvalidItem, 0u, 0u);
 }
@@ -654,11 +684,14 @@ __global__ void __launch_bounds__(kAllocThreads) k_alloc_scatter(AllocArgs A)
     extern __shared__ uint32_t lb[];   // [nbucket] next free position, [blockDim] bucket of each thread, bricks
     uint32_t *sb = lb + A.nbucket, *bt = A.lds_bricks ? sb + blockDim.x : nullptr;
     const int tile = blockIdx.x;
-    const int s = A.tile_snap[tile];
+    const TileInfo TI = A.tiles[tile];
+    const int s = TI.snap;
     const SnapDesc &D = A.snaps[s];
-    const uint64_t first = (uint64_t)(tile - D.tile_begin) * A.tile_cells;
+    const uint64_t first = TI.first;
+    const uint32_t t0 = A.rtile0[TI.region];   // the region's first tile
     for (int b = threadIdx.x; b < A.nbucket; b += blockDim.x)
-        lb[b] = A.bucket_start[b] + A.hist[(size_t)b * A.ntiles + tile];
+        lb[b] = A.rstart[(size_t)TI.region * A.nbucket + b] + A.hist[(size_t)b * A.ntiles + tile] -
+                A.hist[(size_t)b * A.ntiles + t0];
     if (bt) tile_bricks(D, first, A.tile_cells, bt);
     __syncthreads();
     const int cpp = blockDim.x / A.R;
@@ -1963,7 +1996,7 @@ struct rmc_ctx {
     bool up_pending = false;
     int slots_R = 0, slots_real = 0;
     // shared pipeline workspace (used when this context leads a batch)
-    DBuf hist, bucket_total, bucket_start, nchunks, chunk_bucket, items, faces, snaps, tile_snap, counters, red_part,
+    DBuf hist, bucket_total, rstart, run_len, rtile0, nchunks, chunk_bucket, items, faces, snaps, tile_info, counters, red_part,
         outbuf, tune_out;
     DBuf trace_rec, trace_cells, border, kmin, cont, cont_count, probe;
     std::vector<float> h_kmin;
@@ -1972,7 +2005,8 @@ struct rmc_ctx {
     // host staging of the per-compute descriptors (kept alive until the next compute)
     std::vector<double> h_faces;
     std::vector<unsigned char> h_snaps;
-    std::vector<int> h_tile_snap;
+    std::vector<TileInfo> h_tiles;
+    std::vector<uint32_t> h_rtile0;
     std::vector<uint32_t> h_order;
     DBuf small;             // ingest results
     DBuf scal;              // [0]: max cell temperature, [1..8]: largest mole fraction per species
@@ -2015,6 +2049,30 @@ uint64_t ncpad_of(const rmc_ctx *c)
 int auto_tile_cells(uint64_t total_ncpad)
 {
     return (int)std::min<uint64_t>(8192, std::max<uint64_t>(256, (total_ncpad / 1024 + 63) / 64 * 64));
+}
+
+// Regions of the march order: the tiles of a snapshot grouped by the brick row (bi, bj) of
+// their first brick into blocks of gx x gy rows (all of z, which a row spans) holding about
+// region_cells cells, compact in x and y; region_cells < 0: the snapshot is one region.  By
+// default (0) regions of kDefaultRegionCells cells, for snapshots of at least twice that (a
+// smaller record field stays in L2 anyway, and splitting its buckets only shortens the runs).
+constexpr int kDefaultRegionCells = 262144;
+
+void tile_regions(uint64_t ncpad, int nby, int nbz, int ntiles, int tile_cells, int region_cells,
+                  std::vector<uint32_t> &region)
+{
+    region.assign(ntiles, 0u);
+    if (region_cells < 0 || (region_cells == 0 && ncpad < 2ull * kDefaultRegionCells)) return;
+    const uint64_t rows = std::max<uint64_t>(1, (uint64_t)(region_cells > 0 ? region_cells : kDefaultRegionCells) /
+                                                    (64ull * nbz));
+    const int gy = std::max(1, std::min((int)std::lround(std::sqrt((double)rows)), nby));
+    const int gx = (int)std::max<uint64_t>(1, rows / gy);
+    const int ry = (nby + gy - 1) / gy;
+    for (int t = 0; t < ntiles; ++t) {
+        const uint64_t row = (uint64_t)t * (tile_cells / 64) / nbz;   // brick row of the tile's first brick
+        const int bj = (int)(row % nby), bi = (int)(row / nby);
+        region[t] = (uint32_t)((bi / gx) * ry + bj / gy);
+    }
 }
 
 // Temperature and emissivity of wall w (x0, x1, y0, y1, z0, z1); in a periodic box the x and z
@@ -2075,6 +2133,8 @@ rmc_status check_options(const rmc_options *o)
         return fail(RMC_INVALID_ARG, "alloc_tile must be 0 or a multiple of 64 in [256, 65536]");
     if (o->long_ray_form < 0 || o->long_ray_form > 2) return fail(RMC_INVALID_ARG, "long_ray_form must be 0, 1 or 2");
     if (o->alloc_cache != 0 && o->alloc_cache != 1) return fail(RMC_INVALID_ARG, "alloc_cache must be 0 or 1");
+    if (o->region_cells < -1 || (o->region_cells > 0 && o->region_cells < 64))
+        return fail(RMC_INVALID_ARG, "region_cells must be -1, 0 or at least 64");
     return RMC_OK;
 }
 
@@ -2536,7 +2596,9 @@ struct Plan {
     // the leader's buffers)
     double *d_faces = nullptr;
     SnapDesc *d_snaps = nullptr;
-    int *d_tile_snap = nullptr;
+    TileInfo *d_tiles = nullptr;
+    uint32_t *d_rtile0 = nullptr;
+    int nregion = 0;
     uint32_t *d_border = nullptr;
     float *d_kmin = nullptr;
 };
@@ -2570,28 +2632,46 @@ template <class Real> rmc_status plan_pipeline(rmc_ctx *const *ctxs, int nsnap, 
                                      "exceed %d KiB of LDS", L->nT, L->ns, (int)(march_lds_budget(L) / 1024));
     // tiles: whole bricks; about 1024 in total unless the options fix the size
     P.tile_cells = O.alloc_tile > 0 ? O.alloc_tile : auto_tile_cells(total_ncpad);
-    std::vector<int> &tile_snap = L->h_tile_snap;
-    tile_snap.clear();
+    // tiles of each snapshot numbered region by region (regions numbered over the pass)
+    std::vector<TileInfo> &tiles = L->h_tiles;
+    std::vector<uint32_t> &rtile0 = L->h_rtile0;
+    tiles.clear();
+    rtile0.clear();
+    std::vector<uint32_t> reg;
+    std::vector<int> perm;
     for (int q = 0; q < nsnap; ++q) {
-        P.D[q].tile_begin = P.ntiles;
-        P.D[q].ntiles = (int)((P.D[q].ncpad + P.tile_cells - 1) / P.tile_cells);
-        P.ntiles += P.D[q].ntiles;
-        for (int t = 0; t < P.D[q].ntiles; ++t) tile_snap.push_back(q);
-        P.inc_xz = P.inc_xz && P.D[q].hx > 0.0 && P.D[q].hz > 0.0 && !P.D[q].closed;
-        P.periodic_xz = P.periodic_xz && !P.D[q].closed;
+        SnapDesc &D = P.D[q];
+        D.tile_begin = P.ntiles;
+        D.ntiles = (int)((D.ncpad + P.tile_cells - 1) / P.tile_cells);
+        P.ntiles += D.ntiles;
+        tile_regions(D.ncpad, D.nby, D.nbz, D.ntiles, P.tile_cells, O.region_cells, reg);
+        perm.resize(D.ntiles);
+        for (int t = 0; t < D.ntiles; ++t) perm[t] = t;
+        std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return reg[a] < reg[b]; });
+        for (int u = 0; u < D.ntiles; ++u) {
+            const int t = perm[u];
+            if (u == 0 || reg[t] != reg[perm[u - 1]]) rtile0.push_back((uint32_t)tiles.size());
+            tiles.push_back(TileInfo{q, (uint32_t)((uint64_t)t * P.tile_cells), (uint32_t)(rtile0.size() - 1), 0u});
+        }
+        P.inc_xz = P.inc_xz && D.hx > 0.0 && D.hz > 0.0 && !D.closed;
+        P.periodic_xz = P.periodic_xz && !D.closed;
     }
-    const uint64_t max_items = (P.total_cells * R + (uint64_t)nbucket * 63 + 63) / 64 * 64;
+    P.nregion = (int)rtile0.size();
+    rtile0.push_back((uint32_t)tiles.size());
+    const uint64_t nrun = (uint64_t)P.nregion * nbucket;
+    const uint64_t max_items = (P.total_cells * R + nrun * 63 + 63) / 64 * 64;
     P.max_chunks = max_items / 64;
     if (max_items >= (1ull << 32)) return fail(RMC_UNSUPPORTED, "more than 2^32 rays in one pass");
     if ((uint64_t)nbucket * P.ntiles > (1ull << 30))
         return fail(RMC_UNSUPPORTED, "per-tile bucket histograms above 2^30 counters: choose a larger alloc_tile");
     if ((st = L->hist.ensure(sizeof(uint32_t) * (uint64_t)nbucket * P.ntiles)) ||
         (st = L->bucket_total.ensure(sizeof(uint32_t) * nbucket)) ||
-        (st = L->bucket_start.ensure(sizeof(uint32_t) * (nbucket + 1))) ||
+        (st = L->rstart.ensure(sizeof(uint32_t) * (nrun + 1))) || (st = L->run_len.ensure(sizeof(uint32_t) * nrun)) ||
+        (st = L->rtile0.ensure(sizeof(uint32_t) * (P.nregion + 1))) ||
         (st = L->nchunks.ensure(sizeof(uint32_t))) ||
         (st = L->chunk_bucket.ensure(sizeof(uint32_t) * P.max_chunks)) ||
         (st = L->items.ensure(sizeof(uint4) * max_items)) || (st = L->faces.ensure(sizeof(double) * P.nfaces)) ||
-        (st = L->snaps.ensure(sizeof(SnapDesc) * nsnap)) || (st = L->tile_snap.ensure(sizeof(int) * P.ntiles)) ||
+        (st = L->snaps.ensure(sizeof(SnapDesc) * nsnap)) || (st = L->tile_info.ensure(sizeof(TileInfo) * P.ntiles)) ||
         (st = L->border.ensure(sizeof(uint32_t) * nbucket)) ||
         (st = L->counters.ensure(sizeof(unsigned long long) * 4)) ||
         (st = L->red_part.ensure(sizeof(unsigned long long) * 2 * 2048)) ||
@@ -2620,24 +2700,27 @@ template <class Real> rmc_status plan_pipeline(rmc_ctx *const *ctxs, int nsnap, 
     memcpy(L->h_snaps.data(), P.D.data(), sizeof(SnapDesc) * nsnap);
     march_order(L, L->h_order);
     // descriptor uploads from one pinned staging buffer (reused once the last upload is done)
-    const size_t sz[5] = {sizeof(double) * P.nfaces, sizeof(SnapDesc) * nsnap, sizeof(int) * P.ntiles,
-                          sizeof(uint32_t) * nbucket, sizeof(float) * nb * ng};
-    const void *src[5] = {faces.data(), L->h_snaps.data(), tile_snap.data(), L->h_order.data(), L->h_kmin.data()};
+    constexpr int kUp = 6;
+    const size_t sz[kUp] = {sizeof(double) * P.nfaces, sizeof(SnapDesc) * nsnap, sizeof(TileInfo) * P.ntiles,
+                            sizeof(uint32_t) * nbucket, sizeof(float) * nb * ng, sizeof(uint32_t) * rtile0.size()};
+    const void *src[kUp] = {faces.data(), L->h_snaps.data(), tiles.data(), L->h_order.data(), L->h_kmin.data(),
+                            rtile0.data()};
     P.d_faces = L->faces.as<double>();
     P.d_snaps = L->snaps.as<SnapDesc>();
-    P.d_tile_snap = L->tile_snap.as<int>();
+    P.d_tiles = L->tile_info.as<TileInfo>();
     P.d_border = L->border.as<uint32_t>();
     P.d_kmin = L->kmin.as<float>();
-    void *dst[5] = {P.d_faces, P.d_snaps, P.d_tile_snap, P.d_border, P.d_kmin};
-    size_t off[5], total = 0;
-    for (int u = 0; u < 5; ++u) {
+    P.d_rtile0 = L->rtile0.as<uint32_t>();
+    void *dst[kUp] = {P.d_faces, P.d_snaps, P.d_tiles, P.d_border, P.d_kmin, P.d_rtile0};
+    size_t off[kUp], total = 0;
+    for (int u = 0; u < kUp; ++u) {
         off[u] = total;
         total += (sz[u] + 255) & ~(size_t)255;
     }
     if (t_arena) {
         // allocation-free compute: copies from the host staging vectors themselves (pageable;
         // they stay unchanged until this context's next compute)
-        for (int u = 0; u < 5; ++u) HIPCHK(hipMemcpyAsync(dst[u], src[u], sz[u], hipMemcpyHostToDevice, s));
+        for (int u = 0; u < kUp; ++u) HIPCHK(hipMemcpyAsync(dst[u], src[u], sz[u], hipMemcpyHostToDevice, s));
         return RMC_OK;
     }
     if (L->up_pending) {
@@ -2647,7 +2730,7 @@ template <class Real> rmc_status plan_pipeline(rmc_ctx *const *ctxs, int nsnap, 
     if ((st = L->hup.ensure(total))) return st;
     if (!L->up_evt) HIPCHK(hipEventCreateWithFlags(&L->up_evt, hipEventDisableTiming));
     unsigned char *stage = L->hup.as<unsigned char>();
-    for (int u = 0; u < 5; ++u) {
+    for (int u = 0; u < kUp; ++u) {
         memcpy(stage + off[u], src[u], sz[u]);
         HIPCHK(hipMemcpyAsync(dst[u], stage + off[u], sz[u], hipMemcpyHostToDevice, s));
     }
@@ -2677,13 +2760,15 @@ rmc_status enqueue_pipeline(const Plan &P, double *const *divq, double *const *s
     // 3. allocation: histogram per tile, scan per bucket, layout, scatter
     AllocArgs AA;
     AA.snaps = P.d_snaps;
-    AA.tile_snap = P.d_tile_snap;
+    AA.tiles = P.d_tiles;
+    AA.btotal = L->bucket_total.as<uint32_t>();
+    AA.rtile0 = P.d_rtile0;
     AA.ntiles = P.ntiles;
     AA.tile_cells = P.tile_cells;
     AA.nb = nb; AA.ng = ng; AA.nbucket = nbucket; AA.R = R;
     AA.k0 = (uint32_t)O.seed; AA.k1 = (uint32_t)(O.seed >> 32);
     AA.hist = L->hist.as<uint32_t>();
-    AA.bucket_start = L->bucket_start.as<uint32_t>();
+    AA.rstart = L->rstart.as<uint32_t>();
     AA.items = L->items.as<uint4>();
     // 1024 threads per tile unless the bucket counters and the per-thread buckets overflow 64 KiB;
     // the tile's bricks and the plain cdfs go to LDS where they fit beside them
@@ -2700,12 +2785,16 @@ rmc_status enqueue_pipeline(const Plan &P, double *const *divq, double *const *s
     hipLaunchKernelGGL(k_bucket_scan, dim3(nbucket), dim3(64), 0, s, L->hist.as<uint32_t>(), P.ntiles,
                        L->bucket_total.as<uint32_t>());
     HIPCHK(hipGetLastError());
-    hipLaunchKernelGGL(k_bucket_layout, dim3(1), dim3(1024), 0, s, L->bucket_total.as<uint32_t>(),
-                       P.d_border, nbucket, L->bucket_start.as<uint32_t>(), L->nchunks.as<uint32_t>());
+    const uint64_t nrun = (uint64_t)P.nregion * nbucket;
+    hipLaunchKernelGGL(k_run_len, dim3((unsigned)((nrun + 255) / 256)), dim3(256), 0, s, L->hist.as<uint32_t>(),
+                       L->bucket_total.as<uint32_t>(), P.ntiles, P.d_rtile0, nbucket, nrun, L->run_len.as<uint32_t>());
     HIPCHK(hipGetLastError());
-    hipLaunchKernelGGL(k_chunk_map, dim3((nbucket + 3) / 4), dim3(64, 4), 0, s, L->bucket_total.as<uint32_t>(),
-                       L->bucket_start.as<uint32_t>(), nbucket, L->chunk_bucket.as<uint32_t>(),
-                       L->items.as<uint4>());
+    hipLaunchKernelGGL(k_run_layout, dim3(1), dim3(1024), 0, s, L->run_len.as<uint32_t>(), P.d_border, nbucket,
+                       P.nregion, L->rstart.as<uint32_t>(), L->nchunks.as<uint32_t>());
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_chunk_map, dim3((unsigned)((nrun + 3) / 4)), dim3(64, 4), 0, s, L->hist.as<uint32_t>(),
+                       L->bucket_total.as<uint32_t>(), P.ntiles, P.d_rtile0, L->rstart.as<uint32_t>(), nbucket, nrun,
+                       L->chunk_bucket.as<uint32_t>(), L->items.as<uint4>());
     HIPCHK(hipGetLastError());
     if (P.smode == 2) hipLaunchKernelGGL(k_alloc_scatter<2>, dim3(P.ntiles), dim3(at), lds_scatter, s, AA);
     else if (P.smode == 1) hipLaunchKernelGGL(k_alloc_scatter<1>, dim3(P.ntiles), dim3(at), lds_scatter, s, AA);
@@ -2973,7 +3062,7 @@ struct rmc_graph {
     std::vector<std::vector<void *>> ptrs;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    DBuf faces, snaps, tile_snap, border, kmin;   // the graph's own copies of the planned tables
+    DBuf faces, snaps, tile_info, border, kmin, rtile0;   // the graph's own copies of the planned tables
 };
 
 namespace {
@@ -2984,8 +3073,8 @@ std::vector<void *> buffer_ptrs(const rmc_ctx *c)
     const DBuf *b[] = {&c->k64, &c->k32, &c->Ib, &c->dnu, &c->wg, &c->T, &c->X, &c->scal, &c->q, &c->cpdf, &c->ccdf_b,
                        &c->ccdf_g, &c->ccdf_o, &c->pdf_scratch, &c->p, &c->cdf_b, &c->cdf_g, &c->W, &c->Iw,
                        &c->status, &c->rec, &c->Y, &c->st, &c->hist, &c->bucket_total,
-                       &c->bucket_start, &c->nchunks, &c->chunk_bucket, &c->items, &c->faces,
-                       &c->snaps, &c->tile_snap, &c->border, &c->counters, &c->red_part, &c->kmin, &c->cont, &c->cont_count,
+                       &c->rstart, &c->run_len, &c->rtile0, &c->nchunks, &c->chunk_bucket, &c->items, &c->faces,
+                       &c->snaps, &c->tile_info, &c->border, &c->counters, &c->red_part, &c->kmin, &c->cont, &c->cont_count,
                        &c->rbkt, &c->mgT, &c->mgX, &c->mgrec, &c->dprob, &c->dstrat, &c->lpp, &c->prm,
                        &c->musd, &c->nu_c, &c->gxs, &c->kp, &c->feat, &c->fmask, &c->bng, &c->lfaces};
     std::vector<void *> v;
@@ -3088,8 +3177,8 @@ void rmc_destroy(rmc_ctx *c)
         (void)hipDeviceSynchronize();
         DBuf *bufs[] = {&c->k64, &c->k32, &c->Ib, &c->dnu, &c->wg, &c->T, &c->X, &c->stage, &c->stage2, &c->q, &c->cpdf, &c->ccdf_b,
                         &c->ccdf_g, &c->ccdf_o, &c->pdf_scratch, &c->p, &c->cdf_b, &c->cdf_g, &c->W, &c->Iw,
-                        &c->status, &c->rec, &c->Y, &c->st, &c->hist, &c->bucket_total, &c->bucket_start,
-                        &c->nchunks, &c->chunk_bucket, &c->items, &c->faces, &c->snaps, &c->tile_snap,
+                        &c->status, &c->rec, &c->Y, &c->st, &c->hist, &c->bucket_total, &c->rstart, &c->run_len, &c->rtile0,
+                        &c->nchunks, &c->chunk_bucket, &c->items, &c->faces, &c->snaps, &c->tile_info,
                         &c->counters, &c->red_part, &c->outbuf, &c->tune_out, &c->trace_rec, &c->trace_cells, &c->border, &c->small, &c->scal,
                         &c->kmin, &c->cont, &c->cont_count};
         for (DBuf *b : bufs) b->release();
@@ -3596,11 +3685,11 @@ rmc_status rmc_graph_capture(rmc_ctx *const *ctxs, int nsnap, double *const *div
     if (!G) return fail(RMC_OUT_OF_MEMORY, "graph allocation failed");
     {   // the graph reads its own copies of the planned tables
         const size_t nb_ = (size_t)L->nb * L->ng;
-        const size_t sz[5] = {sizeof(double) * P.nfaces, sizeof(SnapDesc) * nsnap, sizeof(int) * P.ntiles,
-                              sizeof(uint32_t) * nb_ * 8, sizeof(float) * nb_};
-        DBuf *dst[5] = {&G->faces, &G->snaps, &G->tile_snap, &G->border, &G->kmin};
-        const void *src[5] = {P.d_faces, P.d_snaps, P.d_tile_snap, P.d_border, P.d_kmin};
-        for (int u = 0; u < 5; ++u) {
+        const size_t sz[6] = {sizeof(double) * P.nfaces, sizeof(SnapDesc) * nsnap, sizeof(TileInfo) * P.ntiles,
+                              sizeof(uint32_t) * nb_ * 8, sizeof(float) * nb_, sizeof(uint32_t) * (P.nregion + 1)};
+        DBuf *dst[6] = {&G->faces, &G->snaps, &G->tile_info, &G->border, &G->kmin, &G->rtile0};
+        const void *src[6] = {P.d_faces, P.d_snaps, P.d_tiles, P.d_border, P.d_kmin, P.d_rtile0};
+        for (int u = 0; u < 6; ++u) {
             if ((st = dst[u]->ensure(sz[u]))) { delete G; return st; }
             if (hipMemcpyAsync(dst[u]->p, src[u], sz[u], hipMemcpyDeviceToDevice, s) != hipSuccess) {
                 delete G;
@@ -3609,9 +3698,10 @@ rmc_status rmc_graph_capture(rmc_ctx *const *ctxs, int nsnap, double *const *div
         }
         P.d_faces = G->faces.as<double>();
         P.d_snaps = G->snaps.as<SnapDesc>();
-        P.d_tile_snap = G->tile_snap.as<int>();
+        P.d_tiles = G->tile_info.as<TileInfo>();
         P.d_border = G->border.as<uint32_t>();
         P.d_kmin = G->kmin.as<float>();
+        P.d_rtile0 = G->rtile0.as<uint32_t>();
     }
     if (hipStreamSynchronize(s) != hipSuccess) { delete G; return fail(RMC_DEVICE_ERROR, "hipStreamSynchronize failed"); }
     if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {

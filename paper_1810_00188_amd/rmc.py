@@ -35,7 +35,8 @@ class Options(C.Structure):
                 ("block_threads", C.c_int32), ("long_ray_steps", C.c_int32),
                 ("xcd_span", C.c_int32), ("length_sort", C.c_int32),
                 ("bucket_order", C.c_int32), ("mg_levels", C.c_int32), ("mg_steps", C.c_int32),
-                ("alloc_tile", C.c_int32), ("long_ray_form", C.c_int32), ("alloc_cache", C.c_int32)]
+                ("alloc_tile", C.c_int32), ("long_ray_form", C.c_int32), ("alloc_cache", C.c_int32),
+                ("region_cells", C.c_int32)]
 
 
 class Stats(C.Structure):

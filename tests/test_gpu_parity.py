@@ -180,13 +180,15 @@ def test_rerun_is_bitwise_identical():
 
 def test_launch_order_does_not_change_results():
     """The XCD-aware chunk order (and the plain order it reduces to), the sort of each
-    bucket's rays by expected length and the allocation tile size only reschedule rays: ray
-    values, step counts and cell estimates are bitwise the same."""
+    bucket's rays by expected length, the regions of the work list (one per snapshot, one per
+    brick row, the default) and the allocation tile size only reschedule rays: ray values, step
+    counts and cell estimates are bitwise the same."""
     w = _small_channel(march="f32", nx=24, ny=16, nz=20, R=16)
     say(f"xcd spans {w.name}")
     out = []
-    for span, lsort, border, tile in ((4, 0, 0, 0), (4, 1, 0, 512), (16, 1, 1, 320), (1024, 0, 1, 65536)):
-        s = _solver(w, xcd_span=span, length_sort=lsort, bucket_order=border, alloc_tile=tile)
+    for span, lsort, border, tile, region in ((4, 0, 0, 0, -1), (4, 1, 0, 512, 0), (16, 1, 1, 320, 64),
+                                              (1024, 0, 1, 65536, 64), (256, 0, 0, 256, 640), (64, 0, 0, 0, 0)):
+        s = _solver(w, xcd_span=span, length_sort=lsort, bucket_order=border, alloc_tile=tile, region_cells=region)
         dq, se = s.compute()
         Y, S = s.ray_values(np.arange(w.ncells))
         out.append((dq, se, Y, S))
@@ -318,7 +320,7 @@ def test_errors_are_reported_not_fatal():
         s.set_species(X)
     assert e.value.status == rmc.RMC_OUT_OF_RANGE
     for bad in (dict(rays_per_cell=0), dict(xcd_span=2), dict(xcd_span=48), dict(long_ray_steps=-1),
-                dict(length_sort=2), dict(mg_levels=-2), dict(mg_levels=9), dict(mg_steps=-1),
+                dict(length_sort=2), dict(region_cells=-2), dict(region_cells=32), dict(mg_levels=-2), dict(mg_levels=9), dict(mg_steps=-1),
                 dict(alloc_tile=192), dict(alloc_tile=300), dict(alloc_tile=65600), dict(long_ray_form=3)):
         with pytest.raises(rmc.RmcError) as e:
             s.set_options(rmc.default_options(**bad))
@@ -353,14 +355,18 @@ def test_cell_pdf_mode_matches_oracle():
 
 
 # ------------------------------------------------------------------------------ batch
-def test_batch_equals_single_snapshots():
+@pytest.mark.parametrize("region", [0, 64])
+def test_batch_equals_single_snapshots(region):
+    """A batch of three snapshots of different grids equals the single-snapshot computes
+    bitwise, with the default regions and with one region per brick row (regions numbered over
+    the whole batch)."""
     ws = [_small_channel(march="f32", nx=8 + 4 * q, ny=6 + q, nz=5, R=8, field_seed=q)
           .replace(snap=q) for q in range(3)]
     kd = ws[0].kd
     ws = [x.replace(kd=kd) for x in ws]
-    say("batch of 3")
+    say(f"batch of 3, region_cells {region}")
     singles = [_solver(x).compute()[0] for x in ws]
-    solvers = [_solver(x) for x in ws]
+    solvers = [_solver(x, region_cells=region) for x in ws]
     outs = [np.zeros(x.ncells) for x in ws]
     rmc.compute_batch(solvers, outs)
     for a, b in zip(singles, outs):
