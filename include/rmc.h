@@ -87,9 +87,12 @@ typedef struct {
                                 one (n, g) pair and nearby cells (power of two in [4, 2^20];
                                 0 = default 256; 4 = plain workgroup order) */
     int32_t length_sort;     /* 1: each march workgroup reorders the rays of its four chunks by a
-                                class of their expected length first, so that a wavefront's rays
-                                end at similar times (fewer idle lanes, less gather coherence);
-                                0 (default): cell order.  Results are the same either way */
+                                class of their expected length first (a counting sort in LDS), so
+                                that a wavefront's rays end at similar times.  The estimate counts
+                                the face crossings of the straight path up to the wall the ray
+                                heads for or to the optical depth ln(1/tol) at a reference kappa
+                                of its (n, g) pair.  0 (default): cell order.  Results are the same
+                                either way */
     int32_t bucket_order;    /* march order of the (n, g, octant) buckets: 0 (default) pairs by
                                 increasing kappa(T_max), the longest rays first; 1 band-major, the
                                 g-points of a band together (they share its intensity table).

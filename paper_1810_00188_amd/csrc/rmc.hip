@@ -721,6 +721,42 @@ __global__ void __launch_bounds__(kAllocThreads) k_alloc_scatter(AllocArgs A)
     }
 }
 
+// ------------------------------------------------------ rays sorted by expected length
+// Classes of expected ray length (length_sort 1): six per octave of the estimated step
+// count, 0 .. kLenClasses - 1.  The estimate follows the straight path from the cell centre for
+// L = min(distance to the y wall it heads for, ln(1/tol) / kappa_ref) and counts its face
+// crossings: L |d_x| nx / Lx + L |d_z| nz / Lz along the uniform periodic axes, and along y the
+// faces between the centre and the end point (bisection in the face table, exact on a stretched
+// grid).  kappa_ref is the pair's kappa at a mid temperature and mole fraction of the field.  It
+// only orders work; no result depends on it.
+constexpr int kLenClasses = 64;
+
+__device__ __forceinline__ uint32_t bucket_len_class(const SnapDesc &D, const double *yf, float kref,
+                                                     float log_inv_tol, int j, uint32_t o, uint32_t w0, uint32_t w1)
+{
+    const float mu = 1.0f - 2.0f * unif_dir<float>(w0);
+    const float phi = 6.28318530718f * unif_dir<float>(w1);
+    const float s = sqrtf((1.0f - mu) * (1.0f + mu));
+    float sn, cs;
+    __sincosf(phi, &sn, &cs);
+    const float ax = fabsf(s * cs), ay = fmaxf(fabsf(mu), 1e-12f), az = fabsf(s * sn);
+    const double yc = 0.5 * (yf[j] + yf[j + 1]);
+    const bool down = (o & 2u) != 0u;
+    const float lw = (float)(down ? yc - yf[0] : yf[D.ny] - yc) / ay;
+    const float L = kref > 0.0f ? fminf(lw, log_inv_tol / kref) : lw;
+    const double ye = down ? yc - (double)(L * ay) : yc + (double)(L * ay);
+    int lo = 0, hi = D.ny + 1;   // faces at or below ye
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (yf[mid] <= ye) lo = mid + 1;
+        else hi = mid;
+    }
+    const int nyc = abs((lo - 1) - j);
+    const float E = 1.0f + L * (ax * (float)((double)D.nx / D.Lx) + az * (float)((double)D.nz / D.Lz)) + (float)nyc;
+    const int c = (int)floorf(6.0f * __log2f(fminf(E, 1e9f)));
+    return (uint32_t)(c < 0 ? 0 : (c >= kLenClasses ? kLenClasses - 1 : c));
+}
+
 // -------------------------------------------------------------------------- march
 // Ray slot write: one 8-byte store per ray in the FP32 march (a ray's slot is a scattered
 // address, so two 4-byte stores would cost two partial-line writes).
@@ -748,6 +784,7 @@ template <class Real> struct MarchArgs {
     int max_steps;
     int cap;                    // steps a ray takes in the lane kernel before it is handed to k_march_long
     const float *kmin;          // per (n, g): lower bound of kappa over the field (segmenting range)
+    const float *kref;          // per (n, g): reference kappa of the expected-length classes
     struct ContRec *cont;       // continuation records of capped rays
     uint32_t *cont_count;
     uint32_t cont_cap;
@@ -942,29 +979,6 @@ __device__ __forceinline__ bool march_levels(Ray<Real, INC_XZ> &R, const SnapDes
     }
 }
 
-// Expected-length class of a ray (quarter octaves of its estimated step count; larger is
-// longer).  The estimate counts the face crossings of the straight path until it reaches the
-// wall it heads for or the optical depth ln(1/tol) at the source cell's kappa:
-//   E = 1 + min(L_wall, ln(1/tol) / kappa_src) (|d_x| n_x / L_x + |d_y| n_y / L_y + |d_z| n_z / L_z).
-// It only orders work; no result depends on it.
-template <class Real>
-__device__ __forceinline__ uint32_t ray_len_class(const SnapDesc &D, const RayGeo &G, const Props<Real> &P, int i,
-                                                  int j, int k, double dx, double dy, double dz, float log_inv_tol)
-{
-    Real kr;
-    double Ir;
-    prop_load(P, brick_x(i, G.bsx) + brick_y(j, G.bsy) + brick_z(k), kr, Ir);
-    const float kap = (float)kr;
-    const double yc = 0.5 * (G.yf[j] + G.yf[j + 1]);
-    const float lw = (float)(((dy > 0.0) ? G.yf[G.ny] - yc : yc - G.yf[0]) / fabs(dy));
-    const float L = kap > 0.0f ? fminf(lw, log_inv_tol / kap) : lw;
-    const float dens = (float)(fabs(dx) * (double)G.nx / D.Lx + fabs(dy) * (double)G.ny / (G.yf[G.ny] - G.yf[0]) +
-                               fabs(dz) * (double)G.nz / D.Lz);
-    const float E = fminf(1.0f + L * dens, 1e9f);
-    const int c = (int)floorf(4.0f * __log2f(E));
-    return (uint32_t)(c < 0 ? 0 : (c > 63 ? 63 : c));
-}
-
 // Wall flux (black walls, one grid): a ray that ended on a black wall adds its wall term
 // w kappa_src tau_w (I_src - I_w), times its source cell's volume over R and over the area of
 // the wall face element it reached, to that element: the net radiative flux the wall receives
@@ -995,7 +1009,7 @@ __device__ __forceinline__ void tally_wall(const SnapDesc &D, const RayGeo &G, c
 // One ray per lane, no refill: every wavefront marches 64 work items of one bucket and
 // retires when its longest ray ends; the hardware scheduler balances the many short-lived
 // wavefronts.  With SORT, the workgroup first reorders the 256 items of its four chunks by
-// expected length (bitonic sort in LDS on (bucket segment, class, index) keys), so that a
+// expected-length class (counting sort in LDS on (bucket segment, class)), so that a
 // wavefront's rays end at similar times while its sources stay within four neighbouring
 // chunks; items never leave the chunks of their bucket.
 // PDF: the ray's probability is per ray (dprob), not per bucket (W).
@@ -1025,51 +1039,52 @@ __global__ void __launch_bounds__(256) k_march_lane(MarchArgs<Real> A)
         if (it.y == kInvalidItem) return;
         octant_direction(it.z, it.w, o, dx, dy, dz);
     } else {
-        __shared__ uint32_t s_key[256];
-        __shared__ uint32_t s_bk[4];
+        // the workgroup's 256 items by (segment, length class): a counting sort in LDS; a
+        // segment is a run of its wavefronts with one bucket, so items never leave their bucket
         __shared__ uint4 s_it[256];
-        __shared__ double s_d[3][256];
+        __shared__ uint32_t s_cnt[4 * kLenClasses];
+        __shared__ uint32_t s_src[256];
+        __shared__ uint32_t s_bk[4];
+        for (int q2 = threadIdx.x; q2 < 4 * kLenClasses; q2 += blockDim.x) s_cnt[q2] = 0u;
         const uint4 it0 = wvalid ? gld(A.items + wave * 64u + (uint32_t)lane) : make_uint4(0u, kInvalidItem, 0u, 0u);
+        s_it[threadIdx.x] = it0;
         if (lane == 0) s_bk[wib] = b;
         __syncthreads();
-        uint32_t seg = 0;           // buckets are contiguous in chunk order
+        uint32_t seg = 0;
         for (int w = 1; w <= wib; ++w) seg += s_bk[w] != s_bk[w - 1] ? 1u : 0u;
-        if (!wvalid) seg = 7;
-        uint32_t ckey = 127;        // padding items last within their segment
-        if (wvalid && it0.y != kInvalidItem) {
+        uint32_t cls = kLenClasses - 1;   // padding last in its segment
+        if (it0.y != kInvalidItem) {
             const SnapDesc &D0 = A.snaps[MULTI ? (int)((it0.y >> 16) & 0x7FFF) : 0];
-            const RayGeo G0 = ray_geo(D0, sf);
-            double ex, ey, ez;
-            octant_direction(it0.z, it0.w, o, ex, ey, ez);
-            const int i0 = (int)(it0.x & 1023), j0 = (int)((it0.x >> 10) & 1023), k0 = (int)((it0.x >> 20) & 1023);
-            ckey = 63u - ray_len_class<Real>(D0, G0, slot_props(tab, A, D0.rec, D0.rw_log2), i0, j0, k0, ex, ey, ez,
-                                             A.log_inv_tol);
-            s_d[0][threadIdx.x] = ex;
-            s_d[1][threadIdx.x] = ey;
-            s_d[2][threadIdx.x] = ez;
+            const uint32_t c = bucket_len_class(D0, sf + D0.face_off + D0.nx + 1, gld(A.kref + pair), A.log_inv_tol,
+                                                (int)((it0.x >> 10) & 1023), (uint32_t)o, it0.z, it0.w);
+            cls = min(c, (uint32_t)kLenClasses - 2);
         }
-        s_it[threadIdx.x] = it0;
-        s_key[threadIdx.x] = (seg << 16) | (ckey << 8) | threadIdx.x;
-        for (uint32_t kk = 2; kk <= 256; kk <<= 1)
-            for (uint32_t jj = kk >> 1; jj > 0; jj >>= 1) {
-                __syncthreads();
-                const uint32_t t = threadIdx.x, pt = t ^ jj;
-                if (pt > t) {
-                    const uint32_t ka = s_key[t], kb = s_key[pt];
-                    if ((ka > kb) == ((t & kk) == 0)) {
-                        s_key[t] = kb;
-                        s_key[pt] = ka;
-                    }
-                }
-            }
+        const uint32_t bin = seg * kLenClasses + cls;
+        const uint32_t rank = atomicAdd(&s_cnt[bin], 1u);
         __syncthreads();
-        const uint32_t src = s_key[threadIdx.x] & 255u;
+        if (threadIdx.x < 64) {   // exclusive scan of the 256 bins, four per lane
+            const uint32_t c0 = s_cnt[4 * threadIdx.x], c1 = s_cnt[4 * threadIdx.x + 1],
+                           c2 = s_cnt[4 * threadIdx.x + 2], c3 = s_cnt[4 * threadIdx.x + 3];
+            const uint32_t sum = c0 + c1 + c2 + c3;
+            uint32_t x = sum;
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t y = __shfl_up(x, off);
+                if ((int)threadIdx.x >= off) x += y;
+            }
+            const uint32_t base = x - sum;
+            s_cnt[4 * threadIdx.x] = base;
+            s_cnt[4 * threadIdx.x + 1] = base + c0;
+            s_cnt[4 * threadIdx.x + 2] = base + c0 + c1;
+            s_cnt[4 * threadIdx.x + 3] = base + c0 + c1 + c2;
+        }
+        __syncthreads();
+        s_src[s_cnt[bin] + rank] = threadIdx.x;
+        __syncthreads();
+        const uint32_t src = s_src[threadIdx.x];
         if (!wvalid) return;
         it = s_it[src];
         if (it.y == kInvalidItem) return;
-        dx = s_d[0][src];
-        dy = s_d[1][src];
-        dz = s_d[2][src];
+        octant_direction(it.z, it.w, o, dx, dy, dz);
         q = xcd_chunk(blockIdx.x, src >> 6, A.span_log2) * 64u + (src & 63u);
     }
     const int s = MULTI ? (int)((it.y >> 16) & 0x7FFF) : 0;
@@ -1999,7 +2014,7 @@ struct rmc_ctx {
     DBuf hist, bucket_total, rstart, run_len, rtile0, nchunks, chunk_bucket, items, faces, snaps, tile_info, counters, red_part,
         outbuf, tune_out;
     DBuf trace_rec, trace_cells, border, kmin, cont, cont_count, probe;
-    std::vector<float> h_kmin;
+    std::vector<float> h_kmin;         // per (n, g) pair: kappa lower bound, then reference kappa
     double Tmin_cells = 0;
     double xmin[8] = {0};
     // host staging of the per-compute descriptors (kept alive until the next compute)
@@ -2282,6 +2297,26 @@ void kappa_lower_bounds(const rmc_ctx *c, std::vector<float> &out)
             kap += c->xmin[sp] * m;
         }
         out[pr] = (float)(kap * (1.0 - 1e-6));
+    }
+}
+
+// Reference kappa per (n, g) pair for the expected-length classes: the mixture at the middle of
+// the field's temperature range and of each species' mole-fraction range.
+void kappa_reference(const rmc_ctx *c, std::vector<float> &out)
+{
+    const int nb = c->nb, ng = c->ng;
+    const double Tm = 0.5 * (c->Tmin_cells + std::max(c->Tmax_cells, c->Tmin_cells));
+    const double u = std::min(std::max((Tm - c->T0) / c->dT, 0.0), (double)(c->nT - 1));
+    const int t = std::min((int)u, c->nT - 2);
+    const double f = u - t;
+    out.assign((size_t)nb * ng, 0.0f);
+    for (int pr = 0; pr < nb * ng; ++pr) {
+        double kap = 0.0;
+        for (int sp = 0; sp < c->ns; ++sp) {
+            const double *tab = c->k64_host.data() + ((size_t)sp * nb * ng + pr) * c->nT;
+            kap += 0.5 * (c->xmin[sp] + c->xhat[sp]) * (tab[t] + f * (tab[t + 1] - tab[t]));
+        }
+        out[pr] = (float)kap;
     }
 }
 
@@ -2675,19 +2710,24 @@ template <class Real> rmc_status plan_pipeline(rmc_ctx *const *ctxs, int nsnap, 
         (st = L->border.ensure(sizeof(uint32_t) * nbucket)) ||
         (st = L->counters.ensure(sizeof(unsigned long long) * 4)) ||
         (st = L->red_part.ensure(sizeof(unsigned long long) * 2 * 2048)) ||
-        (st = L->kmin.ensure(sizeof(float) * nb * ng)) || (st = L->cont_count.ensure(sizeof(uint32_t))))
+        (st = L->kmin.ensure(sizeof(float) * 2 * nb * ng)) || (st = L->cont_count.ensure(sizeof(uint32_t))))
         return st;
     // continuation records of long rays (rays beyond them are finished by the lane kernel);
     // fewer in the allocation-free compute, whose scratch is small
     P.cont_cap = (uint32_t)std::min<uint64_t>(P.total_cells * R, t_arena ? (1u << 16) : (1u << 20));
     if ((st = L->cont.ensure(sizeof(ContRec) * P.cont_cap))) return st;
-    {   // kappa lower bound over all snapshots of the batch
-        std::vector<float> tmp;
+    {   // kappa lower bound over all snapshots of the batch, then the mean reference kappa
+        std::vector<float> tmp, ref, acc((size_t)nb * ng, 0.0f);
         kappa_lower_bounds(ctxs[0], L->h_kmin);
-        for (int q = 1; q < nsnap; ++q) {
-            kappa_lower_bounds(ctxs[q], tmp);
-            for (size_t u = 0; u < tmp.size(); ++u) L->h_kmin[u] = std::min(L->h_kmin[u], tmp[u]);
+        for (int q = 0; q < nsnap; ++q) {
+            if (q > 0) {
+                kappa_lower_bounds(ctxs[q], tmp);
+                for (size_t u = 0; u < tmp.size(); ++u) L->h_kmin[u] = std::min(L->h_kmin[u], tmp[u]);
+            }
+            kappa_reference(ctxs[q], ref);
+            for (size_t u = 0; u < ref.size(); ++u) acc[u] += ref[u] / (float)nsnap;
         }
+        L->h_kmin.insert(L->h_kmin.end(), acc.begin(), acc.end());
     }
     if (t_arena) {   // scratch counters: cleared by a fill kernel at every allocation-free compute
         hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, L->counters.as<unsigned long long>(), 4);
@@ -2702,7 +2742,7 @@ template <class Real> rmc_status plan_pipeline(rmc_ctx *const *ctxs, int nsnap, 
     // descriptor uploads from one pinned staging buffer (reused once the last upload is done)
     constexpr int kUp = 6;
     const size_t sz[kUp] = {sizeof(double) * P.nfaces, sizeof(SnapDesc) * nsnap, sizeof(TileInfo) * P.ntiles,
-                            sizeof(uint32_t) * nbucket, sizeof(float) * nb * ng, sizeof(uint32_t) * rtile0.size()};
+                            sizeof(uint32_t) * nbucket, sizeof(float) * 2 * nb * ng, sizeof(uint32_t) * rtile0.size()};
     const void *src[kUp] = {faces.data(), L->h_snaps.data(), tiles.data(), L->h_order.data(), L->h_kmin.data(),
                             rtile0.data()};
     P.d_faces = L->faces.as<double>();
@@ -2821,6 +2861,7 @@ rmc_status enqueue_pipeline(const Plan &P, double *const *divq, double *const *s
     const int lrs = O.long_ray_steps > 0 ? O.long_ray_steps : 512;
     MA.cap = segment ? std::min(lrs, O.max_steps) : O.max_steps;
     MA.kmin = P.d_kmin;
+    MA.kref = P.d_kmin + (size_t)nb * ng;
     MA.cont = L->cont.as<ContRec>();
     MA.cont_count = L->cont_count.as<uint32_t>();
     MA.cont_cap = P.cont_cap;
@@ -2847,7 +2888,7 @@ rmc_status enqueue_pipeline(const Plan &P, double *const *divq, double *const *s
     const unsigned mblocks = (unsigned)xcd_blocks(P.max_chunks, MA.span_log2);
     const size_t lds_faces = march_lds_bytes(P.nfaces, L->nT, L->ns);   // faces and four table slots
     const bool multi = nsnap > 1;
-    const bool lsort = O.length_sort != 0;
+    const bool lsort = O.length_sort == 1;
 #define RMC_MARCH(PDF_, INC_, MULTI_)                                                                             \
     do {                                                                                                        \
         if (lsort) hipLaunchKernelGGL((k_march_lane<Real, PDF_, INC_, MULTI_, true>), dim3(mblocks), dim3(256), \
@@ -3686,7 +3727,7 @@ rmc_status rmc_graph_capture(rmc_ctx *const *ctxs, int nsnap, double *const *div
     {   // the graph reads its own copies of the planned tables
         const size_t nb_ = (size_t)L->nb * L->ng;
         const size_t sz[6] = {sizeof(double) * P.nfaces, sizeof(SnapDesc) * nsnap, sizeof(TileInfo) * P.ntiles,
-                              sizeof(uint32_t) * nb_ * 8, sizeof(float) * nb_, sizeof(uint32_t) * (P.nregion + 1)};
+                              sizeof(uint32_t) * nb_ * 8, sizeof(float) * 2 * nb_, sizeof(uint32_t) * (P.nregion + 1)};
         DBuf *dst[6] = {&G->faces, &G->snaps, &G->tile_info, &G->border, &G->kmin, &G->rtile0};
         const void *src[6] = {P.d_faces, P.d_snaps, P.d_tiles, P.d_border, P.d_kmin, P.d_rtile0};
         for (int u = 0; u < 6; ++u) {

@@ -217,6 +217,24 @@ def test_allocation_cache_gives_the_same_draws():
     assert e.value.status == rmc.RMC_UNSUPPORTED
 
 
+def test_learned_compute_with_length_sorted_workgroups_keeps_results():
+    """Learned sampling (per-ray probabilities) with each march workgroup's rays sorted by
+    expected length (length_sort 1) and one-brick-row regions: cell estimates bitwise those of
+    cell order."""
+    eps = 0.15
+    w = _workload(R=24, nb=20, ng=7, march="f32")
+    say(f"learned length-sorted runs {w.name}")
+    feat, _ = _solver(w).features()
+    params, mu, sd, nu_c, gx = _network(w, feat)
+    out = []
+    for ls in (0, 1):
+        s = _solver(w, sampling=rmc.SAMPLING_LEARNED, mix_eps=eps, length_sort=ls, region_cells=64 if ls else -1)
+        s.set_allocator(params, mu, sd, nu_c, gx)
+        out.append(s.compute())
+    for dq, se in out[1:]:
+        assert np.array_equal(out[0][0], dq) and np.array_equal(out[0][1], se)
+
+
 def _training_batch(w, s, ncell, seed=4):
     """Plain-run rays of ncell sampled cells (oracle trace): device tensors of a TrainBatch and
     the host arrays the FP64 reference needs."""

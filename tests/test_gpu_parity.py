@@ -187,7 +187,8 @@ def test_launch_order_does_not_change_results():
     say(f"xcd spans {w.name}")
     out = []
     for span, lsort, border, tile, region in ((4, 0, 0, 0, -1), (4, 1, 0, 512, 0), (16, 1, 1, 320, 64),
-                                              (1024, 0, 1, 65536, 64), (256, 0, 0, 256, 640), (64, 0, 0, 0, 0)):
+                                              (1024, 0, 1, 65536, 64), (256, 0, 0, 256, 640), (64, 0, 0, 0, 0),
+                                              (256, 1, 0, 0, 64)):
         s = _solver(w, xcd_span=span, length_sort=lsort, bucket_order=border, alloc_tile=tile, region_cells=region)
         dq, se = s.compute()
         Y, S = s.ray_values(np.arange(w.ncells))
@@ -195,6 +196,52 @@ def test_launch_order_does_not_change_results():
     for dq, se, Y, S in out[1:]:
         assert np.array_equal(dq, out[0][0]) and np.array_equal(se, out[0][1])
         assert np.array_equal(Y, out[0][2]) and np.array_equal(S, out[0][3])
+
+
+@pytest.mark.parametrize("case", ["sparse_runs", "channel64", "channel64_multigrid", "walls", "batch"])
+def test_length_sorted_workgroups_keep_results(case):
+    """length_sort 1 (each march workgroup sorts the rays of its four chunks by a class of their
+    expected length) with regions of the work list only reorders work: cell estimates, ray
+    values and step counts are bitwise those of cell order.  sparse_runs: 2 rays per cell in
+    one-brick-row regions, so most (region, bucket) runs hold a ray or two and runs of one
+    bucket in neighbouring regions meet inside a workgroup's four chunks."""
+    say(f"length-sorted runs {case}")
+    if case == "batch":
+        ws = [_small_channel(march="f32", nx=24 + 8 * q, ny=16 + q, nz=20, R=16, field_seed=q).replace(snap=q)
+              for q in range(3)]
+        ws = [x.replace(kd=ws[0].kd) for x in ws]
+        res = []
+        for ls, reg in ((0, -1), (1, 64), (1, 0)):
+            solvers = [_solver(x, length_sort=ls, region_cells=reg, long_ray_form=2) for x in ws]
+            outs = [np.zeros(x.ncells) for x in ws]
+            rmc.compute_batch(solvers, outs)
+            res.append(outs)
+        for other in res[1:]:
+            for a, b in zip(res[0], other):
+                assert np.array_equal(a, b)
+        return
+    kw = {}
+    if case == "sparse_runs":
+        w = _small_channel(march="f32", nx=20, ny=12, nz=16, R=2)
+        variants = ((0, -1), (1, 64), (1, 0))
+    elif case == "walls":
+        w = _small_channel(march="f32", nx=32, ny=24, nz=28, R=16).replace(eps_walls=(0.5, 0.7))
+        variants = ((0, -1), (1, 0), (1, 4096))
+    else:
+        w = inputs.channel64()
+        kw = dict(mg_levels=3) if case == "channel64_multigrid" else {}
+        variants = ((0, -1), (1, 0), (1, 65536))
+    out = []
+    for ls, reg in variants:
+        s = _solver(w, length_sort=ls, region_cells=reg, long_ray_form=2, **kw)
+        dq, se = s.compute()
+        cells = np.arange(0, w.ncells, 7)
+        Y, S = s.ray_values(cells)
+        out.append((dq, se, Y, S, s.stats()))
+    for dq, se, Y, S, st in out[1:]:
+        assert np.array_equal(dq, out[0][0]) and np.array_equal(se, out[0][1])
+        assert np.array_equal(Y, out[0][2]) and np.array_equal(S, out[0][3])
+        assert st["steps"] == out[0][4]["steps"] and st["rays"] == out[0][4]["rays"]
 
 
 def test_set_fields_equals_separate_ingest():
