@@ -2712,9 +2712,12 @@ template <class Real> rmc_status plan_pipeline(rmc_ctx *const *ctxs, int nsnap, 
         (st = L->red_part.ensure(sizeof(unsigned long long) * 2 * 2048)) ||
         (st = L->kmin.ensure(sizeof(float) * 2 * nb * ng)) || (st = L->cont_count.ensure(sizeof(uint32_t))))
         return st;
-    // continuation records of long rays (rays beyond them are finished by the lane kernel);
-    // fewer in the allocation-free compute, whose scratch is small
-    P.cont_cap = (uint32_t)std::min<uint64_t>(P.total_cells * R, t_arena ? (1u << 16) : (1u << 20));
+    // continuation records of long rays: one per 32 rays of the pass, at least 2^20 (a ray that
+    // finds the list full is finished by its lane in the lane kernel, while the wavefront's other
+    // lanes wait: learned sampling at R = 128 on the DNS-size grid has more than 2^20 long rays);
+    // 2^16 in the allocation-free compute, whose scratch is small
+    const uint64_t nrays = P.total_cells * R;
+    P.cont_cap = (uint32_t)std::min<uint64_t>(nrays, t_arena ? (1u << 16) : std::max<uint64_t>(1u << 20, nrays / 32));
     if ((st = L->cont.ensure(sizeof(ContRec) * P.cont_cap))) return st;
     {   // kappa lower bound over all snapshots of the batch, then the mean reference kappa
         std::vector<float> tmp, ref, acc((size_t)nb * ng, 0.0f);
