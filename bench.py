@@ -662,7 +662,7 @@ def main():
 WORKLOADS = {
     "dns256": ("DNS-size snapshot 256x128x128, tanh-stretched y, 64 modes at 10 %, H2O + CO2 +-20 %, "
                "100 bands x 16 g (BF16-rounded tables), 64 rays/cell, FP32 march, FP64 sums",
-               dict(cpu_stride=4, cpu_stride_1core=256)),
+               dict(cpu_stride=1, cpu_stride_1core=256)),
     "channel64": ("non-grey channel 64x64x64, 20 bands x 7 g, 32 rays/cell, FP32 march, FP64 sums",
                   dict(cpu_stride=1, cpu_stride_1core=16)),
 }
