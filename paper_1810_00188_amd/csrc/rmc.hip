@@ -4,8 +4,9 @@
 // Pipeline of one compute (all kernels on the caller's stream, no host round trip):
 //   1. k_plain_pdf     T_max spectral pdf and its cumulative sums (Eqs. 13, 16-17), ray
 //                      weights per (band, g, octant) bucket (Eq. 14), wall intensities.
-//   2. k_fields        band-major property fields {kappa_{n,g}, I_n} per cell in a bricked
-//                      layout (table interpolation of Sec. 2.2 done once per cell, not per step).
+//   2. k_records       one 16-byte record per cell (table coordinate of T, mole fractions) in a
+//                      bricked layout, read by every (band, g) pair; the march interpolates
+//                      kappa and I_n from its pair's tables in LDS at every step (Sec. 2.2).
 //   3. k_alloc_count   per tile of cells: histogram of the rays' (n, g, octant) buckets.
 //      k_bucket_scan   per bucket: exclusive scan over tiles (no global atomics).
 //      k_run_len / k_run_layout: the work list runs region by region (compact groups of tiles),
@@ -13,7 +14,8 @@
 //                      wavefronts.  k_chunk_map: chunk -> bucket map.
 //      k_alloc_scatter per tile: ray work items into their bucket (narrow-band sorting of
 //                      Sec. 4.2: a wavefront marches rays of one (n, g, octant)).
-//   4. k_march         one lane per ray, Algorithm 1 march, ray value into its slot.
+//   4. k_march_lane    one lane per ray, Algorithm 1 march, ray value into its slot; rays still
+//      k_march_long    marching after long_ray_steps continue in parallel segments.
 //   5. k_reduce        per cell: mean and standard error of the R ray values (FP64, or
 //                      compensated / plain FP32), natural order.
 #include <hip/hip_runtime.h>
@@ -63,7 +65,7 @@ struct SnapDesc {
     double *dprob;              // per-cell pdf or learned sampling: [ncells * R] probability of each ray
     uint32_t *rbkt;             // [ncells * R] bucket (n*ng + g)*8 + o of each ray: written by the
                                 // counting pass (learned sampling: the drawn strata themselves)
-    uint64_t ncpad;             // cells per bricked field plane
+    uint64_t ncpad;             // cells of the padded, bricked record field
     int nx, ny, nz;
     int nbx, nby, nbz;
     int face_off;               // x faces at face_off, y at +nx+1, z at +nx+ny+2
@@ -861,8 +863,8 @@ __device__ __forceinline__ int stage_wave_tables(double *tabs, const MarchArgs<R
 // each XCD starts its workgroups in order.  Wavefront `wib` of workgroup b = 8 k + x takes
 // position p = 4 k + wib in XCD x's sequence, which walks the runs x, x + 8, x + 16, ... of
 // 2^span_log2 consecutive chunks: the waves in flight on one XCD then work on neighbouring
-// chunks (one (n, g) pair, nearby cells), whose property planes its L2 keeps.  A run of 4
-// chunks gives the plain order chunk = 4 b + wib.
+// chunks (one (n, g) pair, nearby cells of one region), whose cell records its L2 keeps.  A run
+// of 4 chunks gives the plain order chunk = 4 b + wib.
 constexpr int kXcds = 8;
 
 __device__ __forceinline__ uint32_t xcd_chunk(uint32_t block, uint32_t wib, int span_log2)
@@ -2254,7 +2256,7 @@ void march_order(const rmc_ctx *c, std::vector<uint32_t> &order)
     });
     if (c->opt.bucket_order == 1) {
         // band-major: the g-points of a band next to each other (they share the band's
-        // intensity plane), bands ordered by their smallest kappa
+        // intensity table), bands ordered by their smallest kappa
         std::vector<int> rank(nb, nb * ng);
         for (int q = 0; q < nb * ng; ++q) rank[key[q].second / ng] = std::min(rank[key[q].second / ng], q);
         std::stable_sort(key.begin(), key.end(), [&](const std::pair<double, int> &a, const std::pair<double, int> &b) {
