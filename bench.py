@@ -779,6 +779,11 @@ def throughput(a):
                      "achievable_probe": f"rmc_gather_probe: {rays} lanes x {probe_steps} steps of the "
                                          f"march's access pattern without the physics, {pms:.3f} ms"},
     }
+    if rec and "valu_issue" in rec:
+        # what the rocprofv3 counters of this kernel (same sources) say binds it
+        out["roofline"]["measured_limiter"] = {"valu_issue": rec["valu_issue"], "l2_hit_rate": rec["l2_hit_rate"],
+                                               "mall_bytes_per_step": rec["bytes_per_launch"] / lane_steps,
+                                               "source": "profiles/march_dns256_traffic.md"}
     s.close()
     del T, X, dq, se
     torch.cuda.empty_cache()
