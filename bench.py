@@ -39,10 +39,10 @@ HBM_PEAK_GBS = 8000.0
 # value of the cell; per ray an 8-byte work item and a 4-byte ray value
 BYTES_PER_STEP = 4 + 4
 BYTES_PER_RAY = 8 + 4
-# what the kernel moves: a 16-byte cell record per step, a 16-byte work item and an 8-byte
+# what the kernel moves: a 16-byte cell record per step, an 8-byte work item and an 8-byte
 # slot record {value, steps | end} per ray
 KERNEL_BYTES_PER_STEP = 16
-KERNEL_BYTES_PER_RAY = 16 + 8
+KERNEL_BYTES_PER_RAY = 8 + 8
 L2_PER_XCD_MB = 4.0
 MALL_MB = 256.0
 ALLOCATOR_DIR = os.path.join(ROOT, "paper_1810_00188_amd", "allocators")

@@ -107,7 +107,7 @@ struct AllocArgs {
     const uint32_t *btotal;     // [nbucket] rays per bucket
     const uint32_t *rtile0;     // [nregion + 1] first tile of each region
     const uint32_t *rstart;     // [nregion][nbucket] start of each (region, bucket) run of the work list
-    uint4 *items;               // (i | j<<10 | k<<20, r | k_ord<<8 | snapshot<<16, dir word 0, dir word 1)
+    uint2 *items;               // (i | j<<10 | k<<20, r | k_ord<<8 | snapshot<<16)
     int lds_bricks;             // the tile's bricks are decoded into LDS (else per cell from the index)
     int lds_cdf;                // plain sampling: the cdfs are staged in LDS by the counting pass
 };
@@ -643,7 +643,7 @@ __global__ void __launch_bounds__(1024) k_run_layout(const uint32_t *run_len, co
 
 // chunk -> bucket map and invalid markers on the padding of each run
 __global__ void k_chunk_map(const uint32_t *hist, const uint32_t *total, int ntiles, const uint32_t *rtile0,
-                            const uint32_t *rstart, int nbucket, uint64_t nrun, uint32_t *chunk_bucket, uint4 *items)
+                            const uint32_t *rstart, int nbucket, uint64_t nrun, uint32_t *chunk_bucket, uint2 *items)
 {
     const uint64_t r = blockIdx.x * (uint64_t)blockDim.y + threadIdx.y;
     if (r >= nrun) return;
@@ -651,7 +651,7 @@ __global__ void k_chunk_map(const uint32_t *hist, const uint32_t *total, int nti
     const uint32_t n = hist_before(hist, total, ntiles, b, rtile0[g + 1]) - hist_before(hist, total, ntiles, b, rtile0[g]);
     const uint32_t s = rstart[r], e = s + ((n + 63u) & ~63u), used = s + n;
     for (uint32_t q = s / 64 + threadIdx.x; q < e / 64; q += blockDim.x) chunk_bucket[q] = (uint32_t)b;
-    for (uint32_t q = used + threadIdx.x; q < e; q += blockDim.x) items[q] = make_uint4(0u, kInvalidItem, 0u, 0u);
+    for (uint32_t q = used + threadIdx.x; q < e; q += blockDim.x) items[q] = make_uint2(0u, kInvalidItem);
 }
 
 // LDS of k_alloc_scatter: nbucket positions, the bucket of each thread, the tile's bricks (if
@@ -710,14 +710,12 @@ __global__ void __launch_bounds__(kAllocThreads) k_alloc_scatter(AllocArgs A)
         sb[threadIdx.x] = bucket;
         __syncthreads();
         if (live) {
+            // the ray's ordinal among its cell's rays in the same bucket: with the cell and the
+            // bucket it keys the ray's direction stream, which the march draws (item_direction)
             const uint32_t kord = same_bucket_before(sb, threadIdx.x - r, r, bucket, by4);
-            // direction stream of the ray, keyed by (cell, band, g, octant, ordinal)
-            const uint32_t n = (bucket >> 3) / (uint32_t)A.ng, g = (bucket >> 3) - n * (uint32_t)A.ng;
-            uint32_t v[4];
-            philox4x32_10(c, (n << 16) | (g << 8) | (bucket & 7u), kord, (D.snap_id << 4) | kTagDir, A.k0, A.k1, v);
             const uint32_t pos = atomicAdd(&lb[bucket], 1u);
-            A.items[pos] = make_uint4((uint32_t)i | ((uint32_t)j << 10) | ((uint32_t)k << 20),
-                                      (uint32_t)r | (kord << 8) | ((uint32_t)s << 16), v[0], v[1]);
+            A.items[pos] = make_uint2((uint32_t)i | ((uint32_t)j << 10) | ((uint32_t)k << 20),
+                                      (uint32_t)r | (kord << 8) | ((uint32_t)s << 16));
         }
         __syncthreads();
     }
@@ -776,7 +774,7 @@ template <class Real> struct MarchArgs {
     const SnapDesc *snaps;
     const double *faces;        // all snapshots' face tables, staged into LDS
     int nfaces;
-    const uint4 *items;
+    const uint2 *items;
     const uint32_t *chunk_bucket;
     const uint32_t *nchunks;
     const double *dnu, *wg;     // per-ray weights in per-cell pdf mode
@@ -1008,6 +1006,29 @@ __device__ __forceinline__ void tally_wall(const SnapDesc &D, const RayGeo &G, c
     atomicAdd(D.wallq + off, vc * yw / ((double)nrays * area));
 }
 
+// Direction of the ray of work item it (cell (i, j, k) of snapshot D, ordinal k_ord) in bucket
+// (pair, octant o): its Philox stream, keyed by (cell, band, g, octant, ordinal), inverted as in
+// Eq. 9 inside the octant.
+__device__ __forceinline__ void item_dir_words(uint2 it, const SnapDesc &D, int pair, int ng, int o, uint32_t k0,
+                                               uint32_t k1, uint32_t &w0, uint32_t &w1)
+{
+    const uint32_t i = it.x & 1023u, j = (it.x >> 10) & 1023u, k = (it.x >> 20) & 1023u;
+    const uint32_t c = (uint32_t)(((uint64_t)i * D.ny + j) * D.nz + k);
+    const uint32_t n = (uint32_t)(pair / ng), g = (uint32_t)pair - n * (uint32_t)ng;
+    uint32_t v[4];
+    philox4x32_10(c, (n << 16) | (g << 8) | (uint32_t)o, (it.y >> 8) & 255u, (D.snap_id << 4) | kTagDir, k0, k1, v);
+    w0 = v[0];
+    w1 = v[1];
+}
+
+__device__ __forceinline__ void item_direction(uint2 it, const SnapDesc &D, int pair, int ng, int o, uint32_t k0,
+                                               uint32_t k1, double &dx, double &dy, double &dz)
+{
+    uint32_t w0, w1;
+    item_dir_words(it, D, pair, ng, o, k0, k1, w0, w1);
+    octant_direction(w0, w1, o, dx, dy, dz);
+}
+
 // One ray per lane, no refill: every wavefront marches 64 work items of one bucket and
 // retires when its longest ray ends; the hardware scheduler balances the many short-lived
 // wavefronts.  With SORT, the workgroup first reorders the 256 items of its four chunks by
@@ -1031,24 +1052,22 @@ __global__ void __launch_bounds__(256) k_march_lane(MarchArgs<Real> A)
     __syncthreads();
     const double *tab = sf + A.tab_off + stage_wave_tables(sf + A.tab_off, A, s_pair, wib) * A.slot_dbl;
     __syncthreads();
-    uint4 it;
+    uint2 it;
     uint32_t q;                 // position of the item in the work list
-    double dx, dy, dz;
     if constexpr (!SORT) {
         if (!wvalid) return;
         q = wave * 64u + (uint32_t)lane;
         it = gld(A.items + q);
         if (it.y == kInvalidItem) return;
-        octant_direction(it.z, it.w, o, dx, dy, dz);
     } else {
         // the workgroup's 256 items by (segment, length class): a counting sort in LDS; a
         // segment is a run of its wavefronts with one bucket, so items never leave their bucket
-        __shared__ uint4 s_it[256];
+        __shared__ uint2 s_it[256];
         __shared__ uint32_t s_cnt[4 * kLenClasses];
         __shared__ uint32_t s_src[256];
         __shared__ uint32_t s_bk[4];
         for (int q2 = threadIdx.x; q2 < 4 * kLenClasses; q2 += blockDim.x) s_cnt[q2] = 0u;
-        const uint4 it0 = wvalid ? gld(A.items + wave * 64u + (uint32_t)lane) : make_uint4(0u, kInvalidItem, 0u, 0u);
+        const uint2 it0 = wvalid ? gld(A.items + wave * 64u + (uint32_t)lane) : make_uint2(0u, kInvalidItem);
         s_it[threadIdx.x] = it0;
         if (lane == 0) s_bk[wib] = b;
         __syncthreads();
@@ -1057,8 +1076,10 @@ __global__ void __launch_bounds__(256) k_march_lane(MarchArgs<Real> A)
         uint32_t cls = kLenClasses - 1;   // padding last in its segment
         if (it0.y != kInvalidItem) {
             const SnapDesc &D0 = A.snaps[MULTI ? (int)((it0.y >> 16) & 0x7FFF) : 0];
+            uint32_t w0, w1;
+            item_dir_words(it0, D0, pair, A.ng, o, A.k0, A.k1, w0, w1);
             const uint32_t c = bucket_len_class(D0, sf + D0.face_off + D0.nx + 1, gld(A.kref + pair), A.log_inv_tol,
-                                                (int)((it0.x >> 10) & 1023), (uint32_t)o, it0.z, it0.w);
+                                                (int)((it0.x >> 10) & 1023), (uint32_t)o, w0, w1);
             cls = min(c, (uint32_t)kLenClasses - 2);
         }
         const uint32_t bin = seg * kLenClasses + cls;
@@ -1086,11 +1107,12 @@ __global__ void __launch_bounds__(256) k_march_lane(MarchArgs<Real> A)
         if (!wvalid) return;
         it = s_it[src];
         if (it.y == kInvalidItem) return;
-        octant_direction(it.z, it.w, o, dx, dy, dz);
         q = xcd_chunk(blockIdx.x, src >> 6, A.span_log2) * 64u + (src & 63u);
     }
     const int s = MULTI ? (int)((it.y >> 16) & 0x7FFF) : 0;
     const SnapDesc &D = A.snaps[s];
+    double dx, dy, dz;
+    item_direction(it, D, pair, A.ng, o, A.k0, A.k1, dx, dy, dz);
     const RayGeo G = ray_geo(D, sf);
     XzUniform U;
     U.hx = D.hx;
@@ -1148,12 +1170,12 @@ __global__ void __launch_bounds__(256) k_march_mg(MarchArgs<Real> A)
     __syncthreads();
     if (!wvalid) return;
     const uint32_t q = wave * 64u + (uint32_t)lane;
-    const uint4 it = gld(A.items + q);
+    const uint2 it = gld(A.items + q);
     if (it.y == kInvalidItem) return;
-    double dx, dy, dz;
-    octant_direction(it.z, it.w, o, dx, dy, dz);
     const int s = MULTI ? (int)((it.y >> 16) & 0x7FFF) : 0;
     const SnapDesc &D = A.snaps[s];
+    double dx, dy, dz;
+    item_direction(it, D, pair, A.ng, o, A.k0, A.k1, dx, dy, dz);
     const RayGeo G = ray_geo(D, sf);
     XzUniform U;
     U.hx = D.hx;
@@ -1241,7 +1263,7 @@ __device__ __forceinline__ void long_rays(const MarchArgs<float> &A, double *sf,
     const uint32_t stride = WG ? gridDim.x : gridDim.x * (blockDim.x >> 6);
     for (uint32_t rec = first; rec < nrec; rec += stride) {
         const ContRec rc = A.cont[rec];
-        const uint4 it = gld(A.items + rc.q);
+        const uint2 it = gld(A.items + rc.q);
         const uint32_t b = gld(A.chunk_bucket + (rc.q >> 6));
         const int s = MULTI ? (int)((it.y >> 16) & 0x7FFF) : 0;
         const SnapDesc &D = A.snaps[s];
@@ -1267,7 +1289,7 @@ __device__ __forceinline__ void long_rays(const MarchArgs<float> &A, double *sf,
         Props<float> P = P0;
         const uint32_t c = (uint32_t)(((uint64_t)ci * D.ny + cj) * D.nz + ck);
         double dx, dy, dz;
-        octant_direction(it.z, it.w, o, dx, dy, dz);
+        item_direction(it, D, pair, A.ng, o, A.k0, A.k1, dx, dy, dz);
         Ray<float, true> R;
         float kap_src;
         double Isrc;
@@ -2707,7 +2729,7 @@ template <class Real> rmc_status plan_pipeline(rmc_ctx *const *ctxs, int nsnap, 
         (st = L->rtile0.ensure(sizeof(uint32_t) * (P.nregion + 1))) ||
         (st = L->nchunks.ensure(sizeof(uint32_t))) ||
         (st = L->chunk_bucket.ensure(sizeof(uint32_t) * P.max_chunks)) ||
-        (st = L->items.ensure(sizeof(uint4) * max_items)) || (st = L->faces.ensure(sizeof(double) * P.nfaces)) ||
+        (st = L->items.ensure(sizeof(uint2) * max_items)) || (st = L->faces.ensure(sizeof(double) * P.nfaces)) ||
         (st = L->snaps.ensure(sizeof(SnapDesc) * nsnap)) || (st = L->tile_info.ensure(sizeof(TileInfo) * P.ntiles)) ||
         (st = L->border.ensure(sizeof(uint32_t) * nbucket)) ||
         (st = L->counters.ensure(sizeof(unsigned long long) * 4)) ||
@@ -2814,7 +2836,7 @@ rmc_status enqueue_pipeline(const Plan &P, double *const *divq, double *const *s
     AA.k0 = (uint32_t)O.seed; AA.k1 = (uint32_t)(O.seed >> 32);
     AA.hist = L->hist.as<uint32_t>();
     AA.rstart = L->rstart.as<uint32_t>();
-    AA.items = L->items.as<uint4>();
+    AA.items = L->items.as<uint2>();
     // 1024 threads per tile unless the bucket counters and the per-thread buckets overflow 64 KiB;
     // the tile's bricks and the plain cdfs go to LDS where they fit beside them
     constexpr size_t kLds = 64 * 1024;
@@ -2839,7 +2861,7 @@ rmc_status enqueue_pipeline(const Plan &P, double *const *divq, double *const *s
     HIPCHK(hipGetLastError());
     hipLaunchKernelGGL(k_chunk_map, dim3((unsigned)((nrun + 3) / 4)), dim3(64, 4), 0, s, L->hist.as<uint32_t>(),
                        L->bucket_total.as<uint32_t>(), P.ntiles, P.d_rtile0, L->rstart.as<uint32_t>(), nbucket, nrun,
-                       L->chunk_bucket.as<uint32_t>(), L->items.as<uint4>());
+                       L->chunk_bucket.as<uint32_t>(), L->items.as<uint2>());
     HIPCHK(hipGetLastError());
     if (P.smode == 2) hipLaunchKernelGGL(k_alloc_scatter<2>, dim3(P.ntiles), dim3(at), lds_scatter, s, AA);
     else if (P.smode == 1) hipLaunchKernelGGL(k_alloc_scatter<1>, dim3(P.ntiles), dim3(at), lds_scatter, s, AA);
@@ -2852,7 +2874,7 @@ rmc_status enqueue_pipeline(const Plan &P, double *const *divq, double *const *s
     MA.snaps = P.d_snaps;
     MA.faces = P.d_faces;
     MA.nfaces = P.nfaces;
-    MA.items = L->items.as<uint4>();
+    MA.items = L->items.as<uint2>();
     MA.chunk_bucket = L->chunk_bucket.as<uint32_t>();
     MA.nchunks = L->nchunks.as<uint32_t>();
     MA.dnu = L->dnu.as<double>();

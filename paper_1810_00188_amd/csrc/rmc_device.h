@@ -63,6 +63,14 @@ __device__ __forceinline__ uint4 gld(const uint4 *p)
     return make_uint4(v.x, v.y, v.z, v.w);
 }
 
+__device__ __forceinline__ uint2 gld(const uint2 *p)
+{
+    typedef unsigned int v2u __attribute__((ext_vector_type(2)));
+    typedef const __attribute__((address_space(1))) v2u gv2u;
+    const v2u v = *(gv2u *)(p);
+    return make_uint2(v.x, v.y);
+}
+
 __device__ __forceinline__ float4 gld(const float4 *p)
 {
     typedef float v4f __attribute__((ext_vector_type(4)));

@@ -21,9 +21,9 @@ def test_roofline_constants():
     assert bench.HBM_PEAK_GBS == 8000.0
     # algorithmic bytes: per ray-cell step one FP32 kappa and one FP32 intensity, per ray an
     # 8-byte work item and a 4-byte value; what the kernel moves: a 16-byte cell record per
-    # step, a 16-byte work item and an 8-byte slot record per ray
+    # step, an 8-byte work item and an 8-byte slot record per ray
     assert bench.BYTES_PER_STEP == 8 and bench.BYTES_PER_RAY == 12
-    assert bench.KERNEL_BYTES_PER_STEP == 16 and bench.KERNEL_BYTES_PER_RAY == 24
+    assert bench.KERNEL_BYTES_PER_STEP == 16 and bench.KERNEL_BYTES_PER_RAY == 16
 
 
 def test_default_workload_is_the_dns_size_snapshot():
