@@ -612,33 +612,67 @@ __global__ void k_run_len(const uint32_t *hist, const uint32_t *total, int ntile
     run_len[e] = (n + 63u) & ~63u;
 }
 
-// Run starts: regions in turn, inside a region the buckets in the given order (longest
-// expected rays first); exclusive scan of the padded lengths, total chunks.
-__global__ void __launch_bounds__(1024) k_run_layout(const uint32_t *run_len, const uint32_t *order, int nbucket,
-                                                      int nregion, uint32_t *rstart, uint32_t *nchunks)
+// Block-wide exclusive scan of one value per thread (1024 threads); returns the thread's
+// exclusive prefix and the block total in *total.
+__device__ __forceinline__ uint32_t block_scan_1024(uint32_t v, uint32_t *part, uint32_t *total)
 {
-    __shared__ uint32_t part[1024];
     const int tid = threadIdx.x;
-    const uint64_t nrun = (uint64_t)nregion * nbucket;
-    const uint64_t per = (nrun + 1023) / 1024;
-    auto run_of = [&](uint64_t x) { return (x / nbucket) * nbucket + order[x % nbucket]; };
-    uint32_t s = 0;
-    for (uint64_t x = tid * per; x < min(nrun, (tid + 1) * per); ++x) s += run_len[run_of(x)];
-    part[tid] = s;
+    part[tid] = v;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
-        const uint32_t v = tid >= off ? part[tid - off] : 0u;
+        const uint32_t u = tid >= off ? part[tid - off] : 0u;
         __syncthreads();
-        part[tid] += v;
+        part[tid] += u;
         __syncthreads();
     }
-    uint32_t run = part[tid] - s;
-    for (uint64_t x = tid * per; x < min(nrun, (tid + 1) * per); ++x) {
-        const uint64_t e = run_of(x);
-        rstart[e] = run;
-        run += run_len[e];
+    const uint32_t incl = part[tid];
+    *total = part[1023];
+    __syncthreads();
+    return incl - v;
+}
+
+// Padded rays of each region (one workgroup per region).
+__global__ void __launch_bounds__(1024) k_run_region_sum(const uint32_t *run_len, int nbucket, uint32_t *region_len)
+{
+    __shared__ uint32_t part[1024];
+    const uint32_t *rl = run_len + (size_t)blockIdx.x * nbucket;
+    uint32_t sum = 0;
+    for (int b = threadIdx.x; b < nbucket; b += 1024) sum += rl[b];
+    uint32_t total;
+    block_scan_1024(sum, part, &total);
+    if (threadIdx.x == 0) region_len[blockIdx.x] = total;
+}
+
+// Run starts: regions in turn, inside a region the buckets in the given order (longest
+// expected rays first); exclusive scan of the padded lengths (one workgroup per region, after
+// the regions before it), total chunks.
+__global__ void __launch_bounds__(1024) k_run_layout(const uint32_t *run_len, const uint32_t *region_len,
+                                                      const uint32_t *order, int nbucket, int nregion, uint32_t *rstart,
+                                                      uint32_t *nchunks)
+{
+    __shared__ uint32_t part[1024];
+    const int g = blockIdx.x, tid = threadIdx.x;
+    uint32_t base = 0;   // padded rays of the regions before this one
+    for (int q = tid; q < g; q += 1024) base += region_len[q];
+    uint32_t before;
+    block_scan_1024(base, part, &before);
+    base = before;
+    const uint32_t *rl = run_len + (size_t)g * nbucket;
+    uint32_t *rs = rstart + (size_t)g * nbucket;
+    const int per = (nbucket + 1023) / 1024;
+    uint32_t s = 0;
+    for (int x = tid * per; x < min(nbucket, (tid + 1) * per); ++x) s += rl[order[x]];
+    uint32_t total;
+    uint32_t run = base + block_scan_1024(s, part, &total);
+    for (int x = tid * per; x < min(nbucket, (tid + 1) * per); ++x) {
+        const uint32_t b = order[x];
+        rs[b] = run;
+        run += rl[b];
     }
-    if (tid == 1023) { rstart[nrun] = part[1023]; *nchunks = part[1023] / 64u; }
+    if (g == nregion - 1 && tid == 0) {
+        rstart[(size_t)nregion * nbucket] = base + total;
+        *nchunks = (base + total) / 64u;
+    }
 }
 
 // chunk -> bucket map and invalid markers on the padding of each run
@@ -2035,7 +2069,7 @@ struct rmc_ctx {
     bool up_pending = false;
     int slots_R = 0, slots_real = 0;
     // shared pipeline workspace (used when this context leads a batch)
-    DBuf hist, bucket_total, rstart, run_len, rtile0, nchunks, chunk_bucket, items, faces, snaps, tile_info, counters, red_part,
+    DBuf hist, bucket_total, rstart, run_len, region_len, rtile0, nchunks, chunk_bucket, items, faces, snaps, tile_info, counters, red_part,
         outbuf, tune_out;
     DBuf trace_rec, trace_cells, border, kmin, cont, cont_count, probe;
     std::vector<float> h_kmin;         // per (n, g) pair: kappa lower bound, then reference kappa
@@ -2726,6 +2760,7 @@ template <class Real> rmc_status plan_pipeline(rmc_ctx *const *ctxs, int nsnap, 
     if ((st = L->hist.ensure(sizeof(uint32_t) * (uint64_t)nbucket * P.ntiles)) ||
         (st = L->bucket_total.ensure(sizeof(uint32_t) * nbucket)) ||
         (st = L->rstart.ensure(sizeof(uint32_t) * (nrun + 1))) || (st = L->run_len.ensure(sizeof(uint32_t) * nrun)) ||
+        (st = L->region_len.ensure(sizeof(uint32_t) * P.nregion)) ||
         (st = L->rtile0.ensure(sizeof(uint32_t) * (P.nregion + 1))) ||
         (st = L->nchunks.ensure(sizeof(uint32_t))) ||
         (st = L->chunk_bucket.ensure(sizeof(uint32_t) * P.max_chunks)) ||
@@ -2856,8 +2891,12 @@ rmc_status enqueue_pipeline(const Plan &P, double *const *divq, double *const *s
     hipLaunchKernelGGL(k_run_len, dim3((unsigned)((nrun + 255) / 256)), dim3(256), 0, s, L->hist.as<uint32_t>(),
                        L->bucket_total.as<uint32_t>(), P.ntiles, P.d_rtile0, nbucket, nrun, L->run_len.as<uint32_t>());
     HIPCHK(hipGetLastError());
-    hipLaunchKernelGGL(k_run_layout, dim3(1), dim3(1024), 0, s, L->run_len.as<uint32_t>(), P.d_border, nbucket,
-                       P.nregion, L->rstart.as<uint32_t>(), L->nchunks.as<uint32_t>());
+    hipLaunchKernelGGL(k_run_region_sum, dim3(P.nregion), dim3(1024), 0, s, L->run_len.as<uint32_t>(), nbucket,
+                       L->region_len.as<uint32_t>());
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_run_layout, dim3(P.nregion), dim3(1024), 0, s, L->run_len.as<uint32_t>(),
+                       L->region_len.as<uint32_t>(), P.d_border, nbucket, P.nregion, L->rstart.as<uint32_t>(),
+                       L->nchunks.as<uint32_t>());
     HIPCHK(hipGetLastError());
     hipLaunchKernelGGL(k_chunk_map, dim3((unsigned)((nrun + 3) / 4)), dim3(64, 4), 0, s, L->hist.as<uint32_t>(),
                        L->bucket_total.as<uint32_t>(), P.ntiles, P.d_rtile0, L->rstart.as<uint32_t>(), nbucket, nrun,
@@ -3141,7 +3180,7 @@ std::vector<void *> buffer_ptrs(const rmc_ctx *c)
     const DBuf *b[] = {&c->k64, &c->k32, &c->Ib, &c->dnu, &c->wg, &c->T, &c->X, &c->scal, &c->q, &c->cpdf, &c->ccdf_b,
                        &c->ccdf_g, &c->ccdf_o, &c->pdf_scratch, &c->p, &c->cdf_b, &c->cdf_g, &c->W, &c->Iw,
                        &c->status, &c->rec, &c->Y, &c->st, &c->hist, &c->bucket_total,
-                       &c->rstart, &c->run_len, &c->rtile0, &c->nchunks, &c->chunk_bucket, &c->items, &c->faces,
+                       &c->rstart, &c->run_len, &c->region_len, &c->rtile0, &c->nchunks, &c->chunk_bucket, &c->items, &c->faces,
                        &c->snaps, &c->tile_info, &c->border, &c->counters, &c->red_part, &c->kmin, &c->cont, &c->cont_count,
                        &c->rbkt, &c->mgT, &c->mgX, &c->mgrec, &c->dprob, &c->dstrat, &c->lpp, &c->prm,
                        &c->musd, &c->nu_c, &c->gxs, &c->kp, &c->feat, &c->fmask, &c->bng, &c->lfaces};
@@ -3245,7 +3284,7 @@ void rmc_destroy(rmc_ctx *c)
         (void)hipDeviceSynchronize();
         DBuf *bufs[] = {&c->k64, &c->k32, &c->Ib, &c->dnu, &c->wg, &c->T, &c->X, &c->stage, &c->stage2, &c->q, &c->cpdf, &c->ccdf_b,
                         &c->ccdf_g, &c->ccdf_o, &c->pdf_scratch, &c->p, &c->cdf_b, &c->cdf_g, &c->W, &c->Iw,
-                        &c->status, &c->rec, &c->Y, &c->st, &c->hist, &c->bucket_total, &c->rstart, &c->run_len, &c->rtile0,
+                        &c->status, &c->rec, &c->Y, &c->st, &c->hist, &c->bucket_total, &c->rstart, &c->run_len, &c->region_len, &c->rtile0,
                         &c->nchunks, &c->chunk_bucket, &c->items, &c->faces, &c->snaps, &c->tile_info,
                         &c->counters, &c->red_part, &c->outbuf, &c->tune_out, &c->trace_rec, &c->trace_cells, &c->border, &c->small, &c->scal,
                         &c->kmin, &c->cont, &c->cont_count};
