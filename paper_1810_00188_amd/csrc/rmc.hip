@@ -1747,8 +1747,10 @@ __global__ void __launch_bounds__(256) k_trace(TraceArgs<Real> A)
 
 // -------------------------------------------------------------------------- reduce
 // Mean of the R ray values of each cell (Eq. 8) and its standard error; total steps.  The
-// slots of a group of cells are loaded coalesced into LDS (padded against bank conflicts),
-// then one thread sums one cell's R values in slot order.
+// slots of a group of cells are loaded coalesced into LDS (padded against bank conflicts).
+// FP64 sums: four lanes per cell, lane u summing the slots r = u mod 4 in order, the four
+// partial sums combined as (s0 + s1) + (s2 + s3) (a fixed order: reproducible); compensated and
+// plain FP32 sums: one lane per cell in slot order.
 constexpr int kRedVals = 4096;
 __device__ __forceinline__ int red_pad(int q) { return q + (q >> 5); }
 
@@ -1780,14 +1782,40 @@ __global__ void __launch_bounds__(256) k_reduce(const void *__restrict__ Yv, con
             }
         }
         __syncthreads();
+        if (accum == RMC_ACC_F64) {
+            const int u = (int)(threadIdx.x & 3);
+            // every lane of a group of four runs the same number of passes (the shuffles below)
+            for (int cq0 = 0; cq0 < ncell; cq0 += (int)(blockDim.x >> 2)) {
+                const int cq = cq0 + (int)(threadIdx.x >> 2);
+                const bool live = cq < ncell;
+                const int o = cq * R;
+                double sum = 0.0;
+                if (live)
+                    for (int r = u; r < R; r += 4) sum += (double)ys[red_pad(o + r)];
+                sum += __shfl_xor(sum, 1);
+                sum += __shfl_xor(sum, 2);
+                const double mean = sum / R;
+                double sq = 0.0;
+                if (live)
+                    for (int r = u; r < R; r += 4) {
+                        const double dv = (double)ys[red_pad(o + r)] - mean;
+                        sq += dv * dv;
+                        const uint32_t w = ss[red_pad(o + r)];
+                        steps += w & 0x0FFFFFFFu;
+                        capped += (w >> 28) == (uint32_t)kEndCap ? 1ull : 0ull;
+                    }
+                sq += __shfl_xor(sq, 1);
+                sq += __shfl_xor(sq, 2);
+                if (live && u == 0) {
+                    divq[base + cq] = mean;
+                    if (se) se[base + cq] = R > 1 ? sqrt(sq / (R - 1) / R) : 0.0;
+                }
+            }
+        } else
         for (int cq = threadIdx.x; cq < ncell; cq += blockDim.x) {
             const int o = cq * R;
             double mean;
-            if (accum == RMC_ACC_F64) {
-                double sum = 0.0;
-                for (int r = 0; r < R; ++r) sum += (double)ys[red_pad(o + r)];
-                mean = sum / R;
-            } else if (accum == RMC_ACC_COMP_F32) {
+            if (accum == RMC_ACC_COMP_F32) {
                 float sum = 0.0f, comp = 0.0f;   // Neumaier's compensated summation
                 for (int r = 0; r < R; ++r) {
                     const float v = (float)ys[red_pad(o + r)];
