@@ -733,14 +733,23 @@ __global__ void __launch_bounds__(kAllocThreads) k_alloc_scatter(AllocArgs A)
     const int cpp = blockDim.x / A.R;
     const int cq = threadIdx.x / A.R, r = threadIdx.x - cq * A.R;
     const bool by4 = (A.R & 3) == 0 && (A.nbucket & 3) == 0;   // sb + cq * R is 16-byte aligned
+    // the thread's ray of the pass starting at cell `base`: its cell and its bucket (drawn by the
+    // counting pass; 0xFFFFFFFF: no ray), read one pass ahead so the load overlaps a pass
+    auto fetch = [&](int base, int &i, int &j, int &k, bool &live, uint32_t &bucket) {
+        i = j = k = 0;
+        bucket = 0xFFFFFFFFu;
+        live = cq < cpp && base + cq < A.tile_cells && alloc_cell(D, bt, first, base + cq, i, j, k);
+        if (live) bucket = D.rbkt[(((size_t)i * D.ny + j) * D.nz + k) * A.R + r];
+    };
+    int ni, nj, nk;
+    bool nlive;
+    uint32_t nbkt;
+    fetch(0, ni, nj, nk, nlive, nbkt);
     for (int base = 0; base < A.tile_cells; base += cpp) {
-        int i = 0, j = 0, k = 0;
-        const bool live = cq < cpp && base + cq < A.tile_cells && alloc_cell(D, bt, first, base + cq, i, j, k);
-        uint32_t bucket = 0xFFFFFFFFu, c = 0;
-        if (live) {
-            c = (uint32_t)(((uint64_t)i * D.ny + j) * D.nz + k);
-            bucket = D.rbkt[(size_t)c * A.R + r];   // drawn by the counting pass
-        }
+        const int i = ni, j = nj, k = nk;
+        const bool live = nlive;
+        const uint32_t bucket = nbkt;
+        if (base + cpp < A.tile_cells) fetch(base + cpp, ni, nj, nk, nlive, nbkt);
         sb[threadIdx.x] = bucket;
         __syncthreads();
         if (live) {
@@ -1259,6 +1268,10 @@ __global__ void __launch_bounds__(256) k_march_mg(MarchArgs<Real> A)
 // stops (tau <= tol, the wall, or the step cap) is re-marched sequentially with its true
 // incoming tau and step count, and the ray value is
 //   acc = acc_before + sum_{l < l*} tau_in(l) acc_l + acc(l*).
+// A stopping segment of more than kSplitCross crossings is not re-marched by its one thread:
+// the contributions before it are added and the next round starts from its start state, with
+// its incoming tau and step count, and ends where it ended, so that this round splits it again
+// and the sequential re-march covers a few crossings only.
 // Products and sums over the segments run in a fixed order (within each wavefront, then over
 // the four wavefronts), so results do not depend on timing.
 // When no segment stops, the contributions are added and the next round starts where the
@@ -1268,6 +1281,7 @@ __global__ void __launch_bounds__(256) k_march_mg(MarchArgs<Real> A)
 // reflections before it with the sequential march's own arithmetic (mirrored origin, flipped
 // direction), so that every segment starts where the sequential march would be.
 constexpr int kLongSeg = 256;   // segments per round: the threads of one workgroup
+constexpr int kSplitCross = 4;  // longest stopping segment (in crossings) re-marched sequentially
 
 // State at the end of the last segment of a round, passed on through LDS.
 struct LongTail {
@@ -1288,7 +1302,8 @@ __device__ __forceinline__ void long_rays(const MarchArgs<float> &A, double *sf,
 {
     constexpr int NSEG = WG ? kLongSeg : 64;
     __shared__ double s_tau[4], s_acc[4];
-    __shared__ int s_steps[4], s_first[4];
+    __shared__ int s_steps[4], s_first[4], s_span;
+    __shared__ double s_tcap;
     __shared__ LongTail s_tail;
     const int lane = (int)(threadIdx.x & 63), wid = (int)(threadIdx.x >> 6);
     const int seg = WG ? (int)threadIdx.x : lane;
@@ -1358,6 +1373,7 @@ __device__ __forceinline__ void long_rays(const MarchArgs<float> &A, double *sf,
         // workgroup-uniform state of the ray at the start of a round
         int si = rc.i, sj = rc.j, sk = rc.k, ssteps = rc.steps, ssgn = rc.sgn;
         double st = rc.t, stx = rc.tx, sty = rc.ty, stz = rc.tz, stau = rc.tau, sacc = rc.acc, soy = rc.oy;
+        double tcap = INFINITY;   // end of the stopping segment a round splits again
         while (true) {
             double tend = G.reflect ? st + tblack : tw;
             const double od = log(stau / (double)A.tol);  // optical depth left (> 0: the ray goes on)
@@ -1370,6 +1386,8 @@ __device__ __forceinline__ void long_rays(const MarchArgs<float> &A, double *sf,
             if (kobs > 0.0) tend = fmin(tend, st + 1.25 * od / kobs);
             const double ta0 = ax ? stx : stz;
             tend = fmin(tend, ta0 + (double)(A.max_steps - ssteps) * dta);   // every crossing is a step
+            tend = fmin(tend, tcap);
+            tcap = INFINITY;
             const long M = ta0 < tend ? (long)floor((tend - ta0) / dta) + 1 : 0;
             const long B0 = (M * seg) / NSEG, B1 = (M * (seg + 1)) / NSEG;
             const bool empty = seg < NSEG - 1 && B1 == B0;
@@ -1542,6 +1560,52 @@ __device__ __forceinline__ void long_rays(const MarchArgs<float> &A, double *sf,
                     st = __shfl(R.t, 63); stx = __shfl(R.tx, 63); sty = __shfl(R.ty, 63); stz = __shfl(R.tz, 63);
                     soy = __shfl(R.oy, 63);
                     ssgn = __shfl(R.sgn, 63);
+                }
+                continue;
+            }
+            // the stopping segment's crossings; a long one is split again in the next round
+            int span;
+            if constexpr (WG) {
+                if (seg == lstar) {
+                    s_span = (int)(B1 - B0);
+                    s_tcap = seg < NSEG - 1 ? ta0 + (double)(B1 - 1) * dta : tend;
+                    s_tail.tau = tau_in;
+                    s_tail.steps = steps_in;
+                    s_tail.i = start_i; s_tail.j = start_j; s_tail.k = start_k;
+                    s_tail.t = start_t; s_tail.tx = start_tx; s_tail.ty = start_ty; s_tail.tz = start_tz;
+                    s_tail.oy = start_oy;
+                    s_tail.sgn = start_sgn;
+                }
+                __syncthreads();
+                span = s_span;
+            } else {
+                span = __shfl((int)(B1 - B0), lstar);
+            }
+            if (span > kSplitCross) {
+                double part = (seg < lstar) ? tau_in * R.acc : 0.0;
+                for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
+                if constexpr (WG) {
+                    if (lane == 0) s_acc[wid] = part;
+                    __syncthreads();
+                    sacc += ((s_acc[0] + s_acc[1]) + s_acc[2]) + s_acc[3];
+                    stau = s_tail.tau;
+                    ssteps = s_tail.steps;
+                    si = s_tail.i; sj = s_tail.j; sk = s_tail.k;
+                    st = s_tail.t; stx = s_tail.tx; sty = s_tail.ty; stz = s_tail.tz;
+                    soy = s_tail.oy;
+                    ssgn = s_tail.sgn;
+                    tcap = s_tcap;
+                    __syncthreads();   // the LDS values are read before the next round writes them
+                } else {
+                    sacc += part;
+                    stau = __shfl(tau_in, lstar);
+                    ssteps = __shfl(steps_in, lstar);
+                    si = __shfl(start_i, lstar); sj = __shfl(start_j, lstar); sk = __shfl(start_k, lstar);
+                    st = __shfl(start_t, lstar); stx = __shfl(start_tx, lstar); sty = __shfl(start_ty, lstar);
+                    stz = __shfl(start_tz, lstar);
+                    soy = __shfl(start_oy, lstar);
+                    ssgn = __shfl(start_sgn, lstar);
+                    tcap = __shfl(seg < NSEG - 1 ? ta0 + (double)(B1 - 1) * dta : tend, lstar);
                 }
                 continue;
             }
