@@ -109,7 +109,7 @@ struct AllocArgs {
     const uint32_t *rstart;     // [nregion][nbucket] start of each (region, bucket) run of the work list
     uint2 *items;               // (i | j<<10 | k<<20, r | k_ord<<8 | snapshot<<16)
     int lds_bricks;             // the tile's bricks are decoded into LDS (else per cell from the index)
-    int lds_cdf;                // plain sampling: the cdfs are staged in LDS by the counting pass
+    int lds_cdf;                // plain sampling, cdfs staged in LDS by the counting pass: 0 none, 1 bands, 2 both
 };
 
 struct Draw {
@@ -139,8 +139,10 @@ __device__ __forceinline__ Draw draw_ray(const SnapDesc &D, int nb, int ng, uint
     const double u0 = unif_alloc(w[0]), u1 = unif_alloc(w[1]), u2 = unif_alloc(w[2]);
     Draw d;
     if constexpr (SM == 0) {
-        d.n = cdf_search(cdf_b ? cdf_b : D.cdf_b, nb, u0);   // the caller may pass copies staged in LDS
-        d.g = cdf_search((cdf_g ? cdf_g : D.cdf_g) + (size_t)d.n * ng, ng, u1);
+        // the caller may pass copies staged in LDS; a row of the g cdf in global memory is ranked
+        // by independent loads
+        d.n = cdf_search(cdf_b ? cdf_b : D.cdf_b, nb, u0);
+        d.g = cdf_g ? cdf_search(cdf_g + (size_t)d.n * ng, ng, u1) : cdf_rank(D.cdf_g + (size_t)d.n * ng, ng, u1);
         d.o = (int)floor(8.0 * u2);
         d.p = D.p[d.n * ng + d.g] / 8.0;
     } else {
@@ -493,6 +495,15 @@ __global__ void __launch_bounds__(256) k_coarsen(const double *__restrict__ T, c
 // of each cell in one pass of the block (cells_per_pass = blockDim / R).
 constexpr int kAllocThreads = 1024;   // threads per tile: R rays of 1024 / R cells per pass
 
+// Workgroup barrier that orders LDS accesses only: global loads and stores in flight stay in
+// flight (__syncthreads waits for them too), for loops whose barriers guard LDS data alone.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // The bricks of a tile (tile_cells is a multiple of 64: whole bricks), decoded once into LDS as
 // bi | bj << 10 | bk << 20, or ~0 past the last brick of the snapshot.
 __device__ __forceinline__ void tile_bricks(const SnapDesc &D, uint64_t first, int tile_cells, uint32_t *bt)
@@ -521,11 +532,12 @@ __device__ __forceinline__ bool tile_cell(const SnapDesc &D, const uint32_t *bt,
     return v != 0xFFFFFFFFu && i < D.nx && j < D.ny && k < D.nz;
 }
 
-// LDS of k_alloc_count: the plain cdfs (nb + nb*ng doubles, if staged), then nbucket counters,
-// then the tile's bricks (if decoded there).
-inline size_t alloc_count_lds(bool cdf, bool bricks, int nb, int ng, int nbucket, int tile_cells)
+// LDS of k_alloc_count: the plain cdfs staged (cdf 1: the band cdf, nb doubles; 2: also the g
+// cdfs, nb*ng), then nbucket counters, then the tile's bricks (if decoded there).
+inline size_t alloc_count_lds(int cdf, bool bricks, int nb, int ng, int nbucket, int tile_cells)
 {
-    return sizeof(double) * (cdf ? nb + nb * ng : 0) + sizeof(uint32_t) * (nbucket + (bricks ? tile_cells / 64 : 0));
+    return sizeof(double) * (cdf == 2 ? nb + nb * ng : cdf == 1 ? nb : 0) +
+           sizeof(uint32_t) * (nbucket + (bricks ? tile_cells / 64 : 0));
 }
 
 // Cell at position p of the tile, from the decoded bricks or from the brick-linear index.
@@ -539,18 +551,19 @@ template <int SM>
 __global__ void __launch_bounds__(kAllocThreads) k_alloc_count(AllocArgs A)
 {
     extern __shared__ double lds_d[];
-    const bool cdf = SM == 0 && A.lds_cdf;
-    const int ncdf = cdf ? A.nb + A.nb * A.ng : 0;
+    const int cdf = SM == 0 ? A.lds_cdf : 0;
+    const int ncdf = cdf == 2 ? A.nb + A.nb * A.ng : cdf == 1 ? A.nb : 0;
     uint32_t *lh = reinterpret_cast<uint32_t *>(lds_d + ncdf);   // [nbucket]
     uint32_t *bt = A.lds_bricks ? lh + A.nbucket : nullptr;        // [tile_cells / 64]
     const int tile = blockIdx.x;
     const TileInfo TI = A.tiles[tile];
-    const SnapDesc &D = A.snaps[TI.snap];
+    const SnapDesc D = A.snaps[TI.snap];   // a copy: its fields stay in registers across the stores
     const uint64_t first = TI.first;
     for (int b = threadIdx.x; b < A.nbucket; b += blockDim.x) lh[b] = 0;
     if (cdf) {
         for (int q = threadIdx.x; q < A.nb; q += blockDim.x) lds_d[q] = D.cdf_b[q];
-        for (int q = threadIdx.x; q < A.nb * A.ng; q += blockDim.x) lds_d[A.nb + q] = D.cdf_g[q];
+        if (cdf == 2)
+            for (int q = threadIdx.x; q < A.nb * A.ng; q += blockDim.x) lds_d[A.nb + q] = D.cdf_g[q];
     }
     if (bt) tile_bricks(D, first, A.tile_cells, bt);
     __syncthreads();
@@ -561,12 +574,12 @@ __global__ void __launch_bounds__(kAllocThreads) k_alloc_count(AllocArgs A)
         if (cq < cpp && base + cq < A.tile_cells && alloc_cell(D, bt, first, base + cq, i, j, k)) {
             const uint32_t c = (uint32_t)(((uint64_t)i * D.ny + j) * D.nz + k);
             const Draw d = draw_ray<SM>(D, A.nb, A.ng, c, (uint32_t)r, A.k0, A.k1, A.R, cdf ? lds_d : nullptr,
-                                        cdf ? lds_d + A.nb : nullptr);
+                                        cdf == 2 ? lds_d + A.nb : nullptr);
             const uint32_t bucket = (uint32_t)((d.n * A.ng + d.g) * 8 + d.o);
             atomicAdd(&lh[bucket], 1u);
             const size_t slot = (size_t)c * A.R + r;
-            if constexpr (SM != 2) D.rbkt[slot] = bucket;   // learned sampling: rbkt already holds it
-            if constexpr (SM == 1) D.dprob[slot] = d.p;      // the march's weight
+            if constexpr (SM != 2) gst(D.rbkt + slot, bucket);   // learned sampling: rbkt already holds it
+            if constexpr (SM == 1) gst(D.dprob + slot, d.p);     // the march's weight
         }
     }
     __syncthreads();
@@ -722,7 +735,7 @@ __global__ void __launch_bounds__(kAllocThreads) k_alloc_scatter(AllocArgs A)
     const int tile = blockIdx.x;
     const TileInfo TI = A.tiles[tile];
     const int s = TI.snap;
-    const SnapDesc &D = A.snaps[s];
+    const SnapDesc D = A.snaps[s];   // a copy: its fields stay in registers across the item stores
     const uint64_t first = TI.first;
     const uint32_t t0 = A.rtile0[TI.region];   // the region's first tile
     for (int b = threadIdx.x; b < A.nbucket; b += blockDim.x)
@@ -733,34 +746,37 @@ __global__ void __launch_bounds__(kAllocThreads) k_alloc_scatter(AllocArgs A)
     const int cpp = blockDim.x / A.R;
     const int cq = threadIdx.x / A.R, r = threadIdx.x - cq * A.R;
     const bool by4 = (A.R & 3) == 0 && (A.nbucket & 3) == 0;   // sb + cq * R is 16-byte aligned
-    // the thread's ray of the pass starting at cell `base`: its cell and its bucket (drawn by the
-    // counting pass; 0xFFFFFFFF: no ray), read one pass ahead so the load overlaps a pass
-    auto fetch = [&](int base, int &i, int &j, int &k, bool &live, uint32_t &bucket) {
-        i = j = k = 0;
-        bucket = 0xFFFFFFFFu;
-        live = cq < cpp && base + cq < A.tile_cells && alloc_cell(D, bt, first, base + cq, i, j, k);
-        if (live) bucket = D.rbkt[(((size_t)i * D.ny + j) * D.nz + k) * A.R + r];
-    };
-    int ni, nj, nk;
-    bool nlive;
-    uint32_t nbkt;
-    fetch(0, ni, nj, nk, nlive, nbkt);
-    for (int base = 0; base < A.tile_cells; base += cpp) {
-        const int i = ni, j = nj, k = nk;
-        const bool live = nlive;
-        const uint32_t bucket = nbkt;
-        if (base + cpp < A.tile_cells) fetch(base + cpp, ni, nj, nk, nlive, nbkt);
-        sb[threadIdx.x] = bucket;
-        __syncthreads();
-        if (live) {
-            // the ray's ordinal among its cell's rays in the same bucket: with the cell and the
-            // bucket it keys the ray's direction stream, which the march draws (item_direction)
-            const uint32_t kord = same_bucket_before(sb, threadIdx.x - r, r, bucket, by4);
-            const uint32_t pos = atomicAdd(&lb[bucket], 1u);
-            A.items[pos] = make_uint2((uint32_t)i | ((uint32_t)j << 10) | ((uint32_t)k << 20),
-                                      (uint32_t)r | (kord << 8) | ((uint32_t)s << 16));
+    // A pass covers 1024 / R cells, a ray per thread.  The buckets (drawn by the counting pass)
+    // of kScatterAhead passes are read at once, so that one load latency is exposed per group
+    // of passes rather than per pass (the barriers order LDS only).  Per pass the thread keeps
+    // its cell packed as i | j << 10 | k << 20 and its bucket (0xFFFFFFFF: no ray).
+    constexpr int kScatterAhead = 8;
+    for (int g = 0; g < A.tile_cells; g += kScatterAhead * cpp) {
+        uint32_t cell[kScatterAhead], bk[kScatterAhead];
+#pragma unroll
+        for (int u = 0; u < kScatterAhead; ++u) {
+            const int p = g + u * cpp + cq;
+            int i = 0, j = 0, k = 0;
+            bk[u] = 0xFFFFFFFFu;
+            if (cq < cpp && p < A.tile_cells && alloc_cell(D, bt, first, p, i, j, k))
+                bk[u] = gld(D.rbkt + (size_t)(((uint32_t)i * D.ny + j) * D.nz + k) * A.R + r);   // cells < 2^30
+            cell[u] = (uint32_t)i | ((uint32_t)j << 10) | ((uint32_t)k << 20);
         }
-        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kScatterAhead; ++u) {
+            if (g + u * cpp >= A.tile_cells) break;   // uniform over the workgroup
+            const uint32_t bucket = bk[u];
+            sb[threadIdx.x] = bucket;
+            lds_barrier();   // the barriers guard sb and lb; no thread reads another's items
+            if (bucket != 0xFFFFFFFFu) {
+                // the ray's ordinal among its cell's rays in the same bucket: with the cell and
+                // the bucket it keys the ray's direction stream, which the march draws
+                const uint32_t kord = same_bucket_before(sb, threadIdx.x - r, r, bucket, by4);
+                const uint32_t pos = atomicAdd(&lb[bucket], 1u);
+                A.items[pos] = make_uint2(cell[u], (uint32_t)r | (kord << 8) | ((uint32_t)s << 16));
+            }
+            lds_barrier();
+        }
     }
 }
 
@@ -1816,10 +1832,12 @@ __global__ void __launch_bounds__(256) k_trace(TraceArgs<Real> A)
 // partial sums combined as (s0 + s1) + (s2 + s3) (a fixed order: reproducible); compensated and
 // plain FP32 sums: one lane per cell in slot order.
 constexpr int kRedVals = 4096;
+constexpr int kRedThreads = 256;                     // threads per workgroup of k_reduce
+constexpr int kRedPer = kRedVals / kRedThreads;      // values each thread loads per group
 __device__ __forceinline__ int red_pad(int q) { return q + (q >> 5); }
 
 template <class Real>
-__global__ void __launch_bounds__(256) k_reduce(const void *__restrict__ Yv, const uint32_t *__restrict__ st,
+__global__ void __launch_bounds__(kRedThreads) k_reduce(const void *__restrict__ Yv, const uint32_t *__restrict__ st,
                                                 uint64_t nc, int R, int accum, double *__restrict__ divq,
                                                 double *__restrict__ se, unsigned long long *part)
 {
@@ -1830,19 +1848,43 @@ __global__ void __launch_bounds__(256) k_reduce(const void *__restrict__ Yv, con
     for (uint64_t base = (uint64_t)blockIdx.x * cpg; base < nc; base += (uint64_t)gridDim.x * cpg) {
         const int ncell = (int)min((uint64_t)cpg, nc - base);
         const int nval = ncell * R;
+        // all of the thread's loads are issued before the first LDS store (kRedPer in flight)
         if constexpr (sizeof(Real) == 4) {
             const uint2 *yb = reinterpret_cast<const uint2 *>(Yv) + base * R;
-            for (int q = threadIdx.x; q < nval; q += blockDim.x) {
-                const uint2 v = yb[q];
-                ys[red_pad(q)] = __uint_as_float(v.x);
-                ss[red_pad(q)] = v.y;
+            uint2 v[kRedPer];
+#pragma unroll
+            for (int m = 0; m < kRedPer; ++m) {
+                const int q = (int)threadIdx.x + m * kRedThreads;
+                if (q < nval) v[m] = yb[q];
+            }
+#pragma unroll
+            for (int m = 0; m < kRedPer; ++m) {
+                const int q = (int)threadIdx.x + m * kRedThreads;
+                if (q < nval) {
+                    ys[red_pad(q)] = __uint_as_float(v[m].x);
+                    ss[red_pad(q)] = v[m].y;
+                }
             }
         } else {
             const double *yb = reinterpret_cast<const double *>(Yv) + base * R;
             const uint32_t *sb = st + base * R;
-            for (int q = threadIdx.x; q < nval; q += blockDim.x) {
-                ys[red_pad(q)] = yb[q];
-                ss[red_pad(q)] = sb[q];
+            double v[kRedPer];
+            uint32_t w[kRedPer];
+#pragma unroll
+            for (int m = 0; m < kRedPer; ++m) {
+                const int q = (int)threadIdx.x + m * kRedThreads;
+                if (q < nval) {
+                    v[m] = yb[q];
+                    w[m] = sb[q];
+                }
+            }
+#pragma unroll
+            for (int m = 0; m < kRedPer; ++m) {
+                const int q = (int)threadIdx.x + m * kRedThreads;
+                if (q < nval) {
+                    ys[red_pad(q)] = v[m];
+                    ss[red_pad(q)] = w[m];
+                }
             }
         }
         __syncthreads();
@@ -2969,7 +3011,9 @@ rmc_status enqueue_pipeline(const Plan &P, double *const *divq, double *const *s
     constexpr size_t kLds = 64 * 1024;
     const int at = sizeof(uint32_t) * (nbucket + kAllocThreads) <= kLds ? kAllocThreads : 256;
     AA.lds_bricks = alloc_scatter_lds(true, nbucket, at, P.tile_cells) <= kLds ? 1 : 0;
-    AA.lds_cdf = P.smode == 0 && alloc_count_lds(true, AA.lds_bricks, nb, ng, nbucket, P.tile_cells) <= kLds ? 1 : 0;
+    AA.lds_cdf = P.smode != 0 ? 0
+                 : alloc_count_lds(2, AA.lds_bricks, nb, ng, nbucket, P.tile_cells) <= kLds ? 2
+                 : alloc_count_lds(1, AA.lds_bricks, nb, ng, nbucket, P.tile_cells) <= kLds ? 1 : 0;
     const size_t lds_count = alloc_count_lds(AA.lds_cdf, AA.lds_bricks, nb, ng, nbucket, P.tile_cells);
     const size_t lds_scatter = alloc_scatter_lds(AA.lds_bricks, nbucket, at, P.tile_cells);
     if (P.smode == 2) hipLaunchKernelGGL(k_alloc_count<2>, dim3(P.ntiles), dim3(at), lds_count, s, AA);
@@ -3100,7 +3144,7 @@ rmc_status enqueue_pipeline(const Plan &P, double *const *divq, double *const *s
         const uint64_t nc = ncells_of(c);
         const uint64_t groups = (nc + (kRedVals / R) - 1) / (kRedVals / R);
         const int nblk = (int)std::min<uint64_t>(groups, 2048);
-        hipLaunchKernelGGL(k_reduce<Real>, dim3((unsigned)nblk), dim3(256), 0, s, c->Y.p,
+        hipLaunchKernelGGL(k_reduce<Real>, dim3((unsigned)nblk), dim3(kRedThreads), 0, s, c->Y.p,
                            sizeof(Real) == 8 ? c->st.as<uint32_t>() : nullptr, nc, R, (int)O.accum, divq[q],
                            se ? se[q] : nullptr, L->red_part.as<unsigned long long>());
         HIPCHK(hipGetLastError());

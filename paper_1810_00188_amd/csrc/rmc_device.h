@@ -34,12 +34,12 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t
 {
 #pragma unroll
     for (int rnd = 0; rnd < 10; ++rnd) {
-        const uint32_t lo0 = c0 * 0xD2511F53u, hi0 = __umulhi(c0, 0xD2511F53u);
-        const uint32_t lo1 = c2 * 0xCD9E8D57u, hi1 = __umulhi(c2, 0xCD9E8D57u);
-        c0 = hi1 ^ c1 ^ k0;
-        c1 = lo1;
-        c2 = hi0 ^ c3 ^ k1;
-        c3 = lo0;
+        // each product as one 32x32->64 multiply (one instruction, not a low and a high half)
+        const uint64_t p0 = (uint64_t)c0 * 0xD2511F53u, p1 = (uint64_t)c2 * 0xCD9E8D57u;
+        c0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        c1 = (uint32_t)p1;
+        c2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c3 = (uint32_t)p0;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
@@ -98,6 +98,29 @@ __device__ __forceinline__ int cdf_search(const double *__restrict__ cdf, int n,
         if (u < cdf[mid]) hi = mid; else lo = mid + 1;
     }
     return lo;
+}
+
+// Store through a global-memory pointer (a generic store also waits on the LDS counter).
+template <class T> __device__ __forceinline__ void gst(T *p, T v)
+{
+    typedef __attribute__((address_space(1))) T gT;
+    *(gT *)(p) = v;
+}
+
+// The same index as cdf_search for a cdf non-decreasing over [0, n - 2] (cumulative sums are):
+// the count of cdf[0 .. n-2] at or below u.  For a table in global memory: the loads are
+// independent, so their latencies overlap instead of adding up along a bisection.
+__device__ __forceinline__ int cdf_rank(const double *cdf, int n, double u)
+{
+    int c = 0;
+    for (int m0 = 0; m0 < n - 1; m0 += 16) {
+        double v[16];   // sixteen loads at a time, the index clamped into the table
+#pragma unroll
+        for (int q = 0; q < 16; ++q) v[q] = gld(cdf + min(m0 + q, n - 2));
+#pragma unroll
+        for (int q = 0; q < 16; ++q) c += (m0 + q < n - 1 && v[q] <= u) ? 1 : 0;
+    }
+    return c;
 }
 
 // Isotropic direction inside octant o (bit 0: -x, bit 1: -y, bit 2: -z): mu = cos(theta) =
