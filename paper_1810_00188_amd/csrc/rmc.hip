@@ -727,6 +727,23 @@ __device__ __forceinline__ uint32_t same_bucket_before(const uint32_t *sb, int s
     return kord;
 }
 
+// The same rank when a cell's R rays are R consecutive lanes of one wavefront (R divides 64):
+// the live lanes of the cell below this one whose bucket agrees with this lane's in each of its
+// nbits bits (one ballot per bit, no LDS).  Every lane of the wavefront calls it.
+__device__ __forceinline__ uint32_t same_bucket_in_wave(uint32_t bucket, bool live, int r, int nbits)
+{
+    uint64_t m = __ballot(live);
+    for (int b = 0; b < nbits; ++b) {
+        const bool bit = ((bucket >> b) & 1u) != 0u;
+        const uint64_t ones = __ballot(bit);
+        m &= bit ? ones : ~ones;
+    }
+    const int lane = (int)(threadIdx.x & 63);
+    const uint64_t below = (1ull << lane) - 1ull;   // the lanes under this one
+    const uint64_t cell = ~0ull << (lane - r);      // from the cell's first lane on
+    return (uint32_t)__popcll(m & below & cell);
+}
+
 template <int SM>
 __global__ void __launch_bounds__(kAllocThreads) k_alloc_scatter(AllocArgs A)
 {
@@ -751,6 +768,8 @@ __global__ void __launch_bounds__(kAllocThreads) k_alloc_scatter(AllocArgs A)
     // of passes rather than per pass (the barriers order LDS only).  Per pass the thread keeps
     // its cell packed as i | j << 10 | k << 20 and its bucket (0xFFFFFFFF: no ray).
     constexpr int kScatterAhead = 8;
+    const bool wave_rank = 64 % A.R == 0;
+    const int nbits = 32 - __clz(max(A.nbucket - 1, 1));
     for (int g = 0; g < A.tile_cells; g += kScatterAhead * cpp) {
         uint32_t cell[kScatterAhead], bk[kScatterAhead];
 #pragma unroll
@@ -766,12 +785,14 @@ __global__ void __launch_bounds__(kAllocThreads) k_alloc_scatter(AllocArgs A)
         for (int u = 0; u < kScatterAhead; ++u) {
             if (g + u * cpp >= A.tile_cells) break;   // uniform over the workgroup
             const uint32_t bucket = bk[u];
-            sb[threadIdx.x] = bucket;
+            // the ray's ordinal among its cell's rays in the same bucket: with the cell and the
+            // bucket it keys the ray's direction stream, which the march draws
+            uint32_t kord = 0;
+            if (wave_rank) kord = same_bucket_in_wave(bucket, bucket != 0xFFFFFFFFu, r, nbits);
+            else sb[threadIdx.x] = bucket;
             lds_barrier();   // the barriers guard sb and lb; no thread reads another's items
             if (bucket != 0xFFFFFFFFu) {
-                // the ray's ordinal among its cell's rays in the same bucket: with the cell and
-                // the bucket it keys the ray's direction stream, which the march draws
-                const uint32_t kord = same_bucket_before(sb, threadIdx.x - r, r, bucket, by4);
+                if (!wave_rank) kord = same_bucket_before(sb, threadIdx.x - r, r, bucket, by4);
                 const uint32_t pos = atomicAdd(&lb[bucket], 1u);
                 A.items[pos] = make_uint2(cell[u], (uint32_t)r | (kord << 8) | ((uint32_t)s << 16));
             }
