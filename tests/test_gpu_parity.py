@@ -45,10 +45,13 @@ def test_trace_fp64_matches_oracle_per_ray(shape):
     _check_fp64_rays(w, cells, got["Y"], ref)
 
 
-def test_compute_fp64_matches_oracle():
+@pytest.mark.parametrize("R", [16, 24, 64])
+def test_compute_fp64_matches_oracle(R):
     """Production pipeline (bucketed work list, march kernel, FP64 reduction): every ray slot
-    and every cell estimate against the oracle."""
-    w = _small_channel(nx=14, ny=11, nz=9, R=16)
+    and every cell estimate against the oracle.  The scatter ranks a ray among its cell's equal
+    draws by ballots where R divides 64 (16, 64) and from the buckets in LDS otherwise (24); the
+    rank keys the ray's direction, so a wrong one shows in the ray values."""
+    w = _small_channel(nx=14, ny=11, nz=9, R=R)
     say(f"compute fp64 {w.name}")
     s = _solver(w)
     dq, se = s.compute()
