@@ -68,6 +68,28 @@ def test_compute_fp64_matches_oracle(R):
     assert st["steps"] == rsteps and st["rays"] == w.ncells * w.R and st["capped_rays"] == 0
 
 
+@pytest.mark.parametrize("ng", [16, 20])
+def test_compute_fp64_large_tables_matches_oracle(ng):
+    """100 bands x 16 g (the DNS-size table shape) and x 20 g on a small grid.  With 16 g the
+    counting pass stages both cdfs in LDS beside the 12,800 bucket counters (64,816 of 65,536
+    bytes); with 20 g (16,000 counters) only the band cdf fits, and a row of the g cdf is ranked
+    in global memory.  Ray slots and cell estimates against the oracle."""
+    w = _small_channel(nx=6, ny=5, nz=4, R=16, nb=100, ng=ng)
+    say(f"compute fp64 {w.name}")
+    s = _solver(w)
+    dq, se = s.compute()
+    P = oracle.Problem(w)
+    rdq, rse, rsteps = oracle.divergence(P)
+    cells = np.arange(w.ncells)
+    ref = oracle.trace_cells(P, cells)
+    Y, S = s.ray_values(cells)
+    np.testing.assert_array_equal(S, ref["steps"])
+    _check_fp64_rays(w, cells, Y, ref)
+    cell_scale = ref["absY"].mean(axis=1) + 1e-300
+    assert (np.abs(dq - rdq) / cell_scale).max() < TOL64
+    assert s.stats()["steps"] == rsteps
+
+
 def test_grey_slab_full_grid():
     """Grey isothermal slab, 32^3 on 1 x 2 x 1 m, kappa = 1, T = 1000 K, R = 16, FP64."""
     w = inputs.grey_slab(n=32, R=16)
